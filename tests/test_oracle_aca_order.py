@@ -1,0 +1,181 @@
+"""Pins of the oracle's ACA, re-compression, ordering and symbolic pass (CPU only)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import reverse_cuthill_mckee as scipy_rcm
+
+import workloads as W
+from oracle import aca, hmatrix, kernel, ordering, partition, symbolic, tree
+
+
+def _rank_r(m, n, r, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.normal(size=(m, r)) + 1j * rng.normal(size=(m, r))
+    b = rng.normal(size=(r, n)) + 1j * rng.normal(size=(r, n))
+    return a @ b
+
+
+@pytest.mark.parametrize("m,n,r", [(40, 30, 5), (64, 64, 12), (10, 50, 10), (33, 17, 1)])
+def test_aca_recovers_exact_low_rank(m, n, r):
+    A = _rank_r(m, n, r, m * n + r)
+    U, V, piv, norm2 = aca.aca(lambda i: A[i], lambda j: A[:, j], m, n, 1e-12)
+    # the stopping test looks at the newest term, so one rounding-level term may follow
+    assert U.shape[1] in (r, min(r + 1, m, n))
+    assert np.linalg.norm(A - U @ V) <= 1e-12 * np.linalg.norm(A)
+    # the incremental Frobenius norm equals the norm of the product
+    assert abs(norm2 - np.linalg.norm(U @ V) ** 2) <= 1e-10 * norm2
+    # pivots are distinct rows and columns
+    assert len({p[0] for p in piv}) == len(piv) and len({p[1] for p in piv}) == len(piv)
+    Un, Vn = aca.recompress(U, V, 1e-12)
+    assert Un.shape[1] == r
+    assert np.linalg.norm(A - Un @ Vn) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_aca_zero_and_rank_one():
+    Z = np.zeros((6, 5), dtype=complex)
+    U, V, piv, _ = aca.aca(lambda i: Z[i], lambda j: Z[:, j], 6, 5, 1e-4)
+    assert U.shape == (6, 0) and V.shape == (0, 5) and piv == []
+    # rank one with a zero first row: the zero row is skipped
+    A = np.outer(np.r_[0.0, 1.0, 2.0, 3.0], np.r_[1.0, -1.0, 2.0]).astype(complex)
+    U, V, piv, _ = aca.aca(lambda i: A[i], lambda j: A[:, j], 4, 3, 1e-8)
+    assert U.shape[1] == 1 and piv[0][0] == 1
+    assert np.allclose(U @ V, A, atol=1e-14)
+
+
+def test_recompress_is_truncated_svd_of_product():
+    rng = np.random.default_rng(3)
+    # ACA-like factors with decaying singular values
+    m, n, r = 50, 40, 12
+    Q1, _ = np.linalg.qr(rng.normal(size=(m, r)) + 1j * rng.normal(size=(m, r)))
+    Q2, _ = np.linalg.qr(rng.normal(size=(n, r)) + 1j * rng.normal(size=(n, r)))
+    s = 0.3 ** np.arange(r)        # no tail sum sits on the truncation threshold
+    A = (Q1 * s) @ Q2.T
+    U = A @ (rng.normal(size=(n, r)))           # non-orthogonal factorisation of A
+    V = np.linalg.lstsq(U, A, rcond=None)[0]
+    for eps in [1e-3, 1e-6]:
+        Un, Vn = aca.recompress(U, V, eps)
+        u, sv, vh = np.linalg.svd(U @ V)
+        tail = np.sqrt(np.cumsum((sv ** 2)[::-1])[::-1])
+        rp = next(i for i in range(len(sv) + 1) if i == len(sv) or tail[i] <= eps * np.linalg.norm(sv))
+        ref = (u[:, :rp] * sv[:rp]) @ vh[:rp]
+        assert Un.shape[1] == rp
+        assert np.linalg.norm(Un @ Vn - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_aca_kernel_blocks_meet_frobenius_bound():
+    # Eq. 10: || Z_sub - U V ||_F <= eps || Z_sub ||_F on real far blocks
+    wl = W.make_config("c1")
+    hm = hmatrix.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, 1e-4)
+    worst = 0.0
+    for (t, s), U, V in zip(hm.part.far, hm.far_u, hm.far_v):
+        a0, a1 = hm.box_range(int(t))
+        b0, b1 = hm.box_range(int(s))
+        Z = kernel.kernel_block(hm.pts[a0:a1], hm.pts[b0:b1], wl.k, wl.self_h)
+        err = np.linalg.norm(Z - U @ V) / np.linalg.norm(Z)
+        worst = max(worst, err)
+        assert U.shape[1] <= min(a1 - a0, b1 - b0)
+    # ACA's stopping test is a heuristic estimate of the error: allow a small factor
+    assert worst <= 5e-4
+
+
+# ---- ordering: hand-worked cases from the stated rules -------------------------------
+
+def _edges(pairs):
+    return np.array(pairs, dtype=np.int64).reshape(-1, 2)
+
+
+def test_cm_path():
+    near = _edges([(0, 1), (1, 2), (2, 3), (3, 4)])
+    assert ordering.cuthill_mckee(5, near).tolist() == [0, 1, 2, 3, 4]
+    assert ordering.reverse_cuthill_mckee(5, near).tolist() == [4, 3, 2, 1, 0]
+
+
+def test_cm_star():
+    near = _edges([(0, 1), (0, 2), (0, 3), (0, 4)])
+    assert ordering.cuthill_mckee(5, near).tolist() == [2, 0, 1, 3, 4]
+    assert ordering.reverse_cuthill_mckee(5, near).tolist() == [4, 3, 1, 0, 2]
+
+
+def test_cm_ring():
+    near = _edges([(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (0, 5)])
+    assert ordering.cuthill_mckee(6, near).tolist() == [3, 2, 4, 1, 5, 0]
+
+
+def test_cm_grid3x3():
+    pairs = []
+    for r in range(3):
+        for c in range(3):
+            v = 3 * r + c
+            if c < 2:
+                pairs.append((v, v + 1))
+            if r < 2:
+                pairs.append((v, v + 3))
+    near = _edges(pairs)
+    assert ordering.cuthill_mckee(9, near).tolist() == [8, 5, 7, 2, 4, 6, 1, 3, 0]
+    assert ordering.reverse_cuthill_mckee(9, near).tolist() == [0, 3, 1, 6, 4, 2, 7, 5, 8]
+
+
+def test_cm_two_components_and_isolated_node():
+    near = _edges([(0, 1), (2, 3), (3, 4), (2, 4), (5, 5)])
+    assert ordering.cuthill_mckee(6, near).tolist() == [5, 0, 1, 3, 2, 4]
+    assert ordering.reverse_cuthill_mckee(6, near).tolist() == [4, 2, 3, 1, 0, 5]
+
+
+def _random_graph(nb, seed, p=0.08):
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(size=(nb, 2))
+    pairs = [(i, i) for i in range(nb)]
+    for i in range(nb):
+        for j in range(i + 1, nb):
+            if np.linalg.norm(pts[i] - pts[j]) < 0.18 or rng.uniform() < p / nb:
+                pairs.append((i, j))
+    return _edges(pairs)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_rcm_permutation_and_profile(seed):
+    nb = 60 + 10 * seed
+    near = _random_graph(nb, seed)
+    cm = ordering.cuthill_mckee(nb, near)
+    rcm = ordering.reverse_cuthill_mckee(nb, near)
+    assert sorted(rcm.tolist()) == list(range(nb))
+    # Liu-Sherman: reversing a Cuthill-McKee ordering never increases the profile
+    assert ordering.profile(nb, near, rcm) <= ordering.profile(nb, near, cm)
+    # sanity: bandwidth comparable with scipy's RCM (different start/tie rules)
+    off = near[near[:, 0] != near[:, 1]]
+    A = sp.coo_matrix((np.ones(len(off)), (off[:, 0], off[:, 1])), shape=(nb, nb))
+    A = (A + A.T).tocsr()
+    sc = scipy_rcm(A, symmetric_mode=True)
+    assert ordering.bandwidth(nb, near, rcm) <= 2 * ordering.bandwidth(nb, near, sc) + 2
+
+
+# ---- symbolic fill: brute force dense boolean elimination -----------------------------
+
+def _dense_fill(nb, near, order):
+    rank = ordering.inverse(order)
+    F = np.zeros((nb, nb), dtype=bool)
+    for i, j in near:
+        a, b = rank[int(i)], rank[int(j)]
+        F[a, b] = F[b, a] = True
+    for k in range(nb):
+        nz = np.flatnonzero(F[k, k + 1:]) + k + 1
+        F[np.ix_(nz, nz)] = True
+    return F
+
+
+@pytest.mark.parametrize("kind", ["natural", "cm", "rcm"])
+def test_symbolic_matches_dense_boolean_elimination(kind):
+    rng = np.random.default_rng(11)
+    pts = W.fibonacci_sphere(900, rng)
+    t = tree.build_tree(pts, 12)
+    p = partition.build_partition(t)
+    order = ordering.make_order(kind, t.nb, p.near)
+    sym = symbolic.symbolic(t.nb, p.near, order)
+    F = _dense_fill(t.nb, p.near, order)
+    nearset = {(int(i), int(j)) for i, j in p.near}
+    for k in range(t.nb):
+        assert sym.rows[k] == (np.flatnonzero(F[k, k + 1:]) + k + 1).tolist()
+        for j, o in zip(sym.rows[k], sym.orig[k]):
+            a, b = sorted((int(order[k]), int(order[j])))
+            assert o == ((a, b) in nearset)
+        assert sym.parent[k] == (sym.rows[k][0] if sym.rows[k] else -1)
