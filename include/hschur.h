@@ -1,0 +1,229 @@
+/*
+ * hschur.h -- C-ABI of the MI355X (gfx950) symmetric near-field
+ * Schur-complement preconditioner for ACA-compressed H-matrix solves.
+ *
+ * The library solves Z x = b with Z complex symmetric (Z = Z^T, Sec. 3.2 of
+ * Negi, Balakrishnan & Rao, arXiv 2111.13483), split as Z = Z_N + Z_F
+ * (Eq. 11): Z_N the dense leaf-level near field, Z_F the ACA-compressed far
+ * field (Eq. 9-10). The preconditioner is the near field scaled to block
+ * diagonal form by the symmetric Schur complement (Eq. 12-21), used as
+ * P^-1 = alpha D^-1 alpha^T (Eq. 23, 24, 28) inside right-preconditioned
+ * GMRES (Eq. 2).
+ *
+ * Matrix entries are the scalar Helmholtz point kernel
+ *   Z_mn = exp(-j k r_mn) / (4 pi r_mn),  Z_mm = (1 - j k h / 2) / (2 pi h).
+ *
+ * Conventions shared by every entry point
+ *  - Complex numbers are interleaved {re, im} doubles (the layout of
+ *    torch.complex128); vectors are N x nrhs column-major, leading
+ *    dimension N, in the caller's point order.
+ *  - Pointers documented "device" must be device memory of the context's
+ *    device; "host" pointers are ordinary host memory.
+ *  - The caller owns every buffer it passes; the library never frees them
+ *    and keeps no pointer to them after the call returns.
+ *  - Handles own their device memory, obtained through the context's
+ *    allocator callback (hipMalloc when none is given). An hs_precond
+ *    refers to its hs_hmatrix, which must outlive it. Handles are
+ *    immutable after creation.
+ *  - Return value 0 is success, HS_NOT_CONVERGED (1) a warning, negative
+ *    values errors. On error every output handle is set to NULL and
+ *    hs_last_error() (thread-local) describes the failure.
+ *  - Work is enqueued on the context's stream; calls that return results
+ *    to the host synchronise that stream before returning.
+ */
+#ifndef HSCHUR_H
+#define HSCHUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define HS_OK               0
+#define HS_NOT_CONVERGED    1   /* x holds the best iterate; stats hold true residuals */
+#define HS_EINVAL         (-1)  /* bad argument (null pointer, size < 1, duplicate points, ...) */
+#define HS_ENOMEM         (-2)  /* device or host allocation failed; earlier handles stay valid */
+#define HS_ENODEVICE      (-3)  /* no usable gfx950 device */
+#define HS_EHIP           (-4)  /* a HIP runtime call failed */
+#define HS_ESINGULAR      (-5)  /* exactly zero pivot in a leaf-block LU */
+#define HS_ENUMERIC       (-6)  /* NaN or Inf met, or an ACA rank exceeded its cap */
+
+/* ---- option enums ------------------------------------------------------ */
+#define HS_ORDER_NATURAL    0   /* leaf (octree depth-first) order */
+#define HS_ORDER_RCM        1   /* reverse Cuthill-McKee (Algorithm 1, Table 3) */
+#define HS_ORDER_CM         2   /* Cuthill-McKee */
+
+#define HS_PREC_FP64        0   /* complex128 throughout */
+
+#define HS_SOLVE_GMRES      0   /* right-preconditioned restarted GMRES, FP64 */
+
+typedef struct hs_context hs_context;
+typedef struct hs_plan    hs_plan;
+typedef struct hs_hmatrix hs_hmatrix;
+typedef struct hs_precond hs_precond;
+
+typedef void* (*hs_alloc_fn)(size_t bytes, void* user);
+typedef void  (*hs_free_fn)(void* ptr, void* user);
+
+typedef struct {
+    int32_t leaf_max;     /* octree leaf size: boxes holding more points are split (Sec. 2) */
+    double  aca_tol;      /* relative Frobenius tolerance of far-field ACA + re-compression (Eq. 10) */
+    int32_t rank_cap;     /* largest ACA rank a far block may reach; 0 = default (256) */
+} hs_build_opts;
+
+typedef struct {
+    int32_t ordering;     /* HS_ORDER_* (Algorithm 1) */
+    double  fill_tol;     /* fill-in compression tolerance (Sec. 3.4); 0 keeps every block dense */
+    int32_t precision;    /* HS_PREC_FP64 */
+} hs_precond_opts;
+
+typedef struct {
+    int32_t method;       /* HS_SOLVE_GMRES */
+    int32_t restart;      /* Krylov dimension m per cycle */
+    double  tol;          /* relative residual ||b - Z x|| / ||b|| to reach (Sec. 5 uses 1e-6) */
+    int32_t max_iters;    /* cap on inner steps per column; 0 = 5000 */
+    int32_t fixed_iters;  /* > 0: run exactly this many inner steps, ignoring tol (parity runs) */
+} hs_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* inner GMRES steps taken */
+    int32_t converged;    /* 1 if the true relative residual <= tol */
+    double  relres;       /* true ||b - Z x|| / ||b|| recomputed at the end */
+} hs_solve_stats;
+
+typedef struct {
+    int64_t n, nb, nbox, n_near, n_far;
+    int64_t n_pattern;      /* off-diagonal blocks of the filled pattern (sum of d_k) */
+    int64_t n_fill;         /* of which fill-in blocks (leaves not near) */
+    int64_t n_lowrank;      /* fill-in blocks stored as U V */
+    int64_t max_dk;         /* largest row of the filled pattern */
+    int64_t max_rank;       /* largest far-field rank after re-compression */
+    int64_t bytes_near, bytes_far, bytes_alpha, bytes_d;   /* stored matrix bytes */
+    int64_t bytes_device;   /* all device memory the handle holds */
+    double  flops_setup;    /* algorithmic flops of the Schur elimination (LU + alpha + updates) */
+    double  flops_fill;     /* ACA/re-compression flops on fill-in blocks, r^2 (m + n) model */
+} hs_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). `alloc`/`free` (both or
+ * neither) supply device memory; `user` is passed back to them.
+ * Errors: HS_ENODEVICE if the device is absent or not gfx950, HS_EINVAL. */
+int32_t hs_context_create(hs_context** out, int32_t device, void* hip_stream,
+                          hs_alloc_fn alloc, hs_free_fn free_fn, void* user);
+/* Change the stream later calls enqueue on. */
+int32_t hs_context_set_stream(hs_context* ctx, void* hip_stream);
+void    hs_context_destroy(hs_context* ctx);
+
+/* ---- host-only planning: the integer phases ------------------------------
+ * Octree (Sec. 2), near/far partition (Eq. 8 with adjacency admissibility),
+ * near-field block ordering (Algorithm 1) and the symbolic fill of the
+ * scaling coefficients (Sec. 3.3), computed on the host from host points.
+ * Needs no GPU; gives exact sizes, footprints and flop counts before any
+ * device memory is touched (used for admission by footprint). */
+int32_t hs_plan_create(const double* points_xyz_host, int64_t n, int32_t leaf_max,
+                       int32_t ordering, hs_plan** out);
+int32_t hs_plan_query(const hs_plan* plan, hs_info* info);
+void    hs_plan_destroy(hs_plan* plan);
+
+/* Export integer arrays of a plan to host memory (all int64).
+ *  HS_X_PERM        N        tree position -> caller index
+ *  HS_X_LEAF_OFF    nb+1     tree-order offsets of the leaves
+ *  HS_X_BOXES       nbox*7   per box: level, start, count, ax, ay, az, leaf id (-1 if internal)
+ *  HS_X_NEAR        n_near*2 leaf pairs (i <= j), sorted
+ *  HS_X_FAR         n_far*2  box pairs (t < s in preorder), sorted
+ *  HS_X_ORDER       nb       new -> old leaf
+ *  HS_X_ROWPTR      nb+1     filled pattern row pointers
+ *  HS_X_COLS        n_pattern  column (new index) of each pattern block
+ *  HS_X_ORIG        n_pattern  1 if the block pair is a near-field pair, 0 for fill-in
+ * `*needed` receives the byte size; with dst == NULL only the size is returned.
+ * HS_EINVAL if `cap` is too small. */
+#define HS_X_PERM      1
+#define HS_X_LEAF_OFF  2
+#define HS_X_BOXES     3
+#define HS_X_NEAR      4
+#define HS_X_FAR       5
+#define HS_X_ORDER     6
+#define HS_X_ROWPTR    7
+#define HS_X_COLS      8
+#define HS_X_ORIG      9
+int32_t hs_plan_export(const hs_plan* plan, int32_t what, void* dst, int64_t cap, int64_t* needed);
+
+/* ---- H-matrix build (Eq. 9-11) -------------------------------------------
+ * points_xyz: device, n x 3 row-major doubles, caller order; copied to the
+ * host for the integer phases. k: wavenumber 2 pi / lambda. self_h: spacing
+ * h of the self term. Near blocks are assembled on the GPU, far blocks are
+ * compressed on the GPU by partial-pivoting ACA then QR + SVD
+ * re-compression at opts->aca_tol.
+ * Errors: HS_EINVAL (n < 1, k < 0, self_h <= 0, leaf_max < 1, coincident
+ * points), HS_ENOMEM, HS_ENUMERIC (rank above rank_cap). */
+int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double k, double self_h,
+                   const hs_build_opts* opts, hs_hmatrix** out);
+int32_t hs_query_hmatrix(const hs_hmatrix* H, hs_info* info);
+void    hs_hmatrix_destroy(hs_hmatrix* H);
+
+/* ---- preconditioner setup (Sec. 3.1-3.4) ---------------------------------
+ * Orders the leaf graph, eliminates the near field block row by block on the
+ * GPU (LU of W_kk, alpha_kj = -W_kk^-1 W_kj, W_ij += W_ki^T alpha_kj) and
+ * compresses fill-in blocks of alpha with ACA + re-compression at
+ * opts->fill_tol. Errors: HS_ESINGULAR, HS_ENUMERIC, HS_ENOMEM, HS_EINVAL. */
+int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_opts* opts,
+                         hs_precond** out);
+int32_t hs_query_precond(const hs_precond* P, hs_info* info);
+void    hs_precond_destroy(hs_precond* P);
+
+/* ---- solve (Eq. 2 with P^-1 of Eq. 23-24, 28) -----------------------------
+ * b: device, N x nrhs complex128; x: device, N x nrhs, output (initial guess
+ * 0). P may be NULL (unpreconditioned). stats: host array of nrhs entries.
+ * Each column is an independent Krylov space; columns share every matrix
+ * read. Returns HS_NOT_CONVERGED if some column missed tol. */
+int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P,
+                 const void* b, void* x, int64_t nrhs, const hs_solve_opts* opts,
+                 hs_solve_stats* stats);
+
+/* ---- operator applications -------------------------------------------------
+ * y = Z_H x (Eq. 11) and z = P^-1 v = alpha D^-1 alpha^T v (Eq. 23-24);
+ * device, N x nrhs complex128, caller order. */
+int32_t hs_matvec(hs_context* ctx, const hs_hmatrix* H, const void* x, void* y, int64_t nrhs);
+int32_t hs_precond_apply(hs_context* ctx, const hs_precond* P, const void* v, void* z, int64_t nrhs);
+
+/* ---- test exports (device handles -> host memory) ---------------------------
+ * H-matrix:
+ *  HS_H_PLAN_*: any HS_X_* code of the plan behind the handle
+ *  HS_H_NEAR_OFF   int64 n_near+1  element offsets of the near blocks
+ *  HS_H_NEAR_DATA  complex128      near blocks, each b_i x b_j row-major
+ *  HS_H_FAR_RANK   int64 n_far     rank after re-compression
+ *  HS_H_FAR_OFF    int64 n_far+1   element offsets of the U and V factors
+ *  HS_H_FAR_UV     complex128      per far block U (m x r, column-major) then V (r x n, row-major)
+ *  HS_H_FAR_PIV    int64 n_far*2*cap ACA pivot log (i, j) per step, -1 padded (cap = rank cap)
+ * Preconditioner (blocks indexed by new numbering):
+ *  HS_P_D          complex128      D_k = final W_kk, each b_k x b_k row-major
+ *  HS_P_ALPHA_KIND int64 n_pattern rank of the stored block, -1 = dense
+ *  HS_P_ALPHA_OFF  int64 n_pattern+1 element offsets into HS_P_ALPHA
+ *  HS_P_ALPHA      complex128      dense blocks b_k x b_j row-major, or U (b_k x r col-major) then V (r x b_j row-major)
+ */
+#define HS_H_NEAR_OFF   101
+#define HS_H_NEAR_DATA  102
+#define HS_H_FAR_RANK   103
+#define HS_H_FAR_OFF    104
+#define HS_H_FAR_UV     105
+#define HS_H_FAR_PIV    106
+#define HS_P_D          201
+#define HS_P_ALPHA_KIND 202
+#define HS_P_ALPHA_OFF  203
+#define HS_P_ALPHA      204
+int32_t hs_hmatrix_export(const hs_hmatrix* H, int32_t what, void* dst, int64_t cap, int64_t* needed);
+int32_t hs_precond_export(const hs_precond* P, int32_t what, void* dst, int64_t cap, int64_t* needed);
+
+/* ---- errors ----------------------------------------------------------------- */
+const char* hs_status_string(int32_t status);
+const char* hs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSCHUR_H */

@@ -52,7 +52,9 @@ class HMatrix:
         return s, s + int(self.tree.count[box])
 
 
-def h_build(points: np.ndarray, k: float, h: float, leaf_max: int, aca_tol: float) -> HMatrix:
+def h_build(points: np.ndarray, k: float, h: float, leaf_max: int, aca_tol: float,
+            with_far: bool = True) -> HMatrix:
+    """Build Z_H; ``with_far=False`` assembles the near field only (Z_N)."""
     tree = build_tree(points, leaf_max)
     part = build_partition(tree)
     pts = np.asarray(points, dtype=np.float64)[tree.perm]
@@ -62,7 +64,7 @@ def h_build(points: np.ndarray, k: float, h: float, leaf_max: int, aca_tol: floa
         a0, a1 = hm.leaf_range(int(i))
         b0, b1 = hm.leaf_range(int(j))
         hm.near_blocks.append(kernel_block(pts[a0:a1], pts[b0:b1], k, h, same=(i == j)))
-    for t, s in part.far:
+    for t, s in (part.far if with_far else []):
         a0, a1 = hm.box_range(int(t))
         b0, b1 = hm.box_range(int(s))
         pt, ps = pts[a0:a1], pts[b0:b1]

@@ -1,0 +1,315 @@
+"""Python binding of libhschur (MI355X symmetric near-field Schur-complement
+preconditioner for complex-symmetric H-matrix solves).
+
+Argument marshalling only: every step of the method runs in the library's
+host C++ and gfx950 HIP kernels. PyTorch supplies device memory (through the
+context's allocator callback, i.e. torch's caching allocator) and streams.
+The names follow the C-ABI in include/hschur.h.
+
+Raises ``HschurError`` on every non-zero status except HS_NOT_CONVERGED,
+which is reported through the returned statistics. Importing never loads a
+fallback: without the built library ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhschur.so")
+
+HS_OK, HS_NOT_CONVERGED = 0, 1
+HS_EINVAL, HS_ENOMEM, HS_ENODEVICE, HS_EHIP, HS_ESINGULAR, HS_ENUMERIC = -1, -2, -3, -4, -5, -6
+ORDER = {"natural": 0, "rcm": 1, "cm": 2}
+X_CODES = {"perm": 1, "leaf_off": 2, "boxes": 3, "near": 4, "far": 5, "order": 6, "rowptr": 7, "cols": 8, "orig": 9}
+H_CODES = {"near_off": 101, "near_data": 102, "far_rank": 103, "far_off": 104, "far_uv": 105, "far_piv": 106}
+P_CODES = {"d": 201, "alpha_kind": 202, "alpha_off": 203, "alpha": 204}
+
+
+class HschurError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"hschur status {status}: {message}")
+        self.status = status
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("leaf_max", ctypes.c_int32), ("aca_tol", ctypes.c_double), ("rank_cap", ctypes.c_int32)]
+
+
+class PrecondOpts(ctypes.Structure):
+    _fields_ = [("ordering", ctypes.c_int32), ("fill_tol", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("restart", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iters", ctypes.c_int32), ("fixed_iters", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("relres", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("n", "nb", "nbox", "n_near", "n_far", "n_pattern", "n_fill", "n_lowrank", "max_dk", "max_rank",
+                 "bytes_near", "bytes_far", "bytes_alpha", "bytes_d", "bytes_device")] + \
+               [("flops_setup", ctypes.c_double), ("flops_fill", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhschur.so and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise HschurError(HS_ENODEVICE, f"{path} is not built; run paper_2111_13483_amd/build.py")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pvp = ctypes.POINTER(vp)
+    sig = {
+        "hs_context_create": (i32, [pvp, i32, vp, ALLOC_FN, FREE_FN, vp]),
+        "hs_context_set_stream": (i32, [vp, vp]),
+        "hs_context_destroy": (None, [vp]),
+        "hs_plan_create": (i32, [vp, i64, i32, i32, pvp]),
+        "hs_plan_query": (i32, [vp, ctypes.POINTER(Info)]),
+        "hs_plan_destroy": (None, [vp]),
+        "hs_plan_export": (i32, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
+        "hs_h_build": (i32, [vp, vp, i64, dbl, dbl, ctypes.POINTER(BuildOpts), pvp]),
+        "hs_query_hmatrix": (i32, [vp, ctypes.POINTER(Info)]),
+        "hs_hmatrix_destroy": (None, [vp]),
+        "hs_precond_setup": (i32, [vp, vp, ctypes.POINTER(PrecondOpts), pvp]),
+        "hs_query_precond": (i32, [vp, ctypes.POINTER(Info)]),
+        "hs_precond_destroy": (None, [vp]),
+        "hs_solve": (i32, [vp, vp, vp, vp, vp, i64, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)]),
+        "hs_matvec": (i32, [vp, vp, vp, vp, i64]),
+        "hs_precond_apply": (i32, [vp, vp, vp, vp, i64]),
+        "hs_hmatrix_export": (i32, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
+        "hs_precond_export": (i32, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
+        "hs_status_string": (ctypes.c_char_p, [i32]),
+        "hs_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+EXPORTED = (
+    "hs_context_create", "hs_context_set_stream", "hs_context_destroy", "hs_plan_create", "hs_plan_query",
+    "hs_plan_destroy", "hs_plan_export", "hs_h_build", "hs_query_hmatrix", "hs_hmatrix_destroy", "hs_precond_setup",
+    "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_precond_apply", "hs_hmatrix_export",
+    "hs_precond_export", "hs_status_string", "hs_last_error",
+)
+
+
+def _check(status: int, allow_not_converged: bool = False) -> int:
+    if status == HS_OK or (allow_not_converged and status == HS_NOT_CONVERGED):
+        return status
+    msg = _lib.hs_last_error().decode(errors="replace")
+    raise HschurError(status, msg)
+
+
+def _export(fn, handle, code: int, dtype):
+    needed = ctypes.c_int64(0)
+    _check(fn(handle, code, None, 0, ctypes.byref(needed)))
+    out = np.empty(needed.value // np.dtype(dtype).itemsize, dtype=dtype)
+    _check(fn(handle, code, out.ctypes.data_as(ctypes.c_void_p), needed.value, ctypes.byref(needed)))
+    return out
+
+
+# ---------------------------------------------------------------- plan (host only)
+
+class Plan:
+    """Integer phases on the host: octree, partition, ordering, symbolic fill."""
+
+    def __init__(self, points: np.ndarray, leaf_max: int, ordering: str = "rcm"):
+        L = load()
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(L.hs_plan_create(pts.ctypes.data_as(ctypes.c_void_p), pts.shape[0], leaf_max, ORDER[ordering],
+                                ctypes.byref(h)))
+        self._h = h
+
+    def export(self, what: str) -> np.ndarray:
+        return _export(_lib.hs_plan_export, self._h, X_CODES[what], np.int64)
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(_lib.hs_plan_query(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hs_plan_destroy(self._h)
+            self._h = None
+
+
+# ---------------------------------------------------------------- device handles
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """A device + stream; device memory comes from torch's caching allocator."""
+
+    def __init__(self, device: int = 0, stream=None, use_torch_allocator: bool = True):
+        torch = _torch()
+        L = load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self._keep = []
+        if use_torch_allocator:
+            dev = device
+
+            def _alloc(nbytes, user):
+                try:
+                    with torch.cuda.device(dev):
+                        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, self.stream)
+                except Exception:   # out of memory -> NULL -> HS_ENOMEM
+                    return None
+
+            def _free(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            a, f = ALLOC_FN(_alloc), FREE_FN(_free)
+            self._keep = [a, f]
+        else:
+            a, f = ALLOC_FN(), FREE_FN()
+        h = ctypes.c_void_p()
+        _check(L.hs_context_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream), a, f, None))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hs_context_destroy(self._h)
+            self._h = None
+
+
+def _dev_c128(t, n: int):
+    torch = _torch()
+    if not (t.is_cuda and t.dtype == torch.complex128):
+        raise HschurError(HS_EINVAL, "expected a cuda complex128 tensor")
+    if t.dim() == 1:
+        t = t.reshape(n, 1)
+    # column-major N x nrhs: store the transpose contiguously
+    return t.t().contiguous(), t.shape[1]
+
+
+class HMatrix:
+    def __init__(self, ctx: Context, points, k: float, self_h: float, leaf_max: int, aca_tol: float = 1e-4,
+                 rank_cap: int = 0):
+        torch = _torch()
+        pts = points if torch.is_tensor(points) else torch.as_tensor(np.ascontiguousarray(points, dtype=np.float64))
+        pts = pts.to(device=f"cuda:{ctx.device}", dtype=torch.float64).contiguous()
+        self.ctx = ctx
+        self.n = int(pts.shape[0])
+        opts = BuildOpts(leaf_max, aca_tol, rank_cap)
+        h = ctypes.c_void_p()
+        _check(_lib.hs_h_build(ctx._h, ctypes.c_void_p(pts.data_ptr()), self.n, float(k), float(self_h),
+                               ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(_lib.hs_query_hmatrix(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def export(self, what: str) -> np.ndarray:
+        if what in X_CODES:
+            return _export(_lib.hs_hmatrix_export, self._h, X_CODES[what], np.int64)
+        dt = np.complex128 if what in ("near_data", "far_uv") else np.int64
+        return _export(_lib.hs_hmatrix_export, self._h, H_CODES[what], dt)
+
+    def matvec(self, x):
+        """y = Z_H x for a cuda complex128 tensor of shape (N,) or (N, nrhs)."""
+        torch = _torch()
+        xc, s = _dev_c128(x, self.n)
+        y = torch.empty_like(xc)
+        _check(_lib.hs_matvec(self.ctx._h, self._h, ctypes.c_void_p(xc.data_ptr()), ctypes.c_void_p(y.data_ptr()), s))
+        y = y.t()
+        return y.reshape(-1) if x.dim() == 1 else y
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hs_hmatrix_destroy(self._h)
+            self._h = None
+
+
+class Precond:
+    def __init__(self, ctx: Context, H: HMatrix, ordering: str = "rcm", fill_tol: float = 1e-2):
+        self.ctx, self.H = ctx, H
+        opts = PrecondOpts(ORDER[ordering], float(fill_tol), 0)
+        h = ctypes.c_void_p()
+        _check(_lib.hs_precond_setup(ctx._h, H._h, ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(_lib.hs_query_precond(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def export(self, what: str) -> np.ndarray:
+        if what in X_CODES:
+            return _export(_lib.hs_precond_export, self._h, X_CODES[what], np.int64)
+        dt = np.complex128 if what in ("d", "alpha") else np.int64
+        return _export(_lib.hs_precond_export, self._h, P_CODES[what], dt)
+
+    def apply(self, v):
+        """z = P^-1 v = alpha D^-1 alpha^T v."""
+        torch = _torch()
+        vc, s = _dev_c128(v, self.H.n)
+        z = torch.empty_like(vc)
+        _check(_lib.hs_precond_apply(self.ctx._h, self._h, ctypes.c_void_p(vc.data_ptr()),
+                                     ctypes.c_void_p(z.data_ptr()), s))
+        z = z.t()
+        return z.reshape(-1) if v.dim() == 1 else z
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hs_precond_destroy(self._h)
+            self._h = None
+
+
+@dataclass
+class Stats:
+    iters: int
+    converged: bool
+    relres: float
+
+
+def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol: float = 1e-6,
+          max_iters: int = 0, fixed_iters: int = 0):
+    """Solve Z x = b (right-preconditioned GMRES); returns (x, [Stats per column])."""
+    torch = _torch()
+    bc, s = _dev_c128(b, H.n)
+    x = torch.empty_like(bc)
+    opts = SolveOpts(0, restart, tol, max_iters, fixed_iters)
+    st = (SolveStats * s)()
+    _check(_lib.hs_solve(ctx._h, H._h, P._h if P is not None else None, ctypes.c_void_p(bc.data_ptr()),
+                         ctypes.c_void_p(x.data_ptr()), s, ctypes.byref(opts), st), allow_not_converged=True)
+    x = x.t()
+    stats = [Stats(st[i].iters, bool(st[i].converged), st[i].relres) for i in range(s)]
+    return (x.reshape(-1) if b.dim() == 1 else x), stats
+
+
+# C-ABI style aliases
+h_build = HMatrix
+precond_setup = Precond

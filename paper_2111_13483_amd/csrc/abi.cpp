@@ -1,0 +1,1169 @@
+// C-ABI of the MI355X symmetric near-field Schur-complement preconditioner:
+// handles, device memory, orchestration of the host integer phases and the
+// gfx950 kernels of the build, setup and solve phases.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hschur.h"
+#include "kernels.h"
+#include "plan.h"
+
+using hs::cd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Error {
+    int32_t code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int32_t code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(HS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int32_t set_error(const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+}
+
+// Device allocator bound to a context's callbacks (hipMalloc when none).
+struct Mem {
+    hs_alloc_fn alloc = nullptr;
+    hs_free_fn freef = nullptr;
+    void* user = nullptr;
+    int device = 0;
+
+    void* get(size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        void* p = nullptr;
+        if (alloc) {
+            p = alloc(bytes, user);
+            if (!p) fail(HS_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        } else {
+            hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                fail(HS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+            }
+        }
+        return p;
+    }
+    void put(void* p) {
+        if (!p) return;
+        if (freef) freef(p, user);
+        else (void)hipFree(p);
+    }
+};
+
+// A set of device allocations released together.
+struct Owned {
+    Mem mem;
+    std::vector<void*> ptrs;
+    int64_t bytes = 0;
+    template <class T>
+    T* get(size_t count) {
+        T* p = static_cast<T*>(mem.get(count * sizeof(T)));
+        ptrs.push_back(p);
+        bytes += (int64_t)(count * sizeof(T));
+        return p;
+    }
+    template <class T>
+    T* upload(const std::vector<T>& v, hipStream_t s) {
+        T* p = get<T>(std::max<size_t>(v.size(), 1));
+        if (!v.empty()) hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "H2D");
+        return p;
+    }
+    void release() {
+        for (void* p : ptrs) mem.put(p);
+        ptrs.clear();
+        bytes = 0;
+    }
+    ~Owned() { release(); }
+};
+
+template <class T>
+std::vector<T> download(const T* d, size_t count, hipStream_t s) {
+    std::vector<T> h(count);
+    if (count) {
+        hip_check(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, s), "D2H");
+        hip_check(hipStreamSynchronize(s), "stream sync");
+    }
+    return h;
+}
+
+void check_device_flag(const int* d_err, hipStream_t s) {
+    int e = download(d_err, 1, s)[0];
+    if (e & hs::kErrCoincident) fail(HS_EINVAL, "coincident distinct points: the kernel is singular there");
+    if (e & hs::kErrSingular) fail(HS_ESINGULAR, "exactly zero pivot in a leaf-block factorisation");
+    if (e & hs::kErrRankCap) fail(HS_ENUMERIC, "an ACA rank reached the rank cap without meeting the tolerance");
+    if (e & hs::kErrNumeric) fail(HS_ENUMERIC, "NaN or Inf met in a leaf-block factorisation");
+}
+
+constexpr int64_t kScratchBudget = int64_t(2) << 30;   // bytes of ACA scratch per batch
+
+}  // namespace
+
+struct hs_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Mem mem;
+};
+
+struct hs_plan {
+    hs::Tree tree;
+    hs::Partition part;
+    hs::Symbolic sym;
+    bool has_sym = false;
+};
+
+// Compressed blocks of one family (far field or fill-in) after ACA +
+// re-compression: per block rank and device pointer to U (m x r, col-major)
+// followed by V (r x n, row-major).
+struct LowRankSet {
+    std::vector<int> rank;          // final rank per block
+    std::vector<int> rank_aca;      // rank before re-compression
+    std::vector<cd*> ptr;           // device pointers (nullptr when rank 0 or not stored)
+};
+
+struct hs_hmatrix {
+    Owned own;
+    hs_plan plan;
+    int64_t n = 0, nb = 0;
+    double k = 0, h = 0;
+    int rank_cap = 0;
+    std::vector<int64_t> leaf_off;
+    std::vector<hs::NearTask> near_tasks;
+    std::vector<hs::AcaTask> far_geom;
+    LowRankSet far;
+    int64_t bytes_near = 0, bytes_far = 0;
+    int64_t slot_total = 0;
+    // device
+    double* d_pts = nullptr;
+    int64_t* d_perm = nullptr;
+    int64_t* d_leaf_off = nullptr;
+    hs::NearTask* d_near_tasks = nullptr;
+    cd* d_near = nullptr;
+    int64_t* d_near_slot = nullptr;
+    hs::AcaTask* d_far_geom = nullptr;
+    int* d_far_rank = nullptr;
+    cd** d_far_ptr = nullptr;
+    int64_t* d_far_slot = nullptr;
+    int* d_far_piv = nullptr;
+    int64_t* d_gptr = nullptr;
+    hs::GatherEnt* d_gent = nullptr;
+};
+
+struct hs_precond {
+    Owned own;
+    const hs_hmatrix* H = nullptr;
+    hs_plan plan;   // ordering + symbolic (tree/partition left empty)
+    int64_t nb = 0;
+    std::vector<int32_t> bsize;
+    std::vector<int64_t> bstart;
+    std::vector<int64_t> d_off;          // element offsets of D_k / D_k^-1
+    std::vector<int64_t> a_off;          // final alpha store offsets per pattern entry
+    std::vector<int> a_rank;             // -1 dense
+    int64_t alpha_elems = 0, d_elems = 0;
+    int64_t n_lowrank = 0, n_fill = 0, max_dk = 0;
+    double flops_setup = 0, flops_fill = 0;
+    // device
+    cd* d_D = nullptr;       // final W_kk
+    cd* d_dinv = nullptr;    // D_k^-1
+    int64_t* d_dinv_off = nullptr;
+    cd* d_alpha = nullptr;
+    int64_t* d_bstart = nullptr;
+    int32_t* d_bsize = nullptr;
+    int64_t* d_rowptr = nullptr;
+    hs::SweepEnt* d_rowent = nullptr;
+    int64_t* d_colptr = nullptr;
+    hs::SweepEnt* d_colent = nullptr;
+};
+
+namespace {
+
+void set_device(const hs_context* ctx) { hip_check(hipSetDevice(ctx->device), "hipSetDevice"); }
+
+// ACA + re-compression of a list of blocks in batches bounded by the scratch
+// budget. Dense blocks read src (row-major m x n at src_off); otherwise the
+// kernel is evaluated on the points. The final factors go into chunks owned
+// by `own`; piv_log (optional) receives (i, j) per ACA step, stride 2*cap_max.
+void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, bool dense, const double* pts,
+                     double k, const cd* src, double eps, int cap_max, int* d_err, int* d_piv_log,
+                     LowRankSet& out, const std::vector<char>* keep_rule_dense /* unused */) {
+    (void)keep_rule_dense;
+    const int64_t nt = (int64_t)tasks.size();
+    out.rank.assign(nt, 0);
+    out.rank_aca.assign(nt, 0);
+    out.ptr.assign(nt, nullptr);
+    if (nt == 0) return;
+    Owned tmp;
+    tmp.mem = own.mem;
+    int64_t b0 = 0;
+    while (b0 < nt) {
+        // batch [b0, b1) within the scratch budget
+        int64_t b1 = b0, elems = 0, flag_bytes = 0;
+        while (b1 < nt) {
+            hs::AcaTask& t = tasks[b1];
+            t.cap = std::min(std::min(t.m, t.n), cap_max);
+            int64_t e = (int64_t)(t.m + t.n) * t.cap;
+            if (b1 > b0 && (elems + e) * 16 + flag_bytes > kScratchBudget) break;
+            t.u_off = elems;
+            t.v_off = elems + (int64_t)t.m * t.cap;
+            t.flag_off = flag_bytes;
+            elems += e;
+            flag_bytes += t.m + t.n;
+            ++b1;
+        }
+        const int64_t nb_ = b1 - b0;
+        std::vector<hs::AcaTask> bt(tasks.begin() + b0, tasks.begin() + b1);
+        tmp.release();
+        hs::AcaTask* d_t = tmp.upload(bt, s);
+        cd* scratch = tmp.get<cd>(elems);
+        uint8_t* flags = tmp.get<uint8_t>(flag_bytes);
+        int* d_rank = tmp.get<int>(nb_);
+        int* d_rank2 = tmp.get<int>(nb_);
+        hs::launch_aca(dense, d_t, nb_, pts, k, src, scratch, flags, eps, d_rank,
+                       d_piv_log ? d_piv_log + b0 * 2 * cap_max : nullptr, 2 * cap_max, d_err, s);
+        hip_check(hipGetLastError(), "k_aca launch");
+        std::vector<int> r = download(d_rank, nb_, s);
+        std::vector<int64_t> ws_off(nb_);
+        int64_t ws = 0;
+        for (int64_t i = 0; i < nb_; ++i) {
+            ws_off[i] = ws;
+            ws += 4 * (int64_t)r[i] * r[i] + r[i];
+        }
+        int64_t* d_ws_off = tmp.upload(ws_off, s);
+        cd* d_ws = tmp.get<cd>(ws);
+        hs::launch_recompress_a(d_t, nb_, scratch, d_rank, d_ws, d_ws_off, eps, d_rank2, s);
+        hip_check(hipGetLastError(), "k_recompress_a launch");
+        std::vector<int> r2 = download(d_rank2, nb_, s);
+        int64_t fin = 0;
+        for (int64_t i = 0; i < nb_; ++i) fin += (int64_t)r2[i] * (bt[i].m + bt[i].n);
+        cd* chunk = own.get<cd>(fin);
+        std::vector<cd*> dst(nb_, nullptr);
+        int64_t off = 0;
+        for (int64_t i = 0; i < nb_; ++i) {
+            out.rank_aca[b0 + i] = r[i];
+            out.rank[b0 + i] = r2[i];
+            if (r2[i] > 0) {
+                dst[i] = chunk + off;
+                out.ptr[b0 + i] = dst[i];
+                off += (int64_t)r2[i] * (bt[i].m + bt[i].n);
+            }
+        }
+        cd** d_dst = tmp.upload(dst, s);
+        hs::launch_recompress_b(d_t, nb_, scratch, d_rank, d_ws, d_ws_off, d_rank2, d_dst, s);
+        hip_check(hipGetLastError(), "k_recompress_b launch");
+        hip_check(hipStreamSynchronize(s), "stream sync");
+        b0 = b1;
+    }
+    tmp.release();
+}
+
+std::vector<int64_t> leaf_offsets(const hs::Tree& t) {
+    std::vector<int64_t> off(t.nb() + 1);
+    for (int64_t l = 0; l < t.nb(); ++l) off[l] = t.start[t.leaf_box[l]];
+    off[t.nb()] = t.n;
+    return off;
+}
+
+void fill_info_plan(const hs_plan& p, hs_info* info) {
+    std::memset(info, 0, sizeof(*info));
+    info->n = p.tree.n;
+    info->nb = p.tree.nb();
+    info->nbox = p.tree.nbox();
+    info->n_near = p.part.n_near();
+    info->n_far = p.part.n_far();
+    if (p.has_sym) {
+        info->n_pattern = p.sym.nnz();
+        int64_t nf = 0, md = 0;
+        for (int64_t e = 0; e < p.sym.nnz(); ++e) nf += p.sym.orig[e] ? 0 : 1;
+        for (int64_t kk = 0; kk < p.tree.nb(); ++kk) md = std::max(md, p.sym.rowptr[kk + 1] - p.sym.rowptr[kk]);
+        info->n_fill = nf;
+        info->max_dk = md;
+        // exact algorithmic counts of the elimination (Sec. 4): LU 8/3 b^3,
+        // alpha 8 b_k^2 b_j, updates 8 b_i b_k b_j; dense alpha bytes
+        const hs::Tree& t = p.tree;
+        std::vector<double> b(t.nb());
+        for (int64_t kk = 0; kk < t.nb(); ++kk) b[kk] = (double)t.count[t.leaf_box[p.sym.order[kk]]];
+        double fl = 0, ab = 0, db = 0;
+        for (int64_t kk = 0; kk < t.nb(); ++kk) {
+            const double bk = b[kk];
+            fl += 8.0 / 3.0 * bk * bk * bk;
+            db += bk * bk * 16.0;
+            double sj = 0, sj2 = 0;
+            for (int64_t e = p.sym.rowptr[kk]; e < p.sym.rowptr[kk + 1]; ++e) {
+                const double bj = b[p.sym.cols[e]];
+                fl += 8.0 * bk * bk * bj;
+                ab += bk * bj * 16.0;
+                sj += bj;
+                sj2 += bj * bj;
+            }
+            fl += 8.0 * bk * 0.5 * (sj * sj + sj2);   // sum over i <= j of b_i b_j
+        }
+        info->flops_setup = fl;
+        info->bytes_alpha = (int64_t)ab;
+        info->bytes_d = (int64_t)db;
+    }
+}
+
+hs::Symbolic make_symbolic(const hs_plan& p, int ordering) {
+    std::vector<int64_t> order = hs::make_order(ordering, p.tree.nb(), p.part);
+    return hs::symbolic(p.tree.nb(), p.part, order);
+}
+
+int32_t export_plan(const hs_plan& p, int32_t what, void* dst, int64_t cap, int64_t* needed) {
+    std::vector<int64_t> v;
+    const hs::Tree& t = p.tree;
+    switch (what) {
+        case HS_X_PERM: v = t.perm; break;
+        case HS_X_LEAF_OFF: v = leaf_offsets(t); break;
+        case HS_X_BOXES:
+            for (int64_t b = 0; b < t.nbox(); ++b) {
+                v.push_back(t.level[b]);
+                v.push_back(t.start[b]);
+                v.push_back(t.count[b]);
+                for (int a = 0; a < 3; ++a) v.push_back(t.anchor[3 * b + a]);
+                v.push_back(t.leaf_id[b]);
+            }
+            break;
+        case HS_X_NEAR: v = p.part.near; break;
+        case HS_X_FAR: v = p.part.far; break;
+        case HS_X_ORDER:
+        case HS_X_ROWPTR:
+        case HS_X_COLS:
+        case HS_X_ORIG:
+            if (!p.has_sym) fail(HS_EINVAL, "the plan has no ordering");
+            v = what == HS_X_ORDER ? p.sym.order
+              : what == HS_X_ROWPTR ? p.sym.rowptr
+              : what == HS_X_COLS ? p.sym.cols : p.sym.orig;
+            break;
+        default: fail(HS_EINVAL, "unknown export code");
+    }
+    const int64_t bytes = (int64_t)(v.size() * sizeof(int64_t));
+    if (needed) *needed = bytes;
+    if (!dst) return HS_OK;
+    if (cap < bytes) fail(HS_EINVAL, "export buffer too small");
+    if (bytes) std::memcpy(dst, v.data(), bytes);
+    return HS_OK;
+}
+
+int32_t copy_out(const void* src_dev, int64_t bytes, void* dst, int64_t cap, int64_t* needed, hipStream_t s) {
+    if (needed) *needed = bytes;
+    if (!dst) return HS_OK;
+    if (cap < bytes) fail(HS_EINVAL, "export buffer too small");
+    if (bytes) {
+        hip_check(hipMemcpyAsync(dst, src_dev, bytes, hipMemcpyDeviceToHost, s), "D2H export");
+        hip_check(hipStreamSynchronize(s), "stream sync");
+    }
+    return HS_OK;
+}
+
+template <class T>
+int32_t copy_host(const std::vector<T>& v, void* dst, int64_t cap, int64_t* needed) {
+    const int64_t bytes = (int64_t)(v.size() * sizeof(T));
+    if (needed) *needed = bytes;
+    if (!dst) return HS_OK;
+    if (cap < bytes) fail(HS_EINVAL, "export buffer too small");
+    if (bytes) std::memcpy(dst, v.data(), bytes);
+    return HS_OK;
+}
+
+// ---- operator applications on tree-order vectors ------------------------------
+
+struct MatvecWs {
+    cd* slots = nullptr;
+};
+
+void matvec_tree(const hs_hmatrix* H, const cd* x, cd* y, int nrhs, cd* slots, hipStream_t s) {
+    hs::launch_near_mv(H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near, x, H->n, nrhs, slots, s);
+    hs::launch_far_mv(H->d_far_geom, H->d_far_rank, H->d_far_ptr, H->d_far_slot, (int64_t)H->far_geom.size(), x, H->n,
+                      nrhs, slots, s);
+    hs::launch_gather(H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, H->n, nrhs, y, s);
+}
+
+struct SweepWs {
+    cd* ywork = nullptr;
+    int* flags = nullptr;
+    unsigned long long* tickets = nullptr;
+    int epoch = 0;
+};
+
+void apply_tree(const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, hipStream_t s) {
+    ws.epoch += 1;
+    hs::launch_sweeps(P->nb, P->d_bstart, P->d_bsize, P->d_colptr, P->d_colent, P->d_rowptr, P->d_rowent, P->d_alpha,
+                      P->d_dinv, P->d_dinv_off, v, ws.ywork, z, P->H->n, nrhs, ws.flags, ws.tickets, ws.epoch, s);
+}
+
+SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
+    SweepWs w;
+    w.ywork = o.get<cd>((size_t)2 * P->H->n * nrhs);
+    w.flags = o.get<int>((size_t)2 * P->nb);
+    w.tickets = o.get<unsigned long long>(2);
+    hip_check(hipMemsetAsync(w.flags, 0, sizeof(int) * 2 * P->nb, s), "memset flags");
+    hip_check(hipMemsetAsync(w.tickets, 0, sizeof(unsigned long long) * 2, s), "memset tickets");
+    return w;
+}
+
+}  // namespace
+
+// =============================================================================== C-ABI
+
+extern "C" {
+
+const char* hs_status_string(int32_t st) {
+    switch (st) {
+        case HS_OK: return "ok";
+        case HS_NOT_CONVERGED: return "not converged";
+        case HS_EINVAL: return "invalid argument";
+        case HS_ENOMEM: return "out of memory";
+        case HS_ENODEVICE: return "no usable gfx950 device";
+        case HS_EHIP: return "HIP runtime error";
+        case HS_ESINGULAR: return "singular leaf block";
+        case HS_ENUMERIC: return "numerical failure";
+        default: return "unknown status";
+    }
+}
+
+const char* hs_last_error(void) { return g_last_error.c_str(); }
+
+int32_t hs_context_create(hs_context** out, int32_t device, void* hip_stream, hs_alloc_fn alloc, hs_free_fn free_fn,
+                          void* user) {
+    try {
+        if (!out) fail(HS_EINVAL, "out is NULL");
+        *out = nullptr;
+        if ((alloc == nullptr) != (free_fn == nullptr)) fail(HS_EINVAL, "alloc and free must be given together");
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+            (void)hipGetLastError();
+            fail(HS_ENODEVICE, "no HIP device present");
+        }
+        if (device < 0 || device >= count) fail(HS_ENODEVICE, "device index out of range");
+        hipDeviceProp_t prop;
+        hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            fail(HS_ENODEVICE, std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950");
+        auto* c = new hs_context;
+        c->device = device;
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        c->mem.alloc = alloc;
+        c->mem.freef = free_fn;
+        c->mem.user = user;
+        c->mem.device = device;
+        *out = c;
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+int32_t hs_context_set_stream(hs_context* ctx, void* hip_stream) {
+    if (!ctx) { g_last_error = "ctx is NULL"; return HS_EINVAL; }
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return HS_OK;
+}
+
+void hs_context_destroy(hs_context* ctx) { delete ctx; }
+
+// ---- plan -----------------------------------------------------------------------
+
+int32_t hs_plan_create(const double* pts, int64_t n, int32_t leaf_max, int32_t ordering, hs_plan** out) {
+    try {
+        if (!out) fail(HS_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!pts) fail(HS_EINVAL, "points is NULL");
+        if (n < 1) fail(HS_EINVAL, "n must be >= 1");
+        if (leaf_max < 1) fail(HS_EINVAL, "leaf_max must be >= 1");
+        if (ordering < 0 || ordering > 2) fail(HS_EINVAL, "unknown ordering");
+        auto p = std::make_unique<hs_plan>();
+        try {
+            p->tree = hs::build_tree(pts, n, leaf_max);
+        } catch (const std::invalid_argument& e) {
+            fail(HS_EINVAL, e.what());
+        }
+        p->part = hs::build_partition(p->tree);
+        p->sym = make_symbolic(*p, ordering);
+        p->has_sym = true;
+        *out = p.release();
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return HS_ENOMEM;
+    }
+}
+
+int32_t hs_plan_query(const hs_plan* plan, hs_info* info) {
+    if (!plan || !info) { g_last_error = "NULL argument"; return HS_EINVAL; }
+    fill_info_plan(*plan, info);
+    return HS_OK;
+}
+
+void hs_plan_destroy(hs_plan* plan) { delete plan; }
+
+int32_t hs_plan_export(const hs_plan* plan, int32_t what, void* dst, int64_t cap, int64_t* needed) {
+    try {
+        if (!plan) fail(HS_EINVAL, "plan is NULL");
+        return export_plan(*plan, what, dst, cap, needed);
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+// ---- H-matrix build ----------------------------------------------------------------
+
+int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double k, double self_h,
+                   const hs_build_opts* opts, hs_hmatrix** out) {
+    try {
+        if (!out) fail(HS_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!ctx || !points_xyz || !opts) fail(HS_EINVAL, "NULL argument");
+        if (n < 1) fail(HS_EINVAL, "n must be >= 1");
+        if (!(k >= 0.0) || !std::isfinite(k)) fail(HS_EINVAL, "k must be finite and >= 0");
+        if (!(self_h > 0.0) || !std::isfinite(self_h)) fail(HS_EINVAL, "self_h must be > 0");
+        if (opts->leaf_max < 1 || opts->leaf_max > hs::kMaxLeaf)
+            fail(HS_EINVAL, "leaf_max must be in [1, " + std::to_string(hs::kMaxLeaf) + "]");
+        if (!(opts->aca_tol > 0.0)) fail(HS_EINVAL, "aca_tol must be > 0");
+        const int cap = opts->rank_cap > 0 ? opts->rank_cap : hs::kMaxRankCap;
+        if (cap > hs::kMaxRankCap) fail(HS_EINVAL, "rank_cap above " + std::to_string(hs::kMaxRankCap));
+        set_device(ctx);
+        hipStream_t s = ctx->stream;
+        std::vector<double> hp = download(points_xyz, (size_t)(3 * n), s);
+        auto H = std::make_unique<hs_hmatrix>();
+        H->own.mem = ctx->mem;
+        try {
+            H->plan.tree = hs::build_tree(hp.data(), n, opts->leaf_max);
+        } catch (const std::invalid_argument& e) {
+            fail(HS_EINVAL, e.what());
+        }
+        const hs::Tree& t = H->plan.tree;
+        for (int64_t l = 0; l < t.nb(); ++l)
+            if (t.count[t.leaf_box[l]] > hs::kMaxLeaf) fail(HS_EINVAL, "a leaf holds more points than the kernels take");
+        // coincident points share a Morton key: compare within runs of equal keys
+        for (int64_t i = 0; i < n;) {
+            int64_t j = i + 1;
+            while (j < n && t.keys[j] == t.keys[i]) ++j;
+            for (int64_t a = i; a < j; ++a)
+                for (int64_t b = a + 1; b < j; ++b) {
+                    const double* pa = &hp[3 * t.perm[a]];
+                    const double* pb = &hp[3 * t.perm[b]];
+                    if (pa[0] == pb[0] && pa[1] == pb[1] && pa[2] == pb[2])
+                        fail(HS_EINVAL, "coincident distinct points (duplicate input point)");
+                }
+            i = j;
+        }
+        H->plan.part = hs::build_partition(t);
+        const hs::Partition& p = H->plan.part;
+        H->n = n;
+        H->nb = t.nb();
+        H->k = k;
+        H->h = self_h;
+        H->rank_cap = cap;
+        H->leaf_off = leaf_offsets(t);
+        std::vector<double> pts_tree(3 * n);
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) pts_tree[3 * i + a] = hp[3 * t.perm[i] + a];
+        Owned& o = H->own;
+        H->d_pts = o.upload(pts_tree, s);
+        H->d_perm = o.upload(t.perm, s);
+        H->d_leaf_off = o.upload(H->leaf_off, s);
+        int* d_err = o.get<int>(1);
+        hip_check(hipMemsetAsync(d_err, 0, sizeof(int), s), "memset");
+        // near field
+        int64_t off = 0;
+        for (int64_t e = 0; e < p.n_near(); ++e) {
+            const int64_t i = p.near[2 * e], j = p.near[2 * e + 1];
+            hs::NearTask nt;
+            nt.off = off;
+            nt.i0 = (int32_t)H->leaf_off[i];
+            nt.m = (int32_t)(H->leaf_off[i + 1] - H->leaf_off[i]);
+            nt.j0 = (int32_t)H->leaf_off[j];
+            nt.n = (int32_t)(H->leaf_off[j + 1] - H->leaf_off[j]);
+            off += (int64_t)nt.m * nt.n;
+            H->near_tasks.push_back(nt);
+        }
+        H->bytes_near = off * 16;
+        H->d_near = o.get<cd>(off);
+        H->d_near_tasks = o.upload(H->near_tasks, s);
+        hs::launch_near_assemble(H->d_near_tasks, (int64_t)H->near_tasks.size(), H->d_pts, k, self_h, H->d_near, d_err, s);
+        hip_check(hipGetLastError(), "k_near_assemble launch");
+        // far field
+        for (int64_t e = 0; e < p.n_far(); ++e) {
+            const int64_t bt = p.far[2 * e], bs = p.far[2 * e + 1];
+            hs::AcaTask a{};
+            a.src_off = 0;
+            a.t0 = (int32_t)t.start[bt];
+            a.m = (int32_t)t.count[bt];
+            a.s0 = (int32_t)t.start[bs];
+            a.n = (int32_t)t.count[bs];
+            H->far_geom.push_back(a);
+        }
+        H->d_far_piv = o.get<int>((size_t)std::max<int64_t>(p.n_far(), 1) * 2 * cap);
+        hip_check(hipMemsetAsync(H->d_far_piv, 0xff, sizeof(int) * std::max<int64_t>(p.n_far(), 1) * 2 * cap, s), "memset");
+        compress_blocks(o, s, H->far_geom, false, H->d_pts, k, nullptr, opts->aca_tol, cap, d_err, H->d_far_piv, H->far,
+                        nullptr);
+        check_device_flag(d_err, s);
+        int64_t fb = 0;
+        for (size_t b = 0; b < H->far_geom.size(); ++b) {
+            H->far_geom[b].cap = cap;
+            fb += (int64_t)H->far.rank[b] * (H->far_geom[b].m + H->far_geom[b].n);
+        }
+        H->bytes_far = fb * 16;
+        H->d_far_geom = o.upload(H->far_geom, s);
+        H->d_far_rank = o.upload(H->far.rank, s);
+        H->d_far_ptr = o.upload(H->far.ptr, s);
+        // matvec slots and per-leaf gather lists (fixed summation order)
+        std::vector<std::vector<hs::GatherEnt>> lists(t.nb());
+        std::vector<int64_t> near_slot(H->near_tasks.size()), far_slot(H->far_geom.size());
+        int64_t slot = 0;
+        for (int64_t e = 0; e < p.n_near(); ++e) {
+            const int64_t i = p.near[2 * e], j = p.near[2 * e + 1];
+            const hs::NearTask& nt = H->near_tasks[e];
+            near_slot[e] = slot;
+            lists[i].push_back(hs::GatherEnt{slot, nt.m, 0});
+            if (i != j) lists[j].push_back(hs::GatherEnt{slot + nt.m, nt.n, 0});
+            slot += nt.m + (i != j ? nt.n : 0);
+        }
+        // leaves of a box: leaf starts are sorted, boxes are contiguous point ranges
+        auto leaves_of = [&](int64_t b, int64_t& l0, int64_t& l1) {
+            const int64_t s0 = t.start[b], s1 = t.start[b] + t.count[b];
+            l0 = std::lower_bound(H->leaf_off.begin(), H->leaf_off.end() - 1, s0) - H->leaf_off.begin();
+            l1 = std::lower_bound(H->leaf_off.begin(), H->leaf_off.end() - 1, s1) - H->leaf_off.begin();
+        };
+        for (int64_t e = 0; e < p.n_far(); ++e) {
+            const hs::AcaTask& g = H->far_geom[e];
+            far_slot[e] = slot;
+            int64_t l0, l1;
+            leaves_of(p.far[2 * e], l0, l1);
+            for (int64_t l = l0; l < l1; ++l)
+                lists[l].push_back(hs::GatherEnt{slot, g.m, (int32_t)(H->leaf_off[l] - g.t0)});
+            leaves_of(p.far[2 * e + 1], l0, l1);
+            for (int64_t l = l0; l < l1; ++l)
+                lists[l].push_back(hs::GatherEnt{slot + g.m, g.n, (int32_t)(H->leaf_off[l] - g.s0)});
+            slot += g.m + g.n;
+        }
+        H->slot_total = slot;
+        std::vector<int64_t> gptr(t.nb() + 1, 0);
+        std::vector<hs::GatherEnt> gent;
+        for (int64_t l = 0; l < t.nb(); ++l) {
+            gent.insert(gent.end(), lists[l].begin(), lists[l].end());
+            gptr[l + 1] = (int64_t)gent.size();
+        }
+        H->d_near_slot = o.upload(near_slot, s);
+        H->d_far_slot = o.upload(far_slot, s);
+        H->d_gptr = o.upload(gptr, s);
+        H->d_gent = o.upload(gent, s);
+        hip_check(hipStreamSynchronize(s), "stream sync");
+        *out = H.release();
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return HS_ENOMEM;
+    }
+}
+
+int32_t hs_query_hmatrix(const hs_hmatrix* H, hs_info* info) {
+    if (!H || !info) { g_last_error = "NULL argument"; return HS_EINVAL; }
+    fill_info_plan(H->plan, info);
+    info->bytes_near = H->bytes_near;
+    info->bytes_far = H->bytes_far;
+    int64_t mr = 0;
+    for (int r : H->far.rank) mr = std::max<int64_t>(mr, r);
+    info->max_rank = mr;
+    info->bytes_device = H->own.bytes;
+    return HS_OK;
+}
+
+void hs_hmatrix_destroy(hs_hmatrix* H) { delete H; }
+
+int32_t hs_hmatrix_export(const hs_hmatrix* H, int32_t what, void* dst, int64_t cap, int64_t* needed) {
+    try {
+        if (!H) fail(HS_EINVAL, "H is NULL");
+        if (what >= HS_X_PERM && what <= HS_X_FAR) return export_plan(H->plan, what, dst, cap, needed);
+        hip_check(hipSetDevice(H->own.mem.device), "hipSetDevice");
+        hipStream_t s = nullptr;
+        hip_check(hipDeviceSynchronize(), "device sync");
+        switch (what) {
+            case HS_H_NEAR_OFF: {
+                std::vector<int64_t> v;
+                for (auto& t : H->near_tasks) v.push_back(t.off);
+                v.push_back(H->bytes_near / 16);
+                return copy_host(v, dst, cap, needed);
+            }
+            case HS_H_NEAR_DATA: return copy_out(H->d_near, H->bytes_near, dst, cap, needed, s);
+            case HS_H_FAR_RANK: {
+                std::vector<int64_t> v(H->far.rank.begin(), H->far.rank.end());
+                return copy_host(v, dst, cap, needed);
+            }
+            case HS_H_FAR_OFF: {
+                std::vector<int64_t> v(1, 0);
+                for (size_t b = 0; b < H->far_geom.size(); ++b)
+                    v.push_back(v.back() + (int64_t)H->far.rank[b] * (H->far_geom[b].m + H->far_geom[b].n));
+                return copy_host(v, dst, cap, needed);
+            }
+            case HS_H_FAR_UV: {
+                int64_t tot = 0;
+                for (size_t b = 0; b < H->far_geom.size(); ++b)
+                    tot += (int64_t)H->far.rank[b] * (H->far_geom[b].m + H->far_geom[b].n);
+                if (needed) *needed = tot * 16;
+                if (!dst) return HS_OK;
+                if (cap < tot * 16) fail(HS_EINVAL, "export buffer too small");
+                char* d = static_cast<char*>(dst);
+                for (size_t b = 0; b < H->far_geom.size(); ++b) {
+                    const int64_t e = (int64_t)H->far.rank[b] * (H->far_geom[b].m + H->far_geom[b].n) * 16;
+                    if (e) hip_check(hipMemcpy(d, H->far.ptr[b], e, hipMemcpyDeviceToHost), "D2H");
+                    d += e;
+                }
+                return HS_OK;
+            }
+            case HS_H_FAR_PIV: {
+                const int64_t cnt = (int64_t)H->far_geom.size() * 2 * H->rank_cap;
+                std::vector<int> raw = download(H->d_far_piv, (size_t)cnt, s);
+                std::vector<int64_t> v(raw.begin(), raw.end());
+                return copy_host(v, dst, cap, needed);
+            }
+            default: fail(HS_EINVAL, "unknown export code");
+        }
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+// ---- preconditioner setup ---------------------------------------------------------
+
+int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_opts* opts, hs_precond** out) {
+    try {
+        if (!out) fail(HS_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!ctx || !H || !opts) fail(HS_EINVAL, "NULL argument");
+        if (opts->ordering < 0 || opts->ordering > 2) fail(HS_EINVAL, "unknown ordering");
+        if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
+        if (opts->precision != HS_PREC_FP64) fail(HS_EINVAL, "unsupported precision");
+        set_device(ctx);
+        hipStream_t s = ctx->stream;
+        auto P = std::make_unique<hs_precond>();
+        P->own.mem = ctx->mem;
+        P->H = H;
+        P->plan.tree = H->plan.tree;
+        P->plan.part = H->plan.part;
+        P->plan.sym = make_symbolic(H->plan, opts->ordering);
+        P->plan.has_sym = true;
+        const hs::Symbolic& sy = P->plan.sym;
+        const hs::Partition& p = H->plan.part;
+        const int64_t nb = H->nb, nnz = sy.nnz();
+        P->nb = nb;
+        P->bsize.resize(nb);
+        P->bstart.resize(nb);
+        for (int64_t kk = 0; kk < nb; ++kk) {
+            const int64_t ol = sy.order[kk];
+            P->bstart[kk] = H->leaf_off[ol];
+            P->bsize[kk] = (int32_t)(H->leaf_off[ol + 1] - H->leaf_off[ol]);
+        }
+        std::vector<int64_t> row_of(nnz);
+        for (int64_t kk = 0; kk < nb; ++kk)
+            for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) row_of[e] = kk;
+        // layouts: W diagonal blocks, W pattern blocks, dense alpha, D^-1
+        std::vector<int64_t> wd_off(nb), w_off(nnz), ad_off(nnz);
+        P->d_off.resize(nb);
+        int64_t wtot = 0, atot = 0, dtot = 0;
+        for (int64_t kk = 0; kk < nb; ++kk) {
+            const int64_t bk = P->bsize[kk];
+            wd_off[kk] = wtot;
+            wtot += bk * bk;
+            P->d_off[kk] = dtot;
+            dtot += bk * bk;
+            for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
+                const int64_t bj = P->bsize[sy.cols[e]];
+                w_off[e] = wtot;
+                wtot += bk * bj;
+                ad_off[e] = atot;
+                atot += bk * bj;
+            }
+        }
+        P->d_elems = dtot;
+        Owned tmp;
+        tmp.mem = ctx->mem;
+        cd* W = tmp.get<cd>(wtot);
+        cd* Ad = tmp.get<cd>(atot);
+        Owned& o = P->own;
+        P->d_dinv = o.get<cd>(dtot);
+        P->d_D = o.get<cd>(dtot);
+        int* d_err = tmp.get<int>(1);
+        hip_check(hipMemsetAsync(d_err, 0, sizeof(int), s), "memset");
+        // scatter Z_N into W (row k of the working matrix = leaf order[k])
+        std::map<std::pair<int64_t, int64_t>, int64_t> near_idx;
+        for (int64_t e = 0; e < p.n_near(); ++e) near_idx[{p.near[2 * e], p.near[2 * e + 1]}] = e;
+        std::vector<hs::CopyTask> init;
+        for (int64_t kk = 0; kk < nb; ++kk) {
+            const int64_t ok = sy.order[kk];
+            const int32_t bk = P->bsize[kk];
+            init.push_back(hs::CopyTask{wd_off[kk], H->near_tasks[near_idx.at({ok, ok})].off, bk, bk, 0, 0});
+            for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
+                const int64_t j = sy.cols[e], oj = sy.order[j];
+                const int32_t bj = P->bsize[j];
+                if (!sy.orig[e]) {
+                    init.push_back(hs::CopyTask{w_off[e], -1, bk, bj, 0, 0});
+                } else if (ok < oj) {
+                    init.push_back(hs::CopyTask{w_off[e], H->near_tasks[near_idx.at({ok, oj})].off, bk, bj, 0, 0});
+                } else {
+                    init.push_back(hs::CopyTask{w_off[e], H->near_tasks[near_idx.at({oj, ok})].off, bk, bj, 1, 0});
+                }
+            }
+        }
+        hs::CopyTask* d_init = tmp.upload(init, s);
+        hs::launch_copy_blocks(d_init, (int64_t)init.size(), H->d_near, W, s);
+        hip_check(hipGetLastError(), "k_copy_blocks launch");
+        // GEMM task lists of every step
+        auto entry = [&](int64_t i, int64_t j) -> int64_t {
+            auto b = sy.cols.begin() + sy.rowptr[i], e = sy.cols.begin() + sy.rowptr[i + 1];
+            auto it = std::lower_bound(b, e, j);
+            if (it == e || *it != j) fail(HS_EINVAL, "internal: filled pattern is not closed");
+            return it - sy.cols.begin();
+        };
+        std::vector<hs::GemmTask> at, st;
+        std::vector<int64_t> at_ptr(nb + 1, 0), st_ptr(nb + 1, 0);
+        for (int64_t kk = 0; kk < nb; ++kk) {
+            const int32_t bk = P->bsize[kk];
+            const int64_t r0 = sy.rowptr[kk], r1 = sy.rowptr[kk + 1];
+            for (int64_t e = r0; e < r1; ++e) {
+                const int32_t bj = P->bsize[sy.cols[e]];
+                at.push_back(hs::GemmTask{ad_off[e], P->d_off[kk], w_off[e], bk, bj, bk, 0});
+            }
+            for (int64_t a = r0; a < r1; ++a) {
+                const int64_t i = sy.cols[a];
+                for (int64_t b = a; b < r1; ++b) {
+                    const int64_t j = sy.cols[b];
+                    const int64_t dst = (i == j) ? wd_off[i] : w_off[entry(i, j)];
+                    st.push_back(hs::GemmTask{dst, w_off[a], ad_off[b], P->bsize[i], P->bsize[j], bk, 0});
+                }
+            }
+            at_ptr[kk + 1] = (int64_t)at.size();
+            st_ptr[kk + 1] = (int64_t)st.size();
+        }
+        hs::GemmTask* d_at = tmp.upload(at, s);
+        hs::GemmTask* d_st = tmp.upload(st, s);
+        for (int64_t kk = 0; kk < nb; ++kk) {
+            hs::launch_factor_inv(W, wd_off[kk], P->bsize[kk], P->d_dinv, P->d_off[kk], d_err, s);
+            hs::launch_gemm(d_at + at_ptr[kk], at_ptr[kk + 1] - at_ptr[kk], P->d_dinv, W, Ad, false, false, -1.0, s);
+            hs::launch_gemm(d_st + st_ptr[kk], st_ptr[kk + 1] - st_ptr[kk], W, Ad, W, true, true, 1.0, s);
+        }
+        hip_check(hipGetLastError(), "elimination launches");
+        check_device_flag(d_err, s);
+        // keep D_k = final W_kk
+        std::vector<hs::CopyTask> dcp;
+        for (int64_t kk = 0; kk < nb; ++kk)
+            dcp.push_back(hs::CopyTask{P->d_off[kk], wd_off[kk], P->bsize[kk], P->bsize[kk], 0, 0});
+        hs::CopyTask* d_dcp = tmp.upload(dcp, s);
+        hs::launch_copy_blocks(d_dcp, (int64_t)dcp.size(), W, P->d_D, s);
+        // fill-in compression (Sec. 3.4)
+        std::vector<int64_t> fill_e;
+        for (int64_t e = 0; e < nnz; ++e)
+            if (!sy.orig[e]) fill_e.push_back(e);
+        P->n_fill = (int64_t)fill_e.size();
+        P->a_rank.assign(nnz, -1);
+        LowRankSet fills;
+        std::vector<char> keep(fill_e.size(), 0);
+        if (opts->fill_tol > 0.0 && !fill_e.empty()) {
+            std::vector<hs::AcaTask> ft;
+            for (int64_t e : fill_e) {
+                hs::AcaTask a{};
+                a.src_off = ad_off[e];
+                a.m = P->bsize[row_of[e]];
+                a.n = P->bsize[sy.cols[e]];
+                ft.push_back(a);
+            }
+            // compress into a temporary owner; kept blocks are copied to the final store
+            Owned lr;
+            lr.mem = ctx->mem;
+            compress_blocks(lr, s, ft, true, nullptr, 0.0, Ad, opts->fill_tol, hs::kMaxLeaf, d_err, nullptr, fills,
+                            nullptr);
+            check_device_flag(d_err, s);
+            for (size_t q = 0; q < fill_e.size(); ++q) {
+                const int64_t bk = ft[q].m, bj = ft[q].n, r = fills.rank[q];
+                keep[q] = (r * (bk + bj) < bk * bj) ? 1 : 0;
+                if (keep[q]) P->a_rank[fill_e[q]] = (int)r;
+                const double rr = fills.rank_aca[q];
+                P->flops_fill += rr * rr * (double)(bk + bj);
+            }
+            // final alpha store
+            P->a_off.resize(nnz);
+            int64_t ftot = 0;
+            for (int64_t e = 0; e < nnz; ++e) {
+                P->a_off[e] = ftot;
+                const int64_t bk = P->bsize[row_of[e]], bj = P->bsize[sy.cols[e]];
+                ftot += P->a_rank[e] >= 0 ? (int64_t)P->a_rank[e] * (bk + bj) : bk * bj;
+            }
+            P->alpha_elems = ftot;
+            P->d_alpha = o.get<cd>(std::max<int64_t>(ftot, 1));
+            std::vector<hs::CopyTask> cp;
+            for (int64_t e = 0; e < nnz; ++e)
+                if (P->a_rank[e] < 0)
+                    cp.push_back(hs::CopyTask{P->a_off[e], ad_off[e], P->bsize[row_of[e]], P->bsize[sy.cols[e]], 0, 0});
+            hs::CopyTask* d_cp = tmp.upload(cp, s);
+            hs::launch_copy_blocks(d_cp, (int64_t)cp.size(), Ad, P->d_alpha, s);
+            for (size_t q = 0; q < fill_e.size(); ++q) {
+                const int64_t e = fill_e[q];
+                if (!keep[q]) continue;
+                const int64_t bytes = (int64_t)P->a_rank[e] * (ft[q].m + ft[q].n) * 16;
+                if (bytes)
+                    hip_check(hipMemcpyAsync(P->d_alpha + P->a_off[e], fills.ptr[q], bytes, hipMemcpyDeviceToDevice, s),
+                              "D2D");
+                ++P->n_lowrank;
+            }
+            hip_check(hipStreamSynchronize(s), "stream sync");
+        } else {
+            P->a_off = ad_off;
+            P->alpha_elems = atot;
+            P->d_alpha = o.get<cd>(std::max<int64_t>(atot, 1));
+            hip_check(hipMemcpyAsync(P->d_alpha, Ad, atot * 16, hipMemcpyDeviceToDevice, s), "D2D");
+        }
+        // sweep structures
+        std::vector<hs::SweepEnt> rowent(nnz);
+        for (int64_t e = 0; e < nnz; ++e) rowent[e] = hs::SweepEnt{P->a_off[e], (int32_t)sy.cols[e], P->a_rank[e]};
+        std::vector<int64_t> colptr(nb + 1, 0);
+        for (int64_t e = 0; e < nnz; ++e) colptr[sy.cols[e] + 1]++;
+        for (int64_t j = 0; j < nb; ++j) colptr[j + 1] += colptr[j];
+        std::vector<hs::SweepEnt> colent(nnz);
+        std::vector<int64_t> fillp(colptr.begin(), colptr.end() - 1);
+        for (int64_t kk = 0; kk < nb; ++kk)   // rows ascending -> each column's list sorted by k
+            for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e)
+                colent[fillp[sy.cols[e]]++] = hs::SweepEnt{P->a_off[e], (int32_t)kk, P->a_rank[e]};
+        P->d_bstart = o.upload(P->bstart, s);
+        P->d_bsize = o.upload(P->bsize, s);
+        P->d_dinv_off = o.upload(P->d_off, s);
+        P->d_rowptr = o.upload(sy.rowptr, s);
+        P->d_rowent = o.upload(rowent, s);
+        P->d_colptr = o.upload(colptr, s);
+        P->d_colent = o.upload(colent, s);
+        hip_check(hipStreamSynchronize(s), "stream sync");
+        tmp.release();
+        hs_info info;
+        fill_info_plan(P->plan, &info);
+        P->flops_setup = info.flops_setup;
+        P->max_dk = info.max_dk;
+        *out = P.release();
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return HS_ENOMEM;
+    }
+}
+
+int32_t hs_query_precond(const hs_precond* P, hs_info* info) {
+    if (!P || !info) { g_last_error = "NULL argument"; return HS_EINVAL; }
+    fill_info_plan(P->plan, info);
+    info->n_lowrank = P->n_lowrank;
+    info->bytes_alpha = P->alpha_elems * 16;
+    info->bytes_d = P->d_elems * 16;
+    info->flops_fill = P->flops_fill;
+    info->bytes_device = P->own.bytes;
+    return HS_OK;
+}
+
+void hs_precond_destroy(hs_precond* P) { delete P; }
+
+int32_t hs_precond_export(const hs_precond* P, int32_t what, void* dst, int64_t cap, int64_t* needed) {
+    try {
+        if (!P) fail(HS_EINVAL, "P is NULL");
+        if (what >= HS_X_PERM && what <= HS_X_ORIG) return export_plan(P->plan, what, dst, cap, needed);
+        hip_check(hipSetDevice(P->own.mem.device), "hipSetDevice");
+        hip_check(hipDeviceSynchronize(), "device sync");
+        switch (what) {
+            case HS_P_D: return copy_out(P->d_D, P->d_elems * 16, dst, cap, needed, nullptr);
+            case HS_P_ALPHA_KIND: {
+                std::vector<int64_t> v(P->a_rank.begin(), P->a_rank.end());
+                return copy_host(v, dst, cap, needed);
+            }
+            case HS_P_ALPHA_OFF: {
+                std::vector<int64_t> v = P->a_off;
+                v.push_back(P->alpha_elems);
+                return copy_host(v, dst, cap, needed);
+            }
+            case HS_P_ALPHA: return copy_out(P->d_alpha, P->alpha_elems * 16, dst, cap, needed, nullptr);
+            default: fail(HS_EINVAL, "unknown export code");
+        }
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+// ---- operator applications -------------------------------------------------------
+
+int32_t hs_matvec(hs_context* ctx, const hs_hmatrix* H, const void* x, void* y, int64_t nrhs) {
+    try {
+        if (!ctx || !H || !x || !y) fail(HS_EINVAL, "NULL argument");
+        if (nrhs < 1) fail(HS_EINVAL, "nrhs must be >= 1");
+        set_device(ctx);
+        hipStream_t s = ctx->stream;
+        Owned w;
+        w.mem = ctx->mem;
+        const int64_t n = H->n;
+        cd* xt = w.get<cd>(n * nrhs);
+        cd* yt = w.get<cd>(n * nrhs);
+        cd* slots = w.get<cd>(H->slot_total * nrhs);
+        hs::launch_permute(static_cast<const cd*>(x), xt, H->d_perm, n, nrhs, true, s);
+        matvec_tree(H, xt, yt, (int)nrhs, slots, s);
+        hs::launch_permute(yt, static_cast<cd*>(y), H->d_perm, n, nrhs, false, s);
+        hip_check(hipGetLastError(), "matvec launches");
+        hip_check(hipStreamSynchronize(s), "stream sync");
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+int32_t hs_precond_apply(hs_context* ctx, const hs_precond* P, const void* v, void* z, int64_t nrhs) {
+    try {
+        if (!ctx || !P || !v || !z) fail(HS_EINVAL, "NULL argument");
+        if (nrhs < 1) fail(HS_EINVAL, "nrhs must be >= 1");
+        set_device(ctx);
+        hipStream_t s = ctx->stream;
+        Owned w;
+        w.mem = ctx->mem;
+        const int64_t n = P->H->n;
+        cd* vt = w.get<cd>(n * nrhs);
+        cd* zt = w.get<cd>(n * nrhs);
+        SweepWs sw = make_sweep_ws(w, P, (int)nrhs, s);
+        hs::launch_permute(static_cast<const cd*>(v), vt, P->H->d_perm, n, nrhs, true, s);
+        apply_tree(P, vt, zt, (int)nrhs, sw, s);
+        hs::launch_permute(zt, static_cast<cd*>(z), P->H->d_perm, n, nrhs, false, s);
+        hip_check(hipGetLastError(), "apply launches");
+        hip_check(hipStreamSynchronize(s), "stream sync");
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+// ---- solve -------------------------------------------------------------------------
+
+int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, const void* b, void* x, int64_t nrhs,
+                 const hs_solve_opts* opts, hs_solve_stats* stats) {
+    try {
+        if (!ctx || !H || !b || !x || !opts || !stats) fail(HS_EINVAL, "NULL argument");
+        if (nrhs < 1) fail(HS_EINVAL, "nrhs must be >= 1");
+        if (P && P->H != H) fail(HS_EINVAL, "the preconditioner belongs to another H-matrix");
+        if (opts->method != HS_SOLVE_GMRES) fail(HS_EINVAL, "unsupported method");
+        const int m = opts->restart;
+        if (m < 1 || m > hs::kMaxRankCap) fail(HS_EINVAL, "restart must be in [1, 256]");
+        if (!(opts->tol >= 0.0)) fail(HS_EINVAL, "tol must be >= 0");
+        const int budget = opts->fixed_iters > 0 ? opts->fixed_iters : (opts->max_iters > 0 ? opts->max_iters : 5000);
+        set_device(ctx);
+        hipStream_t s = ctx->stream;
+        const int64_t n = H->n;
+        const int ns = (int)nrhs;
+        const int nchunk = hs::gmres_nchunk(n);
+        Owned w;
+        w.mem = ctx->mem;
+        cd* bt = w.get<cd>(n * ns);
+        cd* xt = w.get<cd>(n * ns);
+        cd* r = w.get<cd>(n * ns);
+        cd* wv = w.get<cd>(n * ns);
+        cd* tmp = w.get<cd>(n * ns);
+        const int64_t vstride = n * ns;
+        cd* V = w.get<cd>((size_t)(m + 1) * vstride);
+        const int64_t ldh = (int64_t)(m + 1) * m;
+        cd* Hh = w.get<cd>((size_t)ldh * ns);
+        double* csv = w.get<double>((size_t)m * ns);
+        cd* snv = w.get<cd>((size_t)m * ns);
+        cd* g = w.get<cd>((size_t)(m + 1) * ns);
+        cd* y = w.get<cd>((size_t)m * ns);
+        cd* partial = w.get<cd>((size_t)nchunk * (m + 1) * ns);
+        double* npart = w.get<double>((size_t)nchunk * ns);
+        double* inv_hn = w.get<double>(ns);
+        hs::ColState* st = w.get<hs::ColState>(ns);
+        cd* slots = w.get<cd>((size_t)H->slot_total * ns);
+        SweepWs sw;
+        if (P) sw = make_sweep_ws(w, P, ns, s);
+        std::vector<hs::ColState> hst(ns);
+        for (auto& c : hst) {
+            std::memset(&c, 0, sizeof(c));
+            c.tol = opts->tol;
+            c.budget = budget;
+            c.fixed = opts->fixed_iters > 0 ? 1 : 0;
+        }
+        hip_check(hipMemcpyAsync(st, hst.data(), sizeof(hs::ColState) * ns, hipMemcpyHostToDevice, s), "H2D");
+        hip_check(hipMemsetAsync(xt, 0, sizeof(cd) * n * ns, s), "memset");
+        hip_check(hipMemsetAsync(Hh, 0, sizeof(cd) * ldh * ns, s), "memset");
+        hs::launch_permute(static_cast<const cd*>(b), bt, H->d_perm, n, ns, true, s);
+        hs::launch_col_norms(bt, n, ns, npart, nchunk, s);
+        hs::launch_cycle_start(bt, V, n, g, m, npart, nchunk, st, n, ns, true, s);
+        auto precond = [&](const cd* in, cd* outv) {
+            if (P) apply_tree(P, in, outv, ns, sw, s);
+            else hip_check(hipMemcpyAsync(outv, in, sizeof(cd) * n * ns, hipMemcpyDeviceToDevice, s), "D2D");
+        };
+        const int poll = 4;
+        for (;;) {
+            for (int j = 0; j < m; ++j) {
+                precond(V + j * vstride, tmp);
+                matvec_tree(H, tmp, wv, ns, slots, s);
+                hs::launch_dots(V, n, vstride, j + 1, wv, n, ns, st, partial, nchunk, s);
+                hs::launch_basis_update(V, n, vstride, j + 1, partial, nchunk, wv, n, ns, st, Hh, ldh, m + 1, j, false,
+                                        nullptr, s);
+                hs::launch_dots(V, n, vstride, j + 1, wv, n, ns, st, partial, nchunk, s);
+                hs::launch_basis_update(V, n, vstride, j + 1, partial, nchunk, wv, n, ns, st, Hh, ldh, m + 1, j, true,
+                                        npart, s);
+                hs::launch_givens(Hh, ldh, m, j, csv, snv, g, npart, nchunk, st, ns, inv_hn, s);
+                hs::launch_scale_next(wv, V + (j + 1) * vstride, n, n, ns, st, inv_hn, s);
+                if ((j + 1) % poll == 0 && j + 1 < m) {
+                    hip_check(hipGetLastError(), "inner launches");
+                    std::vector<hs::ColState> cur = download(st, ns, s);
+                    bool any = false;
+                    for (auto& c : cur) any |= c.active != 0;
+                    if (!any) break;
+                }
+            }
+            hs::launch_lsq(Hh, ldh, m, g, y, st, ns, s);
+            hs::launch_combine(V, n, vstride, y, m, tmp, n, ns, st, s);
+            precond(tmp, wv);
+            hs::launch_axpy_x(xt, wv, n, ns, st, s);
+            matvec_tree(H, xt, tmp, ns, slots, s);
+            hs::launch_residual(bt, tmp, r, n, ns, npart, nchunk, s);
+            hs::launch_cycle_end(npart, nchunk, st, ns, s);
+            hip_check(hipGetLastError(), "cycle launches");
+            std::vector<hs::ColState> cur = download(st, ns, s);
+            bool all_done = true;
+            for (auto& c : cur) all_done &= c.done != 0;
+            if (all_done) {
+                hst = cur;
+                break;
+            }
+            hip_check(hipMemsetAsync(Hh, 0, sizeof(cd) * ldh * ns, s), "memset");
+            hs::launch_cycle_start(r, V, n, g, m, npart, nchunk, st, n, ns, false, s);
+        }
+        hs::launch_permute(xt, static_cast<cd*>(x), H->d_perm, n, ns, false, s);
+        hip_check(hipGetLastError(), "permute launch");
+        hip_check(hipStreamSynchronize(s), "stream sync");
+        bool all_conv = true;
+        for (int c = 0; c < ns; ++c) {
+            stats[c].iters = hst[c].total;
+            stats[c].relres = hst[c].relres;
+            stats[c].converged = hst[c].relres <= opts->tol ? 1 : 0;
+            if (!std::isfinite(hst[c].relres)) fail(HS_ENUMERIC, "NaN or Inf in the residual");
+            all_conv &= stats[c].converged != 0;
+        }
+        return all_conv ? HS_OK : HS_NOT_CONVERGED;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Device helpers shared by the gfx950 kernels: complex arithmetic on
+// interleaved doubles, wavefront (64-lane) and workgroup reductions, and the
+// device-side error flag.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace hs {
+
+typedef double2 cd;   // {re, im}
+
+__device__ __forceinline__ cd cmk(double r, double i) { cd z; z.x = r; z.y = i; return z; }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return cmk(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cd csub(cd a, cd b) { return cmk(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cd cmul(cd a, cd b) { return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ cd cconj(cd a) { return cmk(a.x, -a.y); }
+__device__ __forceinline__ cd cscale(cd a, double s) { return cmk(a.x * s, a.y * s); }
+// a + b * c
+__device__ __forceinline__ cd cfma(cd b, cd c, cd a) {
+    return cmk(fma(b.x, c.x, fma(-b.y, c.y, a.x)), fma(b.x, c.y, fma(b.y, c.x, a.y)));
+}
+// a + conj(b) * c
+__device__ __forceinline__ cd cfmac(cd b, cd c, cd a) {
+    return cmk(fma(b.x, c.x, fma(b.y, c.y, a.x)), fma(b.x, c.y, fma(-b.y, c.x, a.y)));
+}
+// |a|^2 rounded as re*re + im*im with no contraction (pivot decisions)
+__device__ __forceinline__ double cabs2_exact(cd a) {
+    double r2 = __dmul_rn(a.x, a.x);
+    double i2 = __dmul_rn(a.y, a.y);
+    return __dadd_rn(r2, i2);
+}
+__device__ __forceinline__ double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+    // Smith's algorithm
+    if (fabs(b.x) >= fabs(b.y)) {
+        double r = b.y / b.x, d = b.x + b.y * r;
+        return cmk((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+    } else {
+        double r = b.x / b.y, d = b.y + b.x * r;
+        return cmk((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+    }
+}
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ cd wave_sum(cd v) { return cmk(wave_sum(v.x), wave_sum(v.y)); }
+
+// Argmax with ties to the lowest index; key < 0 marks "no candidate".
+struct ArgMax { double v; int i; };
+__device__ __forceinline__ ArgMax amax_pick(ArgMax a, ArgMax b) {
+    if (b.v > a.v || (b.v == a.v && b.i < a.i && b.v >= 0.0)) return b;
+    return a;
+}
+__device__ __forceinline__ ArgMax wave_argmax(ArgMax a) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        ArgMax b;
+        b.v = __shfl_xor(a.v, o, kWave);
+        b.i = __shfl_xor(a.i, o, kWave);
+        a = amax_pick(a, b);
+    }
+    return a;
+}
+
+// Workgroup reductions through a caller-provided LDS scratch of >= nwaves entries.
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+    constexpr int NW = NT / kWave;
+    v = wave_sum(v);
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) s += red[i];
+    return s;
+}
+
+template <int NT>
+__device__ __forceinline__ ArgMax wg_argmax(ArgMax a, double* redv, int* redi) {
+    constexpr int NW = NT / kWave;
+    a = wave_argmax(a);
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) { redv[w] = a.v; redi[w] = a.i; }
+    __syncthreads();
+    ArgMax r; r.v = redv[0]; r.i = redi[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) { ArgMax b; b.v = redv[i]; b.i = redi[i]; r = amax_pick(r, b); }
+    return r;
+}
+
+// Device error flags: bitwise OR into a global word (codes in kernels.h).
+__device__ __forceinline__ void raise_err(int* flag, int bits) { atomicOr(flag, bits); }
+
+}  // namespace hs

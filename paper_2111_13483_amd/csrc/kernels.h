@@ -1,0 +1,135 @@
+// Task descriptors and launchers of the gfx950 kernels (host-visible).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hs {
+
+typedef double2 cd;
+
+constexpr int kMaxRankCap = 256;   // largest ACA rank a block may reach
+// device error flag bits
+enum : int { kErrSingular = 1, kErrNumeric = 2, kErrRankCap = 4, kErrCoincident = 8 };
+
+constexpr int kMaxLeaf = 96;       // largest leaf block the dense kernels take (LDS bound)
+
+// One stored near block Z_ij (i <= j): b_i x b_j row-major at `off`.
+struct NearTask {
+    int64_t off;
+    int32_t i0, m;        // tree-order start and size of leaf i (rows)
+    int32_t j0, n;        // tree-order start and size of leaf j (columns)
+};
+
+// One block to compress with ACA: rows t0..t0+m, columns s0..s0+n (points),
+// or a dense m x n row-major source at src_off.
+struct AcaTask {
+    int64_t src_off;
+    int32_t t0, m, s0, n;
+    int32_t cap;          // rank cap of this block
+    int32_t pad;
+    int64_t u_off, v_off; // scratch element offsets of U (m x cap) and V (cap x n)
+    int64_t flag_off;     // byte offset of m + n "used" flags
+};
+
+// Copy a (possibly transposed) block or zero it: dst (rows x cols row-major).
+struct CopyTask {
+    int64_t dst_off, src_off;   // src_off < 0: zero fill
+    int32_t rows, cols;
+    int32_t transpose;          // 1: dst[a][b] = src[b][a] (src is cols x rows)
+    int32_t pad;
+};
+
+// C (m x n) = beta_acc ? C + sign * op(A) B : sign * op(A) B, all row-major;
+// op(A)[a][l] = transA ? A[l][a] (A stored kk x m) : A[a][l] (A stored m x kk).
+struct GemmTask {
+    int64_t c_off, a_off, b_off;
+    int32_t m, n, kk;
+    int32_t pad;
+};
+
+// Low-rank or dense operator block of the sweeps / matvec.
+struct SweepEnt {
+    int64_t off;          // element offset into the alpha store
+    int32_t k;            // the other block index
+    int32_t rank;         // -1: dense
+};
+
+// Gather contribution: y[seg + a, c] += slot[s * base + off + a + c * len]
+struct GatherEnt {
+    int64_t base;         // slot start for one right-hand side (scaled by s)
+    int32_t len;          // slot length (column stride within the slot)
+    int32_t off;          // offset of this leaf inside the slot
+};
+
+// ---- build ----
+void launch_near_assemble(const NearTask* tasks, int64_t ntasks, const double* pts, double k, double h, cd* out,
+                          int* err, hipStream_t s);
+void launch_aca(bool dense, const AcaTask* tasks, int64_t ntasks, const double* pts, double k, const cd* dense_src,
+                cd* scratch, uint8_t* flags, double eps, int* rank_out, int* piv_log, int piv_stride, int* err,
+                hipStream_t s);
+void launch_recompress_a(const AcaTask* tasks, int64_t ntasks, cd* scratch, const int* rank_in, cd* ws,
+                         const int64_t* ws_off, double eps, int* rank_out, hipStream_t s);
+void launch_recompress_b(const AcaTask* tasks, int64_t ntasks, const cd* scratch, const int* rank_in, const cd* ws,
+                         const int64_t* ws_off, const int* rank_new, cd* const* dst, hipStream_t s);
+
+// ---- setup ----
+void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s);
+void launch_factor_inv(const cd* W, int64_t w_off, int b, cd* dinv, int64_t dinv_off, int* err, hipStream_t s);
+void launch_gemm(const GemmTask* tasks, int64_t ntasks, const cd* A, const cd* B, cd* C, bool transA, bool accumulate,
+                 double sign, hipStream_t s);
+
+// ---- solve ----
+void launch_permute(const cd* src, cd* dst, const int64_t* perm, int64_t n, int64_t nrhs, bool to_tree,
+                    hipStream_t s);
+void launch_near_mv(const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cd* Z, const cd* x,
+                    int64_t n, int nrhs, cd* slots, hipStream_t s);
+void launch_far_mv(const AcaTask* geom, const int* rank, cd* const* uv, const int64_t* slot_base, int64_t ntasks,
+                   const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
+void launch_gather(const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb, const cd* slots,
+                   int64_t n, int nrhs, cd* y, hipStream_t s);
+// P^-1 v: forward sweep with D^-1 fused, then backward sweep. v, z: tree order.
+// ywork: 2 n nrhs elements; flags: 2 nb ints (zeroed once); tickets: 2
+// counters (zeroed once); epoch: 1, 2, ... for successive applies on the
+// same flags/tickets.
+void launch_sweeps(int64_t nb, const int64_t* blk_start, const int32_t* blk_size, const int64_t* colptr,
+                   const SweepEnt* colent, const int64_t* rowptr, const SweepEnt* rowent, const cd* alpha,
+                   const cd* dinv, const int64_t* dinv_off, const cd* v, cd* ywork, cd* z, int64_t n, int nrhs,
+                   int* flags, unsigned long long* tickets, int epoch, hipStream_t s);
+int sweep_grid(int64_t nb);
+
+// ---- GMRES (per-column state on device) ----
+struct ColState {
+    double bnorm;         // ||b||
+    double beta;          // norm of the cycle's starting residual
+    double relres;        // true relative residual at the last cycle end
+    double tol;
+    int32_t active;       // 1 while the column takes inner steps in this cycle
+    int32_t steps;        // inner steps in the current cycle
+    int32_t total;        // inner steps overall
+    int32_t done;         // 1 once the column has stopped for good
+    int32_t budget;       // max inner steps overall
+    int32_t fixed;        // 1: ignore the inner tolerance test
+    int32_t pad0, pad1;
+};
+void launch_dots(const cd* V, int64_t ldv, int64_t vstride, int nvec, const cd* w, int64_t n, int nrhs,
+                 const ColState* st, cd* partial, int nchunk, hipStream_t s);
+void launch_basis_update(const cd* V, int64_t ldv, int64_t vstride, int nvec, const cd* partial, int nchunk,
+                         cd* w, int64_t n, int nrhs, const ColState* st, cd* H, int64_t ldh, int mp1, int hcol,
+                         bool accumulate_h, double* norm_partial, hipStream_t s);
+void launch_givens(cd* H, int64_t ldh, int m, int j, double* cs, cd* sn, cd* g, const double* norm_partial,
+                   int nchunk, ColState* st, int nrhs, double* inv_hn, hipStream_t s);
+void launch_scale_next(const cd* w, cd* vnext, int64_t ldv, int64_t n, int nrhs, const ColState* st,
+                       const double* inv_hn, hipStream_t s);
+void launch_cycle_start(const cd* r, cd* V, int64_t ldv, cd* g, int m, const double* norm_partial, int nchunk,
+                        ColState* st, int64_t n, int nrhs, bool first, hipStream_t s);
+void launch_lsq(const cd* H, int64_t ldh, int m, const cd* g, cd* y, const ColState* st, int nrhs, hipStream_t s);
+void launch_combine(const cd* V, int64_t ldv, int64_t vstride, const cd* y, int m, cd* u, int64_t n, int nrhs,
+                    const ColState* st, hipStream_t s);
+void launch_axpy_x(cd* x, const cd* z, int64_t n, int nrhs, const ColState* st, hipStream_t s);
+void launch_residual(const cd* b, const cd* zx, cd* r, int64_t n, int nrhs, double* norm_partial, int nchunk,
+                     hipStream_t s);
+void launch_cycle_end(const double* norm_partial, int nchunk, ColState* st, int nrhs, hipStream_t s);
+void launch_col_norms(const cd* v, int64_t n, int nrhs, double* norm_partial, int nchunk, hipStream_t s);
+int gmres_nchunk(int64_t n);
+
+}  // namespace hs

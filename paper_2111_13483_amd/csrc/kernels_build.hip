@@ -1,0 +1,420 @@
+// gfx950 kernels of the H-matrix build and of every low-rank compression:
+//  * near-field assembly of the scalar Helmholtz kernel (Eq. 5-7 kernel,
+//    point collocation), one workgroup per stored near block;
+//  * partial-pivoting ACA (Eq. 9-10), one workgroup per block, rows and
+//    columns generated on the fly from the points (far field) or read from
+//    a stored dense block (fill-in blocks of the scaling coefficients,
+//    Sec. 3.4);
+//  * re-compression (the text after Eq. 10): in-place QR of U and V^T by
+//    classical Gram-Schmidt applied twice, one-sided complex Jacobi SVD of
+//    the r x r core, truncation at the same relative Frobenius tolerance,
+//    and the final factors U' = Q_U W S, V' = X^H Q_V^T.
+#include "devcommon.h"
+#include "kernels.h"
+
+namespace hs {
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int NW = NT / kWave;
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// exp(-j k r) / (4 pi r) with the products and sums rounded as written.
+__device__ __forceinline__ cd green(const double* a, const double* b, double k) {
+#pragma clang fp contract(off)
+    double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double kr = k * r;
+    double s, c;
+    sincos(kr, &s, &c);
+    double den = (4.0 * kPi) * r;
+    return cmk(c / den, -s / den);
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(NT)
+k_near_assemble(const NearTask* __restrict__ tasks, const double* __restrict__ pts, double k, double h,
+                cd* __restrict__ out, int* err) {
+    const NearTask t = tasks[blockIdx.x];
+    const int m = t.m, n = t.n;
+    cd* blk = out + t.off;
+    const bool same = t.i0 == t.j0;
+    cd self;
+    {
+#pragma clang fp contract(off)
+        double den = 2.0 * kPi * h;
+        self = cmk(1.0 / den, -(k * h / 2.0) / den);
+    }
+    for (int e = threadIdx.x; e < m * n; e += NT) {
+        const int a = e / n, b = e % n;
+        if (same && a == b) {
+            blk[e] = self;
+            continue;
+        }
+        const double* pa = pts + 3 * (int64_t)(t.i0 + a);
+        const double* pb = pts + 3 * (int64_t)(t.j0 + b);
+        if (pa[0] == pb[0] && pa[1] == pb[1] && pa[2] == pb[2]) {
+            raise_err(err, kErrCoincident);
+            blk[e] = cmk(0.0, 0.0);
+            continue;
+        }
+        // rows are observers: G(p_a, p_b); r is symmetric in its arguments
+        blk[e] = green(pb, pa, k);
+    }
+}
+
+namespace {
+
+template <bool DENSE>
+__device__ __forceinline__ cd src_val(const AcaTask& t, const double* pts, double k, const cd* dense, int i, int j) {
+    if constexpr (DENSE) {
+        return dense[t.src_off + (int64_t)i * t.n + j];
+    } else {
+        return green(pts + 3 * (int64_t)(t.s0 + j), pts + 3 * (int64_t)(t.t0 + i), k);
+    }
+}
+
+}  // namespace
+
+// Partial-pivoting ACA of one block per workgroup. U (m x cap, column-major)
+// and V (cap x n, row-major) live in the task's scratch region; flags holds
+// m + n "used" bytes.
+template <bool DENSE>
+__global__ void __launch_bounds__(NT)
+k_aca(const AcaTask* __restrict__ tasks, const double* __restrict__ pts, double k, const cd* __restrict__ dense,
+      cd* __restrict__ scratch, uint8_t* __restrict__ flags, double eps, int* __restrict__ rank_out,
+      int* __restrict__ piv_log, int piv_stride, int* err) {
+    __shared__ double redv[NW];
+    __shared__ int redi[NW];
+    __shared__ double cross_part[NW];
+    const AcaTask t = tasks[blockIdx.x];
+    const int m = t.m, n = t.n, cap = t.cap;
+    cd* U = scratch + t.u_off;
+    cd* V = scratch + t.v_off;
+    uint8_t* rused = flags + t.flag_off;
+    uint8_t* cused = rused + m;
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    for (int x = tid; x < m + n; x += NT) rused[x] = 0;
+    __syncthreads();
+    const int rmax = min(min(m, n), cap);
+    int rank = 0;
+    double norm2 = 0.0;
+    int i = 0;
+    bool capped = false;
+    while (rank < rmax) {
+        // residual row i -> V[rank, :], and its largest entry over unused columns
+        cd* vrow = V + (int64_t)rank * n;
+        ArgMax am{-1.0, 0x7fffffff};
+        for (int j = tid; j < n; j += NT) {
+            cd v = src_val<DENSE>(t, pts, k, dense, i, j);
+            for (int l = 0; l < rank; ++l) v = csub(v, cmul(U[(int64_t)l * m + i], V[(int64_t)l * n + j]));
+            vrow[j] = v;
+            if (!cused[j]) am = amax_pick(am, ArgMax{cabs2_exact(v), j});
+        }
+        am = wg_argmax<NT>(am, redv, redi);
+        if (tid == 0) rused[i] = 1;
+        __syncthreads();
+        if (!(am.v > 0.0)) {
+            // zero residual row: try the lowest unused row
+            ArgMax f{-1.0, 0x7fffffff};
+            for (int x = tid; x < m; x += NT)
+                if (!rused[x]) f = amax_pick(f, ArgMax{(double)(m - x), x});
+            f = wg_argmax<NT>(f, redv, redi);
+            if (f.v < 0.0) break;
+            i = f.i;
+            continue;
+        }
+        const int js = am.i;
+        const cd piv = vrow[js];
+        __syncthreads();
+        for (int j = tid; j < n; j += NT) vrow[j] = cdiv(vrow[j], piv);
+        // residual column js -> U[:, rank]
+        cd* ucol = U + (int64_t)rank * m;
+        for (int x = tid; x < m; x += NT) {
+            cd u = src_val<DENSE>(t, pts, k, dense, x, js);
+            for (int l = 0; l < rank; ++l) u = csub(u, cmul(V[(int64_t)l * n + js], U[(int64_t)l * m + x]));
+            ucol[x] = u;
+        }
+        __syncthreads();
+        if (tid == 0) cused[js] = 1;
+        double pu = 0.0, pv = 0.0;
+        for (int x = tid; x < m; x += NT) pu += cabs2(ucol[x]);
+        for (int x = tid; x < n; x += NT) pv += cabs2(vrow[x]);
+        const double nu2 = wg_sum<NT>(pu, redv);
+        const double nv2 = wg_sum<NT>(pv, redv);
+        // cross terms 2 Re((u_l^H u)(v_l^H v)), one previous term per wave at a time
+        double cr = 0.0;
+        for (int l = wid; l < rank; l += NW) {
+            cd du = cmk(0.0, 0.0), dv = cmk(0.0, 0.0);
+            const cd* ul = U + (int64_t)l * m;
+            const cd* vl = V + (int64_t)l * n;
+            for (int x = lane; x < m; x += kWave) du = cfmac(ul[x], ucol[x], du);
+            for (int x = lane; x < n; x += kWave) dv = cfmac(vl[x], vrow[x], dv);
+            du = wave_sum(du);
+            dv = wave_sum(dv);
+            cr += du.x * dv.x - du.y * dv.y;
+        }
+        if (lane == 0) cross_part[wid] = cr;
+        __syncthreads();
+        double cross = 0.0;
+        for (int w = 0; w < NW; ++w) cross += cross_part[w];
+        norm2 += nu2 * nv2 + 2.0 * cross;
+        if (tid == 0 && piv_log) {
+            piv_log[(int64_t)blockIdx.x * piv_stride + 2 * rank] = i;
+            piv_log[(int64_t)blockIdx.x * piv_stride + 2 * rank + 1] = js;
+        }
+        ++rank;
+        if (sqrt(nu2 * nv2) <= eps * sqrt(fmax(norm2, 0.0))) break;
+        if (rank >= rmax) {
+            if (rmax < min(m, n)) capped = true;
+            break;
+        }
+        // next row: largest |u| over unused rows
+        ArgMax nx{-1.0, 0x7fffffff};
+        for (int x = tid; x < m; x += NT)
+            if (!rused[x]) nx = amax_pick(nx, ArgMax{cabs2_exact(ucol[x]), x});
+        nx = wg_argmax<NT>(nx, redv, redi);
+        if (nx.i == 0x7fffffff) break;
+        i = nx.i;
+    }
+    if (tid == 0) {
+        rank_out[blockIdx.x] = rank;
+        if (capped) raise_err(err, kErrRankCap);
+    }
+}
+
+namespace {
+
+// In-place QR of the r columns (each of length len, stride len) of A by
+// classical Gram-Schmidt applied twice; R (r x r, column-major) receives the
+// triangular factor. hbuf: LDS of >= r entries.
+__device__ void cgs2_qr(cd* A, int len, int r, cd* R, cd* hbuf, double* red) {
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    for (int c = 0; c < r; ++c) {
+        cd* ac = A + (int64_t)c * len;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int l = wid; l < c; l += NW) {
+                const cd* al = A + (int64_t)l * len;
+                cd d = cmk(0.0, 0.0);
+                for (int x = lane; x < len; x += kWave) d = cfmac(al[x], ac[x], d);
+                d = wave_sum(d);
+                if (lane == 0) hbuf[l] = d;
+            }
+            __syncthreads();
+            for (int x = tid; x < len; x += NT) {
+                cd v = ac[x];
+                for (int l = 0; l < c; ++l) v = csub(v, cmul(A[(int64_t)l * len + x], hbuf[l]));
+                ac[x] = v;
+            }
+            for (int l = tid; l < c; l += NT) {
+                cd prev = pass == 0 ? cmk(0.0, 0.0) : R[l + (int64_t)c * r];
+                R[l + (int64_t)c * r] = cadd(prev, hbuf[l]);
+            }
+            __syncthreads();
+        }
+        double p = 0.0;
+        for (int x = tid; x < len; x += NT) p += cabs2(ac[x]);
+        const double nrm = sqrt(wg_sum<NT>(p, red));
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        for (int x = tid; x < len; x += NT) ac[x] = cscale(ac[x], inv);
+        if (tid == 0) R[c + (int64_t)c * r] = cmk(nrm, 0.0);
+        for (int l = c + 1 + tid; l < r; l += NT) R[l + (int64_t)c * r] = cmk(0.0, 0.0);
+        __syncthreads();
+    }
+}
+
+// One-sided Jacobi on the columns of M (r x r, column-major), accumulating
+// the right rotations in X (starts as I). Round-robin pairs, one pair per
+// wave at a time.
+__device__ void jacobi_svd(cd* M, cd* X, int r, int* rot_flag) {
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    const int np = (r + 1) & ~1;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) *rot_flag = 0;
+        __syncthreads();
+        for (int round = 0; round < np - 1; ++round) {
+            for (int pk = wid; pk < np / 2; pk += NW) {
+                int p, q;
+                if (pk == 0) { p = round; q = np - 1; }
+                else { p = (round + pk) % (np - 1); q = (round - pk + np - 1) % (np - 1); }
+                if (p > q) { int tt = p; p = q; q = tt; }
+                if (q >= r) continue;
+                cd* mp = M + (int64_t)p * r;
+                cd* mq = M + (int64_t)q * r;
+                double a = 0.0, b = 0.0;
+                cd c = cmk(0.0, 0.0);
+                for (int x = lane; x < r; x += kWave) {
+                    a += cabs2(mp[x]);
+                    b += cabs2(mq[x]);
+                    c = cfmac(mp[x], mq[x], c);
+                }
+                a = wave_sum(a);
+                b = wave_sum(b);
+                c = wave_sum(c);
+                const double ac = sqrt(cabs2(c));
+                if (!(ac > 1e-15 * sqrt(a * b)) || ac == 0.0) continue;
+                const double zeta = (b - a) / (2.0 * ac);
+                const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + tn * tn), sn = cs * tn;
+                const cd ph = cmk(c.x / ac, -c.y / ac);   // e^{-i phi}
+                for (int x = lane; x < r; x += kWave) {
+                    cd u = mp[x], w = cmul(ph, mq[x]);
+                    mp[x] = cmk(cs * u.x - sn * w.x, cs * u.y - sn * w.y);
+                    mq[x] = cmk(sn * u.x + cs * w.x, sn * u.y + cs * w.y);
+                }
+                cd* xp = X + (int64_t)p * r;
+                cd* xq = X + (int64_t)q * r;
+                for (int x = lane; x < r; x += kWave) {
+                    cd u = xp[x], w = cmul(ph, xq[x]);
+                    xp[x] = cmk(cs * u.x - sn * w.x, cs * u.y - sn * w.y);
+                    xq[x] = cmk(sn * u.x + cs * w.x, sn * u.y + cs * w.y);
+                }
+                if (lane == 0) *rot_flag = 1;
+            }
+            __syncthreads();
+        }
+        const int any = *rot_flag;
+        __syncthreads();
+        if (!any) break;
+    }
+}
+
+}  // namespace
+
+// Re-compression, phase A: QR of U and V^T in place, core M = R_U R_V^T,
+// Jacobi SVD, singular values sorted (descending, ties by index) and the
+// truncated rank.
+__global__ void __launch_bounds__(NT)
+k_recompress_a(const AcaTask* __restrict__ tasks, cd* __restrict__ scratch, const int* __restrict__ rank_in,
+               cd* __restrict__ ws, const int64_t* __restrict__ ws_off, double eps, int* __restrict__ rank_out) {
+    __shared__ cd hbuf[kMaxRankCap];
+    __shared__ double red[NW];
+    __shared__ int rot_flag;
+    __shared__ double sig[kMaxRankCap];
+    __shared__ int srt[kMaxRankCap];
+    const AcaTask t = tasks[blockIdx.x];
+    const int r = rank_in[blockIdx.x];
+    const int tid = threadIdx.x;
+    if (r == 0) {
+        if (tid == 0) rank_out[blockIdx.x] = 0;
+        return;
+    }
+    cd* U = scratch + t.u_off;
+    cd* V = scratch + t.v_off;
+    cd* RU = ws + ws_off[blockIdx.x];
+    cd* RV = RU + (int64_t)r * r;
+    cd* M = RV + (int64_t)r * r;
+    cd* X = M + (int64_t)r * r;
+    int* srt_g = reinterpret_cast<int*>(X + (int64_t)r * r);
+    cgs2_qr(U, t.m, r, RU, hbuf, red);
+    cgs2_qr(V, t.n, r, RV, hbuf, red);
+    for (int e = tid; e < r * r; e += NT) {
+        const int a = e % r, b = e / r;
+        cd s = cmk(0.0, 0.0);
+        // R_U upper triangular: l >= a; R_V: l >= b
+        for (int l = max(a, b); l < r; ++l) s = cfma(RU[a + (int64_t)l * r], RV[b + (int64_t)l * r], s);
+        M[e] = s;
+        X[e] = cmk(a == b ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    jacobi_svd(M, X, r, &rot_flag);
+    __syncthreads();
+    for (int c = tid; c < r; c += NT) {
+        double s = 0.0;
+        for (int x = 0; x < r; ++x) s += cabs2(M[x + (int64_t)c * r]);
+        sig[c] = sqrt(s);
+    }
+    __syncthreads();
+    // rank sort: position of column c = #{d : sig[d] > sig[c] or (== and d < c)}
+    for (int c = tid; c < r; c += NT) {
+        int pos = 0;
+        for (int d = 0; d < r; ++d) pos += (sig[d] > sig[c]) || (sig[d] == sig[c] && d < c);
+        srt[pos] = c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double tot = 0.0;
+        for (int c = 0; c < r; ++c) tot += sig[srt[c]] * sig[srt[c]];
+        const double lim = eps * sqrt(tot);
+        // smallest i with sqrt(sum_{l >= i} s_l^2) <= lim (the tail grows as i falls)
+        double tail2 = 0.0;
+        int keep = r;
+        for (int i = r - 1; i >= 0; --i) {
+            tail2 += sig[srt[i]] * sig[srt[i]];
+            if (sqrt(tail2) <= lim) keep = i;
+        }
+        rank_out[blockIdx.x] = keep;
+    }
+    for (int c = tid; c < r; c += NT) srt_g[c] = srt[c];
+}
+
+// Re-compression, phase B: write U' = Q_U M[:, srt[:r']] (m x r'
+// column-major) and V' = X[:, srt[:r']]^H Q_V^T (r' x n row-major).
+__global__ void __launch_bounds__(NT)
+k_recompress_b(const AcaTask* __restrict__ tasks, const cd* __restrict__ scratch, const int* __restrict__ rank_in,
+               const cd* __restrict__ ws, const int64_t* __restrict__ ws_off, const int* __restrict__ rank_new,
+               cd* const* __restrict__ dst) {
+    const AcaTask t = tasks[blockIdx.x];
+    const int r = rank_in[blockIdx.x], rp = rank_new[blockIdx.x];
+    if (rp == 0) return;
+    const int m = t.m, n = t.n;
+    const cd* Q = scratch + t.u_off;
+    const cd* Qv = scratch + t.v_off;
+    const cd* M = ws + ws_off[blockIdx.x] + 2 * (int64_t)r * r;
+    const cd* X = M + (int64_t)r * r;
+    const int* srt = reinterpret_cast<const int*>(X + (int64_t)r * r);
+    cd* Uo = dst[blockIdx.x];
+    if (Uo == nullptr) return;   // block kept dense
+    cd* Vo = Uo + (int64_t)m * rp;
+    for (int e = threadIdx.x; e < m * rp; e += NT) {
+        const int x = e % m, c = e / m;
+        const cd* mc = M + (int64_t)srt[c] * r;
+        cd s = cmk(0.0, 0.0);
+        for (int l = 0; l < r; ++l) s = cfma(Q[(int64_t)l * m + x], mc[l], s);
+        Uo[e] = s;
+    }
+    for (int e = threadIdx.x; e < rp * n; e += NT) {
+        const int c = e / n, y = e % n;
+        const cd* xc = X + (int64_t)srt[c] * r;
+        cd s = cmk(0.0, 0.0);
+        for (int l = 0; l < r; ++l) s = cfmac(xc[l], Qv[(int64_t)l * n + y], s);
+        Vo[e] = s;
+    }
+}
+
+// ---- launchers ----------------------------------------------------------------
+
+void launch_near_assemble(const NearTask* tasks, int64_t ntasks, const double* pts, double k, double h,
+                          cd* out, int* err, hipStream_t s) {
+    if (ntasks > 0) hipLaunchKernelGGL(k_near_assemble, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, pts, k, h, out, err);
+}
+
+void launch_aca(bool dense, const AcaTask* tasks, int64_t ntasks, const double* pts, double k, const cd* dense_src,
+                cd* scratch, uint8_t* flags, double eps, int* rank_out, int* piv_log, int piv_stride, int* err,
+                hipStream_t s) {
+    if (ntasks == 0) return;
+    if (dense)
+        hipLaunchKernelGGL(k_aca<true>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, pts, k, dense_src, scratch, flags,
+                           eps, rank_out, piv_log, piv_stride, err);
+    else
+        hipLaunchKernelGGL(k_aca<false>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, pts, k, dense_src, scratch, flags,
+                           eps, rank_out, piv_log, piv_stride, err);
+}
+
+void launch_recompress_a(const AcaTask* tasks, int64_t ntasks, cd* scratch, const int* rank_in, cd* ws,
+                         const int64_t* ws_off, double eps, int* rank_out, hipStream_t s) {
+    if (ntasks > 0)
+        hipLaunchKernelGGL(k_recompress_a, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, scratch, rank_in, ws, ws_off, eps,
+                           rank_out);
+}
+
+void launch_recompress_b(const AcaTask* tasks, int64_t ntasks, const cd* scratch, const int* rank_in, const cd* ws,
+                         const int64_t* ws_off, const int* rank_new, cd* const* dst, hipStream_t s) {
+    if (ntasks > 0)
+        hipLaunchKernelGGL(k_recompress_b, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, scratch, rank_in, ws, ws_off,
+                           rank_new, dst);
+}
+
+}  // namespace hs

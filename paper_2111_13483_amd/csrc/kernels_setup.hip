@@ -1,0 +1,188 @@
+// gfx950 kernels of the symmetric Schur-complement elimination (Sec. 3.1-3.2):
+//  * block copies (scatter of the near field into the working blocks W);
+//  * inversion of the diagonal block W_kk by in-place Gauss-Jordan with
+//    partial pivoting in LDS (the matrix inversion of Eq. 31-33);
+//  * a batched variable-size complex GEMM used for both the scaling
+//    coefficients alpha_kj = -W_kk^-1 W_kj (Eq. 14, 34-37) and the Schur
+//    updates W_ij += W_ki^T alpha_kj (Eq. 19, 38-42): 64 x 64 output tiles,
+//    4 x 4 complex register micro-tiles per thread, K staged through LDS.
+#include "devcommon.h"
+#include "kernels.h"
+
+namespace hs {
+
+namespace {
+constexpr int NT = 256;
+}
+
+__global__ void __launch_bounds__(NT)
+k_copy_blocks(const CopyTask* __restrict__ tasks, const cd* __restrict__ src, cd* __restrict__ dst) {
+    const CopyTask t = tasks[blockIdx.x];
+    const int rows = t.rows, cols = t.cols;
+    cd* d = dst + t.dst_off;
+    if (t.src_off < 0) {
+        for (int e = threadIdx.x; e < rows * cols; e += NT) d[e] = cmk(0.0, 0.0);
+        return;
+    }
+    const cd* s = src + t.src_off;
+    if (t.transpose) {
+        for (int e = threadIdx.x; e < rows * cols; e += NT) {
+            const int a = e / cols, b = e % cols;
+            d[e] = s[(int64_t)b * rows + a];
+        }
+    } else {
+        for (int e = threadIdx.x; e < rows * cols; e += NT) d[e] = s[e];
+    }
+}
+
+// In-place Gauss-Jordan inversion with partial pivoting (row pivot: largest
+// |a|^2, ties to the lowest row) of one b x b block held in LDS.
+__global__ void __launch_bounds__(NT)
+k_factor_inv(const cd* __restrict__ W, int64_t w_off, int b, cd* __restrict__ dinv, int64_t dinv_off, int* err) {
+    constexpr int LD = kMaxLeaf + 1;
+    __shared__ cd A[kMaxLeaf * LD];
+    __shared__ cd colc[kMaxLeaf];
+    __shared__ int ipiv[kMaxLeaf];
+    __shared__ int s_piv;
+    __shared__ double s_mag;
+    const int tid = threadIdx.x;
+    const cd* src = W + w_off;
+    for (int e = tid; e < b * b; e += NT) A[(e / b) * LD + e % b] = src[e];
+    __syncthreads();
+    for (int c = 0; c < b; ++c) {
+        if (tid < kWave) {
+            ArgMax am{-1.0, 0x7fffffff};
+            for (int r = c + tid; r < b; r += kWave) am = amax_pick(am, ArgMax{cabs2_exact(A[r * LD + c]), r});
+            am = wave_argmax(am);
+            if (tid == 0) { s_piv = am.i; s_mag = am.v; }
+        }
+        __syncthreads();
+        const int p = s_piv;
+        const double mag = s_mag;
+        if (!(mag > 0.0)) {
+            if (tid == 0) raise_err(err, mag == 0.0 ? kErrSingular : kErrNumeric);
+            return;
+        }
+        if (tid == 0) ipiv[c] = p;
+        if (p != c)
+            for (int j = tid; j < b; j += NT) {
+                cd tmp = A[c * LD + j];
+                A[c * LD + j] = A[p * LD + j];
+                A[p * LD + j] = tmp;
+            }
+        __syncthreads();
+        const cd inv = cdiv(cmk(1.0, 0.0), A[c * LD + c]);
+        for (int r = tid; r < b; r += NT) colc[r] = A[r * LD + c];
+        __syncthreads();
+        // scale row c (its pivot entry becomes 1/pivot)
+        for (int j = tid; j < b; j += NT) A[c * LD + j] = (j == c) ? inv : cmul(A[c * LD + j], inv);
+        __syncthreads();
+        // eliminate column c from every other row
+        for (int e = tid; e < b * b; e += NT) {
+            const int r = e / b, j = e % b;
+            if (r == c) continue;
+            const cd f = colc[r];
+            if (j == c) A[r * LD + j] = cmk(-(f.x * inv.x - f.y * inv.y), -(f.x * inv.y + f.y * inv.x));
+            else A[r * LD + j] = csub(A[r * LD + j], cmul(f, A[c * LD + j]));
+        }
+        __syncthreads();
+    }
+    // undo the row interchanges as column interchanges, last first
+    for (int c = b - 1; c >= 0; --c) {
+        const int p = ipiv[c];
+        if (p != c)
+            for (int r = tid; r < b; r += NT) {
+                cd tmp = A[r * LD + c];
+                A[r * LD + c] = A[r * LD + p];
+                A[r * LD + p] = tmp;
+            }
+        __syncthreads();
+    }
+    cd* out = dinv + dinv_off;
+    for (int e = tid; e < b * b; e += NT) out[e] = A[(e / b) * LD + e % b];
+}
+
+// Batched complex GEMM, one task per workgroup, 64 x 64 output tiles.
+template <bool TRANS_A>
+__global__ void __launch_bounds__(NT)
+k_gemm(const GemmTask* __restrict__ tasks, const cd* __restrict__ Ag, const cd* __restrict__ Bg, cd* __restrict__ Cg,
+       int accumulate, double sign) {
+    constexpr int TM = 64, TN = 64, KC = 16;
+    __shared__ cd As[KC][TM];
+    __shared__ cd Bs[KC][TN];
+    const GemmTask t = tasks[blockIdx.x];
+    const int m = t.m, n = t.n, kk = t.kk;
+    const cd* A = Ag + t.a_off;
+    const cd* B = Bg + t.b_off;
+    cd* C = Cg + t.c_off;
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    for (int m0 = 0; m0 < m; m0 += TM) {
+        for (int n0 = 0; n0 < n; n0 += TN) {
+            cd acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = cmk(0.0, 0.0);
+            for (int k0 = 0; k0 < kk; k0 += KC) {
+                __syncthreads();
+                for (int e = tid; e < KC * TM; e += NT) {
+                    const int l = e / TM, a = e % TM;
+                    const int ga = m0 + a, gl = k0 + l;
+                    cd v = cmk(0.0, 0.0);
+                    if (ga < m && gl < kk) v = TRANS_A ? A[(int64_t)gl * m + ga] : A[(int64_t)ga * kk + gl];
+                    As[l][a] = v;
+                }
+                for (int e = tid; e < KC * TN; e += NT) {
+                    const int l = e / TN, c = e % TN;
+                    const int gc = n0 + c, gl = k0 + l;
+                    Bs[l][c] = (gc < n && gl < kk) ? B[(int64_t)gl * n + gc] : cmk(0.0, 0.0);
+                }
+                __syncthreads();
+#pragma unroll 4
+                for (int l = 0; l < KC; ++l) {
+                    cd av[4], bv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) av[i] = As[l][ty * 4 + i];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) bv[j] = Bs[l][tx * 4 + j];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) acc[i][j] = cfma(av[i], bv[j], acc[i][j]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ga = m0 + ty * 4 + i;
+                if (ga >= m) continue;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int gc = n0 + tx * 4 + j;
+                    if (gc >= n) continue;
+                    cd v = cscale(acc[i][j], sign);
+                    cd* dst = C + (int64_t)ga * n + gc;
+                    *dst = accumulate ? cadd(*dst, v) : v;
+                }
+            }
+        }
+    }
+}
+
+void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s) {
+    if (ntasks > 0) hipLaunchKernelGGL(k_copy_blocks, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, src, dst);
+}
+
+void launch_factor_inv(const cd* W, int64_t w_off, int b, cd* dinv, int64_t dinv_off, int* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_factor_inv, dim3(1), dim3(NT), 0, s, W, w_off, b, dinv, dinv_off, err);
+}
+
+void launch_gemm(const GemmTask* tasks, int64_t ntasks, const cd* A, const cd* B, cd* C, bool transA, bool accumulate,
+                 double sign, hipStream_t s) {
+    if (ntasks == 0) return;
+    if (transA)
+        hipLaunchKernelGGL(k_gemm<true>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, A, B, C, (int)accumulate, sign);
+    else
+        hipLaunchKernelGGL(k_gemm<false>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, A, B, C, (int)accumulate, sign);
+}
+
+}  // namespace hs
