@@ -3,10 +3,6 @@
 //    is read once and applied as Z_ij x_j and Z_ij^T x_i; each far block
 //    gives U (V x_s) and V^T (U^T x_t); per-block results go to private
 //    slots and a per-leaf gather sums them in a fixed order (deterministic);
-//  * preconditioner apply P^-1 v = alpha D^-1 alpha^T v (Eq. 23, 24, 28):
-//    forward and backward block sweeps as single launches in which each
-//    workgroup takes block rows by ticket and waits on per-block ready
-//    flags (no grid-wide barrier), with D_k^-1 fused into the forward sweep;
 //  * right-preconditioned GMRES building blocks with per-column state:
 //    classical Gram-Schmidt twice, complex Givens rotations, restart.
 #include "devcommon.h"
@@ -190,245 +186,6 @@ k_gather(const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ gptr,
             acc = cadd(acc, slots[g.base * nrhs + g.off + a + (int64_t)c * g.len]);
         }
         y[i0 + a + (int64_t)c * n] = acc;
-    }
-}
-
-// ---------------------------------------------------------------- sweeps
-namespace {
-
-__device__ __forceinline__ int take_ticket(unsigned long long* ctr, unsigned long long base, int* s_t) {
-    __syncthreads();
-    if (threadIdx.x == 0) *s_t = (int)(atomicAdd(ctr, 1ull) - base);
-    __syncthreads();
-    return *s_t;
-}
-
-__device__ __forceinline__ void wait_ready(const int* flag, int epoch) {
-    if (threadIdx.x == 0) {
-        while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch)
-            __builtin_amdgcn_s_sleep(1);
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ void set_ready(int* flag, int epoch) {
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-}  // namespace
-
-// Forward sweep y_j = v_j + sum_{k < j, j in S_k} alpha_kj^T y_k, then
-// zt_j = D_j^-1 y_j. Blocks are taken in increasing j.
-__global__ void __launch_bounds__(NT)
-k_sweep_fwd(int nb, const int64_t* __restrict__ blk_start, const int32_t* __restrict__ blk_size,
-            const int64_t* __restrict__ colptr, const SweepEnt* __restrict__ colent, const cd* __restrict__ alpha,
-            const cd* __restrict__ dinv, const int64_t* __restrict__ dinv_off, const cd* __restrict__ v,
-            cd* __restrict__ yw, cd* __restrict__ zt, int64_t n, int nrhs, int* flags, unsigned long long* ctr,
-            unsigned long long base, int epoch) {
-    __shared__ int s_t;
-    __shared__ cd yk[kMaxLeaf * SCH];
-    __shared__ cd tl[kMaxLeaf * SCH];
-    __shared__ cd part[NW][kMaxLeaf * SCH];
-    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
-    for (;;) {
-        const int j = take_ticket(ctr, base, &s_t);
-        if (j >= nb) return;
-        const int bj = blk_size[j];
-        const int64_t sj = blk_start[j];
-        for (int c0 = 0; c0 < nrhs; c0 += SCH) {
-            const int cs = min(SCH, nrhs - c0);
-            cd acc[2][SCH];
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int c = 0; c < SCH; ++c) acc[q][c] = cmk(0.0, 0.0);
-            for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) {
-                const SweepEnt ent = colent[e];
-                const int k = ent.k, bk = blk_size[k];
-                wait_ready(flags + k, epoch);
-                const int64_t sk = blk_start[k];
-                for (int q = tid; q < bk * cs; q += NT) yk[q] = yw[sk + q % bk + (int64_t)(c0 + q / bk) * n];
-                __syncthreads();
-                const cd* A = alpha + ent.off;
-                if (ent.rank < 0) {
-                    // dense alpha_kj (bk x bj row-major): out[b] += sum_a A[a][b] y_k[a]
-                    for (int a = wid; a < bk; a += NW) {
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            const int b = lane + q * kWave;
-                            if (b < bj) {
-                                const cd z = A[(int64_t)a * bj + b];
-#pragma unroll
-                                for (int c = 0; c < SCH; ++c)
-                                    if (c < cs) acc[q][c] = cfma(z, yk[a + c * bk], acc[q][c]);
-                            }
-                        }
-                    }
-                } else {
-                    // alpha_kj = U V: out += V^T (U^T y_k)
-                    const int r = ent.rank;
-                    const cd* Uf = A;
-                    const cd* Vf = A + (int64_t)bk * r;
-                    for (int l = wid; l < r; l += NW) {
-                        cd s[SCH];
-#pragma unroll
-                        for (int c = 0; c < SCH; ++c) s[c] = cmk(0.0, 0.0);
-                        for (int a = lane; a < bk; a += kWave) {
-                            const cd u = Uf[(int64_t)l * bk + a];
-#pragma unroll
-                            for (int c = 0; c < SCH; ++c)
-                                if (c < cs) s[c] = cfma(u, yk[a + c * bk], s[c]);
-                        }
-#pragma unroll
-                        for (int c = 0; c < SCH; ++c) {
-                            cd w = wave_sum(s[c]);
-                            if (lane == 0) tl[l * SCH + c] = w;
-                        }
-                    }
-                    __syncthreads();
-                    for (int l = wid; l < r; l += NW) {
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            const int b = lane + q * kWave;
-                            if (b < bj) {
-                                const cd z = Vf[(int64_t)l * bj + b];
-#pragma unroll
-                                for (int c = 0; c < SCH; ++c)
-                                    if (c < cs) acc[q][c] = cfma(z, tl[l * SCH + c], acc[q][c]);
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-            // reduce the wave partials, add v_j
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int b = lane + q * kWave;
-                if (b < bj)
-#pragma unroll
-                    for (int c = 0; c < SCH; ++c)
-                        if (c < cs) part[wid][b + c * bj] = acc[q][c];
-            }
-            __syncthreads();
-            for (int q = tid; q < bj * cs; q += NT) {
-                cd s = v[sj + q % bj + (int64_t)(c0 + q / bj) * n];
-#pragma unroll
-                for (int w = 0; w < NW; ++w) s = cadd(s, part[w][q]);
-                yk[q] = s;
-                yw[sj + q % bj + (int64_t)(c0 + q / bj) * n] = s;
-            }
-            __syncthreads();
-            // zt_j = D_j^-1 y_j (row a per wave, lanes over columns)
-            const cd* Di = dinv + dinv_off[j];
-            for (int a = wid; a < bj; a += NW) {
-                cd s[SCH];
-#pragma unroll
-                for (int c = 0; c < SCH; ++c) s[c] = cmk(0.0, 0.0);
-                for (int b = lane; b < bj; b += kWave) {
-                    const cd d = Di[(int64_t)a * bj + b];
-#pragma unroll
-                    for (int c = 0; c < SCH; ++c)
-                        if (c < cs) s[c] = cfma(d, yk[b + c * bj], s[c]);
-                }
-#pragma unroll
-                for (int c = 0; c < SCH; ++c) {
-                    if (c < cs) {
-                        cd w = wave_sum(s[c]);
-                        if (lane == 0) zt[sj + a + (int64_t)(c0 + c) * n] = w;
-                    }
-                }
-            }
-        }
-        set_ready(flags + j, epoch);
-    }
-}
-
-// Backward sweep z_k = zt_k + sum_{j in S_k} alpha_kj z_j, blocks taken in
-// decreasing k.
-__global__ void __launch_bounds__(NT)
-k_sweep_bwd(int nb, const int64_t* __restrict__ blk_start, const int32_t* __restrict__ blk_size,
-            const int64_t* __restrict__ rowptr, const SweepEnt* __restrict__ rowent, const cd* __restrict__ alpha,
-            const cd* __restrict__ zt, cd* __restrict__ z, int64_t n, int nrhs, int* flags, unsigned long long* ctr,
-            unsigned long long base, int epoch) {
-    __shared__ int s_t;
-    __shared__ cd zj[kMaxLeaf * SCH];
-    __shared__ cd tl[kMaxLeaf * SCH];
-    __shared__ cd acc[kMaxLeaf * SCH];
-    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
-    for (;;) {
-        const int t = take_ticket(ctr, base, &s_t);
-        if (t >= nb) return;
-        const int k = nb - 1 - t;
-        const int bk = blk_size[k];
-        const int64_t sk = blk_start[k];
-        for (int c0 = 0; c0 < nrhs; c0 += SCH) {
-            const int cs = min(SCH, nrhs - c0);
-            for (int q = tid; q < bk * cs; q += NT) acc[q] = zt[sk + q % bk + (int64_t)(c0 + q / bk) * n];
-            __syncthreads();
-            for (int64_t e = rowptr[k + 1] - 1; e >= rowptr[k]; --e) {
-                const SweepEnt ent = rowent[e];
-                const int j = ent.k, bj = blk_size[j];
-                wait_ready(flags + j, epoch);
-                const int64_t sj = blk_start[j];
-                for (int q = tid; q < bj * cs; q += NT) zj[q] = z[sj + q % bj + (int64_t)(c0 + q / bj) * n];
-                __syncthreads();
-                const cd* A = alpha + ent.off;
-                if (ent.rank < 0) {
-                    // dense alpha_kj (bk x bj row-major): acc[a] += sum_b A[a][b] z_j[b]
-                    for (int a = wid; a < bk; a += NW) {
-                        cd s[SCH];
-#pragma unroll
-                        for (int c = 0; c < SCH; ++c) s[c] = cmk(0.0, 0.0);
-                        for (int b = lane; b < bj; b += kWave) {
-                            const cd d = A[(int64_t)a * bj + b];
-#pragma unroll
-                            for (int c = 0; c < SCH; ++c)
-                                if (c < cs) s[c] = cfma(d, zj[b + c * bj], s[c]);
-                        }
-#pragma unroll
-                        for (int c = 0; c < SCH; ++c) {
-                            if (c < cs) {
-                                cd w = wave_sum(s[c]);
-                                if (lane == 0) acc[a + c * bk] = cadd(acc[a + c * bk], w);
-                            }
-                        }
-                    }
-                } else {
-                    const int r = ent.rank;
-                    const cd* Uf = A;
-                    const cd* Vf = A + (int64_t)bk * r;
-                    for (int l = wid; l < r; l += NW) {
-                        cd s[SCH];
-#pragma unroll
-                        for (int c = 0; c < SCH; ++c) s[c] = cmk(0.0, 0.0);
-                        for (int b = lane; b < bj; b += kWave) {
-                            const cd d = Vf[(int64_t)l * bj + b];
-#pragma unroll
-                            for (int c = 0; c < SCH; ++c)
-                                if (c < cs) s[c] = cfma(d, zj[b + c * bj], s[c]);
-                        }
-#pragma unroll
-                        for (int c = 0; c < SCH; ++c) {
-                            cd w = wave_sum(s[c]);
-                            if (lane == 0) tl[l * SCH + c] = w;
-                        }
-                    }
-                    __syncthreads();
-                    for (int q = tid; q < bk * cs; q += NT) {
-                        const int a = q % bk, c = q / bk;
-                        cd s = acc[q];
-                        for (int l = 0; l < r; ++l) s = cfma(Uf[(int64_t)l * bk + a], tl[l * SCH + c], s);
-                        acc[q] = s;
-                    }
-                }
-                __syncthreads();
-            }
-            for (int q = tid; q < bk * cs; q += NT) z[sk + q % bk + (int64_t)(c0 + q / bk) * n] = acc[q];
-            __syncthreads();
-        }
-        set_ready(flags + k, epoch);
     }
 }
 
@@ -714,21 +471,6 @@ void launch_far_mv(const AcaTask* geom, const int* rank, cd* const* uv, const in
 void launch_gather(const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb, const cd* slots,
                    int64_t n, int nrhs, cd* y, hipStream_t s) {
     hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(kWave), 0, s, leaf_off, gptr, gent, slots, n, nrhs, y);
-}
-
-int sweep_grid(int64_t nb) { return (int)(nb < 512 ? nb : 512); }
-
-void launch_sweeps(int64_t nb, const int64_t* blk_start, const int32_t* blk_size, const int64_t* colptr,
-                   const SweepEnt* colent, const int64_t* rowptr, const SweepEnt* rowent, const cd* alpha,
-                   const cd* dinv, const int64_t* dinv_off, const cd* v, cd* ywork, cd* z, int64_t n, int nrhs,
-                   int* flags, unsigned long long* tickets, int epoch, hipStream_t s) {
-    const int G = sweep_grid(nb);
-    const unsigned long long base = (unsigned long long)(epoch - 1) * (unsigned long long)(nb + G);
-    // flags: [0, nb) forward, [nb, 2 nb) backward; tickets[0] forward, tickets[1] backward
-    hipLaunchKernelGGL(k_sweep_fwd, dim3(G), dim3(NT), 0, s, (int)nb, blk_start, blk_size, colptr, colent, alpha, dinv,
-                       dinv_off, v, ywork, ywork + n * nrhs, n, nrhs, flags, tickets, base, epoch);
-    hipLaunchKernelGGL(k_sweep_bwd, dim3(G), dim3(NT), 0, s, (int)nb, blk_start, blk_size, rowptr, rowent, alpha,
-                       (const cd*)(ywork + n * nrhs), z, n, nrhs, flags + nb, tickets + 1, base, epoch);
 }
 
 void launch_dots(const cd* V, int64_t ldv, int64_t vstride, int nvec, const cd* w, int64_t n, int nrhs,
