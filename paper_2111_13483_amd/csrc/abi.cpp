@@ -190,6 +190,9 @@ struct hs_precond {
     hs::SweepEnt* d_rowent = nullptr;
     int64_t* d_colptr = nullptr;
     hs::SweepEnt* d_colent = nullptr;
+    // chunked sweeps
+    int64_t nchunk = 0, linv_elems = 0;
+    hs::SweepPlan sp{};
 };
 
 namespace {
@@ -396,26 +399,27 @@ void matvec_tree(const hs_hmatrix* H, const cd* x, cd* y, int nrhs, cd* slots, h
 }
 
 struct SweepWs {
-    cd* ywork = nullptr;
-    int* flags = nullptr;
-    unsigned long long* tickets = nullptr;
+    hs::SweepWork w{};
     int epoch = 0;
 };
 
 void apply_tree(const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, hipStream_t s) {
     ws.epoch += 1;
-    hs::launch_sweeps(P->nb, P->d_bstart, P->d_bsize, P->d_colptr, P->d_colent, P->d_rowptr, P->d_rowent, P->d_alpha,
-                      P->d_dinv, P->d_dinv_off, v, ws.ywork, z, P->H->n, nrhs, ws.flags, ws.tickets, ws.epoch, s);
+    hs::launch_sweeps(P->sp, v, z, nrhs, ws.w, ws.epoch, s);
 }
 
 SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
-    SweepWs w;
-    w.ywork = o.get<cd>((size_t)2 * P->H->n * nrhs);
-    w.flags = o.get<int>((size_t)2 * P->nb);
-    w.tickets = o.get<unsigned long long>(2);
-    hip_check(hipMemsetAsync(w.flags, 0, sizeof(int) * 2 * P->nb, s), "memset flags");
-    hip_check(hipMemsetAsync(w.tickets, 0, sizeof(unsigned long long) * 2, s), "memset tickets");
-    return w;
+    SweepWs sw;
+    const size_t nn = (size_t)P->H->n * nrhs;
+    sw.w.yw = o.get<cd>(nn);
+    sw.w.zt = o.get<cd>(nn);
+    sw.w.rbuf = o.get<cd>(nn);
+    sw.w.rbuf2 = o.get<cd>(nn);
+    sw.w.flags = o.get<int>((size_t)4 * P->nb);
+    sw.w.tickets = o.get<unsigned long long>(2);
+    hip_check(hipMemsetAsync(sw.w.flags, 0, sizeof(int) * 4 * P->nb, s), "memset flags");
+    hip_check(hipMemsetAsync(sw.w.tickets, 0, sizeof(unsigned long long) * 2, s), "memset tickets");
+    return sw;
 }
 
 }  // namespace
@@ -933,24 +937,110 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             P->d_alpha = o.get<cd>(std::max<int64_t>(atot, 1));
             hip_check(hipMemcpyAsync(P->d_alpha, Ad, atot * 16, hipMemcpyDeviceToDevice, s), "D2D");
         }
-        // sweep structures
-        std::vector<hs::SweepEnt> rowent(nnz);
-        for (int64_t e = 0; e < nnz; ++e) rowent[e] = hs::SweepEnt{P->a_off[e], (int32_t)sy.cols[e], P->a_rank[e]};
-        std::vector<int64_t> colptr(nb + 1, 0);
-        for (int64_t e = 0; e < nnz; ++e) colptr[sy.cols[e] + 1]++;
-        for (int64_t j = 0; j < nb; ++j) colptr[j + 1] += colptr[j];
-        std::vector<hs::SweepEnt> colent(nnz);
-        std::vector<int64_t> fillp(colptr.begin(), colptr.end() - 1);
-        for (int64_t kk = 0; kk < nb; ++kk)   // rows ascending -> each column's list sorted by k
-            for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e)
-                colent[fillp[sy.cols[e]]++] = hs::SweepEnt{P->a_off[e], (int32_t)kk, P->a_rank[e]};
+        // ---- chunked sweep plan: consecutive block rows grouped up to kMaxChunk points
+        std::vector<int32_t> chunk_of(nb), loc(nb), wdt(nb), cfirst(nb), clast(nb), chunk_first;
+        std::vector<int64_t> pos(nb);
+        {
+            int64_t pp = 0;
+            int32_t cur = -1, used = hs::kMaxChunk;
+            for (int64_t kk = 0; kk < nb; ++kk) {
+                const int32_t bk = P->bsize[kk];
+                if (used + bk > hs::kMaxChunk) {
+                    ++cur;
+                    used = 0;
+                    chunk_first.push_back((int32_t)kk);
+                }
+                chunk_of[kk] = cur;
+                loc[kk] = used;
+                used += bk;
+                wdt[kk] = used;
+                pos[kk] = pp;
+                pp += bk;
+            }
+            chunk_first.push_back((int32_t)nb);
+            for (size_t c = 0; c + 1 < chunk_first.size(); ++c)
+                for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) {
+                    cfirst[kk] = chunk_first[c];
+                    clast[kk] = chunk_first[c + 1] - 1;
+                }
+        }
+        P->nchunk = (int64_t)chunk_first.size() - 1;
+        std::vector<int64_t> linv_off(nb);
+        int64_t ltot = 0;
+        for (int64_t kk = 0; kk < nb; ++kk) {
+            linv_off[kk] = ltot;
+            ltot += (int64_t)P->bsize[kk] * wdt[kk];
+        }
+        P->linv_elems = ltot;
+        // entries: in-chunk ones feed Linv, cross-chunk ones the sweeps
+        std::vector<int64_t> colptr(nb + 1, 0), rowptr(nb + 1, 0), intptr(nb + 1, 0);
+        for (int64_t e = 0; e < nnz; ++e) {
+            const int64_t kk = row_of[e], j = sy.cols[e];
+            if (chunk_of[kk] == chunk_of[j]) intptr[j + 1]++;
+            else {
+                colptr[j + 1]++;
+                rowptr[kk + 1]++;
+            }
+        }
+        for (int64_t j = 0; j < nb; ++j) {
+            colptr[j + 1] += colptr[j];
+            rowptr[j + 1] += rowptr[j];
+            intptr[j + 1] += intptr[j];
+        }
+        std::vector<hs::SweepEnt> colent(colptr[nb]), rowent(rowptr[nb]), intent(intptr[nb]);
+        std::vector<hs::ExpandTask> expand;
+        {
+            std::vector<int64_t> fc(colptr.begin(), colptr.end() - 1), fr(rowptr.begin(), rowptr.end() - 1),
+                fi(intptr.begin(), intptr.end() - 1);
+            for (int64_t kk = 0; kk < nb; ++kk)   // rows ascending: per-column lists sorted by k
+                for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
+                    const int64_t j = sy.cols[e];
+                    if (chunk_of[kk] == chunk_of[j]) {
+                        intent[fi[j]++] = hs::SweepEnt{ad_off[e], (int32_t)kk, -1};
+                        if (P->a_rank[e] >= 0)
+                            expand.push_back(hs::ExpandTask{P->a_off[e], ad_off[e], P->bsize[kk], P->bsize[j],
+                                                            P->a_rank[e], 0});
+                    } else {
+                        colent[fc[j]++] = hs::SweepEnt{P->a_off[e], (int32_t)kk, P->a_rank[e]};
+                        rowent[fr[kk]++] = hs::SweepEnt{P->a_off[e], (int32_t)j, P->a_rank[e]};
+                    }
+                }
+        }
         P->d_bstart = o.upload(P->bstart, s);
         P->d_bsize = o.upload(P->bsize, s);
         P->d_dinv_off = o.upload(P->d_off, s);
-        P->d_rowptr = o.upload(sy.rowptr, s);
+        P->d_rowptr = o.upload(rowptr, s);
         P->d_rowent = o.upload(rowent, s);
         P->d_colptr = o.upload(colptr, s);
         P->d_colent = o.upload(colent, s);
+        hs::SweepPlan& sp = P->sp;
+        sp.nb = (int)nb;
+        sp.n = H->n;
+        sp.bstart = P->d_bstart;
+        sp.bsize = P->d_bsize;
+        sp.pos = o.upload(pos, s);
+        sp.loc = o.upload(loc, s);
+        sp.w = o.upload(wdt, s);
+        sp.cfirst = o.upload(cfirst, s);
+        sp.clast = o.upload(clast, s);
+        sp.linv_off = o.upload(linv_off, s);
+        cd* d_linv = o.get<cd>(std::max<int64_t>(ltot, 1));
+        sp.linv = d_linv;
+        sp.colptr = P->d_colptr;
+        sp.colent = P->d_colent;
+        sp.rowptr = P->d_rowptr;
+        sp.rowent = P->d_rowent;
+        sp.alpha = P->d_alpha;
+        sp.dinv = P->d_dinv;
+        sp.dinv_off = P->d_dinv_off;
+        // in-chunk compressed blocks enter Linv as their U V product (the same operator as the apply)
+        hs::ExpandTask* d_exp = tmp.upload(expand, s);
+        hs::launch_lr_expand(d_exp, (int64_t)expand.size(), P->d_alpha, Ad, s);
+        int32_t* d_cf = tmp.upload(chunk_first, s);
+        int64_t* d_ip = tmp.upload(intptr, s);
+        hs::SweepEnt* d_ie = tmp.upload(intent, s);
+        hs::launch_linv(sp, (int)P->nchunk, d_cf, d_ip, d_ie, Ad, d_linv, s);
+        hip_check(hipGetLastError(), "linv launches");
         hip_check(hipStreamSynchronize(s), "stream sync");
         tmp.release();
         hs_info info;

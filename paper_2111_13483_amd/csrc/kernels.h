@@ -87,15 +87,56 @@ void launch_far_mv(const AcaTask* geom, const int* rank, cd* const* uv, const in
                    const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
 void launch_gather(const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb, const cd* slots,
                    int64_t n, int nrhs, cd* y, hipStream_t s);
-// P^-1 v: forward sweep with D^-1 fused, then backward sweep. v, z: tree order.
-// ywork: 2 n nrhs elements; flags: 2 nb ints (zeroed once); tickets: 2
-// counters (zeroed once); epoch: 1, 2, ... for successive applies on the
-// same flags/tickets.
-void launch_sweeps(int64_t nb, const int64_t* blk_start, const int32_t* blk_size, const int64_t* colptr,
-                   const SweepEnt* colent, const int64_t* rowptr, const SweepEnt* rowent, const cd* alpha,
-                   const cd* dinv, const int64_t* dinv_off, const cd* v, cd* ywork, cd* z, int64_t n, int nrhs,
-                   int* flags, unsigned long long* tickets, int epoch, hipStream_t s);
+// P^-1 v = alpha D^-1 alpha^T v by chunked sweeps. Block rows (elimination
+// order) are grouped into chunks of consecutive rows; the coupling inside a
+// chunk is applied through the explicit inverse Linv of the chunk's unit
+// lower-triangular factor, so the dependency chain advances a chunk at a
+// time. Per block row k: pos = elimination-order offset, loc = offset inside
+// its chunk, w = loc + b_k (row width of its Linv rows), cfirst / clast =
+// first / last block of its chunk, linv_off = start of its b_k x w rows.
+struct SweepPlan {
+    int nb;
+    int64_t n;
+    const int64_t* bstart;     // tree-order start of block k
+    const int32_t* bsize;
+    const int64_t* pos;
+    const int32_t* loc;
+    const int32_t* w;
+    const int32_t* cfirst;
+    const int32_t* clast;
+    const int64_t* linv_off;
+    const cd* linv;
+    const int64_t* colptr;     // forward: cross-chunk entries (k, j) listed per column j, k ascending
+    const SweepEnt* colent;
+    const int64_t* rowptr;     // backward: cross-chunk entries (k, j) listed per row k, j ascending
+    const SweepEnt* rowent;
+    const cd* alpha;
+    const cd* dinv;
+    const int64_t* dinv_off;
+};
+// Work buffers of one apply stream: yw, zt, rbuf, rbuf2 (n nrhs each),
+// flags (4 nb ints, zeroed once), tickets (2, zeroed once).
+struct SweepWork {
+    cd* yw;
+    cd* zt;
+    cd* rbuf;
+    cd* rbuf2;
+    int* flags;
+    unsigned long long* tickets;
+};
+constexpr int kMaxChunk = 384;   // points per chunk (bounds the Linv row width)
+void launch_sweeps(const SweepPlan& p, const cd* v, cd* z, int nrhs, const SweepWork& w, int epoch, hipStream_t s);
 int sweep_grid(int64_t nb);
+// Linv of every chunk from the dense alpha blocks inside it (intptr/intent:
+// per column j the in-chunk entries (k, j), offsets into A).
+void launch_linv(const SweepPlan& p, int nchunk, const int32_t* chunk_first, const int64_t* intptr,
+                 const SweepEnt* intent, const cd* A, cd* linv, hipStream_t s);
+// dst (m x n row-major) = U V for low-rank blocks (U m x r column-major then V r x n row-major at src_off).
+struct ExpandTask {
+    int64_t src_off, dst_off;
+    int32_t m, n, r, pad;
+};
+void launch_lr_expand(const ExpandTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s);
 
 // ---- GMRES (per-column state on device) ----
 struct ColState {
