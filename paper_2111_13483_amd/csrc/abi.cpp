@@ -411,7 +411,8 @@ void apply_tree(const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, 
 SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
     SweepWs sw;
     const size_t nn = (size_t)P->H->n * nrhs;
-    sw.w.yw = o.get<cd>(nn);
+    sw.w.ybuf = o.get<cd>(nn);
+    sw.w.zbuf = o.get<cd>(nn);
     sw.w.zt = o.get<cd>(nn);
     sw.w.rbuf = o.get<cd>(nn);
     sw.w.rbuf2 = o.get<cd>(nn);
@@ -938,7 +939,8 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             hip_check(hipMemcpyAsync(P->d_alpha, Ad, atot * 16, hipMemcpyDeviceToDevice, s), "D2D");
         }
         // ---- chunked sweep plan: consecutive block rows grouped up to kMaxChunk points
-        std::vector<int32_t> chunk_of(nb), loc(nb), wdt(nb), cfirst(nb), clast(nb), chunk_first;
+        std::vector<int32_t> chunk_of(nb), loc(nb), wdt(nb), wtt(nb), cfirst(nb), clast(nb), chunk_first;
+        std::vector<int32_t> pf(nb, -1), pl(nb, -1), nf(nb, -1), nl(nb, -1);
         std::vector<int64_t> pos(nb);
         {
             int64_t pp = 0;
@@ -958,26 +960,47 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
                 pp += bk;
             }
             chunk_first.push_back((int32_t)nb);
-            for (size_t c = 0; c + 1 < chunk_first.size(); ++c)
-                for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) {
-                    cfirst[kk] = chunk_first[c];
-                    clast[kk] = chunk_first[c + 1] - 1;
-                }
         }
-        P->nchunk = (int64_t)chunk_first.size() - 1;
-        std::vector<int64_t> linv_off(nb);
-        int64_t ltot = 0;
+        const int64_t nch = (int64_t)chunk_first.size() - 1;
+        P->nchunk = nch;
+        std::vector<int32_t> csize(nch);
+        for (int64_t c = 0; c < nch; ++c) {
+            int32_t sz = 0;
+            for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) sz += P->bsize[kk];
+            csize[c] = sz;
+            for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) {
+                cfirst[kk] = chunk_first[c];
+                clast[kk] = chunk_first[c + 1] - 1;
+                wtt[kk] = sz - loc[kk];
+                if (c > 0) { pf[kk] = chunk_first[c - 1]; pl[kk] = chunk_first[c] - 1; }
+                if (c + 1 < nch) { nf[kk] = chunk_first[c + 1]; nl[kk] = chunk_first[c + 2] - 1; }
+            }
+        }
+        std::vector<int64_t> lf_off(nb), lb_off(nb), mf_off(nb), mb_off(nb), cf_off(nch, -1), cb_off(nch, -1);
+        int64_t lft = 0, lbt = 0, mft = 0, mbt = 0, cft = 0, cbt = 0;
         for (int64_t kk = 0; kk < nb; ++kk) {
-            linv_off[kk] = ltot;
-            ltot += (int64_t)P->bsize[kk] * wdt[kk];
+            const int64_t bk = P->bsize[kk], c = chunk_of[kk];
+            lf_off[kk] = lft;
+            lft += bk * wdt[kk];
+            lb_off[kk] = lbt;
+            lbt += bk * wtt[kk];
+            mf_off[kk] = mft;
+            mft += c > 0 ? bk * csize[c - 1] : 0;
+            mb_off[kk] = mbt;
+            mbt += c + 1 < nch ? bk * csize[c + 1] : 0;
         }
-        P->linv_elems = ltot;
-        // entries: in-chunk ones feed Linv, cross-chunk ones the sweeps
+        for (int64_t c = 0; c < nch; ++c) {
+            if (c > 0) { cf_off[c] = cft; cft += (int64_t)csize[c] * csize[c - 1]; }
+            if (c + 1 < nch) { cb_off[c] = cbt; cbt += (int64_t)csize[c] * csize[c + 1]; }
+        }
+        P->linv_elems = lft + lbt + mft + mbt;
+        // entries: in-chunk ones feed Linv, adjacent-chunk ones the coupling products, the rest phase A
         std::vector<int64_t> colptr(nb + 1, 0), rowptr(nb + 1, 0), intptr(nb + 1, 0);
         for (int64_t e = 0; e < nnz; ++e) {
             const int64_t kk = row_of[e], j = sy.cols[e];
-            if (chunk_of[kk] == chunk_of[j]) intptr[j + 1]++;
-            else {
+            const int32_t d = chunk_of[j] - chunk_of[kk];
+            if (d == 0) intptr[j + 1]++;
+            else if (d >= 2) {
                 colptr[j + 1]++;
                 rowptr[kk + 1]++;
             }
@@ -989,17 +1012,26 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         }
         std::vector<hs::SweepEnt> colent(colptr[nb]), rowent(rowptr[nb]), intent(intptr[nb]);
         std::vector<hs::ExpandTask> expand;
+        std::vector<hs::CopyTask> cfc, cbc;
         {
             std::vector<int64_t> fc(colptr.begin(), colptr.end() - 1), fr(rowptr.begin(), rowptr.end() - 1),
                 fi(intptr.begin(), intptr.end() - 1);
             for (int64_t kk = 0; kk < nb; ++kk)   // rows ascending: per-column lists sorted by k
                 for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
                     const int64_t j = sy.cols[e];
-                    if (chunk_of[kk] == chunk_of[j]) {
+                    const int32_t ck = chunk_of[kk], cj = chunk_of[j];
+                    const int32_t bk = P->bsize[kk], bj = P->bsize[j];
+                    if (cj - ck <= 1 && P->a_rank[e] >= 0)
+                        expand.push_back(hs::ExpandTask{P->a_off[e], ad_off[e], bk, bj, P->a_rank[e], 0});
+                    if (cj == ck) {
                         intent[fi[j]++] = hs::SweepEnt{ad_off[e], (int32_t)kk, -1};
-                        if (P->a_rank[e] >= 0)
-                            expand.push_back(hs::ExpandTask{P->a_off[e], ad_off[e], P->bsize[kk], P->bsize[j],
-                                                            P->a_rank[e], 0});
+                    } else if (cj == ck + 1) {
+                        // forward coupling C_cj: rows of block j, columns of block k (alpha_kj^T)
+                        cfc.push_back(hs::CopyTask{cf_off[cj] + (int64_t)loc[j] * csize[ck] + loc[kk], ad_off[e], bj, bk,
+                                                   1, csize[ck]});
+                        // backward coupling C_cj^T: rows of block k, columns of block j (alpha_kj)
+                        cbc.push_back(hs::CopyTask{cb_off[ck] + (int64_t)loc[kk] * csize[cj] + loc[j], ad_off[e], bk, bj,
+                                                   0, csize[cj]});
                     } else {
                         colent[fc[j]++] = hs::SweepEnt{P->a_off[e], (int32_t)kk, P->a_rank[e]};
                         rowent[fr[kk]++] = hs::SweepEnt{P->a_off[e], (int32_t)j, P->a_rank[e]};
@@ -1021,11 +1053,25 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         sp.pos = o.upload(pos, s);
         sp.loc = o.upload(loc, s);
         sp.w = o.upload(wdt, s);
+        sp.wt = o.upload(wtt, s);
         sp.cfirst = o.upload(cfirst, s);
         sp.clast = o.upload(clast, s);
-        sp.linv_off = o.upload(linv_off, s);
-        cd* d_linv = o.get<cd>(std::max<int64_t>(ltot, 1));
-        sp.linv = d_linv;
+        sp.pf = o.upload(pf, s);
+        sp.pl = o.upload(pl, s);
+        sp.nf = o.upload(nf, s);
+        sp.nl = o.upload(nl, s);
+        sp.lf_off = o.upload(lf_off, s);
+        sp.lb_off = o.upload(lb_off, s);
+        sp.mf_off = o.upload(mf_off, s);
+        sp.mb_off = o.upload(mb_off, s);
+        cd* d_lf = o.get<cd>(std::max<int64_t>(lft, 1));
+        cd* d_lb = o.get<cd>(std::max<int64_t>(lbt, 1));
+        cd* d_mf = o.get<cd>(std::max<int64_t>(mft, 1));
+        cd* d_mb = o.get<cd>(std::max<int64_t>(mbt, 1));
+        sp.lf = d_lf;
+        sp.lb = d_lb;
+        sp.mf = d_mf;
+        sp.mb = d_mb;
         sp.colptr = P->d_colptr;
         sp.colent = P->d_colent;
         sp.rowptr = P->d_rowptr;
@@ -1033,13 +1079,35 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         sp.alpha = P->d_alpha;
         sp.dinv = P->d_dinv;
         sp.dinv_off = P->d_dinv_off;
-        // in-chunk compressed blocks enter Linv as their U V product (the same operator as the apply)
+        // compressed blocks inside a chunk or between neighbouring chunks enter the dense
+        // products as their U V product (the same operator as the rest of the apply)
         hs::ExpandTask* d_exp = tmp.upload(expand, s);
         hs::launch_lr_expand(d_exp, (int64_t)expand.size(), P->d_alpha, Ad, s);
         int32_t* d_cf = tmp.upload(chunk_first, s);
         int64_t* d_ip = tmp.upload(intptr, s);
         hs::SweepEnt* d_ie = tmp.upload(intent, s);
-        hs::launch_linv(sp, (int)P->nchunk, d_cf, d_ip, d_ie, Ad, d_linv, s);
+        hs::launch_linv(sp, (int)nch, d_cf, d_ip, d_ie, Ad, d_lf, s);
+        hs::launch_linv_transpose(sp, d_lb, s);
+        // coupling matrices and their products with Linv / Linv^T
+        cd* d_C = tmp.get<cd>(std::max<int64_t>(cft + cbt, 1));
+        hip_check(hipMemsetAsync(d_C, 0, sizeof(cd) * std::max<int64_t>(cft + cbt, 1), s), "memset");
+        for (auto& t : cbc) t.dst_off += cft;
+        hs::CopyTask* d_cfc = tmp.upload(cfc, s);
+        hs::CopyTask* d_cbc = tmp.upload(cbc, s);
+        hs::launch_copy_blocks(d_cfc, (int64_t)cfc.size(), Ad, d_C, s);
+        hs::launch_copy_blocks(d_cbc, (int64_t)cbc.size(), Ad, d_C, s);
+        std::vector<hs::GemmTask> gf, gb;
+        for (int64_t kk = 0; kk < nb; ++kk) {
+            const int32_t c = chunk_of[kk], bk = P->bsize[kk];
+            if (c > 0) gf.push_back(hs::GemmTask{mf_off[kk], lf_off[kk], cf_off[c], bk, csize[c - 1], wdt[kk], 0});
+            if (c + 1 < nch)
+                gb.push_back(hs::GemmTask{mb_off[kk], lb_off[kk], cft + cb_off[c] + (int64_t)loc[kk] * csize[c + 1], bk,
+                                          csize[c + 1], wtt[kk], 0});
+        }
+        hs::GemmTask* d_gf = tmp.upload(gf, s);
+        hs::GemmTask* d_gb = tmp.upload(gb, s);
+        hs::launch_gemm(d_gf, (int64_t)gf.size(), d_lf, d_C, d_mf, false, false, 1.0, s);
+        hs::launch_gemm(d_gb, (int64_t)gb.size(), d_lb, d_C, d_mb, false, false, 1.0, s);
         hip_check(hipGetLastError(), "linv launches");
         hip_check(hipStreamSynchronize(s), "stream sync");
         tmp.release();

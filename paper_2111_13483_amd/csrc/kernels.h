@@ -36,7 +36,7 @@ struct CopyTask {
     int64_t dst_off, src_off;   // src_off < 0: zero fill
     int32_t rows, cols;
     int32_t transpose;          // 1: dst[a][b] = src[b][a] (src is cols x rows)
-    int32_t pad;
+    int32_t dst_ld;             // row stride of dst (0: cols)
 };
 
 // C (m x n) = beta_acc ? C + sign * op(A) B : sign * op(A) B, all row-major;
@@ -88,12 +88,18 @@ void launch_far_mv(const AcaTask* geom, const int* rank, cd* const* uv, const in
 void launch_gather(const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb, const cd* slots,
                    int64_t n, int nrhs, cd* y, hipStream_t s);
 // P^-1 v = alpha D^-1 alpha^T v by chunked sweeps. Block rows (elimination
-// order) are grouped into chunks of consecutive rows; the coupling inside a
-// chunk is applied through the explicit inverse Linv of the chunk's unit
-// lower-triangular factor, so the dependency chain advances a chunk at a
-// time. Per block row k: pos = elimination-order offset, loc = offset inside
-// its chunk, w = loc + b_k (row width of its Linv rows), cfirst / clast =
-// first / last block of its chunk, linv_off = start of its b_k x w rows.
+// order) are grouped into chunks of consecutive rows. With L the unit lower
+// block-triangular factor (L_jk = -alpha_kj^T), Linv_c the inverse of chunk
+// c's diagonal part and C_c the coupling of chunk c to chunk c-1:
+//   forward   y_c = Linv_c r_c + (Linv_c C_c) y_{c-1},
+//             r_c = v_c + cross terms from chunks <= c-2
+//   backward  z_c = Linv_c^T r'_c + (Linv_c^T C_{c+1}^T) z_{c+1},
+//             r'_c = zt_c + cross terms from chunks >= c+2
+// Per block row k: pos = elimination-order offset, loc = offset in its
+// chunk, w = loc + b_k (forward Linv row width), wt = n_c - loc (backward
+// width), chunk neighbours [pf, pl] (previous) and [nf, nl] (next), -1 when
+// absent; row blocks of Linv (b_k x w), Linv^T (b_k x wt), Linv C
+// (b_k x n_prev) and Linv^T C^T (b_k x n_next), all row-major.
 struct SweepPlan {
     int nb;
     int64_t n;
@@ -102,35 +108,50 @@ struct SweepPlan {
     const int64_t* pos;
     const int32_t* loc;
     const int32_t* w;
+    const int32_t* wt;
     const int32_t* cfirst;
     const int32_t* clast;
-    const int64_t* linv_off;
-    const cd* linv;
-    const int64_t* colptr;     // forward: cross-chunk entries (k, j) listed per column j, k ascending
+    const int32_t* pf;
+    const int32_t* pl;
+    const int32_t* nf;
+    const int32_t* nl;
+    const int64_t* lf_off;     // Linv rows
+    const int64_t* lb_off;     // Linv^T rows
+    const int64_t* mf_off;     // (Linv C) rows
+    const int64_t* mb_off;     // (Linv^T C^T) rows
+    const cd* lf;
+    const cd* lb;
+    const cd* mf;
+    const cd* mb;
+    const int64_t* colptr;     // forward: entries (k, j) with chunk(j) - chunk(k) >= 2, per column j, k ascending
     const SweepEnt* colent;
-    const int64_t* rowptr;     // backward: cross-chunk entries (k, j) listed per row k, j ascending
+    const int64_t* rowptr;     // backward: the same entries per row k, j ascending
     const SweepEnt* rowent;
     const cd* alpha;
     const cd* dinv;
     const int64_t* dinv_off;
 };
-// Work buffers of one apply stream: yw, zt, rbuf, rbuf2 (n nrhs each),
-// flags (4 nb ints, zeroed once), tickets (2, zeroed once).
+// Work buffers of one apply stream: ybuf, zbuf, rbuf, rbuf2 (elimination
+// order) and zt (tree order), n nrhs each; flags (4 nb ints, zeroed once);
+// tickets (2, zeroed once).
 struct SweepWork {
-    cd* yw;
+    cd* ybuf;
+    cd* zbuf;
     cd* zt;
     cd* rbuf;
     cd* rbuf2;
     int* flags;
     unsigned long long* tickets;
 };
-constexpr int kMaxChunk = 384;   // points per chunk (bounds the Linv row width)
+constexpr int kMaxChunk = 384;   // points per chunk (bounds the row widths)
 void launch_sweeps(const SweepPlan& p, const cd* v, cd* z, int nrhs, const SweepWork& w, int epoch, hipStream_t s);
 int sweep_grid(int64_t nb);
-// Linv of every chunk from the dense alpha blocks inside it (intptr/intent:
-// per column j the in-chunk entries (k, j), offsets into A).
+// Linv rows of every chunk from the dense in-chunk alpha blocks (intptr /
+// intent: per column j the in-chunk entries (k, j), offsets into A).
 void launch_linv(const SweepPlan& p, int nchunk, const int32_t* chunk_first, const int64_t* intptr,
-                 const SweepEnt* intent, const cd* A, cd* linv, hipStream_t s);
+                 const SweepEnt* intent, const cd* A, cd* lf, hipStream_t s);
+// Linv^T rows from Linv rows (one workgroup per block row).
+void launch_linv_transpose(const SweepPlan& p, cd* lb, hipStream_t s);
 // dst (m x n row-major) = U V for low-rank blocks (U m x r column-major then V r x n row-major at src_off).
 struct ExpandTask {
     int64_t src_off, dst_off;

@@ -19,19 +19,20 @@ __global__ void __launch_bounds__(NT)
 k_copy_blocks(const CopyTask* __restrict__ tasks, const cd* __restrict__ src, cd* __restrict__ dst) {
     const CopyTask t = tasks[blockIdx.x];
     const int rows = t.rows, cols = t.cols;
+    const int64_t ld = t.dst_ld > 0 ? t.dst_ld : cols;
     cd* d = dst + t.dst_off;
     if (t.src_off < 0) {
-        for (int e = threadIdx.x; e < rows * cols; e += NT) d[e] = cmk(0.0, 0.0);
+        for (int e = threadIdx.x; e < rows * cols; e += NT) d[(e / cols) * ld + e % cols] = cmk(0.0, 0.0);
         return;
     }
     const cd* s = src + t.src_off;
     if (t.transpose) {
         for (int e = threadIdx.x; e < rows * cols; e += NT) {
             const int a = e / cols, b = e % cols;
-            d[e] = s[(int64_t)b * rows + a];
+            d[a * ld + b] = s[(int64_t)b * rows + a];
         }
     } else {
-        for (int e = threadIdx.x; e < rows * cols; e += NT) d[e] = s[e];
+        for (int e = threadIdx.x; e < rows * cols; e += NT) d[(e / cols) * ld + e % cols] = s[e];
     }
 }
 

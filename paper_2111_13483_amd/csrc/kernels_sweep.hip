@@ -6,14 +6,16 @@
 //
 // Under a bandwidth-reducing order each block row depends on the one before
 // it, so both sweeps are chains of nb dependent steps. Consecutive rows are
-// grouped into chunks and the in-chunk coupling is applied through the
-// explicit inverse Linv of the chunk's unit lower-triangular factor
-// (forward: y_c = Linv_c r_c; backward: z_c = Linv_c^T r'_c), where r
-// collects the cross-chunk terms. The chain then advances a chunk at a time:
-// phase A of a row gathers its cross-chunk entries, phase B applies its rows
-// (forward) or columns (backward) of Linv once every row of the chunk has
-// finished phase A. The operator is unchanged; only the evaluation order of
-// the triangular solves differs.
+// grouped into chunks; with Linv_c the explicit inverse of chunk c's unit
+// lower-triangular diagonal part and C_c its coupling to chunk c-1,
+//   forward   y_c = Linv_c r_c + (Linv_c C_c) y_{c-1}
+//   backward  z_c = Linv_c^T r'_c + (Linv_c^T C_{c+1}^T) z_{c+1}
+// where r, r' gather the terms from chunks two or more away. Phase A of a
+// row gathers those terms (they are ready long before they are needed);
+// phase B applies the row's slice of the two dense products once its chunk
+// neighbour has finished, so the chain advances one dense row-block product
+// per chunk. The operator is unchanged; only the evaluation order of the
+// triangular solves differs.
 //
 // Each sweep is one launch. A workgroup takes block rows by ticket in the
 // dependency order, so every row it waits for belongs to a workgroup that is
@@ -91,8 +93,8 @@ __device__ __forceinline__ void for_ready_entries(const SweepEnt* __restrict__ e
         }
     }
 }
-// Wait until flags[first..last] all equal epoch (whole wave), then acquire.
-__device__ __forceinline__ void wait_range(const int* flags, int first, int last, int epoch) {
+// Wait until flags[first..last] all equal epoch (whole wave); no fence.
+__device__ __forceinline__ void wait_range_nofence(const int* flags, int first, int last, int epoch) {
     const int lane = threadIdx.x % kWave;
     for (int b0 = first; b0 <= last; b0 += kWave) {
         const int f = b0 + lane;
@@ -102,11 +104,149 @@ __device__ __forceinline__ void wait_range(const int* flags, int first, int last
             __builtin_amdgcn_s_sleep(1);
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 constexpr int QC = kMaxChunk / kWave;   // 64-wide column groups of a chunk
-constexpr int RB2 = 4;                  // Linv rows whose loads are issued together
+constexpr int RB2 = 2;                  // dense rows whose loads are issued together
+
+// Phase A accumulation over one list of entries (forward: alpha^T y_k into
+// columns b of the row block; backward: alpha z_j into rows a).
+template <int S, bool FWD>
+__device__ __forceinline__ void phase_a(const SweepPlan& p, const SweepEnt* ents, int64_t e0, int dir, int cnt,
+                                        const int* flags, int epoch, const cd* src, int c0, int cs, int bme,
+                                        cd (&acc)[2][S]) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t n = p.n;
+    for_ready_entries(ents, e0, dir, cnt, flags, epoch, [&](const SweepEnt& e) {
+        const int o = e.k, bo = p.bsize[o];
+        const int64_t so = p.pos[o];
+        cd x[2][S];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                const int a = lane + q * kWave;
+                x[q][c] = (a < bo && c < cs) ? src[so + a + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
+            }
+        // the stored block is alpha_{row, col}: forward (row = o, col = me), backward (row = me, col = o)
+        const int rows = FWD ? bo : bme, cols = FWD ? bme : bo;
+        const cd* A = p.alpha + e.off;
+        if (e.rank < 0) {
+            for (int a0 = 0; a0 < rows; a0 += RB) {
+                cd Ar[RB][2];
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int b = lane + q * kWave;
+                        Ar[r][q] = (a0 + r < rows && b < cols) ? A[(int64_t)(a0 + r) * cols + b] : cmk(0.0, 0.0);
+                    }
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const int a = a0 + r;
+                    if (a < rows)
+#pragma unroll
+                    for (int c = 0; c < S; ++c) {
+                        if (FWD) {
+                            const cd xa = shfl_cd(a < kWave ? x[0][c] : x[1][c], a % kWave);
+#pragma unroll
+                            for (int q = 0; q < 2; ++q) acc[q][c] = cfma(Ar[r][q], xa, acc[q][c]);
+                        } else {
+                            cd sr = cmul(Ar[r][0], x[0][c]);
+                            sr = cfma(Ar[r][1], x[1][c], sr);
+                            sr = wave_sum(sr);
+                            if (lane == a % kWave) {
+                                if (a < kWave) acc[0][c] = cadd(acc[0][c], sr);
+                                else acc[1][c] = cadd(acc[1][c], sr);
+                            }
+                        }
+                    }
+                }
+            }
+        } else {
+            const int rk = e.rank;
+            const cd* Uf = A;
+            const cd* Vf = A + (int64_t)rows * rk;
+            for (int l0 = 0; l0 < rk; l0 += RB) {
+                cd Ur[RB][2], Vr[RB][2];
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int xx = lane + q * kWave;
+                        const bool on = l0 + r < rk;
+                        Ur[r][q] = (on && xx < rows) ? Uf[(int64_t)(l0 + r) * rows + xx] : cmk(0.0, 0.0);
+                        Vr[r][q] = (on && xx < cols) ? Vf[(int64_t)(l0 + r) * cols + xx] : cmk(0.0, 0.0);
+                    }
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    if (l0 + r < rk)
+#pragma unroll
+                    for (int c = 0; c < S; ++c) {
+                        if (FWD) {   // out += V^T (U^T x)
+                            cd t = cmul(Ur[r][0], x[0][c]);
+                            t = cfma(Ur[r][1], x[1][c], t);
+                            t = wave_sum(t);
+#pragma unroll
+                            for (int q = 0; q < 2; ++q) acc[q][c] = cfma(Vr[r][q], t, acc[q][c]);
+                        } else {     // out += U (V x)
+                            cd t = cmul(Vr[r][0], x[0][c]);
+                            t = cfma(Vr[r][1], x[1][c], t);
+                            t = wave_sum(t);
+#pragma unroll
+                            for (int q = 0; q < 2; ++q) acc[q][c] = cfma(Ur[r][q], t, acc[q][c]);
+                        }
+                    }
+                }
+            }
+        }
+    });
+}
+
+// out rows a (wave-strided) of [A1 | A2] x [x1; x2]: A1 is rows x w1 at a1,
+// x1 = src1[o1 + col]; A2 rows x w2 at a2, x2 = src2[o2 + col] (w2 may be 0).
+template <int S>
+__device__ __forceinline__ void dense_rows(const cd* A1, int w1, const cd* src1, int64_t o1, const cd* A2, int w2,
+                                           const cd* src2, int64_t o2, int rows, int64_t n, int c0, int cs,
+                                           cd* out_lds) {
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    cd x1[QC][S], x2[QC][S];
+#pragma unroll
+    for (int q = 0; q < QC; ++q)
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            const int col = lane + q * kWave;
+            x1[q][c] = (col < w1 && c < cs) ? src1[o1 + col + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
+            x2[q][c] = (col < w2 && c < cs) ? src2[o2 + col + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
+        }
+    for (int a0 = wid; a0 < rows; a0 += NW * RB2) {
+        cd R1[RB2][QC], R2[RB2][QC];
+#pragma unroll
+        for (int r = 0; r < RB2; ++r)
+#pragma unroll
+            for (int q = 0; q < QC; ++q) {
+                const int a = a0 + NW * r, col = lane + q * kWave;
+                R1[r][q] = (a < rows && col < w1) ? A1[(int64_t)a * w1 + col] : cmk(0.0, 0.0);
+                R2[r][q] = (a < rows && col < w2) ? A2[(int64_t)a * w2 + col] : cmk(0.0, 0.0);
+            }
+#pragma unroll
+        for (int r = 0; r < RB2; ++r) {
+            const int a = a0 + NW * r;
+            if (a < rows)
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                cd sacc = cmk(0.0, 0.0);
+#pragma unroll
+                for (int q = 0; q < QC; ++q) {
+                    sacc = cfma(R1[r][q], x1[q][c], sacc);
+                    sacc = cfma(R2[r][q], x2[q][c], sacc);
+                }
+                sacc = wave_sum(sacc);
+                if (lane == 0 && c < cs) out_lds[a + c * rows] = sacc;
+            }
+        }
+    }
+}
 
 }  // namespace
 
@@ -125,10 +265,10 @@ k_sweep_fwd(SweepPlan p, const cd* __restrict__ v, SweepWork wk, int nrhs, unsig
         const int j = take_ticket(wk.tickets, base, &s_t);
         if (j >= p.nb) return;
         const int bj = p.bsize[j];
-        const int64_t sj = p.bstart[j];
+        const int64_t sj = p.bstart[j], pj = p.pos[j];
         const int64_t e0 = p.colptr[j];
         const int cnt = (int)(p.colptr[j + 1] - e0);
-        // ---- phase A: r_j = v_j + cross-chunk terms
+        // ---- phase A: r_j = v_j + terms from chunks two or more back
         for (int c0 = 0; c0 < nrhs; c0 += S) {
             const int cs = min(S, nrhs - c0);
             cd acc[2][S];
@@ -136,70 +276,7 @@ k_sweep_fwd(SweepPlan p, const cd* __restrict__ v, SweepWork wk, int nrhs, unsig
             for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int c = 0; c < S; ++c) acc[q][c] = cmk(0.0, 0.0);
-            for_ready_entries(p.colent, e0, 1, cnt, flagY, epoch, [&](const SweepEnt& e) {
-                const int k = e.k, bk = p.bsize[k];
-                const int64_t sk = p.bstart[k];
-                cd y[2][S];
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int c = 0; c < S; ++c) {
-                        const int a = lane + q * kWave;
-                        y[q][c] = (a < bk && c < cs) ? wk.yw[sk + a + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
-                    }
-                const cd* A = p.alpha + e.off;
-                if (e.rank < 0) {
-                    for (int a0 = 0; a0 < bk; a0 += RB) {
-                        cd Ar[RB][2];
-#pragma unroll
-                        for (int r = 0; r < RB; ++r)
-#pragma unroll
-                            for (int q = 0; q < 2; ++q) {
-                                const int b = lane + q * kWave;
-                                Ar[r][q] = (a0 + r < bk && b < bj) ? A[(int64_t)(a0 + r) * bj + b] : cmk(0.0, 0.0);
-                            }
-#pragma unroll
-                        for (int r = 0; r < RB; ++r) {
-                            const int a = a0 + r;
-                            if (a < bk)
-#pragma unroll
-                            for (int c = 0; c < S; ++c) {
-                                const cd ya = shfl_cd(a < kWave ? y[0][c] : y[1][c], a % kWave);
-#pragma unroll
-                                for (int q = 0; q < 2; ++q) acc[q][c] = cfma(Ar[r][q], ya, acc[q][c]);
-                            }
-                        }
-                    }
-                } else {
-                    const int rk = e.rank;
-                    const cd* Uf = A;
-                    const cd* Vf = A + (int64_t)bk * rk;
-                    for (int l0 = 0; l0 < rk; l0 += RB) {
-                        cd Ur[RB][2], Vr[RB][2];
-#pragma unroll
-                        for (int r = 0; r < RB; ++r)
-#pragma unroll
-                            for (int q = 0; q < 2; ++q) {
-                                const int x = lane + q * kWave;
-                                const bool on = l0 + r < rk;
-                                Ur[r][q] = (on && x < bk) ? Uf[(int64_t)(l0 + r) * bk + x] : cmk(0.0, 0.0);
-                                Vr[r][q] = (on && x < bj) ? Vf[(int64_t)(l0 + r) * bj + x] : cmk(0.0, 0.0);
-                            }
-#pragma unroll
-                        for (int r = 0; r < RB; ++r) {
-                            if (l0 + r < rk)
-#pragma unroll
-                            for (int c = 0; c < S; ++c) {
-                                cd t = cmul(Ur[r][0], y[0][c]);
-                                t = cfma(Ur[r][1], y[1][c], t);
-                                t = wave_sum(t);
-#pragma unroll
-                                for (int q = 0; q < 2; ++q) acc[q][c] = cfma(Vr[r][q], t, acc[q][c]);
-                            }
-                        }
-                    }
-                }
-            });
+            phase_a<S, true>(p, p.colent, e0, 1, cnt, flagY, epoch, wk.ybuf, c0, cs, bj, acc);
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int b = lane + q * kWave;
@@ -214,60 +291,32 @@ k_sweep_fwd(SweepPlan p, const cd* __restrict__ v, SweepWork wk, int nrhs, unsig
                     cd s = v[sj + q % bj + (int64_t)(c0 + q / bj) * n];
 #pragma unroll
                     for (int w = 0; w < NW; ++w) s = cadd(s, part[w][q]);
-                    wk.rbuf[p.pos[j] + q % bj + (int64_t)(c0 + q / bj) * n] = s;
+                    wk.rbuf[pj + q % bj + (int64_t)(c0 + q / bj) * n] = s;
                 }
                 if (c0 + S >= nrhs) publish(flagR + j, epoch);
             }
             __syncthreads();
         }
-        // ---- phase B: y_j = rows of Linv_c times r_c
+        // ---- phase B: y_j = Linv rows r_c + (Linv C) rows y_{c-1}
         const int cf = p.cfirst[j];
-        const int wj = p.w[j];
-        const int64_t pc = p.pos[cf];
-        const cd* X = p.linv + p.linv_off[j];
-        wait_range(flagR, cf, j, epoch);
+        const int pf = p.pf[j], pl = p.pl[j];
+        wait_range_nofence(flagR, cf, j, epoch);
+        if (pf >= 0) wait_range_nofence(flagY, pf, pl, epoch);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int wprev = pf >= 0 ? (int)(p.pos[pl] + p.bsize[pl] - p.pos[pf]) : 0;
         for (int c0 = 0; c0 < nrhs; c0 += S) {
             const int cs = min(S, nrhs - c0);
-            cd rr[QC][S];
-#pragma unroll
-            for (int q = 0; q < QC; ++q)
-#pragma unroll
-                for (int c = 0; c < S; ++c) {
-                    const int col = lane + q * kWave;
-                    rr[q][c] = (col < wj && c < cs) ? wk.rbuf[pc + col + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
-                }
-            for (int a0 = wid; a0 < bj; a0 += NW * RB2) {
-                cd Xr[RB2][QC];
-#pragma unroll
-                for (int r = 0; r < RB2; ++r)
-#pragma unroll
-                    for (int q = 0; q < QC; ++q) {
-                        const int a = a0 + NW * r, col = lane + q * kWave;
-                        Xr[r][q] = (a < bj && col < wj) ? X[(int64_t)a * wj + col] : cmk(0.0, 0.0);
-                    }
-#pragma unroll
-                for (int r = 0; r < RB2; ++r) {
-                    const int a = a0 + NW * r;
-                    if (a < bj)
-#pragma unroll
-                    for (int c = 0; c < S; ++c) {
-                        cd sacc = cmk(0.0, 0.0);
-#pragma unroll
-                        for (int q = 0; q < QC; ++q) sacc = cfma(Xr[r][q], rr[q][c], sacc);
-                        sacc = wave_sum(sacc);
-                        if (lane == 0 && c < cs) wk.yw[sj + a + (int64_t)(c0 + c) * n] = sacc;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        if (wid == 0) publish(flagY + j, epoch);
-        // ---- zt_j = D_j^-1 y_j, off the chain
-        const cd* Di = p.dinv + p.dinv_off[j];
-        for (int c0 = 0; c0 < nrhs; c0 += S) {
-            const int cs = min(S, nrhs - c0);
-            for (int q = tid; q < bj * cs; q += NT) ysh[q] = wk.yw[sj + q % bj + (int64_t)(c0 + q / bj) * n];
+            dense_rows<S>(p.lf + p.lf_off[j], p.w[j], wk.rbuf, p.pos[cf], p.mf + p.mf_off[j], wprev, wk.ybuf,
+                          pf >= 0 ? p.pos[pf] : 0, bj, n, c0, cs, ysh);
             __syncthreads();
+            if (wid == 0) {
+                for (int q = lane; q < bj * cs; q += kWave)
+                    wk.ybuf[pj + q % bj + (int64_t)(c0 + q / bj) * n] = ysh[q];
+                if (c0 + S >= nrhs) publish(flagY + j, epoch);
+            }
+            __syncthreads();
+            // zt_j = D_j^-1 y_j, off the chain
+            const cd* Di = p.dinv + p.dinv_off[j];
             for (int a0 = wid; a0 < bj; a0 += NW * RB) {
                 cd Dr[RB][2];
 #pragma unroll
@@ -305,6 +354,7 @@ __global__ void __launch_bounds__(NT)
 k_sweep_bwd(SweepPlan p, cd* __restrict__ z, SweepWork wk, int nrhs, unsigned long long base, int epoch) {
     __shared__ int s_t;
     __shared__ cd part[NW][kMaxLeaf * S];
+    __shared__ cd zsh[kMaxLeaf * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
     int* flagZ = wk.flags + 2 * p.nb;
@@ -314,10 +364,10 @@ k_sweep_bwd(SweepPlan p, cd* __restrict__ z, SweepWork wk, int nrhs, unsigned lo
         if (t >= p.nb) return;
         const int k = p.nb - 1 - t;
         const int bk = p.bsize[k];
-        const int64_t sk = p.bstart[k];
+        const int64_t sk = p.bstart[k], pk = p.pos[k];
         const int64_t e_last = p.rowptr[k + 1] - 1;
         const int cnt = (int)(p.rowptr[k + 1] - p.rowptr[k]);
-        // ---- phase A: r'_k = zt_k + cross-chunk terms (j descending: the nearest comes last)
+        // ---- phase A: r'_k = zt_k + terms from chunks two or more ahead (nearest last)
         for (int c0 = 0; c0 < nrhs; c0 += S) {
             const int cs = min(S, nrhs - c0);
             cd acc[2][S];
@@ -325,74 +375,7 @@ k_sweep_bwd(SweepPlan p, cd* __restrict__ z, SweepWork wk, int nrhs, unsigned lo
             for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int c = 0; c < S; ++c) acc[q][c] = cmk(0.0, 0.0);
-            for_ready_entries(p.rowent, e_last, -1, cnt, flagZ, epoch, [&](const SweepEnt& e) {
-                const int j = e.k, bj = p.bsize[j];
-                const int64_t sj = p.bstart[j];
-                cd zz[2][S];
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int c = 0; c < S; ++c) {
-                        const int b = lane + q * kWave;
-                        zz[q][c] = (b < bj && c < cs) ? z[sj + b + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
-                    }
-                const cd* A = p.alpha + e.off;
-                if (e.rank < 0) {
-                    for (int a0 = 0; a0 < bk; a0 += RB) {
-                        cd Ar[RB][2];
-#pragma unroll
-                        for (int r = 0; r < RB; ++r)
-#pragma unroll
-                            for (int q = 0; q < 2; ++q) {
-                                const int b = lane + q * kWave;
-                                Ar[r][q] = (a0 + r < bk && b < bj) ? A[(int64_t)(a0 + r) * bj + b] : cmk(0.0, 0.0);
-                            }
-#pragma unroll
-                        for (int r = 0; r < RB; ++r) {
-                            const int a = a0 + r;
-                            if (a < bk)
-#pragma unroll
-                            for (int c = 0; c < S; ++c) {
-                                cd sr = cmul(Ar[r][0], zz[0][c]);
-                                sr = cfma(Ar[r][1], zz[1][c], sr);
-                                sr = wave_sum(sr);
-                                if (lane == a % kWave) {
-                                    if (a < kWave) acc[0][c] = cadd(acc[0][c], sr);
-                                    else acc[1][c] = cadd(acc[1][c], sr);
-                                }
-                            }
-                        }
-                    }
-                } else {
-                    const int rk = e.rank;
-                    const cd* Uf = A;
-                    const cd* Vf = A + (int64_t)bk * rk;
-                    for (int l0 = 0; l0 < rk; l0 += RB) {
-                        cd Ur[RB][2], Vr[RB][2];
-#pragma unroll
-                        for (int r = 0; r < RB; ++r)
-#pragma unroll
-                            for (int q = 0; q < 2; ++q) {
-                                const int x = lane + q * kWave;
-                                const bool on = l0 + r < rk;
-                                Ur[r][q] = (on && x < bk) ? Uf[(int64_t)(l0 + r) * bk + x] : cmk(0.0, 0.0);
-                                Vr[r][q] = (on && x < bj) ? Vf[(int64_t)(l0 + r) * bj + x] : cmk(0.0, 0.0);
-                            }
-#pragma unroll
-                        for (int r = 0; r < RB; ++r) {
-                            if (l0 + r < rk)
-#pragma unroll
-                            for (int c = 0; c < S; ++c) {
-                                cd tt = cmul(Vr[r][0], zz[0][c]);
-                                tt = cfma(Vr[r][1], zz[1][c], tt);
-                                tt = wave_sum(tt);
-#pragma unroll
-                                for (int q = 0; q < 2; ++q) acc[q][c] = cfma(Ur[r][q], tt, acc[q][c]);
-                            }
-                        }
-                    }
-                }
-            });
+            phase_a<S, false>(p, p.rowent, e_last, -1, cnt, flagZ, epoch, wk.zbuf, c0, cs, bk, acc);
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int a = lane + q * kWave;
@@ -407,65 +390,28 @@ k_sweep_bwd(SweepPlan p, cd* __restrict__ z, SweepWork wk, int nrhs, unsigned lo
                     cd s = wk.zt[sk + q % bk + (int64_t)(c0 + q / bk) * n];
 #pragma unroll
                     for (int w = 0; w < NW; ++w) s = cadd(s, part[w][q]);
-                    wk.rbuf2[p.pos[k] + q % bk + (int64_t)(c0 + q / bk) * n] = s;
+                    wk.rbuf2[pk + q % bk + (int64_t)(c0 + q / bk) * n] = s;
                 }
                 if (c0 + S >= nrhs) publish(flagR + k, epoch);
             }
             __syncthreads();
         }
-        // ---- phase B: z_k = (columns of Linv_c for block k)^T r'_c
+        // ---- phase B: z_k = Linv^T rows r'_c + (Linv^T C^T) rows z_{c+1}
         const int cl = p.clast[k];
-        const int lk = p.loc[k];
-        wait_range(flagR, k, cl, epoch);
+        const int nf = p.nf[k], nl = p.nl[k];
+        wait_range_nofence(flagR, k, cl, epoch);
+        if (nf >= 0) wait_range_nofence(flagZ, nf, nl, epoch);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int wnext = nf >= 0 ? (int)(p.pos[nl] + p.bsize[nl] - p.pos[nf]) : 0;
         for (int c0 = 0; c0 < nrhs; c0 += S) {
             const int cs = min(S, nrhs - c0);
-            cd acc[2][S];
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int c = 0; c < S; ++c) acc[q][c] = cmk(0.0, 0.0);
-            // wave w takes blocks k' = k + w, k + w + NW, ... of the chunk
-            for (int kp = k + wid; kp <= cl; kp += NW) {
-                const int bp = p.bsize[kp], wp = p.w[kp];
-                const cd* X = p.linv + p.linv_off[kp];
-                const int64_t rp = p.pos[kp];
-                for (int b0 = 0; b0 < bp; b0 += RB) {
-                    cd Xr[RB][2], rv[RB][S];
-#pragma unroll
-                    for (int r = 0; r < RB; ++r) {
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            const int a = lane + q * kWave;
-                            Xr[r][q] = (b0 + r < bp && a < bk) ? X[(int64_t)(b0 + r) * wp + lk + a] : cmk(0.0, 0.0);
-                        }
-#pragma unroll
-                        for (int c = 0; c < S; ++c)
-                            rv[r][c] = (b0 + r < bp && c < cs) ? wk.rbuf2[rp + b0 + r + (int64_t)(c0 + c) * n]
-                                                               : cmk(0.0, 0.0);
-                    }
-#pragma unroll
-                    for (int r = 0; r < RB; ++r)
-#pragma unroll
-                        for (int q = 0; q < 2; ++q)
-#pragma unroll
-                            for (int c = 0; c < S; ++c) acc[q][c] = cfma(Xr[r][q], rv[r][c], acc[q][c]);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int a = lane + q * kWave;
-                if (a < bk)
-#pragma unroll
-                    for (int c = 0; c < S; ++c)
-                        if (c < cs) part[wid][a + c * bk] = acc[q][c];
-            }
+            dense_rows<S>(p.lb + p.lb_off[k], p.wt[k], wk.rbuf2, pk, p.mb + p.mb_off[k], wnext, wk.zbuf,
+                          nf >= 0 ? p.pos[nf] : 0, bk, n, c0, cs, zsh);
             __syncthreads();
             if (wid == 0) {
                 for (int q = lane; q < bk * cs; q += kWave) {
-                    cd s = part[0][q];
-#pragma unroll
-                    for (int w = 1; w < NW; ++w) s = cadd(s, part[w][q]);
-                    z[sk + q % bk + (int64_t)(c0 + q / bk) * n] = s;
+                    wk.zbuf[pk + q % bk + (int64_t)(c0 + q / bk) * n] = zsh[q];
+                    z[sk + q % bk + (int64_t)(c0 + q / bk) * n] = zsh[q];
                 }
                 if (c0 + S >= nrhs) publish(flagZ + k, epoch);
             }
@@ -474,16 +420,16 @@ k_sweep_bwd(SweepPlan p, cd* __restrict__ z, SweepWork wk, int nrhs, unsigned lo
     }
 }
 
-// Linv of each chunk (one workgroup per chunk), row blocks in order:
+// Linv rows of each chunk (one workgroup per chunk), row blocks in order:
 // X_j = E_j + sum_{in-chunk (k, j)} alpha_kj^T X_k, X_k stored b_k x w_k.
 __global__ void __launch_bounds__(NT)
 k_linv(SweepPlan p, const int32_t* __restrict__ chunk_first, const int64_t* __restrict__ intptr,
-       const SweepEnt* __restrict__ intent, const cd* __restrict__ A, cd* __restrict__ linv) {
+       const SweepEnt* __restrict__ intent, const cd* __restrict__ A, cd* __restrict__ lf) {
     const int c = blockIdx.x;
     const int j0 = chunk_first[c], j1 = chunk_first[c + 1];
     for (int j = j0; j < j1; ++j) {
         const int bj = p.bsize[j], wj = p.w[j], lj = p.loc[j];
-        cd* X = linv + p.linv_off[j];
+        cd* X = lf + p.lf_off[j];
         for (int e = threadIdx.x; e < bj * wj; e += NT) {
             const int a = e / wj, col = e % wj;
             cd val = cmk(col == lj + a ? 1.0 : 0.0, 0.0);
@@ -492,12 +438,32 @@ k_linv(SweepPlan p, const int32_t* __restrict__ chunk_first, const int64_t* __re
                 const int k = en.k, bk = p.bsize[k], wkk = p.w[k];
                 if (col >= wkk) continue;
                 const cd* Ak = A + en.off;
-                const cd* Xk = linv + p.linv_off[k];
+                const cd* Xk = lf + p.lf_off[k];
                 for (int l = 0; l < bk; ++l) val = cfma(Ak[(int64_t)l * bj + a], Xk[(int64_t)l * wkk + col], val);
             }
             X[e] = val;
         }
         __syncthreads();
+    }
+}
+
+// Linv^T row block k: LT_k[a][col] = Linv[loc_k + col][loc_k + a], col < wt_k.
+__global__ void __launch_bounds__(NT)
+k_linv_transpose(SweepPlan p, cd* __restrict__ lb) {
+    const int k = blockIdx.x;
+    const int bk = p.bsize[k], wtk = p.wt[k], lk = p.loc[k];
+    const int cl = p.clast[k];
+    cd* out = lb + p.lb_off[k];
+    for (int e = threadIdx.x; e < bk * wtk; e += NT) {
+        const int a = e / wtk, col = e % wtk;
+        const int row = lk + col;          // chunk row index
+        // find the block kp holding chunk row `row` (blocks k..cl)
+        int kp = k;
+        while (kp < cl && p.loc[kp] + p.bsize[kp] <= row) ++kp;
+        const int rr = row - p.loc[kp];
+        const int wkp = p.w[kp];
+        const int cc = lk + a;
+        out[e] = cc < wkp ? p.lf[p.lf_off[kp] + (int64_t)rr * wkp + cc] : cmk(0.0, 0.0);
     }
 }
 
@@ -530,9 +496,13 @@ void launch_sweeps(const SweepPlan& p, const cd* v, cd* z, int nrhs, const Sweep
 }
 
 void launch_linv(const SweepPlan& p, int nchunk, const int32_t* chunk_first, const int64_t* intptr,
-                 const SweepEnt* intent, const cd* A, cd* linv, hipStream_t s) {
+                 const SweepEnt* intent, const cd* A, cd* lf, hipStream_t s) {
     if (nchunk > 0)
-        hipLaunchKernelGGL(k_linv, dim3(nchunk), dim3(NT), 0, s, p, chunk_first, intptr, intent, A, linv);
+        hipLaunchKernelGGL(k_linv, dim3(nchunk), dim3(NT), 0, s, p, chunk_first, intptr, intent, A, lf);
+}
+
+void launch_linv_transpose(const SweepPlan& p, cd* lb, hipStream_t s) {
+    if (p.nb > 0) hipLaunchKernelGGL(k_linv_transpose, dim3(p.nb), dim3(NT), 0, s, p, lb);
 }
 
 void launch_lr_expand(const ExpandTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s) {
