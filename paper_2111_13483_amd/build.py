@@ -16,12 +16,13 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhschur.so")
 BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-result",
+    "-Wno-unused-result", "-I" + INCLUDE,
 ]
 GXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall"]
 

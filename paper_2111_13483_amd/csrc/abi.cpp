@@ -13,7 +13,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/hschur.h"
+#include "hschur.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -193,6 +193,7 @@ struct hs_precond {
     // chunked sweeps
     int64_t nchunk = 0, linv_elems = 0;
     hs::SweepPlan sp{};
+    hs::SweepItems items{};
 };
 
 namespace {
@@ -405,7 +406,7 @@ struct SweepWs {
 
 void apply_tree(const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, hipStream_t s) {
     ws.epoch += 1;
-    hs::launch_sweeps(P->sp, v, z, nrhs, ws.w, ws.epoch, s);
+    hs::launch_sweeps(P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s);
 }
 
 SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
@@ -413,12 +414,11 @@ SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
     const size_t nn = (size_t)P->H->n * nrhs;
     sw.w.ybuf = o.get<cd>(nn);
     sw.w.zbuf = o.get<cd>(nn);
-    sw.w.zt = o.get<cd>(nn);
     sw.w.rbuf = o.get<cd>(nn);
     sw.w.rbuf2 = o.get<cd>(nn);
-    sw.w.flags = o.get<int>((size_t)4 * P->nb);
+    sw.w.flags = o.get<int>((size_t)4 * P->nchunk);
     sw.w.tickets = o.get<unsigned long long>(2);
-    hip_check(hipMemsetAsync(sw.w.flags, 0, sizeof(int) * 4 * P->nb, s), "memset flags");
+    hip_check(hipMemsetAsync(sw.w.flags, 0, sizeof(int) * 4 * P->nchunk, s), "memset flags");
     hip_check(hipMemsetAsync(sw.w.tickets, 0, sizeof(unsigned long long) * 2, s), "memset tickets");
     return sw;
 }
@@ -940,7 +940,7 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         }
         // ---- chunked sweep plan: consecutive block rows grouped up to kMaxChunk points
         std::vector<int32_t> chunk_of(nb), loc(nb), wdt(nb), wtt(nb), cfirst(nb), clast(nb), chunk_first;
-        std::vector<int32_t> pf(nb, -1), pl(nb, -1), nf(nb, -1), nl(nb, -1);
+        std::vector<int32_t> fx0(nb, -1), fx1(nb, -1), bx0(nb, -1), bx1(nb, -1);
         std::vector<int64_t> pos(nb);
         {
             int64_t pp = 0;
@@ -964,16 +964,23 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         const int64_t nch = (int64_t)chunk_first.size() - 1;
         P->nchunk = nch;
         std::vector<int32_t> csize(nch);
+        // fold widths: forward = points of chunks [c - kFold, c - 1], backward = [c + 1, c + kFold]
+        std::vector<int32_t> fwidth(nch, 0), bwidth(nch, 0);
         for (int64_t c = 0; c < nch; ++c) {
             int32_t sz = 0;
             for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) sz += P->bsize[kk];
             csize[c] = sz;
+        }
+        for (int64_t c = 0; c < nch; ++c) {
+            const int64_t c0f = std::max<int64_t>(0, c - hs::kFold), c1b = std::min<int64_t>(nch - 1, c + hs::kFold);
+            for (int64_t d = c0f; d < c; ++d) fwidth[c] += csize[d];
+            for (int64_t d = c + 1; d <= c1b; ++d) bwidth[c] += csize[d];
             for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) {
                 cfirst[kk] = chunk_first[c];
                 clast[kk] = chunk_first[c + 1] - 1;
-                wtt[kk] = sz - loc[kk];
-                if (c > 0) { pf[kk] = chunk_first[c - 1]; pl[kk] = chunk_first[c] - 1; }
-                if (c + 1 < nch) { nf[kk] = chunk_first[c + 1]; nl[kk] = chunk_first[c + 2] - 1; }
+                wtt[kk] = csize[c] - loc[kk];
+                if (c > 0) { fx0[kk] = chunk_first[c0f]; fx1[kk] = chunk_first[c] - 1; }
+                if (c + 1 < nch) { bx0[kk] = chunk_first[c + 1]; bx1[kk] = chunk_first[c1b + 1] - 1; }
             }
         }
         std::vector<int64_t> lf_off(nb), lb_off(nb), mf_off(nb), mb_off(nb), cf_off(nch, -1), cb_off(nch, -1);
@@ -985,13 +992,15 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             lb_off[kk] = lbt;
             lbt += bk * wtt[kk];
             mf_off[kk] = mft;
-            mft += c > 0 ? bk * csize[c - 1] : 0;
+            mft += bk * fwidth[c];
             mb_off[kk] = mbt;
-            mbt += c + 1 < nch ? bk * csize[c + 1] : 0;
+            mbt += bk * bwidth[c];
         }
         for (int64_t c = 0; c < nch; ++c) {
-            if (c > 0) { cf_off[c] = cft; cft += (int64_t)csize[c] * csize[c - 1]; }
-            if (c + 1 < nch) { cb_off[c] = cbt; cbt += (int64_t)csize[c] * csize[c + 1]; }
+            cf_off[c] = cft;
+            cft += (int64_t)csize[c] * fwidth[c];
+            cb_off[c] = cbt;
+            cbt += (int64_t)csize[c] * bwidth[c];
         }
         P->linv_elems = lft + lbt + mft + mbt;
         // entries: in-chunk ones feed Linv, adjacent-chunk ones the coupling products, the rest phase A
@@ -1000,7 +1009,7 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             const int64_t kk = row_of[e], j = sy.cols[e];
             const int32_t d = chunk_of[j] - chunk_of[kk];
             if (d == 0) intptr[j + 1]++;
-            else if (d >= 2) {
+            else if (d > hs::kFold) {
                 colptr[j + 1]++;
                 rowptr[kk + 1]++;
             }
@@ -1021,17 +1030,20 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
                     const int64_t j = sy.cols[e];
                     const int32_t ck = chunk_of[kk], cj = chunk_of[j];
                     const int32_t bk = P->bsize[kk], bj = P->bsize[j];
-                    if (cj - ck <= 1 && P->a_rank[e] >= 0)
+                    if (cj - ck <= hs::kFold && P->a_rank[e] >= 0)
                         expand.push_back(hs::ExpandTask{P->a_off[e], ad_off[e], bk, bj, P->a_rank[e], 0});
                     if (cj == ck) {
                         intent[fi[j]++] = hs::SweepEnt{ad_off[e], (int32_t)kk, -1};
-                    } else if (cj == ck + 1) {
-                        // forward coupling C_cj: rows of block j, columns of block k (alpha_kj^T)
-                        cfc.push_back(hs::CopyTask{cf_off[cj] + (int64_t)loc[j] * csize[ck] + loc[kk], ad_off[e], bj, bk,
-                                                   1, csize[ck]});
-                        // backward coupling C_cj^T: rows of block k, columns of block j (alpha_kj)
-                        cbc.push_back(hs::CopyTask{cb_off[ck] + (int64_t)loc[kk] * csize[cj] + loc[j], ad_off[e], bk, bj,
-                                                   0, csize[cj]});
+                    } else if (cj - ck <= hs::kFold) {
+                        // forward coupling of chunk cj: rows of block j, columns of block k (alpha_kj^T),
+                        // columns in elimination order from the first folded block
+                        const int64_t fcol = pos[kk] - pos[fx0[j]];
+                        cfc.push_back(hs::CopyTask{cf_off[cj] + (int64_t)loc[j] * fwidth[cj] + fcol, ad_off[e], bj, bk,
+                                                   1, fwidth[cj]});
+                        // backward coupling of chunk ck: rows of block k, columns of block j (alpha_kj)
+                        const int64_t bcol = pos[j] - pos[bx0[kk]];
+                        cbc.push_back(hs::CopyTask{cb_off[ck] + (int64_t)loc[kk] * bwidth[ck] + bcol, ad_off[e], bk, bj,
+                                                   0, bwidth[ck]});
                     } else {
                         colent[fc[j]++] = hs::SweepEnt{P->a_off[e], (int32_t)kk, P->a_rank[e]};
                         rowent[fr[kk]++] = hs::SweepEnt{P->a_off[e], (int32_t)j, P->a_rank[e]};
@@ -1047,6 +1059,14 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         P->d_colent = o.upload(colent, s);
         hs::SweepPlan& sp = P->sp;
         sp.nb = (int)nb;
+        sp.nch = (int)nch;
+        {
+            std::vector<int32_t> cblocks(nch);
+            for (int64_t c = 0; c < nch; ++c) cblocks[c] = chunk_first[c + 1] - chunk_first[c];
+            sp.chunk_of = o.upload(chunk_of, s);
+            sp.csize = o.upload(csize, s);
+            sp.cblocks = o.upload(cblocks, s);
+        }
         sp.n = H->n;
         sp.bstart = P->d_bstart;
         sp.bsize = P->d_bsize;
@@ -1056,10 +1076,10 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         sp.wt = o.upload(wtt, s);
         sp.cfirst = o.upload(cfirst, s);
         sp.clast = o.upload(clast, s);
-        sp.pf = o.upload(pf, s);
-        sp.pl = o.upload(pl, s);
-        sp.nf = o.upload(nf, s);
-        sp.nl = o.upload(nl, s);
+        sp.fx0 = o.upload(fx0, s);
+        sp.fx1 = o.upload(fx1, s);
+        sp.bx0 = o.upload(bx0, s);
+        sp.bx1 = o.upload(bx1, s);
         sp.lf_off = o.upload(lf_off, s);
         sp.lb_off = o.upload(lb_off, s);
         sp.mf_off = o.upload(mf_off, s);
@@ -1099,16 +1119,44 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         std::vector<hs::GemmTask> gf, gb;
         for (int64_t kk = 0; kk < nb; ++kk) {
             const int32_t c = chunk_of[kk], bk = P->bsize[kk];
-            if (c > 0) gf.push_back(hs::GemmTask{mf_off[kk], lf_off[kk], cf_off[c], bk, csize[c - 1], wdt[kk], 0});
-            if (c + 1 < nch)
-                gb.push_back(hs::GemmTask{mb_off[kk], lb_off[kk], cft + cb_off[c] + (int64_t)loc[kk] * csize[c + 1], bk,
-                                          csize[c + 1], wtt[kk], 0});
+            if (fwidth[c] > 0)
+                gf.push_back(hs::GemmTask{mf_off[kk], lf_off[kk], cf_off[c], bk, fwidth[c], wdt[kk], 0});
+            if (bwidth[c] > 0)
+                gb.push_back(hs::GemmTask{mb_off[kk], lb_off[kk], cft + cb_off[c] + (int64_t)loc[kk] * bwidth[c], bk,
+                                          bwidth[c], wtt[kk], 0});
         }
         hs::GemmTask* d_gf = tmp.upload(gf, s);
         hs::GemmTask* d_gb = tmp.upload(gb, s);
         hs::launch_gemm(d_gf, (int64_t)gf.size(), d_lf, d_C, d_mf, false, false, 1.0, s);
         hs::launch_gemm(d_gb, (int64_t)gb.size(), d_lb, d_C, d_mb, false, false, 1.0, s);
         hip_check(hipGetLastError(), "linv launches");
+        // work items in dependency order: per chunk its block rows (phase A), then its point rows in
+        // groups of four (phase B); forward ascending, backward descending
+        {
+            std::vector<int32_t> fwd, bwd, row_blk(H->n);
+            for (int64_t kk = 0; kk < nb; ++kk)
+                for (int32_t a = 0; a < P->bsize[kk]; ++a) row_blk[pos[kk] + a] = (int32_t)kk;
+            // phase A items of chunk c come kFold chunks ahead of the phase B rows of chunk c
+            auto rows_of = [&](int64_t c, std::vector<int32_t>& out) {
+                const int64_t r0 = pos[chunk_first[c]];
+                for (int64_t r = r0; r < r0 + csize[c]; r += 4) out.push_back((int32_t)(-r - 1));
+            };
+            for (int64_t t = 0; t < nch + hs::kFold; ++t) {
+                if (t < nch)
+                    for (int32_t kk = chunk_first[t]; kk < chunk_first[t + 1]; ++kk) fwd.push_back(kk);
+                if (t - hs::kFold >= 0) rows_of(t - hs::kFold, fwd);
+            }
+            for (int64_t t = 0; t < nch + hs::kFold; ++t) {
+                const int64_t c = nch - 1 - t;
+                if (c >= 0)
+                    for (int32_t kk = chunk_first[c + 1] - 1; kk >= chunk_first[c]; --kk) bwd.push_back(kk);
+                if (t - hs::kFold >= 0) rows_of(c + hs::kFold, bwd);
+            }
+            P->items.nitems = (int64_t)fwd.size();
+            P->items.fwd = o.upload(fwd, s);
+            P->items.bwd = o.upload(bwd, s);
+            P->items.row_blk = o.upload(row_blk, s);
+        }
         hip_check(hipStreamSynchronize(s), "stream sync");
         tmp.release();
         hs_info info;

@@ -90,18 +90,21 @@ void launch_gather(const int64_t* leaf_off, const int64_t* gptr, const GatherEnt
 // P^-1 v = alpha D^-1 alpha^T v by chunked sweeps. Block rows (elimination
 // order) are grouped into chunks of consecutive rows. With L the unit lower
 // block-triangular factor (L_jk = -alpha_kj^T), Linv_c the inverse of chunk
-// c's diagonal part and C_c the coupling of chunk c to chunk c-1:
-//   forward   y_c = Linv_c r_c + (Linv_c C_c) y_{c-1},
-//             r_c = v_c + cross terms from chunks <= c-2
-//   backward  z_c = Linv_c^T r'_c + (Linv_c^T C_{c+1}^T) z_{c+1},
-//             r'_c = zt_c + cross terms from chunks >= c+2
+// c's diagonal part and C_c the coupling of chunk c to the kFold chunks
+// before it (columns in elimination order):
+//   forward   y_c = Linv_c r_c + (Linv_c C_c) y_{c-kFold..c-1},
+//             r_c = v_c + terms from chunks more than kFold back
+//   backward  z_c = Linv_c^T r'_c + (Linv_c^T C'_c) z_{c+1..c+kFold},
+//             r'_c = zt_c + terms from chunks more than kFold ahead
 // Per block row k: pos = elimination-order offset, loc = offset in its
 // chunk, w = loc + b_k (forward Linv row width), wt = n_c - loc (backward
-// width), chunk neighbours [pf, pl] (previous) and [nf, nl] (next), -1 when
-// absent; row blocks of Linv (b_k x w), Linv^T (b_k x wt), Linv C
-// (b_k x n_prev) and Linv^T C^T (b_k x n_next), all row-major.
+// width), fx0..fx1 the blocks of the folded previous chunks and bx0..bx1
+// those of the folded next chunks (-1 when absent); row blocks of Linv
+// (b_k x w), Linv^T (b_k x wt), Linv C (b_k x fold width) and Linv^T C'
+// (b_k x fold width), all row-major.
 struct SweepPlan {
     int nb;
+    int nch;
     int64_t n;
     const int64_t* bstart;     // tree-order start of block k
     const int32_t* bsize;
@@ -111,10 +114,10 @@ struct SweepPlan {
     const int32_t* wt;
     const int32_t* cfirst;
     const int32_t* clast;
-    const int32_t* pf;
-    const int32_t* pl;
-    const int32_t* nf;
-    const int32_t* nl;
+    const int32_t* fx0;
+    const int32_t* fx1;
+    const int32_t* bx0;
+    const int32_t* bx1;
     const int64_t* lf_off;     // Linv rows
     const int64_t* lb_off;     // Linv^T rows
     const int64_t* mf_off;     // (Linv C) rows
@@ -123,7 +126,10 @@ struct SweepPlan {
     const cd* lb;
     const cd* mf;
     const cd* mb;
-    const int64_t* colptr;     // forward: entries (k, j) with chunk(j) - chunk(k) >= 2, per column j, k ascending
+    const int32_t* chunk_of;   // chunk of each block
+    const int32_t* csize;      // points of each chunk
+    const int32_t* cblocks;    // blocks of each chunk
+    const int64_t* colptr;     // forward: entries (k, j) with chunk(j) - chunk(k) > kFold, per column j, k ascending
     const SweepEnt* colent;
     const int64_t* rowptr;     // backward: the same entries per row k, j ascending
     const SweepEnt* rowent;
@@ -131,21 +137,34 @@ struct SweepPlan {
     const cd* dinv;
     const int64_t* dinv_off;
 };
+// Work items in ticket order: item >= 0 is a block row (phase A), item < 0
+// a group of four point rows starting at elimination-order row -item - 1
+// (phase B, one row per wavefront). Phase A items of chunk c + kFold come
+// before the phase B rows of chunk c. row_blk maps an elimination-order row
+// to its block.
+struct SweepItems {
+    int64_t nitems;
+    const int32_t* fwd;
+    const int32_t* bwd;
+    const int32_t* row_blk;
+};
 // Work buffers of one apply stream: ybuf, zbuf, rbuf, rbuf2 (elimination
-// order) and zt (tree order), n nrhs each; flags (4 nb ints, zeroed once);
-// tickets (2, zeroed once).
+// order) n nrhs each; flags (4 nchunk ints: per-chunk counts of finished
+// phase A blocks and phase B rows, forward then backward; zeroed once and
+// compared with epoch multiples); tickets (2, zeroed once).
 struct SweepWork {
     cd* ybuf;
     cd* zbuf;
-    cd* zt;
     cd* rbuf;
     cd* rbuf2;
     int* flags;
     unsigned long long* tickets;
 };
 constexpr int kMaxChunk = 384;   // points per chunk (bounds the row widths)
-void launch_sweeps(const SweepPlan& p, const cd* v, cd* z, int nrhs, const SweepWork& w, int epoch, hipStream_t s);
-int sweep_grid(int64_t nb);
+constexpr int kFold = 3;         // neighbouring chunks folded into the dense products
+void launch_sweeps(const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs, const SweepWork& w,
+                   int epoch, hipStream_t s);
+int sweep_grid(int64_t nitems);
 // Linv rows of every chunk from the dense in-chunk alpha blocks (intptr /
 // intent: per column j the in-chunk entries (k, j), offsets into A).
 void launch_linv(const SweepPlan& p, int nchunk, const int32_t* chunk_first, const int64_t* intptr,

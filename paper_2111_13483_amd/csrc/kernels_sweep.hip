@@ -7,23 +7,24 @@
 // Under a bandwidth-reducing order each block row depends on the one before
 // it, so both sweeps are chains of nb dependent steps. Consecutive rows are
 // grouped into chunks; with Linv_c the explicit inverse of chunk c's unit
-// lower-triangular diagonal part and C_c its coupling to chunk c-1,
-//   forward   y_c = Linv_c r_c + (Linv_c C_c) y_{c-1}
-//   backward  z_c = Linv_c^T r'_c + (Linv_c^T C_{c+1}^T) z_{c+1}
-// where r, r' gather the terms from chunks two or more away. Phase A of a
-// row gathers those terms (they are ready long before they are needed);
-// phase B applies the row's slice of the two dense products once its chunk
-// neighbour has finished, so the chain advances one dense row-block product
-// per chunk. The operator is unchanged; only the evaluation order of the
+// lower-triangular diagonal part and C_c its coupling to the kFold chunks
+// before it,
+//   forward   y_c = Linv_c r_c + (Linv_c C_c) y_{c-kFold..c-1}
+//   backward  z_c = Linv_c^T r'_c + (Linv_c^T C'_c) z_{c+1..c+kFold}
+// where r, r' gather the terms from chunks further away. Phase A of a row
+// gathers those terms (they are ready several chunks before they are
+// needed); phase B applies the row's slice of the two dense products once
+// the neighbouring chunks have finished, so the chain advances one dense
+// row-block product per chunk. The operator is unchanged; only the evaluation order of the
 // triangular solves differs.
 //
-// Each sweep is one launch. A workgroup takes block rows by ticket in the
-// dependency order, so every row it waits for belongs to a workgroup that is
-// already running. A wave checks the ready flags of up to 64 entries at once
-// with relaxed agent-scope loads, takes one acquire fence per ready batch and
-// spins only on an entry that is not ready yet. Results are published with a
-// release fence and a flag store; D^-1 follows the forward flag, off the
-// chain.
+// Each sweep is one launch over a list of work items in dependency order:
+// per chunk, its block rows (phase A, one workgroup each) then its point
+// rows in groups of four (phase B, one wavefront per row). A workgroup
+// takes items by ticket, so every item it waits for belongs to a workgroup
+// that is already running. Ready state is a flag per block for phase A and
+// a per-block count of finished rows for phase B; a wave checks up to 64 of
+// them at once and spins only on one that is not ready yet.
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -39,6 +40,23 @@ __device__ __forceinline__ int relaxed_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Vectors exchanged between workgroups inside a sweep are read and written
+// only with relaxed agent-scope atomics (coherent across the XCDs' L2s by
+// themselves), so no cache-wide writeback/invalidate fence is needed; a
+// publisher waits for its stores to complete before setting the ready flag.
+__device__ __forceinline__ cd ld_sc(const cd* p) {
+    const double* d = reinterpret_cast<const double*>(p);
+    return cmk(__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+               __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_sc(cd* p, cd v) {
+    double* d = reinterpret_cast<double*>(p);
+    __hip_atomic_store(d, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(d + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
 __device__ __forceinline__ cd shfl_cd(cd v, int src) {
     return cmk(__shfl(v.x, src, kWave), __shfl(v.y, src, kWave));
 }
@@ -50,38 +68,43 @@ __device__ __forceinline__ int take_ticket(unsigned long long* ctr, unsigned lon
     return *s_t;
 }
 
-// Publish a row: wave-local stores are complete and visible agent-wide
-// before the flag.
+// Publish: this wave's exchanged stores have completed before the flag.
 __device__ __forceinline__ void publish(int* flag, int epoch) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    stores_done();
     if ((threadIdx.x % kWave) == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Walk this wave's entries (positions w, w + NW, ... of [0, cnt) in the
-// list `ent` starting at `e0` with step `dir`), waiting for each entry's
-// block to be ready, and call body(entry) in list order.
+// list `ent` starting at `e0` with step `dir`), waiting until every row of
+// the chunk holding each entry's block has been published (per-chunk row
+// counter equal to epoch * chunk size), and call body(entry) in list order.
 template <class Body>
 __device__ __forceinline__ void for_ready_entries(const SweepEnt* __restrict__ ents, int64_t e0, int dir, int cnt,
-                                                  const int* flags, int epoch, Body body) {
+                                                  const int* cnts, const int32_t* chunk_of, const int32_t* csize,
+                                                  int epoch, Body body) {
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
     const int mine = cnt > wid ? (cnt - wid + NW - 1) / NW : 0;
     for (int qb = 0; qb < mine; qb += kWave) {
         const int nv = min(kWave, mine - qb);
         SweepEnt my{};
-        if (lane < nv) my = ents[e0 + (int64_t)dir * (wid + NW * (qb + lane))];
+        int need = 0, mc = 0;
+        if (lane < nv) {
+            my = ents[e0 + (int64_t)dir * (wid + NW * (qb + lane))];
+            mc = chunk_of[my.k];
+            need = epoch * csize[mc];
+        }
         int done = 0;
         while (done < nv) {
             const bool pending = lane >= done && lane < nv;
-            const bool ok = !pending || relaxed_load(flags + my.k) == epoch;
+            const bool ok = !pending || relaxed_load(cnts + mc) == need;
             const unsigned long long m = __ballot(ok);
-            // first lane at or after `done` that is not ready
             const unsigned long long notready = ~m & (nv == kWave ? ~0ull : ((1ull << nv) - 1ull));
             const int upto = notready ? __builtin_ctzll(notready) : nv;
             if (upto <= done) {
                 __builtin_amdgcn_s_sleep(1);
                 continue;
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            compiler_fence();
             for (int p = done; p < upto; ++p) {
                 SweepEnt e;
                 e.off = __shfl(my.off, p, kWave);
@@ -93,31 +116,25 @@ __device__ __forceinline__ void for_ready_entries(const SweepEnt* __restrict__ e
         }
     }
 }
-// Wait until flags[first..last] all equal epoch (whole wave); no fence.
-__device__ __forceinline__ void wait_range_nofence(const int* flags, int first, int last, int epoch) {
-    const int lane = threadIdx.x % kWave;
-    for (int b0 = first; b0 <= last; b0 += kWave) {
-        const int f = b0 + lane;
-        for (;;) {
-            const bool ok = f > last || relaxed_load(flags + f) == epoch;
-            if (__ballot(!ok) == 0ull) break;
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
+
+// Wave-level wait (no fence): counter cnts[c] == need (c < 0 skipped).
+__device__ __forceinline__ void wait_count(const int* cnts, int c, int need) {
+    if (c < 0) return;
+    while (relaxed_load(cnts + c) != need) __builtin_amdgcn_s_sleep(1);
 }
 
 constexpr int QC = kMaxChunk / kWave;   // 64-wide column groups of a chunk
-constexpr int RB2 = 2;                  // dense rows whose loads are issued together
+constexpr int QF = kFold * QC;          // column groups of the folded neighbours
 
 // Phase A accumulation over one list of entries (forward: alpha^T y_k into
 // columns b of the row block; backward: alpha z_j into rows a).
 template <int S, bool FWD>
 __device__ __forceinline__ void phase_a(const SweepPlan& p, const SweepEnt* ents, int64_t e0, int dir, int cnt,
-                                        const int* flags, int epoch, const cd* src, int c0, int cs, int bme,
+                                        const int* cnts, int epoch, const cd* src, int c0, int cs, int bme,
                                         cd (&acc)[2][S]) {
     const int lane = threadIdx.x % kWave;
     const int64_t n = p.n;
-    for_ready_entries(ents, e0, dir, cnt, flags, epoch, [&](const SweepEnt& e) {
+    for_ready_entries(ents, e0, dir, cnt, cnts, p.chunk_of, p.csize, epoch, [&](const SweepEnt& e) {
         const int o = e.k, bo = p.bsize[o];
         const int64_t so = p.pos[o];
         cd x[2][S];
@@ -126,7 +143,7 @@ __device__ __forceinline__ void phase_a(const SweepPlan& p, const SweepEnt* ents
 #pragma unroll
             for (int c = 0; c < S; ++c) {
                 const int a = lane + q * kWave;
-                x[q][c] = (a < bo && c < cs) ? src[so + a + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
+                x[q][c] = (a < bo && c < cs) ? ld_sc(src + so + a + (int64_t)(c0 + c) * n) : cmk(0.0, 0.0);
             }
         // the stored block is alpha_{row, col}: forward (row = o, col = me), backward (row = me, col = o)
         const int rows = FWD ? bo : bme, cols = FWD ? bme : bo;
@@ -203,48 +220,40 @@ __device__ __forceinline__ void phase_a(const SweepPlan& p, const SweepEnt* ents
     });
 }
 
-// out rows a (wave-strided) of [A1 | A2] x [x1; x2]: A1 is rows x w1 at a1,
-// x1 = src1[o1 + col]; A2 rows x w2 at a2, x2 = src2[o2 + col] (w2 may be 0).
+// One row of [A1 | A2] x [x1; x2] by one wave: A1 row of width w1 (<=
+// kMaxChunk) times xs1[o1 + col], A2 row of width w2 (<= kFold kMaxChunk)
+// times xs2[col]; xs1 / xs2 are LDS copies (column c at stride ld1 / ld2).
 template <int S>
-__device__ __forceinline__ void dense_rows(const cd* A1, int w1, const cd* src1, int64_t o1, const cd* A2, int w2,
-                                           const cd* src2, int64_t o2, int rows, int64_t n, int c0, int cs,
-                                           cd* out_lds) {
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    cd x1[QC][S], x2[QC][S];
+__device__ __forceinline__ void dense_row(const cd* A1, int w1, const cd* xs1, int o1, int ld1, const cd* A2, int w2,
+                                          const cd* xs2, int ld2, int cs, cd (&out)[S]) {
+    const int lane = threadIdx.x % kWave;
+    cd R1[QC], R2[QF];
 #pragma unroll
-    for (int q = 0; q < QC; ++q)
+    for (int q = 0; q < QC; ++q) {
+        const int col = lane + q * kWave;
+        R1[q] = col < w1 ? A1[col] : cmk(0.0, 0.0);
+    }
 #pragma unroll
-        for (int c = 0; c < S; ++c) {
-            const int col = lane + q * kWave;
-            x1[q][c] = (col < w1 && c < cs) ? src1[o1 + col + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
-            x2[q][c] = (col < w2 && c < cs) ? src2[o2 + col + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
-        }
-    for (int a0 = wid; a0 < rows; a0 += NW * RB2) {
-        cd R1[RB2][QC], R2[RB2][QC];
+    for (int q = 0; q < QF; ++q) {
+        const int col = lane + q * kWave;
+        R2[q] = col < w2 ? A2[col] : cmk(0.0, 0.0);
+    }
 #pragma unroll
-        for (int r = 0; r < RB2; ++r)
+    for (int c = 0; c < S; ++c) {
+        cd sacc = cmk(0.0, 0.0);
+        if (c < cs) {
 #pragma unroll
             for (int q = 0; q < QC; ++q) {
-                const int a = a0 + NW * r, col = lane + q * kWave;
-                R1[r][q] = (a < rows && col < w1) ? A1[(int64_t)a * w1 + col] : cmk(0.0, 0.0);
-                R2[r][q] = (a < rows && col < w2) ? A2[(int64_t)a * w2 + col] : cmk(0.0, 0.0);
+                const int col = lane + q * kWave;
+                if (col < w1) sacc = cfma(R1[q], xs1[o1 + col + c * ld1], sacc);
             }
 #pragma unroll
-        for (int r = 0; r < RB2; ++r) {
-            const int a = a0 + NW * r;
-            if (a < rows)
-#pragma unroll
-            for (int c = 0; c < S; ++c) {
-                cd sacc = cmk(0.0, 0.0);
-#pragma unroll
-                for (int q = 0; q < QC; ++q) {
-                    sacc = cfma(R1[r][q], x1[q][c], sacc);
-                    sacc = cfma(R2[r][q], x2[q][c], sacc);
-                }
-                sacc = wave_sum(sacc);
-                if (lane == 0 && c < cs) out_lds[a + c * rows] = sacc;
+            for (int q = 0; q < QF; ++q) {
+                const int col = lane + q * kWave;
+                if (col < w2) sacc = cfma(R2[q], xs2[col + c * ld2], sacc);
             }
         }
+        out[c] = wave_sum(sacc);
     }
 }
 
@@ -253,97 +262,104 @@ __device__ __forceinline__ void dense_rows(const cd* A1, int w1, const cd* src1,
 // Forward sweep; S right-hand sides per pass.
 template <int S>
 __global__ void __launch_bounds__(NT)
-k_sweep_fwd(SweepPlan p, const cd* __restrict__ v, SweepWork wk, int nrhs, unsigned long long base, int epoch) {
+k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, int nrhs, unsigned long long base,
+            int epoch) {
     __shared__ int s_t;
     __shared__ cd part[NW][kMaxLeaf * S];
-    __shared__ cd ysh[kMaxLeaf * S];
+    __shared__ cd xs1[kMaxChunk * S];
+    __shared__ cd xs2[kFold * kMaxChunk * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
-    int* flagY = wk.flags;
-    int* flagR = wk.flags + p.nb;
+    int* cntA = wk.flags;
+    int* cntB = wk.flags + p.nch;
     for (;;) {
-        const int j = take_ticket(wk.tickets, base, &s_t);
-        if (j >= p.nb) return;
-        const int bj = p.bsize[j];
-        const int64_t sj = p.bstart[j], pj = p.pos[j];
-        const int64_t e0 = p.colptr[j];
-        const int cnt = (int)(p.colptr[j + 1] - e0);
-        // ---- phase A: r_j = v_j + terms from chunks two or more back
-        for (int c0 = 0; c0 < nrhs; c0 += S) {
-            const int cs = min(S, nrhs - c0);
-            cd acc[2][S];
+        const int t = take_ticket(wk.tickets, base, &s_t);
+        if (t >= it.nitems) return;
+        const int item = it.fwd[t];
+        if (item >= 0) {
+            // ---- phase A: r_j = v_j + terms from chunks more than kFold back
+            const int j = item;
+            const int bj = p.bsize[j];
+            const int64_t sj = p.bstart[j], pj = p.pos[j];
+            const int64_t e0 = p.colptr[j];
+            const int cnt = (int)(p.colptr[j + 1] - e0);
+            for (int c0 = 0; c0 < nrhs; c0 += S) {
+                const int cs = min(S, nrhs - c0);
+                cd acc[2][S];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int c = 0; c < S; ++c) acc[q][c] = cmk(0.0, 0.0);
-            phase_a<S, true>(p, p.colent, e0, 1, cnt, flagY, epoch, wk.ybuf, c0, cs, bj, acc);
+                    for (int c = 0; c < S; ++c) acc[q][c] = cmk(0.0, 0.0);
+                phase_a<S, true>(p, p.colent, e0, 1, cnt, cntB, epoch, wk.ybuf, c0, cs, bj, acc);
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int b = lane + q * kWave;
-                if (b < bj)
+                for (int q = 0; q < 2; ++q) {
+                    const int b = lane + q * kWave;
+                    if (b < bj)
 #pragma unroll
-                    for (int c = 0; c < S; ++c)
-                        if (c < cs) part[wid][b + c * bj] = acc[q][c];
-            }
-            __syncthreads();
-            if (wid == 0) {
-                for (int q = lane; q < bj * cs; q += kWave) {
-                    cd s = v[sj + q % bj + (int64_t)(c0 + q / bj) * n];
-#pragma unroll
-                    for (int w = 0; w < NW; ++w) s = cadd(s, part[w][q]);
-                    wk.rbuf[pj + q % bj + (int64_t)(c0 + q / bj) * n] = s;
+                        for (int c = 0; c < S; ++c)
+                            if (c < cs) part[wid][b + c * bj] = acc[q][c];
                 }
-                if (c0 + S >= nrhs) publish(flagR + j, epoch);
-            }
-            __syncthreads();
-        }
-        // ---- phase B: y_j = Linv rows r_c + (Linv C) rows y_{c-1}
-        const int cf = p.cfirst[j];
-        const int pf = p.pf[j], pl = p.pl[j];
-        wait_range_nofence(flagR, cf, j, epoch);
-        if (pf >= 0) wait_range_nofence(flagY, pf, pl, epoch);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const int wprev = pf >= 0 ? (int)(p.pos[pl] + p.bsize[pl] - p.pos[pf]) : 0;
-        for (int c0 = 0; c0 < nrhs; c0 += S) {
-            const int cs = min(S, nrhs - c0);
-            dense_rows<S>(p.lf + p.lf_off[j], p.w[j], wk.rbuf, p.pos[cf], p.mf + p.mf_off[j], wprev, wk.ybuf,
-                          pf >= 0 ? p.pos[pf] : 0, bj, n, c0, cs, ysh);
-            __syncthreads();
-            if (wid == 0) {
-                for (int q = lane; q < bj * cs; q += kWave)
-                    wk.ybuf[pj + q % bj + (int64_t)(c0 + q / bj) * n] = ysh[q];
-                if (c0 + S >= nrhs) publish(flagY + j, epoch);
-            }
-            __syncthreads();
-            // zt_j = D_j^-1 y_j, off the chain
-            const cd* Di = p.dinv + p.dinv_off[j];
-            for (int a0 = wid; a0 < bj; a0 += NW * RB) {
-                cd Dr[RB][2];
+                __syncthreads();
+                if (wid == 0) {
+                    for (int q = lane; q < bj * cs; q += kWave) {
+                        cd s = v[sj + q % bj + (int64_t)(c0 + q / bj) * n];
 #pragma unroll
-                for (int r = 0; r < RB; ++r)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const int a = a0 + NW * r, b = lane + q * kWave;
-                        Dr[r][q] = (a < bj && b < bj) ? Di[(int64_t)a * bj + b] : cmk(0.0, 0.0);
+                        for (int w = 0; w < NW; ++w) s = cadd(s, part[w][q]);
+                        st_sc(wk.rbuf + pj + q % bj + (int64_t)(c0 + q / bj) * n, s);
                     }
-#pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    const int a = a0 + NW * r;
-                    if (a < bj)
-#pragma unroll
-                    for (int c = 0; c < S; ++c) {
-                        cd sacc = cmk(0.0, 0.0);
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            const int b = lane + q * kWave;
-                            if (b < bj) sacc = cfma(Dr[r][q], ysh[b + c * bj], sacc);
-                        }
-                        sacc = wave_sum(sacc);
-                        if (lane == 0 && c < cs) wk.zt[sj + a + (int64_t)(c0 + c) * n] = sacc;
+                    if (c0 + S >= nrhs) {
+                        stores_done();
+                        if (lane == 0)
+                            __hip_atomic_fetch_add(cntA + p.chunk_of[j], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
+                __syncthreads();
+            }
+        } else {
+            // ---- phase B: one point row per wave: y_i = Linv row . r_c + (Linv C) row . y_prev
+            const int r0 = -item - 1;
+            const int jb = it.row_blk[r0];
+            const int c = p.chunk_of[jb];
+            const int cf = p.cfirst[jb];
+            const int f0 = p.fx0[jb], f1 = p.fx1[jb];
+            const int nc = p.csize[c];
+            const int wprev = f1 >= 0 ? (int)(p.pos[f1] + p.bsize[f1] - p.pos[f0]) : 0;
+            if (wid == 0) {
+                wait_count(cntA, c, epoch * p.cblocks[c]);
+                for (int d = 1; d <= kFold; ++d)
+                    if (c - d >= 0) wait_count(cntB, c - d, epoch * p.csize[c - d]);
             }
             __syncthreads();
+            compiler_fence();
+            const int64_t pc = p.pos[cf];
+            const int64_t pf0 = f1 >= 0 ? p.pos[f0] : 0;
+            const int i = r0 + wid;
+            const bool live = i < pc + nc;
+            const int j = live ? it.row_blk[i] : jb;
+            const int a = i - (int)p.pos[j];
+            for (int c0 = 0; c0 < nrhs; c0 += S) {
+                const int cs = min(S, nrhs - c0);
+                for (int q = tid; q < nc * cs; q += NT)
+                    xs1[q] = ld_sc(wk.rbuf + pc + q % nc + (int64_t)(c0 + q / nc) * n);
+                for (int q = tid; q < wprev * cs; q += NT)
+                    xs2[q] = ld_sc(wk.ybuf + pf0 + q % wprev + (int64_t)(c0 + q / wprev) * n);
+                __syncthreads();
+                if (live) {
+                    const int wj = p.w[j];
+                    cd y[S];
+                    dense_row<S>(p.lf + p.lf_off[j] + (int64_t)a * wj, wj, xs1, 0, nc,
+                                 p.mf + p.mf_off[j] + (int64_t)a * wprev, wprev, xs2, wprev, cs, y);
+                    if (lane == 0)
+#pragma unroll
+                        for (int cc = 0; cc < S; ++cc)
+                            if (cc < cs) st_sc(wk.ybuf + i + (int64_t)(c0 + cc) * n, y[cc]);
+                }
+                __syncthreads();
+            }
+            if (live) {
+                stores_done();
+                if (lane == 0) __hip_atomic_fetch_add(cntB + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
 }
@@ -351,71 +367,139 @@ k_sweep_fwd(SweepPlan p, const cd* __restrict__ v, SweepWork wk, int nrhs, unsig
 // Backward sweep; S right-hand sides per pass.
 template <int S>
 __global__ void __launch_bounds__(NT)
-k_sweep_bwd(SweepPlan p, cd* __restrict__ z, SweepWork wk, int nrhs, unsigned long long base, int epoch) {
+k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nrhs, unsigned long long base,
+            int epoch) {
     __shared__ int s_t;
     __shared__ cd part[NW][kMaxLeaf * S];
-    __shared__ cd zsh[kMaxLeaf * S];
+    __shared__ cd ysh[kMaxLeaf * S];
+    __shared__ cd ztsh[kMaxLeaf * S];
+    __shared__ cd xs1[kMaxChunk * S];
+    __shared__ cd xs2[kFold * kMaxChunk * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
-    int* flagZ = wk.flags + 2 * p.nb;
-    int* flagR = wk.flags + 3 * p.nb;
+    int* cntA = wk.flags + 2 * p.nch;
+    int* cntB = wk.flags + 3 * p.nch;
     for (;;) {
         const int t = take_ticket(wk.tickets + 1, base, &s_t);
-        if (t >= p.nb) return;
-        const int k = p.nb - 1 - t;
-        const int bk = p.bsize[k];
-        const int64_t sk = p.bstart[k], pk = p.pos[k];
-        const int64_t e_last = p.rowptr[k + 1] - 1;
-        const int cnt = (int)(p.rowptr[k + 1] - p.rowptr[k]);
-        // ---- phase A: r'_k = zt_k + terms from chunks two or more ahead (nearest last)
-        for (int c0 = 0; c0 < nrhs; c0 += S) {
-            const int cs = min(S, nrhs - c0);
-            cd acc[2][S];
+        if (t >= it.nitems) return;
+        const int item = it.bwd[t];
+        if (item >= 0) {
+            // ---- phase A: r'_k = D_k^-1 y_k + terms from chunks more than kFold ahead
+            const int k = item;
+            const int bk = p.bsize[k];
+            const int64_t pk = p.pos[k];
+            const int64_t e_last = p.rowptr[k + 1] - 1;
+            const int cnt = (int)(p.rowptr[k + 1] - p.rowptr[k]);
+            const cd* Di = p.dinv + p.dinv_off[k];
+            for (int c0 = 0; c0 < nrhs; c0 += S) {
+                const int cs = min(S, nrhs - c0);
+                for (int q = tid; q < bk * cs; q += NT) ysh[q] = wk.ybuf[pk + q % bk + (int64_t)(c0 + q / bk) * n];
+                __syncthreads();
+                for (int a0 = wid; a0 < bk; a0 += NW * RB) {
+                    cd Dr[RB][2];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+                    for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int c = 0; c < S; ++c) acc[q][c] = cmk(0.0, 0.0);
-            phase_a<S, false>(p, p.rowent, e_last, -1, cnt, flagZ, epoch, wk.zbuf, c0, cs, bk, acc);
+                        for (int q = 0; q < 2; ++q) {
+                            const int a = a0 + NW * r, b = lane + q * kWave;
+                            Dr[r][q] = (a < bk && b < bk) ? Di[(int64_t)a * bk + b] : cmk(0.0, 0.0);
+                        }
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int a = lane + q * kWave;
-                if (a < bk)
+                    for (int r = 0; r < RB; ++r) {
+                        const int a = a0 + NW * r;
+                        if (a < bk)
 #pragma unroll
-                    for (int c = 0; c < S; ++c)
-                        if (c < cs) part[wid][a + c * bk] = acc[q][c];
-            }
-            __syncthreads();
-            if (wid == 0) {
-                for (int q = lane; q < bk * cs; q += kWave) {
-                    cd s = wk.zt[sk + q % bk + (int64_t)(c0 + q / bk) * n];
+                        for (int c = 0; c < S; ++c) {
+                            cd sacc = cmk(0.0, 0.0);
 #pragma unroll
-                    for (int w = 0; w < NW; ++w) s = cadd(s, part[w][q]);
-                    wk.rbuf2[pk + q % bk + (int64_t)(c0 + q / bk) * n] = s;
+                            for (int q = 0; q < 2; ++q) {
+                                const int b = lane + q * kWave;
+                                if (b < bk) sacc = cfma(Dr[r][q], ysh[b + c * bk], sacc);
+                            }
+                            sacc = wave_sum(sacc);
+                            if (lane == 0 && c < cs) ztsh[a + c * bk] = sacc;
+                        }
+                    }
                 }
-                if (c0 + S >= nrhs) publish(flagR + k, epoch);
-            }
-            __syncthreads();
-        }
-        // ---- phase B: z_k = Linv^T rows r'_c + (Linv^T C^T) rows z_{c+1}
-        const int cl = p.clast[k];
-        const int nf = p.nf[k], nl = p.nl[k];
-        wait_range_nofence(flagR, k, cl, epoch);
-        if (nf >= 0) wait_range_nofence(flagZ, nf, nl, epoch);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const int wnext = nf >= 0 ? (int)(p.pos[nl] + p.bsize[nl] - p.pos[nf]) : 0;
-        for (int c0 = 0; c0 < nrhs; c0 += S) {
-            const int cs = min(S, nrhs - c0);
-            dense_rows<S>(p.lb + p.lb_off[k], p.wt[k], wk.rbuf2, pk, p.mb + p.mb_off[k], wnext, wk.zbuf,
-                          nf >= 0 ? p.pos[nf] : 0, bk, n, c0, cs, zsh);
-            __syncthreads();
-            if (wid == 0) {
-                for (int q = lane; q < bk * cs; q += kWave) {
-                    wk.zbuf[pk + q % bk + (int64_t)(c0 + q / bk) * n] = zsh[q];
-                    z[sk + q % bk + (int64_t)(c0 + q / bk) * n] = zsh[q];
+                cd acc[2][S];
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int c = 0; c < S; ++c) acc[q][c] = cmk(0.0, 0.0);
+                phase_a<S, false>(p, p.rowent, e_last, -1, cnt, cntB, epoch, wk.zbuf, c0, cs, bk, acc);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int a = lane + q * kWave;
+                    if (a < bk)
+#pragma unroll
+                        for (int c = 0; c < S; ++c)
+                            if (c < cs) part[wid][a + c * bk] = acc[q][c];
                 }
-                if (c0 + S >= nrhs) publish(flagZ + k, epoch);
+                __syncthreads();
+                if (wid == 0) {
+                    for (int q = lane; q < bk * cs; q += kWave) {
+                        cd s = ztsh[q];
+#pragma unroll
+                        for (int w = 0; w < NW; ++w) s = cadd(s, part[w][q]);
+                        st_sc(wk.rbuf2 + pk + q % bk + (int64_t)(c0 + q / bk) * n, s);
+                    }
+                    if (c0 + S >= nrhs) {
+                        stores_done();
+                        if (lane == 0)
+                            __hip_atomic_fetch_add(cntA + p.chunk_of[k], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                __syncthreads();
+            }
+        } else {
+            // ---- phase B: one point row per wave: z_i = Linv^T row . r'_c + (Linv^T C') row . z_next
+            const int r0 = -item - 1;
+            const int kb = it.row_blk[r0];
+            const int c = p.chunk_of[kb];
+            const int cf = p.cfirst[kb];
+            const int g0 = p.bx0[kb], g1 = p.bx1[kb];
+            const int nc = p.csize[c];
+            const int wnext = g0 >= 0 ? (int)(p.pos[g1] + p.bsize[g1] - p.pos[g0]) : 0;
+            if (wid == 0) {
+                wait_count(cntA, c, epoch * p.cblocks[c]);
+                for (int d = 1; d <= kFold; ++d)
+                    if (c + d < p.nch) wait_count(cntB, c + d, epoch * p.csize[c + d]);
             }
             __syncthreads();
+            compiler_fence();
+            const int64_t pc = p.pos[cf];
+            const int64_t pg0 = g0 >= 0 ? p.pos[g0] : 0;
+            const int i = r0 + wid;
+            const bool live = i < pc + nc;
+            const int k = live ? it.row_blk[i] : kb;
+            const int a = i - (int)p.pos[k];
+            const int64_t sk = p.bstart[k];
+            for (int c0 = 0; c0 < nrhs; c0 += S) {
+                const int cs = min(S, nrhs - c0);
+                for (int q = tid; q < nc * cs; q += NT)
+                    xs1[q] = ld_sc(wk.rbuf2 + pc + q % nc + (int64_t)(c0 + q / nc) * n);
+                for (int q = tid; q < wnext * cs; q += NT)
+                    xs2[q] = ld_sc(wk.zbuf + pg0 + q % wnext + (int64_t)(c0 + q / wnext) * n);
+                __syncthreads();
+                if (live) {
+                    const int wtk = p.wt[k];
+                    cd zz[S];
+                    dense_row<S>(p.lb + p.lb_off[k] + (int64_t)a * wtk, wtk, xs1, p.loc[k], nc,
+                                 p.mb + p.mb_off[k] + (int64_t)a * wnext, wnext, xs2, wnext, cs, zz);
+                    if (lane == 0)
+#pragma unroll
+                        for (int cc = 0; cc < S; ++cc)
+                            if (cc < cs) {
+                                st_sc(wk.zbuf + i + (int64_t)(c0 + cc) * n, zz[cc]);
+                                z[sk + a + (int64_t)(c0 + cc) * n] = zz[cc];
+                            }
+                }
+                __syncthreads();
+            }
+            if (live) {
+                stores_done();
+                if (lane == 0) __hip_atomic_fetch_add(cntB + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
 }
@@ -481,17 +565,18 @@ k_lr_expand(const ExpandTask* __restrict__ tasks, const cd* __restrict__ src, cd
     }
 }
 
-int sweep_grid(int64_t nb) { return (int)(nb < 1024 ? nb : 1024); }
+int sweep_grid(int64_t nitems) { return (int)(nitems < 1024 ? nitems : 1024); }
 
-void launch_sweeps(const SweepPlan& p, const cd* v, cd* z, int nrhs, const SweepWork& w, int epoch, hipStream_t s) {
-    const int G = sweep_grid(p.nb);
-    const unsigned long long base = (unsigned long long)(epoch - 1) * (unsigned long long)(p.nb + G);
+void launch_sweeps(const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs, const SweepWork& w,
+                   int epoch, hipStream_t s) {
+    const int G = sweep_grid(it.nitems);
+    const unsigned long long base = (unsigned long long)(epoch - 1) * (unsigned long long)(it.nitems + G);
     if (nrhs == 1) {
-        hipLaunchKernelGGL(k_sweep_fwd<1>, dim3(G), dim3(NT), 0, s, p, v, w, nrhs, base, epoch);
-        hipLaunchKernelGGL(k_sweep_bwd<1>, dim3(G), dim3(NT), 0, s, p, z, w, nrhs, base, epoch);
+        hipLaunchKernelGGL(k_sweep_fwd<1>, dim3(G), dim3(NT), 0, s, p, it, v, w, nrhs, base, epoch);
+        hipLaunchKernelGGL(k_sweep_bwd<1>, dim3(G), dim3(NT), 0, s, p, it, z, w, nrhs, base, epoch);
     } else {
-        hipLaunchKernelGGL(k_sweep_fwd<4>, dim3(G), dim3(NT), 0, s, p, v, w, nrhs, base, epoch);
-        hipLaunchKernelGGL(k_sweep_bwd<4>, dim3(G), dim3(NT), 0, s, p, z, w, nrhs, base, epoch);
+        hipLaunchKernelGGL(k_sweep_fwd<2>, dim3(G), dim3(NT), 0, s, p, it, v, w, nrhs, base, epoch);
+        hipLaunchKernelGGL(k_sweep_bwd<2>, dim3(G), dim3(NT), 0, s, p, it, z, w, nrhs, base, epoch);
     }
 }
 
