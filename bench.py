@@ -23,6 +23,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_kernels_c2_hbm_traffic.md")
+KERNEL_SOURCES = ("paper_2111_13483_amd/csrc/kernels_sweep.hip", "paper_2111_13483_amd/csrc/kernels_solve.hip",
+                  "paper_2111_13483_amd/csrc/kernels.h", "paper_2111_13483_amd/csrc/devcommon.h")
+# the instrumented launches and their kernels' names
+KERNEL_NAME = {"sweep_fwd": "k_sweep_fwd", "sweep_bwd": "k_sweep_bwd", "near_mv": "k_near_mv", "far_mv": "k_far_mv"}
 
 
 def parse():
@@ -35,7 +40,124 @@ def parse():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work to sample")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--summarize-stats", metavar="DIR", help="summarise a rocprofv3 --stats run and exit")
+    ap.add_argument("--out", help="summary file written by --summarize-*")
+    ap.add_argument("--command", default="", help="command line recorded in the summary")
     return ap.parse_args()
+
+
+# ---------------------------------------------------------------- profile summaries
+
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _find_csv(d, suffix):
+    for base, _, files in os.walk(d):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                return os.path.join(base, f)
+    raise SystemExit(f"no *{suffix} under {d}")
+
+
+def _read_counters(d, counter):
+    """Per-dispatch values of one counter: list of (kernel name, value)."""
+    import csv
+    rows = []
+    with open(_find_csv(d, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") == counter:
+                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def _per_kernel(rows):
+    agg = {}
+    for name, v in rows:
+        a = agg.setdefault(name, [0, 0.0])
+        a[0] += 1
+        a[1] += v
+    return agg
+
+
+def summarize_pmc(fetch_dir, write_dir, out, command, copy_bytes):
+    fetch = _read_counters(fetch_dir, "FETCH_SIZE")
+    write = _read_counters(write_dir, "WRITE_SIZE")
+    # calibration: the largest copy dispatch (copy_bytes read and copy_bytes written)
+    cf = max(v for n, v in fetch if "copy" in n.lower())
+    cw = max(v for n, v in write if "copy" in n.lower())
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    af, aw = _per_kernel(fetch), _per_kernel(write)
+    lines = [f"# HBM traffic per launch, sphere + ellipsoid N = 20,000 (bench.py default workload)", "",
+             "Commands (FETCH_SIZE run, then WRITE_SIZE run):", "", "```", command, "```", "",
+             f"Calibration: one device-to-device copy of {copy_bytes} bytes reads FETCH_SIZE = {cf:.0f} KiB and "
+             f"WRITE_SIZE = {cw:.0f} KiB; scale factors {f_scale:.4f} (fetch) and {w_scale:.4f} (write).", "",
+             "| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | scaled MB read | scaled MB written |",
+             "|---|---|---|---|---|---|"]
+    found = {}
+    for key, pre in KERNEL_NAME.items():
+        names = [n for n in af if pre in n]
+        if not names:
+            continue
+        nf = sum(af[n][0] for n in names)
+        vf = sum(af[n][1] for n in names) / nf
+        nw = sum(aw[n][0] for n in names if n in aw)
+        vw = sum(aw[n][1] for n in names if n in aw) / max(nw, 1)
+        rb, wb = vf * 1024.0 * f_scale, vw * 1024.0 * w_scale
+        found[key] = (rb, wb)
+        lines.append(f"| {pre} | {nf} | {vf:.0f} | {vw:.0f} | {rb / 1e6:.1f} | {wb / 1e6:.1f} |")
+    lines += ["", "Machine-readable (bench.py reads these while the kernel sources hash to `source`):", ""]
+    for key, (rb, wb) in found.items():
+        lines.append(f"traffic: kernel={key} read_bytes={rb:.0f} write_bytes={wb:.0f} source={_source_hash()}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_stats(d, out, command, top=25):
+    import csv
+    with open(_find_csv(d, "kernel_stats.csv")) as f:
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# Kernel time, sphere + ellipsoid N = 20,000 (bench.py default workload)", "",
+             "Command:", "", "```", command, "```", "",
+             "| kernel | calls | total ms | average us | min us | max us | share % |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"]
+        name = name if len(name) < 90 else name[:87] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def committed_traffic():
+    """Scaled HBM bytes per launch from the committed counter summary; a
+    kernel is absent when its sources changed since the counters were taken."""
+    if not os.path.exists(PMC_SUMMARY):
+        return {}
+    src = _source_hash()
+    out = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if not line.startswith("traffic: "):
+                continue
+            kv = dict(p.split("=", 1) for p in line.split()[1:])
+            if kv.get("source") == src:
+                out[kv["kernel"]] = float(kv["read_bytes"]) + float(kv["write_bytes"])
+    return out
 
 
 def cpu_baseline(wl, gpu_iters, budget_s):
@@ -137,6 +259,13 @@ def cpu_baseline(wl, gpu_iters, budget_s):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.out, args.command,
+                      args.copy_calib_mib << 20)
+        return
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats, args.out, args.command)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -151,6 +280,11 @@ def main():
     ctx = hsl.Context(0)
     pts = torch.as_tensor(wl.points, device=dev)
     rhs = torch.as_tensor(np.ascontiguousarray(wl.rhs), device=dev)
+    if args.copy_calib_mib:
+        src = torch.ones(args.copy_calib_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        del src, dst
     torch.cuda.synchronize()
 
     def step(record):
@@ -174,11 +308,13 @@ def main():
         step(warm)
     rec = []
     torch.cuda.synchronize()
+    ctx.timing_begin()
     T0 = time.perf_counter()
     for _ in range(args.steps):
         H, P = step(rec)
     torch.cuda.synchronize()
     T = time.perf_counter() - T0
+    ktimes = ctx.timing_end()
     hinfo, pinfo = H.info(), P.info()
     nrhs = args.nrhs
     steps = args.steps
@@ -205,6 +341,26 @@ def main():
         "precond": {k: pinfo[k] for k in ("n_pattern", "n_fill", "n_lowrank", "max_dk", "bytes_alpha", "bytes_d",
                                           "flops_setup")},
     }
+    # algorithmic HBM bytes per launch: each stored matrix byte the kernel
+    # needs is read once, plus one read and one write of its N x nrhs vectors
+    vec = 32 * wl.n * nrhs
+    alg = {"sweep_fwd": pinfo["bytes_alpha"] + vec,
+           "sweep_bwd": pinfo["bytes_alpha"] + pinfo["bytes_d"] + vec,
+           "near_mv": hinfo["bytes_near"] + vec,
+           "far_mv": hinfo["bytes_far"] + vec}
+    kern = {}
+    for name, (cnt, ms) in ktimes.items():
+        if cnt:
+            avg = ms / cnt
+            kern[name] = {"launches": cnt, "avg_ms": avg, "alg_bytes": alg[name],
+                          "GB_per_s": alg[name] / (avg * 1e-3) / 1e9}
+    dom = max(kern, key=lambda k: kern[k]["launches"] * kern[k]["avg_ms"])
+    traffic = committed_traffic()
+    achieved = kern[dom]["GB_per_s"]
+    out["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAME[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic.get(dom),
+                       "alg_bytes_per_launch": alg[dom], "avg_launch_ms": kern[dom]["avg_ms"]}
+    out["kernels"] = kern
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, rec[-1]["iters"], args.cpu_budget)
     print(json.dumps(out), flush=True)

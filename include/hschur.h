@@ -191,6 +191,26 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P,
 int32_t hs_matvec(hs_context* ctx, const hs_hmatrix* H, const void* x, void* y, int64_t nrhs);
 int32_t hs_precond_apply(hs_context* ctx, const hs_precond* P, const void* v, void* z, int64_t nrhs);
 
+/* ---- kernel timing (measurement) -------------------------------------------
+ * Between hs_timing_begin and hs_timing_end every launch of the forward and
+ * backward preconditioner sweeps (Eq. 23-24) and of the near and far matvec
+ * kernels (Eq. 11) made through ctx is bracketed by a pair of HIP events on
+ * ctx's stream. hs_timing_end synchronises that stream and fills out with
+ * the launch count and summed event time (ms) per kernel; it resets the
+ * record. Intended for benchmarks: the events add a small gap per launch.
+ * Errors: HS_EINVAL (NULL argument), HS_EHIP. */
+#define HS_KT_SWEEP_FWD 0
+#define HS_KT_SWEEP_BWD 1
+#define HS_KT_NEAR_MV   2
+#define HS_KT_FAR_MV    3
+#define HS_KT_COUNT     4
+typedef struct hs_kernel_times {
+    int64_t launches[HS_KT_COUNT];
+    double  total_ms[HS_KT_COUNT];
+} hs_kernel_times;
+int32_t hs_timing_begin(hs_context* ctx);
+int32_t hs_timing_end(hs_context* ctx, hs_kernel_times* out);
+
 /* ---- test exports (device handles -> host memory) ---------------------------
  * H-matrix:
  *  HS_H_PLAN_*: any HS_X_* code of the plan behind the handle

@@ -62,6 +62,10 @@ class Info(ctypes.Structure):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -97,6 +101,8 @@ def load(path: str = LIB_PATH):
         "hs_precond_apply": (i32, [vp, vp, vp, vp, i64]),
         "hs_hmatrix_export": (i32, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
         "hs_precond_export": (i32, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
+        "hs_timing_begin": (i32, [vp]),
+        "hs_timing_end": (i32, [vp, ctypes.POINTER(KernelTimes)]),
         "hs_status_string": (ctypes.c_char_p, [i32]),
         "hs_last_error": (ctypes.c_char_p, []),
     }
@@ -112,8 +118,10 @@ EXPORTED = (
     "hs_context_create", "hs_context_set_stream", "hs_context_destroy", "hs_plan_create", "hs_plan_query",
     "hs_plan_destroy", "hs_plan_export", "hs_h_build", "hs_query_hmatrix", "hs_hmatrix_destroy", "hs_precond_setup",
     "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_precond_apply", "hs_hmatrix_export",
-    "hs_precond_export", "hs_status_string", "hs_last_error",
+    "hs_precond_export", "hs_timing_begin", "hs_timing_end", "hs_status_string", "hs_last_error",
 )
+
+KT_NAMES = ("sweep_fwd", "sweep_bwd", "near_mv", "far_mv")
 
 
 def _check(status: int, allow_not_converged: bool = False) -> int:
@@ -196,6 +204,16 @@ class Context:
         h = ctypes.c_void_p()
         _check(L.hs_context_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream), a, f, None))
         self._h = h
+
+    def timing_begin(self):
+        """Start bracketing the sweep and matvec launches with HIP events."""
+        _check(_lib.hs_timing_begin(self._h))
+
+    def timing_end(self) -> dict:
+        """Stop timing; {kernel: (launches, total ms)}."""
+        kt = KernelTimes()
+        _check(_lib.hs_timing_end(self._h, ctypes.byref(kt)))
+        return {name: (int(kt.launches[i]), float(kt.total_ms[i])) for i, name in enumerate(KT_NAMES)}
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

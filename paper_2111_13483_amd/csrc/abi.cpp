@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -116,11 +117,63 @@ constexpr int64_t kScratchBudget = int64_t(2) << 30;   // bytes of ACA scratch p
 
 }  // namespace
 
+// Kernel timing for measurement: while enabled, each instrumented launch is
+// bracketed by a pair of events on the context's stream.
+struct KernelTimer {
+    bool on = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> recs;
+    hipEvent_t take() {
+        if (pool.empty()) {
+            hipEvent_t e;
+            hip_check(hipEventCreate(&e), "hipEventCreate");
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    void release() {
+        for (auto& r : recs) {
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        recs.clear();
+    }
+    ~KernelTimer() {
+        release();
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 struct hs_context {
     int device = 0;
     hipStream_t stream = nullptr;
     Mem mem;
+    KernelTimer timer;
 };
+
+namespace {
+
+// Runs f (launches on s), bracketed by timing events when the timer is on.
+template <class F>
+void timed(hs_context* ctx, int kind, hipStream_t s, F&& f) {
+    if (!ctx || !ctx->timer.on) {
+        f();
+        return;
+    }
+    KernelTimer::Rec r{kind, ctx->timer.take(), ctx->timer.take()};
+    hip_check(hipEventRecord(r.a, s), "hipEventRecord");
+    f();
+    hip_check(hipEventRecord(r.b, s), "hipEventRecord");
+    ctx->timer.recs.push_back(r);
+}
+
+}  // namespace
 
 struct hs_plan {
     hs::Tree tree;
@@ -186,12 +239,9 @@ struct hs_precond {
     cd* d_alpha = nullptr;
     int64_t* d_bstart = nullptr;
     int32_t* d_bsize = nullptr;
-    int64_t* d_rowptr = nullptr;
-    hs::SweepEnt* d_rowent = nullptr;
-    int64_t* d_colptr = nullptr;
-    hs::SweepEnt* d_colent = nullptr;
     // chunked sweeps
     int64_t nchunk = 0, linv_elems = 0;
+    int64_t fslot_total = 0, bslot_total = 0;
     hs::SweepPlan sp{};
     hs::SweepItems items{};
 };
@@ -392,10 +442,15 @@ struct MatvecWs {
     cd* slots = nullptr;
 };
 
-void matvec_tree(const hs_hmatrix* H, const cd* x, cd* y, int nrhs, cd* slots, hipStream_t s) {
-    hs::launch_near_mv(H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near, x, H->n, nrhs, slots, s);
-    hs::launch_far_mv(H->d_far_geom, H->d_far_rank, H->d_far_ptr, H->d_far_slot, (int64_t)H->far_geom.size(), x, H->n,
-                      nrhs, slots, s);
+void matvec_tree(hs_context* ctx, const hs_hmatrix* H, const cd* x, cd* y, int nrhs, cd* slots, hipStream_t s) {
+    timed(ctx, HS_KT_NEAR_MV, s, [&] {
+        hs::launch_near_mv(H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near, x, H->n, nrhs,
+                           slots, s);
+    });
+    timed(ctx, HS_KT_FAR_MV, s, [&] {
+        hs::launch_far_mv(H->d_far_geom, H->d_far_rank, H->d_far_ptr, H->d_far_slot, (int64_t)H->far_geom.size(), x,
+                          H->n, nrhs, slots, s);
+    });
     hs::launch_gather(H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, H->n, nrhs, y, s);
 }
 
@@ -404,9 +459,10 @@ struct SweepWs {
     int epoch = 0;
 };
 
-void apply_tree(const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, hipStream_t s) {
+void apply_tree(hs_context* ctx, const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, hipStream_t s) {
     ws.epoch += 1;
-    hs::launch_sweeps(P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s);
+    timed(ctx, HS_KT_SWEEP_FWD, s, [&] { hs::launch_sweep(true, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s); });
+    timed(ctx, HS_KT_SWEEP_BWD, s, [&] { hs::launch_sweep(false, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s); });
 }
 
 SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
@@ -416,9 +472,11 @@ SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
     sw.w.zbuf = o.get<cd>(nn);
     sw.w.rbuf = o.get<cd>(nn);
     sw.w.rbuf2 = o.get<cd>(nn);
-    sw.w.flags = o.get<int>((size_t)4 * P->nchunk);
+    sw.w.slots_f = o.get<cd>((size_t)std::max<int64_t>(P->fslot_total, 1) * nrhs);
+    sw.w.slots_b = o.get<cd>((size_t)std::max<int64_t>(P->bslot_total, 1) * nrhs);
+    sw.w.flags = o.get<int>((size_t)6 * P->nchunk);
     sw.w.tickets = o.get<unsigned long long>(2);
-    hip_check(hipMemsetAsync(sw.w.flags, 0, sizeof(int) * 4 * P->nchunk, s), "memset flags");
+    hip_check(hipMemsetAsync(sw.w.flags, 0, sizeof(int) * 6 * P->nchunk, s), "memset flags");
     hip_check(hipMemsetAsync(sw.w.tickets, 0, sizeof(unsigned long long) * 2, s), "memset tickets");
     return sw;
 }
@@ -482,6 +540,38 @@ int32_t hs_context_set_stream(hs_context* ctx, void* hip_stream) {
 }
 
 void hs_context_destroy(hs_context* ctx) { delete ctx; }
+
+int32_t hs_timing_begin(hs_context* ctx) {
+    try {
+        if (!ctx) fail(HS_EINVAL, "ctx is NULL");
+        set_device(ctx);
+        ctx->timer.release();
+        ctx->timer.on = true;
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+int32_t hs_timing_end(hs_context* ctx, hs_kernel_times* out) {
+    try {
+        if (!ctx || !out) fail(HS_EINVAL, "NULL argument");
+        set_device(ctx);
+        std::memset(out, 0, sizeof(*out));
+        ctx->timer.on = false;
+        hip_check(hipStreamSynchronize(ctx->stream), "stream sync");
+        for (const auto& r : ctx->timer.recs) {
+            float ms = 0.0f;
+            hip_check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+            out->launches[r.kind] += 1;
+            out->total_ms[r.kind] += ms;
+        }
+        ctx->timer.release();
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
 
 // ---- plan -----------------------------------------------------------------------
 
@@ -1003,29 +1093,19 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             cbt += (int64_t)csize[c] * bwidth[c];
         }
         P->linv_elems = lft + lbt + mft + mbt;
-        // entries: in-chunk ones feed Linv, adjacent-chunk ones the coupling products, the rest phase A
-        std::vector<int64_t> colptr(nb + 1, 0), rowptr(nb + 1, 0), intptr(nb + 1, 0);
-        for (int64_t e = 0; e < nnz; ++e) {
-            const int64_t kk = row_of[e], j = sy.cols[e];
-            const int32_t d = chunk_of[j] - chunk_of[kk];
-            if (d == 0) intptr[j + 1]++;
-            else if (d > hs::kFold) {
-                colptr[j + 1]++;
-                rowptr[kk + 1]++;
-            }
-        }
-        for (int64_t j = 0; j < nb; ++j) {
-            colptr[j + 1] += colptr[j];
-            rowptr[j + 1] += rowptr[j];
-            intptr[j + 1] += intptr[j];
-        }
-        std::vector<hs::SweepEnt> colent(colptr[nb]), rowent(rowptr[nb]), intent(intptr[nb]);
+        // entries: in-chunk ones feed Linv, those up to kFold chunks apart the coupling
+        // products, the rest are pushed from their source block into per-entry slots
+        std::vector<int64_t> intptr(nb + 1, 0);
+        for (int64_t e = 0; e < nnz; ++e)
+            if (chunk_of[row_of[e]] == chunk_of[sy.cols[e]]) intptr[sy.cols[e] + 1]++;
+        for (int64_t j = 0; j < nb; ++j) intptr[j + 1] += intptr[j];
+        std::vector<hs::SweepEnt> intent(intptr[nb]);
         std::vector<hs::ExpandTask> expand;
         std::vector<hs::CopyTask> cfc, cbc;
+        std::vector<int64_t> far_e;   // pattern entries more than kFold chunks apart, row-major order
         {
-            std::vector<int64_t> fc(colptr.begin(), colptr.end() - 1), fr(rowptr.begin(), rowptr.end() - 1),
-                fi(intptr.begin(), intptr.end() - 1);
-            for (int64_t kk = 0; kk < nb; ++kk)   // rows ascending: per-column lists sorted by k
+            std::vector<int64_t> fi(intptr.begin(), intptr.end() - 1);
+            for (int64_t kk = 0; kk < nb; ++kk)
                 for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
                     const int64_t j = sy.cols[e];
                     const int32_t ck = chunk_of[kk], cj = chunk_of[j];
@@ -1045,21 +1125,84 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
                         cbc.push_back(hs::CopyTask{cb_off[ck] + (int64_t)loc[kk] * bwidth[ck] + bcol, ad_off[e], bk, bj,
                                                    0, bwidth[ck]});
                     } else {
-                        colent[fc[j]++] = hs::SweepEnt{P->a_off[e], (int32_t)kk, P->a_rank[e]};
-                        rowent[fr[kk]++] = hs::SweepEnt{P->a_off[e], (int32_t)j, P->a_rank[e]};
+                        far_e.push_back(e);
                     }
                 }
+        }
+        // push lists (grouped by source chunk) and per-target gather lists
+        std::vector<hs::PushEnt> fpush, bpush;
+        std::vector<int32_t> fgrp, fgrp_n, bgrp, bgrp_n, fpush_cnt(nch, 0), bpush_cnt(nch, 0);
+        std::vector<int32_t> fsrc_lo(nb, std::numeric_limits<int32_t>::max()), bsrc_hi(nb, -1);
+        std::vector<int64_t> fgptr(nb + 1, 0), bgptr(nb + 1, 0), fgslot, bgslot;
+        std::vector<std::vector<int32_t>> fgrp_of(nch), bgrp_of(nch);   // group ids per source chunk
+        {
+            // forward: source k (rows ascending = sources ascending); backward: source j
+            std::vector<int64_t> fo(far_e), bo(far_e);
+            std::stable_sort(fo.begin(), fo.end(), [&](int64_t x, int64_t y) {
+                return row_of[x] != row_of[y] ? row_of[x] < row_of[y] : sy.cols[x] < sy.cols[y];
+            });
+            std::stable_sort(bo.begin(), bo.end(), [&](int64_t x, int64_t y) {
+                return sy.cols[x] != sy.cols[y] ? sy.cols[x] < sy.cols[y] : row_of[x] < row_of[y];
+            });
+            std::vector<int64_t> fslot(nnz, -1), bslot(nnz, -1);
+            int64_t fs = 0, bs = 0;
+            for (int64_t e : fo) {
+                const int32_t kk = (int32_t)row_of[e], j = (int32_t)sy.cols[e];
+                fslot[e] = fs;
+                fs += P->bsize[j];
+                fpush.push_back(hs::PushEnt{P->a_off[e], fslot[e], kk, j, P->a_rank[e], 0});
+                fpush_cnt[chunk_of[kk]]++;
+                fsrc_lo[j] = std::min(fsrc_lo[j], chunk_of[kk]);
+            }
+            for (int64_t e : bo) {
+                const int32_t kk = (int32_t)row_of[e], j = (int32_t)sy.cols[e];
+                bslot[e] = bs;
+                bs += P->bsize[kk];
+                bpush.push_back(hs::PushEnt{P->a_off[e], bslot[e], j, kk, P->a_rank[e], 0});
+                bpush_cnt[chunk_of[j]]++;
+                bsrc_hi[kk] = std::max(bsrc_hi[kk], chunk_of[j]);
+            }
+            P->fslot_total = fs;
+            P->bslot_total = bs;
+            auto groups = [&](const std::vector<hs::PushEnt>& lst, std::vector<int32_t>& grp, std::vector<int32_t>& grpn,
+                              std::vector<std::vector<int32_t>>& of) {
+                size_t q = 0;
+                while (q < lst.size()) {
+                    const int32_t c = chunk_of[lst[q].src];
+                    size_t r = q;
+                    while (r < lst.size() && r - q < 4 && chunk_of[lst[r].src] == c) ++r;
+                    of[c].push_back((int32_t)grp.size());
+                    grp.push_back((int32_t)q);
+                    grpn.push_back((int32_t)(r - q));
+                    q = r;
+                }
+            };
+            groups(fpush, fgrp, fgrp_n, fgrp_of);
+            groups(bpush, bgrp, bgrp_n, bgrp_of);
+            // gather lists: forward target j sums its slots by ascending source k; backward target k by ascending j
+            for (int64_t e : fo) fgptr[sy.cols[e] + 1]++;
+            for (int64_t e : bo) bgptr[row_of[e] + 1]++;
+            for (int64_t x = 0; x < nb; ++x) {
+                fgptr[x + 1] += fgptr[x];
+                bgptr[x + 1] += bgptr[x];
+            }
+            fgslot.resize(fgptr[nb]);
+            bgslot.resize(bgptr[nb]);
+            std::vector<int64_t> ff(fgptr.begin(), fgptr.end() - 1), bf(bgptr.begin(), bgptr.end() - 1);
+            for (int64_t e : fo) fgslot[ff[sy.cols[e]]++] = fslot[e];   // fo is sorted by source k
+            std::vector<int64_t> bo2(far_e);   // backward targets gather by ascending source j
+            std::stable_sort(bo2.begin(), bo2.end(), [&](int64_t x, int64_t y) {
+                return row_of[x] != row_of[y] ? row_of[x] < row_of[y] : sy.cols[x] < sy.cols[y];
+            });
+            for (int64_t e : bo2) bgslot[bf[row_of[e]]++] = bslot[e];
         }
         P->d_bstart = o.upload(P->bstart, s);
         P->d_bsize = o.upload(P->bsize, s);
         P->d_dinv_off = o.upload(P->d_off, s);
-        P->d_rowptr = o.upload(rowptr, s);
-        P->d_rowent = o.upload(rowent, s);
-        P->d_colptr = o.upload(colptr, s);
-        P->d_colent = o.upload(colent, s);
         hs::SweepPlan& sp = P->sp;
         sp.nb = (int)nb;
         sp.nch = (int)nch;
+        sp.bmax = *std::max_element(P->bsize.begin(), P->bsize.end());
         {
             std::vector<int32_t> cblocks(nch);
             for (int64_t c = 0; c < nch; ++c) cblocks[c] = chunk_first[c + 1] - chunk_first[c];
@@ -1092,10 +1235,20 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         sp.lb = d_lb;
         sp.mf = d_mf;
         sp.mb = d_mb;
-        sp.colptr = P->d_colptr;
-        sp.colent = P->d_colent;
-        sp.rowptr = P->d_rowptr;
-        sp.rowent = P->d_rowent;
+        sp.fpush = o.upload(fpush, s);
+        sp.fgrp = o.upload(fgrp, s);
+        sp.fgrp_n = o.upload(fgrp_n, s);
+        sp.fpush_cnt = o.upload(fpush_cnt, s);
+        sp.fgptr = o.upload(fgptr, s);
+        sp.fgslot = o.upload(fgslot, s);
+        sp.fsrc_lo = o.upload(fsrc_lo, s);
+        sp.bpush = o.upload(bpush, s);
+        sp.bgrp = o.upload(bgrp, s);
+        sp.bgrp_n = o.upload(bgrp_n, s);
+        sp.bpush_cnt = o.upload(bpush_cnt, s);
+        sp.bgptr = o.upload(bgptr, s);
+        sp.bgslot = o.upload(bgslot, s);
+        sp.bsrc_hi = o.upload(bsrc_hi, s);
         sp.alpha = P->d_alpha;
         sp.dinv = P->d_dinv;
         sp.dinv_off = P->d_dinv_off;
@@ -1144,14 +1297,23 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             for (int64_t t = 0; t < nch + hs::kFold; ++t) {
                 if (t < nch)
                     for (int32_t kk = chunk_first[t]; kk < chunk_first[t + 1]; ++kk) fwd.push_back(kk);
-                if (t - hs::kFold >= 0) rows_of(t - hs::kFold, fwd);
+                if (t - hs::kFold >= 0) {
+                    const int64_t cb = t - hs::kFold;
+                    rows_of(cb, fwd);
+                    for (int32_t g : fgrp_of[cb]) fwd.push_back((int32_t)nb + g);
+                }
             }
             for (int64_t t = 0; t < nch + hs::kFold; ++t) {
                 const int64_t c = nch - 1 - t;
                 if (c >= 0)
                     for (int32_t kk = chunk_first[c + 1] - 1; kk >= chunk_first[c]; --kk) bwd.push_back(kk);
-                if (t - hs::kFold >= 0) rows_of(c + hs::kFold, bwd);
+                if (t - hs::kFold >= 0) {
+                    const int64_t cb = c + hs::kFold;
+                    rows_of(cb, bwd);
+                    for (int32_t g : bgrp_of[cb]) bwd.push_back((int32_t)nb + g);
+                }
             }
+            if (fwd.size() != bwd.size()) fail(HS_EINVAL, "internal: sweep item lists differ in length");
             P->items.nitems = (int64_t)fwd.size();
             P->items.fwd = o.upload(fwd, s);
             P->items.bwd = o.upload(bwd, s);
@@ -1226,7 +1388,7 @@ int32_t hs_matvec(hs_context* ctx, const hs_hmatrix* H, const void* x, void* y, 
         cd* yt = w.get<cd>(n * nrhs);
         cd* slots = w.get<cd>(H->slot_total * nrhs);
         hs::launch_permute(static_cast<const cd*>(x), xt, H->d_perm, n, nrhs, true, s);
-        matvec_tree(H, xt, yt, (int)nrhs, slots, s);
+        matvec_tree(ctx, H, xt, yt, (int)nrhs, slots, s);
         hs::launch_permute(yt, static_cast<cd*>(y), H->d_perm, n, nrhs, false, s);
         hip_check(hipGetLastError(), "matvec launches");
         hip_check(hipStreamSynchronize(s), "stream sync");
@@ -1249,7 +1411,7 @@ int32_t hs_precond_apply(hs_context* ctx, const hs_precond* P, const void* v, vo
         cd* zt = w.get<cd>(n * nrhs);
         SweepWs sw = make_sweep_ws(w, P, (int)nrhs, s);
         hs::launch_permute(static_cast<const cd*>(v), vt, P->H->d_perm, n, nrhs, true, s);
-        apply_tree(P, vt, zt, (int)nrhs, sw, s);
+        apply_tree(ctx, P, vt, zt, (int)nrhs, sw, s);
         hs::launch_permute(zt, static_cast<cd*>(z), P->H->d_perm, n, nrhs, false, s);
         hip_check(hipGetLastError(), "apply launches");
         hip_check(hipStreamSynchronize(s), "stream sync");
@@ -1313,14 +1475,14 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         hs::launch_col_norms(bt, n, ns, npart, nchunk, s);
         hs::launch_cycle_start(bt, V, n, g, m, npart, nchunk, st, n, ns, true, s);
         auto precond = [&](const cd* in, cd* outv) {
-            if (P) apply_tree(P, in, outv, ns, sw, s);
+            if (P) apply_tree(ctx, P, in, outv, ns, sw, s);
             else hip_check(hipMemcpyAsync(outv, in, sizeof(cd) * n * ns, hipMemcpyDeviceToDevice, s), "D2D");
         };
         const int poll = 4;
         for (;;) {
             for (int j = 0; j < m; ++j) {
                 precond(V + j * vstride, tmp);
-                matvec_tree(H, tmp, wv, ns, slots, s);
+                matvec_tree(ctx, H, tmp, wv, ns, slots, s);
                 hs::launch_dots(V, n, vstride, j + 1, wv, n, ns, st, partial, nchunk, s);
                 hs::launch_basis_update(V, n, vstride, j + 1, partial, nchunk, wv, n, ns, st, Hh, ldh, m + 1, j, false,
                                         nullptr, s);
@@ -1341,7 +1503,7 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
             hs::launch_combine(V, n, vstride, y, m, tmp, n, ns, st, s);
             precond(tmp, wv);
             hs::launch_axpy_x(xt, wv, n, ns, st, s);
-            matvec_tree(H, xt, tmp, ns, slots, s);
+            matvec_tree(ctx, H, xt, tmp, ns, slots, s);
             hs::launch_residual(bt, tmp, r, n, ns, npart, nchunk, s);
             hs::launch_cycle_end(npart, nchunk, st, ns, s);
             hip_check(hipGetLastError(), "cycle launches");

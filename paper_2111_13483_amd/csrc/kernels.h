@@ -47,6 +47,13 @@ struct GemmTask {
     int32_t pad;
 };
 
+// One far entry of a sweep: alpha block at aoff (dense if rank < 0, else
+// U V), source and target blocks, slot base (times nrhs) of its result.
+struct PushEnt {
+    int64_t aoff, slot;
+    int32_t src, dst, rank, pad;
+};
+
 // Low-rank or dense operator block of the sweeps / matvec.
 struct SweepEnt {
     int64_t off;          // element offset into the alpha store
@@ -105,6 +112,7 @@ void launch_gather(const int64_t* leaf_off, const int64_t* gptr, const GatherEnt
 struct SweepPlan {
     int nb;
     int nch;
+    int bmax;                  // largest block
     int64_t n;
     const int64_t* bstart;     // tree-order start of block k
     const int32_t* bsize;
@@ -129,19 +137,34 @@ struct SweepPlan {
     const int32_t* chunk_of;   // chunk of each block
     const int32_t* csize;      // points of each chunk
     const int32_t* cblocks;    // blocks of each chunk
-    const int64_t* colptr;     // forward: entries (k, j) with chunk(j) - chunk(k) > kFold, per column j, k ascending
-    const SweepEnt* colent;
-    const int64_t* rowptr;     // backward: the same entries per row k, j ascending
-    const SweepEnt* rowent;
+    // far entries (k, j), chunk(j) - chunk(k) > kFold: pushed from their source
+    // block once its chunk is final, into one slot per entry, then gathered by
+    // the target block. Forward: source k -> target j; backward: source j ->
+    // target k. Pushes are grouped by source chunk, up to four per group.
+    const PushEnt* fpush;
+    const int32_t* fgrp;       // per push group: first entry; entries of a group share a source chunk
+    const int32_t* fgrp_n;
+    const int32_t* fpush_cnt;  // pushes per source chunk
+    const int64_t* fgptr;      // per target block: its slots (ascending source block)
+    const int64_t* fgslot;
+    const int32_t* fsrc_lo;    // per target block: first source chunk (> last: none)
+    const PushEnt* bpush;
+    const int32_t* bgrp;
+    const int32_t* bgrp_n;
+    const int32_t* bpush_cnt;
+    const int64_t* bgptr;
+    const int64_t* bgslot;
+    const int32_t* bsrc_hi;    // per target block: last source chunk (< first: none)
     const cd* alpha;
     const cd* dinv;
     const int64_t* dinv_off;
 };
-// Work items in ticket order: item >= 0 is a block row (phase A), item < 0
-// a group of four point rows starting at elimination-order row -item - 1
+// Work items in ticket order: 0 <= item < nb is a block row (phase A: gather
+// of its far-entry slots), item >= nb the push group item - nb, item < 0 a
+// group of four point rows starting at elimination-order row -item - 1
 // (phase B, one row per wavefront). Phase A items of chunk c + kFold come
-// before the phase B rows of chunk c. row_blk maps an elimination-order row
-// to its block.
+// before the phase B rows of chunk c, whose pushes follow them. row_blk maps
+// an elimination-order row to its block.
 struct SweepItems {
     int64_t nitems;
     const int32_t* fwd;
@@ -149,21 +172,26 @@ struct SweepItems {
     const int32_t* row_blk;
 };
 // Work buffers of one apply stream: ybuf, zbuf, rbuf, rbuf2 (elimination
-// order) n nrhs each; flags (4 nchunk ints: per-chunk counts of finished
-// phase A blocks and phase B rows, forward then backward; zeroed once and
+// order) n nrhs each; slots_f / slots_b (push results, nrhs times the slot
+// totals); flags (6 nchunk ints: per-chunk counts of finished phase A
+// blocks, phase B rows and pushes, forward then backward; zeroed once and
 // compared with epoch multiples); tickets (2, zeroed once).
 struct SweepWork {
     cd* ybuf;
     cd* zbuf;
     cd* rbuf;
     cd* rbuf2;
+    cd* slots_f;
+    cd* slots_b;
     int* flags;
     unsigned long long* tickets;
 };
 constexpr int kMaxChunk = 384;   // points per chunk (bounds the row widths)
 constexpr int kFold = 3;         // neighbouring chunks folded into the dense products
-void launch_sweeps(const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs, const SweepWork& w,
-                   int epoch, hipStream_t s);
+// One sweep (forward: v -> y in the work buffers; backward: D^-1 y -> z);
+// the backward launch must follow the forward one of the same epoch.
+void launch_sweep(bool forward, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs,
+                  const SweepWork& w, int epoch, hipStream_t s);
 int sweep_grid(int64_t nitems);
 // Linv rows of every chunk from the dense in-chunk alpha blocks (intptr /
 // intent: per column j the in-chunk entries (k, j), offsets into A).

@@ -18,13 +18,16 @@
 // row-block product per chunk. The operator is unchanged; only the evaluation order of the
 // triangular solves differs.
 //
-// Each sweep is one launch over a list of work items in dependency order:
-// per chunk, its block rows (phase A, one workgroup each) then its point
-// rows in groups of four (phase B, one wavefront per row). A workgroup
-// takes items by ticket, so every item it waits for belongs to a workgroup
-// that is already running. Ready state is a flag per block for phase A and
-// a per-block count of finished rows for phase B; a wave checks up to 64 of
-// them at once and spins only on one that is not ready yet.
+// The terms from chunks further away are pushed: as soon as a chunk is
+// final, one wavefront per far entry (k, j) computes alpha_kj^T y_k (forward)
+// or alpha_kj z_j (backward) into a slot of its own; phase A of the target
+// block then only sums its slots in a fixed order (deterministic).
+//
+// Each sweep is one launch over a list of work items in dependency order; a
+// workgroup takes items by ticket, so every item it waits for belongs to a
+// workgroup that is already running. Readiness is tracked by per-chunk
+// counters (finished phase A blocks, phase B rows and pushes) compared with
+// multiples of the apply's epoch, polled by one wave per workgroup.
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -34,7 +37,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NW = NT / kWave;
-constexpr int RB = 8;    // block rows (or rank terms) whose loads are issued together
+constexpr int RB = 16;   // block rows (or rank terms) whose loads are issued together
 
 __device__ __forceinline__ int relaxed_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -55,6 +58,29 @@ __device__ __forceinline__ void st_sc(cd* p, cd v) {
     __hip_atomic_store(d + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Stage two exchanged segments (n1 and n2 values per right-hand side, column
+// stride n in memory) into LDS with every load issued before the first LDS
+// write.
+template <int S, int NTH>
+__device__ __forceinline__ void stage_pair(cd* xs1, const cd* g1, int n1, cd* xs2, const cd* g2, int n2, int64_t n,
+                                           int cs) {
+    constexpr int PER = (kMaxChunk * (1 + kFold) * S + NTH - 1) / NTH;
+    const int t1 = n1 * cs, t2 = n2 * cs;
+    cd v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * NTH;
+        if (e < t1) v[u] = ld_sc(g1 + e % n1 + (int64_t)(e / n1) * n);
+        else if (e < t1 + t2) v[u] = ld_sc(g2 + (e - t1) % n2 + (int64_t)((e - t1) / n2) * n);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * NTH;
+        if (e < t1) xs1[e] = v[u];
+        else if (e < t1 + t2) xs2[e - t1] = v[u];
+    }
+}
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
 __device__ __forceinline__ cd shfl_cd(cd v, int src) {
@@ -68,157 +94,13 @@ __device__ __forceinline__ int take_ticket(unsigned long long* ctr, unsigned lon
     return *s_t;
 }
 
-// Publish: this wave's exchanged stores have completed before the flag.
-__device__ __forceinline__ void publish(int* flag, int epoch) {
-    stores_done();
-    if ((threadIdx.x % kWave) == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Walk this wave's entries (positions w, w + NW, ... of [0, cnt) in the
-// list `ent` starting at `e0` with step `dir`), waiting until every row of
-// the chunk holding each entry's block has been published (per-chunk row
-// counter equal to epoch * chunk size), and call body(entry) in list order.
-template <class Body>
-__device__ __forceinline__ void for_ready_entries(const SweepEnt* __restrict__ ents, int64_t e0, int dir, int cnt,
-                                                  const int* cnts, const int32_t* chunk_of, const int32_t* csize,
-                                                  int epoch, Body body) {
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    const int mine = cnt > wid ? (cnt - wid + NW - 1) / NW : 0;
-    for (int qb = 0; qb < mine; qb += kWave) {
-        const int nv = min(kWave, mine - qb);
-        SweepEnt my{};
-        int need = 0, mc = 0;
-        if (lane < nv) {
-            my = ents[e0 + (int64_t)dir * (wid + NW * (qb + lane))];
-            mc = chunk_of[my.k];
-            need = epoch * csize[mc];
-        }
-        int done = 0;
-        while (done < nv) {
-            const bool pending = lane >= done && lane < nv;
-            const bool ok = !pending || relaxed_load(cnts + mc) == need;
-            const unsigned long long m = __ballot(ok);
-            const unsigned long long notready = ~m & (nv == kWave ? ~0ull : ((1ull << nv) - 1ull));
-            const int upto = notready ? __builtin_ctzll(notready) : nv;
-            if (upto <= done) {
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            compiler_fence();
-            for (int p = done; p < upto; ++p) {
-                SweepEnt e;
-                e.off = __shfl(my.off, p, kWave);
-                e.k = __shfl(my.k, p, kWave);
-                e.rank = __shfl(my.rank, p, kWave);
-                body(e);
-            }
-            done = upto;
-        }
-    }
-}
-
-// Wave-level wait (no fence): counter cnts[c] == need (c < 0 skipped).
+// Wave-level wait (no fence): counter cnts[c] == need.
 __device__ __forceinline__ void wait_count(const int* cnts, int c, int need) {
-    if (c < 0) return;
     while (relaxed_load(cnts + c) != need) __builtin_amdgcn_s_sleep(1);
 }
 
 constexpr int QC = kMaxChunk / kWave;   // 64-wide column groups of a chunk
 constexpr int QF = kFold * QC;          // column groups of the folded neighbours
-
-// Phase A accumulation over one list of entries (forward: alpha^T y_k into
-// columns b of the row block; backward: alpha z_j into rows a).
-template <int S, bool FWD>
-__device__ __forceinline__ void phase_a(const SweepPlan& p, const SweepEnt* ents, int64_t e0, int dir, int cnt,
-                                        const int* cnts, int epoch, const cd* src, int c0, int cs, int bme,
-                                        cd (&acc)[2][S]) {
-    const int lane = threadIdx.x % kWave;
-    const int64_t n = p.n;
-    for_ready_entries(ents, e0, dir, cnt, cnts, p.chunk_of, p.csize, epoch, [&](const SweepEnt& e) {
-        const int o = e.k, bo = p.bsize[o];
-        const int64_t so = p.pos[o];
-        cd x[2][S];
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int c = 0; c < S; ++c) {
-                const int a = lane + q * kWave;
-                x[q][c] = (a < bo && c < cs) ? ld_sc(src + so + a + (int64_t)(c0 + c) * n) : cmk(0.0, 0.0);
-            }
-        // the stored block is alpha_{row, col}: forward (row = o, col = me), backward (row = me, col = o)
-        const int rows = FWD ? bo : bme, cols = FWD ? bme : bo;
-        const cd* A = p.alpha + e.off;
-        if (e.rank < 0) {
-            for (int a0 = 0; a0 < rows; a0 += RB) {
-                cd Ar[RB][2];
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const int b = lane + q * kWave;
-                        Ar[r][q] = (a0 + r < rows && b < cols) ? A[(int64_t)(a0 + r) * cols + b] : cmk(0.0, 0.0);
-                    }
-#pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    const int a = a0 + r;
-                    if (a < rows)
-#pragma unroll
-                    for (int c = 0; c < S; ++c) {
-                        if (FWD) {
-                            const cd xa = shfl_cd(a < kWave ? x[0][c] : x[1][c], a % kWave);
-#pragma unroll
-                            for (int q = 0; q < 2; ++q) acc[q][c] = cfma(Ar[r][q], xa, acc[q][c]);
-                        } else {
-                            cd sr = cmul(Ar[r][0], x[0][c]);
-                            sr = cfma(Ar[r][1], x[1][c], sr);
-                            sr = wave_sum(sr);
-                            if (lane == a % kWave) {
-                                if (a < kWave) acc[0][c] = cadd(acc[0][c], sr);
-                                else acc[1][c] = cadd(acc[1][c], sr);
-                            }
-                        }
-                    }
-                }
-            }
-        } else {
-            const int rk = e.rank;
-            const cd* Uf = A;
-            const cd* Vf = A + (int64_t)rows * rk;
-            for (int l0 = 0; l0 < rk; l0 += RB) {
-                cd Ur[RB][2], Vr[RB][2];
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const int xx = lane + q * kWave;
-                        const bool on = l0 + r < rk;
-                        Ur[r][q] = (on && xx < rows) ? Uf[(int64_t)(l0 + r) * rows + xx] : cmk(0.0, 0.0);
-                        Vr[r][q] = (on && xx < cols) ? Vf[(int64_t)(l0 + r) * cols + xx] : cmk(0.0, 0.0);
-                    }
-#pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    if (l0 + r < rk)
-#pragma unroll
-                    for (int c = 0; c < S; ++c) {
-                        if (FWD) {   // out += V^T (U^T x)
-                            cd t = cmul(Ur[r][0], x[0][c]);
-                            t = cfma(Ur[r][1], x[1][c], t);
-                            t = wave_sum(t);
-#pragma unroll
-                            for (int q = 0; q < 2; ++q) acc[q][c] = cfma(Vr[r][q], t, acc[q][c]);
-                        } else {     // out += U (V x)
-                            cd t = cmul(Vr[r][0], x[0][c]);
-                            t = cfma(Vr[r][1], x[1][c], t);
-                            t = wave_sum(t);
-#pragma unroll
-                            for (int q = 0; q < 2; ++q) acc[q][c] = cfma(Ur[r][q], t, acc[q][c]);
-                        }
-                    }
-                }
-            }
-        }
-    });
-}
 
 // One row of [A1 | A2] x [x1; x2] by one wave: A1 row of width w1 (<=
 // kMaxChunk) times xs1[o1 + col], A2 row of width w2 (<= kFold kMaxChunk)
@@ -257,63 +139,185 @@ __device__ __forceinline__ void dense_row(const cd* A1, int w1, const cd* xs1, i
     }
 }
 
+// Push of one far entry by one wave. Forward (FWD): out[b] = sum_a A[a][b]
+// x[a] with A = alpha_kj (bo x bt, source rows); backward: out[a] = sum_b
+// A[a][b] x[b] with A = alpha_kj (bt x bo, target rows). x is the source
+// block's segment (elimination order, column stride n); out goes to the
+// entry's slot (column stride bt).
+template <int S, bool FWD, int Q>
+__device__ __forceinline__ void push_one(const PushEnt& e, const cd* alpha, const cd* src, int64_t so, int bo, int bt,
+                                         int64_t n, int c0, int cs, cd* slot) {
+    const int lane = threadIdx.x % kWave;
+    cd x[Q][S], acc[Q][S];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            const int a = lane + q * kWave;
+            x[q][c] = (a < bo && c < cs) ? ld_sc(src + so + a + (int64_t)(c0 + c) * n) : cmk(0.0, 0.0);
+            acc[q][c] = cmk(0.0, 0.0);
+        }
+    const int rows = FWD ? bo : bt, cols = FWD ? bt : bo;
+    const cd* A = alpha + e.aoff;
+    if (e.rank < 0) {
+        for (int a0 = 0; a0 < rows; a0 += RB) {
+            cd Ar[RB][Q];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int b = lane + q * kWave;
+                    Ar[r][q] = (a0 + r < rows && b < cols) ? A[(int64_t)(a0 + r) * cols + b] : cmk(0.0, 0.0);
+                }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int a = a0 + r;
+                if (a < rows)
+#pragma unroll
+                for (int c = 0; c < S; ++c) {
+                    if (FWD) {
+                        const cd xa = shfl_cd(a < kWave ? x[0][c] : x[Q - 1][c], a % kWave);
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) acc[q][c] = cfma(Ar[r][q], xa, acc[q][c]);
+                    } else {
+                        cd sr = cmul(Ar[r][0], x[0][c]);
+                        if (Q > 1) sr = cfma(Ar[r][Q - 1], x[Q - 1][c], sr);
+                        sr = wave_sum(sr);
+                        if (lane == a % kWave) {
+                            if (a < kWave) acc[0][c] = cadd(acc[0][c], sr);
+                            else acc[Q - 1][c] = cadd(acc[Q - 1][c], sr);
+                        }
+                    }
+                }
+            }
+        }
+    } else {
+        const int rk = e.rank;
+        const cd* Uf = A;
+        const cd* Vf = A + (int64_t)rows * rk;
+        for (int l0 = 0; l0 < rk; l0 += RB) {
+            cd Ur[RB][Q], Vr[RB][Q];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int xx = lane + q * kWave;
+                    const bool on = l0 + r < rk;
+                    Ur[r][q] = (on && xx < rows) ? Uf[(int64_t)(l0 + r) * rows + xx] : cmk(0.0, 0.0);
+                    Vr[r][q] = (on && xx < cols) ? Vf[(int64_t)(l0 + r) * cols + xx] : cmk(0.0, 0.0);
+                }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                if (l0 + r < rk)
+#pragma unroll
+                for (int c = 0; c < S; ++c) {
+                    if (FWD) {   // V^T (U^T x)
+                        cd t = cmul(Ur[r][0], x[0][c]);
+                        if (Q > 1) t = cfma(Ur[r][Q - 1], x[Q - 1][c], t);
+                        t = wave_sum(t);
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) acc[q][c] = cfma(Vr[r][q], t, acc[q][c]);
+                    } else {     // U (V x)
+                        cd t = cmul(Vr[r][0], x[0][c]);
+                        if (Q > 1) t = cfma(Vr[r][Q - 1], x[Q - 1][c], t);
+                        t = wave_sum(t);
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) acc[q][c] = cfma(Ur[r][q], t, acc[q][c]);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = lane + q * kWave;
+        if (b < bt)
+#pragma unroll
+            for (int c = 0; c < S; ++c)
+                if (c < cs) st_sc(slot + b + (int64_t)c * bt, acc[q][c]);
+    }
+}
+
+// Sum of a target block's slots (fixed order) plus base, one entry per
+// thread-owned (row, column) element; base and out in elimination order.
+template <int S>
+__device__ __forceinline__ void gather_slots(const int64_t* gslot, int64_t g0, int64_t g1, const cd* slots, int nrhs,
+                                             int bt, int c0, int cs, const cd* base_lds, cd* out, int64_t n) {
+    for (int q = threadIdx.x; q < bt * cs; q += NT) {
+        const int a = q % bt, c = q / bt;
+        cd s = base_lds[q];
+        int64_t g = g0;
+        for (; g + 4 <= g1; g += 4) {
+            cd v0 = ld_sc(slots + gslot[g] * nrhs + (int64_t)(c0 + c) * bt + a);
+            cd v1 = ld_sc(slots + gslot[g + 1] * nrhs + (int64_t)(c0 + c) * bt + a);
+            cd v2 = ld_sc(slots + gslot[g + 2] * nrhs + (int64_t)(c0 + c) * bt + a);
+            cd v3 = ld_sc(slots + gslot[g + 3] * nrhs + (int64_t)(c0 + c) * bt + a);
+            s = cadd(cadd(cadd(cadd(s, v0), v1), v2), v3);
+        }
+        for (; g < g1; ++g) s = cadd(s, ld_sc(slots + gslot[g] * nrhs + (int64_t)(c0 + c) * bt + a));
+        st_sc(out + a + (int64_t)(c0 + c) * n, s);
+    }
+}
+
 }  // namespace
 
 // Forward sweep; S right-hand sides per pass.
-template <int S>
+template <int S, int Q>
 __global__ void __launch_bounds__(NT)
 k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, int nrhs, unsigned long long base,
             int epoch) {
     __shared__ int s_t;
-    __shared__ cd part[NW][kMaxLeaf * S];
+    __shared__ cd bsh[kMaxLeaf * S];
     __shared__ cd xs1[kMaxChunk * S];
     __shared__ cd xs2[kFold * kMaxChunk * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
     int* cntA = wk.flags;
     int* cntB = wk.flags + p.nch;
+    int* cntP = wk.flags + 2 * p.nch;
     for (;;) {
         const int t = take_ticket(wk.tickets, base, &s_t);
         if (t >= it.nitems) return;
         const int item = it.fwd[t];
-        if (item >= 0) {
-            // ---- phase A: r_j = v_j + terms from chunks more than kFold back
+        if (item >= 0 && item < p.nb) {
+            // ---- phase A: r_j = v_j + sum of the far-entry slots of block j
             const int j = item;
+            const int c = p.chunk_of[j];
             const int bj = p.bsize[j];
             const int64_t sj = p.bstart[j], pj = p.pos[j];
-            const int64_t e0 = p.colptr[j];
-            const int cnt = (int)(p.colptr[j + 1] - e0);
+            if (wid == 0)
+                for (int cc = p.fsrc_lo[j]; cc <= c - kFold - 1; ++cc)
+                    if (p.fpush_cnt[cc] > 0) wait_count(cntP, cc, epoch * p.fpush_cnt[cc]);
+            __syncthreads();
+            compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
-                cd acc[2][S];
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int c = 0; c < S; ++c) acc[q][c] = cmk(0.0, 0.0);
-                phase_a<S, true>(p, p.colent, e0, 1, cnt, cntB, epoch, wk.ybuf, c0, cs, bj, acc);
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int b = lane + q * kWave;
-                    if (b < bj)
-#pragma unroll
-                        for (int c = 0; c < S; ++c)
-                            if (c < cs) part[wid][b + c * bj] = acc[q][c];
-                }
+                for (int q = tid; q < bj * cs; q += NT) bsh[q] = v[sj + q % bj + (int64_t)(c0 + q / bj) * n];
                 __syncthreads();
-                if (wid == 0) {
-                    for (int q = lane; q < bj * cs; q += kWave) {
-                        cd s = v[sj + q % bj + (int64_t)(c0 + q / bj) * n];
-#pragma unroll
-                        for (int w = 0; w < NW; ++w) s = cadd(s, part[w][q]);
-                        st_sc(wk.rbuf + pj + q % bj + (int64_t)(c0 + q / bj) * n, s);
-                    }
-                    if (c0 + S >= nrhs) {
-                        stores_done();
-                        if (lane == 0)
-                            __hip_atomic_fetch_add(cntA + p.chunk_of[j], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
+                gather_slots<S>(p.fgslot, p.fgptr[j], p.fgptr[j + 1], wk.slots_f, nrhs, bj, c0, cs, bsh, wk.rbuf + pj,
+                                n);
                 __syncthreads();
+            }
+            stores_done();
+            __syncthreads();
+            if (tid == 0) __hip_atomic_fetch_add(cntA + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (item >= p.nb) {
+            // ---- pushes of one source chunk: one far entry per wave
+            const int g = item - p.nb;
+            const int e0 = p.fgrp[g];
+            const PushEnt& f0 = p.fpush[e0];
+            const int csrc = p.chunk_of[f0.src];
+            if (wid == 0) wait_count(cntB, csrc, epoch * p.csize[csrc]);
+            __syncthreads();
+            compiler_fence();
+            if (wid < p.fgrp_n[g]) {
+                const PushEnt e = p.fpush[e0 + wid];
+                const int bo = p.bsize[e.src], bt = p.bsize[e.dst];
+                for (int c0 = 0; c0 < nrhs; c0 += S)
+                    push_one<S, true, Q>(e, p.alpha, wk.ybuf, p.pos[e.src], bo, bt, n, c0, min(S, nrhs - c0),
+                                      wk.slots_f + e.slot * nrhs + (int64_t)c0 * bt);
+                stores_done();
+                if (lane == 0) __hip_atomic_fetch_add(cntP + csrc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         } else {
             // ---- phase B: one point row per wave: y_i = Linv row . r_c + (Linv C) row . y_prev
@@ -339,10 +343,8 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
             const int a = i - (int)p.pos[j];
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
-                for (int q = tid; q < nc * cs; q += NT)
-                    xs1[q] = ld_sc(wk.rbuf + pc + q % nc + (int64_t)(c0 + q / nc) * n);
-                for (int q = tid; q < wprev * cs; q += NT)
-                    xs2[q] = ld_sc(wk.ybuf + pf0 + q % wprev + (int64_t)(c0 + q / wprev) * n);
+                stage_pair<S, NT>(xs1, wk.rbuf + pc + (int64_t)c0 * n, nc, xs2, wk.ybuf + pf0 + (int64_t)c0 * n, wprev, n,
+                                  cs);
                 __syncthreads();
                 if (live) {
                     const int wj = p.w[j];
@@ -365,91 +367,91 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
 }
 
 // Backward sweep; S right-hand sides per pass.
-template <int S>
+template <int S, int Q>
 __global__ void __launch_bounds__(NT)
 k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nrhs, unsigned long long base,
             int epoch) {
     __shared__ int s_t;
-    __shared__ cd part[NW][kMaxLeaf * S];
     __shared__ cd ysh[kMaxLeaf * S];
     __shared__ cd ztsh[kMaxLeaf * S];
     __shared__ cd xs1[kMaxChunk * S];
     __shared__ cd xs2[kFold * kMaxChunk * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
-    int* cntA = wk.flags + 2 * p.nch;
-    int* cntB = wk.flags + 3 * p.nch;
+    int* cntA = wk.flags + 3 * p.nch;
+    int* cntB = wk.flags + 4 * p.nch;
+    int* cntP = wk.flags + 5 * p.nch;
     for (;;) {
         const int t = take_ticket(wk.tickets + 1, base, &s_t);
         if (t >= it.nitems) return;
         const int item = it.bwd[t];
-        if (item >= 0) {
-            // ---- phase A: r'_k = D_k^-1 y_k + terms from chunks more than kFold ahead
+        if (item >= 0 && item < p.nb) {
+            // ---- phase A: r'_k = D_k^-1 y_k + sum of the far-entry slots of block k
             const int k = item;
+            const int c = p.chunk_of[k];
             const int bk = p.bsize[k];
             const int64_t pk = p.pos[k];
-            const int64_t e_last = p.rowptr[k + 1] - 1;
-            const int cnt = (int)(p.rowptr[k + 1] - p.rowptr[k]);
             const cd* Di = p.dinv + p.dinv_off[k];
+            if (wid == 0)
+                for (int cc = c + kFold + 1; cc <= p.bsrc_hi[k]; ++cc)
+                    if (p.bpush_cnt[cc] > 0) wait_count(cntP, cc, epoch * p.bpush_cnt[cc]);
+            __syncthreads();
+            compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
                 for (int q = tid; q < bk * cs; q += NT) ysh[q] = wk.ybuf[pk + q % bk + (int64_t)(c0 + q / bk) * n];
                 __syncthreads();
                 for (int a0 = wid; a0 < bk; a0 += NW * RB) {
-                    cd Dr[RB][2];
+                    cd Dr[RB][Q];
 #pragma unroll
                     for (int r = 0; r < RB; ++r)
 #pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            const int a = a0 + NW * r, b = lane + q * kWave;
-                            Dr[r][q] = (a < bk && b < bk) ? Di[(int64_t)a * bk + b] : cmk(0.0, 0.0);
+                        for (int q = 0; q < Q; ++q) {
+                            const int aa = a0 + NW * r, b = lane + q * kWave;
+                            Dr[r][q] = (aa < bk && b < bk) ? Di[(int64_t)aa * bk + b] : cmk(0.0, 0.0);
                         }
 #pragma unroll
                     for (int r = 0; r < RB; ++r) {
-                        const int a = a0 + NW * r;
-                        if (a < bk)
+                        const int aa = a0 + NW * r;
+                        if (aa < bk)
 #pragma unroll
-                        for (int c = 0; c < S; ++c) {
+                        for (int cc = 0; cc < S; ++cc) {
                             cd sacc = cmk(0.0, 0.0);
 #pragma unroll
-                            for (int q = 0; q < 2; ++q) {
+                            for (int q = 0; q < Q; ++q) {
                                 const int b = lane + q * kWave;
-                                if (b < bk) sacc = cfma(Dr[r][q], ysh[b + c * bk], sacc);
+                                if (b < bk) sacc = cfma(Dr[r][q], ysh[b + cc * bk], sacc);
                             }
                             sacc = wave_sum(sacc);
-                            if (lane == 0 && c < cs) ztsh[a + c * bk] = sacc;
+                            if (lane == 0 && cc < cs) ztsh[aa + cc * bk] = sacc;
                         }
                     }
                 }
-                cd acc[2][S];
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int c = 0; c < S; ++c) acc[q][c] = cmk(0.0, 0.0);
-                phase_a<S, false>(p, p.rowent, e_last, -1, cnt, cntB, epoch, wk.zbuf, c0, cs, bk, acc);
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int a = lane + q * kWave;
-                    if (a < bk)
-#pragma unroll
-                        for (int c = 0; c < S; ++c)
-                            if (c < cs) part[wid][a + c * bk] = acc[q][c];
-                }
                 __syncthreads();
-                if (wid == 0) {
-                    for (int q = lane; q < bk * cs; q += kWave) {
-                        cd s = ztsh[q];
-#pragma unroll
-                        for (int w = 0; w < NW; ++w) s = cadd(s, part[w][q]);
-                        st_sc(wk.rbuf2 + pk + q % bk + (int64_t)(c0 + q / bk) * n, s);
-                    }
-                    if (c0 + S >= nrhs) {
-                        stores_done();
-                        if (lane == 0)
-                            __hip_atomic_fetch_add(cntA + p.chunk_of[k], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
+                gather_slots<S>(p.bgslot, p.bgptr[k], p.bgptr[k + 1], wk.slots_b, nrhs, bk, c0, cs, ztsh, wk.rbuf2 + pk,
+                                n);
                 __syncthreads();
+            }
+            stores_done();
+            __syncthreads();
+            if (tid == 0) __hip_atomic_fetch_add(cntA + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (item >= p.nb) {
+            // ---- pushes of one source chunk: alpha_kj z_j into the slot of (k, j)
+            const int g = item - p.nb;
+            const int e0 = p.bgrp[g];
+            const PushEnt& b0 = p.bpush[e0];
+            const int csrc = p.chunk_of[b0.src];
+            if (wid == 0) wait_count(cntB, csrc, epoch * p.csize[csrc]);
+            __syncthreads();
+            compiler_fence();
+            if (wid < p.bgrp_n[g]) {
+                const PushEnt e = p.bpush[e0 + wid];
+                const int bo = p.bsize[e.src], bt = p.bsize[e.dst];
+                for (int c0 = 0; c0 < nrhs; c0 += S)
+                    push_one<S, false, Q>(e, p.alpha, wk.zbuf, p.pos[e.src], bo, bt, n, c0, min(S, nrhs - c0),
+                                       wk.slots_b + e.slot * nrhs + (int64_t)c0 * bt);
+                stores_done();
+                if (lane == 0) __hip_atomic_fetch_add(cntP + csrc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         } else {
             // ---- phase B: one point row per wave: z_i = Linv^T row . r'_c + (Linv^T C') row . z_next
@@ -476,10 +478,8 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
             const int64_t sk = p.bstart[k];
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
-                for (int q = tid; q < nc * cs; q += NT)
-                    xs1[q] = ld_sc(wk.rbuf2 + pc + q % nc + (int64_t)(c0 + q / nc) * n);
-                for (int q = tid; q < wnext * cs; q += NT)
-                    xs2[q] = ld_sc(wk.zbuf + pg0 + q % wnext + (int64_t)(c0 + q / wnext) * n);
+                stage_pair<S, NT>(xs1, wk.rbuf2 + pc + (int64_t)c0 * n, nc, xs2, wk.zbuf + pg0 + (int64_t)c0 * n, wnext,
+                                  n, cs);
                 __syncthreads();
                 if (live) {
                     const int wtk = p.wt[k];
@@ -567,17 +567,24 @@ k_lr_expand(const ExpandTask* __restrict__ tasks, const cd* __restrict__ src, cd
 
 int sweep_grid(int64_t nitems) { return (int)(nitems < 1024 ? nitems : 1024); }
 
-void launch_sweeps(const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs, const SweepWork& w,
-                   int epoch, hipStream_t s) {
+void launch_sweep(bool forward, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs,
+                  const SweepWork& w, int epoch, hipStream_t s) {
     const int G = sweep_grid(it.nitems);
     const unsigned long long base = (unsigned long long)(epoch - 1) * (unsigned long long)(it.nitems + G);
+    const bool wide = p.bmax > kWave;
+#define HS_SWEEP(SS, QQ)                                                                                         \
+    do {                                                                                                          \
+        if (forward)                                                                                              \
+            hipLaunchKernelGGL((k_sweep_fwd<SS, QQ>), dim3(G), dim3(NT), 0, s, p, it, v, w, nrhs, base, epoch);   \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_sweep_bwd<SS, QQ>), dim3(G), dim3(NT), 0, s, p, it, z, w, nrhs, base, epoch);   \
+    } while (0)
     if (nrhs == 1) {
-        hipLaunchKernelGGL(k_sweep_fwd<1>, dim3(G), dim3(NT), 0, s, p, it, v, w, nrhs, base, epoch);
-        hipLaunchKernelGGL(k_sweep_bwd<1>, dim3(G), dim3(NT), 0, s, p, it, z, w, nrhs, base, epoch);
+        if (wide) HS_SWEEP(1, 2); else HS_SWEEP(1, 1);
     } else {
-        hipLaunchKernelGGL(k_sweep_fwd<2>, dim3(G), dim3(NT), 0, s, p, it, v, w, nrhs, base, epoch);
-        hipLaunchKernelGGL(k_sweep_bwd<2>, dim3(G), dim3(NT), 0, s, p, it, z, w, nrhs, base, epoch);
+        if (wide) HS_SWEEP(2, 2); else HS_SWEEP(2, 1);
     }
+#undef HS_SWEEP
 }
 
 void launch_linv(const SweepPlan& p, int nchunk, const int32_t* chunk_first, const int64_t* intptr,

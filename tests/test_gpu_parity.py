@@ -289,3 +289,24 @@ def test_ragged_leaves_tiny_and_leaf1(env):
         ry = np.empty_like(v)
         ry[perm] = ohm.matvec(hm, v[perm])
         assert _rel(y, ry) <= TOL
+
+
+@pytest.mark.parametrize("fill_tol", [0.0, 1e-2])
+def test_precond_wide_leaves(env, fill_tol):
+    # leaves of up to 96 points: blocks wider than one wavefront
+    hsl, torch, ctx = env
+    wl = W.make_config("c2", n=2500)
+    wl.leaf_max = 96
+    hm = ohm.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, 1e-4)
+    assert int(np.max(np.diff(hm.tree.leaf_offsets()))) > 64
+    pc = opl.precond_setup(hm, "rcm", fill_tol)
+    H = _gpu_h(env, wl)
+    P = hsl.Precond(ctx, H, "rcm", fill_tol)
+    rng = np.random.default_rng(5)
+    perm = hm.tree.perm
+    for cols in (1, 2):
+        v = rng.normal(size=(wl.n, cols)) + 1j * rng.normal(size=(wl.n, cols))
+        z = P.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
+        ref = np.empty_like(v)
+        ref[perm] = osch.apply(pc, v[perm])
+        assert _rel(z, ref) <= TOL
