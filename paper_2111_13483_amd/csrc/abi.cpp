@@ -1012,15 +1012,16 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
                     cp.push_back(hs::CopyTask{P->a_off[e], ad_off[e], P->bsize[row_of[e]], P->bsize[sy.cols[e]], 0, 0});
             hs::CopyTask* d_cp = tmp.upload(cp, s);
             hs::launch_copy_blocks(d_cp, (int64_t)cp.size(), Ad, P->d_alpha, s);
+            std::vector<hs::PtrCopy> pc;
             for (size_t q = 0; q < fill_e.size(); ++q) {
                 const int64_t e = fill_e[q];
                 if (!keep[q]) continue;
-                const int64_t bytes = (int64_t)P->a_rank[e] * (ft[q].m + ft[q].n) * 16;
-                if (bytes)
-                    hip_check(hipMemcpyAsync(P->d_alpha + P->a_off[e], fills.ptr[q], bytes, hipMemcpyDeviceToDevice, s),
-                              "D2D");
+                const int64_t cnt = (int64_t)P->a_rank[e] * (ft[q].m + ft[q].n);
+                if (cnt) pc.push_back(hs::PtrCopy{fills.ptr[q], P->a_off[e], cnt});
                 ++P->n_lowrank;
             }
+            hs::PtrCopy* d_pc = tmp.upload(pc, s);
+            hs::launch_copy_ptrs(d_pc, (int64_t)pc.size(), P->d_alpha, s);
             hip_check(hipStreamSynchronize(s), "stream sync");
         } else {
             P->a_off = ad_off;

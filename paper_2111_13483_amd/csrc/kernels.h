@@ -80,6 +80,13 @@ void launch_recompress_b(const AcaTask* tasks, int64_t ntasks, const cd* scratch
                          const int64_t* ws_off, const int* rank_new, cd* const* dst, hipStream_t s);
 
 // ---- setup ----
+// Contiguous copies from scattered device sources: dst[dst_off + e] = src[e], e < count.
+struct PtrCopy {
+    const cd* src;
+    int64_t dst_off;
+    int64_t count;
+};
+void launch_copy_ptrs(const PtrCopy* tasks, int64_t ntasks, cd* dst, hipStream_t s);
 void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s);
 void launch_factor_inv(const cd* W, int64_t w_off, int b, cd* dinv, int64_t dinv_off, int* err, hipStream_t s);
 void launch_gemm(const GemmTask* tasks, int64_t ntasks, const cd* A, const cd* B, cd* C, bool transA, bool accumulate,

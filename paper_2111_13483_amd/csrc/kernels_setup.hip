@@ -36,6 +36,12 @@ k_copy_blocks(const CopyTask* __restrict__ tasks, const cd* __restrict__ src, cd
     }
 }
 
+__global__ void __launch_bounds__(NT) k_copy_ptrs(const PtrCopy* __restrict__ tasks, cd* __restrict__ dst) {
+    const PtrCopy t = tasks[blockIdx.x];
+    cd* d = dst + t.dst_off;
+    for (int64_t e = threadIdx.x; e < t.count; e += NT) d[e] = t.src[e];
+}
+
 // In-place Gauss-Jordan inversion with partial pivoting (row pivot: largest
 // |a|^2, ties to the lowest row) of one b x b block held in LDS.
 __global__ void __launch_bounds__(NT)
@@ -171,6 +177,10 @@ k_gemm(const GemmTask* __restrict__ tasks, const cd* __restrict__ Ag, const cd* 
 
 void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s) {
     if (ntasks > 0) hipLaunchKernelGGL(k_copy_blocks, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, src, dst);
+}
+
+void launch_copy_ptrs(const PtrCopy* tasks, int64_t ntasks, cd* dst, hipStream_t s) {
+    if (ntasks > 0) hipLaunchKernelGGL(k_copy_ptrs, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, dst);
 }
 
 void launch_factor_inv(const cd* W, int64_t w_off, int b, cd* dinv, int64_t dinv_off, int* err, hipStream_t s) {

@@ -28,11 +28,17 @@ __global__ void k_permute(const cd* __restrict__ src, cd* __restrict__ dst, cons
 }
 
 // ---------------------------------------------------------------- near matvec
+// One workgroup per stored near block Z_ij (m x nn, row-major): s1 = Z_ij x_j
+// (rows, one wave per row, RU rows' loads issued together) and, off the
+// diagonal, s2 = Z_ij^T x_i (columns, lanes over columns, then the waves'
+// partial sums in a fixed order). S right-hand sides per pass.
+template <int S>
 __global__ void __launch_bounds__(NT)
 k_near_mv(const NearTask* __restrict__ tasks, const int64_t* __restrict__ slot_base, const cd* __restrict__ Z,
           const cd* __restrict__ x, int64_t n, int nrhs, cd* __restrict__ slots) {
-    __shared__ cd xi[kMaxLeaf * SCH], xj[kMaxLeaf * SCH];
-    __shared__ cd colp[NW][kMaxLeaf * SCH];
+    constexpr int RU = 4;
+    __shared__ cd xi[kMaxLeaf * S], xj[kMaxLeaf * S];
+    __shared__ cd colp[NW][kMaxLeaf * S];
     const NearTask t = tasks[blockIdx.x];
     const int m = t.m, nn = t.n;
     const bool diag = t.i0 == t.j0;
@@ -40,40 +46,49 @@ k_near_mv(const NearTask* __restrict__ tasks, const int64_t* __restrict__ slot_b
     cd* s1 = slots + slot_base[blockIdx.x] * nrhs;
     cd* s2 = s1 + (int64_t)m * nrhs;
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
-    for (int c0 = 0; c0 < nrhs; c0 += SCH) {
-        const int cs = min(SCH, nrhs - c0);
+    for (int c0 = 0; c0 < nrhs; c0 += S) {
+        const int cs = min(S, nrhs - c0);
         __syncthreads();
         for (int e = tid; e < m * cs; e += NT) xi[e] = x[t.i0 + e % m + (int64_t)(c0 + e / m) * n];
         for (int e = tid; e < nn * cs; e += NT) xj[e] = x[t.j0 + e % nn + (int64_t)(c0 + e / nn) * n];
         __syncthreads();
-        cd cacc[2][SCH];
+        cd cacc[2][S];
 #pragma unroll
         for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int c = 0; c < SCH; ++c) cacc[q][c] = cmk(0.0, 0.0);
-        for (int a = wid; a < m; a += NW) {
-            cd racc[SCH];
+            for (int c = 0; c < S; ++c) cacc[q][c] = cmk(0.0, 0.0);
+        for (int a0 = wid; a0 < m; a0 += NW * RU) {
+            cd z[RU][2];
 #pragma unroll
-            for (int c = 0; c < SCH; ++c) racc[c] = cmk(0.0, 0.0);
+            for (int u = 0; u < RU; ++u)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int b = lane + q * kWave;
-                if (b < nn) {
-                    const cd z = blk[(int64_t)a * nn + b];
-#pragma unroll
-                    for (int c = 0; c < SCH; ++c) {
-                        if (c < cs) {
-                            racc[c] = cfma(z, xj[b + c * nn], racc[c]);
-                            cacc[q][c] = cfma(z, xi[a + c * m], cacc[q][c]);
-                        }
-                    }
+                for (int q = 0; q < 2; ++q) {
+                    const int a = a0 + u * NW, b = lane + q * kWave;
+                    z[u][q] = (a < m && b < nn) ? blk[(int64_t)a * nn + b] : cmk(0.0, 0.0);
                 }
-            }
 #pragma unroll
-            for (int c = 0; c < SCH; ++c) {
-                if (c < cs) {
-                    cd r = wave_sum(racc[c]);
-                    if (lane == 0) s1[a + (int64_t)(c0 + c) * m] = r;
+            for (int u = 0; u < RU; ++u) {
+                const int a = a0 + u * NW;
+                cd racc[S];
+#pragma unroll
+                for (int c = 0; c < S; ++c) racc[c] = cmk(0.0, 0.0);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int b = lane + q * kWave;
+                    if (b < nn && a < m)
+#pragma unroll
+                        for (int c = 0; c < S; ++c)
+                            if (c < cs) {
+                                racc[c] = cfma(z[u][q], xj[b + c * nn], racc[c]);
+                                cacc[q][c] = cfma(z[u][q], xi[a + c * m], cacc[q][c]);
+                            }
+                }
+#pragma unroll
+                for (int c = 0; c < S; ++c) {
+                    if (c < cs) {
+                        const cd r = wave_sum(racc[c]);
+                        if (lane == 0 && a < m) s1[a + (int64_t)(c0 + c) * m] = r;
+                    }
                 }
             }
         }
@@ -83,97 +98,127 @@ k_near_mv(const NearTask* __restrict__ tasks, const int64_t* __restrict__ slot_b
                 const int b = lane + q * kWave;
                 if (b < nn)
 #pragma unroll
-                    for (int c = 0; c < SCH; ++c)
+                    for (int c = 0; c < S; ++c)
                         if (c < cs) colp[wid][b + c * nn] = cacc[q][c];
             }
             __syncthreads();
             for (int e = tid; e < nn * cs; e += NT) {
-                cd s = colp[0][e];
+                cd sum = colp[0][e];
 #pragma unroll
-                for (int w = 1; w < NW; ++w) s = cadd(s, colp[w][e]);
-                s2[e % nn + (int64_t)(c0 + e / nn) * nn] = s;
+                for (int w = 1; w < NW; ++w) sum = cadd(sum, colp[w][e]);
+                s2[e % nn + (int64_t)(c0 + e / nn) * nn] = sum;
             }
         }
     }
 }
 
 // ---------------------------------------------------------------- far matvec
+// One workgroup per far block (t, s) with U (m x r, column-major) and V
+// (r x nn, row-major): t1 = V x_s and t2 = U^T x_t (the 2r rows of V and of
+// U^T, one wave per row, RU rows' loads issued together), then
+// slot_t = U t1 and slot_s = V^T t2 (one thread per output row, LG rank
+// terms' loads issued together). S right-hand sides per pass.
+template <int S>
 __global__ void __launch_bounds__(NT)
 k_far_mv(const AcaTask* __restrict__ geom, const int* __restrict__ rank, cd* const* __restrict__ uv,
          const int64_t* __restrict__ slot_base, const cd* __restrict__ x, int64_t n, int nrhs, cd* __restrict__ slots) {
-    __shared__ cd t1[kMaxRankCap * SCH], t2[kMaxRankCap * SCH];
+    constexpr int RU = 4, LG = 8;
+    __shared__ cd t12[2 * (kMaxRankCap + LG) * S];
     const AcaTask g = geom[blockIdx.x];
     const int m = g.m, nn = g.n, r = rank[blockIdx.x];
+    if (r == 0) {
+        cd* st = slots + slot_base[blockIdx.x] * nrhs;
+        for (int64_t e = threadIdx.x; e < (int64_t)(m + nn) * nrhs; e += NT) st[e] = cmk(0.0, 0.0);
+        return;
+    }
     const cd* U = uv[blockIdx.x];
     const cd* V = U + (int64_t)m * r;
     cd* st = slots + slot_base[blockIdx.x] * nrhs;
     cd* ss = st + (int64_t)m * nrhs;
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
-    const cd* xt = x + g.t0;
-    const cd* xs = x + g.s0;
-    for (int c0 = 0; c0 < nrhs; c0 += SCH) {
-        const int cs = min(SCH, nrhs - c0);
+    const int rp = r + LG;   // t1 rows [0, r), padding, t2 rows from rp
+    const int len_max = max(m, nn);
+    for (int c0 = 0; c0 < nrhs; c0 += S) {
+        const int cs = min(S, nrhs - c0);
         __syncthreads();
-        for (int l = wid; l < r; l += NW) {
-            cd a1[SCH], a2[SCH];
+        for (int l0 = wid; l0 < 2 * r; l0 += NW * RU) {
+            cd acc[RU][S];
 #pragma unroll
-            for (int c = 0; c < SCH; ++c) { a1[c] = cmk(0.0, 0.0); a2[c] = cmk(0.0, 0.0); }
-            const cd* vl = V + (int64_t)l * nn;
-            const cd* ul = U + (int64_t)l * m;
-            for (int j = lane; j < nn; j += kWave) {
-                const cd v = vl[j];
+            for (int u = 0; u < RU; ++u)
 #pragma unroll
-                for (int c = 0; c < SCH; ++c)
-                    if (c < cs) a1[c] = cfma(v, xs[j + (int64_t)(c0 + c) * n], a1[c]);
+                for (int c = 0; c < S; ++c) acc[u][c] = cmk(0.0, 0.0);
+            for (int j0 = 0; j0 < len_max; j0 += kWave) {
+                const int j = j0 + lane;
+                cd val[RU];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const int l = l0 + u * NW;
+                    const bool isv = l < r;
+                    const int len = isv ? nn : m;
+                    const cd* row = isv ? V + (int64_t)l * nn : U + (int64_t)(l - r) * m;
+                    val[u] = (l < 2 * r && j < len) ? row[j] : cmk(0.0, 0.0);
+                }
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const int l = l0 + u * NW;
+                    const bool isv = l < r;
+                    const int len = isv ? nn : m;
+                    const cd* xseg = x + (isv ? g.s0 : g.t0);
+                    if (l < 2 * r && j < len)
+#pragma unroll
+                        for (int c = 0; c < S; ++c)
+                            if (c < cs) acc[u][c] = cfma(val[u], xseg[j + (int64_t)(c0 + c) * n], acc[u][c]);
+                }
             }
-            for (int i = lane; i < m; i += kWave) {
-                const cd u = ul[i];
 #pragma unroll
-                for (int c = 0; c < SCH; ++c)
-                    if (c < cs) a2[c] = cfma(u, xt[i + (int64_t)(c0 + c) * n], a2[c]);
-            }
+            for (int u = 0; u < RU; ++u) {
+                const int l = l0 + u * NW;
 #pragma unroll
-            for (int c = 0; c < SCH; ++c) {
-                if (c < cs) {
-                    cd s1 = wave_sum(a1[c]), s2v = wave_sum(a2[c]);
-                    if (lane == 0) { t1[l * SCH + c] = s1; t2[l * SCH + c] = s2v; }
+                for (int c = 0; c < S; ++c) {
+                    const cd sum = wave_sum(acc[u][c]);
+                    if (lane == 0 && l < 2 * r) t12[((l < r) ? l : rp + (l - r)) * S + c] = sum;
                 }
             }
         }
-        __syncthreads();
-        for (int i = tid; i < m; i += NT) {
-            cd acc[SCH];
-#pragma unroll
-            for (int c = 0; c < SCH; ++c) acc[c] = cmk(0.0, 0.0);
-            for (int l = 0; l < r; ++l) {
-                const cd u = U[(int64_t)l * m + i];
-#pragma unroll
-                for (int c = 0; c < SCH; ++c) acc[c] = cfma(u, t1[l * SCH + c], acc[c]);
-            }
-#pragma unroll
-            for (int c = 0; c < SCH; ++c)
-                if (c < cs) st[i + (int64_t)(c0 + c) * m] = acc[c];
+        // zero padding so the grouped loads below read finite values
+        if (tid < LG * S) {
+            t12[r * S + tid] = cmk(0.0, 0.0);
+            t12[(rp + r) * S + tid] = cmk(0.0, 0.0);
         }
-        for (int j = tid; j < nn; j += NT) {
-            cd acc[SCH];
+        __syncthreads();
+        for (int e = tid; e < m + nn; e += NT) {
+            const bool top = e < m;
+            const int idx = top ? e : e - m;
+            const int ld = top ? m : nn;
+            const cd* base = (top ? U : V) + idx;
+            const cd* tv = t12 + (top ? 0 : rp) * S;
+            cd acc[S];
 #pragma unroll
-            for (int c = 0; c < SCH; ++c) acc[c] = cmk(0.0, 0.0);
-            for (int l = 0; l < r; ++l) {
-                const cd v = V[(int64_t)l * nn + j];
+            for (int c = 0; c < S; ++c) acc[c] = cmk(0.0, 0.0);
+            for (int l0 = 0; l0 < r; l0 += LG) {
+                cd bv[LG];
 #pragma unroll
-                for (int c = 0; c < SCH; ++c) acc[c] = cfma(v, t2[l * SCH + c], acc[c]);
+                for (int u = 0; u < LG; ++u) bv[u] = (l0 + u < r) ? base[(int64_t)(l0 + u) * ld] : cmk(0.0, 0.0);
+#pragma unroll
+                for (int u = 0; u < LG; ++u)
+#pragma unroll
+                    for (int c = 0; c < S; ++c) acc[c] = cfma(bv[u], tv[(l0 + u) * S + c], acc[c]);
             }
+            cd* out = top ? st : ss;
 #pragma unroll
-            for (int c = 0; c < SCH; ++c)
-                if (c < cs) ss[j + (int64_t)(c0 + c) * nn] = acc[c];
+            for (int c = 0; c < S; ++c)
+                if (c < cs) out[idx + (int64_t)(c0 + c) * ld] = acc[c];
         }
     }
 }
 
 // ---------------------------------------------------------------- gather
+// y on leaf L = sum of the slots that cover it, in the fixed order of the
+// leaf's gather list (GR entries' loads issued together).
 __global__ void __launch_bounds__(kWave)
 k_gather(const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ gptr, const GatherEnt* __restrict__ gent,
          const cd* __restrict__ slots, int64_t n, int nrhs, cd* __restrict__ y) {
+    constexpr int GR = 8;
     const int64_t L = blockIdx.x;
     const int64_t i0 = leaf_off[L];
     const int b = (int)(leaf_off[L + 1] - i0);
@@ -181,9 +226,20 @@ k_gather(const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ gptr,
     for (int e = threadIdx.x; e < b * nrhs; e += kWave) {
         const int a = e % b, c = e / b;
         cd acc = cmk(0.0, 0.0);
-        for (int64_t q = e0; q < e1; ++q) {
-            const GatherEnt g = gent[q];
-            acc = cadd(acc, slots[g.base * nrhs + g.off + a + (int64_t)c * g.len]);
+        for (int64_t q = e0; q < e1; q += GR) {
+            cd v[GR];
+#pragma unroll
+            for (int u = 0; u < GR; ++u) {
+                if (q + u < e1) {
+                    const GatherEnt g = gent[q + u];
+                    v[u] = slots[g.base * nrhs + g.off + a + (int64_t)c * g.len];
+                } else {
+                    v[u] = cmk(0.0, 0.0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < GR; ++u)
+                if (q + u < e1) acc = cadd(acc, v[u]);
         }
         y[i0 + a + (int64_t)c * n] = acc;
     }
@@ -191,7 +247,7 @@ k_gather(const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ gptr,
 
 // ---------------------------------------------------------------- GMRES pieces
 int gmres_nchunk(int64_t n) {
-    int64_t c = (n + 4095) / 4096;
+    int64_t c = (n + NT - 1) / NT;
     if (c < 1) c = 1;
     if (c > 128) c = 128;
     return (int)c;
@@ -203,24 +259,52 @@ __device__ __forceinline__ void chunk_range(int64_t n, int nchunk, int ch, int64
     i0 = ch * len;
     i1 = min(n, i0 + len);
 }
+
+// Sum of the chunks' partials of column c, by the whole workgroup in a fixed order.
+__device__ __forceinline__ double sum_chunks(const double* __restrict__ p, int nchunk, int nrhs, int c, double* red) {
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nchunk; q += NT) s += p[(int64_t)q * nrhs + c];
+    return wg_sum<NT>(s, red);
+}
 }  // namespace
 
-// partial[(ch * nrhs + c) * nvec + l] = sum_{i in chunk} conj(V_l[i, c]) w[i, c]
+// partial[(ch * nrhs + c) * nvec + l] = sum_{i in chunk} conj(V_l[i, c]) w[i, c].
+// Rows over threads; the vectors' loads are issued in groups of DG.
 __global__ void __launch_bounds__(NT)
 k_dots(const cd* __restrict__ V, int64_t ldv, int64_t vstride, int nvec, const cd* __restrict__ w, int64_t n,
        int nrhs, const ColState* __restrict__ st, cd* __restrict__ partial, int nchunk) {
+    constexpr int DG = 8;
+    __shared__ cd red[NW][kMaxRankCap + 1];
     const int ch = blockIdx.x, c = blockIdx.y;
     if (!st[c].active) return;
     int64_t i0, i1;
     chunk_range(n, nchunk, ch, i0, i1);
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    const cd* wc = w + c * n;
-    for (int l = wid; l < nvec; l += NW) {
-        const cd* vl = V + l * vstride + c * ldv;
-        cd s = cmk(0.0, 0.0);
-        for (int64_t i = i0 + lane; i < i1; i += kWave) s = cfmac(vl[i], wc[i], s);
-        s = wave_sum(s);
-        if (lane == 0) partial[((int64_t)ch * nrhs + c) * nvec + l] = s;
+    cd acc[DG];
+    for (int l0 = 0; l0 < nvec; l0 += DG) {
+#pragma unroll
+        for (int u = 0; u < DG; ++u) acc[u] = cmk(0.0, 0.0);
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += NT) {
+            const cd wi = w[c * n + i];
+            const cd* vb = V + c * ldv + i;
+            cd vv[DG];
+#pragma unroll
+            for (int u = 0; u < DG; ++u) vv[u] = (l0 + u < nvec) ? vb[(int64_t)(l0 + u) * vstride] : cmk(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < DG; ++u) acc[u] = cfmac(vv[u], wi, acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < DG; ++u) {
+            const cd sum = wave_sum(acc[u]);
+            if (lane == 0 && l0 + u < nvec) red[wid][l0 + u] = sum;
+        }
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < nvec; l += NT) {
+        cd sum = red[0][l];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) sum = cadd(sum, red[q][l]);
+        partial[((int64_t)ch * nrhs + c) * nvec + l] = sum;
     }
 }
 
@@ -231,19 +315,33 @@ __global__ void __launch_bounds__(NT)
 k_basis_update(const cd* __restrict__ V, int64_t ldv, int64_t vstride, int nvec, const cd* __restrict__ partial,
                int nchunk, cd* __restrict__ w, int64_t n, int nrhs, const ColState* __restrict__ st, cd* __restrict__ H,
                int64_t ldh, int mp1, int hcol, int accumulate_h, double* __restrict__ norm_partial) {
-    __shared__ cd h[kMaxRankCap + 1];
+    constexpr int DG = 8;
+    __shared__ cd h[kMaxRankCap + DG];
+    __shared__ cd hp[NW][kWave];
     __shared__ double red[NW];
     const int ch = blockIdx.x, c = blockIdx.y;
     if (!st[c].active) return;
-    for (int l = threadIdx.x; l < nvec; l += NT) {
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    for (int l0 = 0; l0 < nvec; l0 += kWave) {
+        const int l = l0 + lane;
         cd s = cmk(0.0, 0.0);
-        for (int q = 0; q < nchunk; ++q) s = cadd(s, partial[((int64_t)q * nrhs + c) * nvec + l]);
-        h[l] = s;
-        if (ch == 0) {
-            cd* hp = H + c * ldh + l + (int64_t)hcol * mp1;
-            *hp = accumulate_h ? cadd(*hp, s) : s;
+        if (l < nvec)
+            for (int q = wid; q < nchunk; q += NW) s = cadd(s, partial[((int64_t)q * nrhs + c) * nvec + l]);
+        hp[wid][lane] = s;
+        __syncthreads();
+        if (threadIdx.x < kWave && l < nvec) {
+            cd t = hp[0][lane];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) t = cadd(t, hp[q][lane]);
+            h[l] = t;
+            if (ch == 0) {
+                cd* hq = H + c * ldh + l + (int64_t)hcol * mp1;
+                *hq = accumulate_h ? cadd(*hq, t) : t;
+            }
         }
+        __syncthreads();
     }
+    if (threadIdx.x < DG) h[nvec + threadIdx.x] = cmk(0.0, 0.0);
     __syncthreads();
     int64_t i0, i1;
     chunk_range(n, nchunk, ch, i0, i1);
@@ -251,7 +349,14 @@ k_basis_update(const cd* __restrict__ V, int64_t ldv, int64_t vstride, int nvec,
     double ss = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += NT) {
         cd v = wc[i];
-        for (int l = 0; l < nvec; ++l) v = csub(v, cmul(V[l * vstride + c * ldv + i], h[l]));
+        const cd* vb = V + c * ldv + i;
+        for (int l0 = 0; l0 < nvec; l0 += DG) {
+            cd vv[DG];
+#pragma unroll
+            for (int u = 0; u < DG; ++u) vv[u] = (l0 + u < nvec) ? vb[(int64_t)(l0 + u) * vstride] : cmk(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < DG; ++u) v = csub(v, cmul(vv[u], h[l0 + u]));
+        }
         wc[i] = v;
         ss += cabs2(v);
     }
@@ -263,17 +368,18 @@ k_basis_update(const cd* __restrict__ V, int64_t ldv, int64_t vstride, int nvec,
 
 // One Arnoldi step's Hessenberg column j: h_{j+1,j} = ||w||, previous
 // rotations, a new complex Givens rotation (real cosine), the residual
-// estimate g and the column's stopping test. One thread per column.
-__global__ void k_givens(cd* __restrict__ H, int64_t ldh, int m, int j, double* __restrict__ csv, cd* __restrict__ snv,
-                         cd* __restrict__ g, const double* __restrict__ norm_partial, int nchunk,
-                         ColState* __restrict__ st, int nrhs, double* __restrict__ inv_hn) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nrhs) return;
+// estimate g and the column's stopping test. One workgroup per column.
+__global__ void __launch_bounds__(NT)
+k_givens(cd* __restrict__ H, int64_t ldh, int m, int j, double* __restrict__ csv, cd* __restrict__ snv,
+         cd* __restrict__ g, const double* __restrict__ norm_partial, int nchunk, ColState* __restrict__ st, int nrhs,
+         double* __restrict__ inv_hn) {
+    __shared__ double red[NW];
+    const int c = blockIdx.x;
+    if (!st[c].active) return;
+    const double nn = sum_chunks(norm_partial, nchunk, nrhs, c, red);
+    if (threadIdx.x != 0) return;
     ColState s = st[c];
-    if (!s.active) return;
     const int mp1 = m + 1;
-    double nn = 0.0;
-    for (int q = 0; q < nchunk; ++q) nn += norm_partial[(int64_t)q * nrhs + c];
     const double hn = sqrt(nn);
     cd* Hc = H + c * ldh + (int64_t)j * mp1;
     double* cs = csv + (int64_t)c * m;
@@ -330,10 +436,9 @@ __global__ void __launch_bounds__(NT)
 k_cycle_start(const cd* __restrict__ r, cd* __restrict__ V, int64_t ldv, cd* __restrict__ g, int m,
               const double* __restrict__ norm_partial, int nchunk, ColState* __restrict__ st, int64_t n, int nrhs,
               int first) {
+    __shared__ double red[NW];
     const int ch = blockIdx.x, c = blockIdx.y;
-    double nn = 0.0;
-    for (int q = 0; q < nchunk; ++q) nn += norm_partial[(int64_t)q * nrhs + c];
-    const double beta = sqrt(nn);
+    const double beta = sqrt(sum_chunks(norm_partial, nchunk, nrhs, c, red));
     ColState s = st[c];
     if (first) {
         s.bnorm = beta;
@@ -426,14 +531,15 @@ k_col_norms(const cd* __restrict__ v, int64_t n, int nrhs, double* __restrict__ 
 }
 
 // End of a cycle: true relative residual and the column's final stop test.
-__global__ void k_cycle_end(const double* __restrict__ norm_partial, int nchunk, ColState* __restrict__ st, int nrhs) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nrhs) return;
+// One workgroup per column.
+__global__ void __launch_bounds__(NT)
+k_cycle_end(const double* __restrict__ norm_partial, int nchunk, ColState* __restrict__ st, int nrhs) {
+    __shared__ double red[NW];
+    const int c = blockIdx.x;
+    if (st[c].done) return;
+    const double beta = sqrt(sum_chunks(norm_partial, nchunk, nrhs, c, red));
+    if (threadIdx.x != 0) return;
     ColState s = st[c];
-    if (s.done) return;
-    double nn = 0.0;
-    for (int q = 0; q < nchunk; ++q) nn += norm_partial[(int64_t)q * nrhs + c];
-    const double beta = sqrt(nn);
     s.relres = beta / s.bnorm;
     if (!isfinite(s.relres)) s.done = 1;
     if (!s.fixed && s.relres <= s.tol) s.done = 1;
@@ -458,14 +564,23 @@ void launch_permute(const cd* src, cd* dst, const int64_t* perm, int64_t n, int6
 
 void launch_near_mv(const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cd* Z, const cd* x, int64_t n,
                     int nrhs, cd* slots, hipStream_t s) {
-    if (ntasks > 0)
-        hipLaunchKernelGGL(k_near_mv, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, slot_base, Z, x, n, nrhs, slots);
+    if (ntasks == 0) return;
+    if (nrhs == 1)
+        hipLaunchKernelGGL(k_near_mv<1>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, slot_base, Z, x, n, nrhs, slots);
+    else
+        hipLaunchKernelGGL(k_near_mv<SCH>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, slot_base, Z, x, n, nrhs,
+                           slots);
 }
 
 void launch_far_mv(const AcaTask* geom, const int* rank, cd* const* uv, const int64_t* slot_base, int64_t ntasks,
                    const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
-    if (ntasks > 0)
-        hipLaunchKernelGGL(k_far_mv, dim3((unsigned)ntasks), dim3(NT), 0, s, geom, rank, uv, slot_base, x, n, nrhs, slots);
+    if (ntasks == 0) return;
+    if (nrhs == 1)
+        hipLaunchKernelGGL(k_far_mv<1>, dim3((unsigned)ntasks), dim3(NT), 0, s, geom, rank, uv, slot_base, x, n, nrhs,
+                           slots);
+    else
+        hipLaunchKernelGGL(k_far_mv<SCH>, dim3((unsigned)ntasks), dim3(NT), 0, s, geom, rank, uv, slot_base, x, n, nrhs,
+                           slots);
 }
 
 void launch_gather(const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb, const cd* slots,
@@ -487,8 +602,8 @@ void launch_basis_update(const cd* V, int64_t ldv, int64_t vstride, int nvec, co
 
 void launch_givens(cd* H, int64_t ldh, int m, int j, double* cs, cd* sn, cd* g, const double* norm_partial, int nchunk,
                    ColState* st, int nrhs, double* inv_hn, hipStream_t s) {
-    hipLaunchKernelGGL(k_givens, dim3((nrhs + 63) / 64), dim3(64), 0, s, H, ldh, m, j, cs, sn, g, norm_partial, nchunk,
-                       st, nrhs, inv_hn);
+    hipLaunchKernelGGL(k_givens, dim3(nrhs), dim3(NT), 0, s, H, ldh, m, j, cs, sn, g, norm_partial, nchunk, st, nrhs,
+                       inv_hn);
 }
 
 void launch_scale_next(const cd* w, cd* vnext, int64_t ldv, int64_t n, int nrhs, const ColState* st,
@@ -525,7 +640,7 @@ void launch_col_norms(const cd* v, int64_t n, int nrhs, double* norm_partial, in
 }
 
 void launch_cycle_end(const double* norm_partial, int nchunk, ColState* st, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_cycle_end, dim3((nrhs + 63) / 64), dim3(64), 0, s, norm_partial, nchunk, st, nrhs);
+    hipLaunchKernelGGL(k_cycle_end, dim3(nrhs), dim3(NT), 0, s, norm_partial, nchunk, st, nrhs);
 }
 
 }  // namespace hs

@@ -59,28 +59,37 @@ __device__ __forceinline__ void st_sc(cd* p, cd v) {
 }
 __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Stage two exchanged segments (n1 and n2 values per right-hand side, column
-// stride n in memory) into LDS with every load issued before the first LDS
-// write.
-template <int S, int NTH>
-__device__ __forceinline__ void stage_pair(cd* xs1, const cd* g1, int n1, cd* xs2, const cd* g2, int n2, int64_t n,
-                                           int cs) {
-    constexpr int PER = (kMaxChunk * (1 + kFold) * S + NTH - 1) / NTH;
+// Stage up to two segments into LDS with every load issued before the first
+// LDS write: segment s copies len_s values per right-hand side from g_s
+// (column stride n) to x_s (column stride ld_s).
+template <int S, int MAXTOT>
+__device__ __forceinline__ void stage_segs(cd* x1, int ld1, const cd* g1, int n1, cd* x2, int ld2, const cd* g2, int n2,
+                                           int64_t n, int cs) {
+    constexpr int PER = (MAXTOT * S + NT - 1) / NT;
     const int t1 = n1 * cs, t2 = n2 * cs;
     cd v[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int e = threadIdx.x + u * NTH;
-        if (e < t1) v[u] = ld_sc(g1 + e % n1 + (int64_t)(e / n1) * n);
-        else if (e < t1 + t2) v[u] = ld_sc(g2 + (e - t1) % n2 + (int64_t)((e - t1) / n2) * n);
+        const int e = threadIdx.x + u * NT;
+        if (e < t1) {
+            v[u] = ld_sc(g1 + e % n1 + (int64_t)(e / n1) * n);
+        } else if (e < t1 + t2) {
+            const int f = e - t1;
+            v[u] = ld_sc(g2 + f % n2 + (int64_t)(f / n2) * n);
+        }
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int e = threadIdx.x + u * NTH;
-        if (e < t1) xs1[e] = v[u];
-        else if (e < t1 + t2) xs2[e - t1] = v[u];
+        const int e = threadIdx.x + u * NT;
+        if (e < t1) {
+            x1[e % n1 + (e / n1) * ld1] = v[u];
+        } else if (e < t1 + t2) {
+            const int f = e - t1;
+            x2[f % n2 + (f / n2) * ld2] = v[u];
+        }
     }
 }
+
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
 __device__ __forceinline__ cd shfl_cd(cd v, int src) {
@@ -99,17 +108,26 @@ __device__ __forceinline__ void wait_count(const int* cnts, int c, int need) {
     while (relaxed_load(cnts + c) != need) __builtin_amdgcn_s_sleep(1);
 }
 
+// Two counters polled together (b may be null): *a == na and *b == nb.
+__device__ __forceinline__ void wait_pair(const int* a, int na, const int* b, int nb) {
+    for (;;) {
+        const int va = relaxed_load(a);
+        const int vb = b ? relaxed_load(b) : nb;
+        if (va == na && vb == nb) return;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 constexpr int QC = kMaxChunk / kWave;   // 64-wide column groups of a chunk
 constexpr int QF = kFold * QC;          // column groups of the folded neighbours
 
-// One row of [A1 | A2] x [x1; x2] by one wave: A1 row of width w1 (<=
-// kMaxChunk) times xs1[o1 + col], A2 row of width w2 (<= kFold kMaxChunk)
-// times xs2[col]; xs1 / xs2 are LDS copies (column c at stride ld1 / ld2).
-template <int S>
-__device__ __forceinline__ void dense_row(const cd* A1, int w1, const cd* xs1, int o1, int ld1, const cd* A2, int w2,
-                                          const cd* xs2, int ld2, int cs, cd (&out)[S]) {
+// One row of [A1 | A2] x [x1; x2] by one wave, in two parts so that the
+// row's loads (independent of the chain) are issued before the wait for its
+// inputs: load_row reads A1 (width w1 <= kMaxChunk) and A2 (width w2 <=
+// kFold kMaxChunk) into registers; apply_row multiplies them with the LDS
+// copies xs1[o1 + col] and xs2[col] (column c at stride ld1 / ld2).
+__device__ __forceinline__ void load_row(const cd* A1, int w1, const cd* A2, int w2, cd (&R1)[QC], cd (&R2)[QF]) {
     const int lane = threadIdx.x % kWave;
-    cd R1[QC], R2[QF];
 #pragma unroll
     for (int q = 0; q < QC; ++q) {
         const int col = lane + q * kWave;
@@ -120,6 +138,12 @@ __device__ __forceinline__ void dense_row(const cd* A1, int w1, const cd* xs1, i
         const int col = lane + q * kWave;
         R2[q] = col < w2 ? A2[col] : cmk(0.0, 0.0);
     }
+}
+
+template <int S>
+__device__ __forceinline__ void apply_row(const cd (&R1)[QC], int w1, const cd* xs1, int o1, int ld1,
+                                          const cd (&R2)[QF], int w2, const cd* xs2, int ld2, int cs, cd (&out)[S]) {
+    const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int c = 0; c < S; ++c) {
         cd sacc = cmk(0.0, 0.0);
@@ -328,29 +352,45 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
             const int f0 = p.fx0[jb], f1 = p.fx1[jb];
             const int nc = p.csize[c];
             const int wprev = f1 >= 0 ? (int)(p.pos[f1] + p.bsize[f1] - p.pos[f0]) : 0;
-            if (wid == 0) {
-                wait_count(cntA, c, epoch * p.cblocks[c]);
-                for (int d = 1; d <= kFold; ++d)
-                    if (c - d >= 0) wait_count(cntB, c - d, epoch * p.csize[c - d]);
-            }
-            __syncthreads();
-            compiler_fence();
             const int64_t pc = p.pos[cf];
             const int64_t pf0 = f1 >= 0 ? p.pos[f0] : 0;
             const int i = r0 + wid;
             const bool live = i < pc + nc;
             const int j = live ? it.row_blk[i] : jb;
             const int a = i - (int)p.pos[j];
+            const int wj = live ? p.w[j] : 0;
+            cd R1[QC], R2[QF];
+            load_row(p.lf + p.lf_off[j] + (int64_t)a * wj, wj, p.mf + p.mf_off[j] + (int64_t)a * wprev,
+                     live ? wprev : 0, R1, R2);
+            // Rows of chunk c need r_c (phase A) and chunks c-kFold..c-1; the
+            // chunks before c-1 are final once c-1 is (its rows waited for
+            // them), so the part of y_prev outside c-1 is staged before the
+            // wait for c-1, and only c-1's own part after it.
+            const int pc1 = cf > 0 ? (int)p.pos[p.cfirst[cf - 1]] : 0;
+            const int n_old = f1 >= 0 ? max(0, min(wprev, pc1 - (int)pf0)) : 0;
+            if (wid == 0)
+                wait_pair(cntA + c, epoch * p.cblocks[c], c >= 2 ? cntB + c - 2 : nullptr,
+                          c >= 2 ? epoch * p.csize[c - 2] : 0);
+            __syncthreads();
+            compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
-                stage_pair<S, NT>(xs1, wk.rbuf + pc + (int64_t)c0 * n, nc, xs2, wk.ybuf + pf0 + (int64_t)c0 * n, wprev, n,
-                                  cs);
+                if (c0 == 0) {
+                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, nc, wk.rbuf + pc, nc, xs2, wprev, wk.ybuf + pf0, n_old,
+                                                           n, cs);
+                    if (wid == 0 && c >= 1) wait_count(cntB, c - 1, epoch * p.csize[c - 1]);
+                    __syncthreads();
+                    compiler_fence();
+                    stage_segs<S, kMaxChunk>(xs2 + n_old, wprev, wk.ybuf + pf0 + n_old, wprev - n_old, nullptr, 0,
+                                             nullptr, 0, n, cs);
+                } else {
+                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, nc, wk.rbuf + pc + (int64_t)c0 * n, nc, xs2, wprev,
+                                                           wk.ybuf + pf0 + (int64_t)c0 * n, wprev, n, cs);
+                }
                 __syncthreads();
                 if (live) {
-                    const int wj = p.w[j];
                     cd y[S];
-                    dense_row<S>(p.lf + p.lf_off[j] + (int64_t)a * wj, wj, xs1, 0, nc,
-                                 p.mf + p.mf_off[j] + (int64_t)a * wprev, wprev, xs2, wprev, cs, y);
+                    apply_row<S>(R1, wj, xs1, 0, nc, R2, wprev, xs2, wprev, cs, y);
                     if (lane == 0)
 #pragma unroll
                         for (int cc = 0; cc < S; ++cc)
@@ -462,13 +502,6 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
             const int g0 = p.bx0[kb], g1 = p.bx1[kb];
             const int nc = p.csize[c];
             const int wnext = g0 >= 0 ? (int)(p.pos[g1] + p.bsize[g1] - p.pos[g0]) : 0;
-            if (wid == 0) {
-                wait_count(cntA, c, epoch * p.cblocks[c]);
-                for (int d = 1; d <= kFold; ++d)
-                    if (c + d < p.nch) wait_count(cntB, c + d, epoch * p.csize[c + d]);
-            }
-            __syncthreads();
-            compiler_fence();
             const int64_t pc = p.pos[cf];
             const int64_t pg0 = g0 >= 0 ? p.pos[g0] : 0;
             const int i = r0 + wid;
@@ -476,16 +509,36 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
             const int k = live ? it.row_blk[i] : kb;
             const int a = i - (int)p.pos[k];
             const int64_t sk = p.bstart[k];
+            const int wtk = live ? p.wt[k] : 0;
+            cd R1[QC], R2[QF];
+            load_row(p.lb + p.lb_off[k] + (int64_t)a * wtk, wtk, p.mb + p.mb_off[k] + (int64_t)a * wnext,
+                     live ? wnext : 0, R1, R2);
+            // Mirror of the forward order: chunk c+1's part of z_next is staged
+            // after the wait for c+1, the rest (final once c+1 is) before it.
+            const int e1 = c + 1 < p.nch ? (int)(pc + nc) + p.csize[c + 1] : 0;
+            const int n_new = g0 >= 0 ? max(0, min(wnext, e1 - (int)pg0)) : 0;
+            if (wid == 0)
+                wait_pair(cntA + c, epoch * p.cblocks[c], c + 2 < p.nch ? cntB + c + 2 : nullptr,
+                          c + 2 < p.nch ? epoch * p.csize[c + 2] : 0);
+            __syncthreads();
+            compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
-                stage_pair<S, NT>(xs1, wk.rbuf2 + pc + (int64_t)c0 * n, nc, xs2, wk.zbuf + pg0 + (int64_t)c0 * n, wnext,
-                                  n, cs);
+                if (c0 == 0) {
+                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, nc, wk.rbuf2 + pc, nc, xs2 + n_new, wnext,
+                                                           wk.zbuf + pg0 + n_new, wnext - n_new, n, cs);
+                    if (wid == 0 && c + 1 < p.nch) wait_count(cntB, c + 1, epoch * p.csize[c + 1]);
+                    __syncthreads();
+                    compiler_fence();
+                    stage_segs<S, kMaxChunk>(xs2, wnext, wk.zbuf + pg0, n_new, nullptr, 0, nullptr, 0, n, cs);
+                } else {
+                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, nc, wk.rbuf2 + pc + (int64_t)c0 * n, nc, xs2, wnext,
+                                                           wk.zbuf + pg0 + (int64_t)c0 * n, wnext, n, cs);
+                }
                 __syncthreads();
                 if (live) {
-                    const int wtk = p.wt[k];
                     cd zz[S];
-                    dense_row<S>(p.lb + p.lb_off[k] + (int64_t)a * wtk, wtk, xs1, p.loc[k], nc,
-                                 p.mb + p.mb_off[k] + (int64_t)a * wnext, wnext, xs2, wnext, cs, zz);
+                    apply_row<S>(R1, wtk, xs1, p.loc[k], nc, R2, wnext, xs2, wnext, cs, zz);
                     if (lane == 0)
 #pragma unroll
                         for (int cc = 0; cc < S; ++cc)
