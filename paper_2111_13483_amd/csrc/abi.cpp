@@ -474,9 +474,10 @@ SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
     sw.w.rbuf2 = o.get<cd>(nn);
     sw.w.slots_f = o.get<cd>((size_t)std::max<int64_t>(P->fslot_total, 1) * nrhs);
     sw.w.slots_b = o.get<cd>((size_t)std::max<int64_t>(P->bslot_total, 1) * nrhs);
-    sw.w.flags = o.get<int>((size_t)6 * P->nchunk);
+    const size_t nflags = (size_t)4 * P->nchunk + (size_t)2 * P->nb;
+    sw.w.flags = o.get<int>(nflags);
     sw.w.tickets = o.get<unsigned long long>(2);
-    hip_check(hipMemsetAsync(sw.w.flags, 0, sizeof(int) * 6 * P->nchunk, s), "memset flags");
+    hip_check(hipMemsetAsync(sw.w.flags, 0, sizeof(int) * nflags, s), "memset flags");
     hip_check(hipMemsetAsync(sw.w.tickets, 0, sizeof(unsigned long long) * 2, s), "memset tickets");
     return sw;
 }
@@ -851,6 +852,10 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
         if (opts->precision != HS_PREC_FP64) fail(HS_EINVAL, "unsupported precision");
         set_device(ctx);
+        // the sweeps keep kRowWorkers workgroups resident for a whole launch
+        // and need others beside them
+        if (hs::sweep_capacity(ctx->device) < hs::kRowWorkers + 32)
+            fail(HS_ENODEVICE, "too few resident workgroups for the preconditioner sweeps");
         hipStream_t s = ctx->stream;
         auto P = std::make_unique<hs_precond>();
         P->own.mem = ctx->mem;
@@ -1132,8 +1137,7 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         }
         // push lists (grouped by source chunk) and per-target gather lists
         std::vector<hs::PushEnt> fpush, bpush;
-        std::vector<int32_t> fgrp, fgrp_n, bgrp, bgrp_n, fpush_cnt(nch, 0), bpush_cnt(nch, 0);
-        std::vector<int32_t> fsrc_lo(nb, std::numeric_limits<int32_t>::max()), bsrc_hi(nb, -1);
+        std::vector<int32_t> fgrp, fgrp_n, bgrp, bgrp_n;
         std::vector<int64_t> fgptr(nb + 1, 0), bgptr(nb + 1, 0), fgslot, bgslot;
         std::vector<std::vector<int32_t>> fgrp_of(nch), bgrp_of(nch);   // group ids per source chunk
         {
@@ -1148,21 +1152,36 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             std::vector<int64_t> fslot(nnz, -1), bslot(nnz, -1);
             int64_t fs = 0, bs = 0;
             for (int64_t e : fo) {
-                const int32_t kk = (int32_t)row_of[e], j = (int32_t)sy.cols[e];
                 fslot[e] = fs;
-                fs += P->bsize[j];
-                fpush.push_back(hs::PushEnt{P->a_off[e], fslot[e], kk, j, P->a_rank[e], 0});
-                fpush_cnt[chunk_of[kk]]++;
-                fsrc_lo[j] = std::min(fsrc_lo[j], chunk_of[kk]);
+                fs += P->bsize[sy.cols[e]];
             }
             for (int64_t e : bo) {
-                const int32_t kk = (int32_t)row_of[e], j = (int32_t)sy.cols[e];
                 bslot[e] = bs;
-                bs += P->bsize[kk];
-                bpush.push_back(hs::PushEnt{P->a_off[e], bslot[e], j, kk, P->a_rank[e], 0});
-                bpush_cnt[chunk_of[j]]++;
-                bsrc_hi[kk] = std::max(bsrc_hi[kk], chunk_of[j]);
+                bs += P->bsize[row_of[e]];
             }
+            // push order: by source chunk, then the target chunk needed soonest
+            // (forward the lowest, backward the highest), then source and target
+            std::vector<int64_t> fpo(far_e), bpo(far_e);
+            std::stable_sort(fpo.begin(), fpo.end(), [&](int64_t x, int64_t y) {
+                const int32_t sx = chunk_of[row_of[x]], sy_ = chunk_of[row_of[y]];
+                if (sx != sy_) return sx < sy_;
+                const int32_t tx = chunk_of[sy.cols[x]], ty = chunk_of[sy.cols[y]];
+                if (tx != ty) return tx < ty;
+                return row_of[x] != row_of[y] ? row_of[x] < row_of[y] : sy.cols[x] < sy.cols[y];
+            });
+            std::stable_sort(bpo.begin(), bpo.end(), [&](int64_t x, int64_t y) {
+                const int32_t sx = chunk_of[sy.cols[x]], sy_ = chunk_of[sy.cols[y]];
+                if (sx != sy_) return sx < sy_;
+                const int32_t tx = chunk_of[row_of[x]], ty = chunk_of[row_of[y]];
+                if (tx != ty) return tx > ty;
+                return sy.cols[x] != sy.cols[y] ? sy.cols[x] < sy.cols[y] : row_of[x] < row_of[y];
+            });
+            for (int64_t e : fpo)
+                fpush.push_back(hs::PushEnt{P->a_off[e], fslot[e], (int32_t)row_of[e], (int32_t)sy.cols[e],
+                                            P->a_rank[e], 0});
+            for (int64_t e : bpo)
+                bpush.push_back(hs::PushEnt{P->a_off[e], bslot[e], (int32_t)sy.cols[e], (int32_t)row_of[e],
+                                            P->a_rank[e], 0});
             P->fslot_total = fs;
             P->bslot_total = bs;
             auto groups = [&](const std::vector<hs::PushEnt>& lst, std::vector<int32_t>& grp, std::vector<int32_t>& grpn,
@@ -1171,7 +1190,7 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
                 while (q < lst.size()) {
                     const int32_t c = chunk_of[lst[q].src];
                     size_t r = q;
-                    while (r < lst.size() && r - q < 4 && chunk_of[lst[r].src] == c) ++r;
+                    while (r < lst.size() && r - q < (size_t)hs::kPushGroup && chunk_of[lst[r].src] == c) ++r;
                     of[c].push_back((int32_t)grp.size());
                     grp.push_back((int32_t)q);
                     grpn.push_back((int32_t)(r - q));
@@ -1239,17 +1258,30 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         sp.fpush = o.upload(fpush, s);
         sp.fgrp = o.upload(fgrp, s);
         sp.fgrp_n = o.upload(fgrp_n, s);
-        sp.fpush_cnt = o.upload(fpush_cnt, s);
         sp.fgptr = o.upload(fgptr, s);
         sp.fgslot = o.upload(fgslot, s);
-        sp.fsrc_lo = o.upload(fsrc_lo, s);
+        {
+            // backward pushes of dense entries read alpha_kj^T (b_j x b_k row-major),
+            // so they run as column sums like the forward ones
+            std::vector<hs::CopyTask> tc;
+            int64_t tt = 0;
+            for (auto& e : bpush)
+                if (e.rank < 0) {
+                    const int32_t bk = P->bsize[e.dst], bj = P->bsize[e.src];
+                    tc.push_back(hs::CopyTask{tt, e.aoff, bj, bk, 1, 0});
+                    e.aoff = tt;
+                    tt += (int64_t)bk * bj;
+                }
+            cd* d_at = o.get<cd>(std::max<int64_t>(tt, 1));
+            hs::CopyTask* d_tc = tmp.upload(tc, s);
+            hs::launch_copy_blocks(d_tc, (int64_t)tc.size(), P->d_alpha, d_at, s);
+            sp.alpha_t = d_at;
+        }
         sp.bpush = o.upload(bpush, s);
         sp.bgrp = o.upload(bgrp, s);
         sp.bgrp_n = o.upload(bgrp_n, s);
-        sp.bpush_cnt = o.upload(bpush_cnt, s);
         sp.bgptr = o.upload(bgptr, s);
         sp.bgslot = o.upload(bgslot, s);
-        sp.bsrc_hi = o.upload(bsrc_hi, s);
         sp.alpha = P->d_alpha;
         sp.dinv = P->d_dinv;
         sp.dinv_off = P->d_dinv_off;
@@ -1284,41 +1316,78 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         hs::launch_gemm(d_gf, (int64_t)gf.size(), d_lf, d_C, d_mf, false, false, 1.0, s);
         hs::launch_gemm(d_gb, (int64_t)gb.size(), d_lb, d_C, d_mb, false, false, 1.0, s);
         hip_check(hipGetLastError(), "linv launches");
-        // work items in dependency order: per chunk its block rows (phase A), then its point rows in
-        // groups of four (phase B); forward ascending, backward descending
+        // Row workers: per chunk its ranges, per point row its matrix slices.
+        // Work items of the other workgroups in dependency order: per chunk its
+        // block rows (phase A) kFold chunks ahead of the pushes from the chunk
+        // whose rows finish then; forward ascending, backward descending.
         {
-            std::vector<int32_t> fwd, bwd, row_blk(H->n);
-            for (int64_t kk = 0; kk < nb; ++kk)
-                for (int32_t a = 0; a < P->bsize[kk]; ++a) row_blk[pos[kk] + a] = (int32_t)kk;
-            // phase A items of chunk c come kFold chunks ahead of the phase B rows of chunk c
-            auto rows_of = [&](int64_t c, std::vector<int32_t>& out) {
-                const int64_t r0 = pos[chunk_first[c]];
-                for (int64_t r = r0; r < r0 + csize[c]; r += 4) out.push_back((int32_t)(-r - 1));
-            };
+            std::vector<hs::SweepChunk> fch(nch), bch(nch);
+            std::vector<hs::RowTask> frow(H->n), brow(H->n);
+            for (int64_t c = 0; c < nch; ++c) {
+                const int32_t pc = (int32_t)pos[chunk_first[c]], nc = csize[c];
+                const int32_t nbk = chunk_first[c + 1] - chunk_first[c];
+                hs::SweepChunk f{};
+                f.pc = pc;
+                f.nc = nc;
+                f.nblocks = nbk;
+                if (c > 0) {
+                    f.x2 = (int32_t)pos[chunk_first[std::max<int64_t>(0, c - hs::kFold)]];
+                    f.w2 = fwidth[c];
+                    const int32_t s1 = (int32_t)pos[chunk_first[c - 1]] - f.x2;   // chunk c-1 within the range
+                    f.e_lo = 0;
+                    f.e_hi = s1;
+                    f.l_lo = s1;
+                    f.l_hi = f.w2;
+                    f.need1 = csize[c - 1];
+                    f.need2 = c >= 2 ? csize[c - 2] : 0;
+                }
+                fch[c] = f;
+                hs::SweepChunk b{};
+                b.pc = pc;
+                b.nc = nc;
+                b.nblocks = nbk;
+                if (c + 1 < nch) {
+                    b.x2 = pc + nc;
+                    b.w2 = bwidth[c];
+                    b.l_lo = 0;
+                    b.l_hi = csize[c + 1];
+                    b.e_lo = b.l_hi;
+                    b.e_hi = b.w2;
+                    b.need1 = csize[c + 1];
+                    b.need2 = c + 2 < nch ? csize[c + 2] : 0;
+                }
+                bch[c] = b;
+                for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk)
+                    for (int32_t r = 0; r < P->bsize[kk]; ++r) {
+                        const int64_t i = pos[kk] + r;
+                        frow[i] = hs::RowTask{lf_off[kk] + (int64_t)r * wdt[kk], mf_off[kk] + (int64_t)r * fwidth[c],
+                                              wdt[kk], 0, (int32_t)(P->bstart[kk] + r), 0};
+                        brow[i] = hs::RowTask{lb_off[kk] + (int64_t)r * wtt[kk], mb_off[kk] + (int64_t)r * bwidth[c],
+                                              wtt[kk], loc[kk], (int32_t)(P->bstart[kk] + r), 0};
+                    }
+            }
+            std::vector<int32_t> fwd, bwd;
             for (int64_t t = 0; t < nch + hs::kFold; ++t) {
                 if (t < nch)
                     for (int32_t kk = chunk_first[t]; kk < chunk_first[t + 1]; ++kk) fwd.push_back(kk);
-                if (t - hs::kFold >= 0) {
-                    const int64_t cb = t - hs::kFold;
-                    rows_of(cb, fwd);
-                    for (int32_t g : fgrp_of[cb]) fwd.push_back((int32_t)nb + g);
-                }
+                if (t - hs::kFold >= 0)
+                    for (int32_t g : fgrp_of[t - hs::kFold]) fwd.push_back((int32_t)nb + g);
             }
             for (int64_t t = 0; t < nch + hs::kFold; ++t) {
                 const int64_t c = nch - 1 - t;
                 if (c >= 0)
                     for (int32_t kk = chunk_first[c + 1] - 1; kk >= chunk_first[c]; --kk) bwd.push_back(kk);
-                if (t - hs::kFold >= 0) {
-                    const int64_t cb = c + hs::kFold;
-                    rows_of(cb, bwd);
-                    for (int32_t g : bgrp_of[cb]) bwd.push_back((int32_t)nb + g);
-                }
+                if (t - hs::kFold >= 0)
+                    for (int32_t g : bgrp_of[c + hs::kFold]) bwd.push_back((int32_t)nb + g);
             }
             if (fwd.size() != bwd.size()) fail(HS_EINVAL, "internal: sweep item lists differ in length");
             P->items.nitems = (int64_t)fwd.size();
             P->items.fwd = o.upload(fwd, s);
             P->items.bwd = o.upload(bwd, s);
-            P->items.row_blk = o.upload(row_blk, s);
+            P->items.fchunk = o.upload(fch, s);
+            P->items.bchunk = o.upload(bch, s);
+            P->items.frow = o.upload(frow, s);
+            P->items.brow = o.upload(brow, s);
         }
         hip_check(hipStreamSynchronize(s), "stream sync");
         tmp.release();

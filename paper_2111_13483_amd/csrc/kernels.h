@@ -146,23 +146,22 @@ struct SweepPlan {
     const int32_t* cblocks;    // blocks of each chunk
     // far entries (k, j), chunk(j) - chunk(k) > kFold: pushed from their source
     // block once its chunk is final, into one slot per entry, then gathered by
-    // the target block. Forward: source k -> target j; backward: source j ->
-    // target k. Pushes are grouped by source chunk, up to four per group.
+    // the target block, which waits for its own count of pushed entries.
+    // Forward: source k -> target j; backward: source j -> target k. Pushes are
+    // grouped by source chunk (up to kPushGroup per group), nearest target
+    // chunk first.
     const PushEnt* fpush;
     const int32_t* fgrp;       // per push group: first entry; entries of a group share a source chunk
     const int32_t* fgrp_n;
-    const int32_t* fpush_cnt;  // pushes per source chunk
     const int64_t* fgptr;      // per target block: its slots (ascending source block)
     const int64_t* fgslot;
-    const int32_t* fsrc_lo;    // per target block: first source chunk (> last: none)
     const PushEnt* bpush;
     const int32_t* bgrp;
     const int32_t* bgrp_n;
-    const int32_t* bpush_cnt;
     const int64_t* bgptr;
     const int64_t* bgslot;
-    const int32_t* bsrc_hi;    // per target block: last source chunk (< first: none)
     const cd* alpha;
+    const cd* alpha_t;         // transposed copies of the dense backward push entries
     const cd* dinv;
     const int64_t* dinv_off;
 };
@@ -172,17 +171,45 @@ struct SweepPlan {
 // (phase B, one row per wavefront). Phase A items of chunk c + kFold come
 // before the phase B rows of chunk c, whose pushes follow them. row_blk maps
 // an elimination-order row to its block.
+// Per chunk, for the row workers of one sweep direction.
+struct SweepChunk {
+    int32_t pc, nc;          // first elimination-order position and points of the chunk
+    int32_t x2, w2;          // first position and width of the folded neighbour range
+    int32_t e_lo, e_hi;      // part of that range final once chunk c -/+ 2 is
+    int32_t l_lo, l_hi;      // part of that range in chunk c -/+ 1
+    int32_t nblocks;         // blocks of the chunk (phase A count)
+    int32_t need1, need2;    // points of chunks c -/+ 1 and c -/+ 2 (0 if absent)
+    int32_t pad;
+};
+// Per point row (indexed by elimination-order position): its slices of the
+// chunk inverse (a1, width w1, first column o1 in the chunk) and of the
+// folded coupling product (a2, width w2 of its chunk), and its tree-order
+// position zpos (output of the backward sweep).
+struct RowTask {
+    int64_t a1, a2;
+    int32_t w1, o1;
+    int32_t zpos, pad;
+};
+// Row slots per chunk handled by the persistent row workers: one point row
+// per wave, kMaxChunk / 4 workgroups of four waves.
+constexpr int kRowWorkers = 96;
+// Far entries of one source chunk per push item (four waves take turns).
+constexpr int kPushGroup = 16;
 struct SweepItems {
-    int64_t nitems;
+    int64_t nitems;          // phase A and push items per direction
     const int32_t* fwd;
     const int32_t* bwd;
-    const int32_t* row_blk;
+    const SweepChunk* fchunk;
+    const SweepChunk* bchunk;
+    const RowTask* frow;
+    const RowTask* brow;
 };
 // Work buffers of one apply stream: ybuf, zbuf, rbuf, rbuf2 (elimination
 // order) n nrhs each; slots_f / slots_b (push results, nrhs times the slot
-// totals); flags (6 nchunk ints: per-chunk counts of finished phase A
-// blocks, phase B rows and pushes, forward then backward; zeroed once and
-// compared with epoch multiples); tickets (2, zeroed once).
+// totals); flags (4 nchunk + 2 nb ints: per chunk the finished phase A
+// blocks and phase B rows, per target block its pushed entries, forward then
+// backward; zeroed once and compared with epoch multiples); tickets (2,
+// zeroed once).
 struct SweepWork {
     cd* ybuf;
     cd* zbuf;
@@ -195,11 +222,15 @@ struct SweepWork {
 };
 constexpr int kMaxChunk = 384;   // points per chunk (bounds the row widths)
 constexpr int kFold = 3;         // neighbouring chunks folded into the dense products
+static_assert(kRowWorkers * 4 == kMaxChunk, "one point row per wave of the row workers");
 // One sweep (forward: v -> y in the work buffers; backward: D^-1 y -> z);
 // the backward launch must follow the forward one of the same epoch.
 void launch_sweep(bool forward, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs,
                   const SweepWork& w, int epoch, hipStream_t s);
 int sweep_grid(int64_t nitems);
+// Workgroups of the sweep kernels that can be resident at once on a device;
+// the row workers spin for the whole launch, so this must exceed kRowWorkers.
+int sweep_capacity(int device);
 // Linv rows of every chunk from the dense in-chunk alpha blocks (intptr /
 // intent: per column j the in-chunk entries (k, j), offsets into A).
 void launch_linv(const SweepPlan& p, int nchunk, const int32_t* chunk_first, const int64_t* intptr,

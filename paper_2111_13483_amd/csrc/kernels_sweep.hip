@@ -19,15 +19,21 @@
 // triangular solves differs.
 //
 // The terms from chunks further away are pushed: as soon as a chunk is
-// final, one wavefront per far entry (k, j) computes alpha_kj^T y_k (forward)
+// final, a wavefront per far entry (k, j) computes alpha_kj^T y_k (forward)
 // or alpha_kj z_j (backward) into a slot of its own; phase A of the target
 // block then only sums its slots in a fixed order (deterministic).
 //
-// Each sweep is one launch over a list of work items in dependency order; a
-// workgroup takes items by ticket, so every item it waits for belongs to a
-// workgroup that is already running. Readiness is tracked by per-chunk
-// counters (finished phase A blocks, phase B rows and pushes) compared with
-// multiples of the apply's epoch, polled by one wave per workgroup.
+// Each sweep is one launch. The first kRowWorkers workgroups to start are
+// row workers: each owns four point-row slots and walks the chunks in chain
+// order, loading its rows' matrix slices before waiting for their inputs.
+// The other workgroups take the phase A and push items by ticket from a list
+// in dependency order, so every item they wait for belongs to a workgroup
+// that is already running. Readiness is tracked by counters (per chunk: its
+// finished phase A blocks and phase B rows; per target block: its pushed
+// entries) compared with multiples of the apply's epoch, polled by one wave
+// per workgroup. The row workers stay resident for the whole launch, so the
+// device must hold more workgroups than that at once (checked at setup), and
+// sweeps of different streams must not run at the same time.
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -163,9 +169,10 @@ __device__ __forceinline__ void apply_row(const cd (&R1)[QC], int w1, const cd* 
     }
 }
 
-// Push of one far entry by one wave. Forward (FWD): out[b] = sum_a A[a][b]
-// x[a] with A = alpha_kj (bo x bt, source rows); backward: out[a] = sum_b
-// A[a][b] x[b] with A = alpha_kj (bt x bo, target rows). x is the source
+// Push of one far entry by one wave. FWD: out[b] = sum_a A[a][b] x[a] with A
+// bo x bt (source rows): alpha_kj forward, the transposed copy of a dense
+// alpha_kj backward; otherwise out[a] = sum_b A[a][b] x[b] with A = alpha_kj
+// (bt x bo, target rows; used for low-rank backward entries). x is the source
 // block's segment (elimination order, column stride n); out goes to the
 // entry's slot (column stride bt).
 template <int S, bool FWD, int Q>
@@ -298,20 +305,69 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
     const int64_t n = p.n;
     int* cntA = wk.flags;
     int* cntB = wk.flags + p.nch;
-    int* cntP = wk.flags + 2 * p.nch;
-    for (;;) {
-        const int t = take_ticket(wk.tickets, base, &s_t);
+    int* cntT = wk.flags + 2 * p.nch;
+    const int role = take_ticket(wk.tickets, base, &s_t);
+    if (role < kRowWorkers) {
+        // ---- phase B, persistent: slot role * NW + wid of every chunk in order,
+        // y_i = Linv row . r_c + (Linv C) row . y_prev
+        const int slot = role * NW + wid;
+        for (int c = 0; c < p.nch; ++c) {
+            const SweepChunk d = it.fchunk[c];
+            const bool live = slot < d.nc;
+            const int i = d.pc + (live ? slot : 0);
+            const RowTask rt = it.frow[i];
+            const int w1 = live ? rt.w1 : 0;
+            cd R1[QC], R2[QF];
+            load_row(p.lf + rt.a1, w1, p.mf + rt.a2, live ? d.w2 : 0, R1, R2);
+            if (wid == 0)
+                wait_pair(cntA + c, epoch * d.nblocks, c >= 2 ? cntB + c - 2 : nullptr, epoch * d.need2);
+            __syncthreads();
+            compiler_fence();
+            for (int c0 = 0; c0 < nrhs; c0 += S) {
+                const int cs = min(S, nrhs - c0);
+                if (c0 == 0) {
+                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, d.nc, wk.rbuf + d.pc, d.nc, xs2 + d.e_lo, d.w2,
+                                                           wk.ybuf + d.x2 + d.e_lo, d.e_hi - d.e_lo, n, cs);
+                    if (wid == 0 && c >= 1) wait_count(cntB, c - 1, epoch * d.need1);
+                    __syncthreads();
+                    compiler_fence();
+                    stage_segs<S, kMaxChunk>(xs2 + d.l_lo, d.w2, wk.ybuf + d.x2 + d.l_lo, d.l_hi - d.l_lo, nullptr, 0,
+                                             nullptr, 0, n, cs);
+                } else {
+                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2,
+                                                           d.w2, wk.ybuf + d.x2 + (int64_t)c0 * n, d.w2, n, cs);
+                }
+                __syncthreads();
+                if (live) {
+                    cd y[S];
+                    apply_row<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.w2, xs2, d.w2, cs, y);
+                    if (lane == 0)
+#pragma unroll
+                        for (int cc = 0; cc < S; ++cc)
+                            if (cc < cs) st_sc(wk.ybuf + i + (int64_t)(c0 + cc) * n, y[cc]);
+                }
+                __syncthreads();
+            }
+            // one count per workgroup: its live rows, once all of them are stored
+            if (live) stores_done();
+            __syncthreads();
+            const int nlive = min(max(d.nc - role * NW, 0), NW);
+            if (tid == 0 && nlive > 0)
+                __hip_atomic_fetch_add(cntB + c, nlive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    for (int t = role - kRowWorkers;; t = take_ticket(wk.tickets, base, &s_t) - kRowWorkers) {
         if (t >= it.nitems) return;
         const int item = it.fwd[t];
-        if (item >= 0 && item < p.nb) {
+        if (item < p.nb) {
             // ---- phase A: r_j = v_j + sum of the far-entry slots of block j
             const int j = item;
             const int c = p.chunk_of[j];
             const int bj = p.bsize[j];
             const int64_t sj = p.bstart[j], pj = p.pos[j];
-            if (wid == 0)
-                for (int cc = p.fsrc_lo[j]; cc <= c - kFold - 1; ++cc)
-                    if (p.fpush_cnt[cc] > 0) wait_count(cntP, cc, epoch * p.fpush_cnt[cc]);
+            const int nin = (int)(p.fgptr[j + 1] - p.fgptr[j]);
+            if (wid == 0 && nin > 0) wait_count(cntT, j, epoch * nin);
             __syncthreads();
             compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
@@ -325,8 +381,8 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
             stores_done();
             __syncthreads();
             if (tid == 0) __hip_atomic_fetch_add(cntA + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else if (item >= p.nb) {
-            // ---- pushes of one source chunk: one far entry per wave
+        } else {
+            // ---- pushes of one source chunk: far entries taken by the waves in turn
             const int g = item - p.nb;
             const int e0 = p.fgrp[g];
             const PushEnt& f0 = p.fpush[e0];
@@ -334,73 +390,24 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
             if (wid == 0) wait_count(cntB, csrc, epoch * p.csize[csrc]);
             __syncthreads();
             compiler_fence();
-            if (wid < p.fgrp_n[g]) {
-                const PushEnt e = p.fpush[e0 + wid];
-                const int bo = p.bsize[e.src], bt = p.bsize[e.dst];
-                for (int c0 = 0; c0 < nrhs; c0 += S)
-                    push_one<S, true, Q>(e, p.alpha, wk.ybuf, p.pos[e.src], bo, bt, n, c0, min(S, nrhs - c0),
-                                      wk.slots_f + e.slot * nrhs + (int64_t)c0 * bt);
-                stores_done();
-                if (lane == 0) __hip_atomic_fetch_add(cntP + csrc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        } else {
-            // ---- phase B: one point row per wave: y_i = Linv row . r_c + (Linv C) row . y_prev
-            const int r0 = -item - 1;
-            const int jb = it.row_blk[r0];
-            const int c = p.chunk_of[jb];
-            const int cf = p.cfirst[jb];
-            const int f0 = p.fx0[jb], f1 = p.fx1[jb];
-            const int nc = p.csize[c];
-            const int wprev = f1 >= 0 ? (int)(p.pos[f1] + p.bsize[f1] - p.pos[f0]) : 0;
-            const int64_t pc = p.pos[cf];
-            const int64_t pf0 = f1 >= 0 ? p.pos[f0] : 0;
-            const int i = r0 + wid;
-            const bool live = i < pc + nc;
-            const int j = live ? it.row_blk[i] : jb;
-            const int a = i - (int)p.pos[j];
-            const int wj = live ? p.w[j] : 0;
-            cd R1[QC], R2[QF];
-            load_row(p.lf + p.lf_off[j] + (int64_t)a * wj, wj, p.mf + p.mf_off[j] + (int64_t)a * wprev,
-                     live ? wprev : 0, R1, R2);
-            // Rows of chunk c need r_c (phase A) and chunks c-kFold..c-1; the
-            // chunks before c-1 are final once c-1 is (its rows waited for
-            // them), so the part of y_prev outside c-1 is staged before the
-            // wait for c-1, and only c-1's own part after it.
-            const int pc1 = cf > 0 ? (int)p.pos[p.cfirst[cf - 1]] : 0;
-            const int n_old = f1 >= 0 ? max(0, min(wprev, pc1 - (int)pf0)) : 0;
-            if (wid == 0)
-                wait_pair(cntA + c, epoch * p.cblocks[c], c >= 2 ? cntB + c - 2 : nullptr,
-                          c >= 2 ? epoch * p.csize[c - 2] : 0);
-            __syncthreads();
-            compiler_fence();
-            for (int c0 = 0; c0 < nrhs; c0 += S) {
-                const int cs = min(S, nrhs - c0);
-                if (c0 == 0) {
-                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, nc, wk.rbuf + pc, nc, xs2, wprev, wk.ybuf + pf0, n_old,
-                                                           n, cs);
-                    if (wid == 0 && c >= 1) wait_count(cntB, c - 1, epoch * p.csize[c - 1]);
-                    __syncthreads();
-                    compiler_fence();
-                    stage_segs<S, kMaxChunk>(xs2 + n_old, wprev, wk.ybuf + pf0 + n_old, wprev - n_old, nullptr, 0,
-                                             nullptr, 0, n, cs);
-                } else {
-                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, nc, wk.rbuf + pc + (int64_t)c0 * n, nc, xs2, wprev,
-                                                           wk.ybuf + pf0 + (int64_t)c0 * n, wprev, n, cs);
-                }
-                __syncthreads();
-                if (live) {
-                    cd y[S];
-                    apply_row<S>(R1, wj, xs1, 0, nc, R2, wprev, xs2, wprev, cs, y);
-                    if (lane == 0)
+            const int ng = p.fgrp_n[g];
+            if (wid < ng) {
+                int dst[kPushGroup / NW];
 #pragma unroll
-                        for (int cc = 0; cc < S; ++cc)
-                            if (cc < cs) st_sc(wk.ybuf + i + (int64_t)(c0 + cc) * n, y[cc]);
+                for (int u = 0; u < kPushGroup / NW; ++u) dst[u] = -1;
+                for (int q = wid; q < ng; q += NW) {
+                    const PushEnt e = p.fpush[e0 + q];
+                    dst[q / NW] = e.dst;
+                    const int bo = p.bsize[e.src], bt = p.bsize[e.dst];
+                    for (int c0 = 0; c0 < nrhs; c0 += S)
+                        push_one<S, true, Q>(e, p.alpha, wk.ybuf, p.pos[e.src], bo, bt, n, c0, min(S, nrhs - c0),
+                                             wk.slots_f + e.slot * nrhs + (int64_t)c0 * bt);
                 }
-                __syncthreads();
-            }
-            if (live) {
                 stores_done();
-                if (lane == 0) __hip_atomic_fetch_add(cntB + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0)
+#pragma unroll
+                    for (int u = 0; u < kPushGroup / NW; ++u)
+                        if (dst[u] >= 0) __hip_atomic_fetch_add(cntT + dst[u], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -418,23 +425,75 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
     __shared__ cd xs2[kFold * kMaxChunk * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
-    int* cntA = wk.flags + 3 * p.nch;
-    int* cntB = wk.flags + 4 * p.nch;
-    int* cntP = wk.flags + 5 * p.nch;
-    for (;;) {
-        const int t = take_ticket(wk.tickets + 1, base, &s_t);
+    int* cntA = wk.flags + 2 * p.nch + p.nb;
+    int* cntB = wk.flags + 3 * p.nch + p.nb;
+    int* cntT = wk.flags + 4 * p.nch + p.nb;
+    const int role = take_ticket(wk.tickets + 1, base, &s_t);
+    if (role < kRowWorkers) {
+        // ---- phase B, persistent: slot role * NW + wid of every chunk, last
+        // chunk first, z_i = Linv^T row . r'_c + (Linv^T C') row . z_next
+        const int slot = role * NW + wid;
+        for (int c = p.nch - 1; c >= 0; --c) {
+            const SweepChunk d = it.bchunk[c];
+            const bool live = slot < d.nc;
+            const int i = d.pc + (live ? slot : 0);
+            const RowTask rt = it.brow[i];
+            const int w1 = live ? rt.w1 : 0;
+            cd R1[QC], R2[QF];
+            load_row(p.lb + rt.a1, w1, p.mb + rt.a2, live ? d.w2 : 0, R1, R2);
+            if (wid == 0)
+                wait_pair(cntA + c, epoch * d.nblocks, c + 2 < p.nch ? cntB + c + 2 : nullptr, epoch * d.need2);
+            __syncthreads();
+            compiler_fence();
+            for (int c0 = 0; c0 < nrhs; c0 += S) {
+                const int cs = min(S, nrhs - c0);
+                if (c0 == 0) {
+                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, d.nc, wk.rbuf2 + d.pc, d.nc, xs2 + d.e_lo, d.w2,
+                                                           wk.zbuf + d.x2 + d.e_lo, d.e_hi - d.e_lo, n, cs);
+                    if (wid == 0 && c + 1 < p.nch) wait_count(cntB, c + 1, epoch * d.need1);
+                    __syncthreads();
+                    compiler_fence();
+                    stage_segs<S, kMaxChunk>(xs2 + d.l_lo, d.w2, wk.zbuf + d.x2 + d.l_lo, d.l_hi - d.l_lo, nullptr, 0,
+                                             nullptr, 0, n, cs);
+                } else {
+                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2,
+                                                           d.w2, wk.zbuf + d.x2 + (int64_t)c0 * n, d.w2, n, cs);
+                }
+                __syncthreads();
+                if (live) {
+                    cd zz[S];
+                    apply_row<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.w2, xs2, d.w2, cs, zz);
+                    if (lane == 0)
+#pragma unroll
+                        for (int cc = 0; cc < S; ++cc)
+                            if (cc < cs) {
+                                st_sc(wk.zbuf + i + (int64_t)(c0 + cc) * n, zz[cc]);
+                                z[rt.zpos + (int64_t)(c0 + cc) * n] = zz[cc];
+                            }
+                }
+                __syncthreads();
+            }
+            // one count per workgroup: its live rows, once all of them are stored
+            if (live) stores_done();
+            __syncthreads();
+            const int nlive = min(max(d.nc - role * NW, 0), NW);
+            if (tid == 0 && nlive > 0)
+                __hip_atomic_fetch_add(cntB + c, nlive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    for (int t = role - kRowWorkers;; t = take_ticket(wk.tickets + 1, base, &s_t) - kRowWorkers) {
         if (t >= it.nitems) return;
         const int item = it.bwd[t];
-        if (item >= 0 && item < p.nb) {
+        if (item < p.nb) {
             // ---- phase A: r'_k = D_k^-1 y_k + sum of the far-entry slots of block k
             const int k = item;
             const int c = p.chunk_of[k];
             const int bk = p.bsize[k];
             const int64_t pk = p.pos[k];
             const cd* Di = p.dinv + p.dinv_off[k];
-            if (wid == 0)
-                for (int cc = c + kFold + 1; cc <= p.bsrc_hi[k]; ++cc)
-                    if (p.bpush_cnt[cc] > 0) wait_count(cntP, cc, epoch * p.bpush_cnt[cc]);
+            const int nin = (int)(p.bgptr[k + 1] - p.bgptr[k]);
+            if (wid == 0 && nin > 0) wait_count(cntT, k, epoch * nin);
             __syncthreads();
             compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
@@ -475,7 +534,7 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
             stores_done();
             __syncthreads();
             if (tid == 0) __hip_atomic_fetch_add(cntA + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else if (item >= p.nb) {
+        } else {
             // ---- pushes of one source chunk: alpha_kj z_j into the slot of (k, j)
             const int g = item - p.nb;
             const int e0 = p.bgrp[g];
@@ -484,74 +543,30 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
             if (wid == 0) wait_count(cntB, csrc, epoch * p.csize[csrc]);
             __syncthreads();
             compiler_fence();
-            if (wid < p.bgrp_n[g]) {
-                const PushEnt e = p.bpush[e0 + wid];
-                const int bo = p.bsize[e.src], bt = p.bsize[e.dst];
-                for (int c0 = 0; c0 < nrhs; c0 += S)
-                    push_one<S, false, Q>(e, p.alpha, wk.zbuf, p.pos[e.src], bo, bt, n, c0, min(S, nrhs - c0),
-                                       wk.slots_b + e.slot * nrhs + (int64_t)c0 * bt);
-                stores_done();
-                if (lane == 0) __hip_atomic_fetch_add(cntP + csrc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        } else {
-            // ---- phase B: one point row per wave: z_i = Linv^T row . r'_c + (Linv^T C') row . z_next
-            const int r0 = -item - 1;
-            const int kb = it.row_blk[r0];
-            const int c = p.chunk_of[kb];
-            const int cf = p.cfirst[kb];
-            const int g0 = p.bx0[kb], g1 = p.bx1[kb];
-            const int nc = p.csize[c];
-            const int wnext = g0 >= 0 ? (int)(p.pos[g1] + p.bsize[g1] - p.pos[g0]) : 0;
-            const int64_t pc = p.pos[cf];
-            const int64_t pg0 = g0 >= 0 ? p.pos[g0] : 0;
-            const int i = r0 + wid;
-            const bool live = i < pc + nc;
-            const int k = live ? it.row_blk[i] : kb;
-            const int a = i - (int)p.pos[k];
-            const int64_t sk = p.bstart[k];
-            const int wtk = live ? p.wt[k] : 0;
-            cd R1[QC], R2[QF];
-            load_row(p.lb + p.lb_off[k] + (int64_t)a * wtk, wtk, p.mb + p.mb_off[k] + (int64_t)a * wnext,
-                     live ? wnext : 0, R1, R2);
-            // Mirror of the forward order: chunk c+1's part of z_next is staged
-            // after the wait for c+1, the rest (final once c+1 is) before it.
-            const int e1 = c + 1 < p.nch ? (int)(pc + nc) + p.csize[c + 1] : 0;
-            const int n_new = g0 >= 0 ? max(0, min(wnext, e1 - (int)pg0)) : 0;
-            if (wid == 0)
-                wait_pair(cntA + c, epoch * p.cblocks[c], c + 2 < p.nch ? cntB + c + 2 : nullptr,
-                          c + 2 < p.nch ? epoch * p.csize[c + 2] : 0);
-            __syncthreads();
-            compiler_fence();
-            for (int c0 = 0; c0 < nrhs; c0 += S) {
-                const int cs = min(S, nrhs - c0);
-                if (c0 == 0) {
-                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, nc, wk.rbuf2 + pc, nc, xs2 + n_new, wnext,
-                                                           wk.zbuf + pg0 + n_new, wnext - n_new, n, cs);
-                    if (wid == 0 && c + 1 < p.nch) wait_count(cntB, c + 1, epoch * p.csize[c + 1]);
-                    __syncthreads();
-                    compiler_fence();
-                    stage_segs<S, kMaxChunk>(xs2, wnext, wk.zbuf + pg0, n_new, nullptr, 0, nullptr, 0, n, cs);
-                } else {
-                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, nc, wk.rbuf2 + pc + (int64_t)c0 * n, nc, xs2, wnext,
-                                                           wk.zbuf + pg0 + (int64_t)c0 * n, wnext, n, cs);
-                }
-                __syncthreads();
-                if (live) {
-                    cd zz[S];
-                    apply_row<S>(R1, wtk, xs1, p.loc[k], nc, R2, wnext, xs2, wnext, cs, zz);
-                    if (lane == 0)
+            const int ng = p.bgrp_n[g];
+            if (wid < ng) {
+                int dst[kPushGroup / NW];
 #pragma unroll
-                        for (int cc = 0; cc < S; ++cc)
-                            if (cc < cs) {
-                                st_sc(wk.zbuf + i + (int64_t)(c0 + cc) * n, zz[cc]);
-                                z[sk + a + (int64_t)(c0 + cc) * n] = zz[cc];
-                            }
+                for (int u = 0; u < kPushGroup / NW; ++u) dst[u] = -1;
+                for (int q = wid; q < ng; q += NW) {
+                    const PushEnt e = p.bpush[e0 + q];
+                    dst[q / NW] = e.dst;
+                    const int bo = p.bsize[e.src], bt = p.bsize[e.dst];
+                    for (int c0 = 0; c0 < nrhs; c0 += S) {
+                        cd* slot = wk.slots_b + e.slot * nrhs + (int64_t)c0 * bt;
+                        if (e.rank < 0)   // column sums over the transposed copy
+                            push_one<S, true, Q>(e, p.alpha_t, wk.zbuf, p.pos[e.src], bo, bt, n, c0,
+                                                 min(S, nrhs - c0), slot);
+                        else
+                            push_one<S, false, Q>(e, p.alpha, wk.zbuf, p.pos[e.src], bo, bt, n, c0,
+                                                  min(S, nrhs - c0), slot);
+                    }
                 }
-                __syncthreads();
-            }
-            if (live) {
                 stores_done();
-                if (lane == 0) __hip_atomic_fetch_add(cntB + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0)
+#pragma unroll
+                    for (int u = 0; u < kPushGroup / NW; ++u)
+                        if (dst[u] >= 0) __hip_atomic_fetch_add(cntT + dst[u], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -618,7 +633,30 @@ k_lr_expand(const ExpandTask* __restrict__ tasks, const cd* __restrict__ src, cd
     }
 }
 
-int sweep_grid(int64_t nitems) { return (int)(nitems < 1024 ? nitems : 1024); }
+int sweep_grid(int64_t nitems) {
+    const int64_t others = nitems < 1 ? 1 : (nitems < 1024 - kRowWorkers ? nitems : 1024 - kRowWorkers);
+    return kRowWorkers + (int)others;
+}
+
+int sweep_capacity(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    int mn = 1 << 30;
+    auto chk = [&](const void* f) {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, NT, 0) != hipSuccess) b = 0;
+        mn = b < mn ? b : mn;
+    };
+    chk(reinterpret_cast<const void*>(&k_sweep_fwd<1, 1>));
+    chk(reinterpret_cast<const void*>(&k_sweep_fwd<1, 2>));
+    chk(reinterpret_cast<const void*>(&k_sweep_fwd<2, 1>));
+    chk(reinterpret_cast<const void*>(&k_sweep_fwd<2, 2>));
+    chk(reinterpret_cast<const void*>(&k_sweep_bwd<1, 1>));
+    chk(reinterpret_cast<const void*>(&k_sweep_bwd<1, 2>));
+    chk(reinterpret_cast<const void*>(&k_sweep_bwd<2, 1>));
+    chk(reinterpret_cast<const void*>(&k_sweep_bwd<2, 2>));
+    return mn * cus;
+}
 
 void launch_sweep(bool forward, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs,
                   const SweepWork& w, int epoch, hipStream_t s) {
