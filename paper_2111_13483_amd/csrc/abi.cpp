@@ -852,9 +852,9 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
         if (opts->precision != HS_PREC_FP64) fail(HS_EINVAL, "unsupported precision");
         set_device(ctx);
-        // the sweeps keep kRowWorkers workgroups resident for a whole launch
+        // the sweeps keep their row workers resident for a whole launch
         // and need others beside them
-        if (hs::sweep_capacity(ctx->device) < hs::kRowWorkers + 32)
+        if (hs::sweep_capacity(ctx->device) < hs::kRowWorkers * hs::kRowSets + 32)
             fail(HS_ENODEVICE, "too few resident workgroups for the preconditioner sweeps");
         hipStream_t s = ctx->stream;
         auto P = std::make_unique<hs_precond>();

@@ -190,9 +190,10 @@ struct RowTask {
     int32_t w1, o1;
     int32_t zpos, pad;
 };
-// Row slots per chunk handled by the persistent row workers: one point row
-// per wave, kMaxChunk / 4 workgroups of four waves.
+// Persistent row workers: kRowSets sets that take turns over the chunks, each
+// of kMaxChunk / 4 workgroups with one point row per wave.
 constexpr int kRowWorkers = 96;
+constexpr int kRowSets = 2;
 // Far entries of one source chunk per push item (four waves take turns).
 constexpr int kPushGroup = 16;
 struct SweepItems {
@@ -221,7 +222,7 @@ struct SweepWork {
     unsigned long long* tickets;
 };
 constexpr int kMaxChunk = 384;   // points per chunk (bounds the row widths)
-constexpr int kFold = 3;         // neighbouring chunks folded into the dense products
+constexpr int kFold = 6;         // neighbouring chunks folded into the dense products
 static_assert(kRowWorkers * 4 == kMaxChunk, "one point row per wave of the row workers");
 // One sweep (forward: v -> y in the work buffers; backward: D^-1 y -> z);
 // the backward launch must follow the forward one of the same epoch.
@@ -229,7 +230,8 @@ void launch_sweep(bool forward, const SweepPlan& p, const SweepItems& it, const 
                   const SweepWork& w, int epoch, hipStream_t s);
 int sweep_grid(int64_t nitems);
 // Workgroups of the sweep kernels that can be resident at once on a device;
-// the row workers spin for the whole launch, so this must exceed kRowWorkers.
+// the row workers spin for the whole launch, so this must exceed
+// kRowSets x kRowWorkers.
 int sweep_capacity(int device);
 // Linv rows of every chunk from the dense in-chunk alpha blocks (intptr /
 // intent: per column j the in-chunk entries (k, j), offsets into A).

@@ -23,9 +23,11 @@
 // or alpha_kj z_j (backward) into a slot of its own; phase A of the target
 // block then only sums its slots in a fixed order (deterministic).
 //
-// Each sweep is one launch. The first kRowWorkers workgroups to start are
-// row workers: each owns four point-row slots and walks the chunks in chain
-// order, loading its rows' matrix slices before waiting for their inputs.
+// Each sweep is one launch. The first kRowSets x kRowWorkers workgroups to
+// start are row workers: each owns four point-row slots of every
+// kRowSets-th chunk and walks them in chain order, loading its rows' matrix
+// slices and taking the part of each row whose inputs are already final
+// while the chunk before is still being computed by the other set.
 // The other workgroups take the phase A and push items by ticket from a list
 // in dependency order, so every item they wait for belongs to a workgroup
 // that is already running. Readiness is tracked by counters (per chunk: its
@@ -65,33 +67,36 @@ __device__ __forceinline__ void st_sc(cd* p, cd v) {
 }
 __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Stage up to two segments into LDS with every load issued before the first
-// LDS write: segment s copies len_s values per right-hand side from g_s
-// (column stride n) to x_s (column stride ld_s).
-template <int S, int MAXTOT>
+// Stage up to two segments into LDS: segment s copies len_s values per
+// right-hand side from g_s (column stride n) to x_s (column stride ld_s).
+// Loads go out in rounds of up to ROUND values per right-hand side, every
+// load of a round issued before its first LDS write.
+template <int S, int ROUND>
 __device__ __forceinline__ void stage_segs(cd* x1, int ld1, const cd* g1, int n1, cd* x2, int ld2, const cd* g2, int n2,
                                            int64_t n, int cs) {
-    constexpr int PER = (MAXTOT * S + NT - 1) / NT;
+    constexpr int PER = (ROUND * S + NT - 1) / NT;
     const int t1 = n1 * cs, t2 = n2 * cs;
-    cd v[PER];
+    for (int e0 = 0; e0 < t1 + t2; e0 += PER * NT) {
+        cd v[PER];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int e = threadIdx.x + u * NT;
-        if (e < t1) {
-            v[u] = ld_sc(g1 + e % n1 + (int64_t)(e / n1) * n);
-        } else if (e < t1 + t2) {
-            const int f = e - t1;
-            v[u] = ld_sc(g2 + f % n2 + (int64_t)(f / n2) * n);
+        for (int u = 0; u < PER; ++u) {
+            const int e = e0 + threadIdx.x + u * NT;
+            if (e < t1) {
+                v[u] = ld_sc(g1 + e % n1 + (int64_t)(e / n1) * n);
+            } else if (e < t1 + t2) {
+                const int f = e - t1;
+                v[u] = ld_sc(g2 + f % n2 + (int64_t)(f / n2) * n);
+            }
         }
-    }
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int e = threadIdx.x + u * NT;
-        if (e < t1) {
-            x1[e % n1 + (e / n1) * ld1] = v[u];
-        } else if (e < t1 + t2) {
-            const int f = e - t1;
-            x2[f % n2 + (f / n2) * ld2] = v[u];
+        for (int u = 0; u < PER; ++u) {
+            const int e = e0 + threadIdx.x + u * NT;
+            if (e < t1) {
+                x1[e % n1 + (e / n1) * ld1] = v[u];
+            } else if (e < t1 + t2) {
+                const int f = e - t1;
+                x2[f % n2 + (f / n2) * ld2] = v[u];
+            }
         }
     }
 }
@@ -127,11 +132,11 @@ __device__ __forceinline__ void wait_pair(const int* a, int na, const int* b, in
 constexpr int QC = kMaxChunk / kWave;   // 64-wide column groups of a chunk
 constexpr int QF = kFold * QC;          // column groups of the folded neighbours
 
-// One row of [A1 | A2] x [x1; x2] by one wave, in two parts so that the
-// row's loads (independent of the chain) are issued before the wait for its
+// One row of [A1 | A2] x [x1; x2] by one wave, in parts so that the row's
+// loads (independent of the chain) are issued before the wait for its
 // inputs: load_row reads A1 (width w1 <= kMaxChunk) and A2 (width w2 <=
-// kFold kMaxChunk) into registers; apply_row multiplies them with the LDS
-// copies xs1[o1 + col] and xs2[col] (column c at stride ld1 / ld2).
+// kFold kMaxChunk) into registers; row_partial multiplies them with the LDS
+// copies of x1 and x2, a column range at a time.
 __device__ __forceinline__ void load_row(const cd* A1, int w1, const cd* A2, int w2, cd (&R1)[QC], cd (&R2)[QF]) {
     const int lane = threadIdx.x % kWave;
 #pragma unroll
@@ -146,26 +151,28 @@ __device__ __forceinline__ void load_row(const cd* A1, int w1, const cd* A2, int
     }
 }
 
+// Lane partial sums of one row over part of its columns: A1's (if with1)
+// and A2's columns in [lo, hi); the caller reduces over the wave at the end.
 template <int S>
-__device__ __forceinline__ void apply_row(const cd (&R1)[QC], int w1, const cd* xs1, int o1, int ld1,
-                                          const cd (&R2)[QF], int w2, const cd* xs2, int ld2, int cs, cd (&out)[S]) {
+__device__ __forceinline__ void row_partial(const cd (&R1)[QC], int w1, const cd* xs1, int o1, int ld1, bool with1,
+                                            const cd (&R2)[QF], int lo, int hi, const cd* xs2, int ld2, int cs,
+                                            cd (&acc)[S]) {
     const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int c = 0; c < S; ++c) {
-        cd sacc = cmk(0.0, 0.0);
         if (c < cs) {
+            if (with1)
 #pragma unroll
-            for (int q = 0; q < QC; ++q) {
-                const int col = lane + q * kWave;
-                if (col < w1) sacc = cfma(R1[q], xs1[o1 + col + c * ld1], sacc);
-            }
+                for (int q = 0; q < QC; ++q) {
+                    const int col = lane + q * kWave;
+                    if (col < w1) acc[c] = cfma(R1[q], xs1[o1 + col + c * ld1], acc[c]);
+                }
 #pragma unroll
             for (int q = 0; q < QF; ++q) {
                 const int col = lane + q * kWave;
-                if (col < w2) sacc = cfma(R2[q], xs2[col + c * ld2], sacc);
+                if (col >= lo && col < hi) acc[c] = cfma(R2[q], xs2[col + c * ld2], acc[c]);
             }
         }
-        out[c] = wave_sum(sacc);
     }
 }
 
@@ -307,11 +314,12 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
     int* cntB = wk.flags + p.nch;
     int* cntT = wk.flags + 2 * p.nch;
     const int role = take_ticket(wk.tickets, base, &s_t);
-    if (role < kRowWorkers) {
-        // ---- phase B, persistent: slot role * NW + wid of every chunk in order,
-        // y_i = Linv row . r_c + (Linv C) row . y_prev
-        const int slot = role * NW + wid;
-        for (int c = 0; c < p.nch; ++c) {
+    if (role < kRowWorkers * kRowSets) {
+        // ---- phase B, persistent: row slot (role % kRowWorkers) * NW + wid of
+        // every kRowSets-th chunk in order, y_i = Linv row . r_c + (Linv C) row . y_prev
+        const int wkr = role % kRowWorkers;
+        const int slot = wkr * NW + wid;
+        for (int c = role / kRowWorkers; c < p.nch; c += kRowSets) {
             const SweepChunk d = it.fchunk[c];
             const bool live = slot < d.nc;
             const int i = d.pc + (live ? slot : 0);
@@ -325,22 +333,33 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
             compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
+                cd acc[S];
+#pragma unroll
+                for (int cc = 0; cc < S; ++cc) acc[cc] = cmk(0.0, 0.0);
                 if (c0 == 0) {
-                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, d.nc, wk.rbuf + d.pc, d.nc, xs2 + d.e_lo, d.w2,
+                    // everything but the newest neighbour chunk is final: stage it
+                    // and take its part of the row before waiting for that chunk
+                    stage_segs<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf + d.pc, d.nc, xs2 + d.e_lo, d.w2,
                                                            wk.ybuf + d.x2 + d.e_lo, d.e_hi - d.e_lo, n, cs);
+                    __syncthreads();
+                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, true, R2, d.e_lo, d.e_hi, xs2, d.w2, cs, acc);
                     if (wid == 0 && c >= 1) wait_count(cntB, c - 1, epoch * d.need1);
                     __syncthreads();
                     compiler_fence();
                     stage_segs<S, kMaxChunk>(xs2 + d.l_lo, d.w2, wk.ybuf + d.x2 + d.l_lo, d.l_hi - d.l_lo, nullptr, 0,
                                              nullptr, 0, n, cs);
+                    __syncthreads();
+                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, false, R2, d.l_lo, d.l_hi, xs2, d.w2, cs, acc);
                 } else {
-                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2,
+                    stage_segs<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2,
                                                            d.w2, wk.ybuf + d.x2 + (int64_t)c0 * n, d.w2, n, cs);
+                    __syncthreads();
+                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, true, R2, 0, d.w2, xs2, d.w2, cs, acc);
                 }
-                __syncthreads();
                 if (live) {
                     cd y[S];
-                    apply_row<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.w2, xs2, d.w2, cs, y);
+#pragma unroll
+                    for (int cc = 0; cc < S; ++cc) y[cc] = wave_sum(acc[cc]);
                     if (lane == 0)
 #pragma unroll
                         for (int cc = 0; cc < S; ++cc)
@@ -351,13 +370,14 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
             // one count per workgroup: its live rows, once all of them are stored
             if (live) stores_done();
             __syncthreads();
-            const int nlive = min(max(d.nc - role * NW, 0), NW);
+            const int nlive = min(max(d.nc - wkr * NW, 0), NW);
             if (tid == 0 && nlive > 0)
                 __hip_atomic_fetch_add(cntB + c, nlive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
     }
-    for (int t = role - kRowWorkers;; t = take_ticket(wk.tickets, base, &s_t) - kRowWorkers) {
+    for (int t = role - kRowWorkers * kRowSets;;
+         t = take_ticket(wk.tickets, base, &s_t) - kRowWorkers * kRowSets) {
         if (t >= it.nitems) return;
         const int item = it.fwd[t];
         if (item < p.nb) {
@@ -429,11 +449,13 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
     int* cntB = wk.flags + 3 * p.nch + p.nb;
     int* cntT = wk.flags + 4 * p.nch + p.nb;
     const int role = take_ticket(wk.tickets + 1, base, &s_t);
-    if (role < kRowWorkers) {
-        // ---- phase B, persistent: slot role * NW + wid of every chunk, last
-        // chunk first, z_i = Linv^T row . r'_c + (Linv^T C') row . z_next
-        const int slot = role * NW + wid;
-        for (int c = p.nch - 1; c >= 0; --c) {
+    if (role < kRowWorkers * kRowSets) {
+        // ---- phase B, persistent: row slot (role % kRowWorkers) * NW + wid of
+        // every kRowSets-th chunk, last chunk first,
+        // z_i = Linv^T row . r'_c + (Linv^T C') row . z_next
+        const int wkr = role % kRowWorkers;
+        const int slot = wkr * NW + wid;
+        for (int c = p.nch - 1 - role / kRowWorkers; c >= 0; c -= kRowSets) {
             const SweepChunk d = it.bchunk[c];
             const bool live = slot < d.nc;
             const int i = d.pc + (live ? slot : 0);
@@ -447,28 +469,39 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
             compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
+                cd acc[S];
+#pragma unroll
+                for (int cc = 0; cc < S; ++cc) acc[cc] = cmk(0.0, 0.0);
                 if (c0 == 0) {
-                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, d.nc, wk.rbuf2 + d.pc, d.nc, xs2 + d.e_lo, d.w2,
+                    // everything but the newest neighbour chunk is final: stage it
+                    // and take its part of the row before waiting for that chunk
+                    stage_segs<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf2 + d.pc, d.nc, xs2 + d.e_lo, d.w2,
                                                            wk.zbuf + d.x2 + d.e_lo, d.e_hi - d.e_lo, n, cs);
+                    __syncthreads();
+                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, true, R2, d.e_lo, d.e_hi, xs2, d.w2, cs, acc);
                     if (wid == 0 && c + 1 < p.nch) wait_count(cntB, c + 1, epoch * d.need1);
                     __syncthreads();
                     compiler_fence();
                     stage_segs<S, kMaxChunk>(xs2 + d.l_lo, d.w2, wk.zbuf + d.x2 + d.l_lo, d.l_hi - d.l_lo, nullptr, 0,
                                              nullptr, 0, n, cs);
+                    __syncthreads();
+                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, false, R2, d.l_lo, d.l_hi, xs2, d.w2, cs, acc);
                 } else {
-                    stage_segs<S, kMaxChunk * (1 + kFold)>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2,
+                    stage_segs<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2,
                                                            d.w2, wk.zbuf + d.x2 + (int64_t)c0 * n, d.w2, n, cs);
+                    __syncthreads();
+                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, true, R2, 0, d.w2, xs2, d.w2, cs, acc);
                 }
-                __syncthreads();
                 if (live) {
-                    cd zz[S];
-                    apply_row<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.w2, xs2, d.w2, cs, zz);
+                    cd y[S];
+#pragma unroll
+                    for (int cc = 0; cc < S; ++cc) y[cc] = wave_sum(acc[cc]);
                     if (lane == 0)
 #pragma unroll
                         for (int cc = 0; cc < S; ++cc)
                             if (cc < cs) {
-                                st_sc(wk.zbuf + i + (int64_t)(c0 + cc) * n, zz[cc]);
-                                z[rt.zpos + (int64_t)(c0 + cc) * n] = zz[cc];
+                                st_sc(wk.zbuf + i + (int64_t)(c0 + cc) * n, y[cc]);
+                                z[rt.zpos + (int64_t)(c0 + cc) * n] = y[cc];
                             }
                 }
                 __syncthreads();
@@ -476,13 +509,14 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
             // one count per workgroup: its live rows, once all of them are stored
             if (live) stores_done();
             __syncthreads();
-            const int nlive = min(max(d.nc - role * NW, 0), NW);
+            const int nlive = min(max(d.nc - wkr * NW, 0), NW);
             if (tid == 0 && nlive > 0)
                 __hip_atomic_fetch_add(cntB + c, nlive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
     }
-    for (int t = role - kRowWorkers;; t = take_ticket(wk.tickets + 1, base, &s_t) - kRowWorkers) {
+    for (int t = role - kRowWorkers * kRowSets;;
+         t = take_ticket(wk.tickets + 1, base, &s_t) - kRowWorkers * kRowSets) {
         if (t >= it.nitems) return;
         const int item = it.bwd[t];
         if (item < p.nb) {
@@ -634,8 +668,9 @@ k_lr_expand(const ExpandTask* __restrict__ tasks, const cd* __restrict__ src, cd
 }
 
 int sweep_grid(int64_t nitems) {
-    const int64_t others = nitems < 1 ? 1 : (nitems < 1024 - kRowWorkers ? nitems : 1024 - kRowWorkers);
-    return kRowWorkers + (int)others;
+    constexpr int rows = kRowWorkers * kRowSets;
+    const int64_t others = nitems < 1 ? 1 : (nitems < 1024 - rows ? nitems : 1024 - rows);
+    return rows + (int)others;
 }
 
 int sweep_capacity(int device) {
