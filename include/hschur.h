@@ -78,6 +78,13 @@ typedef struct {
     int32_t ordering;     /* HS_ORDER_* (Algorithm 1) */
     double  fill_tol;     /* fill-in compression tolerance (Sec. 3.4); 0 keeps every block dense */
     int32_t precision;    /* HS_PREC_FP64 */
+    /* Evaluation layout of the apply (the operator is the same up to rounding):
+     * points per chunk of consecutive block rows (0 = 384, at most 384) and
+     * columns of the neighbour range folded into each chunk's dense products
+     * (0 = 3072; else at least the chunk size, at most 3072). Smaller values
+     * send more entries through the pushed far-entry path. */
+    int32_t sweep_chunk;
+    int32_t sweep_fold_cols;
 } hs_precond_opts;
 
 typedef struct {

@@ -40,7 +40,8 @@ class BuildOpts(ctypes.Structure):
 
 
 class PrecondOpts(ctypes.Structure):
-    _fields_ = [("ordering", ctypes.c_int32), ("fill_tol", ctypes.c_double), ("precision", ctypes.c_int32)]
+    _fields_ = [("ordering", ctypes.c_int32), ("fill_tol", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("sweep_chunk", ctypes.c_int32), ("sweep_fold_cols", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -272,9 +273,10 @@ class HMatrix:
 
 
 class Precond:
-    def __init__(self, ctx: Context, H: HMatrix, ordering: str = "rcm", fill_tol: float = 1e-2):
+    def __init__(self, ctx: Context, H: HMatrix, ordering: str = "rcm", fill_tol: float = 1e-2, sweep_chunk: int = 0,
+                 sweep_fold_cols: int = 0):
         self.ctx, self.H = ctx, H
-        opts = PrecondOpts(ORDER[ordering], float(fill_tol), 0)
+        opts = PrecondOpts(ORDER[ordering], float(fill_tol), 0, int(sweep_chunk), int(sweep_fold_cols))
         h = ctypes.c_void_p()
         _check(_lib.hs_precond_setup(ctx._h, H._h, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h

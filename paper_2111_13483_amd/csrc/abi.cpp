@@ -851,6 +851,11 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         if (opts->ordering < 0 || opts->ordering > 2) fail(HS_EINVAL, "unknown ordering");
         if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
         if (opts->precision != HS_PREC_FP64) fail(HS_EINVAL, "unsupported precision");
+        if (opts->sweep_chunk < 0 || opts->sweep_chunk > hs::kMaxChunk) fail(HS_EINVAL, "sweep_chunk must be in [0, 384]");
+        const int32_t chunk_lim = opts->sweep_chunk > 0 ? opts->sweep_chunk : hs::kMaxChunk;
+        if (opts->sweep_fold_cols != 0 && (opts->sweep_fold_cols < chunk_lim || opts->sweep_fold_cols > hs::kFoldCols))
+            fail(HS_EINVAL, "sweep_fold_cols must be 0 or in [chunk size, 3072]");
+        const int32_t fold_cols = opts->sweep_fold_cols > 0 ? opts->sweep_fold_cols : hs::kFoldCols;
         set_device(ctx);
         // the sweeps keep their row workers resident for a whole launch
         // and need others beside them
@@ -1035,15 +1040,14 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             hip_check(hipMemcpyAsync(P->d_alpha, Ad, atot * 16, hipMemcpyDeviceToDevice, s), "D2D");
         }
         // ---- chunked sweep plan: consecutive block rows grouped up to kMaxChunk points
-        std::vector<int32_t> chunk_of(nb), loc(nb), wdt(nb), wtt(nb), cfirst(nb), clast(nb), chunk_first;
-        std::vector<int32_t> fx0(nb, -1), fx1(nb, -1), bx0(nb, -1), bx1(nb, -1);
+        std::vector<int32_t> chunk_of(nb), loc(nb), wdt(nb), wtt(nb), clast(nb), chunk_first;
         std::vector<int64_t> pos(nb);
         {
             int64_t pp = 0;
-            int32_t cur = -1, used = hs::kMaxChunk;
+            int32_t cur = -1, used = chunk_lim;
             for (int64_t kk = 0; kk < nb; ++kk) {
                 const int32_t bk = P->bsize[kk];
-                if (used + bk > hs::kMaxChunk) {
+                if (used + bk > chunk_lim) {
                     ++cur;
                     used = 0;
                     chunk_first.push_back((int32_t)kk);
@@ -1060,24 +1064,80 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         const int64_t nch = (int64_t)chunk_first.size() - 1;
         P->nchunk = nch;
         std::vector<int32_t> csize(nch);
-        // fold widths: forward = points of chunks [c - kFold, c - 1], backward = [c + 1, c + kFold]
-        std::vector<int32_t> fwidth(nch, 0), bwidth(nch, 0);
         for (int64_t c = 0; c < nch; ++c) {
             int32_t sz = 0;
             for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) sz += P->bsize[kk];
             csize[c] = sz;
-        }
-        for (int64_t c = 0; c < nch; ++c) {
-            const int64_t c0f = std::max<int64_t>(0, c - hs::kFold), c1b = std::min<int64_t>(nch - 1, c + hs::kFold);
-            for (int64_t d = c0f; d < c; ++d) fwidth[c] += csize[d];
-            for (int64_t d = c + 1; d <= c1b; ++d) bwidth[c] += csize[d];
             for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) {
-                cfirst[kk] = chunk_first[c];
                 clast[kk] = chunk_first[c + 1] - 1;
-                wtt[kk] = csize[c] - loc[kk];
-                if (c > 0) { fx0[kk] = chunk_first[c0f]; fx1[kk] = chunk_first[c] - 1; }
-                if (c + 1 < nch) { bx0[kk] = chunk_first[c + 1]; bx1[kk] = chunk_first[c1b + 1] - 1; }
+                wtt[kk] = sz - loc[kk];
             }
+        }
+        // Folded neighbour ranges. Forward, chunk c: all of chunk c-1 (contiguous),
+        // then the source blocks of chunks <= c-2 coupled to chunk c, nearest chunk
+        // first, while they fit in fold_cols columns; the entries of the source
+        // blocks left out are pushed. Backward mirrored (chunk c+1, then >= c+2).
+        std::vector<int32_t> fwidth(nch, 0), bwidth(nch, 0), fl_n(nch, 0), bl_n(nch, 0);
+        std::vector<std::unordered_map<int32_t, int32_t>> ffold(nch), bfold(nch);   // block -> column
+        std::vector<int32_t> femap, bemap, fe_off(nch + 1, 0), be_off(nch + 1, 0);
+        {
+            std::vector<std::vector<int32_t>> fsrc(nch), bsrc(nch);
+            for (int64_t kk = 0; kk < nb; ++kk)
+                for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
+                    const int32_t j = (int32_t)sy.cols[e];
+                    const int32_t ck = chunk_of[kk], cj = chunk_of[j];
+                    if (cj >= ck + 2) {
+                        fsrc[cj].push_back((int32_t)kk);
+                        bsrc[ck].push_back(j);
+                    }
+                }
+            auto uniq = [](std::vector<int32_t>& v) {
+                std::sort(v.begin(), v.end());
+                v.erase(std::unique(v.begin(), v.end()), v.end());
+            };
+            for (int64_t c = 0; c < nch; ++c) {
+                uniq(fsrc[c]);
+                uniq(bsrc[c]);
+                // nearest chunk first, blocks ascending within a chunk
+                std::stable_sort(fsrc[c].begin(), fsrc[c].end(),
+                                 [&](int32_t x, int32_t y) { return chunk_of[x] > chunk_of[y]; });
+                std::stable_sort(bsrc[c].begin(), bsrc[c].end(),
+                                 [&](int32_t x, int32_t y) { return chunk_of[x] < chunk_of[y]; });
+                fe_off[c] = (int32_t)femap.size();
+                if (c > 0) {
+                    int32_t cols = 0;
+                    for (int32_t kk = chunk_first[c - 1]; kk < chunk_first[c]; ++kk) {
+                        ffold[c][kk] = cols;
+                        cols += P->bsize[kk];
+                    }
+                    fl_n[c] = cols;
+                    for (int32_t kk : fsrc[c]) {
+                        if (cols + P->bsize[kk] > fold_cols) break;
+                        ffold[c][kk] = cols;
+                        for (int32_t q = 0; q < P->bsize[kk]; ++q) femap.push_back((int32_t)(pos[kk] + q));
+                        cols += P->bsize[kk];
+                    }
+                    fwidth[c] = cols;
+                }
+                be_off[c] = (int32_t)bemap.size();
+                if (c + 1 < nch) {
+                    int32_t cols = 0;
+                    for (int32_t kk = chunk_first[c + 1]; kk < chunk_first[c + 2]; ++kk) {
+                        bfold[c][kk] = cols;
+                        cols += P->bsize[kk];
+                    }
+                    bl_n[c] = cols;
+                    for (int32_t kk : bsrc[c]) {
+                        if (cols + P->bsize[kk] > fold_cols) break;
+                        bfold[c][kk] = cols;
+                        for (int32_t q = 0; q < P->bsize[kk]; ++q) bemap.push_back((int32_t)(pos[kk] + q));
+                        cols += P->bsize[kk];
+                    }
+                    bwidth[c] = cols;
+                }
+            }
+            fe_off[nch] = (int32_t)femap.size();
+            be_off[nch] = (int32_t)bemap.size();
         }
         std::vector<int64_t> lf_off(nb), lb_off(nb), mf_off(nb), mb_off(nb), cf_off(nch, -1), cb_off(nch, -1);
         int64_t lft = 0, lbt = 0, mft = 0, mbt = 0, cft = 0, cbt = 0;
@@ -1099,8 +1159,9 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             cbt += (int64_t)csize[c] * bwidth[c];
         }
         P->linv_elems = lft + lbt + mft + mbt;
-        // entries: in-chunk ones feed Linv, those up to kFold chunks apart the coupling
-        // products, the rest are pushed from their source block into per-entry slots
+        // entries: in-chunk ones feed Linv, folded ones the coupling products of
+        // their target chunk, the rest are pushed from their source block into
+        // per-entry slots (separately per direction)
         std::vector<int64_t> intptr(nb + 1, 0);
         for (int64_t e = 0; e < nnz; ++e)
             if (chunk_of[row_of[e]] == chunk_of[sy.cols[e]]) intptr[sy.cols[e] + 1]++;
@@ -1108,31 +1169,37 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         std::vector<hs::SweepEnt> intent(intptr[nb]);
         std::vector<hs::ExpandTask> expand;
         std::vector<hs::CopyTask> cfc, cbc;
-        std::vector<int64_t> far_e;   // pattern entries more than kFold chunks apart, row-major order
+        std::vector<int64_t> far_f, far_b;   // pushed entries, row-major order
         {
             std::vector<int64_t> fi(intptr.begin(), intptr.end() - 1);
             for (int64_t kk = 0; kk < nb; ++kk)
                 for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
-                    const int64_t j = sy.cols[e];
+                    const int32_t j = (int32_t)sy.cols[e];
                     const int32_t ck = chunk_of[kk], cj = chunk_of[j];
                     const int32_t bk = P->bsize[kk], bj = P->bsize[j];
-                    if (cj - ck <= hs::kFold && P->a_rank[e] >= 0)
+                    const auto fit = ffold[cj].find((int32_t)kk);
+                    const auto bit = bfold[ck].find(j);
+                    const bool in_chunk = cj == ck;
+                    const bool ffolded = !in_chunk && fit != ffold[cj].end();
+                    const bool bfolded = !in_chunk && bit != bfold[ck].end();
+                    if ((in_chunk || ffolded || bfolded) && P->a_rank[e] >= 0)
                         expand.push_back(hs::ExpandTask{P->a_off[e], ad_off[e], bk, bj, P->a_rank[e], 0});
-                    if (cj == ck) {
+                    if (in_chunk) {
                         intent[fi[j]++] = hs::SweepEnt{ad_off[e], (int32_t)kk, -1};
-                    } else if (cj - ck <= hs::kFold) {
-                        // forward coupling of chunk cj: rows of block j, columns of block k (alpha_kj^T),
-                        // columns in elimination order from the first folded block
-                        const int64_t fcol = pos[kk] - pos[fx0[j]];
-                        cfc.push_back(hs::CopyTask{cf_off[cj] + (int64_t)loc[j] * fwidth[cj] + fcol, ad_off[e], bj, bk,
-                                                   1, fwidth[cj]});
-                        // backward coupling of chunk ck: rows of block k, columns of block j (alpha_kj)
-                        const int64_t bcol = pos[j] - pos[bx0[kk]];
-                        cbc.push_back(hs::CopyTask{cb_off[ck] + (int64_t)loc[kk] * bwidth[ck] + bcol, ad_off[e], bk, bj,
-                                                   0, bwidth[ck]});
-                    } else {
-                        far_e.push_back(e);
+                        continue;
                     }
+                    // forward coupling of chunk cj: rows of block j, columns of block k (alpha_kj^T)
+                    if (ffolded)
+                        cfc.push_back(hs::CopyTask{cf_off[cj] + (int64_t)loc[j] * fwidth[cj] + fit->second, ad_off[e],
+                                                   bj, bk, 1, fwidth[cj]});
+                    else
+                        far_f.push_back(e);
+                    // backward coupling of chunk ck: rows of block k, columns of block j (alpha_kj)
+                    if (bfolded)
+                        cbc.push_back(hs::CopyTask{cb_off[ck] + (int64_t)loc[kk] * bwidth[ck] + bit->second, ad_off[e],
+                                                   bk, bj, 0, bwidth[ck]});
+                    else
+                        far_b.push_back(e);
                 }
         }
         // push lists (grouped by source chunk) and per-target gather lists
@@ -1142,7 +1209,7 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         std::vector<std::vector<int32_t>> fgrp_of(nch), bgrp_of(nch);   // group ids per source chunk
         {
             // forward: source k (rows ascending = sources ascending); backward: source j
-            std::vector<int64_t> fo(far_e), bo(far_e);
+            std::vector<int64_t> fo(far_f), bo(far_b);
             std::stable_sort(fo.begin(), fo.end(), [&](int64_t x, int64_t y) {
                 return row_of[x] != row_of[y] ? row_of[x] < row_of[y] : sy.cols[x] < sy.cols[y];
             });
@@ -1161,7 +1228,7 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             }
             // push order: by source chunk, then the target chunk needed soonest
             // (forward the lowest, backward the highest), then source and target
-            std::vector<int64_t> fpo(far_e), bpo(far_e);
+            std::vector<int64_t> fpo(far_f), bpo(far_b);
             std::stable_sort(fpo.begin(), fpo.end(), [&](int64_t x, int64_t y) {
                 const int32_t sx = chunk_of[row_of[x]], sy_ = chunk_of[row_of[y]];
                 if (sx != sy_) return sx < sy_;
@@ -1210,7 +1277,7 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             bgslot.resize(bgptr[nb]);
             std::vector<int64_t> ff(fgptr.begin(), fgptr.end() - 1), bf(bgptr.begin(), bgptr.end() - 1);
             for (int64_t e : fo) fgslot[ff[sy.cols[e]]++] = fslot[e];   // fo is sorted by source k
-            std::vector<int64_t> bo2(far_e);   // backward targets gather by ascending source j
+            std::vector<int64_t> bo2(far_b);   // backward targets gather by ascending source j
             std::stable_sort(bo2.begin(), bo2.end(), [&](int64_t x, int64_t y) {
                 return row_of[x] != row_of[y] ? row_of[x] < row_of[y] : sy.cols[x] < sy.cols[y];
             });
@@ -1223,13 +1290,8 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         sp.nb = (int)nb;
         sp.nch = (int)nch;
         sp.bmax = *std::max_element(P->bsize.begin(), P->bsize.end());
-        {
-            std::vector<int32_t> cblocks(nch);
-            for (int64_t c = 0; c < nch; ++c) cblocks[c] = chunk_first[c + 1] - chunk_first[c];
-            sp.chunk_of = o.upload(chunk_of, s);
-            sp.csize = o.upload(csize, s);
-            sp.cblocks = o.upload(cblocks, s);
-        }
+        sp.chunk_of = o.upload(chunk_of, s);
+        sp.csize = o.upload(csize, s);
         sp.n = H->n;
         sp.bstart = P->d_bstart;
         sp.bsize = P->d_bsize;
@@ -1237,12 +1299,7 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         sp.loc = o.upload(loc, s);
         sp.w = o.upload(wdt, s);
         sp.wt = o.upload(wtt, s);
-        sp.cfirst = o.upload(cfirst, s);
         sp.clast = o.upload(clast, s);
-        sp.fx0 = o.upload(fx0, s);
-        sp.fx1 = o.upload(fx1, s);
-        sp.bx0 = o.upload(bx0, s);
-        sp.bx1 = o.upload(bx1, s);
         sp.lf_off = o.upload(lf_off, s);
         sp.lb_off = o.upload(lb_off, s);
         sp.mf_off = o.upload(mf_off, s);
@@ -1318,8 +1375,8 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         hip_check(hipGetLastError(), "linv launches");
         // Row workers: per chunk its ranges, per point row its matrix slices.
         // Work items of the other workgroups in dependency order: per chunk its
-        // block rows (phase A) kFold chunks ahead of the pushes from the chunk
-        // whose rows finish then; forward ascending, backward descending.
+        // block rows (phase A), then the pushes from the chunk before it;
+        // forward ascending, backward descending.
         {
             std::vector<hs::SweepChunk> fch(nch), bch(nch);
             std::vector<hs::RowTask> frow(H->n), brow(H->n);
@@ -1331,13 +1388,11 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
                 f.nc = nc;
                 f.nblocks = nbk;
                 if (c > 0) {
-                    f.x2 = (int32_t)pos[chunk_first[std::max<int64_t>(0, c - hs::kFold)]];
                     f.w2 = fwidth[c];
-                    const int32_t s1 = (int32_t)pos[chunk_first[c - 1]] - f.x2;   // chunk c-1 within the range
-                    f.e_lo = 0;
-                    f.e_hi = s1;
-                    f.l_lo = s1;
-                    f.l_hi = f.w2;
+                    f.l_n = fl_n[c];
+                    f.l_g = (int32_t)pos[chunk_first[c - 1]];
+                    f.e_n = f.w2 - f.l_n;
+                    f.e_off = fe_off[c];
                     f.need1 = csize[c - 1];
                     f.need2 = c >= 2 ? csize[c - 2] : 0;
                 }
@@ -1347,12 +1402,11 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
                 b.nc = nc;
                 b.nblocks = nbk;
                 if (c + 1 < nch) {
-                    b.x2 = pc + nc;
                     b.w2 = bwidth[c];
-                    b.l_lo = 0;
-                    b.l_hi = csize[c + 1];
-                    b.e_lo = b.l_hi;
-                    b.e_hi = b.w2;
+                    b.l_n = bl_n[c];
+                    b.l_g = pc + nc;
+                    b.e_n = b.w2 - b.l_n;
+                    b.e_off = be_off[c];
                     b.need1 = csize[c + 1];
                     b.need2 = c + 2 < nch ? csize[c + 2] : 0;
                 }
@@ -1367,27 +1421,29 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
                     }
             }
             std::vector<int32_t> fwd, bwd;
-            for (int64_t t = 0; t < nch + hs::kFold; ++t) {
+            for (int64_t t = 0; t <= nch; ++t) {
                 if (t < nch)
                     for (int32_t kk = chunk_first[t]; kk < chunk_first[t + 1]; ++kk) fwd.push_back(kk);
-                if (t - hs::kFold >= 0)
-                    for (int32_t g : fgrp_of[t - hs::kFold]) fwd.push_back((int32_t)nb + g);
+                if (t >= 1)
+                    for (int32_t g : fgrp_of[t - 1]) fwd.push_back((int32_t)nb + g);
             }
-            for (int64_t t = 0; t < nch + hs::kFold; ++t) {
+            for (int64_t t = 0; t <= nch; ++t) {
                 const int64_t c = nch - 1 - t;
                 if (c >= 0)
                     for (int32_t kk = chunk_first[c + 1] - 1; kk >= chunk_first[c]; --kk) bwd.push_back(kk);
-                if (t - hs::kFold >= 0)
-                    for (int32_t g : bgrp_of[c + hs::kFold]) bwd.push_back((int32_t)nb + g);
+                if (t >= 1)
+                    for (int32_t g : bgrp_of[c + 1]) bwd.push_back((int32_t)nb + g);
             }
-            if (fwd.size() != bwd.size()) fail(HS_EINVAL, "internal: sweep item lists differ in length");
-            P->items.nitems = (int64_t)fwd.size();
+            P->items.nfwd = (int64_t)fwd.size();
+            P->items.nbwd = (int64_t)bwd.size();
             P->items.fwd = o.upload(fwd, s);
             P->items.bwd = o.upload(bwd, s);
             P->items.fchunk = o.upload(fch, s);
             P->items.bchunk = o.upload(bch, s);
             P->items.frow = o.upload(frow, s);
             P->items.brow = o.upload(brow, s);
+            P->items.femap = o.upload(femap, s);
+            P->items.bemap = o.upload(bemap, s);
         }
         hip_check(hipStreamSynchronize(s), "stream sync");
         tmp.release();

@@ -104,18 +104,16 @@ void launch_gather(const int64_t* leaf_off, const int64_t* gptr, const GatherEnt
 // P^-1 v = alpha D^-1 alpha^T v by chunked sweeps. Block rows (elimination
 // order) are grouped into chunks of consecutive rows. With L the unit lower
 // block-triangular factor (L_jk = -alpha_kj^T), Linv_c the inverse of chunk
-// c's diagonal part and C_c the coupling of chunk c to the kFold chunks
-// before it (columns in elimination order):
-//   forward   y_c = Linv_c r_c + (Linv_c C_c) y_{c-kFold..c-1},
-//             r_c = v_c + terms from chunks more than kFold back
-//   backward  z_c = Linv_c^T r'_c + (Linv_c^T C'_c) z_{c+1..c+kFold},
-//             r'_c = zt_c + terms from chunks more than kFold ahead
+// c's diagonal part and C_c the coupling of chunk c to its folded neighbour
+// range (SweepChunk):
+//   forward   y_c = Linv_c r_c + (Linv_c C_c) y_range,
+//             r_c = v_c + pushed terms of the entries outside the range
+//   backward  z_c = Linv_c^T r'_c + (Linv_c^T C'_c) z_range,
+//             r'_c = zt_c + pushed terms of the entries outside the range
 // Per block row k: pos = elimination-order offset, loc = offset in its
 // chunk, w = loc + b_k (forward Linv row width), wt = n_c - loc (backward
-// width), fx0..fx1 the blocks of the folded previous chunks and bx0..bx1
-// those of the folded next chunks (-1 when absent); row blocks of Linv
-// (b_k x w), Linv^T (b_k x wt), Linv C (b_k x fold width) and Linv^T C'
-// (b_k x fold width), all row-major.
+// width); row blocks of Linv (b_k x w), Linv^T (b_k x wt), Linv C (b_k x
+// range width) and Linv^T C' (b_k x range width), all row-major.
 struct SweepPlan {
     int nb;
     int nch;
@@ -127,12 +125,7 @@ struct SweepPlan {
     const int32_t* loc;
     const int32_t* w;
     const int32_t* wt;
-    const int32_t* cfirst;
     const int32_t* clast;
-    const int32_t* fx0;
-    const int32_t* fx1;
-    const int32_t* bx0;
-    const int32_t* bx1;
     const int64_t* lf_off;     // Linv rows
     const int64_t* lb_off;     // Linv^T rows
     const int64_t* mf_off;     // (Linv C) rows
@@ -143,8 +136,7 @@ struct SweepPlan {
     const cd* mb;
     const int32_t* chunk_of;   // chunk of each block
     const int32_t* csize;      // points of each chunk
-    const int32_t* cblocks;    // blocks of each chunk
-    // far entries (k, j), chunk(j) - chunk(k) > kFold: pushed from their source
+    // entries (k, j) outside the target chunk's folded range: pushed from their source
     // block once its chunk is final, into one slot per entry, then gathered by
     // the target block, which waits for its own count of pushed entries.
     // Forward: source k -> target j; backward: source j -> target k. Pushes are
@@ -165,21 +157,24 @@ struct SweepPlan {
     const cd* dinv;
     const int64_t* dinv_off;
 };
-// Work items in ticket order: 0 <= item < nb is a block row (phase A: gather
-// of its far-entry slots), item >= nb the push group item - nb, item < 0 a
-// group of four point rows starting at elimination-order row -item - 1
-// (phase B, one row per wavefront). Phase A items of chunk c + kFold come
-// before the phase B rows of chunk c, whose pushes follow them. row_blk maps
-// an elimination-order row to its block.
-// Per chunk, for the row workers of one sweep direction.
+// Work items of the non-row workgroups in ticket order: item < nb is a block
+// row (phase A: r = v or D^-1 y plus its pushed slots), item >= nb the push
+// group item - nb. Phase A of chunk c comes before the pushes from chunk c - 1
+// (forward; mirrored backward), which come before phase A of chunk c + 1.
+// Per chunk, for the row workers of one sweep direction. The folded
+// neighbour range (columns of the coupling product) starts with all of the
+// neighbour chunk the chain came from (c - 1 forward, c + 1 backward), whose
+// values arrive last; then come the coupled source blocks of the chunks
+// further away, nearest first, up to kFoldCols columns. Those are final one
+// chunk earlier; their elimination-order positions are listed in a map.
 struct SweepChunk {
     int32_t pc, nc;          // first elimination-order position and points of the chunk
-    int32_t x2, w2;          // first position and width of the folded neighbour range
-    int32_t e_lo, e_hi;      // part of that range final once chunk c -/+ 2 is
-    int32_t l_lo, l_hi;      // part of that range in chunk c -/+ 1
+    int32_t w2;              // width of the folded range
+    int32_t l_n, l_g;        // newest neighbour chunk: its points (range columns [0, l_n)) and first position
+    int32_t e_n, e_off;      // the rest (columns [l_n, w2)): points and their offset into the position map
     int32_t nblocks;         // blocks of the chunk (phase A count)
     int32_t need1, need2;    // points of chunks c -/+ 1 and c -/+ 2 (0 if absent)
-    int32_t pad;
+    int32_t pad[2];
 };
 // Per point row (indexed by elimination-order position): its slices of the
 // chunk inverse (a1, width w1, first column o1 in the chunk) and of the
@@ -197,13 +192,15 @@ constexpr int kRowSets = 2;
 // Far entries of one source chunk per push item (four waves take turns).
 constexpr int kPushGroup = 16;
 struct SweepItems {
-    int64_t nitems;          // phase A and push items per direction
+    int64_t nfwd, nbwd;      // phase A and push items of each direction
     const int32_t* fwd;
     const int32_t* bwd;
     const SweepChunk* fchunk;
     const SweepChunk* bchunk;
     const RowTask* frow;
     const RowTask* brow;
+    const int32_t* femap;     // positions of the early range columns, per chunk from SweepChunk::e_off
+    const int32_t* bemap;
 };
 // Work buffers of one apply stream: ybuf, zbuf, rbuf, rbuf2 (elimination
 // order) n nrhs each; slots_f / slots_b (push results, nrhs times the slot
@@ -222,8 +219,9 @@ struct SweepWork {
     unsigned long long* tickets;
 };
 constexpr int kMaxChunk = 384;   // points per chunk (bounds the row widths)
-constexpr int kFold = 6;         // neighbouring chunks folded into the dense products
+constexpr int kFoldCols = 3072;   // columns of the folded neighbour range per chunk
 static_assert(kRowWorkers * 4 == kMaxChunk, "one point row per wave of the row workers");
+static_assert(kFoldCols % 64 == 0 && kFoldCols >= kMaxChunk, "fold range in whole wavefront groups");
 // One sweep (forward: v -> y in the work buffers; backward: D^-1 y -> z);
 // the backward launch must follow the forward one of the same epoch.
 void launch_sweep(bool forward, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs,

@@ -7,18 +7,18 @@
 // Under a bandwidth-reducing order each block row depends on the one before
 // it, so both sweeps are chains of nb dependent steps. Consecutive rows are
 // grouped into chunks; with Linv_c the explicit inverse of chunk c's unit
-// lower-triangular diagonal part and C_c its coupling to the kFold chunks
-// before it,
-//   forward   y_c = Linv_c r_c + (Linv_c C_c) y_{c-kFold..c-1}
-//   backward  z_c = Linv_c^T r'_c + (Linv_c^T C'_c) z_{c+1..c+kFold}
-// where r, r' gather the terms from chunks further away. Phase A of a row
-// gathers those terms (they are ready several chunks before they are
-// needed); phase B applies the row's slice of the two dense products once
-// the neighbouring chunks have finished, so the chain advances one dense
-// row-block product per chunk. The operator is unchanged; only the evaluation order of the
-// triangular solves differs.
+// lower-triangular diagonal part and C_c its coupling to a folded range of
+// earlier points (all of chunk c-1, then the coupled blocks of earlier chunks,
+// nearest first, up to kFoldCols columns),
+//   forward   y_c = Linv_c r_c + (Linv_c C_c) y_range
+//   backward  z_c = Linv_c^T r'_c + (Linv_c^T C'_c) z_range
+// where r, r' gather the terms of the entries outside the range. Phase A of
+// a block row gathers those terms (they are ready well before they are
+// needed); phase B applies a row's slice of the two dense products, so the
+// chain advances one dense row-block product per chunk. The operator is
+// unchanged; only the evaluation order of the triangular solves differs.
 //
-// The terms from chunks further away are pushed: as soon as a chunk is
+// The terms outside the range are pushed: as soon as a chunk is
 // final, a wavefront per far entry (k, j) computes alpha_kj^T y_k (forward)
 // or alpha_kj z_j (backward) into a slot of its own; phase A of the target
 // block then only sums its slots in a fixed order (deterministic).
@@ -101,6 +101,39 @@ __device__ __forceinline__ void stage_segs(cd* x1, int ld1, const cd* g1, int n1
     }
 }
 
+// Stage r (n1 contiguous values per right-hand side from g1) and the early
+// part of the folded range (n2 values gathered from g2 at the positions in
+// map) into LDS, in rounds like stage_segs.
+template <int S, int ROUND>
+__device__ __forceinline__ void stage_mapped(cd* x1, int ld1, const cd* g1, int n1, cd* x2, int ld2, const cd* g2,
+                                             const int32_t* map, int n2, int64_t n, int cs) {
+    constexpr int PER = (ROUND * S + NT - 1) / NT;
+    const int t1 = n1 * cs, t2 = n2 * cs;
+    for (int e0 = 0; e0 < t1 + t2; e0 += PER * NT) {
+        cd v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = e0 + threadIdx.x + u * NT;
+            if (e < t1) {
+                v[u] = ld_sc(g1 + e % n1 + (int64_t)(e / n1) * n);
+            } else if (e < t1 + t2) {
+                const int f = e - t1;
+                v[u] = ld_sc(g2 + map[f % n2] + (int64_t)(f / n2) * n);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = e0 + threadIdx.x + u * NT;
+            if (e < t1) {
+                x1[e % n1 + (e / n1) * ld1] = v[u];
+            } else if (e < t1 + t2) {
+                const int f = e - t1;
+                x2[f % n2 + (f / n2) * ld2] = v[u];
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
 __device__ __forceinline__ cd shfl_cd(cd v, int src) {
@@ -130,12 +163,12 @@ __device__ __forceinline__ void wait_pair(const int* a, int na, const int* b, in
 }
 
 constexpr int QC = kMaxChunk / kWave;   // 64-wide column groups of a chunk
-constexpr int QF = kFold * QC;          // column groups of the folded neighbours
+constexpr int QF = kFoldCols / kWave;   // column groups of the folded neighbour range
 
 // One row of [A1 | A2] x [x1; x2] by one wave, in parts so that the row's
 // loads (independent of the chain) are issued before the wait for its
 // inputs: load_row reads A1 (width w1 <= kMaxChunk) and A2 (width w2 <=
-// kFold kMaxChunk) into registers; row_partial multiplies them with the LDS
+// kFoldCols) into registers; row_partial multiplies them with the LDS
 // copies of x1 and x2, a column range at a time.
 __device__ __forceinline__ void load_row(const cd* A1, int w1, const cd* A2, int w2, cd (&R1)[QC], cd (&R2)[QF]) {
     const int lane = threadIdx.x % kWave;
@@ -151,26 +184,41 @@ __device__ __forceinline__ void load_row(const cd* A1, int w1, const cd* A2, int
     }
 }
 
-// Lane partial sums of one row over part of its columns: A1's (if with1)
-// and A2's columns in [lo, hi); the caller reduces over the wave at the end.
+// Lane partial sums of one row (the caller reduces over the wave at the end):
+// row_partial takes all of A1 and the A2 columns in [lo, hi); row_head the A2
+// columns in [0, hi) with hi <= kMaxChunk, which lie in the first QC groups.
 template <int S>
-__device__ __forceinline__ void row_partial(const cd (&R1)[QC], int w1, const cd* xs1, int o1, int ld1, bool with1,
+__device__ __forceinline__ void row_partial(const cd (&R1)[QC], int w1, const cd* xs1, int o1, int ld1,
                                             const cd (&R2)[QF], int lo, int hi, const cd* xs2, int ld2, int cs,
                                             cd (&acc)[S]) {
     const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int c = 0; c < S; ++c) {
         if (c < cs) {
-            if (with1)
 #pragma unroll
-                for (int q = 0; q < QC; ++q) {
-                    const int col = lane + q * kWave;
-                    if (col < w1) acc[c] = cfma(R1[q], xs1[o1 + col + c * ld1], acc[c]);
-                }
+            for (int q = 0; q < QC; ++q) {
+                const int col = lane + q * kWave;
+                if (col < w1) acc[c] = cfma(R1[q], xs1[o1 + col + c * ld1], acc[c]);
+            }
 #pragma unroll
             for (int q = 0; q < QF; ++q) {
                 const int col = lane + q * kWave;
                 if (col >= lo && col < hi) acc[c] = cfma(R2[q], xs2[col + c * ld2], acc[c]);
+            }
+        }
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void row_head(const cd (&R2)[QF], int hi, const cd* xs2, int ld2, int cs, cd (&acc)[S]) {
+    const int lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        if (c < cs) {
+#pragma unroll
+            for (int q = 0; q < QC; ++q) {
+                const int col = lane + q * kWave;
+                if (col < hi) acc[c] = cfma(R2[q], xs2[col + c * ld2], acc[c]);
             }
         }
     }
@@ -284,15 +332,17 @@ __device__ __forceinline__ void gather_slots(const int64_t* gslot, int64_t g0, i
     for (int q = threadIdx.x; q < bt * cs; q += NT) {
         const int a = q % bt, c = q / bt;
         cd s = base_lds[q];
-        int64_t g = g0;
-        for (; g + 4 <= g1; g += 4) {
-            cd v0 = ld_sc(slots + gslot[g] * nrhs + (int64_t)(c0 + c) * bt + a);
-            cd v1 = ld_sc(slots + gslot[g + 1] * nrhs + (int64_t)(c0 + c) * bt + a);
-            cd v2 = ld_sc(slots + gslot[g + 2] * nrhs + (int64_t)(c0 + c) * bt + a);
-            cd v3 = ld_sc(slots + gslot[g + 3] * nrhs + (int64_t)(c0 + c) * bt + a);
-            s = cadd(cadd(cadd(cadd(s, v0), v1), v2), v3);
+        // GW slot loads in flight per round, added in slot order
+        constexpr int GW = 16;
+        for (int64_t g = g0; g < g1; g += GW) {
+            cd v[GW];
+#pragma unroll
+            for (int u = 0; u < GW; ++u)
+                v[u] = g + u < g1 ? ld_sc(slots + gslot[g + u] * nrhs + (int64_t)(c0 + c) * bt + a) : cmk(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < GW; ++u)
+                if (g + u < g1) s = cadd(s, v[u]);
         }
-        for (; g < g1; ++g) s = cadd(s, ld_sc(slots + gslot[g] * nrhs + (int64_t)(c0 + c) * bt + a));
         st_sc(out + a + (int64_t)(c0 + c) * n, s);
     }
 }
@@ -307,7 +357,7 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
     __shared__ int s_t;
     __shared__ cd bsh[kMaxLeaf * S];
     __shared__ cd xs1[kMaxChunk * S];
-    __shared__ cd xs2[kFold * kMaxChunk * S];
+    __shared__ cd xs2[kFoldCols * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
     int* cntA = wk.flags;
@@ -339,22 +389,26 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
                 if (c0 == 0) {
                     // everything but the newest neighbour chunk is final: stage it
                     // and take its part of the row before waiting for that chunk
-                    stage_segs<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf + d.pc, d.nc, xs2 + d.e_lo, d.w2,
-                                                           wk.ybuf + d.x2 + d.e_lo, d.e_hi - d.e_lo, n, cs);
+                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf + d.pc, d.nc, xs2 + d.l_n, d.w2, wk.ybuf,
+                                                   it.femap + d.e_off, d.e_n, n, cs);
                     __syncthreads();
-                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, true, R2, d.e_lo, d.e_hi, xs2, d.w2, cs, acc);
+                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
                     if (wid == 0 && c >= 1) wait_count(cntB, c - 1, epoch * d.need1);
                     __syncthreads();
                     compiler_fence();
-                    stage_segs<S, kMaxChunk>(xs2 + d.l_lo, d.w2, wk.ybuf + d.x2 + d.l_lo, d.l_hi - d.l_lo, nullptr, 0,
-                                             nullptr, 0, n, cs);
+                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.ybuf + d.l_g, d.l_n, nullptr, 0, nullptr, 0, n, cs);
                     __syncthreads();
-                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, false, R2, d.l_lo, d.l_hi, xs2, d.w2, cs, acc);
+                    if (live) row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
                 } else {
-                    stage_segs<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2,
-                                                           d.w2, wk.ybuf + d.x2 + (int64_t)c0 * n, d.w2, n, cs);
+                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n,
+                                                   d.w2, wk.ybuf + (int64_t)c0 * n, it.femap + d.e_off, d.e_n, n, cs);
+                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.ybuf + d.l_g + (int64_t)c0 * n, d.l_n, nullptr, 0, nullptr, 0,
+                                             n, cs);
                     __syncthreads();
-                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, true, R2, 0, d.w2, xs2, d.w2, cs, acc);
+                    if (live) {
+                        row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
+                        row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
+                    }
                 }
                 if (live) {
                     cd y[S];
@@ -378,7 +432,7 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
     }
     for (int t = role - kRowWorkers * kRowSets;;
          t = take_ticket(wk.tickets, base, &s_t) - kRowWorkers * kRowSets) {
-        if (t >= it.nitems) return;
+        if (t >= it.nfwd) return;
         const int item = it.fwd[t];
         if (item < p.nb) {
             // ---- phase A: r_j = v_j + sum of the far-entry slots of block j
@@ -442,7 +496,7 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
     __shared__ cd ysh[kMaxLeaf * S];
     __shared__ cd ztsh[kMaxLeaf * S];
     __shared__ cd xs1[kMaxChunk * S];
-    __shared__ cd xs2[kFold * kMaxChunk * S];
+    __shared__ cd xs2[kFoldCols * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
     int* cntA = wk.flags + 2 * p.nch + p.nb;
@@ -475,22 +529,26 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
                 if (c0 == 0) {
                     // everything but the newest neighbour chunk is final: stage it
                     // and take its part of the row before waiting for that chunk
-                    stage_segs<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf2 + d.pc, d.nc, xs2 + d.e_lo, d.w2,
-                                                           wk.zbuf + d.x2 + d.e_lo, d.e_hi - d.e_lo, n, cs);
+                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf2 + d.pc, d.nc, xs2 + d.l_n, d.w2, wk.zbuf,
+                                                   it.bemap + d.e_off, d.e_n, n, cs);
                     __syncthreads();
-                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, true, R2, d.e_lo, d.e_hi, xs2, d.w2, cs, acc);
+                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
                     if (wid == 0 && c + 1 < p.nch) wait_count(cntB, c + 1, epoch * d.need1);
                     __syncthreads();
                     compiler_fence();
-                    stage_segs<S, kMaxChunk>(xs2 + d.l_lo, d.w2, wk.zbuf + d.x2 + d.l_lo, d.l_hi - d.l_lo, nullptr, 0,
-                                             nullptr, 0, n, cs);
+                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.zbuf + d.l_g, d.l_n, nullptr, 0, nullptr, 0, n, cs);
                     __syncthreads();
-                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, false, R2, d.l_lo, d.l_hi, xs2, d.w2, cs, acc);
+                    if (live) row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
                 } else {
-                    stage_segs<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2,
-                                                           d.w2, wk.zbuf + d.x2 + (int64_t)c0 * n, d.w2, n, cs);
+                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n,
+                                                   d.w2, wk.zbuf + (int64_t)c0 * n, it.bemap + d.e_off, d.e_n, n, cs);
+                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.zbuf + d.l_g + (int64_t)c0 * n, d.l_n, nullptr, 0, nullptr, 0,
+                                             n, cs);
                     __syncthreads();
-                    if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, true, R2, 0, d.w2, xs2, d.w2, cs, acc);
+                    if (live) {
+                        row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
+                        row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
+                    }
                 }
                 if (live) {
                     cd y[S];
@@ -517,7 +575,7 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
     }
     for (int t = role - kRowWorkers * kRowSets;;
          t = take_ticket(wk.tickets + 1, base, &s_t) - kRowWorkers * kRowSets) {
-        if (t >= it.nitems) return;
+        if (t >= it.nbwd) return;
         const int item = it.bwd[t];
         if (item < p.nb) {
             // ---- phase A: r'_k = D_k^-1 y_k + sum of the far-entry slots of block k
@@ -695,8 +753,9 @@ int sweep_capacity(int device) {
 
 void launch_sweep(bool forward, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs,
                   const SweepWork& w, int epoch, hipStream_t s) {
-    const int G = sweep_grid(it.nitems);
-    const unsigned long long base = (unsigned long long)(epoch - 1) * (unsigned long long)(it.nitems + G);
+    const int64_t nit = forward ? it.nfwd : it.nbwd;
+    const int G = sweep_grid(nit);
+    const unsigned long long base = (unsigned long long)(epoch - 1) * (unsigned long long)(nit + G);
     const bool wide = p.bmax > kWave;
 #define HS_SWEEP(SS, QQ)                                                                                         \
     do {                                                                                                          \

@@ -310,3 +310,57 @@ def test_precond_wide_leaves(env, fill_tol):
         ref = np.empty_like(v)
         ref[perm] = osch.apply(pc, v[perm])
         assert _rel(z, ref) <= TOL
+
+
+@pytest.fixture(scope="module")
+def pair_oracle():
+    wl = _case("pair")
+    hm = ohm.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, 1e-4)
+    return wl, hm, opl.precond_setup(hm, "rcm", 1e-2)
+
+
+@pytest.mark.parametrize("layout", [(64, 64), (128, 256), (100, 300), (384, 1152), (384, 3072)])
+def test_precond_sweep_layouts(env, pair_oracle, layout):
+    # the chunked evaluation of the sweeps must leave the operator unchanged;
+    # small chunks and folds send most entries through the far-entry path
+    hsl, torch, ctx = env
+    wl, hm, pc = pair_oracle
+    H = _gpu_h(env, wl)
+    P = hsl.Precond(ctx, H, "rcm", 1e-2, sweep_chunk=layout[0], sweep_fold_cols=layout[1])
+    rng = np.random.default_rng(6)
+    perm = hm.tree.perm
+    for cols in (1, 3):
+        v = rng.normal(size=(wl.n, cols)) + 1j * rng.normal(size=(wl.n, cols))
+        z = P.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
+        ref = np.empty_like(v)
+        ref[perm] = osch.apply(pc, v[perm])
+        assert _rel(z, ref) <= TOL, (layout, cols)
+
+
+def test_precond_wide_leaves_small_chunks(env):
+    # leaves wider than a wavefront through the far-entry path (one-block chunks)
+    hsl, torch, ctx = env
+    wl = W.make_config("c2", n=2500)
+    wl.leaf_max = 96
+    hm = ohm.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, 1e-4)
+    pc = opl.precond_setup(hm, "rcm", 0.0)
+    H = _gpu_h(env, wl)
+    P = hsl.Precond(ctx, H, "rcm", 0.0, sweep_chunk=96, sweep_fold_cols=96)
+    rng = np.random.default_rng(7)
+    perm = hm.tree.perm
+    for cols in (1, 2):
+        v = rng.normal(size=(wl.n, cols)) + 1j * rng.normal(size=(wl.n, cols))
+        z = P.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
+        ref = np.empty_like(v)
+        ref[perm] = osch.apply(pc, v[perm])
+        assert _rel(z, ref) <= TOL
+
+
+def test_precond_layout_arguments(env, c1_oracle):
+    hsl, torch, ctx = env
+    wl, hm = c1_oracle
+    H = _gpu_h(env, wl)
+    for bad in ((385, 0), (-1, 0), (0, 3073), (0, -2), (128, 64)):
+        with pytest.raises(hsl.HschurError) as ei:
+            hsl.Precond(ctx, H, "rcm", 1e-2, sweep_chunk=bad[0], sweep_fold_cols=bad[1])
+        assert ei.value.status == hsl.HS_EINVAL
