@@ -210,10 +210,11 @@ struct hs_hmatrix {
     hs::NearTask* d_near_tasks = nullptr;
     cd* d_near = nullptr;
     int64_t* d_near_slot = nullptr;
-    hs::AcaTask* d_far_geom = nullptr;
-    int* d_far_rank = nullptr;
-    cd** d_far_ptr = nullptr;
-    int64_t* d_far_slot = nullptr;
+    // the far blocks again, largest r (m + n) first, for the matvec launch
+    hs::AcaTask* d_mv_geom = nullptr;
+    int* d_mv_rank = nullptr;
+    cd** d_mv_ptr = nullptr;
+    int64_t* d_mv_slot = nullptr;
     int* d_far_piv = nullptr;
     int64_t* d_gptr = nullptr;
     hs::GatherEnt* d_gent = nullptr;
@@ -448,7 +449,7 @@ void matvec_tree(hs_context* ctx, const hs_hmatrix* H, const cd* x, cd* y, int n
                            slots, s);
     });
     timed(ctx, HS_KT_FAR_MV, s, [&] {
-        hs::launch_far_mv(H->d_far_geom, H->d_far_rank, H->d_far_ptr, H->d_far_slot, (int64_t)H->far_geom.size(), x,
+        hs::launch_far_mv(H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr, H->d_mv_slot, (int64_t)H->far_geom.size(), x,
                           H->n, nrhs, slots, s);
     });
     hs::launch_gather(H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, H->n, nrhs, y, s);
@@ -719,9 +720,6 @@ int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double 
             fb += (int64_t)H->far.rank[b] * (H->far_geom[b].m + H->far_geom[b].n);
         }
         H->bytes_far = fb * 16;
-        H->d_far_geom = o.upload(H->far_geom, s);
-        H->d_far_rank = o.upload(H->far.rank, s);
-        H->d_far_ptr = o.upload(H->far.ptr, s);
         // matvec slots and per-leaf gather lists (fixed summation order)
         std::vector<std::vector<hs::GatherEnt>> lists(t.nb());
         std::vector<int64_t> near_slot(H->near_tasks.size()), far_slot(H->far_geom.size());
@@ -760,7 +758,31 @@ int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double 
             gptr[l + 1] = (int64_t)gent.size();
         }
         H->d_near_slot = o.upload(near_slot, s);
-        H->d_far_slot = o.upload(far_slot, s);
+        {
+            // the matvec takes the far blocks largest first so the long ones do
+            // not trail the launch
+            const int64_t nf = p.n_far();
+            std::vector<int64_t> ord(nf);
+            for (int64_t e = 0; e < nf; ++e) ord[e] = e;
+            auto cost = [&](int64_t e) {
+                return (int64_t)H->far.rank[e] * (H->far_geom[e].m + H->far_geom[e].n);
+            };
+            std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
+            std::vector<hs::AcaTask> mg(nf);
+            std::vector<int> mr(nf);
+            std::vector<cd*> mp(nf);
+            std::vector<int64_t> ms(nf);
+            for (int64_t q = 0; q < nf; ++q) {
+                mg[q] = H->far_geom[ord[q]];
+                mr[q] = H->far.rank[ord[q]];
+                mp[q] = H->far.ptr[ord[q]];
+                ms[q] = far_slot[ord[q]];
+            }
+            H->d_mv_geom = o.upload(mg, s);
+            H->d_mv_rank = o.upload(mr, s);
+            H->d_mv_ptr = o.upload(mp, s);
+            H->d_mv_slot = o.upload(ms, s);
+        }
         H->d_gptr = o.upload(gptr, s);
         H->d_gent = o.upload(gent, s);
         hip_check(hipStreamSynchronize(s), "stream sync");
