@@ -23,7 +23,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_kernels_c2_hbm_traffic.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_c2_sphere_ellipsoid_n20000.md")
 KERNEL_SOURCES = ("paper_2111_13483_amd/csrc/kernels_sweep.hip", "paper_2111_13483_amd/csrc/kernels_solve.hip",
                   "paper_2111_13483_amd/csrc/kernels.h", "paper_2111_13483_amd/csrc/devcommon.h")
 # the instrumented launches and their kernels' names
@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--summarize-stats", metavar="DIR", help="summarise a rocprofv3 --stats run and exit")
     ap.add_argument("--out", help="summary file written by --summarize-*")
     ap.add_argument("--command", default="", help="command line recorded in the summary")
+    ap.add_argument("--write-workload", metavar="PATH",
+                    help="write the workload (points, first right-hand side) for the hs_bench driver and exit")
     return ap.parse_args()
 
 
@@ -98,7 +100,8 @@ def summarize_pmc(fetch_dir, write_dir, out, command, copy_bytes):
     f_scale = copy_bytes / (cf * 1024.0)
     w_scale = copy_bytes / (cw * 1024.0)
     af, aw = _per_kernel(fetch), _per_kernel(write)
-    lines = [f"# HBM traffic per launch, sphere + ellipsoid N = 20,000 (bench.py default workload)", "",
+    lines = ["# HBM traffic per launch, sphere + ellipsoid N = 20,000 (one step through the C-ABI driver hs_bench)",
+             "",
              "Commands (FETCH_SIZE run, then WRITE_SIZE run):", "", "```", command, "```", "",
              f"Calibration: one device-to-device copy of {copy_bytes} bytes reads FETCH_SIZE = {cf:.0f} KiB and "
              f"WRITE_SIZE = {cw:.0f} KiB; scale factors {f_scale:.4f} (fetch) and {w_scale:.4f} (write).", "",
@@ -141,6 +144,21 @@ def summarize_stats(d, out, command, top=25):
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
+
+
+def write_workload(args):
+    """Binary workload for the C-ABI driver: header (n, k, self_h, leaf_max,
+    restart, aca_tol, fill_tol, tol), points n x 3, one right-hand side."""
+    import struct
+    import workloads as W
+    wl = W.make_config(args.workload, n=args.n or None, nrhs=1)
+    if args.workload == "c2":
+        wl.restart = 50
+    with open(args.write_workload, "wb") as f:
+        f.write(struct.pack("<qddiiddd", wl.n, wl.k, wl.self_h, wl.leaf_max, wl.restart, wl.aca_tol, wl.fill_tol,
+                            wl.tol))
+        f.write(np.ascontiguousarray(wl.points, dtype=np.float64).tobytes())
+        f.write(np.ascontiguousarray(wl.rhs[:, 0], dtype=np.complex128).tobytes())
 
 
 def committed_traffic():
@@ -265,6 +283,9 @@ def main():
         return
     if args.summarize_stats:
         summarize_stats(args.summarize_stats, args.out, args.command)
+        return
+    if args.write_workload:
+        write_workload(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))

@@ -14,6 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhschur.so")
+BENCH_EXE = os.path.join(HERE, "hs_bench")
 BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
@@ -61,6 +62,11 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, OUT)
+    # C-ABI-only driver for hardware-counter runs (links the library by rpath)
+    tmp = BENCH_EXE + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17", "-I" + INCLUDE, os.path.join(CSRC, "hs_bench.cpp"),
+          "-o", tmp, "-L" + HERE, "-lhschur", "-Wl,-rpath,$ORIGIN"])
+    os.replace(tmp, BENCH_EXE)
     return OUT
 
 
