@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--summarize-stats", metavar="DIR", help="summarise a rocprofv3 --stats run and exit")
     ap.add_argument("--out", help="summary file written by --summarize-*")
     ap.add_argument("--command", default="", help="command line recorded in the summary")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving run instead of the step benchmark: resident geometries, Poisson request arrivals")
+    ap.add_argument("--serve-rates", default="5,20,80", help="request arrival rates per second")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="span of arrivals per rate")
     ap.add_argument("--write-workload", metavar="PATH",
                     help="write the workload (points, first right-hand side) for the hs_bench driver and exit")
     return ap.parse_args()
@@ -159,6 +163,74 @@ def write_workload(args):
                             wl.tol))
         f.write(np.ascontiguousarray(wl.points, dtype=np.float64).tobytes())
         f.write(np.ascontiguousarray(wl.rhs[:, 0], dtype=np.complex128).tobytes())
+
+
+def serve(args):
+    """Serving: four geometries resident on the GPU (admitted by device
+    footprint); requests of 1-8 right-hand-side columns (half plane waves,
+    half port vectors) arrive as a Poisson process and are batched per
+    geometry, oldest request first, up to 16 columns per solve. Reports
+    arrival-to-completion latency percentiles and RHS solves/s per rate;
+    progress goes to stderr, one line per batch."""
+    import torch
+    import paper_2111_13483_amd as hsl
+    import workloads as W
+
+    ctx = hsl.Context(0)
+    specs = [("c2", 8000), ("c2", 5000), ("c1", 4000), ("plate", 3000)]
+    geos, t_setup = [], []
+    srv = hsl.Server(ctx, 64 << 30, max_batch_cols=16, restart=50, tol=1e-6, max_iters=5000)
+    for name, n in specs:
+        wl = W.make_config(name, n=n)
+        t0 = time.perf_counter()
+        H = hsl.HMatrix(ctx, wl.points, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol)
+        P = hsl.Precond(ctx, H, "rcm", wl.fill_tol)
+        torch.cuda.synchronize()
+        t_setup.append(time.perf_counter() - t0)
+        geos.append((wl, srv.admit(H, P), H, P))
+        print(f"serve: geometry {name} N={wl.n} ready in {t_setup[-1]:.2f} s", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(5)
+    out = {"metric": "serving latency p50/p99 (arrival to completion) and RHS solves/s", "unit": "s, RHS/s",
+           "data": "synthetic", "n_gpus": 1, "dtype": "c128",
+           "config": {"workload": "resident " + ", ".join(f"{a} N={b}" for a, b in specs),
+                      "columns_per_request": "uniform 1-8", "max_batch_cols": 16, "solver": "GMRES(50) to 1e-6"},
+           "build_and_setup_s": t_setup, "rates": []}
+    for rate in [float(r) for r in args.serve_rates.split(",")]:
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.serve_seconds * 3) + 8))
+        arr = arr[arr <= args.serve_seconds]
+        reqs = []
+        for a in arr:
+            gi = int(rng.integers(0, len(geos)))
+            wl = geos[gi][0]
+            nc = int(rng.integers(1, 9))
+            cols = [W.plane_wave(wl.points, wl.k, rng) if rng.random() < 0.5 else W.port_vector(wl.n, rng)
+                    for _ in range(nc)]
+            reqs.append((a, gi, torch.as_tensor(np.stack(cols, axis=1), device="cuda")))
+        torch.cuda.synchronize()
+        t0 = hsl.Server.clock()
+        ids, i, batches = [], 0, 0
+        while i < len(reqs) or srv.pending()[0]:
+            now = hsl.Server.clock() - t0
+            while i < len(reqs) and reqs[i][0] <= now:
+                ids.append(srv.submit(geos[reqs[i][1]][1], reqs[i][2], t0 + reqs[i][0]))
+                i += 1
+            if srv.pending()[0]:
+                cols = srv.step()
+                batches += 1
+                print(f"serve: rate {rate:g} batch {batches} columns {cols} at {hsl.Server.clock() - t0:.2f} s",
+                      file=sys.stderr, flush=True)
+            elif i < len(reqs):
+                time.sleep(max(0.0, reqs[i][0] - (hsl.Server.clock() - t0)))
+        st = [srv.request(r) for r in ids]
+        lat = np.array([s["t_done"] - s["t_arrival"] for s in st])
+        ncol = sum(s["ncols"] for s in st)
+        span = max(s["t_done"] for s in st) - t0
+        out["rates"].append({"rate_per_s": rate, "requests": len(st), "columns": ncol, "batches": batches,
+                             "latency_p50_s": float(np.percentile(lat, 50)),
+                             "latency_p99_s": float(np.percentile(lat, 99)),
+                             "rhs_per_s": ncol / span, "all_converged": all(s["converged"] for s in st),
+                             "max_relres": max(s["relres"] for s in st)})
+    print(json.dumps(out), flush=True)
 
 
 def committed_traffic():
@@ -290,6 +362,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.serve:
+        serve(args)
+        return
     import torch
     import paper_2111_13483_amd as hsl
     import workloads as W

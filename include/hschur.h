@@ -246,6 +246,52 @@ int32_t hs_timing_end(hs_context* ctx, hs_kernel_times* out);
 int32_t hs_hmatrix_export(const hs_hmatrix* H, int32_t what, void* dst, int64_t cap, int64_t* needed);
 int32_t hs_precond_export(const hs_precond* P, int32_t what, void* dst, int64_t cap, int64_t* needed);
 
+/* ---- serving -----------------------------------------------------------------
+ * Resident H-matrices and preconditioners on one context, admitted by their
+ * device footprint (hs_query_*.bytes_device; an H-matrix shared by several
+ * preconditioners counts once); requests of right-hand-side columns are
+ * batched per geometry into one multi-column hs_solve (Sec. 5 solves each
+ * right-hand side on its own; batching shares every matrix read, the columns
+ * stay independent Krylov spaces).
+ *  hs_server_create: budget in bytes, max_batch_cols >= 1, solve options used
+ *    for every batch. The context must outlive the server.
+ *  hs_server_admit: H (and P, or NULL for unpreconditioned) become geometry
+ *    number *geometry; HS_ENOMEM when the footprint exceeds what is left of
+ *    the budget. The handles must outlive the server.
+ *  hs_server_submit: b and x device, N x ncols complex128 in the caller's
+ *    order, owned by the caller until the request is served; t_arrival on
+ *    the hs_server_clock() time base (seconds). Returns a request number.
+ *  hs_server_step: serves one batch: the geometry of the oldest pending
+ *    request (earliest arrival, then submission), and its pending requests
+ *    in arrival order while the batch holds at most max_batch_cols columns
+ *    (a larger first request runs alone). Synchronous; *columns_served = 0
+ *    when nothing is pending. A column that misses tol is not an error: its
+ *    request's stats say so.
+ *  hs_server_request: state of a request (done, iterations, residual,
+ *    arrival and completion times). */
+typedef struct hs_server hs_server;
+typedef struct {
+    int32_t geometry;
+    int32_t ncols;
+    int32_t iters;        /* largest inner-step count over the request's columns */
+    int32_t converged;    /* 1 if every column met tol */
+    double  relres;       /* largest true relative residual over the columns */
+    double  t_arrival;    /* as submitted */
+    double  t_done;       /* completion of the batch that served it */
+    int32_t done;
+    int32_t pad;
+} hs_request_stats;
+double  hs_server_clock(void);
+int32_t hs_server_create(hs_context* ctx, int64_t device_budget_bytes, int32_t max_batch_cols,
+                         const hs_solve_opts* opts, hs_server** out);
+int32_t hs_server_admit(hs_server* s, const hs_hmatrix* H, const hs_precond* P, int32_t* geometry);
+int32_t hs_server_submit(hs_server* s, int32_t geometry, const void* b, void* x, int32_t ncols, double t_arrival,
+                         int64_t* request);
+int32_t hs_server_step(hs_server* s, int32_t* columns_served);
+int32_t hs_server_pending(const hs_server* s, int64_t* requests, int64_t* columns);
+int32_t hs_server_request(const hs_server* s, int64_t request, hs_request_stats* out);
+void    hs_server_destroy(hs_server* s);
+
 /* ---- errors ----------------------------------------------------------------- */
 const char* hs_status_string(int32_t status);
 const char* hs_last_error(void);

@@ -63,6 +63,15 @@ class Info(ctypes.Structure):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
+class RequestStats(ctypes.Structure):
+    _fields_ = [("geometry", ctypes.c_int32), ("ncols", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("relres", ctypes.c_double), ("t_arrival", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("done", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "pad"}
+
+
 class KernelTimes(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
 
@@ -102,6 +111,14 @@ def load(path: str = LIB_PATH):
         "hs_precond_apply": (i32, [vp, vp, vp, vp, i64]),
         "hs_hmatrix_export": (i32, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
         "hs_precond_export": (i32, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
+        "hs_server_clock": (dbl, []),
+        "hs_server_create": (i32, [vp, i64, i32, ctypes.POINTER(SolveOpts), pvp]),
+        "hs_server_admit": (i32, [vp, vp, vp, ctypes.POINTER(i32)]),
+        "hs_server_submit": (i32, [vp, i32, vp, vp, i32, dbl, ctypes.POINTER(i64)]),
+        "hs_server_step": (i32, [vp, ctypes.POINTER(i32)]),
+        "hs_server_pending": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "hs_server_request": (i32, [vp, i64, ctypes.POINTER(RequestStats)]),
+        "hs_server_destroy": (None, [vp]),
         "hs_timing_begin": (i32, [vp]),
         "hs_timing_end": (i32, [vp, ctypes.POINTER(KernelTimes)]),
         "hs_status_string": (ctypes.c_char_p, [i32]),
@@ -119,7 +136,9 @@ EXPORTED = (
     "hs_context_create", "hs_context_set_stream", "hs_context_destroy", "hs_plan_create", "hs_plan_query",
     "hs_plan_destroy", "hs_plan_export", "hs_h_build", "hs_query_hmatrix", "hs_hmatrix_destroy", "hs_precond_setup",
     "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_precond_apply", "hs_hmatrix_export",
-    "hs_precond_export", "hs_timing_begin", "hs_timing_end", "hs_status_string", "hs_last_error",
+    "hs_precond_export", "hs_timing_begin", "hs_timing_end", "hs_server_clock", "hs_server_create",
+    "hs_server_admit", "hs_server_submit", "hs_server_step", "hs_server_pending", "hs_server_request",
+    "hs_server_destroy", "hs_status_string", "hs_last_error",
 )
 
 KT_NAMES = ("sweep_fwd", "sweep_bwd", "near_mv", "far_mv")
@@ -328,6 +347,69 @@ def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol
     x = x.t()
     stats = [Stats(st[i].iters, bool(st[i].converged), st[i].relres) for i in range(s)]
     return (x.reshape(-1) if b.dim() == 1 else x), stats
+
+
+class Server:
+    """Resident geometries admitted by device footprint; request columns are
+    batched per geometry into multi-column solves (hs_server_*)."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_batch_cols: int = 32, restart: int = 30,
+                 tol: float = 1e-6, max_iters: int = 0):
+        self.ctx = ctx
+        self._opts = SolveOpts(0, restart, tol, max_iters, 0)
+        h = ctypes.c_void_p()
+        _check(_lib.hs_server_create(ctx._h, int(budget_bytes), int(max_batch_cols), ctypes.byref(self._opts),
+                                     ctypes.byref(h)))
+        self._h = h
+        self._keep = {}     # request -> (b, x) device buffers, alive until served
+        self._geo = []
+
+    @staticmethod
+    def clock() -> float:
+        return float(load().hs_server_clock())
+
+    def admit(self, H: HMatrix, P: Precond | None) -> int:
+        g = ctypes.c_int32()
+        _check(_lib.hs_server_admit(self._h, H._h, P._h if P is not None else None, ctypes.byref(g)))
+        self._geo.append((H, P))
+        return g.value
+
+    def submit(self, geometry: int, b, t_arrival: float) -> int:
+        torch = _torch()
+        H = self._geo[geometry][0]
+        bc, s = _dev_c128(b, H.n)
+        x = torch.empty_like(bc)
+        r = ctypes.c_int64()
+        _check(_lib.hs_server_submit(self._h, geometry, ctypes.c_void_p(bc.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                     s, float(t_arrival), ctypes.byref(r)))
+        self._keep[r.value] = (bc, x, b.dim() == 1)
+        return r.value
+
+    def step(self) -> int:
+        c = ctypes.c_int32()
+        _check(_lib.hs_server_step(self._h, ctypes.byref(c)))
+        return c.value
+
+    def pending(self):
+        r, c = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.hs_server_pending(self._h, ctypes.byref(r), ctypes.byref(c)))
+        return r.value, c.value
+
+    def request(self, r: int) -> dict:
+        st = RequestStats()
+        _check(_lib.hs_server_request(self._h, r, ctypes.byref(st)))
+        return st.as_dict()
+
+    def result(self, r: int):
+        """x of a served request (caller order, N or N x ncols)."""
+        bc, x, vec = self._keep[r]
+        x = x.t()
+        return x.reshape(-1) if vec else x
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hs_server_destroy(self._h)
+            self._h = None
 
 
 # C-ABI style aliases

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -443,16 +444,18 @@ struct MatvecWs {
     cd* slots = nullptr;
 };
 
-void matvec_tree(hs_context* ctx, const hs_hmatrix* H, const cd* x, cd* y, int nrhs, cd* slots, hipStream_t s) {
+// mk selects the columns computed (all for the public entry points)
+void matvec_tree(hs_context* ctx, const hs_hmatrix* H, const cd* x, cd* y, int nrhs, cd* slots, hipStream_t s,
+                 const hs::ColMask& mk) {
     timed(ctx, HS_KT_NEAR_MV, s, [&] {
-        hs::launch_near_mv(H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near, x, H->n, nrhs,
-                           slots, s);
+        hs::launch_near_mv(mk, H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near, x, H->n,
+                           nrhs, slots, s);
     });
     timed(ctx, HS_KT_FAR_MV, s, [&] {
-        hs::launch_far_mv(H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr, H->d_mv_slot, (int64_t)H->far_geom.size(), x,
+        hs::launch_far_mv(mk, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr, H->d_mv_slot, (int64_t)H->far_geom.size(), x,
                           H->n, nrhs, slots, s);
     });
-    hs::launch_gather(H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, H->n, nrhs, y, s);
+    hs::launch_gather(mk, H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, H->n, nrhs, y, s);
 }
 
 struct SweepWs {
@@ -460,11 +463,16 @@ struct SweepWs {
     int epoch = 0;
 };
 
-void apply_tree(hs_context* ctx, const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, hipStream_t s) {
+void apply_tree(hs_context* ctx, const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, hipStream_t s,
+                const hs::ColMask& mk) {
     ws.epoch += 1;
-    timed(ctx, HS_KT_SWEEP_FWD, s, [&] { hs::launch_sweep(true, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s); });
-    timed(ctx, HS_KT_SWEEP_BWD, s, [&] { hs::launch_sweep(false, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s); });
+    timed(ctx, HS_KT_SWEEP_FWD, s,
+          [&] { hs::launch_sweep(true, mk, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s); });
+    timed(ctx, HS_KT_SWEEP_BWD, s,
+          [&] { hs::launch_sweep(false, mk, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s); });
 }
+
+const hs::ColMask kAllCols{nullptr, 0, 0};
 
 SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
     SweepWs sw;
@@ -1536,7 +1544,7 @@ int32_t hs_matvec(hs_context* ctx, const hs_hmatrix* H, const void* x, void* y, 
         cd* yt = w.get<cd>(n * nrhs);
         cd* slots = w.get<cd>(H->slot_total * nrhs);
         hs::launch_permute(static_cast<const cd*>(x), xt, H->d_perm, n, nrhs, true, s);
-        matvec_tree(ctx, H, xt, yt, (int)nrhs, slots, s);
+        matvec_tree(ctx, H, xt, yt, (int)nrhs, slots, s, kAllCols);
         hs::launch_permute(yt, static_cast<cd*>(y), H->d_perm, n, nrhs, false, s);
         hip_check(hipGetLastError(), "matvec launches");
         hip_check(hipStreamSynchronize(s), "stream sync");
@@ -1559,7 +1567,7 @@ int32_t hs_precond_apply(hs_context* ctx, const hs_precond* P, const void* v, vo
         cd* zt = w.get<cd>(n * nrhs);
         SweepWs sw = make_sweep_ws(w, P, (int)nrhs, s);
         hs::launch_permute(static_cast<const cd*>(v), vt, P->H->d_perm, n, nrhs, true, s);
-        apply_tree(ctx, P, vt, zt, (int)nrhs, sw, s);
+        apply_tree(ctx, P, vt, zt, (int)nrhs, sw, s, kAllCols);
         hs::launch_permute(zt, static_cast<cd*>(z), P->H->d_perm, n, nrhs, false, s);
         hip_check(hipGetLastError(), "apply launches");
         hip_check(hipStreamSynchronize(s), "stream sync");
@@ -1622,15 +1630,18 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         hs::launch_permute(static_cast<const cd*>(b), bt, H->d_perm, n, ns, true, s);
         hs::launch_col_norms(bt, n, ns, npart, nchunk, s);
         hs::launch_cycle_start(bt, V, n, g, m, npart, nchunk, st, n, ns, true, s);
-        auto precond = [&](const cd* in, cd* outv) {
-            if (P) apply_tree(ctx, P, in, outv, ns, sw, s);
+        // inside a cycle only the columns still stepping are computed; at its end
+        // those that stepped in it
+        const hs::ColMask active{st, 1, 0}, stepped{st, 2, 0};
+        auto precond = [&](const cd* in, cd* outv, const hs::ColMask& mk) {
+            if (P) apply_tree(ctx, P, in, outv, ns, sw, s, mk);
             else hip_check(hipMemcpyAsync(outv, in, sizeof(cd) * n * ns, hipMemcpyDeviceToDevice, s), "D2D");
         };
         const int poll = 4;
         for (;;) {
             for (int j = 0; j < m; ++j) {
-                precond(V + j * vstride, tmp);
-                matvec_tree(ctx, H, tmp, wv, ns, slots, s);
+                precond(V + j * vstride, tmp, active);
+                matvec_tree(ctx, H, tmp, wv, ns, slots, s, active);
                 hs::launch_dots(V, n, vstride, j + 1, wv, n, ns, st, partial, nchunk, s);
                 hs::launch_basis_update(V, n, vstride, j + 1, partial, nchunk, wv, n, ns, st, Hh, ldh, m + 1, j, false,
                                         nullptr, s);
@@ -1649,9 +1660,9 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
             }
             hs::launch_lsq(Hh, ldh, m, g, y, st, ns, s);
             hs::launch_combine(V, n, vstride, y, m, tmp, n, ns, st, s);
-            precond(tmp, wv);
+            precond(tmp, wv, stepped);
             hs::launch_axpy_x(xt, wv, n, ns, st, s);
-            matvec_tree(ctx, H, xt, tmp, ns, slots, s);
+            matvec_tree(ctx, H, xt, tmp, ns, slots, s, stepped);
             hs::launch_residual(bt, tmp, r, n, ns, npart, nchunk, s);
             hs::launch_cycle_end(npart, nchunk, st, ns, s);
             hip_check(hipGetLastError(), "cycle launches");
@@ -1681,5 +1692,195 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         return set_error(e);
     }
 }
+
+// ---- serving ------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct hs_server {
+    hs_context* ctx = nullptr;
+    int64_t budget = 0, used = 0;
+    int32_t max_cols = 32;
+    hs_solve_opts opts{};
+    struct Geometry {
+        const hs_hmatrix* H;
+        const hs_precond* P;
+    };
+    std::vector<Geometry> geos;
+    std::vector<const hs_hmatrix*> counted_h;
+    struct Request {
+        int32_t geometry, ncols;
+        const cd* b;
+        cd* x;
+        hs_request_stats st;
+    };
+    std::vector<Request> reqs;
+    std::vector<int64_t> pending;   // request ids in submission order
+};
+
+namespace {
+double server_clock() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+extern "C" {
+
+double hs_server_clock(void) { return server_clock(); }
+
+int32_t hs_server_create(hs_context* ctx, int64_t device_budget_bytes, int32_t max_batch_cols,
+                         const hs_solve_opts* opts, hs_server** out) {
+    try {
+        if (!ctx || !opts || !out) fail(HS_EINVAL, "NULL argument");
+        *out = nullptr;
+        if (device_budget_bytes <= 0) fail(HS_EINVAL, "device budget must be positive");
+        if (max_batch_cols < 1) fail(HS_EINVAL, "max_batch_cols must be >= 1");
+        auto* s = new hs_server;
+        s->ctx = ctx;
+        s->budget = device_budget_bytes;
+        s->max_cols = max_batch_cols;
+        s->opts = *opts;
+        *out = s;
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+int32_t hs_server_admit(hs_server* s, const hs_hmatrix* H, const hs_precond* P, int32_t* geometry) {
+    try {
+        if (!s || !H || !geometry) fail(HS_EINVAL, "NULL argument");
+        if (P && P->H != H) fail(HS_EINVAL, "the preconditioner belongs to another H-matrix");
+        int64_t add = P ? P->own.bytes : 0;
+        const bool h_new = std::find(s->counted_h.begin(), s->counted_h.end(), H) == s->counted_h.end();
+        if (h_new) add += H->own.bytes;
+        if (s->used + add > s->budget)
+            fail(HS_ENOMEM, "admission refused: the geometry's device footprint exceeds the remaining budget");
+        s->used += add;
+        if (h_new) s->counted_h.push_back(H);
+        s->geos.push_back({H, P});
+        *geometry = (int32_t)s->geos.size() - 1;
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+int32_t hs_server_submit(hs_server* s, int32_t geometry, const void* b, void* x, int32_t ncols, double t_arrival,
+                         int64_t* request) {
+    try {
+        if (!s || !b || !x || !request) fail(HS_EINVAL, "NULL argument");
+        if (geometry < 0 || geometry >= (int32_t)s->geos.size()) fail(HS_EINVAL, "unknown geometry");
+        if (ncols < 1) fail(HS_EINVAL, "ncols must be >= 1");
+        hs_server::Request r{};
+        r.geometry = geometry;
+        r.ncols = ncols;
+        r.b = static_cast<const cd*>(b);
+        r.x = static_cast<cd*>(x);
+        r.st.geometry = geometry;
+        r.st.ncols = ncols;
+        r.st.t_arrival = t_arrival;
+        s->reqs.push_back(r);
+        *request = (int64_t)s->reqs.size() - 1;
+        s->pending.push_back(*request);
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+int32_t hs_server_step(hs_server* s, int32_t* columns_served) {
+    try {
+        if (!s || !columns_served) fail(HS_EINVAL, "NULL argument");
+        *columns_served = 0;
+        if (s->pending.empty()) return HS_OK;
+        // the oldest pending request decides the geometry; its pending
+        // requests join in arrival order while the batch has room
+        auto older = [&](int64_t p, int64_t q) {
+            const auto &a = s->reqs[p].st, &b = s->reqs[q].st;
+            return a.t_arrival != b.t_arrival ? a.t_arrival < b.t_arrival : p < q;
+        };
+        std::vector<int64_t> order(s->pending);
+        std::stable_sort(order.begin(), order.end(), older);
+        const int32_t g = s->reqs[order[0]].geometry;
+        std::vector<int64_t> batch;
+        int32_t cols = 0;
+        for (int64_t q : order) {
+            const auto& r = s->reqs[q];
+            if (r.geometry != g) continue;
+            if (!batch.empty() && cols + r.ncols > s->max_cols) break;
+            batch.push_back(q);
+            cols += r.ncols;
+        }
+        const hs_hmatrix* H = s->geos[g].H;
+        const hs_precond* P = s->geos[g].P;
+        hs_context* ctx = s->ctx;
+        set_device(ctx);
+        hipStream_t st = ctx->stream;
+        const int64_t n = H->n;
+        Owned w;
+        w.mem = ctx->mem;
+        cd* B = w.get<cd>((size_t)n * cols);
+        cd* X = w.get<cd>((size_t)n * cols);
+        int64_t off = 0;
+        for (int64_t q : batch) {
+            const auto& r = s->reqs[q];
+            hip_check(hipMemcpyAsync(B + off, r.b, sizeof(cd) * n * r.ncols, hipMemcpyDeviceToDevice, st), "D2D");
+            off += n * r.ncols;
+        }
+        std::vector<hs_solve_stats> stats(cols);
+        const int32_t rc = hs_solve(ctx, H, P, B, X, cols, &s->opts, stats.data());
+        if (rc != HS_OK && rc != HS_NOT_CONVERGED) return rc;
+        off = 0;
+        int32_t c0 = 0;
+        for (int64_t q : batch) {
+            auto& r = s->reqs[q];
+            hip_check(hipMemcpyAsync(r.x, X + off, sizeof(cd) * n * r.ncols, hipMemcpyDeviceToDevice, st), "D2D");
+            off += n * r.ncols;
+            r.st.iters = 0;
+            r.st.relres = 0.0;
+            r.st.converged = 1;
+            for (int32_t c = 0; c < r.ncols; ++c) {
+                const auto& cs = stats[c0 + c];
+                r.st.iters = std::max(r.st.iters, cs.iters);
+                r.st.relres = std::max(r.st.relres, cs.relres);
+                r.st.converged &= cs.converged;
+            }
+            c0 += r.ncols;
+        }
+        hip_check(hipStreamSynchronize(st), "stream sync");
+        const double t = server_clock();
+        for (int64_t q : batch) {
+            s->reqs[q].st.t_done = t;
+            s->reqs[q].st.done = 1;
+        }
+        std::vector<int64_t> rest;
+        for (int64_t q : s->pending)
+            if (!s->reqs[q].st.done) rest.push_back(q);
+        s->pending.swap(rest);
+        *columns_served = cols;
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+int32_t hs_server_pending(const hs_server* s, int64_t* requests, int64_t* columns) {
+    if (!s || !requests || !columns) { g_last_error = "NULL argument"; return HS_EINVAL; }
+    *requests = (int64_t)s->pending.size();
+    int64_t c = 0;
+    for (int64_t q : s->pending) c += s->reqs[q].ncols;
+    *columns = c;
+    return HS_OK;
+}
+
+int32_t hs_server_request(const hs_server* s, int64_t request, hs_request_stats* out) {
+    if (!s || !out) { g_last_error = "NULL argument"; return HS_EINVAL; }
+    if (request < 0 || request >= (int64_t)s->reqs.size()) { g_last_error = "unknown request"; return HS_EINVAL; }
+    *out = s->reqs[request].st;
+    return HS_OK;
+}
+
+void hs_server_destroy(hs_server* s) { delete s; }
 
 }  // extern "C"

@@ -13,6 +13,39 @@ enum : int { kErrSingular = 1, kErrNumeric = 2, kErrRankCap = 4, kErrCoincident 
 
 constexpr int kMaxLeaf = 96;       // largest leaf block the dense kernels take (LDS bound)
 
+// Per-column GMRES state on the device.
+struct ColState {
+    double bnorm;         // ||b||
+    double beta;          // norm of the cycle's starting residual
+    double relres;        // true relative residual at the last cycle end
+    double tol;
+    int32_t active;       // 1 while the column takes inner steps in this cycle
+    int32_t steps;        // inner steps in the current cycle
+    int32_t total;        // inner steps overall
+    int32_t done;         // 1 once the column has stopped for good
+    int32_t budget;       // max inner steps overall
+    int32_t fixed;        // 1: ignore the inner tolerance test
+    int32_t pad0, pad1;
+};
+// Which right-hand-side columns a matvec or sweep launch computes: all
+// (mode 0), those still taking steps in the cycle (1: active), or those that
+// took steps in it (2: steps > 0). Skipped columns' outputs are left as they
+// were; every counter of a sweep advances as usual.
+struct ColMask {
+    const ColState* st;
+    int32_t mode;
+    int32_t pad;
+};
+__device__ __forceinline__ bool col_live(const ColMask& m, int c) {
+    if (m.mode == 0) return true;
+    return m.mode == 1 ? m.st[c].active != 0 : m.st[c].steps > 0;
+}
+__device__ __forceinline__ bool cols_live(const ColMask& m, int c0, int cs) {
+    bool any = false;
+    for (int c = 0; c < cs; ++c) any |= col_live(m, c0 + c);
+    return any;
+}
+
 // One stored near block Z_ij (i <= j): b_i x b_j row-major at `off`.
 struct NearTask {
     int64_t off;
@@ -95,12 +128,12 @@ void launch_gemm(const GemmTask* tasks, int64_t ntasks, const cd* A, const cd* B
 // ---- solve ----
 void launch_permute(const cd* src, cd* dst, const int64_t* perm, int64_t n, int64_t nrhs, bool to_tree,
                     hipStream_t s);
-void launch_near_mv(const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cd* Z, const cd* x,
-                    int64_t n, int nrhs, cd* slots, hipStream_t s);
-void launch_far_mv(const AcaTask* geom, const int* rank, cd* const* uv, const int64_t* slot_base, int64_t ntasks,
-                   const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
-void launch_gather(const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb, const cd* slots,
-                   int64_t n, int nrhs, cd* y, hipStream_t s);
+void launch_near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cd* Z,
+                    const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
+void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cd* const* uv, const int64_t* slot_base,
+                   int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
+void launch_gather(const ColMask& mk, const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb,
+                   const cd* slots, int64_t n, int nrhs, cd* y, hipStream_t s);
 // P^-1 v = alpha D^-1 alpha^T v by chunked sweeps. Block rows (elimination
 // order) are grouped into chunks of consecutive rows. With L the unit lower
 // block-triangular factor (L_jk = -alpha_kj^T), Linv_c the inverse of chunk
@@ -224,8 +257,8 @@ static_assert(kRowWorkers * 4 == kMaxChunk, "one point row per wave of the row w
 static_assert(kFoldCols % 64 == 0 && kFoldCols >= kMaxChunk, "fold range in whole wavefront groups");
 // One sweep (forward: v -> y in the work buffers; backward: D^-1 y -> z);
 // the backward launch must follow the forward one of the same epoch.
-void launch_sweep(bool forward, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs,
-                  const SweepWork& w, int epoch, hipStream_t s);
+void launch_sweep(bool forward, const ColMask& mk, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z,
+                  int nrhs, const SweepWork& w, int epoch, hipStream_t s);
 int sweep_grid(int64_t nitems);
 // Workgroups of the sweep kernels that can be resident at once on a device;
 // the row workers spin for the whole launch, so this must exceed
@@ -244,20 +277,6 @@ struct ExpandTask {
 };
 void launch_lr_expand(const ExpandTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s);
 
-// ---- GMRES (per-column state on device) ----
-struct ColState {
-    double bnorm;         // ||b||
-    double beta;          // norm of the cycle's starting residual
-    double relres;        // true relative residual at the last cycle end
-    double tol;
-    int32_t active;       // 1 while the column takes inner steps in this cycle
-    int32_t steps;        // inner steps in the current cycle
-    int32_t total;        // inner steps overall
-    int32_t done;         // 1 once the column has stopped for good
-    int32_t budget;       // max inner steps overall
-    int32_t fixed;        // 1: ignore the inner tolerance test
-    int32_t pad0, pad1;
-};
 void launch_dots(const cd* V, int64_t ldv, int64_t vstride, int nvec, const cd* w, int64_t n, int nrhs,
                  const ColState* st, cd* partial, int nchunk, hipStream_t s);
 void launch_basis_update(const cd* V, int64_t ldv, int64_t vstride, int nvec, const cd* partial, int nchunk,

@@ -34,7 +34,7 @@ __global__ void k_permute(const cd* __restrict__ src, cd* __restrict__ dst, cons
 // partial sums in a fixed order). S right-hand sides per pass.
 template <int S>
 __global__ void __launch_bounds__(NT)
-k_near_mv(const NearTask* __restrict__ tasks, const int64_t* __restrict__ slot_base, const cd* __restrict__ Z,
+k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restrict__ slot_base, const cd* __restrict__ Z,
           const cd* __restrict__ x, int64_t n, int nrhs, cd* __restrict__ slots) {
     constexpr int RU = 4;
     __shared__ cd xi[kMaxLeaf * S], xj[kMaxLeaf * S];
@@ -48,6 +48,7 @@ k_near_mv(const NearTask* __restrict__ tasks, const int64_t* __restrict__ slot_b
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     for (int c0 = 0; c0 < nrhs; c0 += S) {
         const int cs = min(S, nrhs - c0);
+        if (!cols_live(mk, c0, cs)) continue;
         __syncthreads();
         for (int e = tid; e < m * cs; e += NT) xi[e] = x[t.i0 + e % m + (int64_t)(c0 + e / m) * n];
         for (int e = tid; e < nn * cs; e += NT) xj[e] = x[t.j0 + e % nn + (int64_t)(c0 + e / nn) * n];
@@ -120,7 +121,7 @@ k_near_mv(const NearTask* __restrict__ tasks, const int64_t* __restrict__ slot_b
 // terms' loads issued together). S right-hand sides per pass.
 template <int S>
 __global__ void __launch_bounds__(NT)
-k_far_mv(const AcaTask* __restrict__ geom, const int* __restrict__ rank, cd* const* __restrict__ uv,
+k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ rank, cd* const* __restrict__ uv,
          const int64_t* __restrict__ slot_base, const cd* __restrict__ x, int64_t n, int nrhs, cd* __restrict__ slots) {
     constexpr int RU = 4, LG = 8;
     __shared__ cd t12[2 * (kMaxRankCap + LG) * S];
@@ -140,6 +141,7 @@ k_far_mv(const AcaTask* __restrict__ geom, const int* __restrict__ rank, cd* con
     const int len_max = max(m, nn);
     for (int c0 = 0; c0 < nrhs; c0 += S) {
         const int cs = min(S, nrhs - c0);
+        if (!cols_live(mk, c0, cs)) continue;
         __syncthreads();
         for (int l0 = wid; l0 < 2 * r; l0 += NW * RU) {
             cd acc[RU][S];
@@ -216,8 +218,8 @@ k_far_mv(const AcaTask* __restrict__ geom, const int* __restrict__ rank, cd* con
 // y on leaf L = sum of the slots that cover it, in the fixed order of the
 // leaf's gather list (GR entries' loads issued together).
 __global__ void __launch_bounds__(kWave)
-k_gather(const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ gptr, const GatherEnt* __restrict__ gent,
-         const cd* __restrict__ slots, int64_t n, int nrhs, cd* __restrict__ y) {
+k_gather(ColMask mk, const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ gptr,
+         const GatherEnt* __restrict__ gent, const cd* __restrict__ slots, int64_t n, int nrhs, cd* __restrict__ y) {
     constexpr int GR = 8;
     const int64_t L = blockIdx.x;
     const int64_t i0 = leaf_off[L];
@@ -225,6 +227,7 @@ k_gather(const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ gptr,
     const int64_t e0 = gptr[L], e1 = gptr[L + 1];
     for (int e = threadIdx.x; e < b * nrhs; e += kWave) {
         const int a = e % b, c = e / b;
+        if (!col_live(mk, c)) continue;
         cd acc = cmk(0.0, 0.0);
         for (int64_t q = e0; q < e1; q += GR) {
             cd v[GR];
@@ -562,30 +565,31 @@ void launch_permute(const cd* src, cd* dst, const int64_t* perm, int64_t n, int6
     hipLaunchKernelGGL(k_permute, dim3(grid1(n * nrhs)), dim3(NT), 0, s, src, dst, perm, n, nrhs, (int)to_tree);
 }
 
-void launch_near_mv(const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cd* Z, const cd* x, int64_t n,
-                    int nrhs, cd* slots, hipStream_t s) {
+void launch_near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cd* Z,
+                    const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
     if (ntasks == 0) return;
     if (nrhs == 1)
-        hipLaunchKernelGGL(k_near_mv<1>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, slot_base, Z, x, n, nrhs, slots);
+        hipLaunchKernelGGL(k_near_mv<1>, dim3((unsigned)ntasks), dim3(NT), 0, s, mk, tasks, slot_base, Z, x, n, nrhs,
+                           slots);
     else
-        hipLaunchKernelGGL(k_near_mv<SCH>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, slot_base, Z, x, n, nrhs,
+        hipLaunchKernelGGL(k_near_mv<SCH>, dim3((unsigned)ntasks), dim3(NT), 0, s, mk, tasks, slot_base, Z, x, n, nrhs,
                            slots);
 }
 
-void launch_far_mv(const AcaTask* geom, const int* rank, cd* const* uv, const int64_t* slot_base, int64_t ntasks,
-                   const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
+void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cd* const* uv, const int64_t* slot_base,
+                   int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
     if (ntasks == 0) return;
     if (nrhs == 1)
-        hipLaunchKernelGGL(k_far_mv<1>, dim3((unsigned)ntasks), dim3(NT), 0, s, geom, rank, uv, slot_base, x, n, nrhs,
-                           slots);
+        hipLaunchKernelGGL(k_far_mv<1>, dim3((unsigned)ntasks), dim3(NT), 0, s, mk, geom, rank, uv, slot_base, x, n,
+                           nrhs, slots);
     else
-        hipLaunchKernelGGL(k_far_mv<SCH>, dim3((unsigned)ntasks), dim3(NT), 0, s, geom, rank, uv, slot_base, x, n, nrhs,
-                           slots);
+        hipLaunchKernelGGL(k_far_mv<SCH>, dim3((unsigned)ntasks), dim3(NT), 0, s, mk, geom, rank, uv, slot_base, x, n,
+                           nrhs, slots);
 }
 
-void launch_gather(const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb, const cd* slots,
-                   int64_t n, int nrhs, cd* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(kWave), 0, s, leaf_off, gptr, gent, slots, n, nrhs, y);
+void launch_gather(const ColMask& mk, const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb,
+                   const cd* slots, int64_t n, int nrhs, cd* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(kWave), 0, s, mk, leaf_off, gptr, gent, slots, n, nrhs, y);
 }
 
 void launch_dots(const cd* V, int64_t ldv, int64_t vstride, int nvec, const cd* w, int64_t n, int nrhs,

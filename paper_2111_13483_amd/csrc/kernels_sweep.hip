@@ -352,8 +352,8 @@ __device__ __forceinline__ void gather_slots(const int64_t* gslot, int64_t g0, i
 // Forward sweep; S right-hand sides per pass.
 template <int S, int Q>
 __global__ void __launch_bounds__(NT)
-k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, int nrhs, unsigned long long base,
-            int epoch) {
+k_sweep_fwd(ColMask mk, SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, int nrhs,
+            unsigned long long base, int epoch) {
     __shared__ int s_t;
     __shared__ cd bsh[kMaxLeaf * S];
     __shared__ cd xs1[kMaxChunk * S];
@@ -381,22 +381,26 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
                 wait_pair(cntA + c, epoch * d.nblocks, c >= 2 ? cntB + c - 2 : nullptr, epoch * d.need2);
             __syncthreads();
             compiler_fence();
+            bool first = true;   // the first computed pass waits for the newest chunk
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
+                if (!cols_live(mk, c0, cs)) continue;
                 cd acc[S];
 #pragma unroll
                 for (int cc = 0; cc < S; ++cc) acc[cc] = cmk(0.0, 0.0);
-                if (c0 == 0) {
+                if (first) {
                     // everything but the newest neighbour chunk is final: stage it
                     // and take its part of the row before waiting for that chunk
-                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf + d.pc, d.nc, xs2 + d.l_n, d.w2, wk.ybuf,
-                                                   it.femap + d.e_off, d.e_n, n, cs);
+                    first = false;
+                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n,
+                                                   d.w2, wk.ybuf + (int64_t)c0 * n, it.femap + d.e_off, d.e_n, n, cs);
                     __syncthreads();
                     if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
                     if (wid == 0 && c >= 1) wait_count(cntB, c - 1, epoch * d.need1);
                     __syncthreads();
                     compiler_fence();
-                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.ybuf + d.l_g, d.l_n, nullptr, 0, nullptr, 0, n, cs);
+                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.ybuf + d.l_g + (int64_t)c0 * n, d.l_n, nullptr, 0, nullptr, 0,
+                                             n, cs);
                     __syncthreads();
                     if (live) row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
                 } else {
@@ -446,6 +450,7 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
             compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
+                if (!cols_live(mk, c0, cs)) continue;
                 for (int q = tid; q < bj * cs; q += NT) bsh[q] = v[sj + q % bj + (int64_t)(c0 + q / bj) * n];
                 __syncthreads();
                 gather_slots<S>(p.fgslot, p.fgptr[j], p.fgptr[j + 1], wk.slots_f, nrhs, bj, c0, cs, bsh, wk.rbuf + pj,
@@ -474,8 +479,9 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
                     dst[q / NW] = e.dst;
                     const int bo = p.bsize[e.src], bt = p.bsize[e.dst];
                     for (int c0 = 0; c0 < nrhs; c0 += S)
-                        push_one<S, true, Q>(e, p.alpha, wk.ybuf, p.pos[e.src], bo, bt, n, c0, min(S, nrhs - c0),
-                                             wk.slots_f + e.slot * nrhs + (int64_t)c0 * bt);
+                        if (cols_live(mk, c0, min(S, nrhs - c0)))
+                            push_one<S, true, Q>(e, p.alpha, wk.ybuf, p.pos[e.src], bo, bt, n, c0, min(S, nrhs - c0),
+                                                 wk.slots_f + e.slot * nrhs + (int64_t)c0 * bt);
                 }
                 stores_done();
                 if (lane == 0)
@@ -490,8 +496,8 @@ k_sweep_fwd(SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, 
 // Backward sweep; S right-hand sides per pass.
 template <int S, int Q>
 __global__ void __launch_bounds__(NT)
-k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nrhs, unsigned long long base,
-            int epoch) {
+k_sweep_bwd(ColMask mk, SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nrhs,
+            unsigned long long base, int epoch) {
     __shared__ int s_t;
     __shared__ cd ysh[kMaxLeaf * S];
     __shared__ cd ztsh[kMaxLeaf * S];
@@ -521,22 +527,26 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
                 wait_pair(cntA + c, epoch * d.nblocks, c + 2 < p.nch ? cntB + c + 2 : nullptr, epoch * d.need2);
             __syncthreads();
             compiler_fence();
+            bool first = true;   // the first computed pass waits for the newest chunk
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
+                if (!cols_live(mk, c0, cs)) continue;
                 cd acc[S];
 #pragma unroll
                 for (int cc = 0; cc < S; ++cc) acc[cc] = cmk(0.0, 0.0);
-                if (c0 == 0) {
+                if (first) {
                     // everything but the newest neighbour chunk is final: stage it
                     // and take its part of the row before waiting for that chunk
-                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf2 + d.pc, d.nc, xs2 + d.l_n, d.w2, wk.zbuf,
-                                                   it.bemap + d.e_off, d.e_n, n, cs);
+                    first = false;
+                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n,
+                                                   d.w2, wk.zbuf + (int64_t)c0 * n, it.bemap + d.e_off, d.e_n, n, cs);
                     __syncthreads();
                     if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
                     if (wid == 0 && c + 1 < p.nch) wait_count(cntB, c + 1, epoch * d.need1);
                     __syncthreads();
                     compiler_fence();
-                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.zbuf + d.l_g, d.l_n, nullptr, 0, nullptr, 0, n, cs);
+                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.zbuf + d.l_g + (int64_t)c0 * n, d.l_n, nullptr, 0, nullptr, 0,
+                                             n, cs);
                     __syncthreads();
                     if (live) row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
                 } else {
@@ -590,6 +600,7 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
             compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
+                if (!cols_live(mk, c0, cs)) continue;
                 for (int q = tid; q < bk * cs; q += NT) ysh[q] = wk.ybuf[pk + q % bk + (int64_t)(c0 + q / bk) * n];
                 __syncthreads();
                 for (int a0 = wid; a0 < bk; a0 += NW * RB) {
@@ -645,6 +656,7 @@ k_sweep_bwd(SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nr
                     dst[q / NW] = e.dst;
                     const int bo = p.bsize[e.src], bt = p.bsize[e.dst];
                     for (int c0 = 0; c0 < nrhs; c0 += S) {
+                        if (!cols_live(mk, c0, min(S, nrhs - c0))) continue;
                         cd* slot = wk.slots_b + e.slot * nrhs + (int64_t)c0 * bt;
                         if (e.rank < 0)   // column sums over the transposed copy
                             push_one<S, true, Q>(e, p.alpha_t, wk.zbuf, p.pos[e.src], bo, bt, n, c0,
@@ -751,8 +763,8 @@ int sweep_capacity(int device) {
     return mn * cus;
 }
 
-void launch_sweep(bool forward, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z, int nrhs,
-                  const SweepWork& w, int epoch, hipStream_t s) {
+void launch_sweep(bool forward, const ColMask& mk, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z,
+                  int nrhs, const SweepWork& w, int epoch, hipStream_t s) {
     const int64_t nit = forward ? it.nfwd : it.nbwd;
     const int G = sweep_grid(nit);
     const unsigned long long base = (unsigned long long)(epoch - 1) * (unsigned long long)(nit + G);
@@ -760,9 +772,9 @@ void launch_sweep(bool forward, const SweepPlan& p, const SweepItems& it, const 
 #define HS_SWEEP(SS, QQ)                                                                                         \
     do {                                                                                                          \
         if (forward)                                                                                              \
-            hipLaunchKernelGGL((k_sweep_fwd<SS, QQ>), dim3(G), dim3(NT), 0, s, p, it, v, w, nrhs, base, epoch);   \
+            hipLaunchKernelGGL((k_sweep_fwd<SS, QQ>), dim3(G), dim3(NT), 0, s, mk, p, it, v, w, nrhs, base, epoch); \
         else                                                                                                      \
-            hipLaunchKernelGGL((k_sweep_bwd<SS, QQ>), dim3(G), dim3(NT), 0, s, p, it, z, w, nrhs, base, epoch);   \
+            hipLaunchKernelGGL((k_sweep_bwd<SS, QQ>), dim3(G), dim3(NT), 0, s, mk, p, it, z, w, nrhs, base, epoch); \
     } while (0)
     if (nrhs == 1) {
         if (wide) HS_SWEEP(1, 2); else HS_SWEEP(1, 1);
