@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--summarize-stats", metavar="DIR", help="summarise a rocprofv3 --stats run and exit")
     ap.add_argument("--out", help="summary file written by --summarize-*")
     ap.add_argument("--command", default="", help="command line recorded in the summary")
+    ap.add_argument("--mixed", action="store_true",
+                    help="mixed path: FP64 flexible GMRES(20) with inner GMRES(20) on complex64 copies")
     ap.add_argument("--serve", action="store_true",
                     help="serving run instead of the step benchmark: resident geometries, Poisson request arrivals")
     ap.add_argument("--serve-rates", default="5,20,80", help="request arrival rates per second")
@@ -385,13 +387,17 @@ def main():
 
     def step(record):
         t0 = time.perf_counter()
-        H = hsl.HMatrix(ctx, pts, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol)
+        H = hsl.HMatrix(ctx, pts, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol, store_c64=args.mixed)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        P = hsl.Precond(ctx, H, "rcm", wl.fill_tol)
+        P = hsl.Precond(ctx, H, "rcm", wl.fill_tol, mixed=args.mixed)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        x, st = hsl.solve(ctx, H, P, rhs if args.nrhs > 1 else rhs[:, 0], restart=wl.restart, tol=wl.tol)
+        if args.mixed:
+            x, st = hsl.solve(ctx, H, P, rhs if args.nrhs > 1 else rhs[:, 0], restart=20, tol=wl.tol, mixed=True,
+                              inner_steps=20, inner_tol=1e-2)
+        else:
+            x, st = hsl.solve(ctx, H, P, rhs if args.nrhs > 1 else rhs[:, 0], restart=wl.restart, tol=wl.tol)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         record.append({"h_build": t1 - t0, "setup": t2 - t1, "solve": t3 - t2, "step": t3 - t0,
@@ -425,7 +431,9 @@ def main():
         "dtype": "c128", "data": "synthetic",
         "config": {"workload": f"{wl.name}: sphere+ellipsoid N={wl.n}, lambda=0.1, leaf<=64, ACA 1e-4, RCM, "
                                f"fill 1e-2, {nrhs} plane-wave RHS, GMRES({wl.restart}) to 1e-6",
-                   "n": wl.n, "nrhs": nrhs, "path": "plain FP64"},
+                   "n": wl.n, "nrhs": nrhs,
+                   "path": "mixed: FP64 FGMRES(20), inner GMRES(20) to 1e-2 on complex64 copies" if args.mixed
+                   else "plain FP64"},
         "precond_setup_s": float(np.median([r["setup"] for r in rec])),
         "h_build_s": float(np.median([r["h_build"] for r in rec])),
         "solve_s": float(np.median([r["solve"] for r in rec])),

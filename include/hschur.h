@@ -57,8 +57,13 @@ extern "C" {
 #define HS_ORDER_CM         2   /* Cuthill-McKee */
 
 #define HS_PREC_FP64        0   /* complex128 throughout */
+#define HS_PREC_MIXED       1   /* also keep complex64 copies of the apply's matrices (for HS_SOLVE_FGMRES_MIXED) */
 
 #define HS_SOLVE_GMRES      0   /* right-preconditioned restarted GMRES, FP64 */
+#define HS_SOLVE_FGMRES_MIXED 1 /* FP64 flexible GMRES on the FP64 operator; each preconditioning step is an
+                                   inner right-preconditioned GMRES on the complex64 operator copies with the
+                                   complex64 preconditioner copies (vectors and Arnoldi in FP64); needs
+                                   store_c64 at build and HS_PREC_MIXED at setup */
 
 typedef struct hs_context hs_context;
 typedef struct hs_plan    hs_plan;
@@ -72,6 +77,7 @@ typedef struct {
     int32_t leaf_max;     /* octree leaf size: boxes holding more points are split (Sec. 2) */
     double  aca_tol;      /* relative Frobenius tolerance of far-field ACA + re-compression (Eq. 10) */
     int32_t rank_cap;     /* largest ACA rank a far block may reach; 0 = default (256) */
+    int32_t store_c64;    /* 1: also keep complex64 copies of the near and far blocks (mixed solves) */
 } hs_build_opts;
 
 typedef struct {
@@ -93,6 +99,8 @@ typedef struct {
     double  tol;          /* relative residual ||b - Z x|| / ||b|| to reach (Sec. 5 uses 1e-6) */
     int32_t max_iters;    /* cap on inner steps per column; 0 = 5000 */
     int32_t fixed_iters;  /* > 0: run exactly this many inner steps, ignoring tol (parity runs) */
+    int32_t inner_steps;  /* HS_SOLVE_FGMRES_MIXED: steps of each inner solve; 0 = 20 */
+    double  inner_tol;    /* HS_SOLVE_FGMRES_MIXED: relative tolerance ending an inner solve early; 0 = 1e-2 */
 } hs_solve_opts;
 
 typedef struct {

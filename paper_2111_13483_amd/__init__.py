@@ -36,7 +36,8 @@ class HschurError(RuntimeError):
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("leaf_max", ctypes.c_int32), ("aca_tol", ctypes.c_double), ("rank_cap", ctypes.c_int32)]
+    _fields_ = [("leaf_max", ctypes.c_int32), ("aca_tol", ctypes.c_double), ("rank_cap", ctypes.c_int32),
+                ("store_c64", ctypes.c_int32)]
 
 
 class PrecondOpts(ctypes.Structure):
@@ -46,7 +47,8 @@ class PrecondOpts(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("restart", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_iters", ctypes.c_int32), ("fixed_iters", ctypes.c_int32)]
+                ("max_iters", ctypes.c_int32), ("fixed_iters", ctypes.c_int32), ("inner_steps", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):
@@ -253,13 +255,13 @@ def _dev_c128(t, n: int):
 
 class HMatrix:
     def __init__(self, ctx: Context, points, k: float, self_h: float, leaf_max: int, aca_tol: float = 1e-4,
-                 rank_cap: int = 0):
+                 rank_cap: int = 0, store_c64: bool = False):
         torch = _torch()
         pts = points if torch.is_tensor(points) else torch.as_tensor(np.ascontiguousarray(points, dtype=np.float64))
         pts = pts.to(device=f"cuda:{ctx.device}", dtype=torch.float64).contiguous()
         self.ctx = ctx
         self.n = int(pts.shape[0])
-        opts = BuildOpts(leaf_max, aca_tol, rank_cap)
+        opts = BuildOpts(leaf_max, aca_tol, rank_cap, int(bool(store_c64)))
         h = ctypes.c_void_p()
         _check(_lib.hs_h_build(ctx._h, ctypes.c_void_p(pts.data_ptr()), self.n, float(k), float(self_h),
                                ctypes.byref(opts), ctypes.byref(h)))
@@ -293,9 +295,9 @@ class HMatrix:
 
 class Precond:
     def __init__(self, ctx: Context, H: HMatrix, ordering: str = "rcm", fill_tol: float = 1e-2, sweep_chunk: int = 0,
-                 sweep_fold_cols: int = 0):
+                 sweep_fold_cols: int = 0, mixed: bool = False):
         self.ctx, self.H = ctx, H
-        opts = PrecondOpts(ORDER[ordering], float(fill_tol), 0, int(sweep_chunk), int(sweep_fold_cols))
+        opts = PrecondOpts(ORDER[ordering], float(fill_tol), 1 if mixed else 0, int(sweep_chunk), int(sweep_fold_cols))
         h = ctypes.c_void_p()
         _check(_lib.hs_precond_setup(ctx._h, H._h, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
@@ -335,12 +337,14 @@ class Stats:
 
 
 def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol: float = 1e-6,
-          max_iters: int = 0, fixed_iters: int = 0):
-    """Solve Z x = b (right-preconditioned GMRES); returns (x, [Stats per column])."""
+          max_iters: int = 0, fixed_iters: int = 0, mixed: bool = False, inner_steps: int = 0, inner_tol: float = 0.0):
+    """Solve Z x = b: right-preconditioned GMRES, or with mixed=True FP64
+    flexible GMRES whose preconditioning steps are inner GMRES solves on the
+    complex64 copies; returns (x, [Stats per column])."""
     torch = _torch()
     bc, s = _dev_c128(b, H.n)
     x = torch.empty_like(bc)
-    opts = SolveOpts(0, restart, tol, max_iters, fixed_iters)
+    opts = SolveOpts(1 if mixed else 0, restart, tol, max_iters, fixed_iters, inner_steps, inner_tol)
     st = (SolveStats * s)()
     _check(_lib.hs_solve(ctx._h, H._h, P._h if P is not None else None, ctypes.c_void_p(bc.data_ptr()),
                          ctypes.c_void_p(x.data_ptr()), s, ctypes.byref(opts), st), allow_not_converged=True)
@@ -356,7 +360,7 @@ class Server:
     def __init__(self, ctx: Context, budget_bytes: int, max_batch_cols: int = 32, restart: int = 30,
                  tol: float = 1e-6, max_iters: int = 0):
         self.ctx = ctx
-        self._opts = SolveOpts(0, restart, tol, max_iters, 0)
+        self._opts = SolveOpts(0, restart, tol, max_iters, 0, 0, 0.0)
         h = ctypes.c_void_p()
         _check(_lib.hs_server_create(ctx._h, int(budget_bytes), int(max_batch_cols), ctypes.byref(self._opts),
                                      ctypes.byref(h)))

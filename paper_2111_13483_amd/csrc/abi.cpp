@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <map>
 #include <memory>
@@ -116,6 +117,17 @@ void check_device_flag(const int* d_err, hipStream_t s) {
 
 constexpr int64_t kScratchBudget = int64_t(2) << 30;   // bytes of ACA scratch per batch
 
+// complex64 copy of a contiguous complex128 array (count elements), owned by own
+hs::cf* c64_copy(Owned& own, Owned& tmp, const cd* src, int64_t count, hipStream_t s) {
+    hs::cf* dst = own.get<hs::cf>((size_t)std::max<int64_t>(count, 1));
+    constexpr int64_t piece = int64_t(1) << 16;
+    std::vector<hs::PtrCopy> t;
+    for (int64_t o = 0; o < count; o += piece) t.push_back(hs::PtrCopy{src + o, o, std::min(piece, count - o)});
+    hs::PtrCopy* d_t = tmp.upload(t, s);
+    hs::launch_to_c64(d_t, (int64_t)t.size(), dst, s);
+    return dst;
+}
+
 }  // namespace
 
 // Kernel timing for measurement: while enabled, each instrumented launch is
@@ -219,6 +231,10 @@ struct hs_hmatrix {
     int* d_far_piv = nullptr;
     int64_t* d_gptr = nullptr;
     hs::GatherEnt* d_gent = nullptr;
+    // complex64 copies for mixed solves (store_c64)
+    bool c64 = false;
+    hs::cf* d_near32 = nullptr;
+    hs::cf** d_mv_ptr32 = nullptr;
 };
 
 struct hs_precond {
@@ -246,6 +262,10 @@ struct hs_precond {
     int64_t fslot_total = 0, bslot_total = 0;
     hs::SweepPlan sp{};
     hs::SweepItems items{};
+    int64_t alpha_t_elems = 0;
+    // complex64 copies of the apply's matrices (HS_PREC_MIXED)
+    bool c64 = false;
+    hs::SweepPlanT<hs::cf> sp32{};
 };
 
 namespace {
@@ -790,6 +810,28 @@ int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double 
             H->d_mv_rank = o.upload(mr, s);
             H->d_mv_ptr = o.upload(mp, s);
             H->d_mv_slot = o.upload(ms, s);
+            if (opts->store_c64) {
+                Owned tmp;
+                tmp.mem = o.mem;
+                H->d_near32 = c64_copy(o, tmp, H->d_near, H->bytes_near / 16, s);
+                int64_t tot = 0;
+                for (int64_t q = 0; q < nf; ++q) tot += (int64_t)mr[q] * (mg[q].m + mg[q].n);
+                hs::cf* base = o.get<hs::cf>((size_t)std::max<int64_t>(tot, 1));
+                std::vector<hs::PtrCopy> t;
+                std::vector<hs::cf*> mp32(nf, nullptr);
+                int64_t off = 0;
+                for (int64_t q = 0; q < nf; ++q) {
+                    const int64_t cnt = (int64_t)mr[q] * (mg[q].m + mg[q].n);
+                    mp32[q] = base + off;
+                    if (cnt) t.push_back(hs::PtrCopy{mp[q], off, cnt});
+                    off += cnt;
+                }
+                hs::PtrCopy* d_t = tmp.upload(t, s);
+                hs::launch_to_c64(d_t, (int64_t)t.size(), base, s);
+                H->d_mv_ptr32 = o.upload(mp32, s);
+                hip_check(hipStreamSynchronize(s), "stream sync");
+                H->c64 = true;
+            }
         }
         H->d_gptr = o.upload(gptr, s);
         H->d_gent = o.upload(gent, s);
@@ -880,7 +922,7 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         if (!ctx || !H || !opts) fail(HS_EINVAL, "NULL argument");
         if (opts->ordering < 0 || opts->ordering > 2) fail(HS_EINVAL, "unknown ordering");
         if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
-        if (opts->precision != HS_PREC_FP64) fail(HS_EINVAL, "unsupported precision");
+        if (opts->precision != HS_PREC_FP64 && opts->precision != HS_PREC_MIXED) fail(HS_EINVAL, "unsupported precision");
         if (opts->sweep_chunk < 0 || opts->sweep_chunk > hs::kMaxChunk) fail(HS_EINVAL, "sweep_chunk must be in [0, 384]");
         const int32_t chunk_lim = opts->sweep_chunk > 0 ? opts->sweep_chunk : hs::kMaxChunk;
         if (opts->sweep_fold_cols != 0 && (opts->sweep_fold_cols < chunk_lim || opts->sweep_fold_cols > hs::kFoldCols))
@@ -1360,6 +1402,7 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
                     tt += (int64_t)bk * bj;
                 }
             cd* d_at = o.get<cd>(std::max<int64_t>(tt, 1));
+            P->alpha_t_elems = tt;
             hs::CopyTask* d_tc = tmp.upload(tc, s);
             hs::launch_copy_blocks(d_tc, (int64_t)tc.size(), P->d_alpha, d_at, s);
             sp.alpha_t = d_at;
@@ -1475,6 +1518,19 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             P->items.femap = o.upload(femap, s);
             P->items.bemap = o.upload(bemap, s);
         }
+        if (opts->precision == HS_PREC_MIXED) {
+            // the same plan over complex64 copies of every matrix the apply reads
+            static_assert(sizeof(hs::SweepPlanT<hs::cf>) == sizeof(hs::SweepPlan), "plans differ only in types");
+            std::memcpy(static_cast<void*>(&P->sp32), &sp, sizeof(sp));
+            P->sp32.lf = c64_copy(o, tmp, sp.lf, lft, s);
+            P->sp32.lb = c64_copy(o, tmp, sp.lb, lbt, s);
+            P->sp32.mf = c64_copy(o, tmp, sp.mf, mft, s);
+            P->sp32.mb = c64_copy(o, tmp, sp.mb, mbt, s);
+            P->sp32.alpha = c64_copy(o, tmp, sp.alpha, P->alpha_elems, s);
+            P->sp32.alpha_t = c64_copy(o, tmp, sp.alpha_t, P->alpha_t_elems, s);
+            P->sp32.dinv = c64_copy(o, tmp, sp.dinv, P->d_elems, s);
+            P->c64 = true;
+        }
         hip_check(hipStreamSynchronize(s), "stream sync");
         tmp.release();
         hs_info info;
@@ -1579,42 +1635,135 @@ int32_t hs_precond_apply(hs_context* ctx, const hs_precond* P, const void* v, vo
 
 // ---- solve -------------------------------------------------------------------------
 
+}  // extern "C"
+
+namespace {
+
+using ApplyFn = std::function<void(const cd* in, cd* out, const hs::ColMask& mk)>;
+
+// Workspace of a multi-column GMRES(m) (or flexible GMRES(m): Z keeps the
+// preconditioned basis) on tree-order vectors.
+struct GmresWs {
+    int64_t n = 0, vstride = 0, ldh = 0;
+    int ns = 0, m = 0, nchunk = 0;
+    cd *r, *wv, *tmp, *V, *Z, *Hh, *snv, *g, *y, *partial;
+    double *csv, *npart, *inv_hn;
+    hs::ColState* st;
+    void alloc(Owned& w, int64_t n_, int ns_, int m_, bool flexible) {
+        n = n_;
+        ns = ns_;
+        m = m_;
+        nchunk = hs::gmres_nchunk(n);
+        vstride = n * ns;
+        ldh = (int64_t)(m + 1) * m;
+        r = w.get<cd>(n * ns);
+        wv = w.get<cd>(n * ns);
+        tmp = w.get<cd>(n * ns);
+        V = w.get<cd>((size_t)(m + 1) * vstride);
+        Z = flexible ? w.get<cd>((size_t)m * vstride) : nullptr;
+        Hh = w.get<cd>((size_t)ldh * ns);
+        csv = w.get<double>((size_t)m * ns);
+        snv = w.get<cd>((size_t)m * ns);
+        g = w.get<cd>((size_t)(m + 1) * ns);
+        y = w.get<cd>((size_t)m * ns);
+        partial = w.get<cd>((size_t)nchunk * (m + 1) * ns);
+        npart = w.get<double>((size_t)nchunk * ns);
+        inv_hn = w.get<double>(ns);
+        st = w.get<hs::ColState>(ns);
+    }
+};
+
+// Restart cycles of right-preconditioned GMRES(m) from x = 0 (x must hold
+// zeros), with the column states already initialised in G.st. Plain: the
+// preconditioned vector only feeds the matvec and x += P^-1 (V y).
+// Flexible: z_j = precond(v_j) is kept and x += Z y. single: one cycle and
+// no true-residual pass (inner solves). Otherwise cycles run until every
+// column is done; inside a cycle only the columns still stepping are
+// computed, at its end those that stepped.
+void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& matvec, const ApplyFn& precond,
+               bool flexible, bool single, int poll) {
+    const int64_t n = G.n, vs = G.vstride;
+    const int ns = G.ns, m = G.m;
+    const hs::ColMask active{G.st, 1, 0}, stepped{G.st, 2, 0};
+    hip_check(hipMemsetAsync(G.Hh, 0, sizeof(cd) * G.ldh * ns, s), "memset");
+    hs::launch_col_norms(b, n, ns, G.npart, G.nchunk, s);
+    hs::launch_cycle_start(b, G.V, n, G.g, m, G.npart, G.nchunk, G.st, n, ns, true, s);
+    for (;;) {
+        for (int j = 0; j < m; ++j) {
+            cd* zj = flexible ? G.Z + j * vs : G.tmp;
+            precond(G.V + j * vs, zj, active);
+            matvec(zj, G.wv, active);
+            hs::launch_dots(G.V, n, vs, j + 1, G.wv, n, ns, G.st, G.partial, G.nchunk, s);
+            hs::launch_basis_update(G.V, n, vs, j + 1, G.partial, G.nchunk, G.wv, n, ns, G.st, G.Hh, G.ldh, m + 1, j,
+                                    false, nullptr, s);
+            hs::launch_dots(G.V, n, vs, j + 1, G.wv, n, ns, G.st, G.partial, G.nchunk, s);
+            hs::launch_basis_update(G.V, n, vs, j + 1, G.partial, G.nchunk, G.wv, n, ns, G.st, G.Hh, G.ldh, m + 1, j,
+                                    true, G.npart, s);
+            hs::launch_givens(G.Hh, G.ldh, m, j, G.csv, G.snv, G.g, G.npart, G.nchunk, G.st, ns, G.inv_hn, s);
+            hs::launch_scale_next(G.wv, G.V + (j + 1) * vs, n, n, ns, G.st, G.inv_hn, s);
+            if ((j + 1) % poll == 0 && j + 1 < m) {
+                hip_check(hipGetLastError(), "inner launches");
+                std::vector<hs::ColState> cur = download(G.st, ns, s);
+                bool any = false;
+                for (auto& c : cur) any |= c.active != 0;
+                if (!any) break;
+            }
+        }
+        hs::launch_lsq(G.Hh, G.ldh, m, G.g, G.y, G.st, ns, s);
+        if (flexible) {
+            hs::launch_combine(G.Z, n, vs, G.y, m, G.tmp, n, ns, G.st, s);
+            hs::launch_axpy_x(x, G.tmp, n, ns, G.st, s);
+        } else {
+            hs::launch_combine(G.V, n, vs, G.y, m, G.tmp, n, ns, G.st, s);
+            precond(G.tmp, G.wv, stepped);
+            hs::launch_axpy_x(x, G.wv, n, ns, G.st, s);
+        }
+        if (single) break;
+        matvec(x, G.tmp, stepped);
+        hs::launch_residual(b, G.tmp, G.r, n, ns, G.npart, G.nchunk, s);
+        hs::launch_cycle_end(G.npart, G.nchunk, G.st, ns, s);
+        hip_check(hipGetLastError(), "cycle launches");
+        std::vector<hs::ColState> cur = download(G.st, ns, s);
+        bool all_done = true;
+        for (auto& c : cur) all_done &= c.done != 0;
+        if (all_done) break;
+        hip_check(hipMemsetAsync(G.Hh, 0, sizeof(cd) * G.ldh * ns, s), "memset");
+        hs::launch_cycle_start(G.r, G.V, n, G.g, m, G.npart, G.nchunk, G.st, n, ns, false, s);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
 int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, const void* b, void* x, int64_t nrhs,
                  const hs_solve_opts* opts, hs_solve_stats* stats) {
     try {
         if (!ctx || !H || !b || !x || !opts || !stats) fail(HS_EINVAL, "NULL argument");
         if (nrhs < 1) fail(HS_EINVAL, "nrhs must be >= 1");
         if (P && P->H != H) fail(HS_EINVAL, "the preconditioner belongs to another H-matrix");
-        if (opts->method != HS_SOLVE_GMRES) fail(HS_EINVAL, "unsupported method");
+        const bool mixed = opts->method == HS_SOLVE_FGMRES_MIXED;
+        if (opts->method != HS_SOLVE_GMRES && !mixed) fail(HS_EINVAL, "unsupported method");
+        if (mixed && !H->c64) fail(HS_EINVAL, "the mixed solve needs an H-matrix built with store_c64");
+        if (mixed && P && !P->c64) fail(HS_EINVAL, "the mixed solve needs a preconditioner set up with HS_PREC_MIXED");
         const int m = opts->restart;
         if (m < 1 || m > hs::kMaxRankCap) fail(HS_EINVAL, "restart must be in [1, 256]");
         if (!(opts->tol >= 0.0)) fail(HS_EINVAL, "tol must be >= 0");
+        const int m_in = opts->inner_steps > 0 ? opts->inner_steps : 20;
+        const double tol_in = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-2;
+        if (mixed && m_in > hs::kMaxRankCap) fail(HS_EINVAL, "inner_steps must be in [1, 256]");
         const int budget = opts->fixed_iters > 0 ? opts->fixed_iters : (opts->max_iters > 0 ? opts->max_iters : 5000);
         set_device(ctx);
         hipStream_t s = ctx->stream;
         const int64_t n = H->n;
         const int ns = (int)nrhs;
-        const int nchunk = hs::gmres_nchunk(n);
         Owned w;
         w.mem = ctx->mem;
         cd* bt = w.get<cd>(n * ns);
         cd* xt = w.get<cd>(n * ns);
-        cd* r = w.get<cd>(n * ns);
-        cd* wv = w.get<cd>(n * ns);
-        cd* tmp = w.get<cd>(n * ns);
-        const int64_t vstride = n * ns;
-        cd* V = w.get<cd>((size_t)(m + 1) * vstride);
-        const int64_t ldh = (int64_t)(m + 1) * m;
-        cd* Hh = w.get<cd>((size_t)ldh * ns);
-        double* csv = w.get<double>((size_t)m * ns);
-        cd* snv = w.get<cd>((size_t)m * ns);
-        cd* g = w.get<cd>((size_t)(m + 1) * ns);
-        cd* y = w.get<cd>((size_t)m * ns);
-        cd* partial = w.get<cd>((size_t)nchunk * (m + 1) * ns);
-        double* npart = w.get<double>((size_t)nchunk * ns);
-        double* inv_hn = w.get<double>(ns);
-        hs::ColState* st = w.get<hs::ColState>(ns);
         cd* slots = w.get<cd>((size_t)H->slot_total * ns);
+        GmresWs G;
+        G.alloc(w, n, ns, m, mixed);
         SweepWs sw;
         if (P) sw = make_sweep_ws(w, P, ns, s);
         std::vector<hs::ColState> hst(ns);
@@ -1624,58 +1773,48 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
             c.budget = budget;
             c.fixed = opts->fixed_iters > 0 ? 1 : 0;
         }
-        hip_check(hipMemcpyAsync(st, hst.data(), sizeof(hs::ColState) * ns, hipMemcpyHostToDevice, s), "H2D");
+        hip_check(hipMemcpyAsync(G.st, hst.data(), sizeof(hs::ColState) * ns, hipMemcpyHostToDevice, s), "H2D");
         hip_check(hipMemsetAsync(xt, 0, sizeof(cd) * n * ns, s), "memset");
-        hip_check(hipMemsetAsync(Hh, 0, sizeof(cd) * ldh * ns, s), "memset");
         hs::launch_permute(static_cast<const cd*>(b), bt, H->d_perm, n, ns, true, s);
-        hs::launch_col_norms(bt, n, ns, npart, nchunk, s);
-        hs::launch_cycle_start(bt, V, n, g, m, npart, nchunk, st, n, ns, true, s);
-        // inside a cycle only the columns still stepping are computed; at its end
-        // those that stepped in it
-        const hs::ColMask active{st, 1, 0}, stepped{st, 2, 0};
-        auto precond = [&](const cd* in, cd* outv, const hs::ColMask& mk) {
-            if (P) apply_tree(ctx, P, in, outv, ns, sw, s, mk);
-            else hip_check(hipMemcpyAsync(outv, in, sizeof(cd) * n * ns, hipMemcpyDeviceToDevice, s), "D2D");
+        ApplyFn matvec = [&](const cd* in, cd* out, const hs::ColMask& mk) {
+            matvec_tree(ctx, H, in, out, ns, slots, s, mk);
         };
-        const int poll = 4;
-        for (;;) {
-            for (int j = 0; j < m; ++j) {
-                precond(V + j * vstride, tmp, active);
-                matvec_tree(ctx, H, tmp, wv, ns, slots, s, active);
-                hs::launch_dots(V, n, vstride, j + 1, wv, n, ns, st, partial, nchunk, s);
-                hs::launch_basis_update(V, n, vstride, j + 1, partial, nchunk, wv, n, ns, st, Hh, ldh, m + 1, j, false,
-                                        nullptr, s);
-                hs::launch_dots(V, n, vstride, j + 1, wv, n, ns, st, partial, nchunk, s);
-                hs::launch_basis_update(V, n, vstride, j + 1, partial, nchunk, wv, n, ns, st, Hh, ldh, m + 1, j, true,
-                                        npart, s);
-                hs::launch_givens(Hh, ldh, m, j, csv, snv, g, npart, nchunk, st, ns, inv_hn, s);
-                hs::launch_scale_next(wv, V + (j + 1) * vstride, n, n, ns, st, inv_hn, s);
-                if ((j + 1) % poll == 0 && j + 1 < m) {
-                    hip_check(hipGetLastError(), "inner launches");
-                    std::vector<hs::ColState> cur = download(st, ns, s);
-                    bool any = false;
-                    for (auto& c : cur) any |= c.active != 0;
-                    if (!any) break;
+        ApplyFn precond = [&](const cd* in, cd* out, const hs::ColMask& mk) {
+            if (P) apply_tree(ctx, P, in, out, ns, sw, s, mk);
+            else hip_check(hipMemcpyAsync(out, in, sizeof(cd) * n * ns, hipMemcpyDeviceToDevice, s), "D2D");
+        };
+        if (!mixed) {
+            gmres_run(G, s, bt, xt, matvec, precond, false, false, 4);
+        } else {
+            // inner solves: complex64 operator and preconditioner copies, FP64 vectors
+            GmresWs Gi;
+            Gi.alloc(w, n, ns, m_in, false);
+            ApplyFn matvec32 = [&](const cd* in, cd* out, const hs::ColMask& mk) {
+                hs::launch_near_mv(mk, H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near32,
+                                   in, n, ns, slots, s);
+                hs::launch_far_mv(mk, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr32, H->d_mv_slot,
+                                  (int64_t)H->far_geom.size(), in, n, ns, slots, s);
+                hs::launch_gather(mk, H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, n, ns, out, s);
+            };
+            ApplyFn precond32 = [&](const cd* in, cd* out, const hs::ColMask& mk) {
+                if (!P) {
+                    hip_check(hipMemcpyAsync(out, in, sizeof(cd) * n * ns, hipMemcpyDeviceToDevice, s), "D2D");
+                    return;
                 }
-            }
-            hs::launch_lsq(Hh, ldh, m, g, y, st, ns, s);
-            hs::launch_combine(V, n, vstride, y, m, tmp, n, ns, st, s);
-            precond(tmp, wv, stepped);
-            hs::launch_axpy_x(xt, wv, n, ns, st, s);
-            matvec_tree(ctx, H, xt, tmp, ns, slots, s, stepped);
-            hs::launch_residual(bt, tmp, r, n, ns, npart, nchunk, s);
-            hs::launch_cycle_end(npart, nchunk, st, ns, s);
-            hip_check(hipGetLastError(), "cycle launches");
-            std::vector<hs::ColState> cur = download(st, ns, s);
-            bool all_done = true;
-            for (auto& c : cur) all_done &= c.done != 0;
-            if (all_done) {
-                hst = cur;
-                break;
-            }
-            hip_check(hipMemsetAsync(Hh, 0, sizeof(cd) * ldh * ns, s), "memset");
-            hs::launch_cycle_start(r, V, n, g, m, npart, nchunk, st, n, ns, false, s);
+                sw.epoch += 1;
+                hs::launch_sweep(true, mk, P->sp32, P->items, in, out, ns, sw.w, sw.epoch, s);
+                hs::launch_sweep(false, mk, P->sp32, P->items, in, out, ns, sw.w, sw.epoch, s);
+            };
+            // one flexible preconditioning step: z = approximate Z^-1 v for the
+            // columns still stepping in the outer cycle
+            ApplyFn inner = [&](const cd* in, cd* out, const hs::ColMask& mk) {
+                hip_check(hipMemsetAsync(out, 0, sizeof(cd) * n * ns, s), "memset");
+                hs::launch_col_init(Gi.st, mk.st, ns, tol_in, m_in, s);
+                gmres_run(Gi, s, in, out, matvec32, precond32, false, true, 4);
+            };
+            gmres_run(G, s, bt, xt, matvec, inner, true, false, 4);
         }
+        hst = download(G.st, ns, s);
         hs::launch_permute(xt, static_cast<cd*>(x), H->d_perm, n, ns, false, s);
         hip_check(hipGetLastError(), "permute launch");
         hip_check(hipStreamSynchronize(s), "stream sync");

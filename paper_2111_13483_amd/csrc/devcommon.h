@@ -10,6 +10,16 @@
 namespace hs {
 
 typedef double2 cd;   // {re, im}
+typedef float2 cf;    // complex64 storage of the mixed-precision operator copies
+
+// matrix element loads: complex128 as stored, complex64 widened to complex128
+__device__ __forceinline__ cd to_cd(cd v) { return v; }
+__device__ __forceinline__ cd to_cd(cf v) {
+    cd z;
+    z.x = (double)v.x;
+    z.y = (double)v.y;
+    return z;
+}
 
 __device__ __forceinline__ cd cmk(double r, double i) { cd z; z.x = r; z.y = i; return z; }
 __device__ __forceinline__ cd cadd(cd a, cd b) { return cmk(a.x + b.x, a.y + b.y); }

@@ -86,7 +86,7 @@ int main(int argc, char** argv) {
     hs_context* ctx = nullptr;
     if (!ok(hs_context_create(&ctx, 0, nullptr, nullptr, nullptr, nullptr), "context")) return 1;
     const double t0 = now();
-    hs_build_opts bo{h.leaf_max, h.aca_tol, 0};
+    hs_build_opts bo{h.leaf_max, h.aca_tol, 0, 0};
     hs_hmatrix* H = nullptr;
     if (!ok(hs_h_build(ctx, d_pts, h.n, h.k, h.self_h, &bo, &H), "h_build")) return 1;
     const double t1 = now();
@@ -94,7 +94,7 @@ int main(int argc, char** argv) {
     hs_precond* P = nullptr;
     if (!ok(hs_precond_setup(ctx, H, &po, &P), "precond_setup")) return 1;
     const double t2 = now();
-    hs_solve_opts so{HS_SOLVE_GMRES, h.restart, h.tol, 0, 0};
+    hs_solve_opts so{HS_SOLVE_GMRES, h.restart, h.tol, 0, 0, 0, 0.0};
     hs_solve_stats st{};
     if (!ok(hs_solve(ctx, H, P, d_b, d_x, 1, &so, &st), "solve")) return 1;
     const double t3 = now();

@@ -6,6 +6,7 @@
 namespace hs {
 
 typedef double2 cd;
+typedef float2 cf;
 
 constexpr int kMaxRankCap = 256;   // largest ACA rank a block may reach
 // device error flag bits
@@ -128,10 +129,18 @@ void launch_gemm(const GemmTask* tasks, int64_t ntasks, const cd* A, const cd* B
 // ---- solve ----
 void launch_permute(const cd* src, cd* dst, const int64_t* perm, int64_t n, int64_t nrhs, bool to_tree,
                     hipStream_t s);
+// Near and far parts of the matvec from complex128 or complex64 matrix
+// copies (vectors and accumulation in complex128 either way).
 void launch_near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cd* Z,
+                    const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
+void launch_near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cf* Z,
                     const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
 void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cd* const* uv, const int64_t* slot_base,
                    int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
+void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cf* const* uv, const int64_t* slot_base,
+                   int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
+// complex128 -> complex64 copies: dst[dst_off + e] = src[e], e < count
+void launch_to_c64(const PtrCopy* tasks, int64_t ntasks, cf* dst, hipStream_t s);
 void launch_gather(const ColMask& mk, const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb,
                    const cd* slots, int64_t n, int nrhs, cd* y, hipStream_t s);
 // P^-1 v = alpha D^-1 alpha^T v by chunked sweeps. Block rows (elimination
@@ -147,7 +156,8 @@ void launch_gather(const ColMask& mk, const int64_t* leaf_off, const int64_t* gp
 // chunk, w = loc + b_k (forward Linv row width), wt = n_c - loc (backward
 // width); row blocks of Linv (b_k x w), Linv^T (b_k x wt), Linv C (b_k x
 // range width) and Linv^T C' (b_k x range width), all row-major.
-struct SweepPlan {
+template <class T>   // T: matrix storage, cd (complex128) or cf (complex64 copies)
+struct SweepPlanT {
     int nb;
     int nch;
     int bmax;                  // largest block
@@ -163,10 +173,10 @@ struct SweepPlan {
     const int64_t* lb_off;     // Linv^T rows
     const int64_t* mf_off;     // (Linv C) rows
     const int64_t* mb_off;     // (Linv^T C^T) rows
-    const cd* lf;
-    const cd* lb;
-    const cd* mf;
-    const cd* mb;
+    const T* lf;
+    const T* lb;
+    const T* mf;
+    const T* mb;
     const int32_t* chunk_of;   // chunk of each block
     const int32_t* csize;      // points of each chunk
     // entries (k, j) outside the target chunk's folded range: pushed from their source
@@ -185,11 +195,12 @@ struct SweepPlan {
     const int32_t* bgrp_n;
     const int64_t* bgptr;
     const int64_t* bgslot;
-    const cd* alpha;
-    const cd* alpha_t;         // transposed copies of the dense backward push entries
-    const cd* dinv;
+    const T* alpha;
+    const T* alpha_t;          // transposed copies of the dense backward push entries
+    const T* dinv;
     const int64_t* dinv_off;
 };
+using SweepPlan = SweepPlanT<cd>;
 // Work items of the non-row workgroups in ticket order: item < nb is a block
 // row (phase A: r = v or D^-1 y plus its pushed slots), item >= nb the push
 // group item - nb. Phase A of chunk c comes before the pushes from chunk c - 1
@@ -259,6 +270,8 @@ static_assert(kFoldCols % 64 == 0 && kFoldCols >= kMaxChunk, "fold range in whol
 // the backward launch must follow the forward one of the same epoch.
 void launch_sweep(bool forward, const ColMask& mk, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z,
                   int nrhs, const SweepWork& w, int epoch, hipStream_t s);
+void launch_sweep(bool forward, const ColMask& mk, const SweepPlanT<cf>& p, const SweepItems& it, const cd* v, cd* z,
+                  int nrhs, const SweepWork& w, int epoch, hipStream_t s);
 int sweep_grid(int64_t nitems);
 // Workgroups of the sweep kernels that can be resident at once on a device;
 // the row workers spin for the whole launch, so this must exceed
@@ -288,6 +301,7 @@ void launch_scale_next(const cd* w, cd* vnext, int64_t ldv, int64_t n, int nrhs,
                        const double* inv_hn, hipStream_t s);
 void launch_cycle_start(const cd* r, cd* V, int64_t ldv, cd* g, int m, const double* norm_partial, int nchunk,
                         ColState* st, int64_t n, int nrhs, bool first, hipStream_t s);
+void launch_col_init(ColState* st, const ColState* outer, int nrhs, double tol, int budget, hipStream_t s);
 void launch_lsq(const cd* H, int64_t ldh, int m, const cd* g, cd* y, const ColState* st, int nrhs, hipStream_t s);
 void launch_combine(const cd* V, int64_t ldv, int64_t vstride, const cd* y, int m, cd* u, int64_t n, int nrhs,
                     const ColState* st, hipStream_t s);

@@ -42,6 +42,18 @@ __global__ void __launch_bounds__(NT) k_copy_ptrs(const PtrCopy* __restrict__ ta
     for (int64_t e = threadIdx.x; e < t.count; e += NT) d[e] = t.src[e];
 }
 
+__global__ void __launch_bounds__(NT) k_to_c64(const PtrCopy* __restrict__ tasks, cf* __restrict__ dst) {
+    const PtrCopy t = tasks[blockIdx.x];
+    cf* d = dst + t.dst_off;
+    for (int64_t e = threadIdx.x; e < t.count; e += NT) {
+        const cd v = t.src[e];
+        cf w;
+        w.x = (float)v.x;
+        w.y = (float)v.y;
+        d[e] = w;
+    }
+}
+
 // In-place Gauss-Jordan inversion with partial pivoting (row pivot: largest
 // |a|^2, ties to the lowest row) of one b x b block held in LDS.
 __global__ void __launch_bounds__(NT)
@@ -181,6 +193,10 @@ void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd
 
 void launch_copy_ptrs(const PtrCopy* tasks, int64_t ntasks, cd* dst, hipStream_t s) {
     if (ntasks > 0) hipLaunchKernelGGL(k_copy_ptrs, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, dst);
+}
+
+void launch_to_c64(const PtrCopy* tasks, int64_t ntasks, cf* dst, hipStream_t s) {
+    if (ntasks > 0) hipLaunchKernelGGL(k_to_c64, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, dst);
 }
 
 void launch_factor_inv(const cd* W, int64_t w_off, int b, cd* dinv, int64_t dinv_off, int* err, hipStream_t s) {

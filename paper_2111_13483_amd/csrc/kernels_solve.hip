@@ -32,9 +32,9 @@ __global__ void k_permute(const cd* __restrict__ src, cd* __restrict__ dst, cons
 // (rows, one wave per row, RU rows' loads issued together) and, off the
 // diagonal, s2 = Z_ij^T x_i (columns, lanes over columns, then the waves'
 // partial sums in a fixed order). S right-hand sides per pass.
-template <int S>
+template <int S, class T>
 __global__ void __launch_bounds__(NT)
-k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restrict__ slot_base, const cd* __restrict__ Z,
+k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restrict__ slot_base, const T* __restrict__ Z,
           const cd* __restrict__ x, int64_t n, int nrhs, cd* __restrict__ slots) {
     constexpr int RU = 4;
     __shared__ cd xi[kMaxLeaf * S], xj[kMaxLeaf * S];
@@ -42,7 +42,7 @@ k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restr
     const NearTask t = tasks[blockIdx.x];
     const int m = t.m, nn = t.n;
     const bool diag = t.i0 == t.j0;
-    const cd* blk = Z + t.off;
+    const T* blk = Z + t.off;
     cd* s1 = slots + slot_base[blockIdx.x] * nrhs;
     cd* s2 = s1 + (int64_t)m * nrhs;
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
@@ -65,7 +65,7 @@ k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restr
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     const int a = a0 + u * NW, b = lane + q * kWave;
-                    z[u][q] = (a < m && b < nn) ? blk[(int64_t)a * nn + b] : cmk(0.0, 0.0);
+                    z[u][q] = (a < m && b < nn) ? to_cd(blk[(int64_t)a * nn + b]) : cmk(0.0, 0.0);
                 }
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
@@ -119,9 +119,9 @@ k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restr
 // U^T, one wave per row, RU rows' loads issued together), then
 // slot_t = U t1 and slot_s = V^T t2 (one thread per output row, LG rank
 // terms' loads issued together). S right-hand sides per pass.
-template <int S>
+template <int S, class T>
 __global__ void __launch_bounds__(NT)
-k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ rank, cd* const* __restrict__ uv,
+k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ rank, T* const* __restrict__ uv,
          const int64_t* __restrict__ slot_base, const cd* __restrict__ x, int64_t n, int nrhs, cd* __restrict__ slots) {
     constexpr int RU = 4, LG = 8;
     __shared__ cd t12[2 * (kMaxRankCap + LG) * S];
@@ -132,8 +132,8 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
         for (int64_t e = threadIdx.x; e < (int64_t)(m + nn) * nrhs; e += NT) st[e] = cmk(0.0, 0.0);
         return;
     }
-    const cd* U = uv[blockIdx.x];
-    const cd* V = U + (int64_t)m * r;
+    const T* U = uv[blockIdx.x];
+    const T* V = U + (int64_t)m * r;
     cd* st = slots + slot_base[blockIdx.x] * nrhs;
     cd* ss = st + (int64_t)m * nrhs;
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
@@ -157,8 +157,8 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
                     const int l = l0 + u * NW;
                     const bool isv = l < r;
                     const int len = isv ? nn : m;
-                    const cd* row = isv ? V + (int64_t)l * nn : U + (int64_t)(l - r) * m;
-                    val[u] = (l < 2 * r && j < len) ? row[j] : cmk(0.0, 0.0);
+                    const T* row = isv ? V + (int64_t)l * nn : U + (int64_t)(l - r) * m;
+                    val[u] = (l < 2 * r && j < len) ? to_cd(row[j]) : cmk(0.0, 0.0);
                 }
 #pragma unroll
                 for (int u = 0; u < RU; ++u) {
@@ -192,7 +192,7 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
             const bool top = e < m;
             const int idx = top ? e : e - m;
             const int ld = top ? m : nn;
-            const cd* base = (top ? U : V) + idx;
+            const T* base = (top ? U : V) + idx;
             const cd* tv = t12 + (top ? 0 : rp) * S;
             cd acc[S];
 #pragma unroll
@@ -200,7 +200,7 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
             for (int l0 = 0; l0 < r; l0 += LG) {
                 cd bv[LG];
 #pragma unroll
-                for (int u = 0; u < LG; ++u) bv[u] = (l0 + u < r) ? base[(int64_t)(l0 + u) * ld] : cmk(0.0, 0.0);
+                for (int u = 0; u < LG; ++u) bv[u] = (l0 + u < r) ? to_cd(base[(int64_t)(l0 + u) * ld]) : cmk(0.0, 0.0);
 #pragma unroll
                 for (int u = 0; u < LG; ++u)
 #pragma unroll
@@ -443,11 +443,11 @@ k_cycle_start(const cd* __restrict__ r, cd* __restrict__ V, int64_t ldv, cd* __r
     const int ch = blockIdx.x, c = blockIdx.y;
     const double beta = sqrt(sum_chunks(norm_partial, nchunk, nrhs, c, red));
     ColState s = st[c];
-    if (first) {
+    if (first) {   // a column marked done beforehand stays done
         s.bnorm = beta;
         s.relres = beta > 0.0 ? 1.0 : 0.0;
         s.total = 0;
-        s.done = beta > 0.0 ? 0 : 1;
+        s.done = (s.done || !(beta > 0.0)) ? 1 : 0;
     }
     const bool run = !s.done && beta > 0.0;
     if (ch == 0 && threadIdx.x == 0) {
@@ -463,6 +463,23 @@ k_cycle_start(const cd* __restrict__ r, cd* __restrict__ V, int64_t ldv, cd* __r
     int64_t i0, i1;
     chunk_range(n, nchunk, ch, i0, i1);
     for (int64_t i = i0 + threadIdx.x; i < i1; i += NT) V[c * ldv + i] = cscale(r[c * n + i], inv);
+}
+
+// Fresh column states: tolerance, step budget; a column is done from the
+// start where the outer column (if given) is not active.
+__global__ void k_col_init(ColState* __restrict__ st, const ColState* __restrict__ outer, int nrhs, double tol,
+                           int budget) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nrhs) return;
+    ColState s;
+    s.bnorm = s.beta = s.relres = 0.0;
+    s.tol = tol;
+    s.active = s.steps = s.total = 0;
+    s.done = (outer && !outer[c].active) ? 1 : 0;
+    s.budget = budget;
+    s.fixed = 0;
+    s.pad0 = s.pad1 = 0;
+    st[c] = s;
 }
 
 // y = H^-1 g on the leading steps x steps triangle (back substitution).
@@ -565,26 +582,46 @@ void launch_permute(const cd* src, cd* dst, const int64_t* perm, int64_t n, int6
     hipLaunchKernelGGL(k_permute, dim3(grid1(n * nrhs)), dim3(NT), 0, s, src, dst, perm, n, nrhs, (int)to_tree);
 }
 
+namespace {
+template <class T>
+void near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const T* Z, const cd* x,
+             int64_t n, int nrhs, cd* slots, hipStream_t s) {
+    if (ntasks == 0) return;
+    if (nrhs == 1)
+        hipLaunchKernelGGL((k_near_mv<1, T>), dim3((unsigned)ntasks), dim3(NT), 0, s, mk, tasks, slot_base, Z, x, n,
+                           nrhs, slots);
+    else
+        hipLaunchKernelGGL((k_near_mv<SCH, T>), dim3((unsigned)ntasks), dim3(NT), 0, s, mk, tasks, slot_base, Z, x, n,
+                           nrhs, slots);
+}
+template <class T>
+void far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, T* const* uv, const int64_t* slot_base,
+            int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
+    if (ntasks == 0) return;
+    if (nrhs == 1)
+        hipLaunchKernelGGL((k_far_mv<1, T>), dim3((unsigned)ntasks), dim3(NT), 0, s, mk, geom, rank, uv, slot_base, x,
+                           n, nrhs, slots);
+    else
+        hipLaunchKernelGGL((k_far_mv<SCH, T>), dim3((unsigned)ntasks), dim3(NT), 0, s, mk, geom, rank, uv, slot_base,
+                           x, n, nrhs, slots);
+}
+}  // namespace
+
 void launch_near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cd* Z,
                     const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
-    if (ntasks == 0) return;
-    if (nrhs == 1)
-        hipLaunchKernelGGL(k_near_mv<1>, dim3((unsigned)ntasks), dim3(NT), 0, s, mk, tasks, slot_base, Z, x, n, nrhs,
-                           slots);
-    else
-        hipLaunchKernelGGL(k_near_mv<SCH>, dim3((unsigned)ntasks), dim3(NT), 0, s, mk, tasks, slot_base, Z, x, n, nrhs,
-                           slots);
+    near_mv(mk, tasks, slot_base, ntasks, Z, x, n, nrhs, slots, s);
 }
-
+void launch_near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cf* Z,
+                    const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
+    near_mv(mk, tasks, slot_base, ntasks, Z, x, n, nrhs, slots, s);
+}
 void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cd* const* uv, const int64_t* slot_base,
                    int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
-    if (ntasks == 0) return;
-    if (nrhs == 1)
-        hipLaunchKernelGGL(k_far_mv<1>, dim3((unsigned)ntasks), dim3(NT), 0, s, mk, geom, rank, uv, slot_base, x, n,
-                           nrhs, slots);
-    else
-        hipLaunchKernelGGL(k_far_mv<SCH>, dim3((unsigned)ntasks), dim3(NT), 0, s, mk, geom, rank, uv, slot_base, x, n,
-                           nrhs, slots);
+    far_mv(mk, geom, rank, uv, slot_base, ntasks, x, n, nrhs, slots, s);
+}
+void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cf* const* uv, const int64_t* slot_base,
+                   int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
+    far_mv(mk, geom, rank, uv, slot_base, ntasks, x, n, nrhs, slots, s);
 }
 
 void launch_gather(const ColMask& mk, const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb,
@@ -619,6 +656,10 @@ void launch_cycle_start(const cd* r, cd* V, int64_t ldv, cd* g, int m, const dou
                         ColState* st, int64_t n, int nrhs, bool first, hipStream_t s) {
     hipLaunchKernelGGL(k_cycle_start, dim3(nchunk, nrhs), dim3(NT), 0, s, r, V, ldv, g, m, norm_partial, nchunk, st, n,
                        nrhs, (int)first);
+}
+
+void launch_col_init(ColState* st, const ColState* outer, int nrhs, double tol, int budget, hipStream_t s) {
+    hipLaunchKernelGGL(k_col_init, dim3((nrhs + 63) / 64), dim3(64), 0, s, st, outer, nrhs, tol, budget);
 }
 
 void launch_lsq(const cd* H, int64_t ldh, int m, const cd* g, cd* y, const ColState* st, int nrhs, hipStream_t s) {

@@ -170,17 +170,18 @@ constexpr int QF = kFoldCols / kWave;   // column groups of the folded neighbour
 // inputs: load_row reads A1 (width w1 <= kMaxChunk) and A2 (width w2 <=
 // kFoldCols) into registers; row_partial multiplies them with the LDS
 // copies of x1 and x2, a column range at a time.
-__device__ __forceinline__ void load_row(const cd* A1, int w1, const cd* A2, int w2, cd (&R1)[QC], cd (&R2)[QF]) {
+template <class T>
+__device__ __forceinline__ void load_row(const T* A1, int w1, const T* A2, int w2, cd (&R1)[QC], cd (&R2)[QF]) {
     const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int q = 0; q < QC; ++q) {
         const int col = lane + q * kWave;
-        R1[q] = col < w1 ? A1[col] : cmk(0.0, 0.0);
+        R1[q] = col < w1 ? to_cd(A1[col]) : cmk(0.0, 0.0);
     }
 #pragma unroll
     for (int q = 0; q < QF; ++q) {
         const int col = lane + q * kWave;
-        R2[q] = col < w2 ? A2[col] : cmk(0.0, 0.0);
+        R2[q] = col < w2 ? to_cd(A2[col]) : cmk(0.0, 0.0);
     }
 }
 
@@ -230,8 +231,8 @@ __device__ __forceinline__ void row_head(const cd (&R2)[QF], int hi, const cd* x
 // (bt x bo, target rows; used for low-rank backward entries). x is the source
 // block's segment (elimination order, column stride n); out goes to the
 // entry's slot (column stride bt).
-template <int S, bool FWD, int Q>
-__device__ __forceinline__ void push_one(const PushEnt& e, const cd* alpha, const cd* src, int64_t so, int bo, int bt,
+template <int S, bool FWD, int Q, class T>
+__device__ __forceinline__ void push_one(const PushEnt& e, const T* alpha, const cd* src, int64_t so, int bo, int bt,
                                          int64_t n, int c0, int cs, cd* slot) {
     const int lane = threadIdx.x % kWave;
     cd x[Q][S], acc[Q][S];
@@ -244,7 +245,7 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const cd* alpha, cons
             acc[q][c] = cmk(0.0, 0.0);
         }
     const int rows = FWD ? bo : bt, cols = FWD ? bt : bo;
-    const cd* A = alpha + e.aoff;
+    const T* A = alpha + e.aoff;
     if (e.rank < 0) {
         for (int a0 = 0; a0 < rows; a0 += RB) {
             cd Ar[RB][Q];
@@ -253,7 +254,7 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const cd* alpha, cons
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     const int b = lane + q * kWave;
-                    Ar[r][q] = (a0 + r < rows && b < cols) ? A[(int64_t)(a0 + r) * cols + b] : cmk(0.0, 0.0);
+                    Ar[r][q] = (a0 + r < rows && b < cols) ? to_cd(A[(int64_t)(a0 + r) * cols + b]) : cmk(0.0, 0.0);
                 }
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -279,8 +280,8 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const cd* alpha, cons
         }
     } else {
         const int rk = e.rank;
-        const cd* Uf = A;
-        const cd* Vf = A + (int64_t)rows * rk;
+        const T* Uf = A;
+        const T* Vf = A + (int64_t)rows * rk;
         for (int l0 = 0; l0 < rk; l0 += RB) {
             cd Ur[RB][Q], Vr[RB][Q];
 #pragma unroll
@@ -289,8 +290,8 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const cd* alpha, cons
                 for (int q = 0; q < Q; ++q) {
                     const int xx = lane + q * kWave;
                     const bool on = l0 + r < rk;
-                    Ur[r][q] = (on && xx < rows) ? Uf[(int64_t)(l0 + r) * rows + xx] : cmk(0.0, 0.0);
-                    Vr[r][q] = (on && xx < cols) ? Vf[(int64_t)(l0 + r) * cols + xx] : cmk(0.0, 0.0);
+                    Ur[r][q] = (on && xx < rows) ? to_cd(Uf[(int64_t)(l0 + r) * rows + xx]) : cmk(0.0, 0.0);
+                    Vr[r][q] = (on && xx < cols) ? to_cd(Vf[(int64_t)(l0 + r) * cols + xx]) : cmk(0.0, 0.0);
                 }
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -350,9 +351,9 @@ __device__ __forceinline__ void gather_slots(const int64_t* gslot, int64_t g0, i
 }  // namespace
 
 // Forward sweep; S right-hand sides per pass.
-template <int S, int Q>
+template <int S, int Q, class T>
 __global__ void __launch_bounds__(NT)
-k_sweep_fwd(ColMask mk, SweepPlan p, SweepItems it, const cd* __restrict__ v, SweepWork wk, int nrhs,
+k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v, SweepWork wk, int nrhs,
             unsigned long long base, int epoch) {
     __shared__ int s_t;
     __shared__ cd bsh[kMaxLeaf * S];
@@ -480,7 +481,7 @@ k_sweep_fwd(ColMask mk, SweepPlan p, SweepItems it, const cd* __restrict__ v, Sw
                     const int bo = p.bsize[e.src], bt = p.bsize[e.dst];
                     for (int c0 = 0; c0 < nrhs; c0 += S)
                         if (cols_live(mk, c0, min(S, nrhs - c0)))
-                            push_one<S, true, Q>(e, p.alpha, wk.ybuf, p.pos[e.src], bo, bt, n, c0, min(S, nrhs - c0),
+                            push_one<S, true, Q, T>(e, p.alpha, wk.ybuf, p.pos[e.src], bo, bt, n, c0, min(S, nrhs - c0),
                                                  wk.slots_f + e.slot * nrhs + (int64_t)c0 * bt);
                 }
                 stores_done();
@@ -494,9 +495,9 @@ k_sweep_fwd(ColMask mk, SweepPlan p, SweepItems it, const cd* __restrict__ v, Sw
 }
 
 // Backward sweep; S right-hand sides per pass.
-template <int S, int Q>
+template <int S, int Q, class T>
 __global__ void __launch_bounds__(NT)
-k_sweep_bwd(ColMask mk, SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nrhs,
+k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nrhs,
             unsigned long long base, int epoch) {
     __shared__ int s_t;
     __shared__ cd ysh[kMaxLeaf * S];
@@ -593,7 +594,7 @@ k_sweep_bwd(ColMask mk, SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWor
             const int c = p.chunk_of[k];
             const int bk = p.bsize[k];
             const int64_t pk = p.pos[k];
-            const cd* Di = p.dinv + p.dinv_off[k];
+            const T* Di = p.dinv + p.dinv_off[k];
             const int nin = (int)(p.bgptr[k + 1] - p.bgptr[k]);
             if (wid == 0 && nin > 0) wait_count(cntT, k, epoch * nin);
             __syncthreads();
@@ -610,7 +611,7 @@ k_sweep_bwd(ColMask mk, SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWor
 #pragma unroll
                         for (int q = 0; q < Q; ++q) {
                             const int aa = a0 + NW * r, b = lane + q * kWave;
-                            Dr[r][q] = (aa < bk && b < bk) ? Di[(int64_t)aa * bk + b] : cmk(0.0, 0.0);
+                            Dr[r][q] = (aa < bk && b < bk) ? to_cd(Di[(int64_t)aa * bk + b]) : cmk(0.0, 0.0);
                         }
 #pragma unroll
                     for (int r = 0; r < RB; ++r) {
@@ -659,10 +660,10 @@ k_sweep_bwd(ColMask mk, SweepPlan p, SweepItems it, cd* __restrict__ z, SweepWor
                         if (!cols_live(mk, c0, min(S, nrhs - c0))) continue;
                         cd* slot = wk.slots_b + e.slot * nrhs + (int64_t)c0 * bt;
                         if (e.rank < 0)   // column sums over the transposed copy
-                            push_one<S, true, Q>(e, p.alpha_t, wk.zbuf, p.pos[e.src], bo, bt, n, c0,
+                            push_one<S, true, Q, T>(e, p.alpha_t, wk.zbuf, p.pos[e.src], bo, bt, n, c0,
                                                  min(S, nrhs - c0), slot);
                         else
-                            push_one<S, false, Q>(e, p.alpha, wk.zbuf, p.pos[e.src], bo, bt, n, c0,
+                            push_one<S, false, Q, T>(e, p.alpha, wk.zbuf, p.pos[e.src], bo, bt, n, c0,
                                                   min(S, nrhs - c0), slot);
                     }
                 }
@@ -752,29 +753,35 @@ int sweep_capacity(int device) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, NT, 0) != hipSuccess) b = 0;
         mn = b < mn ? b : mn;
     };
-    chk(reinterpret_cast<const void*>(&k_sweep_fwd<1, 1>));
-    chk(reinterpret_cast<const void*>(&k_sweep_fwd<1, 2>));
-    chk(reinterpret_cast<const void*>(&k_sweep_fwd<2, 1>));
-    chk(reinterpret_cast<const void*>(&k_sweep_fwd<2, 2>));
-    chk(reinterpret_cast<const void*>(&k_sweep_bwd<1, 1>));
-    chk(reinterpret_cast<const void*>(&k_sweep_bwd<1, 2>));
-    chk(reinterpret_cast<const void*>(&k_sweep_bwd<2, 1>));
-    chk(reinterpret_cast<const void*>(&k_sweep_bwd<2, 2>));
+#define HS_CHK(SS, QQ, TT)                                                     \
+    chk(reinterpret_cast<const void*>(&k_sweep_fwd<SS, QQ, TT>));              \
+    chk(reinterpret_cast<const void*>(&k_sweep_bwd<SS, QQ, TT>))
+    HS_CHK(1, 1, cd);
+    HS_CHK(1, 2, cd);
+    HS_CHK(2, 1, cd);
+    HS_CHK(2, 2, cd);
+    HS_CHK(1, 1, cf);
+    HS_CHK(1, 2, cf);
+    HS_CHK(2, 1, cf);
+    HS_CHK(2, 2, cf);
+#undef HS_CHK
     return mn * cus;
 }
 
-void launch_sweep(bool forward, const ColMask& mk, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z,
-                  int nrhs, const SweepWork& w, int epoch, hipStream_t s) {
+namespace {
+template <class T>
+void sweep(bool forward, const ColMask& mk, const SweepPlanT<T>& p, const SweepItems& it, const cd* v, cd* z, int nrhs,
+           const SweepWork& w, int epoch, hipStream_t s) {
     const int64_t nit = forward ? it.nfwd : it.nbwd;
     const int G = sweep_grid(nit);
     const unsigned long long base = (unsigned long long)(epoch - 1) * (unsigned long long)(nit + G);
     const bool wide = p.bmax > kWave;
-#define HS_SWEEP(SS, QQ)                                                                                         \
-    do {                                                                                                          \
-        if (forward)                                                                                              \
-            hipLaunchKernelGGL((k_sweep_fwd<SS, QQ>), dim3(G), dim3(NT), 0, s, mk, p, it, v, w, nrhs, base, epoch); \
-        else                                                                                                      \
-            hipLaunchKernelGGL((k_sweep_bwd<SS, QQ>), dim3(G), dim3(NT), 0, s, mk, p, it, z, w, nrhs, base, epoch); \
+#define HS_SWEEP(SS, QQ)                                                                                          \
+    do {                                                                                                           \
+        if (forward)                                                                                               \
+            hipLaunchKernelGGL((k_sweep_fwd<SS, QQ, T>), dim3(G), dim3(NT), 0, s, mk, p, it, v, w, nrhs, base, epoch); \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_sweep_bwd<SS, QQ, T>), dim3(G), dim3(NT), 0, s, mk, p, it, z, w, nrhs, base, epoch); \
     } while (0)
     if (nrhs == 1) {
         if (wide) HS_SWEEP(1, 2); else HS_SWEEP(1, 1);
@@ -782,6 +789,16 @@ void launch_sweep(bool forward, const ColMask& mk, const SweepPlan& p, const Swe
         if (wide) HS_SWEEP(2, 2); else HS_SWEEP(2, 1);
     }
 #undef HS_SWEEP
+}
+}  // namespace
+
+void launch_sweep(bool forward, const ColMask& mk, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z,
+                  int nrhs, const SweepWork& w, int epoch, hipStream_t s) {
+    sweep(forward, mk, p, it, v, z, nrhs, w, epoch, s);
+}
+void launch_sweep(bool forward, const ColMask& mk, const SweepPlanT<cf>& p, const SweepItems& it, const cd* v, cd* z,
+                  int nrhs, const SweepWork& w, int epoch, hipStream_t s) {
+    sweep(forward, mk, p, it, v, z, nrhs, w, epoch, s);
 }
 
 void launch_linv(const SweepPlan& p, int nchunk, const int32_t* chunk_first, const int64_t* intptr,
