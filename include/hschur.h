@@ -188,6 +188,13 @@ void    hs_hmatrix_destroy(hs_hmatrix* H);
  * opts->fill_tol. Errors: HS_ESINGULAR, HS_ENUMERIC, HS_ENOMEM, HS_EINVAL. */
 int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_opts* opts,
                          hs_precond** out);
+/* Batched setup of count geometries with the same options: the elimination
+ * step k of every geometry with more than k leaves runs in one launch per
+ * kernel, so many small geometries share launches. out[g] receives the
+ * preconditioner of Hs[g]; on error every out[g] is NULL. Results equal
+ * those of separate hs_precond_setup calls. */
+int32_t hs_precond_setup_many(hs_context* ctx, int64_t count, const hs_hmatrix* const* Hs,
+                              const hs_precond_opts* opts, hs_precond** out);
 int32_t hs_query_precond(const hs_precond* P, hs_info* info);
 void    hs_precond_destroy(hs_precond* P);
 

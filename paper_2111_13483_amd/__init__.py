@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
         "hs_query_hmatrix": (i32, [vp, ctypes.POINTER(Info)]),
         "hs_hmatrix_destroy": (None, [vp]),
         "hs_precond_setup": (i32, [vp, vp, ctypes.POINTER(PrecondOpts), pvp]),
+        "hs_precond_setup_many": (i32, [vp, i64, pvp, ctypes.POINTER(PrecondOpts), pvp]),
         "hs_query_precond": (i32, [vp, ctypes.POINTER(Info)]),
         "hs_precond_destroy": (None, [vp]),
         "hs_solve": (i32, [vp, vp, vp, vp, vp, i64, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)]),
@@ -137,7 +138,7 @@ def load(path: str = LIB_PATH):
 EXPORTED = (
     "hs_context_create", "hs_context_set_stream", "hs_context_destroy", "hs_plan_create", "hs_plan_query",
     "hs_plan_destroy", "hs_plan_export", "hs_h_build", "hs_query_hmatrix", "hs_hmatrix_destroy", "hs_precond_setup",
-    "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_precond_apply", "hs_hmatrix_export",
+    "hs_precond_setup_many", "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_precond_apply", "hs_hmatrix_export",
     "hs_precond_export", "hs_timing_begin", "hs_timing_end", "hs_server_clock", "hs_server_create",
     "hs_server_admit", "hs_server_submit", "hs_server_step", "hs_server_pending", "hs_server_request",
     "hs_server_destroy", "hs_status_string", "hs_last_error",
@@ -301,6 +302,23 @@ class Precond:
         h = ctypes.c_void_p()
         _check(_lib.hs_precond_setup(ctx._h, H._h, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
+
+    @classmethod
+    def many(cls, ctx: Context, Hs, ordering: str = "rcm", fill_tol: float = 1e-2, sweep_chunk: int = 0,
+             sweep_fold_cols: int = 0, mixed: bool = False):
+        """Batched setup (hs_precond_setup_many): one preconditioner per H-matrix,
+        the elimination steps of all of them sharing launches."""
+        opts = PrecondOpts(ORDER[ordering], float(fill_tol), 1 if mixed else 0, int(sweep_chunk), int(sweep_fold_cols))
+        hs_arr = (ctypes.c_void_p * len(Hs))(*[H._h.value for H in Hs])
+        outs = (ctypes.c_void_p * len(Hs))()
+        _check(_lib.hs_precond_setup_many(ctx._h, len(Hs), hs_arr, ctypes.byref(opts), outs))
+        res = []
+        for H, h in zip(Hs, outs):
+            P = cls.__new__(cls)
+            P.ctx, P.H = ctx, H
+            P._h = ctypes.c_void_p(h)
+            res.append(P)
+        return res
 
     def info(self) -> dict:
         inf = Info()

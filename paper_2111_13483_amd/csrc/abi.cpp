@@ -913,28 +913,33 @@ int32_t hs_hmatrix_export(const hs_hmatrix* H, int32_t what, void* dst, int64_t 
     }
 }
 
-// ---- preconditioner setup ---------------------------------------------------------
+}  // extern "C"
 
-int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_opts* opts, hs_precond** out) {
-    try {
-        if (!out) fail(HS_EINVAL, "out is NULL");
-        *out = nullptr;
-        if (!ctx || !H || !opts) fail(HS_EINVAL, "NULL argument");
-        if (opts->ordering < 0 || opts->ordering > 2) fail(HS_EINVAL, "unknown ordering");
-        if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
-        if (opts->precision != HS_PREC_FP64 && opts->precision != HS_PREC_MIXED) fail(HS_EINVAL, "unsupported precision");
-        if (opts->sweep_chunk < 0 || opts->sweep_chunk > hs::kMaxChunk) fail(HS_EINVAL, "sweep_chunk must be in [0, 384]");
-        const int32_t chunk_lim = opts->sweep_chunk > 0 ? opts->sweep_chunk : hs::kMaxChunk;
-        if (opts->sweep_fold_cols != 0 && (opts->sweep_fold_cols < chunk_lim || opts->sweep_fold_cols > hs::kFoldCols))
-            fail(HS_EINVAL, "sweep_fold_cols must be 0 or in [chunk size, 3072]");
-        const int32_t fold_cols = opts->sweep_fold_cols > 0 ? opts->sweep_fold_cols : hs::kFoldCols;
-        set_device(ctx);
-        // the sweeps keep their row workers resident for a whole launch
-        // and need others beside them
-        if (hs::sweep_capacity(ctx->device) < hs::kRowWorkers * hs::kRowSets + 32)
-            fail(HS_ENODEVICE, "too few resident workgroups for the preconditioner sweeps");
-        hipStream_t s = ctx->stream;
-        auto P = std::make_unique<hs_precond>();
+namespace {
+
+// One preconditioner setup, in phases so that the elimination steps of several
+// geometries can share launches (hs_precond_setup_many).
+struct SetupJob {
+    hs_context* ctx = nullptr;
+    const hs_hmatrix* H = nullptr;
+    const hs_precond_opts* opts = nullptr;
+    hipStream_t s = nullptr;
+    int32_t chunk_lim = 0, fold_cols = 0;
+    std::unique_ptr<hs_precond> P;
+    int64_t nb = 0, nnz = 0;
+    std::vector<int64_t> row_of, wd_off, w_off, ad_off;
+    int64_t wtot = 0, atot = 0, dtot = 0;
+    Owned tmp;
+    cd* W = nullptr;
+    cd* Ad = nullptr;
+    int* d_err = nullptr;
+    // per elimination step: alpha tasks at[at_ptr[k] .. at_ptr[k+1]), Schur updates likewise
+    std::vector<hs::GemmTask> at, st;
+    std::vector<int64_t> at_ptr, st_ptr;
+
+    // ordering, symbolic fill, layouts, initial blocks, per-step task lists
+    void prepare() {
+        P = std::make_unique<hs_precond>();
         P->own.mem = ctx->mem;
         P->H = H;
         P->plan.tree = H->plan.tree;
@@ -943,7 +948,8 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         P->plan.has_sym = true;
         const hs::Symbolic& sy = P->plan.sym;
         const hs::Partition& p = H->plan.part;
-        const int64_t nb = H->nb, nnz = sy.nnz();
+        nb = H->nb;
+        nnz = sy.nnz();
         P->nb = nb;
         P->bsize.resize(nb);
         P->bstart.resize(nb);
@@ -952,13 +958,17 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             P->bstart[kk] = H->leaf_off[ol];
             P->bsize[kk] = (int32_t)(H->leaf_off[ol + 1] - H->leaf_off[ol]);
         }
-        std::vector<int64_t> row_of(nnz);
+        row_of.assign(nnz, 0);
         for (int64_t kk = 0; kk < nb; ++kk)
             for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) row_of[e] = kk;
         // layouts: W diagonal blocks, W pattern blocks, dense alpha, D^-1
-        std::vector<int64_t> wd_off(nb), w_off(nnz), ad_off(nnz);
+        wd_off.assign(nb, 0);
+        w_off.assign(nnz, 0);
+        ad_off.assign(nnz, 0);
         P->d_off.resize(nb);
-        int64_t wtot = 0, atot = 0, dtot = 0;
+        wtot = 0;
+        atot = 0;
+        dtot = 0;
         for (int64_t kk = 0; kk < nb; ++kk) {
             const int64_t bk = P->bsize[kk];
             wd_off[kk] = wtot;
@@ -974,14 +984,13 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             }
         }
         P->d_elems = dtot;
-        Owned tmp;
         tmp.mem = ctx->mem;
-        cd* W = tmp.get<cd>(wtot);
-        cd* Ad = tmp.get<cd>(atot);
+        W = tmp.get<cd>(wtot);
+        Ad = tmp.get<cd>(atot);
         Owned& o = P->own;
         P->d_dinv = o.get<cd>(dtot);
         P->d_D = o.get<cd>(dtot);
-        int* d_err = tmp.get<int>(1);
+        d_err = tmp.get<int>(1);
         hip_check(hipMemsetAsync(d_err, 0, sizeof(int), s), "memset");
         // scatter Z_N into W (row k of the working matrix = leaf order[k])
         std::map<std::pair<int64_t, int64_t>, int64_t> near_idx;
@@ -1013,8 +1022,10 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             if (it == e || *it != j) fail(HS_EINVAL, "internal: filled pattern is not closed");
             return it - sy.cols.begin();
         };
-        std::vector<hs::GemmTask> at, st;
-        std::vector<int64_t> at_ptr(nb + 1, 0), st_ptr(nb + 1, 0);
+        at.clear();
+        st.clear();
+        at_ptr.assign(nb + 1, 0);
+        st_ptr.assign(nb + 1, 0);
         for (int64_t kk = 0; kk < nb; ++kk) {
             const int32_t bk = P->bsize[kk];
             const int64_t r0 = sy.rowptr[kk], r1 = sy.rowptr[kk + 1];
@@ -1033,13 +1044,15 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
             at_ptr[kk + 1] = (int64_t)at.size();
             st_ptr[kk + 1] = (int64_t)st.size();
         }
-        hs::GemmTask* d_at = tmp.upload(at, s);
-        hs::GemmTask* d_st = tmp.upload(st, s);
-        for (int64_t kk = 0; kk < nb; ++kk) {
-            hs::launch_factor_inv(W, wd_off[kk], P->bsize[kk], P->d_dinv, P->d_off[kk], d_err, s);
-            hs::launch_gemm(d_at + at_ptr[kk], at_ptr[kk + 1] - at_ptr[kk], P->d_dinv, W, Ad, false, false, -1.0, s);
-            hs::launch_gemm(d_st + st_ptr[kk], st_ptr[kk + 1] - st_ptr[kk], W, Ad, W, true, true, 1.0, s);
-        }
+    }
+
+    // after the elimination: D, fill-in compression, the alpha store and the sweep plan
+    void finish() {
+        const hs::Symbolic& sy = P->plan.sym;
+        const hs::Partition& p = H->plan.part;
+        Owned& o = P->own;
+        (void)p;
+        (void)o;
         hip_check(hipGetLastError(), "elimination launches");
         check_device_flag(d_err, s);
         // keep D_k = final W_kk
@@ -1537,7 +1550,103 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
         fill_info_plan(P->plan, &info);
         P->flops_setup = info.flops_setup;
         P->max_dk = info.max_dk;
-        *out = P.release();
+    }
+};
+
+// The elimination of every job: step k of all jobs with more than k blocks
+// in one launch per kernel (Eq. 14, 19: invert W_kk, alpha_kj = -W_kk^-1 W_kj,
+// W_ij += W_ki^T alpha_kj).
+void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
+    Owned tmp;
+    tmp.mem = jobs.front()->ctx->mem;
+    int64_t steps = 0;
+    for (auto* j : jobs) steps = std::max(steps, j->nb);
+    std::vector<hs::FactorTask> ft;
+    std::vector<hs::GemmTaskP> at, st;
+    std::vector<int64_t> fp(steps + 1, 0), ap(steps + 1, 0), sp(steps + 1, 0);
+    for (int64_t k = 0; k < steps; ++k) {
+        for (auto* j : jobs) {
+            if (k >= j->nb) continue;
+            hs_precond* P = j->P.get();
+            ft.push_back(hs::FactorTask{j->W + j->wd_off[k], P->d_dinv + P->d_off[k], P->bsize[k], 0});
+            for (int64_t q = j->at_ptr[k]; q < j->at_ptr[k + 1]; ++q) {
+                const hs::GemmTask& t = j->at[q];
+                at.push_back(hs::GemmTaskP{j->Ad + t.c_off, P->d_dinv + t.a_off, j->W + t.b_off, t.m, t.n, t.kk, 0});
+            }
+            for (int64_t q = j->st_ptr[k]; q < j->st_ptr[k + 1]; ++q) {
+                const hs::GemmTask& t = j->st[q];
+                st.push_back(hs::GemmTaskP{j->W + t.c_off, j->W + t.a_off, j->Ad + t.b_off, t.m, t.n, t.kk, 0});
+            }
+        }
+        fp[k + 1] = (int64_t)ft.size();
+        ap[k + 1] = (int64_t)at.size();
+        sp[k + 1] = (int64_t)st.size();
+    }
+    hs::FactorTask* d_ft = tmp.upload(ft, s);
+    hs::GemmTaskP* d_at = tmp.upload(at, s);
+    hs::GemmTaskP* d_st = tmp.upload(st, s);
+    // one error flag per job would be finer; the first job's flag serves all
+    int* d_err = jobs.front()->d_err;
+    for (int64_t k = 0; k < steps; ++k) {
+        hs::launch_factor_inv(d_ft + fp[k], fp[k + 1] - fp[k], d_err, s);
+        hs::launch_gemm_p(d_at + ap[k], ap[k + 1] - ap[k], false, false, -1.0, s);
+        hs::launch_gemm_p(d_st + sp[k], sp[k + 1] - sp[k], true, true, 1.0, s);
+    }
+    hip_check(hipStreamSynchronize(s), "stream sync");
+}
+
+}  // namespace
+
+extern "C" {
+
+// ---- preconditioner setup ---------------------------------------------------------
+
+int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_opts* opts, hs_precond** out) {
+    if (!out) { g_last_error = "out is NULL"; return HS_EINVAL; }
+    return hs_precond_setup_many(ctx, 1, &H, opts, out);
+}
+
+int32_t hs_precond_setup_many(hs_context* ctx, int64_t count, const hs_hmatrix* const* Hs, const hs_precond_opts* opts,
+                              hs_precond** out) {
+    try {
+        if (!out) fail(HS_EINVAL, "out is NULL");
+        if (count < 1) fail(HS_EINVAL, "count must be >= 1");
+        for (int64_t g = 0; g < count; ++g) out[g] = nullptr;
+        if (!Hs) fail(HS_EINVAL, "NULL argument");
+        for (int64_t g = 0; g < count; ++g) {
+            const hs_hmatrix* H = Hs[g];
+        if (!ctx || !H || !opts) fail(HS_EINVAL, "NULL argument");
+            if (opts->ordering < 0 || opts->ordering > 2) fail(HS_EINVAL, "unknown ordering");
+            if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
+            if (opts->precision != HS_PREC_FP64 && opts->precision != HS_PREC_MIXED) fail(HS_EINVAL, "unsupported precision");
+            if (opts->sweep_chunk < 0 || opts->sweep_chunk > hs::kMaxChunk) fail(HS_EINVAL, "sweep_chunk must be in [0, 384]");
+            const int32_t chunk_lim = opts->sweep_chunk > 0 ? opts->sweep_chunk : hs::kMaxChunk;
+            if (opts->sweep_fold_cols != 0 && (opts->sweep_fold_cols < chunk_lim || opts->sweep_fold_cols > hs::kFoldCols))
+                fail(HS_EINVAL, "sweep_fold_cols must be 0 or in [chunk size, 3072]");
+            set_device(ctx);
+            // the sweeps keep their row workers resident for a whole launch
+            // and need others beside them
+            if (hs::sweep_capacity(ctx->device) < hs::kRowWorkers * hs::kRowSets + 32)
+                fail(HS_ENODEVICE, "too few resident workgroups for the preconditioner sweeps");
+            if (H->plan.part.n_near() == 0) fail(HS_EINVAL, "empty H-matrix");
+        }
+        std::vector<std::unique_ptr<SetupJob>> jobs;
+        std::vector<SetupJob*> jp;
+        for (int64_t g = 0; g < count; ++g) {
+            auto j = std::make_unique<SetupJob>();
+            j->ctx = ctx;
+            j->H = Hs[g];
+            j->opts = opts;
+            j->s = ctx->stream;
+            j->chunk_lim = opts->sweep_chunk > 0 ? opts->sweep_chunk : hs::kMaxChunk;
+            j->fold_cols = opts->sweep_fold_cols > 0 ? opts->sweep_fold_cols : hs::kFoldCols;
+            j->prepare();
+            jp.push_back(j.get());
+            jobs.push_back(std::move(j));
+        }
+        eliminate(jp, ctx->stream);
+        for (auto& j : jobs) j->finish();
+        for (int64_t g = 0; g < count; ++g) out[g] = jobs[g]->P.release();
         return HS_OK;
     } catch (const Error& e) {
         return set_error(e);

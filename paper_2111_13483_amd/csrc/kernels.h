@@ -122,7 +122,21 @@ struct PtrCopy {
 };
 void launch_copy_ptrs(const PtrCopy* tasks, int64_t ntasks, cd* dst, hipStream_t s);
 void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s);
-void launch_factor_inv(const cd* W, int64_t w_off, int b, cd* dinv, int64_t dinv_off, int* err, hipStream_t s);
+// One diagonal block to invert: b x b row-major at w, inverse to dinv.
+struct FactorTask {
+    const cd* w;
+    cd* dinv;
+    int32_t b, pad;
+};
+void launch_factor_inv(const FactorTask* tasks, int64_t ntasks, int* err, hipStream_t s);
+// A GEMM with operands by pointer: C (m x n) (+)= sign op(A) B.
+struct GemmTaskP {
+    cd* c;
+    const cd* a;
+    const cd* b;
+    int32_t m, n, kk, pad;
+};
+void launch_gemm_p(const GemmTaskP* tasks, int64_t ntasks, bool transA, bool accumulate, double sign, hipStream_t s);
 void launch_gemm(const GemmTask* tasks, int64_t ntasks, const cd* A, const cd* B, cd* C, bool transA, bool accumulate,
                  double sign, hipStream_t s);
 

@@ -55,9 +55,13 @@ __global__ void __launch_bounds__(NT) k_to_c64(const PtrCopy* __restrict__ tasks
 }
 
 // In-place Gauss-Jordan inversion with partial pivoting (row pivot: largest
-// |a|^2, ties to the lowest row) of one b x b block held in LDS.
+// |a|^2, ties to the lowest row) of one b x b block held in LDS; one block
+// per workgroup (the diagonal blocks of one elimination step, one per
+// geometry of a batch).
 __global__ void __launch_bounds__(NT)
-k_factor_inv(const cd* __restrict__ W, int64_t w_off, int b, cd* __restrict__ dinv, int64_t dinv_off, int* err) {
+k_factor_inv(const FactorTask* __restrict__ tasks, int* err) {
+    const FactorTask ft = tasks[blockIdx.x];
+    const int b = ft.b;
     constexpr int LD = kMaxLeaf + 1;
     __shared__ cd A[kMaxLeaf * LD];
     __shared__ cd colc[kMaxLeaf];
@@ -65,7 +69,7 @@ k_factor_inv(const cd* __restrict__ W, int64_t w_off, int b, cd* __restrict__ di
     __shared__ int s_piv;
     __shared__ double s_mag;
     const int tid = threadIdx.x;
-    const cd* src = W + w_off;
+    const cd* src = ft.w;
     for (int e = tid; e < b * b; e += NT) A[(e / b) * LD + e % b] = src[e];
     __syncthreads();
     for (int c = 0; c < b; ++c) {
@@ -117,23 +121,19 @@ k_factor_inv(const cd* __restrict__ W, int64_t w_off, int b, cd* __restrict__ di
             }
         __syncthreads();
     }
-    cd* out = dinv + dinv_off;
+    cd* out = ft.dinv;
     for (int e = tid; e < b * b; e += NT) out[e] = A[(e / b) * LD + e % b];
 }
 
-// Batched complex GEMM, one task per workgroup, 64 x 64 output tiles.
+// Complex GEMM of one task by one workgroup, 64 x 64 output tiles, 4 x 4
+// complex register micro-tiles per thread, K staged through LDS:
+// C (m x n) (+)= sign * op(A) B with op(A) = A (m x kk) or A^T (A kk x m).
 template <bool TRANS_A>
-__global__ void __launch_bounds__(NT)
-k_gemm(const GemmTask* __restrict__ tasks, const cd* __restrict__ Ag, const cd* __restrict__ Bg, cd* __restrict__ Cg,
-       int accumulate, double sign) {
+__device__ __forceinline__ void gemm_task(const cd* __restrict__ A, const cd* __restrict__ B, cd* __restrict__ C, int m,
+                                          int n, int kk, int accumulate, double sign) {
     constexpr int TM = 64, TN = 64, KC = 16;
     __shared__ cd As[KC][TM];
     __shared__ cd Bs[KC][TN];
-    const GemmTask t = tasks[blockIdx.x];
-    const int m = t.m, n = t.n, kk = t.kk;
-    const cd* A = Ag + t.a_off;
-    const cd* B = Bg + t.b_off;
-    cd* C = Cg + t.c_off;
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
     for (int m0 = 0; m0 < m; m0 += TM) {
         for (int n0 = 0; n0 < n; n0 += TN) {
@@ -187,6 +187,24 @@ k_gemm(const GemmTask* __restrict__ tasks, const cd* __restrict__ Ag, const cd* 
     }
 }
 
+// Batched GEMM, one task per workgroup, operands at offsets from shared bases.
+template <bool TRANS_A>
+__global__ void __launch_bounds__(NT)
+k_gemm(const GemmTask* __restrict__ tasks, const cd* __restrict__ Ag, const cd* __restrict__ Bg, cd* __restrict__ Cg,
+       int accumulate, double sign) {
+    const GemmTask t = tasks[blockIdx.x];
+    gemm_task<TRANS_A>(Ag + t.a_off, Bg + t.b_off, Cg + t.c_off, t.m, t.n, t.kk, accumulate, sign);
+}
+
+// Batched GEMM, one task per workgroup, operands by pointer (tasks of
+// several geometries in one launch).
+template <bool TRANS_A>
+__global__ void __launch_bounds__(NT)
+k_gemm_p(const GemmTaskP* __restrict__ tasks, int accumulate, double sign) {
+    const GemmTaskP t = tasks[blockIdx.x];
+    gemm_task<TRANS_A>(t.a, t.b, t.c, t.m, t.n, t.kk, accumulate, sign);
+}
+
 void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s) {
     if (ntasks > 0) hipLaunchKernelGGL(k_copy_blocks, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, src, dst);
 }
@@ -199,8 +217,16 @@ void launch_to_c64(const PtrCopy* tasks, int64_t ntasks, cf* dst, hipStream_t s)
     if (ntasks > 0) hipLaunchKernelGGL(k_to_c64, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, dst);
 }
 
-void launch_factor_inv(const cd* W, int64_t w_off, int b, cd* dinv, int64_t dinv_off, int* err, hipStream_t s) {
-    hipLaunchKernelGGL(k_factor_inv, dim3(1), dim3(NT), 0, s, W, w_off, b, dinv, dinv_off, err);
+void launch_factor_inv(const FactorTask* tasks, int64_t ntasks, int* err, hipStream_t s) {
+    if (ntasks > 0) hipLaunchKernelGGL(k_factor_inv, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, err);
+}
+
+void launch_gemm_p(const GemmTaskP* tasks, int64_t ntasks, bool transA, bool accumulate, double sign, hipStream_t s) {
+    if (ntasks == 0) return;
+    if (transA)
+        hipLaunchKernelGGL(k_gemm_p<true>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, (int)accumulate, sign);
+    else
+        hipLaunchKernelGGL(k_gemm_p<false>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, (int)accumulate, sign);
 }
 
 void launch_gemm(const GemmTask* tasks, int64_t ntasks, const cd* A, const cd* B, cd* C, bool transA, bool accumulate,

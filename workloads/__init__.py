@@ -185,3 +185,34 @@ def make_config(name: str, n: int | None = None, nrhs: int = 1, seed: int | None
 
 
 CONFIGS = ("c1", "c2", "c3", "plate")
+
+
+def batch_geometries(count: int = 64, n_max: int = 40000, seed: int = 4, nrhs: int = 4) -> list:
+    """Many geometries for batched runs: the body is uniform over sphere,
+    ellipsoid (axes 1, 0.6, 0.3), cube (edge 2) and plate box (2 x 2 x 0.05);
+    N uniform in [2000, n_max]; leaf_max uniform in [24, 96]; lambda = 10 h
+    (about ten points per wavelength); nrhs plane waves. Geometry i uses the
+    child seed 1000 * seed + i."""
+    out = []
+    top = np.random.default_rng(seed)
+    kinds = top.integers(0, 4, size=count)
+    ns = top.integers(2000, n_max + 1, size=count)
+    leaves = top.integers(24, 97, size=count)
+    for i in range(count):
+        rng = np.random.default_rng(1000 * seed + i)
+        n = int(ns[i])
+        kind = int(kinds[i])
+        if kind == 0:
+            pts, area, name = fibonacci_sphere(n, rng), 4.0 * math.pi, "sphere"
+        elif kind == 1:
+            pts, area, name = fibonacci_sphere(n, rng, axes=(1.0, 0.6, 0.3)), ellipsoid_area(1.0, 0.6, 0.3), "ellipsoid"
+        elif kind == 2:
+            (pts, area), name = cube_surface(n, rng), "cube"
+        else:
+            (pts, area), name = plate_box(n, rng), "plate"
+        h = math.sqrt(area / n)
+        k = 2.0 * math.pi / (10.0 * h)
+        rhs = np.stack([plane_wave(pts, k, rng) for _ in range(nrhs)], axis=1)
+        out.append(Workload(name=name, points=pts, k=k, self_h=h, leaf_max=int(leaves[i]), restart=30,
+                            rhs=np.asfortranarray(rhs)))
+    return out
