@@ -1559,6 +1559,25 @@ struct SetupJob {
 void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
     Owned tmp;
     tmp.mem = jobs.front()->ctx->mem;
+    if (jobs.size() == 1) {
+        // one geometry: its task lists as built, operands at offsets from its buffers
+        SetupJob& j = *jobs.front();
+        hs_precond* P = j.P.get();
+        std::vector<hs::FactorTask> ft(j.nb);
+        for (int64_t k = 0; k < j.nb; ++k)
+            ft[k] = hs::FactorTask{j.W + j.wd_off[k], P->d_dinv + P->d_off[k], P->bsize[k], 0};
+        hs::FactorTask* d_ft = tmp.upload(ft, s);
+        hs::GemmTask* d_at = tmp.upload(j.at, s);
+        hs::GemmTask* d_st = tmp.upload(j.st, s);
+        for (int64_t k = 0; k < j.nb; ++k) {
+            hs::launch_factor_inv(d_ft + k, 1, j.d_err, s);
+            hs::launch_gemm(d_at + j.at_ptr[k], j.at_ptr[k + 1] - j.at_ptr[k], P->d_dinv, j.W, j.Ad, false, false, -1.0,
+                            s);
+            hs::launch_gemm(d_st + j.st_ptr[k], j.st_ptr[k + 1] - j.st_ptr[k], j.W, j.Ad, j.W, true, true, 1.0, s);
+        }
+        hip_check(hipStreamSynchronize(s), "stream sync");
+        return;
+    }
     int64_t steps = 0;
     for (auto* j : jobs) steps = std::max(steps, j->nb);
     std::vector<hs::FactorTask> ft;
