@@ -27,7 +27,7 @@ HIP_FLAGS = [
 ]
 GXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall"]
 
-HIP_SOURCES = ["kernels_build.hip", "kernels_setup.hip", "kernels_solve.hip", "kernels_sweep.hip", "abi.cpp"]
+HIP_SOURCES = ["kernels_build.hip", "kernels_setup.hip", "kernels_elim.hip", "kernels_solve.hip", "kernels_sweep.hip", "abi.cpp"]
 CXX_SOURCES = ["plan.cpp"]
 
 

@@ -933,9 +933,13 @@ struct SetupJob {
     cd* W = nullptr;
     cd* Ad = nullptr;
     int* d_err = nullptr;
-    // per elimination step: alpha tasks at[at_ptr[k] .. at_ptr[k+1]), Schur updates likewise
-    std::vector<hs::GemmTask> at, st;
-    std::vector<int64_t> at_ptr, st_ptr;
+    // elimination panels: the pattern in CSR (int32), per row the panel column
+    // starts (ne + 1 values at rowptr[k] + k), the pair-table offsets, and the
+    // Schur output tiles (ti, tj) of every step at tile_ptr[k] .. tile_ptr[k+1]
+    std::vector<int32_t> rp32, cols32, pcol;
+    std::vector<int64_t> pair_ptr, tile_ptr;
+    std::vector<int32_t> panel_m;
+    std::vector<std::pair<int16_t, int16_t>> tiles;
 
     // ordering, symbolic fill, layouts, initial blocks, per-step task lists
     void prepare() {
@@ -1015,34 +1019,48 @@ struct SetupJob {
         hs::CopyTask* d_init = tmp.upload(init, s);
         hs::launch_copy_blocks(d_init, (int64_t)init.size(), H->d_near, W, s);
         hip_check(hipGetLastError(), "k_copy_blocks launch");
-        // GEMM task lists of every step
-        auto entry = [&](int64_t i, int64_t j) -> int64_t {
-            auto b = sy.cols.begin() + sy.rowptr[i], e = sy.cols.begin() + sy.rowptr[i + 1];
-            auto it = std::lower_bound(b, e, j);
-            if (it == e || *it != j) fail(HS_EINVAL, "internal: filled pattern is not closed");
-            return it - sy.cols.begin();
-        };
-        at.clear();
-        st.clear();
-        at_ptr.assign(nb + 1, 0);
-        st_ptr.assign(nb + 1, 0);
+        // elimination panels of every step
+        rp32.assign(nb + 1, 0);
+        cols32.assign(nnz, 0);
+        pcol.assign(nnz + nb, 0);
+        pair_ptr.assign(nb + 1, 0);
+        tile_ptr.assign(nb + 1, 0);
+        panel_m.assign(nb, 0);
+        tiles.clear();
+        std::vector<int32_t> afirst, alast;
         for (int64_t kk = 0; kk < nb; ++kk) {
-            const int32_t bk = P->bsize[kk];
-            const int64_t r0 = sy.rowptr[kk], r1 = sy.rowptr[kk + 1];
+            const int64_t r0 = sy.rowptr[kk], r1 = sy.rowptr[kk + 1], ne = r1 - r0;
+            if (ne > hs::kMaxPattern) fail(HS_EINVAL, "a row of the filled pattern has more than 1024 blocks");
+            rp32[kk + 1] = (int32_t)r1;
+            int32_t* pc = pcol.data() + r0 + kk;
+            pc[0] = 0;
             for (int64_t e = r0; e < r1; ++e) {
-                const int32_t bj = P->bsize[sy.cols[e]];
-                at.push_back(hs::GemmTask{ad_off[e], P->d_off[kk], w_off[e], bk, bj, bk, 0});
+                cols32[e] = (int32_t)sy.cols[e];
+                pc[e - r0 + 1] = pc[e - r0] + P->bsize[sy.cols[e]];
             }
-            for (int64_t a = r0; a < r1; ++a) {
-                const int64_t i = sy.cols[a];
-                for (int64_t b = a; b < r1; ++b) {
-                    const int64_t j = sy.cols[b];
-                    const int64_t dst = (i == j) ? wd_off[i] : w_off[entry(i, j)];
-                    st.push_back(hs::GemmTask{dst, w_off[a], ad_off[b], P->bsize[i], P->bsize[j], bk, 0});
-                }
+            const int32_t m = pc[ne];
+            panel_m[kk] = m;
+            pair_ptr[kk + 1] = pair_ptr[kk] + ne * (ne + 1) / 2;
+            // tile (ti, tj) holds an element with block(row) <= block(column)
+            // iff the block of its first row is <= the block of its last column
+            const int32_t nt = (m + 63) / 64;
+            afirst.assign(nt, 0);
+            alast.assign(nt, 0);
+            int32_t a = 0;
+            for (int32_t t = 0; t < nt; ++t) {
+                while (pc[a + 1] <= 64 * t) ++a;
+                afirst[t] = a;
             }
-            at_ptr[kk + 1] = (int64_t)at.size();
-            st_ptr[kk + 1] = (int64_t)st.size();
+            a = 0;
+            for (int32_t t = 0; t < nt; ++t) {
+                const int32_t g = std::min(64 * t + 63, m - 1);
+                while (pc[a + 1] <= g) ++a;
+                alast[t] = a;
+            }
+            for (int32_t ti = 0; ti < nt; ++ti)
+                for (int32_t tj = 0; tj < nt; ++tj)
+                    if (afirst[ti] <= alast[tj]) tiles.emplace_back((int16_t)ti, (int16_t)tj);
+            tile_ptr[kk + 1] = (int64_t)tiles.size();
         }
     }
 
@@ -1553,64 +1571,73 @@ struct SetupJob {
     }
 };
 
-// The elimination of every job: step k of all jobs with more than k blocks
-// in one launch per kernel (Eq. 14, 19: invert W_kk, alpha_kj = -W_kk^-1 W_kj,
-// W_ij += W_ki^T alpha_kj).
+// The elimination of every job (Eq. 14, 19: invert W_kk, alpha_kj =
+// -W_kk^-1 W_kj, W_ij += W_ki^T alpha_kj): step k of all jobs with more than
+// k blocks shares one factor/alpha launch and one Schur launch.
 void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
     Owned tmp;
     tmp.mem = jobs.front()->ctx->mem;
-    if (jobs.size() == 1) {
-        // one geometry: its task lists as built, operands at offsets from its buffers
-        SetupJob& j = *jobs.front();
-        hs_precond* P = j.P.get();
-        std::vector<hs::FactorTask> ft(j.nb);
-        for (int64_t k = 0; k < j.nb; ++k)
-            ft[k] = hs::FactorTask{j.W + j.wd_off[k], P->d_dinv + P->d_off[k], P->bsize[k], 0};
-        hs::FactorTask* d_ft = tmp.upload(ft, s);
-        hs::GemmTask* d_at = tmp.upload(j.at, s);
-        hs::GemmTask* d_st = tmp.upload(j.st, s);
-        for (int64_t k = 0; k < j.nb; ++k) {
-            hs::launch_factor_inv(d_ft + k, 1, j.d_err, s);
-            hs::launch_gemm(d_at + j.at_ptr[k], j.at_ptr[k + 1] - j.at_ptr[k], P->d_dinv, j.W, j.Ad, false, false, -1.0,
-                            s);
-            hs::launch_gemm(d_st + j.st_ptr[k], j.st_ptr[k + 1] - j.st_ptr[k], j.W, j.Ad, j.W, true, true, 1.0, s);
-        }
-        hip_check(hipStreamSynchronize(s), "stream sync");
-        return;
-    }
     int64_t steps = 0;
-    for (auto* j : jobs) steps = std::max(steps, j->nb);
-    std::vector<hs::FactorTask> ft;
-    std::vector<hs::GemmTaskP> at, st;
-    std::vector<int64_t> fp(steps + 1, 0), ap(steps + 1, 0), sp(steps + 1, 0);
+    std::vector<hs::ElimStep> es;
+    std::vector<int64_t> base;
+    for (auto* j : jobs) {
+        hs_precond* P = j->P.get();
+        const hs::Symbolic& sy = P->plan.sym;
+        steps = std::max(steps, j->nb);
+        const int32_t* d_rp = tmp.upload(j->rp32, s);
+        const int32_t* d_cols = tmp.upload(j->cols32, s);
+        const int64_t* d_woff = tmp.upload(j->w_off, s);
+        const int64_t* d_wdoff = tmp.upload(j->wd_off, s);
+        const int32_t* d_pcol = tmp.upload(j->pcol, s);
+        int64_t* d_pair = tmp.get<int64_t>(std::max<int64_t>(j->pair_ptr[j->nb], 1));
+        std::vector<hs::PairStep> ps;
+        base.push_back((int64_t)es.size());
+        for (int64_t k = 0; k < j->nb; ++k) {
+            const int64_t r0 = sy.rowptr[k];
+            const int32_t ne = (int32_t)(sy.rowptr[k + 1] - r0);
+            if (ne > 0) ps.push_back(hs::PairStep{d_cols + r0, d_rp, d_cols, d_woff, d_wdoff, d_pair + j->pair_ptr[k], ne, 0});
+            hs::ElimStep e{};
+            e.wkk = j->W + j->wd_off[k];
+            e.dinv = P->d_dinv + P->d_off[k];
+            e.x = ne > 0 ? j->W + j->w_off[r0] : j->W;
+            e.y = ne > 0 ? j->Ad + j->ad_off[r0] : j->Ad;
+            e.w = j->W;
+            e.pair = d_pair + j->pair_ptr[k];
+            e.pcol = d_pcol + r0 + k;
+            e.err = j->d_err;
+            e.bk = P->bsize[k];
+            e.ne = ne;
+            e.m = j->panel_m[k];
+            es.push_back(e);
+        }
+        hs::PairStep* d_ps = tmp.upload(ps, s);
+        hs::launch_pair_table(d_ps, (int64_t)ps.size(), j->d_err, s);
+    }
+    // per step: factor/alpha tiles (one per 64 panel columns, at least one)
+    // and Schur tiles of every job
+    std::vector<hs::ElimTile> ft, st;
+    std::vector<int64_t> fp(steps + 1, 0), sp(steps + 1, 0);
     for (int64_t k = 0; k < steps; ++k) {
-        for (auto* j : jobs) {
+        for (size_t q = 0; q < jobs.size(); ++q) {
+            SetupJob* j = jobs[q];
             if (k >= j->nb) continue;
-            hs_precond* P = j->P.get();
-            ft.push_back(hs::FactorTask{j->W + j->wd_off[k], P->d_dinv + P->d_off[k], P->bsize[k], 0});
-            for (int64_t q = j->at_ptr[k]; q < j->at_ptr[k + 1]; ++q) {
-                const hs::GemmTask& t = j->at[q];
-                at.push_back(hs::GemmTaskP{j->Ad + t.c_off, P->d_dinv + t.a_off, j->W + t.b_off, t.m, t.n, t.kk, 0});
-            }
-            for (int64_t q = j->st_ptr[k]; q < j->st_ptr[k + 1]; ++q) {
-                const hs::GemmTask& t = j->st[q];
-                st.push_back(hs::GemmTaskP{j->W + t.c_off, j->W + t.a_off, j->Ad + t.b_off, t.m, t.n, t.kk, 0});
-            }
+            const int32_t step = (int32_t)(base[q] + k);
+            const int32_t nt = std::max<int32_t>(1, (j->panel_m[k] + 63) / 64);
+            for (int32_t t = 0; t < nt; ++t) ft.push_back(hs::ElimTile{step, (int16_t)t, 0});
+            for (int64_t t = j->tile_ptr[k]; t < j->tile_ptr[k + 1]; ++t)
+                st.push_back(hs::ElimTile{step, j->tiles[t].first, j->tiles[t].second});
         }
         fp[k + 1] = (int64_t)ft.size();
-        ap[k + 1] = (int64_t)at.size();
         sp[k + 1] = (int64_t)st.size();
     }
-    hs::FactorTask* d_ft = tmp.upload(ft, s);
-    hs::GemmTaskP* d_at = tmp.upload(at, s);
-    hs::GemmTaskP* d_st = tmp.upload(st, s);
-    // one error flag per job would be finer; the first job's flag serves all
-    int* d_err = jobs.front()->d_err;
+    hs::ElimStep* d_es = tmp.upload(es, s);
+    hs::ElimTile* d_ft = tmp.upload(ft, s);
+    hs::ElimTile* d_st = tmp.upload(st, s);
     for (int64_t k = 0; k < steps; ++k) {
-        hs::launch_factor_inv(d_ft + fp[k], fp[k + 1] - fp[k], d_err, s);
-        hs::launch_gemm_p(d_at + ap[k], ap[k + 1] - ap[k], false, false, -1.0, s);
-        hs::launch_gemm_p(d_st + sp[k], sp[k + 1] - sp[k], true, true, 1.0, s);
+        hs::launch_factor_alpha(d_es, d_ft + fp[k], fp[k + 1] - fp[k], s);
+        hs::launch_schur_tiles(d_es, d_st + sp[k], sp[k + 1] - sp[k], s);
     }
+    hip_check(hipGetLastError(), "elimination launches");
     hip_check(hipStreamSynchronize(s), "stream sync");
 }
 

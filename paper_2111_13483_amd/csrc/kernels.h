@@ -13,6 +13,7 @@ constexpr int kMaxRankCap = 256;   // largest ACA rank a block may reach
 enum : int { kErrSingular = 1, kErrNumeric = 2, kErrRankCap = 4, kErrCoincident = 8 };
 
 constexpr int kMaxLeaf = 96;       // largest leaf block the dense kernels take (LDS bound)
+constexpr int kMaxPattern = 1024;  // longest row of the filled pattern the elimination takes
 
 // Per-column GMRES state on the device.
 struct ColState {
@@ -122,21 +123,43 @@ struct PtrCopy {
 };
 void launch_copy_ptrs(const PtrCopy* tasks, int64_t ntasks, cd* dst, hipStream_t s);
 void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s);
-// One diagonal block to invert: b x b row-major at w, inverse to dinv.
-struct FactorTask {
-    const cd* w;
-    cd* dinv;
-    int32_t b, pad;
+// One elimination step k of one geometry (Eq. 14, 19). The pattern blocks
+// W_kj of row k (j in S_k ascending) lie back to back at x, b_k x b_j each,
+// row-major; alpha_kj gets the same packing at y. Panel column g (< m) of the
+// step is local column g - pcol[a] of block a, pcol[a] <= g < pcol[a + 1].
+// pair[tri(a, b)], a <= b < ne, row-major over the upper triangle, is the
+// offset from w of target block (S_k[a], S_k[b]).
+struct ElimStep {
+    const cd* wkk;         // W_kk, b_k x b_k row-major
+    cd* dinv;              // W_kk^-1 (out)
+    const cd* x;           // W_kS panel
+    cd* y;                 // alpha_kS panel (out)
+    cd* w;                 // base of the Schur targets
+    const int64_t* pair;   // ne (ne + 1) / 2 target offsets
+    const int32_t* pcol;   // ne + 1 panel column starts
+    int* err;              // device error flag of the geometry
+    int32_t bk, ne, m, pad;
 };
-void launch_factor_inv(const FactorTask* tasks, int64_t ntasks, int* err, hipStream_t s);
-// A GEMM with operands by pointer: C (m x n) (+)= sign op(A) B.
-struct GemmTaskP {
-    cd* c;
-    const cd* a;
-    const cd* b;
-    int32_t m, n, kk, pad;
+// One workgroup's share of a step: panel column tile ti (factor/alpha) or
+// output tile (ti, tj) (Schur update).
+struct ElimTile {
+    int32_t step;
+    int16_t ti, tj;
 };
-void launch_gemm_p(const GemmTaskP* tasks, int64_t ntasks, bool transA, bool accumulate, double sign, hipStream_t s);
+// Input of the pair tables: S_k (ne entries) and the filled pattern in CSR
+// with the W offsets of its blocks.
+struct PairStep {
+    const int32_t* sk;
+    const int32_t* rowptr;
+    const int32_t* cols;
+    const int64_t* w_off;
+    const int64_t* wd_off;
+    int64_t* pair;
+    int32_t ne, pad;
+};
+void launch_pair_table(const PairStep* steps, int64_t nsteps, int* err, hipStream_t s);
+void launch_factor_alpha(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, hipStream_t s);
+void launch_schur_tiles(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, hipStream_t s);
 void launch_gemm(const GemmTask* tasks, int64_t ntasks, const cd* A, const cd* B, cd* C, bool transA, bool accumulate,
                  double sign, hipStream_t s);
 

@@ -1,11 +1,10 @@
-// gfx950 kernels of the symmetric Schur-complement elimination (Sec. 3.1-3.2):
-//  * block copies (scatter of the near field into the working blocks W);
-//  * inversion of the diagonal block W_kk by in-place Gauss-Jordan with
-//    partial pivoting in LDS (the matrix inversion of Eq. 31-33);
-//  * a batched variable-size complex GEMM used for both the scaling
-//    coefficients alpha_kj = -W_kk^-1 W_kj (Eq. 14, 34-37) and the Schur
-//    updates W_ij += W_ki^T alpha_kj (Eq. 19, 38-42): 64 x 64 output tiles,
-//    4 x 4 complex register micro-tiles per thread, K staged through LDS.
+// gfx950 set-up kernels around the elimination:
+//  * block copies (scatter of the near field into the working blocks W, D,
+//    the dense part of the alpha store) and pointer-list copies;
+//  * complex64 copies of stored blocks for the mixed-precision solve;
+//  * a batched variable-size complex GEMM (64 x 64 output tiles, 4 x 4
+//    complex register micro-tiles per thread, K staged through LDS), used for
+//    the coupling products of the sweep plan.
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -52,77 +51,6 @@ __global__ void __launch_bounds__(NT) k_to_c64(const PtrCopy* __restrict__ tasks
         w.y = (float)v.y;
         d[e] = w;
     }
-}
-
-// In-place Gauss-Jordan inversion with partial pivoting (row pivot: largest
-// |a|^2, ties to the lowest row) of one b x b block held in LDS; one block
-// per workgroup (the diagonal blocks of one elimination step, one per
-// geometry of a batch).
-__global__ void __launch_bounds__(NT)
-k_factor_inv(const FactorTask* __restrict__ tasks, int* err) {
-    const FactorTask ft = tasks[blockIdx.x];
-    const int b = ft.b;
-    constexpr int LD = kMaxLeaf + 1;
-    __shared__ cd A[kMaxLeaf * LD];
-    __shared__ cd colc[kMaxLeaf];
-    __shared__ int ipiv[kMaxLeaf];
-    __shared__ int s_piv;
-    __shared__ double s_mag;
-    const int tid = threadIdx.x;
-    const cd* src = ft.w;
-    for (int e = tid; e < b * b; e += NT) A[(e / b) * LD + e % b] = src[e];
-    __syncthreads();
-    for (int c = 0; c < b; ++c) {
-        if (tid < kWave) {
-            ArgMax am{-1.0, 0x7fffffff};
-            for (int r = c + tid; r < b; r += kWave) am = amax_pick(am, ArgMax{cabs2_exact(A[r * LD + c]), r});
-            am = wave_argmax(am);
-            if (tid == 0) { s_piv = am.i; s_mag = am.v; }
-        }
-        __syncthreads();
-        const int p = s_piv;
-        const double mag = s_mag;
-        if (!(mag > 0.0)) {
-            if (tid == 0) raise_err(err, mag == 0.0 ? kErrSingular : kErrNumeric);
-            return;
-        }
-        if (tid == 0) ipiv[c] = p;
-        if (p != c)
-            for (int j = tid; j < b; j += NT) {
-                cd tmp = A[c * LD + j];
-                A[c * LD + j] = A[p * LD + j];
-                A[p * LD + j] = tmp;
-            }
-        __syncthreads();
-        const cd inv = cdiv(cmk(1.0, 0.0), A[c * LD + c]);
-        for (int r = tid; r < b; r += NT) colc[r] = A[r * LD + c];
-        __syncthreads();
-        // scale row c (its pivot entry becomes 1/pivot)
-        for (int j = tid; j < b; j += NT) A[c * LD + j] = (j == c) ? inv : cmul(A[c * LD + j], inv);
-        __syncthreads();
-        // eliminate column c from every other row
-        for (int e = tid; e < b * b; e += NT) {
-            const int r = e / b, j = e % b;
-            if (r == c) continue;
-            const cd f = colc[r];
-            if (j == c) A[r * LD + j] = cmk(-(f.x * inv.x - f.y * inv.y), -(f.x * inv.y + f.y * inv.x));
-            else A[r * LD + j] = csub(A[r * LD + j], cmul(f, A[c * LD + j]));
-        }
-        __syncthreads();
-    }
-    // undo the row interchanges as column interchanges, last first
-    for (int c = b - 1; c >= 0; --c) {
-        const int p = ipiv[c];
-        if (p != c)
-            for (int r = tid; r < b; r += NT) {
-                cd tmp = A[r * LD + c];
-                A[r * LD + c] = A[r * LD + p];
-                A[r * LD + p] = tmp;
-            }
-        __syncthreads();
-    }
-    cd* out = ft.dinv;
-    for (int e = tid; e < b * b; e += NT) out[e] = A[(e / b) * LD + e % b];
 }
 
 // Complex GEMM of one task by one workgroup, 64 x 64 output tiles, 4 x 4
@@ -196,15 +124,6 @@ k_gemm(const GemmTask* __restrict__ tasks, const cd* __restrict__ Ag, const cd* 
     gemm_task<TRANS_A>(Ag + t.a_off, Bg + t.b_off, Cg + t.c_off, t.m, t.n, t.kk, accumulate, sign);
 }
 
-// Batched GEMM, one task per workgroup, operands by pointer (tasks of
-// several geometries in one launch).
-template <bool TRANS_A>
-__global__ void __launch_bounds__(NT)
-k_gemm_p(const GemmTaskP* __restrict__ tasks, int accumulate, double sign) {
-    const GemmTaskP t = tasks[blockIdx.x];
-    gemm_task<TRANS_A>(t.a, t.b, t.c, t.m, t.n, t.kk, accumulate, sign);
-}
-
 void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s) {
     if (ntasks > 0) hipLaunchKernelGGL(k_copy_blocks, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, src, dst);
 }
@@ -215,18 +134,6 @@ void launch_copy_ptrs(const PtrCopy* tasks, int64_t ntasks, cd* dst, hipStream_t
 
 void launch_to_c64(const PtrCopy* tasks, int64_t ntasks, cf* dst, hipStream_t s) {
     if (ntasks > 0) hipLaunchKernelGGL(k_to_c64, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, dst);
-}
-
-void launch_factor_inv(const FactorTask* tasks, int64_t ntasks, int* err, hipStream_t s) {
-    if (ntasks > 0) hipLaunchKernelGGL(k_factor_inv, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, err);
-}
-
-void launch_gemm_p(const GemmTaskP* tasks, int64_t ntasks, bool transA, bool accumulate, double sign, hipStream_t s) {
-    if (ntasks == 0) return;
-    if (transA)
-        hipLaunchKernelGGL(k_gemm_p<true>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, (int)accumulate, sign);
-    else
-        hipLaunchKernelGGL(k_gemm_p<false>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, (int)accumulate, sign);
 }
 
 void launch_gemm(const GemmTask* tasks, int64_t ntasks, const cd* A, const cd* B, cd* C, bool transA, bool accumulate,
