@@ -21,19 +21,29 @@ namespace hs {
 namespace {
 
 constexpr int NT = 256;
+constexpr int NTF = 512;            // the factor/alpha kernel: eight waves
+constexpr int NWF = NTF / kWave;
 constexpr int kLdc = kMaxLeaf + 1;   // column stride of the LDS inverse (odd: conflict-free column writes)
 constexpr int kTile = 64;            // panel tile edge
 constexpr int kKc = 32;              // K chunk of the Schur tiles
 
-// panel column g -> (block a, local column) by binary search over pcol[0..ne]
-__device__ __forceinline__ int panel_block(const int* pcol, int ne, int g) {
-    int lo = 0, hi = ne - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pcol[mid] <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+// loads and stores through global-address-space pointers (global_* rather
+// than flat_* instructions, so waits count only memory operations)
+template <class T>
+__device__ __forceinline__ T gld(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+typedef double v2d __attribute__((ext_vector_type(2)));
+template <>
+__device__ __forceinline__ cd gld<cd>(const cd* p) {
+    const v2d v = *(const __attribute__((address_space(1))) v2d*)p;
+    return cmk(v.x, v.y);
+}
+__device__ __forceinline__ void gst(cd* p, cd v) {
+    v2d t;
+    t.x = v.x;
+    t.y = v.y;
+    *(__attribute__((address_space(1))) v2d*)p = t;
 }
 
 }  // namespace
@@ -74,61 +84,121 @@ __global__ void __launch_bounds__(NT) k_pair_table(const PairStep* __restrict__ 
     }
 }
 
+// 1 / a as conj(a) / |a|^2: one division (pivots are far from the
+// overflow and underflow ranges)
+__device__ __forceinline__ cd crecip(cd a) {
+    const double r = 1.0 / cabs2_exact(a);
+    return cmk(a.x * r, -a.y * r);
+}
+
+// DPP lane moves of a double (whole wave active)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+// maximum over the wave (NaN ignored unless every lane holds one)
+__device__ __forceinline__ double wave_max_f64(double v) {
+    v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_f64<0x124>(v));   // row_ror:4
+    v = fmax(v, dpp_f64<0x128>(v));   // row_ror:8
+    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
+// Pivot row of a column held as (row lane, value n0) and (row lane + 64, n1):
+// largest |a|^2 among rows lo..b-1, ties to the lowest row. Returns the row,
+// or -1 (all zero: singular) / -2 (no finite candidate).
+__device__ __forceinline__ int pivot_row(cd n0, cd n1, int lo, int b, bool two) {
+    const int lane = threadIdx.x % kWave;
+    const int r0 = lane, r1 = lane + kWave;
+    double v0 = (r0 >= lo && r0 < b) ? cabs2_exact(n0) : -1.0;
+    const double v1 = (two && r1 >= lo && r1 < b) ? cabs2_exact(n1) : -1.0;
+    const bool pick1 = v1 > v0;
+    const double v = pick1 ? v1 : v0;
+    const double vmax = wave_max_f64(v);
+    if (!(vmax > 0.0)) return vmax == 0.0 ? -1 : -2;
+    const unsigned long long m0 = __ballot(v == vmax && !pick1);
+    if (m0) return __ffsll((long long)m0) - 1;
+    return __ffsll((long long)__ballot(v == vmax)) - 1 + kWave;
+}
+
 // Gauss-Jordan inversion of W_kk with partial pivoting (row pivot: largest
 // |a|^2 among the rows not yet eliminated, ties to the lowest row; rows
-// interchanged as they are chosen, columns interchanged back at the end),
-// then one tile of alpha. The block sits column-major in LDS; lane r of every
-// wave owns rows r and r + 64, the four waves take the columns in turn. The
-// pivot column of the next step is copied aside as it is produced, so a step
-// needs one barrier: every wave finds the pivot itself from that copy.
-__global__ void __launch_bounds__(NT) k_factor_alpha(const ElimStep* __restrict__ steps,
-                                                     const ElimTile* __restrict__ tiles) {
-    const ElimTile tl = tiles[blockIdx.x];
-    const ElimStep st = steps[tl.step];
-    const int b = st.bk;
-    __shared__ cd A[kMaxLeaf * kLdc];
-    __shared__ cd colbuf[2][kMaxLeaf];
-    __shared__ int srcmap[kMaxLeaf];
-    __shared__ int pcol[kMaxPattern + 1];
-    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
-    for (int e = tid; e < b * b; e += NT) {
-        const int i = e / b, j = e - (e / b) * b;
-        const cd v = st.wkk[e];
-        A[j * kLdc + i] = v;
-        if (j == 0) colbuf[0][i] = v;
-    }
-    for (int a = tid; a <= st.ne; a += NT) pcol[a] = st.pcol[a];
+// interchanged as they are chosen, columns interchanged back at the end).
+// The block lives in registers: wave w holds columns w, w + 8, ... (S slots),
+// lane r rows r and r + 64 (TWO), so row interchanges and the pivot row are
+// read across lanes. In step c the wave holding column c + 1 publishes it
+// (the multipliers of the next step), finds the next pivot in it and
+// publishes the pivot row and its reciprocal: a step costs one exchange
+// through LDS and one barrier. On return the eliminated block is in LDS
+// (column-major, stride kLdc) and srcmap holds the column interchanges;
+// false if the block is singular (the error flag is raised).
+template <int S, bool TWO>
+__device__ __forceinline__ bool gj_invert(const cd* __restrict__ wkk, int b, int* err, cd* A, cd (*colbuf)[kMaxLeaf],
+                                          cd* pinv, int* prow, int* srcmap) {
+    const int tid = threadIdx.x, lane = tid % kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int r0 = lane, r1 = lane + kWave;
-    const bool two = b > kWave;
+    const bool v0 = r0 < b, v1 = TWO && r1 < b;
+    cd a0[S], a1[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+        const int j = wv + NWF * u;
+        const int jj = j < b ? j : 0;
+        a0[u] = gld(wkk + (v0 ? r0 : 0) * b + jj);
+        a1[u] = TWO ? gld(wkk + (v1 ? r1 : 0) * b + jj) : cmk(0.0, 0.0);
+    }
     int x0 = lane, x1 = lane + kWave;   // source column trackers of the final column interchanges
+    auto publish = [&](int jn, cd e0, cd e1) {
+        cd* nb = colbuf[jn & 1];
+        if (v0) nb[r0] = e0;
+        if (v1) nb[r1] = e1;
+        const int q = pivot_row(e0, e1, jn, b, TWO);
+        cd qinv = cmk(0.0, 0.0);
+        if (q >= 0)
+            qinv = crecip(q < kWave ? cmk(readlane_f64(e0.x, q), readlane_f64(e0.y, q))
+                                    : cmk(readlane_f64(e1.x, q - kWave), readlane_f64(e1.y, q - kWave)));
+        if (lane == 0) {
+            prow[jn & 1] = q;
+            pinv[jn & 1] = qinv;
+        }
+    };
+    if (wv == 0) publish(0, a0[0], a1[0]);
     __syncthreads();
     for (int c = 0; c < b; ++c) {
-        const cd* cb = colbuf[c & 1];
-        ArgMax am{-1.0, 0x7fffffff};
-        if (r0 >= c && r0 < b) am = ArgMax{cabs2_exact(cb[r0]), r0};
-        if (two && r1 >= c && r1 < b) am = amax_pick(am, ArgMax{cabs2_exact(cb[r1]), r1});
-        am = wave_argmax(am);
-        const int p = am.i;
-        if (!(am.v > 0.0)) {
-            if (tid == 0) raise_err(st.err, am.v == 0.0 ? kErrSingular : kErrNumeric);
-            return;   // every wave takes the same decision
+        const int p = __builtin_amdgcn_readfirstlane(prow[c & 1]);
+        const cd inv = pinv[c & 1];
+        if (p < 0) {
+            if (tid == 0) raise_err(err, p == -1 ? kErrSingular : kErrNumeric);
+            return false;   // every wave reads the same pivot
         }
-        const cd inv = cdiv(cmk(1.0, 0.0), cb[p]);
+        const cd* cb = colbuf[c & 1];
         // after interchanging rows c and p, row r holds what row srow(r) held
         const int s0 = r0 == c ? p : (r0 == p ? c : r0);
         const int s1 = r1 == c ? p : (r1 == p ? c : r1);
-        const cd f0 = cb[s0 < b ? s0 : 0];
-        const cd f1 = two ? cb[s1 < b ? s1 : 0] : cmk(0.0, 0.0);
+        const cd f0 = v0 ? cb[s0] : cmk(0.0, 0.0);
+        const cd f1 = v1 ? cb[s1] : cmk(0.0, 0.0);
         x0 = x0 == c ? p : (x0 == p ? c : x0);
         x1 = x1 == c ? p : (x1 == p ? c : x1);
-        cd* nb = colbuf[(c + 1) & 1];
-        for (int j = wv; j < b; j += NT / kWave) {
-            cd* col = A + j * kLdc;
-            // every read of this column before any write to it
-            const cd pj = col[p];
-            const cd o0 = col[s0 < b ? s0 : 0];
-            const cd o1 = two ? col[s1 < b ? s1 : 0] : cmk(0.0, 0.0);
-            const cd pjs = (j == c) ? inv : cmul(pj, inv);
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            const int j = wv + NWF * u;
+            cd& e0 = a0[u];
+            cd& e1 = a1[u];
+            const cd pv = (!TWO || p < kWave) ? cmk(readlane_f64(e0.x, p), readlane_f64(e0.y, p))
+                                              : cmk(readlane_f64(e1.x, p - kWave), readlane_f64(e1.y, p - kWave));
+            const cd cv = (!TWO || c < kWave) ? cmk(readlane_f64(e0.x, c), readlane_f64(e0.y, c))
+                                              : cmk(readlane_f64(e1.x, c - kWave), readlane_f64(e1.y, c - kWave));
+            const cd o0 = r0 == c ? pv : (r0 == p ? cv : e0);
+            const cd o1 = r1 == c ? pv : (r1 == p ? cv : e1);
+            const cd pjs = (j == c) ? inv : cmul(pv, inv);
             cd n0, n1;
             if (r0 == c) n0 = pjs;
             else if (j == c) n0 = cmk(-(f0.x * inv.x - f0.y * inv.y), -(f0.x * inv.y + f0.y * inv.x));
@@ -136,37 +206,84 @@ __global__ void __launch_bounds__(NT) k_factor_alpha(const ElimStep* __restrict_
             if (r1 == c) n1 = pjs;
             else if (j == c) n1 = cmk(-(f1.x * inv.x - f1.y * inv.y), -(f1.x * inv.y + f1.y * inv.x));
             else n1 = csub(o1, cmul(f1, pjs));
-            if (r0 < b) {
-                col[r0] = n0;
-                if (j == c + 1) nb[r0] = n0;
-            }
-            if (two && r1 < b) {
-                col[r1] = n1;
-                if (j == c + 1) nb[r1] = n1;
-            }
+            e0 = n0;
+            if (TWO) e1 = n1;
+        }
+        const int jn = c + 1;
+        if (jn < b && jn % NWF == wv) {
+            // the next pivot column, picked out of the slots
+            const int un = jn / NWF;
+            cd e0 = a0[0], e1 = a1[0];
+#pragma unroll
+            for (int u = 1; u < S; ++u)
+                if (u == un) {
+                    e0 = a0[u];
+                    e1 = a1[u];
+                }
+            publish(jn, e0, e1);
         }
         __syncthreads();
     }
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+        const int j = wv + NWF * u;
+        if (j < b) {
+            if (v0) A[j * kLdc + r0] = a0[u];
+            if (v1) A[j * kLdc + r1] = a1[u];
+        }
+    }
     if (wv == 0) {
-        if (r0 < b) srcmap[r0] = x0;
-        if (two && r1 < b) srcmap[r1] = x1;
+        if (lane < b) srcmap[lane] = x0;
+        if (lane + kWave < b) srcmap[lane + kWave] = x1;
     }
     __syncthreads();
+    return true;
+}
+
+// W_kk^-1 (Gauss-Jordan above), then one 64-column tile of alpha.
+__global__ void __launch_bounds__(NTF) k_factor_alpha(const ElimStep* __restrict__ steps,
+                                                      const ElimTile* __restrict__ tiles) {
+    const ElimTile tl = tiles[blockIdx.x];
+    const ElimStep st = steps[tl.step];
+    const int b = st.bk;
+    __shared__ cd A[kMaxLeaf * kLdc];
+    __shared__ cd colbuf[2][kMaxLeaf];
+    __shared__ cd pinv[2];
+    __shared__ int prow[2];
+    __shared__ int srcmap[kMaxLeaf];
+    __shared__ int pcol[kMaxPattern + 1];
+    const int tid = threadIdx.x, lane = tid % kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    for (int a = tid; a <= st.ne; a += NTF) pcol[a] = gld(st.pcol + a);
+    bool ok;
+    if (b <= 3 * NWF) ok = gj_invert<3, false>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
+    else if (b <= 4 * NWF) ok = gj_invert<4, false>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
+    else if (b <= kWave) ok = gj_invert<8, false>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
+    else ok = gj_invert<(kMaxLeaf + NWF - 1) / NWF, true>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
+    if (!ok) return;
     // W_kk^-1[i][j] = A[i][srcmap[j]]
     if (tl.ti == 0)
-        for (int e = tid; e < b * b; e += NT) {
+        for (int e = tid; e < b * b; e += NTF) {
             const int i = e / b, j = e - (e / b) * b;
-            st.dinv[e] = A[srcmap[j] * kLdc + i];
+            gst(st.dinv + e, A[srcmap[j] * kLdc + i]);
         }
-    // alpha tile: Y[r][g] = -sum_l W_kk^-1[r][l] X[l][g], lane = column, wave = rows wv, wv + 4, ...
-    const int g = tl.ti * kTile + lane;
+    // panel block of each column of this tile: every block marks its span
+    __shared__ int cblk[kTile];
+    const int g0 = tl.ti * kTile;
+    for (int a = tid; a < st.ne; a += NTF) {
+        const int lo = pcol[a] > g0 ? pcol[a] : g0, hi = pcol[a + 1] < g0 + kTile ? pcol[a + 1] : g0 + kTile;
+        for (int g = lo; g < hi; ++g) cblk[g - g0] = a;
+    }
+    __syncthreads();
+    // alpha tile: Y[r][g] = -sum_l W_kk^-1[r][l] X[l][g], lane = column, wave = rows wv, wv + 8, ...
+    const int g = g0 + lane;
     if (g >= st.m) return;
-    const int a = panel_block(pcol, st.ne, g);
+    const int a = cblk[lane];
     const int bj = pcol[a + 1] - pcol[a];
     const int64_t off = (int64_t)b * pcol[a] + (g - pcol[a]);
     const cd* xg = st.x + off;
     cd* yg = st.y + off;
-    constexpr int RW = (kMaxLeaf + 3) / 4;
+    constexpr int RW = (kMaxLeaf + NWF - 1) / NWF;
     cd acc[RW];
 #pragma unroll
     for (int q = 0; q < RW; ++q) acc[q] = cmk(0.0, 0.0);
@@ -174,7 +291,7 @@ __global__ void __launch_bounds__(NT) k_factor_alpha(const ElimStep* __restrict_
     for (int l0 = 0; l0 < b; l0 += LB) {
         cd xv[LB];
 #pragma unroll
-        for (int u = 0; u < LB; ++u) xv[u] = (l0 + u < b) ? xg[(int64_t)(l0 + u) * bj] : cmk(0.0, 0.0);
+        for (int u = 0; u < LB; ++u) xv[u] = gld(xg + (int64_t)(l0 + u < b ? l0 + u : b - 1) * bj);
 #pragma unroll
         for (int u = 0; u < LB; ++u) {
             const int l = l0 + u;
@@ -182,15 +299,15 @@ __global__ void __launch_bounds__(NT) k_factor_alpha(const ElimStep* __restrict_
             const cd* dcol = A + srcmap[l] * kLdc;
 #pragma unroll
             for (int q = 0; q < RW; ++q) {
-                const int r = wv + 4 * q;
+                const int r = wv + NWF * q;
                 if (r < b) acc[q] = cfma(dcol[r], xv[u], acc[q]);
             }
         }
     }
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
-        const int r = wv + 4 * q;
-        if (r < b) yg[(int64_t)r * bj] = cscale(acc[q], -1.0);
+        const int r = wv + NWF * q;
+        if (r < b) gst(yg + (int64_t)r * bj, cscale(acc[q], -1.0));
     }
 }
 
@@ -203,42 +320,89 @@ __global__ void __launch_bounds__(NT) k_schur_tiles(const ElimStep* __restrict__
     const int kk = st.bk, m = st.m, ne = st.ne;
     __shared__ cd Xs[kKc][kTile];
     __shared__ cd Ys[kKc][kTile];
-    __shared__ int pcol[kMaxPattern + 1];
-    __shared__ int rblk[kTile], cblk[kTile];
-    __shared__ int64_t roff[kTile], coff[kTile];
-    __shared__ int rbj[kTile], cbj[kTile];
+    __shared__ int rblk[kTile], cblk[kTile];   // panel block of each tile row / column (-1 past the panel)
+    __shared__ int rst[kTile], cst[kTile];     // its first panel column
+    __shared__ int rbj[kTile], cbj[kTile];     // its width
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    for (int a = tid; a <= ne; a += NT) pcol[a] = st.pcol[a];
+    const int gr = tl.ti * kTile, gc = tl.tj * kTile;
+    if (tid < kTile) { rblk[tid] = -1; cblk[tid] = -1; }
     __syncthreads();
-    if (tid < 2 * kTile) {
-        const int c = tid % kTile;
-        const int g = (tid < kTile ? tl.ti : tl.tj) * kTile + c;
-        int a = -1, bj = 0;
-        int64_t off = 0;
-        if (g < m) {
-            a = panel_block(pcol, ne, g);
-            bj = pcol[a + 1] - pcol[a];
-            off = (int64_t)kk * pcol[a] + (g - pcol[a]);
+    // every block marks its span in the row tile and in the column tile
+    for (int a = tid; a < ne; a += NT) {
+        const int p0 = gld(st.pcol + a), p1 = gld(st.pcol + a + 1);
+        for (int g = (p0 > gr ? p0 : gr); g < (p1 < gr + kTile ? p1 : gr + kTile); ++g) {
+            rblk[g - gr] = a; rst[g - gr] = p0; rbj[g - gr] = p1 - p0;
         }
-        if (tid < kTile) { rblk[c] = a; rbj[c] = bj; roff[c] = off; }
-        else { cblk[c] = a; cbj[c] = bj; coff[c] = off; }
+        for (int g = (p0 > gc ? p0 : gc); g < (p1 < gc + kTile ? p1 : gc + kTile); ++g) {
+            cblk[g - gc] = a; cst[g - gc] = p0; cbj[g - gc] = p1 - p0;
+        }
+    }
+    __syncthreads();
+    // target of (p, q): W + pair[tri(a_p, a_q)] + (local row) * b_q + (local
+    // column). Targets lie in later block rows than the panels and belong to
+    // this tile alone, so they are read before the product is formed.
+    int64_t dst[4][4];
+    bool live[4][4];
+    {
+        int ap[4], lr[4], aq[4], lc[4], bq[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int pr = ty * 4 + i, qc = tx * 4 + i;
+            ap[i] = rblk[pr];
+            lr[i] = gr + pr - rst[pr];
+            aq[i] = cblk[qc];
+            lc[i] = gc + qc - cst[qc];
+            bq[i] = cbj[qc];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t tbase = (int64_t)ap[i] * ne - (int64_t)ap[i] * (ap[i] - 1) / 2 - ap[i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                live[i][j] = ap[i] >= 0 && aq[j] >= ap[i];   // aq = -1 past the panel
+                dst[i][j] = gld(st.pair + (live[i][j] ? tbase + aq[j] : 0));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dst[i][j] = live[i][j] ? dst[i][j] + (int64_t)lr[i] * bq[j] + lc[j] : 0;
     }
     cd acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = cmk(0.0, 0.0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = gld(st.w + dst[i][j]);
+    // staging: thread tid always serves panel column tid % 64 of both tiles,
+    // rows tid / 64 + 4 u of the K chunk
+    constexpr int SU = kKc * kTile / NT;
+    const int c = tid % kTile, l0 = tid / kTile;
+    const int ra = rblk[c], ca = cblk[c];
+    const int64_t ro = ra >= 0 ? (int64_t)kk * rst[c] + (gr + c - rst[c]) : 0;
+    const int64_t co = ca >= 0 ? (int64_t)kk * cst[c] + (gc + c - cst[c]) : 0;
+    const int rb = rbj[c], cbw = cbj[c];
+    // the product is accumulated from zero in ascending l and added once
+    cd prod[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) prod[i][j] = cmk(0.0, 0.0);
     for (int k0 = 0; k0 < kk; k0 += kKc) {
-        __syncthreads();
-        for (int e = tid; e < kKc * kTile; e += NT) {
-            const int l = e / kTile, c = e % kTile, gl = k0 + l;
-            cd xv = cmk(0.0, 0.0), yv = cmk(0.0, 0.0);
-            if (gl < kk) {
-                if (rblk[c] >= 0) xv = st.x[roff[c] + (int64_t)gl * rbj[c]];
-                if (cblk[c] >= 0) yv = st.y[coff[c] + (int64_t)gl * cbj[c]];
-            }
-            Xs[l][c] = xv;
-            Ys[l][c] = yv;
+        cd xv[SU], yv[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int gl = k0 + l0 + 4 * u;
+            const bool ok = gl < kk;
+            xv[u] = gld(st.x + ((ok && ra >= 0) ? ro + (int64_t)gl * rb : 0));
+            yv[u] = gld(st.y + ((ok && ca >= 0) ? co + (int64_t)gl * cbw : 0));
+        }
+        if (k0 > 0) __syncthreads();
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int gl = k0 + l0 + 4 * u;
+            const bool ok = gl < kk;
+            Xs[l0 + 4 * u][c] = (ok && ra >= 0) ? xv[u] : cmk(0.0, 0.0);
+            Ys[l0 + 4 * u][c] = (ok && ca >= 0) ? yv[u] : cmk(0.0, 0.0);
         }
         __syncthreads();
         const int lend = kk - k0 < kKc ? kk - k0 : kKc;
@@ -251,27 +415,14 @@ __global__ void __launch_bounds__(NT) k_schur_tiles(const ElimStep* __restrict__
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = cfma(av[i], bv[j], acc[i][j]);
+                for (int j = 0; j < 4; ++j) prod[i][j] = cfma(av[i], bv[j], prod[i][j]);
         }
     }
-    // target of (p, q): W + pair[tri(a_p, a_q)] + (local row) * b_q + (local column)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int pr = ty * 4 + i;
-        const int ap = rblk[pr];
-        if (ap < 0) continue;
-        const int lr = tl.ti * kTile + pr - pcol[ap];
-        const int64_t tbase = (int64_t)ap * ne - (int64_t)ap * (ap - 1) / 2 - ap;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int qc = tx * 4 + j;
-            const int aq = cblk[qc];
-            if (aq < ap) continue;   // also skips columns past the panel (aq = -1)
-            const int lc = tl.tj * kTile + qc - pcol[aq];
-            cd* dst = st.w + st.pair[tbase + aq] + (int64_t)lr * cbj[qc] + lc;
-            *dst = cadd(*dst, acc[i][j]);
-        }
-    }
+        for (int j = 0; j < 4; ++j)
+            if (live[i][j]) gst(st.w + dst[i][j], cadd(acc[i][j], prod[i][j]));
 }
 
 void launch_pair_table(const PairStep* steps, int64_t nsteps, int* err, hipStream_t s) {
@@ -279,7 +430,7 @@ void launch_pair_table(const PairStep* steps, int64_t nsteps, int* err, hipStrea
 }
 
 void launch_factor_alpha(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, hipStream_t s) {
-    if (ntiles > 0) hipLaunchKernelGGL(k_factor_alpha, dim3((unsigned)ntiles), dim3(NT), 0, s, steps, tiles);
+    if (ntiles > 0) hipLaunchKernelGGL(k_factor_alpha, dim3((unsigned)ntiles), dim3(NTF), 0, s, steps, tiles);
 }
 
 void launch_schur_tiles(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, hipStream_t s) {
