@@ -18,6 +18,9 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NW = NT / kWave;
+// Re-compression: one workgroup per block.
+constexpr int NTR = 256;
+constexpr int NWR = NTR / kWave;
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
 // exp(-j k r) / (4 pi r) with the products and sums rounded as written.
@@ -195,7 +198,7 @@ __device__ void cgs2_qr(cd* A, int len, int r, cd* R, cd* hbuf, double* red) {
     for (int c = 0; c < r; ++c) {
         cd* ac = A + (int64_t)c * len;
         for (int pass = 0; pass < 2; ++pass) {
-            for (int l = wid; l < c; l += NW) {
+            for (int l = wid; l < c; l += NWR) {
                 const cd* al = A + (int64_t)l * len;
                 cd d = cmk(0.0, 0.0);
                 for (int x = lane; x < len; x += kWave) d = cfmac(al[x], ac[x], d);
@@ -203,24 +206,24 @@ __device__ void cgs2_qr(cd* A, int len, int r, cd* R, cd* hbuf, double* red) {
                 if (lane == 0) hbuf[l] = d;
             }
             __syncthreads();
-            for (int x = tid; x < len; x += NT) {
+            for (int x = tid; x < len; x += NTR) {
                 cd v = ac[x];
                 for (int l = 0; l < c; ++l) v = csub(v, cmul(A[(int64_t)l * len + x], hbuf[l]));
                 ac[x] = v;
             }
-            for (int l = tid; l < c; l += NT) {
+            for (int l = tid; l < c; l += NTR) {
                 cd prev = pass == 0 ? cmk(0.0, 0.0) : R[l + (int64_t)c * r];
                 R[l + (int64_t)c * r] = cadd(prev, hbuf[l]);
             }
             __syncthreads();
         }
         double p = 0.0;
-        for (int x = tid; x < len; x += NT) p += cabs2(ac[x]);
-        const double nrm = sqrt(wg_sum<NT>(p, red));
+        for (int x = tid; x < len; x += NTR) p += cabs2(ac[x]);
+        const double nrm = sqrt(wg_sum<NTR>(p, red));
         const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        for (int x = tid; x < len; x += NT) ac[x] = cscale(ac[x], inv);
+        for (int x = tid; x < len; x += NTR) ac[x] = cscale(ac[x], inv);
         if (tid == 0) R[c + (int64_t)c * r] = cmk(nrm, 0.0);
-        for (int l = c + 1 + tid; l < r; l += NT) R[l + (int64_t)c * r] = cmk(0.0, 0.0);
+        for (int l = c + 1 + tid; l < r; l += NTR) R[l + (int64_t)c * r] = cmk(0.0, 0.0);
         __syncthreads();
     }
 }
@@ -235,7 +238,7 @@ __device__ void jacobi_svd(cd* M, cd* X, int r, int* rot_flag) {
         if (tid == 0) *rot_flag = 0;
         __syncthreads();
         for (int round = 0; round < np - 1; ++round) {
-            for (int pk = wid; pk < np / 2; pk += NW) {
+            for (int pk = wid; pk < np / 2; pk += NWR) {
                 int p, q;
                 if (pk == 0) { p = round; q = np - 1; }
                 else { p = (round + pk) % (np - 1); q = (round - pk + np - 1) % (np - 1); }
@@ -286,11 +289,11 @@ __device__ void jacobi_svd(cd* M, cd* X, int r, int* rot_flag) {
 // Re-compression, phase A: QR of U and V^T in place, core M = R_U R_V^T,
 // Jacobi SVD, singular values sorted (descending, ties by index) and the
 // truncated rank.
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NTR)
 k_recompress_a(const AcaTask* __restrict__ tasks, cd* __restrict__ scratch, const int* __restrict__ rank_in,
                cd* __restrict__ ws, const int64_t* __restrict__ ws_off, double eps, int* __restrict__ rank_out) {
     __shared__ cd hbuf[kMaxRankCap];
-    __shared__ double red[NW];
+    __shared__ double red[NWR];
     __shared__ int rot_flag;
     __shared__ double sig[kMaxRankCap];
     __shared__ int srt[kMaxRankCap];
@@ -310,7 +313,7 @@ k_recompress_a(const AcaTask* __restrict__ tasks, cd* __restrict__ scratch, cons
     int* srt_g = reinterpret_cast<int*>(X + (int64_t)r * r);
     cgs2_qr(U, t.m, r, RU, hbuf, red);
     cgs2_qr(V, t.n, r, RV, hbuf, red);
-    for (int e = tid; e < r * r; e += NT) {
+    for (int e = tid; e < r * r; e += NTR) {
         const int a = e % r, b = e / r;
         cd s = cmk(0.0, 0.0);
         // R_U upper triangular: l >= a; R_V: l >= b
@@ -321,14 +324,14 @@ k_recompress_a(const AcaTask* __restrict__ tasks, cd* __restrict__ scratch, cons
     __syncthreads();
     jacobi_svd(M, X, r, &rot_flag);
     __syncthreads();
-    for (int c = tid; c < r; c += NT) {
+    for (int c = tid; c < r; c += NTR) {
         double s = 0.0;
         for (int x = 0; x < r; ++x) s += cabs2(M[x + (int64_t)c * r]);
         sig[c] = sqrt(s);
     }
     __syncthreads();
     // rank sort: position of column c = #{d : sig[d] > sig[c] or (== and d < c)}
-    for (int c = tid; c < r; c += NT) {
+    for (int c = tid; c < r; c += NTR) {
         int pos = 0;
         for (int d = 0; d < r; ++d) pos += (sig[d] > sig[c]) || (sig[d] == sig[c] && d < c);
         srt[pos] = c;
@@ -347,12 +350,12 @@ k_recompress_a(const AcaTask* __restrict__ tasks, cd* __restrict__ scratch, cons
         }
         rank_out[blockIdx.x] = keep;
     }
-    for (int c = tid; c < r; c += NT) srt_g[c] = srt[c];
+    for (int c = tid; c < r; c += NTR) srt_g[c] = srt[c];
 }
 
 // Re-compression, phase B: write U' = Q_U M[:, srt[:r']] (m x r'
 // column-major) and V' = X[:, srt[:r']]^H Q_V^T (r' x n row-major).
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NTR)
 k_recompress_b(const AcaTask* __restrict__ tasks, const cd* __restrict__ scratch, const int* __restrict__ rank_in,
                const cd* __restrict__ ws, const int64_t* __restrict__ ws_off, const int* __restrict__ rank_new,
                cd* const* __restrict__ dst) {
@@ -368,14 +371,14 @@ k_recompress_b(const AcaTask* __restrict__ tasks, const cd* __restrict__ scratch
     cd* Uo = dst[blockIdx.x];
     if (Uo == nullptr) return;   // block kept dense
     cd* Vo = Uo + (int64_t)m * rp;
-    for (int e = threadIdx.x; e < m * rp; e += NT) {
+    for (int e = threadIdx.x; e < m * rp; e += NTR) {
         const int x = e % m, c = e / m;
         const cd* mc = M + (int64_t)srt[c] * r;
         cd s = cmk(0.0, 0.0);
         for (int l = 0; l < r; ++l) s = cfma(Q[(int64_t)l * m + x], mc[l], s);
         Uo[e] = s;
     }
-    for (int e = threadIdx.x; e < rp * n; e += NT) {
+    for (int e = threadIdx.x; e < rp * n; e += NTR) {
         const int c = e / n, y = e % n;
         const cd* xc = X + (int64_t)srt[c] * r;
         cd s = cmk(0.0, 0.0);
@@ -406,14 +409,14 @@ void launch_aca(bool dense, const AcaTask* tasks, int64_t ntasks, const double* 
 void launch_recompress_a(const AcaTask* tasks, int64_t ntasks, cd* scratch, const int* rank_in, cd* ws,
                          const int64_t* ws_off, double eps, int* rank_out, hipStream_t s) {
     if (ntasks > 0)
-        hipLaunchKernelGGL(k_recompress_a, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, scratch, rank_in, ws, ws_off, eps,
+        hipLaunchKernelGGL(k_recompress_a, dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, scratch, rank_in, ws, ws_off, eps,
                            rank_out);
 }
 
 void launch_recompress_b(const AcaTask* tasks, int64_t ntasks, const cd* scratch, const int* rank_in, const cd* ws,
                          const int64_t* ws_off, const int* rank_new, cd* const* dst, hipStream_t s) {
     if (ntasks > 0)
-        hipLaunchKernelGGL(k_recompress_b, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, scratch, rank_in, ws, ws_off,
+        hipLaunchKernelGGL(k_recompress_b, dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, scratch, rank_in, ws, ws_off,
                            rank_new, dst);
 }
 

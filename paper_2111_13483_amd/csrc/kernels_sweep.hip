@@ -677,28 +677,36 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
     }
 }
 
-// Linv rows of each chunk (one workgroup per chunk), row blocks in order:
+// Linv rows of each chunk, row blocks in order:
 // X_j = E_j + sum_{in-chunk (k, j)} alpha_kj^T X_k, X_k stored b_k x w_k.
+// Columns are independent, so each workgroup takes a slice of kLinvCols
+// columns of one chunk and keeps that slice of the chunk's rows in LDS.
+constexpr int kLinvCols = 8;
 __global__ void __launch_bounds__(NT)
 k_linv(SweepPlan p, const int32_t* __restrict__ chunk_first, const int64_t* __restrict__ intptr,
        const SweepEnt* __restrict__ intent, const cd* __restrict__ A, cd* __restrict__ lf) {
-    const int c = blockIdx.x;
+    constexpr int NS = kMaxChunk / kLinvCols;
+    const int c = blockIdx.x / NS;
+    const int col0 = (blockIdx.x % NS) * kLinvCols;
+    if (col0 >= p.csize[c]) return;
+    __shared__ cd Xs[kMaxChunk][kLinvCols];
     const int j0 = chunk_first[c], j1 = chunk_first[c + 1];
     for (int j = j0; j < j1; ++j) {
         const int bj = p.bsize[j], wj = p.w[j], lj = p.loc[j];
         cd* X = lf + p.lf_off[j];
-        for (int e = threadIdx.x; e < bj * wj; e += NT) {
-            const int a = e / wj, col = e % wj;
+        for (int e = threadIdx.x; e < bj * kLinvCols; e += NT) {
+            const int a = e / kLinvCols, cl = e % kLinvCols, col = col0 + cl;
+            if (col >= wj) continue;
             cd val = cmk(col == lj + a ? 1.0 : 0.0, 0.0);
             for (int64_t q = intptr[j]; q < intptr[j + 1]; ++q) {
                 const SweepEnt en = intent[q];
-                const int k = en.k, bk = p.bsize[k], wkk = p.w[k];
-                if (col >= wkk) continue;
+                const int k = en.k, bk = p.bsize[k], lk = p.loc[k];
+                if (col >= p.w[k]) continue;
                 const cd* Ak = A + en.off;
-                const cd* Xk = lf + p.lf_off[k];
-                for (int l = 0; l < bk; ++l) val = cfma(Ak[(int64_t)l * bj + a], Xk[(int64_t)l * wkk + col], val);
+                for (int l = 0; l < bk; ++l) val = cfma(Ak[(int64_t)l * bj + a], Xs[lk + l][cl], val);
             }
-            X[e] = val;
+            Xs[lj + a][cl] = val;
+            X[(int64_t)a * wj + col] = val;
         }
         __syncthreads();
     }
@@ -804,7 +812,8 @@ void launch_sweep(bool forward, const ColMask& mk, const SweepPlanT<cf>& p, cons
 void launch_linv(const SweepPlan& p, int nchunk, const int32_t* chunk_first, const int64_t* intptr,
                  const SweepEnt* intent, const cd* A, cd* lf, hipStream_t s) {
     if (nchunk > 0)
-        hipLaunchKernelGGL(k_linv, dim3(nchunk), dim3(NT), 0, s, p, chunk_first, intptr, intent, A, lf);
+        hipLaunchKernelGGL(k_linv, dim3((unsigned)nchunk * (kMaxChunk / kLinvCols)), dim3(NT), 0, s, p, chunk_first,
+                           intptr, intent, A, lf);
 }
 
 void launch_linv_transpose(const SweepPlan& p, cd* lb, hipStream_t s) {
