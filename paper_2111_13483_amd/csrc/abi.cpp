@@ -163,11 +163,30 @@ struct KernelTimer {
     }
 };
 
+// A second stream owned by the library (default priority) with a fork and a
+// join event: the near-field matvec runs on it beside the far-field matvec.
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    void ensure() {
+        if (s) return;
+        hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+        hip_check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreateWithFlags");
+        hip_check(hipEventCreateWithFlags(&join, hipEventDisableTiming), "hipEventCreateWithFlags");
+    }
+    ~AuxStream() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
 struct hs_context {
     int device = 0;
     hipStream_t stream = nullptr;
     Mem mem;
     KernelTimer timer;
+    AuxStream aux;
 };
 
 namespace {
@@ -465,16 +484,25 @@ struct MatvecWs {
 };
 
 // mk selects the columns computed (all for the public entry points)
+// Near and far matvec write disjoint slot ranges and only read x, so the near
+// part runs on the auxiliary stream beside the far part; the gather waits for
+// both. The fork follows all earlier work on s.
 void matvec_tree(hs_context* ctx, const hs_hmatrix* H, const cd* x, cd* y, int nrhs, cd* slots, hipStream_t s,
                  const hs::ColMask& mk) {
-    timed(ctx, HS_KT_NEAR_MV, s, [&] {
+    AuxStream& ax = ctx->aux;
+    ax.ensure();
+    hip_check(hipEventRecord(ax.fork, s), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(ax.s, ax.fork, 0), "hipStreamWaitEvent");
+    timed(ctx, HS_KT_NEAR_MV, ax.s, [&] {
         hs::launch_near_mv(mk, H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near, x, H->n,
-                           nrhs, slots, s);
+                           nrhs, slots, ax.s);
     });
     timed(ctx, HS_KT_FAR_MV, s, [&] {
         hs::launch_far_mv(mk, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr, H->d_mv_slot, (int64_t)H->far_geom.size(), x,
                           H->n, nrhs, slots, s);
     });
+    hip_check(hipEventRecord(ax.join, ax.s), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(s, ax.join, 0), "hipStreamWaitEvent");
     hs::launch_gather(mk, H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, H->n, nrhs, y, s);
 }
 
@@ -1945,10 +1973,16 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
             GmresWs Gi;
             Gi.alloc(w, n, ns, m_in, false);
             ApplyFn matvec32 = [&](const cd* in, cd* out, const hs::ColMask& mk) {
+                AuxStream& ax = ctx->aux;
+                ax.ensure();
+                hip_check(hipEventRecord(ax.fork, s), "hipEventRecord");
+                hip_check(hipStreamWaitEvent(ax.s, ax.fork, 0), "hipStreamWaitEvent");
                 hs::launch_near_mv(mk, H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near32,
-                                   in, n, ns, slots, s);
+                                   in, n, ns, slots, ax.s);
                 hs::launch_far_mv(mk, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr32, H->d_mv_slot,
                                   (int64_t)H->far_geom.size(), in, n, ns, slots, s);
+                hip_check(hipEventRecord(ax.join, ax.s), "hipEventRecord");
+                hip_check(hipStreamWaitEvent(s, ax.join, 0), "hipStreamWaitEvent");
                 hs::launch_gather(mk, H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, n, ns, out, s);
             };
             ApplyFn precond32 = [&](const cd* in, cd* out, const hs::ColMask& mk) {
