@@ -115,7 +115,7 @@ void check_device_flag(const int* d_err, hipStream_t s) {
     if (e & hs::kErrNumeric) fail(HS_ENUMERIC, "NaN or Inf met in a leaf-block factorisation");
 }
 
-constexpr int64_t kScratchBudget = int64_t(2) << 30;   // bytes of ACA scratch per batch
+constexpr int64_t kScratchBudget = int64_t(16) << 30;  // most bytes of ACA scratch per batch
 
 // complex64 copy of a contiguous complex128 array (count elements), owned by own
 hs::cf* c64_copy(Owned& own, Owned& tmp, const cd* src, int64_t count, hipStream_t s) {
@@ -306,6 +306,14 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
     if (nt == 0) return;
     Owned tmp;
     tmp.mem = own.mem;
+    // one batch where memory allows, so the slowest blocks of the whole list
+    // overlap in one launch per kernel: at most half of the free device memory
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = 0;
+    }
+    const int64_t budget = std::max<int64_t>(int64_t(1) << 30, std::min<int64_t>(kScratchBudget, (int64_t)(free_b / 2)));
     int64_t b0 = 0;
     while (b0 < nt) {
         // batch [b0, b1) within the scratch budget
@@ -314,7 +322,7 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
             hs::AcaTask& t = tasks[b1];
             t.cap = std::min(std::min(t.m, t.n), cap_max);
             int64_t e = (int64_t)(t.m + t.n) * t.cap;
-            if (b1 > b0 && (elems + e) * 16 + flag_bytes > kScratchBudget) break;
+            if (b1 > b0 && (elems + e) * 16 + flag_bytes > budget) break;
             t.u_off = elems;
             t.v_off = elems + (int64_t)t.m * t.cap;
             t.flag_off = flag_bytes;
