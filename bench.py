@@ -516,7 +516,12 @@ def main():
             avg = ms / cnt
             kern[name] = {"launches": cnt, "avg_ms": avg, "alg_bytes": alg[name],
                           "GB_per_s": alg[name] / (avg * 1e-3) / 1e9}
-    dom = max(kern, key=lambda k: kern[k]["launches"] * kern[k]["avg_ms"])
+    # the near-field matvec runs on a second stream beside the far-field one:
+    # its event time spans the concurrent far kernel, so it is reported but
+    # not a candidate for the dominant kernel
+    if "near_mv" in kern:
+        kern["near_mv"]["overlaps"] = "far_mv"
+    dom = max((k for k in kern if "overlaps" not in kern[k]), key=lambda k: kern[k]["launches"] * kern[k]["avg_ms"])
     traffic = committed_traffic()
     achieved = kern[dom]["GB_per_s"]
     out["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAME[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
