@@ -1499,19 +1499,39 @@ struct SetupJob {
         hs::CopyTask* d_cbc = tmp.upload(cbc, s);
         hs::launch_copy_blocks(d_cfc, (int64_t)cfc.size(), Ad, d_C, s);
         hs::launch_copy_blocks(d_cbc, (int64_t)cbc.size(), Ad, d_C, s);
-        std::vector<hs::GemmTask> gf, gb;
+        // M_f = Linv C_f and M_b = Linv^T C_b per chunk, by 64 x 64 output tiles
+        // over the chunk's rows: a row of block k covers chunk columns
+        // [0, loc_k + b_k) forward and [loc_k, csize) backward
+        std::vector<hs::ChunkRow> rf(H->n), rb(H->n);
+        std::vector<hs::ChunkTile> tf, tb;
         for (int64_t kk = 0; kk < nb; ++kk) {
             const int32_t c = chunk_of[kk], bk = P->bsize[kk];
-            if (fwidth[c] > 0)
-                gf.push_back(hs::GemmTask{mf_off[kk], lf_off[kk], cf_off[c], bk, fwidth[c], wdt[kk], 0});
-            if (bwidth[c] > 0)
-                gb.push_back(hs::GemmTask{mb_off[kk], lb_off[kk], cft + cb_off[c] + (int64_t)loc[kk] * bwidth[c], bk,
-                                          bwidth[c], wtt[kk], 0});
+            const int64_t r0 = pos[chunk_first[c]] + loc[kk];
+            for (int32_t a = 0; a < bk; ++a) {
+                rf[r0 + a] = hs::ChunkRow{lf_off[kk] + (int64_t)a * wdt[kk], mf_off[kk] + (int64_t)a * fwidth[c], 0,
+                                          wdt[kk]};
+                rb[r0 + a] = hs::ChunkRow{lb_off[kk] + (int64_t)a * wtt[kk], mb_off[kk] + (int64_t)a * bwidth[c],
+                                          loc[kk], wtt[kk]};
+            }
         }
-        hs::GemmTask* d_gf = tmp.upload(gf, s);
-        hs::GemmTask* d_gb = tmp.upload(gb, s);
-        hs::launch_gemm(d_gf, (int64_t)gf.size(), d_lf, d_C, d_mf, false, false, 1.0, s);
-        hs::launch_gemm(d_gb, (int64_t)gb.size(), d_lb, d_C, d_mb, false, false, 1.0, s);
+        for (int64_t c = 0; c < nch; ++c) {
+            const int32_t base = (int32_t)pos[chunk_first[c]], cs = csize[c];
+            for (int32_t t0 = 0; t0 < cs; t0 += 64) {
+                const int32_t nr = std::min(64, cs - t0);
+                const hs::ChunkRow& last = rf[base + t0 + nr - 1];
+                const hs::ChunkRow& first = rb[base + t0];
+                for (int32_t c0 = 0; c0 < fwidth[c]; c0 += 64)
+                    tf.push_back(hs::ChunkTile{cf_off[c], base + t0, nr, c0, fwidth[c], 0, last.k0 + last.kw});
+                for (int32_t c0 = 0; c0 < bwidth[c]; c0 += 64)
+                    tb.push_back(hs::ChunkTile{cft + cb_off[c], base + t0, nr, c0, bwidth[c], first.k0, cs});
+            }
+        }
+        hs::ChunkRow* d_rf = tmp.upload(rf, s);
+        hs::ChunkRow* d_rb = tmp.upload(rb, s);
+        hs::ChunkTile* d_tf = tmp.upload(tf, s);
+        hs::ChunkTile* d_tb = tmp.upload(tb, s);
+        hs::launch_chunk_gemm(d_tf, (int64_t)tf.size(), d_rf, d_lf, d_C, d_mf, s);
+        hs::launch_chunk_gemm(d_tb, (int64_t)tb.size(), d_rb, d_lb, d_C, d_mb, s);
         hip_check(hipGetLastError(), "linv launches");
         // Row workers: per chunk its ranges, per point row its matrix slices.
         // Work items of the other workgroups in dependency order: per chunk its

@@ -160,6 +160,22 @@ struct PairStep {
 void launch_pair_table(const PairStep* steps, int64_t nsteps, int* err, hipStream_t s);
 void launch_factor_alpha(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, hipStream_t s);
 void launch_schur_tiles(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, hipStream_t s);
+// Chunk products M = L C of the sweep plan, by 64 x 64 output tiles: one
+// entry per row of a chunk (A row at a_off, nonzero over chunk columns
+// [k0, k0 + kw), output row at c_off) and one per tile (chunk, first row,
+// rows, first column).
+struct ChunkRow {
+    int64_t a_off, c_off;
+    int32_t k0, kw;
+};
+struct ChunkTile {
+    int64_t b_off;        // the chunk's C (csize x width, row-major)
+    int32_t row0, nrow;   // chunk rows [row0, row0 + nrow) as ChunkRow indices
+    int32_t col0, width;  // output columns [col0, col0 + 64) of width
+    int32_t kmin, kmax;   // union of the rows' column ranges
+};
+void launch_chunk_gemm(const ChunkTile* tiles, int64_t ntiles, const ChunkRow* rows, const cd* A, const cd* B, cd* C,
+                       hipStream_t s);
 void launch_gemm(const GemmTask* tasks, int64_t ntasks, const cd* A, const cd* B, cd* C, bool transA, bool accumulate,
                  double sign, hipStream_t s);
 

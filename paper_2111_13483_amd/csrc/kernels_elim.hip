@@ -240,6 +240,115 @@ __device__ __forceinline__ bool gj_invert(const cd* __restrict__ wkk, int b, int
     return true;
 }
 
+// The same inversion for b <= 32, two columns per register: half h of a wave
+// (32 lanes, lane = row) holds one column, wave w columns 16u + 2w + h. Rows
+// are not moved: each lane keeps its row's position in the interchanged
+// order and a used flag, the pivot is the largest |a|^2 among unused rows
+// with ties to the lowest position (the row the interchanging algorithm
+// picks), and each column is stored by final position at the end, so the
+// result and its layout match gj_invert.
+template <int S>
+__device__ __forceinline__ bool gj_invert_half(const cd* __restrict__ wkk, int b, int* err, cd* A,
+                                               cd (*colbuf)[kMaxLeaf], cd* pinv, int* prow, int* srcmap) {
+    const int tid = threadIdx.x, lane = tid % kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int h = lane >> 5, r = lane & 31;
+    const bool vr = r < b;
+    cd e[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+        const int j = 16 * u + 2 * wv + h;
+        e[u] = gld(wkk + (vr ? r : 0) * b + (j < b ? j : 0));
+    }
+    int pos = r;           // position of this lane's row in the interchanged order
+    bool used = false;
+    int x0 = lane;         // source column tracker of the final column interchanges (column = lane)
+    // the wave holding column jn publishes it, picks the next pivot and its
+    // reciprocal; slot layout: prow[2 * (jn & 1)] = row, [+1] = its position
+    auto publish = [&](int jn, cd ev) {
+        const int hn = jn & 1;
+        cd* nb = colbuf[jn & 1];
+        if (h == hn && vr) nb[r] = ev;
+        const double v = (h == hn && vr && !used) ? cabs2_exact(ev) : -1.0;
+        const double vmax = wave_max_f64(v);
+        int q = -2;
+        if (vmax > 0.0) {
+            unsigned long long m = __ballot(v == vmax);
+            q = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            if (m) {   // ties: lowest position
+                int qpos = __builtin_amdgcn_readlane(pos, q);
+                while (m) {
+                    const int l2 = __ffsll((long long)m) - 1;
+                    m &= m - 1;
+                    const int p2 = __builtin_amdgcn_readlane(pos, l2);
+                    if (p2 < qpos) { q = l2; qpos = p2; }
+                }
+            }
+        } else if (vmax == 0.0) {
+            q = -1;
+        }
+        cd qinv = cmk(0.0, 0.0);
+        int qpos = 0;
+        if (q >= 0) {
+            qinv = crecip(cmk(readlane_f64(ev.x, q), readlane_f64(ev.y, q)));
+            qpos = __builtin_amdgcn_readlane(pos, q);
+        }
+        if (lane == 0) {
+            prow[2 * (jn & 1)] = q < 0 ? q : q - 32 * hn;
+            prow[2 * (jn & 1) + 1] = qpos;
+            pinv[jn & 1] = qinv;
+        }
+    };
+    if (wv == 0) publish(0, e[0]);
+    __syncthreads();
+    for (int c = 0; c < b; ++c) {
+        const int p = __builtin_amdgcn_readfirstlane(prow[2 * (c & 1)]);
+        const int pp = __builtin_amdgcn_readfirstlane(prow[2 * (c & 1) + 1]);
+        const cd inv = pinv[c & 1];
+        if (p < 0) {
+            if (tid == 0) raise_err(err, p == -1 ? kErrSingular : kErrNumeric);
+            return false;
+        }
+        const cd f = vr ? colbuf[c & 1][r] : cmk(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            const int j = 16 * u + 2 * wv + h;
+            // the pivot row's entry of this lane's column
+            const double p0x = readlane_f64(e[u].x, p), p0y = readlane_f64(e[u].y, p);
+            const double p1x = readlane_f64(e[u].x, p + 32), p1y = readlane_f64(e[u].y, p + 32);
+            const cd pv = h ? cmk(p1x, p1y) : cmk(p0x, p0y);
+            const cd pjs = (j == c) ? inv : cmul(pv, inv);
+            if (r == p) e[u] = pjs;
+            else if (j == c) e[u] = cmk(-(f.x * inv.x - f.y * inv.y), -(f.x * inv.y + f.y * inv.x));
+            else e[u] = csub(e[u], cmul(f, pjs));
+        }
+        // row p becomes position c; the row at position c takes p's position
+        if (r == p) used = true;
+        pos = (r == p) ? c : (pos == c ? pp : pos);
+        x0 = x0 == c ? pp : (x0 == pp ? c : x0);
+        const int jn = c + 1;
+        if (jn < b && (jn % 16) / 2 == wv) {
+            const int un = jn / 16;
+            cd ev = e[0];
+#pragma unroll
+            for (int u = 1; u < S; ++u)
+                if (u == un) ev = e[u];
+            publish(jn, ev);
+        }
+        __syncthreads();
+    }
+    // columns stored by final position
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+        const int j = 16 * u + 2 * wv + h;
+        if (j < b && vr) A[j * kLdc + pos] = e[u];
+    }
+    if (wv == 0 && lane < b) srcmap[lane] = x0;
+    __syncthreads();
+    return true;
+}
+
 // W_kk^-1 (Gauss-Jordan above), then one 64-column tile of alpha.
 __global__ void __launch_bounds__(NTF) k_factor_alpha(const ElimStep* __restrict__ steps,
                                                       const ElimTile* __restrict__ tiles) {
@@ -249,15 +358,15 @@ __global__ void __launch_bounds__(NTF) k_factor_alpha(const ElimStep* __restrict
     __shared__ cd A[kMaxLeaf * kLdc];
     __shared__ cd colbuf[2][kMaxLeaf];
     __shared__ cd pinv[2];
-    __shared__ int prow[2];
+    __shared__ int prow[4];
     __shared__ int srcmap[kMaxLeaf];
     __shared__ int pcol[kMaxPattern + 1];
     const int tid = threadIdx.x, lane = tid % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
     for (int a = tid; a <= st.ne; a += NTF) pcol[a] = gld(st.pcol + a);
     bool ok;
-    if (b <= 3 * NWF) ok = gj_invert<3, false>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
-    else if (b <= 4 * NWF) ok = gj_invert<4, false>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
+    if (b <= 16) ok = gj_invert_half<1>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
+    else if (b <= 32) ok = gj_invert_half<2>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
     else if (b <= kWave) ok = gj_invert<8, false>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
     else ok = gj_invert<(kMaxLeaf + NWF - 1) / NWF, true>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
     if (!ok) return;

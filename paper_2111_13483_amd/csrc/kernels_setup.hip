@@ -124,6 +124,90 @@ k_gemm(const GemmTask* __restrict__ tasks, const cd* __restrict__ Ag, const cd* 
     gemm_task<TRANS_A>(Ag + t.a_off, Bg + t.b_off, Cg + t.c_off, t.m, t.n, t.kk, accumulate, sign);
 }
 
+// C rows (64 per tile) = sum over k of A_row[k - k0] B[k][col]: one tile per
+// workgroup, K staged through LDS, 4 x 4 complex micro-tiles per thread,
+// ascending k from zero (rows add exact zeros outside their range).
+__global__ void __launch_bounds__(NT)
+k_chunk_gemm(const ChunkTile* __restrict__ tiles, const ChunkRow* __restrict__ rows, const cd* __restrict__ A,
+             const cd* __restrict__ B, cd* __restrict__ C) {
+    constexpr int TM = 64, TN = 64, KC = 16;
+    __shared__ cd As[KC][TM];
+    __shared__ cd Bs[KC][TN];
+    __shared__ int64_t aoff[TM];
+    __shared__ int rk0[TM], rkw[TM];
+    const ChunkTile t = tiles[blockIdx.x];
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    if (tid < TM) {
+        if (tid < t.nrow) {
+            const ChunkRow r = rows[t.row0 + tid];
+            aoff[tid] = r.a_off;
+            rk0[tid] = r.k0;
+            rkw[tid] = r.kw;
+        } else {
+            aoff[tid] = 0;
+            rk0[tid] = 0;
+            rkw[tid] = 0;
+        }
+    }
+    cd acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = cmk(0.0, 0.0);
+    // staging: thread tid serves row / column tid % 64, K rows tid / 64 + 4 u
+    const int c = tid % TM, l0 = tid / TM;
+    const int gc = t.col0 + c;
+    for (int k0 = t.kmin; k0 < t.kmax; k0 += KC) {
+        __syncthreads();
+        cd av[KC / 4], bv[KC / 4];
+#pragma unroll
+        for (int u = 0; u < KC / 4; ++u) {
+            const int k = k0 + l0 + 4 * u;
+            const int lk = k - rk0[c];
+            const bool oka = c < t.nrow && lk >= 0 && lk < rkw[c];
+            av[u] = A[oka ? aoff[c] + lk : 0];
+            const bool okb = k < t.kmax && gc < t.width;
+            bv[u] = B[okb ? t.b_off + (int64_t)k * t.width + gc : 0];
+            av[u] = oka ? av[u] : cmk(0.0, 0.0);
+            bv[u] = okb ? bv[u] : cmk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < KC / 4; ++u) {
+            As[l0 + 4 * u][c] = av[u];
+            Bs[l0 + 4 * u][c] = bv[u];
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int l = 0; l < KC; ++l) {
+            cd a4[4], b4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a4[i] = As[l][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b4[j] = Bs[l][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = cfma(a4[i], b4[j], acc[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int rr = ty * 4 + i;
+        if (rr >= t.nrow) continue;
+        const int64_t co = rows[t.row0 + rr].c_off;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int cc = t.col0 + tx * 4 + j;
+            if (cc < t.width) C[co + cc] = acc[i][j];
+        }
+    }
+}
+
+void launch_chunk_gemm(const ChunkTile* tiles, int64_t ntiles, const ChunkRow* rows, const cd* A, const cd* B, cd* C,
+                       hipStream_t s) {
+    if (ntiles > 0) hipLaunchKernelGGL(k_chunk_gemm, dim3((unsigned)ntiles), dim3(NT), 0, s, tiles, rows, A, B, C);
+}
+
 void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s) {
     if (ntasks > 0) hipLaunchKernelGGL(k_copy_blocks, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, src, dst);
 }
