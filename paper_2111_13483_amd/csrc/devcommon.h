@@ -55,10 +55,30 @@ __device__ __forceinline__ cd cdiv(cd a, cd b) {
 
 constexpr int kWave = 64;
 
+// Lane moves of a double by DPP (the whole wave must be active) and a read
+// of one lane's value into every lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave (every lane active), the same value in every lane: DPP
+// sums within each row of 16 lanes (quad_perm [1,0,3,2], [2,3,0,1], then
+// row_ror 4 and 8), then lane 0's sums of the four rows. DPP moves run in the
+// vector ALU; lane shuffles would go through the LDS crossbar.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x124>(v);
+    v += dpp_f64<0x128>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 __device__ __forceinline__ cd wave_sum(cd v) { return cmk(wave_sum(v.x), wave_sum(v.y)); }
 
@@ -68,15 +88,30 @@ __device__ __forceinline__ ArgMax amax_pick(ArgMax a, ArgMax b) {
     if (b.v > a.v || (b.v == a.v && b.i < a.i && b.v >= 0.0)) return b;
     return a;
 }
+// Over the wave (every lane active): the largest value, ties to the lowest
+// index among the lanes holding it (NaN never wins).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
 __device__ __forceinline__ ArgMax wave_argmax(ArgMax a) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        ArgMax b;
-        b.v = __shfl_xor(a.v, o, kWave);
-        b.i = __shfl_xor(a.i, o, kWave);
-        a = amax_pick(a, b);
-    }
-    return a;
+    double vm = a.v;
+    vm = fmax(vm, dpp_f64<0xB1>(vm));
+    vm = fmax(vm, dpp_f64<0x4E>(vm));
+    vm = fmax(vm, dpp_f64<0x124>(vm));
+    vm = fmax(vm, dpp_f64<0x128>(vm));
+    vm = fmax(fmax(readlane_f64(vm, 0), readlane_f64(vm, 16)), fmax(readlane_f64(vm, 32), readlane_f64(vm, 48)));
+    int im = (a.v == vm) ? a.i : 0x7fffffff;
+    im = min(im, dpp_i32<0xB1>(im));
+    im = min(im, dpp_i32<0x4E>(im));
+    im = min(im, dpp_i32<0x124>(im));
+    im = min(im, dpp_i32<0x128>(im));
+    im = min(min(__builtin_amdgcn_readlane(im, 0), __builtin_amdgcn_readlane(im, 16)),
+             min(__builtin_amdgcn_readlane(im, 32), __builtin_amdgcn_readlane(im, 48)));
+    ArgMax r;
+    r.v = vm;
+    r.i = im;
+    return r;
 }
 
 // Workgroup reductions through a caller-provided LDS scratch of >= nwaves entries.

@@ -91,18 +91,6 @@ __device__ __forceinline__ cd crecip(cd a) {
     return cmk(a.x * r, -a.y * r);
 }
 
-// DPP lane moves of a double (whole wave active)
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
-}
 // maximum over the wave (NaN ignored unless every lane holds one)
 __device__ __forceinline__ double wave_max_f64(double v) {
     v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]

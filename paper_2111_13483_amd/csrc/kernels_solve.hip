@@ -215,36 +215,53 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
 }
 
 // ---------------------------------------------------------------- gather
-// y on leaf L = sum of the slots that cover it, in the fixed order of the
-// leaf's gather list (GR entries' loads issued together).
-__global__ void __launch_bounds__(kWave)
+// y on leaf L = sum of the slots that cover it. The four waves of the
+// workgroup take the leaf's gather entries in turn (GR loads in flight per
+// lane) and their partial sums are added in wave order, so the result does
+// not depend on timing.
+__global__ void __launch_bounds__(NT)
 k_gather(ColMask mk, const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ gptr,
          const GatherEnt* __restrict__ gent, const cd* __restrict__ slots, int64_t n, int nrhs, cd* __restrict__ y) {
     constexpr int GR = 8;
+    __shared__ cd part[NW][kWave];
     const int64_t L = blockIdx.x;
     const int64_t i0 = leaf_off[L];
     const int b = (int)(leaf_off[L + 1] - i0);
     const int64_t e0 = gptr[L], e1 = gptr[L + 1];
-    for (int e = threadIdx.x; e < b * nrhs; e += kWave) {
-        const int a = e % b, c = e / b;
-        if (!col_live(mk, c)) continue;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    for (int base = 0; base < b * nrhs; base += kWave) {
+        const int e = base + lane;
+        const bool ok = e < b * nrhs;
+        const int a = ok ? e % b : 0, c = ok ? e / b : 0;
+        const bool live = ok && col_live(mk, c);
         cd acc = cmk(0.0, 0.0);
-        for (int64_t q = e0; q < e1; q += GR) {
-            cd v[GR];
+        if (live) {
+            for (int64_t q = e0 + wid; q < e1; q += NW * GR) {
+                cd v[GR];
 #pragma unroll
-            for (int u = 0; u < GR; ++u) {
-                if (q + u < e1) {
-                    const GatherEnt g = gent[q + u];
-                    v[u] = slots[g.base * nrhs + g.off + a + (int64_t)c * g.len];
-                } else {
-                    v[u] = cmk(0.0, 0.0);
+                for (int u = 0; u < GR; ++u) {
+                    const int64_t qq = q + (int64_t)u * NW;
+                    if (qq < e1) {
+                        const GatherEnt g = gent[qq];
+                        v[u] = slots[g.base * nrhs + g.off + a + (int64_t)c * g.len];
+                    } else {
+                        v[u] = cmk(0.0, 0.0);
+                    }
                 }
-            }
 #pragma unroll
-            for (int u = 0; u < GR; ++u)
-                if (q + u < e1) acc = cadd(acc, v[u]);
+                for (int u = 0; u < GR; ++u)
+                    if (q + (int64_t)u * NW < e1) acc = cadd(acc, v[u]);
+            }
         }
-        y[i0 + a + (int64_t)c * n] = acc;
+        part[wid][lane] = acc;
+        __syncthreads();
+        if (wid == 0 && live) {
+            cd sum = part[0][lane];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) sum = cadd(sum, part[w][lane]);
+            y[i0 + a + (int64_t)c * n] = sum;
+        }
+        __syncthreads();
     }
 }
 
@@ -626,7 +643,7 @@ void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cf* 
 
 void launch_gather(const ColMask& mk, const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb,
                    const cd* slots, int64_t n, int nrhs, cd* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(kWave), 0, s, mk, leaf_off, gptr, gent, slots, n, nrhs, y);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(NT), 0, s, mk, leaf_off, gptr, gent, slots, n, nrhs, y);
 }
 
 void launch_dots(const cd* V, int64_t ldv, int64_t vstride, int nvec, const cd* w, int64_t n, int nrhs,

@@ -136,8 +136,9 @@ __device__ __forceinline__ void stage_mapped(cd* x1, int ld1, const cd* g1, int 
 
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
-__device__ __forceinline__ cd shfl_cd(cd v, int src) {
-    return cmk(__shfl(v.x, src, kWave), __shfl(v.y, src, kWave));
+// v of lane src in every lane (src the same in every lane of the wave)
+__device__ __forceinline__ cd bcast_cd(cd v, int src) {
+    return cmk(readlane_f64(v.x, src), readlane_f64(v.y, src));
 }
 
 __device__ __forceinline__ int take_ticket(unsigned long long* ctr, unsigned long long base, int* s_t) {
@@ -263,7 +264,7 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const T* alpha, const
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
                     if (FWD) {
-                        const cd xa = shfl_cd(a < kWave ? x[0][c] : x[Q - 1][c], a % kWave);
+                        const cd xa = bcast_cd(a < kWave ? x[0][c] : x[Q - 1][c], a % kWave);
 #pragma unroll
                         for (int q = 0; q < Q; ++q) acc[q][c] = cfma(Ar[r][q], xa, acc[q][c]);
                     } else {
