@@ -539,7 +539,7 @@ SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
     sw.w.rbuf2 = o.get<cd>(nn);
     sw.w.slots_f = o.get<cd>((size_t)std::max<int64_t>(P->fslot_total, 1) * nrhs);
     sw.w.slots_b = o.get<cd>((size_t)std::max<int64_t>(P->bslot_total, 1) * nrhs);
-    const size_t nflags = (size_t)4 * P->nchunk + (size_t)2 * P->nb;
+    const size_t nflags = (size_t)4 * hs::kCntPad * P->nchunk + (size_t)2 * P->nb;
     sw.w.flags = o.get<int>(nflags);
     sw.w.tickets = o.get<unsigned long long>(2);
     hip_check(hipMemsetAsync(sw.w.flags, 0, sizeof(int) * nflags, s), "memset flags");

@@ -288,6 +288,7 @@ constexpr int kRowWorkers = 96;
 constexpr int kRowSets = 2;
 // Far entries of one source chunk per push item (four waves take turns).
 constexpr int kPushGroup = 16;
+constexpr int kCntPad = 32;      // ints between the per-chunk sweep counters (one 128-byte line each)
 struct SweepItems {
     int64_t nfwd, nbwd;      // phase A and push items of each direction
     const int32_t* fwd;

@@ -148,9 +148,9 @@ __device__ __forceinline__ int take_ticket(unsigned long long* ctr, unsigned lon
     return *s_t;
 }
 
-// Wave-level wait (no fence): counter cnts[c] == need.
-__device__ __forceinline__ void wait_count(const int* cnts, int c, int need) {
-    while (relaxed_load(cnts + c) != need) __builtin_amdgcn_s_sleep(1);
+// Wave-level wait (no fence): counter *cnt == need.
+__device__ __forceinline__ void wait_count(const int* cnt, int need) {
+    while (relaxed_load(cnt) != need) __builtin_amdgcn_s_sleep(1);
 }
 
 // Two counters polled together (b may be null): *a == na and *b == nb.
@@ -362,9 +362,10 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
     __shared__ cd xs2[kFoldCols * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
+    // per-chunk counters one cache line apart (polled by many workgroups)
     int* cntA = wk.flags;
-    int* cntB = wk.flags + p.nch;
-    int* cntT = wk.flags + 2 * p.nch;
+    int* cntB = wk.flags + kCntPad * p.nch;
+    int* cntT = wk.flags + 2 * kCntPad * p.nch;
     const int role = take_ticket(wk.tickets, base, &s_t);
     if (role < kRowWorkers * kRowSets) {
         // ---- phase B, persistent: row slot (role % kRowWorkers) * NW + wid of
@@ -380,7 +381,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             cd R1[QC], R2[QF];
             load_row(p.lf + rt.a1, w1, p.mf + rt.a2, live ? d.w2 : 0, R1, R2);
             if (wid == 0)
-                wait_pair(cntA + c, epoch * d.nblocks, c >= 2 ? cntB + c - 2 : nullptr, epoch * d.need2);
+                wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c >= 2 ? cntB + kCntPad * (c - 2) : nullptr, epoch * d.need2);
             __syncthreads();
             compiler_fence();
             bool first = true;   // the first computed pass waits for the newest chunk
@@ -398,7 +399,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
                                                    d.w2, wk.ybuf + (int64_t)c0 * n, it.femap + d.e_off, d.e_n, n, cs);
                     __syncthreads();
                     if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
-                    if (wid == 0 && c >= 1) wait_count(cntB, c - 1, epoch * d.need1);
+                    if (wid == 0 && c >= 1) wait_count(cntB + kCntPad * (c - 1), epoch * d.need1);
                     __syncthreads();
                     compiler_fence();
                     stage_segs<S, kMaxChunk>(xs2, d.w2, wk.ybuf + d.l_g + (int64_t)c0 * n, d.l_n, nullptr, 0, nullptr, 0,
@@ -432,7 +433,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             __syncthreads();
             const int nlive = min(max(d.nc - wkr * NW, 0), NW);
             if (tid == 0 && nlive > 0)
-                __hip_atomic_fetch_add(cntB + c, nlive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(cntB + kCntPad * c, nlive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
     }
@@ -447,7 +448,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             const int bj = p.bsize[j];
             const int64_t sj = p.bstart[j], pj = p.pos[j];
             const int nin = (int)(p.fgptr[j + 1] - p.fgptr[j]);
-            if (wid == 0 && nin > 0) wait_count(cntT, j, epoch * nin);
+            if (wid == 0 && nin > 0) wait_count(cntT + j, epoch * nin);
             __syncthreads();
             compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
@@ -461,14 +462,14 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             }
             stores_done();
             __syncthreads();
-            if (tid == 0) __hip_atomic_fetch_add(cntA + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0) __hip_atomic_fetch_add(cntA + kCntPad * c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             // ---- pushes of one source chunk: far entries taken by the waves in turn
             const int g = item - p.nb;
             const int e0 = p.fgrp[g];
             const PushEnt& f0 = p.fpush[e0];
             const int csrc = p.chunk_of[f0.src];
-            if (wid == 0) wait_count(cntB, csrc, epoch * p.csize[csrc]);
+            if (wid == 0) wait_count(cntB + kCntPad * csrc, epoch * p.csize[csrc]);
             __syncthreads();
             compiler_fence();
             const int ng = p.fgrp_n[g];
@@ -507,9 +508,9 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
     __shared__ cd xs2[kFoldCols * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
-    int* cntA = wk.flags + 2 * p.nch + p.nb;
-    int* cntB = wk.flags + 3 * p.nch + p.nb;
-    int* cntT = wk.flags + 4 * p.nch + p.nb;
+    int* cntA = wk.flags + 2 * kCntPad * p.nch + p.nb;
+    int* cntB = wk.flags + 3 * kCntPad * p.nch + p.nb;
+    int* cntT = wk.flags + 4 * kCntPad * p.nch + p.nb;
     const int role = take_ticket(wk.tickets + 1, base, &s_t);
     if (role < kRowWorkers * kRowSets) {
         // ---- phase B, persistent: row slot (role % kRowWorkers) * NW + wid of
@@ -526,7 +527,7 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             cd R1[QC], R2[QF];
             load_row(p.lb + rt.a1, w1, p.mb + rt.a2, live ? d.w2 : 0, R1, R2);
             if (wid == 0)
-                wait_pair(cntA + c, epoch * d.nblocks, c + 2 < p.nch ? cntB + c + 2 : nullptr, epoch * d.need2);
+                wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c + 2 < p.nch ? cntB + kCntPad * (c + 2) : nullptr, epoch * d.need2);
             __syncthreads();
             compiler_fence();
             bool first = true;   // the first computed pass waits for the newest chunk
@@ -544,7 +545,7 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
                                                    d.w2, wk.zbuf + (int64_t)c0 * n, it.bemap + d.e_off, d.e_n, n, cs);
                     __syncthreads();
                     if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
-                    if (wid == 0 && c + 1 < p.nch) wait_count(cntB, c + 1, epoch * d.need1);
+                    if (wid == 0 && c + 1 < p.nch) wait_count(cntB + kCntPad * (c + 1), epoch * d.need1);
                     __syncthreads();
                     compiler_fence();
                     stage_segs<S, kMaxChunk>(xs2, d.w2, wk.zbuf + d.l_g + (int64_t)c0 * n, d.l_n, nullptr, 0, nullptr, 0,
@@ -581,7 +582,7 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             __syncthreads();
             const int nlive = min(max(d.nc - wkr * NW, 0), NW);
             if (tid == 0 && nlive > 0)
-                __hip_atomic_fetch_add(cntB + c, nlive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(cntB + kCntPad * c, nlive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
     }
@@ -597,7 +598,7 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             const int64_t pk = p.pos[k];
             const T* Di = p.dinv + p.dinv_off[k];
             const int nin = (int)(p.bgptr[k + 1] - p.bgptr[k]);
-            if (wid == 0 && nin > 0) wait_count(cntT, k, epoch * nin);
+            if (wid == 0 && nin > 0) wait_count(cntT + k, epoch * nin);
             __syncthreads();
             compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
@@ -638,14 +639,14 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             }
             stores_done();
             __syncthreads();
-            if (tid == 0) __hip_atomic_fetch_add(cntA + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0) __hip_atomic_fetch_add(cntA + kCntPad * c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             // ---- pushes of one source chunk: alpha_kj z_j into the slot of (k, j)
             const int g = item - p.nb;
             const int e0 = p.bgrp[g];
             const PushEnt& b0 = p.bpush[e0];
             const int csrc = p.chunk_of[b0.src];
-            if (wid == 0) wait_count(cntB, csrc, epoch * p.csize[csrc]);
+            if (wid == 0) wait_count(cntB + kCntPad * csrc, epoch * p.csize[csrc]);
             __syncthreads();
             compiler_fence();
             const int ng = p.bgrp_n[g];
