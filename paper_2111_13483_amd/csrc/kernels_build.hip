@@ -20,6 +20,10 @@ constexpr int NT = 256;
 constexpr int NW = NT / kWave;
 // Re-compression: one workgroup per block.
 constexpr int NTR = 256;
+// a factor with len * r <= kRcLds elements is factored in LDS, and the core
+// with its rotations (2 r^2 <= kRcLds) rotated there; small enough (8 KB)
+// that the kernel's occupancy stays bound by its registers
+constexpr int kRcLds = 512;
 constexpr int NWR = NTR / kWave;
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
@@ -297,6 +301,7 @@ k_recompress_a(const AcaTask* __restrict__ tasks, cd* __restrict__ scratch, cons
     __shared__ int rot_flag;
     __shared__ double sig[kMaxRankCap];
     __shared__ int srt[kMaxRankCap];
+    __shared__ cd lbuf[kRcLds];
     const AcaTask t = tasks[blockIdx.x];
     const int r = rank_in[blockIdx.x];
     const int tid = threadIdx.x;
@@ -311,22 +316,41 @@ k_recompress_a(const AcaTask* __restrict__ tasks, cd* __restrict__ scratch, cons
     cd* M = RV + (int64_t)r * r;
     cd* X = M + (int64_t)r * r;
     int* srt_g = reinterpret_cast<int*>(X + (int64_t)r * r);
-    cgs2_qr(U, t.m, r, RU, hbuf, red);
-    cgs2_qr(V, t.n, r, RV, hbuf, red);
+    auto qr = [&](cd* G, int len, cd* R) {
+        if (len * r <= kRcLds) {
+            for (int e = tid; e < len * r; e += NTR) lbuf[e] = G[e];
+            __syncthreads();
+            cgs2_qr(lbuf, len, r, R, hbuf, red);
+            for (int e = tid; e < len * r; e += NTR) G[e] = lbuf[e];
+            __syncthreads();
+        } else {
+            cgs2_qr(G, len, r, R, hbuf, red);
+        }
+    };
+    qr(U, t.m, RU);
+    qr(V, t.n, RV);
+    const bool core_lds = 2 * r * r <= kRcLds;
+    cd* Mw = core_lds ? lbuf : M;
+    cd* Xw = core_lds ? lbuf + r * r : X;
     for (int e = tid; e < r * r; e += NTR) {
         const int a = e % r, b = e / r;
         cd s = cmk(0.0, 0.0);
         // R_U upper triangular: l >= a; R_V: l >= b
         for (int l = max(a, b); l < r; ++l) s = cfma(RU[a + (int64_t)l * r], RV[b + (int64_t)l * r], s);
-        M[e] = s;
-        X[e] = cmk(a == b ? 1.0 : 0.0, 0.0);
+        Mw[e] = s;
+        Xw[e] = cmk(a == b ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
-    jacobi_svd(M, X, r, &rot_flag);
+    jacobi_svd(Mw, Xw, r, &rot_flag);
     __syncthreads();
+    if (core_lds)
+        for (int e = tid; e < r * r; e += NTR) {
+            M[e] = Mw[e];
+            X[e] = Xw[e];
+        }
     for (int c = tid; c < r; c += NTR) {
         double s = 0.0;
-        for (int x = 0; x < r; ++x) s += cabs2(M[x + (int64_t)c * r]);
+        for (int x = 0; x < r; ++x) s += cabs2(Mw[x + (int64_t)c * r]);
         sig[c] = sqrt(s);
     }
     __syncthreads();
