@@ -544,6 +544,12 @@ SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
     sw.w.tickets = o.get<unsigned long long>(2);
     hip_check(hipMemsetAsync(sw.w.flags, 0, sizeof(int) * nflags, s), "memset flags");
     hip_check(hipMemsetAsync(sw.w.tickets, 0, sizeof(unsigned long long) * 2, s), "memset tickets");
+    // epochs start at 1 for each workspace: clear the flagged copies so no
+    // stale word of an earlier workspace carries a matching epoch
+    sw.w.llf = o.get<unsigned long long>(4 * nn);
+    sw.w.llb = o.get<unsigned long long>(4 * nn);
+    hip_check(hipMemsetAsync(sw.w.llf, 0, sizeof(unsigned long long) * 4 * nn, s), "memset llf");
+    hip_check(hipMemsetAsync(sw.w.llb, 0, sizeof(unsigned long long) * 4 * nn, s), "memset llb");
     return sw;
 }
 

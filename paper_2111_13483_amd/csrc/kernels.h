@@ -315,6 +315,12 @@ struct SweepWork {
     cd* slots_b;
     int* flags;
     unsigned long long* tickets;
+    // flagged copies of the row results (forward y, backward z), 4 words per
+    // value: word w holds 32-bit part w of the complex128 value in its low
+    // half and the apply's epoch in its high half, so a reader that sees the
+    // epoch in all four words has the value without a separate ready count
+    unsigned long long* llf;
+    unsigned long long* llb;
 };
 constexpr int kMaxChunk = 384;   // points per chunk (bounds the row widths)
 constexpr int kFoldCols = 3072;   // columns of the folded neighbour range per chunk

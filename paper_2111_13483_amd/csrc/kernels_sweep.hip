@@ -33,7 +33,9 @@
 // that is already running. Readiness is tracked by counters (per chunk: its
 // finished phase A blocks and phase B rows; per target block: its pushed
 // entries) compared with multiples of the apply's epoch, polled by one wave
-// per workgroup. The row workers stay resident for the whole launch, so the
+// per workgroup. The one exchange on the chain itself, chunk c-1's rows read
+// by the row workers of chunk c, skips the counters: each row result is also
+// written as epoch-tagged words that the readers poll directly. The row workers stay resident for the whole launch, so the
 // device must hold more workgroups than that at once (checked at setup), and
 // sweeps of different streams must not run at the same time.
 #include "devcommon.h"
@@ -67,74 +69,134 @@ __device__ __forceinline__ void st_sc(cd* p, cd v) {
 }
 __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Stage up to two segments into LDS: segment s copies len_s values per
-// right-hand side from g_s (column stride n) to x_s (column stride ld_s).
-// Loads go out in rounds of up to ROUND values per right-hand side, every
-// load of a round issued before its first LDS write.
-template <int S, int ROUND>
-__device__ __forceinline__ void stage_segs(cd* x1, int ld1, const cd* g1, int n1, cd* x2, int ld2, const cd* g2, int n2,
-                                           int64_t n, int cs) {
-    constexpr int PER = (ROUND * S + NT - 1) / NT;
-    const int t1 = n1 * cs, t2 = n2 * cs;
-    for (int e0 = 0; e0 < t1 + t2; e0 += PER * NT) {
-        cd v[PER];
+// The chain's critical exchange (chunk c-1's results read by the row workers
+// of chunk c) goes through flagged copies: 4 words per complex128 value,
+// word w = (epoch << 32) | 32-bit part w of the value. A 64-bit word is
+// written and read whole, so a reader that sees the epoch in all four words
+// has the value: no store-completion wait, ready count or second load sits
+// between the producing row and the row that consumes it.
+//
+// publish_ll: lane 4 c + w of a wave writes word w of column c of the
+// wave-uniform row results y[0 .. cs) of position i.
+template <int S>
+__device__ __forceinline__ void publish_ll(unsigned long long* ll, int64_t i, int64_t n, int c0, int cs,
+                                           const cd (&y)[S], unsigned tag) {
+    const int lane = threadIdx.x % kWave;
+    const int c = lane / 4, w = lane % 4;
+    if (c < cs) {
+        cd v = y[0];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = e0 + threadIdx.x + u * NT;
-            if (e < t1) {
-                v[u] = ld_sc(g1 + e % n1 + (int64_t)(e / n1) * n);
-            } else if (e < t1 + t2) {
-                const int f = e - t1;
-                v[u] = ld_sc(g2 + f % n2 + (int64_t)(f / n2) * n);
-            }
-        }
+        for (int cc = 1; cc < S; ++cc)
+            if (c == cc) v = y[cc];
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(w < 2 ? v.x : v.y);
+        const unsigned part = (w & 1) ? (unsigned)(bits >> 32) : (unsigned)bits;
+        __hip_atomic_store(ll + ((int64_t)(c0 + c) * n + i) * 4 + w, ((unsigned long long)tag << 32) | part,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// stage_ll: len values per right-hand side (columns c0 .. c0 + cs - 1) from
+// position g0 of a flagged copy into LDS x (column stride ld), once every
+// word carries tag. Thread t takes words t, t + NT, ... of the contiguous word
+// range (a wave's loads cover 512 consecutive bytes) and reloads only the
+// words still missing, until no thread of the workgroup misses one. Every
+// word is written once per launch by the row worker that owns the position,
+// for the same live columns, so the loop ends.
+template <int S>
+__device__ __forceinline__ void stage_ll(cd* x, int ld, const unsigned long long* ll, int64_t g0, int len, int64_t n,
+                                         int c0, int cs, unsigned tag) {
+    constexpr int PER = (4 * kMaxChunk * S + NT - 1) / NT;
+    const int wl = 4 * len, tot = wl * cs;
+    unsigned* xw = reinterpret_cast<unsigned*>(x);
+    // word e of the range sits at byte 8 (e / wl * 4 n + e % wl) from base
+    const char* base = reinterpret_cast<const char*>(ll + ((int64_t)c0 * n + g0) * 4);
+    const unsigned cstride = (unsigned)(4 * n);
+    unsigned pend = 0;
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = e0 + threadIdx.x + u * NT;
-            if (e < t1) {
-                x1[e % n1 + (e / n1) * ld1] = v[u];
-            } else if (e < t1 + t2) {
-                const int f = e - t1;
-                x2[f % n2 + (f / n2) * ld2] = v[u];
+    for (int u = 0; u < PER; ++u)
+        if ((int)threadIdx.x + u * NT < tot) pend |= 1u << u;
+    for (;;) {
+        // groups of G words in flight (registers: the row workers hold their
+        // matrix rows beside this)
+        constexpr int G = 6;
+#pragma unroll
+        for (int u0 = 0; u0 < PER; u0 += G) {
+            unsigned long long w[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                w[u] = 0;
+                if (u0 + u < PER && (pend >> (u0 + u) & 1u)) {
+                    int e = threadIdx.x + (u0 + u) * NT;
+                    asm volatile("" : "+v"(e));   // recomputed per round, not held across the wait
+                    const unsigned off = 8u * ((unsigned)(e / wl) * cstride + (unsigned)(e % wl));
+                    w[u] = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(base + off), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+                if (u0 + u < PER && (pend >> (u0 + u) & 1u) && (unsigned)(w[u] >> 32) == tag) {
+                    const int e = threadIdx.x + (u0 + u) * NT, col = e / wl, r = e % wl;
+                    xw[(r / 4 + col * ld) * 4 + r % 4] = (unsigned)w[u];
+                    pend &= ~(1u << (u0 + u));
+                }
         }
+        if (!__syncthreads_or(pend != 0)) break;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+// Loads that write LDS directly (16 bytes per lane: lane l of the wave lands
+// at dst + 16 l, dst uniform over the wave), with the same agent-scope
+// coherence bit (sc1) as the relaxed agent-scope atomic loads.
+__device__ __forceinline__ void load_lds16(const cd* src, cd* dst_wave) {
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                     (__attribute__((address_space(3))) void*)dst_wave, 16, 0, 16);
+}
+
+constexpr int PR = (kMaxChunk + NT - 1) / NT;    // r values per thread and column
+constexpr int PM = (kFoldCols + NT - 1) / NT;    // early range columns per thread
+
+// Positions of the early range columns l_n + tid + u NT (0 past e_n), loaded
+// before the waits (the map is fixed at setup).
+__device__ __forceinline__ void load_map(const int32_t* map, int n2, int (&mp)[PM]) {
+#pragma unroll
+    for (int u = 0; u < PM; ++u) {
+        const int k = u * NT + (int)threadIdx.x;
+        mp[u] = k < n2 ? map[k] : 0;
     }
 }
 
 // Stage r (n1 contiguous values per right-hand side from g1) and the early
-// part of the folded range (n2 values gathered from g2 at the positions in
-// map) into LDS, in rounds like stage_segs.
-template <int S, int ROUND>
-__device__ __forceinline__ void stage_mapped(cd* x1, int ld1, const cd* g1, int n1, cd* x2, int ld2, const cd* g2,
-                                             const int32_t* map, int n2, int64_t n, int cs) {
-    constexpr int PER = (ROUND * S + NT - 1) / NT;
-    const int t1 = n1 * cs, t2 = n2 * cs;
-    for (int e0 = 0; e0 < t1 + t2; e0 += PER * NT) {
-        cd v[PER];
+// part of the folded range (n2 values per right-hand side gathered from g2 at
+// the positions mp) into LDS x1 / x2 (column strides ld1 / ld2). Value k of a
+// part is loaded by thread k % NT straight into LDS, so every load of both
+// parts is in flight at once and no value passes through registers.
+template <int S>
+__device__ __forceinline__ void stage_direct(cd* x1, int ld1, const cd* g1, int n1, cd* x2, int ld2, const cd* g2,
+                                             const int (&mp)[PM], int n2, int64_t n, int cs) {
+    const int tid = threadIdx.x, wb = tid - tid % kWave;
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = e0 + threadIdx.x + u * NT;
-            if (e < t1) {
-                v[u] = ld_sc(g1 + e % n1 + (int64_t)(e / n1) * n);
-            } else if (e < t1 + t2) {
-                const int f = e - t1;
-                v[u] = ld_sc(g2 + map[f % n2] + (int64_t)(f / n2) * n);
+    for (int col = 0; col < S; ++col) {
+        if (col < cs) {
+#pragma unroll
+            for (int u = 0; u < PR; ++u) {
+                const int k = u * NT + tid;
+                if (k < n1) load_lds16(g1 + k + (int64_t)col * n, x1 + col * ld1 + u * NT + wb);
             }
-        }
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = e0 + threadIdx.x + u * NT;
-            if (e < t1) {
-                x1[e % n1 + (e / n1) * ld1] = v[u];
-            } else if (e < t1 + t2) {
-                const int f = e - t1;
-                x2[f % n2 + (f / n2) * ld2] = v[u];
+            for (int u = 0; u < PM; ++u) {
+                const int k = u * NT + tid;
+                if (k < n2) load_lds16(g2 + mp[u] + (int64_t)col * n, x2 + col * ld2 + u * NT + wb);
             }
         }
     }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
 }
-
-__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
 // v of lane src in every lane (src the same in every lane of the wave)
 __device__ __forceinline__ cd bcast_cd(cd v, int src) {
@@ -380,6 +442,8 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             const int w1 = live ? rt.w1 : 0;
             cd R1[QC], R2[QF];
             load_row(p.lf + rt.a1, w1, p.mf + rt.a2, live ? d.w2 : 0, R1, R2);
+            int mp[PM];
+            load_map(it.femap + d.e_off, d.e_n, mp);
             if (wid == 0)
                 wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c >= 2 ? cntB + kCntPad * (c - 2) : nullptr, epoch * d.need2);
             __syncthreads();
@@ -395,23 +459,16 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
                     // everything but the newest neighbour chunk is final: stage it
                     // and take its part of the row before waiting for that chunk
                     first = false;
-                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n,
-                                                   d.w2, wk.ybuf + (int64_t)c0 * n, it.femap + d.e_off, d.e_n, n, cs);
-                    __syncthreads();
+                    stage_direct<S>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n, d.w2,
+                                    wk.ybuf + (int64_t)c0 * n, mp, d.e_n, n, cs);
                     if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
-                    if (wid == 0 && c >= 1) wait_count(cntB + kCntPad * (c - 1), epoch * d.need1);
-                    __syncthreads();
-                    compiler_fence();
-                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.ybuf + d.l_g + (int64_t)c0 * n, d.l_n, nullptr, 0, nullptr, 0,
-                                             n, cs);
-                    __syncthreads();
+                    // chunk c-1 (range columns [0, l_n), not read above) as it lands
+                    stage_ll<S>(xs2, d.w2, wk.llf, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch);
                     if (live) row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
                 } else {
-                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n,
-                                                   d.w2, wk.ybuf + (int64_t)c0 * n, it.femap + d.e_off, d.e_n, n, cs);
-                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.ybuf + d.l_g + (int64_t)c0 * n, d.l_n, nullptr, 0, nullptr, 0,
-                                             n, cs);
-                    __syncthreads();
+                    stage_direct<S>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n, d.w2,
+                                    wk.ybuf + (int64_t)c0 * n, mp, d.e_n, n, cs);
+                    stage_ll<S>(xs2, d.w2, wk.llf, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch);
                     if (live) {
                         row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
                         row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
@@ -421,6 +478,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
                     cd y[S];
 #pragma unroll
                     for (int cc = 0; cc < S; ++cc) y[cc] = wave_sum(acc[cc]);
+                    publish_ll<S>(wk.llf, i, n, c0, cs, y, (unsigned)epoch);
                     if (lane == 0)
 #pragma unroll
                         for (int cc = 0; cc < S; ++cc)
@@ -526,6 +584,8 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             const int w1 = live ? rt.w1 : 0;
             cd R1[QC], R2[QF];
             load_row(p.lb + rt.a1, w1, p.mb + rt.a2, live ? d.w2 : 0, R1, R2);
+            int mp[PM];
+            load_map(it.bemap + d.e_off, d.e_n, mp);
             if (wid == 0)
                 wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c + 2 < p.nch ? cntB + kCntPad * (c + 2) : nullptr, epoch * d.need2);
             __syncthreads();
@@ -541,23 +601,16 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
                     // everything but the newest neighbour chunk is final: stage it
                     // and take its part of the row before waiting for that chunk
                     first = false;
-                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n,
-                                                   d.w2, wk.zbuf + (int64_t)c0 * n, it.bemap + d.e_off, d.e_n, n, cs);
-                    __syncthreads();
+                    stage_direct<S>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n, d.w2,
+                                    wk.zbuf + (int64_t)c0 * n, mp, d.e_n, n, cs);
                     if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
-                    if (wid == 0 && c + 1 < p.nch) wait_count(cntB + kCntPad * (c + 1), epoch * d.need1);
-                    __syncthreads();
-                    compiler_fence();
-                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.zbuf + d.l_g + (int64_t)c0 * n, d.l_n, nullptr, 0, nullptr, 0,
-                                             n, cs);
-                    __syncthreads();
+                    // chunk c+1 (range columns [0, l_n), not read above) as it lands
+                    stage_ll<S>(xs2, d.w2, wk.llb, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch);
                     if (live) row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
                 } else {
-                    stage_mapped<S, 4 * kMaxChunk>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n,
-                                                   d.w2, wk.zbuf + (int64_t)c0 * n, it.bemap + d.e_off, d.e_n, n, cs);
-                    stage_segs<S, kMaxChunk>(xs2, d.w2, wk.zbuf + d.l_g + (int64_t)c0 * n, d.l_n, nullptr, 0, nullptr, 0,
-                                             n, cs);
-                    __syncthreads();
+                    stage_direct<S>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n, d.w2,
+                                    wk.zbuf + (int64_t)c0 * n, mp, d.e_n, n, cs);
+                    stage_ll<S>(xs2, d.w2, wk.llb, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch);
                     if (live) {
                         row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
                         row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
@@ -567,6 +620,7 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
                     cd y[S];
 #pragma unroll
                     for (int cc = 0; cc < S; ++cc) y[cc] = wave_sum(acc[cc]);
+                    publish_ll<S>(wk.llb, i, n, c0, cs, y, (unsigned)epoch);
                     if (lane == 0)
 #pragma unroll
                         for (int cc = 0; cc < S; ++cc)
