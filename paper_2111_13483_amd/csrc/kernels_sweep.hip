@@ -259,16 +259,20 @@ __device__ __forceinline__ void row_partial(const cd (&R1)[QC], int w1, const cd
 #pragma unroll
     for (int c = 0; c < S; ++c) {
         if (c < cs) {
+            // two interleaved partial sums (even and odd column groups) halve
+            // the dependent FMA chain; they are added in a fixed order
+            cd a[2] = {cmk(0.0, 0.0), cmk(0.0, 0.0)};
 #pragma unroll
             for (int q = 0; q < QC; ++q) {
                 const int col = lane + q * kWave;
-                if (col < w1) acc[c] = cfma(R1[q], xs1[o1 + col + c * ld1], acc[c]);
+                if (col < w1) a[q & 1] = cfma(R1[q], xs1[o1 + col + c * ld1], a[q & 1]);
             }
 #pragma unroll
             for (int q = 0; q < QF; ++q) {
                 const int col = lane + q * kWave;
-                if (col >= lo && col < hi) acc[c] = cfma(R2[q], xs2[col + c * ld2], acc[c]);
+                if (col >= lo && col < hi) a[q & 1] = cfma(R2[q], xs2[col + c * ld2], a[q & 1]);
             }
+            acc[c] = cadd(acc[c], cadd(a[0], a[1]));
         }
     }
 }
@@ -434,16 +438,23 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
         // every kRowSets-th chunk in order, y_i = Linv row . r_c + (Linv C) row . y_prev
         const int wkr = role % kRowWorkers;
         const int slot = wkr * NW + wid;
-        for (int c = role / kRowWorkers; c < p.nch; c += kRowSets) {
-            const SweepChunk d = it.fchunk[c];
+        const int cfirst = role / kRowWorkers;
+        if (cfirst >= p.nch) return;
+        // the chunk's descriptors and its rows' matrix slices; the next
+        // chunk's descriptors are read while this one is in flight, and its
+        // rows' loads are issued as soon as this chunk's rows are published
+        SweepChunk d = it.fchunk[cfirst];
+        RowTask rt = it.frow[d.pc + (slot < d.nc ? slot : 0)];
+        cd R1[QC], R2[QF];
+        int mp[PM];
+        load_row(p.lf + rt.a1, slot < d.nc ? rt.w1 : 0, p.mf + rt.a2, slot < d.nc ? d.w2 : 0, R1, R2);
+        load_map(it.femap + d.e_off, d.e_n, mp);
+        for (int c = cfirst; c < p.nch; c += kRowSets) {
             const bool live = slot < d.nc;
             const int i = d.pc + (live ? slot : 0);
-            const RowTask rt = it.frow[i];
             const int w1 = live ? rt.w1 : 0;
-            cd R1[QC], R2[QF];
-            load_row(p.lf + rt.a1, w1, p.mf + rt.a2, live ? d.w2 : 0, R1, R2);
-            int mp[PM];
-            load_map(it.femap + d.e_off, d.e_n, mp);
+            const int cn = c + kRowSets;
+            const SweepChunk dn = it.fchunk[cn < p.nch ? cn : c];
             if (wid == 0)
                 wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c >= 2 ? cntB + kCntPad * (c - 2) : nullptr, epoch * d.need2);
             __syncthreads();
@@ -492,6 +503,12 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             const int nlive = min(max(d.nc - wkr * NW, 0), NW);
             if (tid == 0 && nlive > 0)
                 __hip_atomic_fetch_add(cntB + kCntPad * c, nlive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cn < p.nch) {
+                d = dn;
+                rt = it.frow[d.pc + (slot < d.nc ? slot : 0)];
+                load_row(p.lf + rt.a1, slot < d.nc ? rt.w1 : 0, p.mf + rt.a2, slot < d.nc ? d.w2 : 0, R1, R2);
+                load_map(it.femap + d.e_off, d.e_n, mp);
+            }
         }
         return;
     }
@@ -576,16 +593,21 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
         // z_i = Linv^T row . r'_c + (Linv^T C') row . z_next
         const int wkr = role % kRowWorkers;
         const int slot = wkr * NW + wid;
-        for (int c = p.nch - 1 - role / kRowWorkers; c >= 0; c -= kRowSets) {
-            const SweepChunk d = it.bchunk[c];
+        const int cfirst = p.nch - 1 - role / kRowWorkers;
+        if (cfirst < 0) return;
+        // descriptors and rows fetched one chunk ahead, as in the forward sweep
+        SweepChunk d = it.bchunk[cfirst];
+        RowTask rt = it.brow[d.pc + (slot < d.nc ? slot : 0)];
+        cd R1[QC], R2[QF];
+        int mp[PM];
+        load_row(p.lb + rt.a1, slot < d.nc ? rt.w1 : 0, p.mb + rt.a2, slot < d.nc ? d.w2 : 0, R1, R2);
+        load_map(it.bemap + d.e_off, d.e_n, mp);
+        for (int c = cfirst; c >= 0; c -= kRowSets) {
             const bool live = slot < d.nc;
             const int i = d.pc + (live ? slot : 0);
-            const RowTask rt = it.brow[i];
             const int w1 = live ? rt.w1 : 0;
-            cd R1[QC], R2[QF];
-            load_row(p.lb + rt.a1, w1, p.mb + rt.a2, live ? d.w2 : 0, R1, R2);
-            int mp[PM];
-            load_map(it.bemap + d.e_off, d.e_n, mp);
+            const int cn = c - kRowSets;
+            const SweepChunk dn = it.bchunk[cn >= 0 ? cn : c];
             if (wid == 0)
                 wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c + 2 < p.nch ? cntB + kCntPad * (c + 2) : nullptr, epoch * d.need2);
             __syncthreads();
@@ -637,6 +659,12 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             const int nlive = min(max(d.nc - wkr * NW, 0), NW);
             if (tid == 0 && nlive > 0)
                 __hip_atomic_fetch_add(cntB + kCntPad * c, nlive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cn >= 0) {
+                d = dn;
+                rt = it.brow[d.pc + (slot < d.nc ? slot : 0)];
+                load_row(p.lb + rt.a1, slot < d.nc ? rt.w1 : 0, p.mb + rt.a2, slot < d.nc ? d.w2 : 0, R1, R2);
+                load_map(it.bemap + d.e_off, d.e_n, mp);
+            }
         }
         return;
     }
