@@ -48,6 +48,10 @@ namespace {
 constexpr int NT = 256;
 constexpr int NW = NT / kWave;
 constexpr int RB = 16;   // block rows (or rank terms) whose loads are issued together
+// the same for blocks of up to Q x 64 points (half as many for Q = 2, so the
+// push and phase A registers stay within the row workers' budget)
+template <int Q>
+constexpr int rb_of() { return Q == 1 ? RB : RB / 2; }
 
 __device__ __forceinline__ int relaxed_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -314,17 +318,18 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const T* alpha, const
     const int rows = FWD ? bo : bt, cols = FWD ? bt : bo;
     const T* A = alpha + e.aoff;
     if (e.rank < 0) {
-        for (int a0 = 0; a0 < rows; a0 += RB) {
-            cd Ar[RB][Q];
+        constexpr int RQ = rb_of<Q>();
+        for (int a0 = 0; a0 < rows; a0 += RQ) {
+            cd Ar[RQ][Q];
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
+            for (int r = 0; r < RQ; ++r)
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     const int b = lane + q * kWave;
                     Ar[r][q] = (a0 + r < rows && b < cols) ? to_cd(A[(int64_t)(a0 + r) * cols + b]) : cmk(0.0, 0.0);
                 }
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
+            for (int r = 0; r < RQ; ++r) {
                 const int a = a0 + r;
                 if (a < rows)
 #pragma unroll
@@ -349,10 +354,11 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const T* alpha, const
         const int rk = e.rank;
         const T* Uf = A;
         const T* Vf = A + (int64_t)rows * rk;
-        for (int l0 = 0; l0 < rk; l0 += RB) {
-            cd Ur[RB][Q], Vr[RB][Q];
+        constexpr int RQ = rb_of<Q>();
+        for (int l0 = 0; l0 < rk; l0 += RQ) {
+            cd Ur[RQ][Q], Vr[RQ][Q];
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
+            for (int r = 0; r < RQ; ++r)
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     const int xx = lane + q * kWave;
@@ -361,7 +367,7 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const T* alpha, const
                     Vr[r][q] = (on && xx < cols) ? to_cd(Vf[(int64_t)(l0 + r) * cols + xx]) : cmk(0.0, 0.0);
                 }
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
+            for (int r = 0; r < RQ; ++r) {
                 if (l0 + r < rk)
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
@@ -688,17 +694,18 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
                 if (!cols_live(mk, c0, cs)) continue;
                 for (int q = tid; q < bk * cs; q += NT) ysh[q] = wk.ybuf[pk + q % bk + (int64_t)(c0 + q / bk) * n];
                 __syncthreads();
-                for (int a0 = wid; a0 < bk; a0 += NW * RB) {
-                    cd Dr[RB][Q];
+                constexpr int RQ = rb_of<Q>();
+                for (int a0 = wid; a0 < bk; a0 += NW * RQ) {
+                    cd Dr[RQ][Q];
 #pragma unroll
-                    for (int r = 0; r < RB; ++r)
+                    for (int r = 0; r < RQ; ++r)
 #pragma unroll
                         for (int q = 0; q < Q; ++q) {
                             const int aa = a0 + NW * r, b = lane + q * kWave;
                             Dr[r][q] = (aa < bk && b < bk) ? to_cd(Di[(int64_t)aa * bk + b]) : cmk(0.0, 0.0);
                         }
 #pragma unroll
-                    for (int r = 0; r < RB; ++r) {
+                    for (int r = 0; r < RQ; ++r) {
                         const int aa = a0 + NW * r;
                         if (aa < bk)
 #pragma unroll

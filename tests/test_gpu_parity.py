@@ -337,15 +337,17 @@ def test_precond_sweep_layouts(env, pair_oracle, layout):
         assert _rel(z, ref) <= TOL, (layout, cols)
 
 
-def test_precond_wide_leaves_small_chunks(env):
-    # leaves wider than a wavefront through the far-entry path (one-block chunks)
+@pytest.mark.parametrize("fill_tol", [0.0, 1e-2])
+def test_precond_wide_leaves_small_chunks(env, fill_tol):
+    # leaves wider than a wavefront through the far-entry path (one-block
+    # chunks): dense entries, and low-rank ones once fill-in is compressed
     hsl, torch, ctx = env
     wl = W.make_config("c2", n=2500)
     wl.leaf_max = 96
     hm = ohm.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, 1e-4)
-    pc = opl.precond_setup(hm, "rcm", 0.0)
+    pc = opl.precond_setup(hm, "rcm", fill_tol)
     H = _gpu_h(env, wl)
-    P = hsl.Precond(ctx, H, "rcm", 0.0, sweep_chunk=96, sweep_fold_cols=96)
+    P = hsl.Precond(ctx, H, "rcm", fill_tol, sweep_chunk=96, sweep_fold_cols=96)
     rng = np.random.default_rng(7)
     perm = hm.tree.perm
     for cols in (1, 2):
