@@ -245,6 +245,7 @@ struct hs_hmatrix {
     // the far blocks again, largest r (m + n) first, for the matvec launch
     hs::AcaTask* d_mv_geom = nullptr;
     int* d_mv_rank = nullptr;
+    int64_t n_far_wg = 0;   // matvec far tasks taken by a whole workgroup (the rest by one wave)
     cd** d_mv_ptr = nullptr;
     int64_t* d_mv_slot = nullptr;
     int* d_far_piv = nullptr;
@@ -506,8 +507,8 @@ void matvec_tree(hs_context* ctx, const hs_hmatrix* H, const cd* x, cd* y, int n
                            nrhs, slots, ax.s);
     });
     timed(ctx, HS_KT_FAR_MV, s, [&] {
-        hs::launch_far_mv(mk, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr, H->d_mv_slot, (int64_t)H->far_geom.size(), x,
-                          H->n, nrhs, slots, s);
+        hs::launch_far_mv(mk, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr, H->d_mv_slot, H->n_far_wg,
+                          (int64_t)H->far_geom.size(), x, H->n, nrhs, slots, s);
     });
     hip_check(hipEventRecord(ax.join, ax.s), "hipEventRecord");
     hip_check(hipStreamWaitEvent(s, ax.join, 0), "hipStreamWaitEvent");
@@ -829,15 +830,24 @@ int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double 
         }
         H->d_near_slot = o.upload(near_slot, s);
         {
-            // the matvec takes the far blocks largest first so the long ones do
-            // not trail the launch
+            // the matvec takes the workgroup blocks largest first so the long
+            // ones do not trail the launch, then the blocks small enough for
+            // one wave (at most 64 x 64 points, rank <= kFarWaveRank)
             const int64_t nf = p.n_far();
             std::vector<int64_t> ord(nf);
             for (int64_t e = 0; e < nf; ++e) ord[e] = e;
             auto cost = [&](int64_t e) {
                 return (int64_t)H->far.rank[e] * (H->far_geom[e].m + H->far_geom[e].n);
             };
-            std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
+            auto wave = [&](int64_t e) {
+                return H->far_geom[e].m <= 64 && H->far_geom[e].n <= 64 && H->far.rank[e] <= hs::kFarWaveRank;
+            };
+            std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+                if (wave(x) != wave(y)) return !wave(x);
+                return cost(x) > cost(y);
+            });
+            H->n_far_wg = 0;
+            for (int64_t e = 0; e < nf; ++e) H->n_far_wg += wave(e) ? 0 : 1;
             std::vector<hs::AcaTask> mg(nf);
             std::vector<int> mr(nf);
             std::vector<cd*> mp(nf);
@@ -2013,7 +2023,7 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
                 hip_check(hipStreamWaitEvent(ax.s, ax.fork, 0), "hipStreamWaitEvent");
                 hs::launch_near_mv(mk, H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near32,
                                    in, n, ns, slots, ax.s);
-                hs::launch_far_mv(mk, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr32, H->d_mv_slot,
+                hs::launch_far_mv(mk, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr32, H->d_mv_slot, H->n_far_wg,
                                   (int64_t)H->far_geom.size(), in, n, ns, slots, s);
                 hip_check(hipEventRecord(ax.join, ax.s), "hipEventRecord");
                 hip_check(hipStreamWaitEvent(s, ax.join, 0), "hipStreamWaitEvent");

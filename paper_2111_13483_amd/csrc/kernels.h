@@ -188,10 +188,13 @@ void launch_near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slo
                     const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
 void launch_near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base, int64_t ntasks, const cf* Z,
                     const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
+// Far tasks [0, nwg) take one workgroup each; tasks [nwg, ntasks) have at
+// most 64 x 64 points and rank <= kFarWaveRank and take one wave each.
+constexpr int kFarWaveRank = 16;
 void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cd* const* uv, const int64_t* slot_base,
-                   int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
+                   int64_t nwg, int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
 void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cf* const* uv, const int64_t* slot_base,
-                   int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
+                   int64_t nwg, int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s);
 // complex128 -> complex64 copies: dst[dst_off + e] = src[e], e < count
 void launch_to_c64(const PtrCopy* tasks, int64_t ntasks, cf* dst, hipStream_t s);
 void launch_gather(const ColMask& mk, const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb,

@@ -114,17 +114,79 @@ k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restr
 }
 
 // ---------------------------------------------------------------- far matvec
-// One workgroup per far block (t, s) with U (m x r, column-major) and V
-// (r x nn, row-major): t1 = V x_s and t2 = U^T x_t (the 2r rows of V and of
-// U^T, one wave per row, RU rows' loads issued together), then
-// slot_t = U t1 and slot_s = V^T t2 (one thread per output row, LG rank
-// terms' loads issued together). S right-hand sides per pass.
+// A far block (t, s) with U (m x r, column-major) and V (r x nn, row-major)
+// adds slot_t = U (V x_s) and slot_s = V^T (U^T x_t).
+//
+// Blocks of at most 64 x 64 points and rank <= kFarWaveRank take one wave
+// each: lane j holds row j of U and column j of V for every rank term, so
+// each factor is read once; t1 = V x_s and t2 = U^T x_t are wave sums and
+// both slots follow from the registers. S right-hand sides per pass.
+template <int S, class T>
+__device__ __forceinline__ void far_wave(const ColMask& mk, const AcaTask& g, int r, const T* U, cd* st, const cd* x,
+                                         int64_t n, int nrhs) {
+    constexpr int RS = kFarWaveRank;
+    const int lane = threadIdx.x % kWave;
+    const int m = g.m, nn = g.n;
+    cd* ss = st + (int64_t)m * nrhs;
+    const T* V = U + (int64_t)m * r;
+    cd u[RS], v[RS];
+#pragma unroll
+    for (int l = 0; l < RS; ++l) {
+        u[l] = (l < r && lane < m) ? to_cd(U[lane + (int64_t)l * m]) : cmk(0.0, 0.0);
+        v[l] = (l < r && lane < nn) ? to_cd(V[(int64_t)l * nn + lane]) : cmk(0.0, 0.0);
+    }
+    for (int c0 = 0; c0 < nrhs; c0 += S) {
+        const int cs = min(S, nrhs - c0);
+        if (!cols_live(mk, c0, cs)) continue;
+        cd xs[S], xt[S], ot[S], os[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            xs[c] = (c < cs && lane < nn) ? x[g.s0 + lane + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
+            xt[c] = (c < cs && lane < m) ? x[g.t0 + lane + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
+            ot[c] = cmk(0.0, 0.0);
+            os[c] = cmk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int l = 0; l < RS; ++l) {
+            if (l < r) {
+#pragma unroll
+                for (int c = 0; c < S; ++c) {
+                    const cd t1 = wave_sum(cmul(v[l], xs[c]));
+                    const cd t2 = wave_sum(cmul(u[l], xt[c]));
+                    ot[c] = cfma(u[l], t1, ot[c]);
+                    os[c] = cfma(v[l], t2, os[c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            if (c < cs) {
+                if (lane < m) st[lane + (int64_t)(c0 + c) * m] = ot[c];
+                if (lane < nn) ss[lane + (int64_t)(c0 + c) * nn] = os[c];
+            }
+        }
+    }
+}
+
+// The other blocks take one workgroup each: t1 and t2 (the 2r rows of V and
+// of U^T, one wave per row, RU rows' loads issued together), then slot_t and
+// slot_s (one thread per output row, LG rank terms' loads issued together).
+// Workgroups [0, nwg) take tasks [0, nwg) (largest first); the rest take
+// NW wave tasks each from nwg on. One launch covers every far block, so the
+// small blocks fill the machine while the largest ones run.
 template <int S, class T>
 __global__ void __launch_bounds__(NT)
 k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ rank, T* const* __restrict__ uv,
-         const int64_t* __restrict__ slot_base, const cd* __restrict__ x, int64_t n, int nrhs, cd* __restrict__ slots) {
+         const int64_t* __restrict__ slot_base, int64_t nwg, int64_t ntasks, const cd* __restrict__ x, int64_t n,
+         int nrhs, cd* __restrict__ slots) {
     constexpr int RU = 4, LG = 8;
     __shared__ cd t12[2 * (kMaxRankCap + LG) * S];
+    if ((int64_t)blockIdx.x >= nwg) {
+        const int64_t task = nwg + ((int64_t)blockIdx.x - nwg) * NW + threadIdx.x / kWave;
+        if (task >= ntasks) return;
+        far_wave<S, T>(mk, geom[task], rank[task], uv[task], slots + slot_base[task] * nrhs, x, n, nrhs);
+        return;
+    }
     const AcaTask g = geom[blockIdx.x];
     const int m = g.m, nn = g.n, r = rank[blockIdx.x];
     if (r == 0) {
@@ -613,14 +675,15 @@ void near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base,
 }
 template <class T>
 void far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, T* const* uv, const int64_t* slot_base,
-            int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
+            int64_t nwg, int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
     if (ntasks == 0) return;
+    const int64_t grid = nwg + (ntasks - nwg + NW - 1) / NW;
     if (nrhs == 1)
-        hipLaunchKernelGGL((k_far_mv<1, T>), dim3((unsigned)ntasks), dim3(NT), 0, s, mk, geom, rank, uv, slot_base, x,
-                           n, nrhs, slots);
+        hipLaunchKernelGGL((k_far_mv<1, T>), dim3((unsigned)grid), dim3(NT), 0, s, mk, geom, rank, uv, slot_base, nwg,
+                           ntasks, x, n, nrhs, slots);
     else
-        hipLaunchKernelGGL((k_far_mv<SCH, T>), dim3((unsigned)ntasks), dim3(NT), 0, s, mk, geom, rank, uv, slot_base,
-                           x, n, nrhs, slots);
+        hipLaunchKernelGGL((k_far_mv<SCH, T>), dim3((unsigned)grid), dim3(NT), 0, s, mk, geom, rank, uv, slot_base,
+                           nwg, ntasks, x, n, nrhs, slots);
 }
 }  // namespace
 
@@ -633,12 +696,12 @@ void launch_near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slo
     near_mv(mk, tasks, slot_base, ntasks, Z, x, n, nrhs, slots, s);
 }
 void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cd* const* uv, const int64_t* slot_base,
-                   int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
-    far_mv(mk, geom, rank, uv, slot_base, ntasks, x, n, nrhs, slots, s);
+                   int64_t nwg, int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
+    far_mv(mk, geom, rank, uv, slot_base, nwg, ntasks, x, n, nrhs, slots, s);
 }
 void launch_far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, cf* const* uv, const int64_t* slot_base,
-                   int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
-    far_mv(mk, geom, rank, uv, slot_base, ntasks, x, n, nrhs, slots, s);
+                   int64_t nwg, int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
+    far_mv(mk, geom, rank, uv, slot_base, nwg, ntasks, x, n, nrhs, slots, s);
 }
 
 void launch_gather(const ColMask& mk, const int64_t* leaf_off, const int64_t* gptr, const GatherEnt* gent, int64_t nb,
