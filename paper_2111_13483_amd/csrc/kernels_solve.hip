@@ -179,7 +179,9 @@ __global__ void __launch_bounds__(NT)
 k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ rank, T* const* __restrict__ uv,
          const int64_t* __restrict__ slot_base, int64_t nwg, int64_t ntasks, const cd* __restrict__ x, int64_t n,
          int nrhs, cd* __restrict__ slots) {
-    constexpr int RU = 4, LG = 8;
+    // one column: twice the loads in flight (within the register count the
+    // wave path already sets); more columns keep the shallower groups
+    constexpr int RU = S == 1 ? 8 : 4, LG = S == 1 ? 16 : 8;
     __shared__ cd t12[2 * (kMaxRankCap + LG) * S];
     if ((int64_t)blockIdx.x >= nwg) {
         const int64_t task = nwg + ((int64_t)blockIdx.x - nwg) * NW + threadIdx.x / kWave;
