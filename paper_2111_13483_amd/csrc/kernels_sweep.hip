@@ -255,26 +255,57 @@ __device__ __forceinline__ void load_row(const T* A1, int w1, const T* A2, int w
 // Lane partial sums of one row (the caller reduces over the wave at the end):
 // row_partial takes all of A1 and the A2 columns in [lo, hi); row_head the A2
 // columns in [0, hi) with hi <= kMaxChunk, which lie in the first QC groups.
+//
+// One column: every column group reads LDS at its natural index (inside the
+// arrays: xs1 holds kMaxChunk (S + 1) values, see the kernels) and a select
+// zeroes the columns outside the row's range, so the reads carry no branch,
+// use one base address with immediate offsets and go out XG at a time; the
+// exact zeros added leave the sums unchanged. With more columns the
+// registers are not there for that, and each group is a guarded read.
 template <int S>
 __device__ __forceinline__ void row_partial(const cd (&R1)[QC], int w1, const cd* xs1, int o1, int ld1,
                                             const cd (&R2)[QF], int lo, int hi, const cd* xs2, int ld2, int cs,
                                             cd (&acc)[S]) {
     const int lane = threadIdx.x % kWave;
+    const cd zero = cmk(0.0, 0.0);
 #pragma unroll
     for (int c = 0; c < S; ++c) {
         if (c < cs) {
             // two interleaved partial sums (even and odd column groups) halve
             // the dependent FMA chain; they are added in a fixed order
-            cd a[2] = {cmk(0.0, 0.0), cmk(0.0, 0.0)};
+            cd a[2] = {zero, zero};
+            if constexpr (S == 1) {
 #pragma unroll
-            for (int q = 0; q < QC; ++q) {
-                const int col = lane + q * kWave;
-                if (col < w1) a[q & 1] = cfma(R1[q], xs1[o1 + col + c * ld1], a[q & 1]);
-            }
+                for (int q = 0; q < QC; ++q) {
+                    const int col = lane + q * kWave;
+                    const cd xv = xs1[o1 + col];
+                    a[q & 1] = cfma(R1[q], col < w1 ? xv : zero, a[q & 1]);
+                }
+                constexpr int XG = 4;
+                static_assert(QF % XG == 0, "whole read groups");
 #pragma unroll
-            for (int q = 0; q < QF; ++q) {
-                const int col = lane + q * kWave;
-                if (col >= lo && col < hi) a[q & 1] = cfma(R2[q], xs2[col + c * ld2], a[q & 1]);
+                for (int q0 = 0; q0 < QF; q0 += XG) {
+                    cd xv[XG];
+#pragma unroll
+                    for (int g = 0; g < XG; ++g) xv[g] = xs2[lane + (q0 + g) * kWave];
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int g = 0; g < XG; ++g) {
+                        const int q = q0 + g, col = lane + q * kWave;
+                        a[q & 1] = cfma(R2[q], (col >= lo && col < hi) ? xv[g] : zero, a[q & 1]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < QC; ++q) {
+                    const int col = lane + q * kWave;
+                    if (col < w1) a[q & 1] = cfma(R1[q], xs1[o1 + col + c * ld1], a[q & 1]);
+                }
+#pragma unroll
+                for (int q = 0; q < QF; ++q) {
+                    const int col = lane + q * kWave;
+                    if (col >= lo && col < hi) a[q & 1] = cfma(R2[q], xs2[col + c * ld2], a[q & 1]);
+                }
             }
             acc[c] = cadd(acc[c], cadd(a[0], a[1]));
         }
@@ -284,13 +315,19 @@ __device__ __forceinline__ void row_partial(const cd (&R1)[QC], int w1, const cd
 template <int S>
 __device__ __forceinline__ void row_head(const cd (&R2)[QF], int hi, const cd* xs2, int ld2, int cs, cd (&acc)[S]) {
     const int lane = threadIdx.x % kWave;
+    const cd zero = cmk(0.0, 0.0);
 #pragma unroll
     for (int c = 0; c < S; ++c) {
         if (c < cs) {
 #pragma unroll
             for (int q = 0; q < QC; ++q) {
                 const int col = lane + q * kWave;
-                if (col < hi) acc[c] = cfma(R2[q], xs2[col + c * ld2], acc[c]);
+                if constexpr (S == 1) {
+                    const cd xv = xs2[col];
+                    acc[c] = cfma(R2[q], col < hi ? xv : zero, acc[c]);
+                } else {
+                    if (col < hi) acc[c] = cfma(R2[q], xs2[col + c * ld2], acc[c]);
+                }
             }
         }
     }
@@ -430,7 +467,8 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             unsigned long long base, int epoch) {
     __shared__ int s_t;
     __shared__ cd bsh[kMaxLeaf * S];
-    __shared__ cd xs1[kMaxChunk * S];
+    // xs1 padded by kMaxChunk: the row products read it at o1 + col (< 2 kMaxChunk)
+    __shared__ cd xs1[kMaxChunk * (S + 1)];
     __shared__ cd xs2[kFoldCols * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
@@ -585,7 +623,8 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
     __shared__ int s_t;
     __shared__ cd ysh[kMaxLeaf * S];
     __shared__ cd ztsh[kMaxLeaf * S];
-    __shared__ cd xs1[kMaxChunk * S];
+    // xs1 padded by kMaxChunk: the row products read it at o1 + col (< 2 kMaxChunk)
+    __shared__ cd xs1[kMaxChunk * (S + 1)];
     __shared__ cd xs2[kFoldCols * S];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int64_t n = p.n;
