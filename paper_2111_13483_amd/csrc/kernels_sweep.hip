@@ -281,7 +281,7 @@ __device__ __forceinline__ void row_partial(const cd (&R1)[QC], int w1, const cd
                     const cd xv = xs1[o1 + col];
                     a[q & 1] = cfma(R1[q], col < w1 ? xv : zero, a[q & 1]);
                 }
-                constexpr int XG = 4;
+                constexpr int XG = 8;
                 static_assert(QF % XG == 0, "whole read groups");
 #pragma unroll
                 for (int q0 = 0; q0 < QF; q0 += XG) {
