@@ -179,9 +179,9 @@ __global__ void __launch_bounds__(NT)
 k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ rank, T* const* __restrict__ uv,
          const int64_t* __restrict__ slot_base, int64_t nwg, int64_t ntasks, const cd* __restrict__ x, int64_t n,
          int nrhs, cd* __restrict__ slots) {
-    // one column: twice the loads in flight (within the register count the
-    // wave path already sets); more columns keep the shallower groups
-    constexpr int RU = S == 1 ? 8 : 4, LG = S == 1 ? 16 : 8;
+    // one column: more loads in flight (within the register count the wave
+    // path already sets); more columns keep the shallower groups
+    constexpr int RU = S == 1 ? 6 : 4, JU = S == 1 ? 2 : 1, LG = S == 1 ? 16 : 8;
     __shared__ cd t12[2 * (kMaxRankCap + LG) * S];
     if ((int64_t)blockIdx.x >= nwg) {
         const int64_t task = nwg + ((int64_t)blockIdx.x - nwg) * NW + threadIdx.x / kWave;
@@ -213,28 +213,36 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
             for (int u = 0; u < RU; ++u)
 #pragma unroll
                 for (int c = 0; c < S; ++c) acc[u][c] = cmk(0.0, 0.0);
-            for (int j0 = 0; j0 < len_max; j0 += kWave) {
-                const int j = j0 + lane;
-                cd val[RU];
+            // JU column groups per step; x_s and x_t are read once per group
+            // and shared by the rows (entries past a row's end are zero)
+            for (int j0 = 0; j0 < len_max; j0 += JU * kWave) {
+                cd val[JU][RU], xsv[JU][S], xtv[JU][S];
 #pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    const int l = l0 + u * NW;
-                    const bool isv = l < r;
-                    const int len = isv ? nn : m;
-                    const T* row = isv ? V + (int64_t)l * nn : U + (int64_t)(l - r) * m;
-                    val[u] = (l < 2 * r && j < len) ? to_cd(row[j]) : cmk(0.0, 0.0);
+                for (int jj = 0; jj < JU; ++jj) {
+                    const int j = j0 + jj * kWave + lane;
+#pragma unroll
+                    for (int c = 0; c < S; ++c) {
+                        xsv[jj][c] = (c < cs && j < nn) ? x[g.s0 + j + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
+                        xtv[jj][c] = (c < cs && j < m) ? x[g.t0 + j + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        const int l = l0 + u * NW;
+                        const bool isv = l < r;
+                        const int len = isv ? nn : m;
+                        const T* row = isv ? V + (int64_t)l * nn : U + (int64_t)(l - r) * m;
+                        val[jj][u] = (l < 2 * r && j < len) ? to_cd(row[j]) : cmk(0.0, 0.0);
+                    }
                 }
 #pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    const int l = l0 + u * NW;
-                    const bool isv = l < r;
-                    const int len = isv ? nn : m;
-                    const cd* xseg = x + (isv ? g.s0 : g.t0);
-                    if (l < 2 * r && j < len)
+                for (int jj = 0; jj < JU; ++jj)
+#pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        const bool isv = l0 + u * NW < r;
 #pragma unroll
                         for (int c = 0; c < S; ++c)
-                            if (c < cs) acc[u][c] = cfma(val[u], xseg[j + (int64_t)(c0 + c) * n], acc[u][c]);
-                }
+                            acc[u][c] = cfma(val[jj][u], isv ? xsv[jj][c] : xtv[jj][c], acc[u][c]);
+                    }
             }
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
