@@ -417,7 +417,7 @@ def main():
         write_workload(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1"}))
         sys.exit(2)
     if args.serve:
         serve(args)
