@@ -217,7 +217,10 @@ int32_t hs_precond_apply(hs_context* ctx, const hs_precond* P, const void* v, vo
  * Between hs_timing_begin and hs_timing_end every launch of the forward and
  * backward preconditioner sweeps (Eq. 23-24) and of the near and far matvec
  * kernels (Eq. 11) made through ctx is bracketed by a pair of HIP events on
- * ctx's stream. hs_timing_end synchronises that stream and fills out with
+ * the stream it runs on: ctx's stream, except the near matvec, which runs on
+ * the library's second stream beside the far matvec (its time therefore
+ * spans the concurrent far kernel). hs_timing_end synchronises ctx's stream
+ * (which waits for the second stream after every matvec) and fills out with
  * the launch count and summed event time (ms) per kernel; it resets the
  * record. Intended for benchmarks: the events add a small gap per launch.
  * Errors: HS_EINVAL (NULL argument), HS_EHIP. */
