@@ -168,9 +168,128 @@ __device__ __forceinline__ void far_wave(const ColMask& mk, const AcaTask& g, in
     }
 }
 
+// One column, one workgroup: the larger factor is read once. With A the
+// smaller side and B the larger (element (i, l) of U at U[i + l m], of V^T at
+// V[i + l n]; xA, xB and outA, outB the matching segments of x and slots):
+//   tA[l] = sum_j A(j, l) xA[j]                 (rows of A^T, RU per wave)
+//   outB[i] = sum_l B(i, l) tA[l],  tB[l] = sum_i B(i, l) xB[i]
+//                                               (B streamed once, by waves of
+//                                                RB x 64 rows; per-wave partial
+//                                                tB summed in wave order)
+//   outA[j] = sum_l A(j, l) tB[l]               (one thread per row)
+template <class T, int RU, int JU, int LG>
+__device__ __forceinline__ void far_wg_once(const AcaTask& g, int r, const T* U, const cd* x, cd* st, cd* tA, cd* tB,
+                                            cd (*tp)[kMaxRankCap]) {
+    constexpr int RB = 4, LB = 4;
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    const int m = g.m, nn = g.n;
+    const T* V = U + (int64_t)m * r;
+    const bool ubig = m >= nn;
+    const T* Ab = ubig ? V : U;
+    const T* Bb = ubig ? U : V;
+    const int lenA = ubig ? nn : m, lenB = ubig ? m : nn;
+    const cd* xA = x + (ubig ? g.s0 : g.t0);
+    const cd* xB = x + (ubig ? g.t0 : g.s0);
+    cd* outA = ubig ? st + m : st;
+    cd* outB = ubig ? st : st + m;
+    // tA: rows of A^T, JU column groups per step
+    for (int l0 = wid; l0 < r; l0 += NW * RU) {
+        cd acc[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) acc[u] = cmk(0.0, 0.0);
+        for (int j0 = 0; j0 < lenA; j0 += JU * kWave) {
+            cd val[JU][RU], xv[JU];
+#pragma unroll
+            for (int jj = 0; jj < JU; ++jj) {
+                const int j = j0 + jj * kWave + lane;
+                xv[jj] = j < lenA ? xA[j] : cmk(0.0, 0.0);
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const int l = l0 + u * NW;
+                    val[jj][u] = (l < r && j < lenA) ? to_cd(Ab[(int64_t)l * lenA + j]) : cmk(0.0, 0.0);
+                }
+            }
+#pragma unroll
+            for (int jj = 0; jj < JU; ++jj)
+#pragma unroll
+                for (int u = 0; u < RU; ++u) acc[u] = cfma(val[jj][u], xv[jj], acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int l = l0 + u * NW;
+            const cd sum = wave_sum(acc[u]);
+            if (lane == 0 && l < r) tA[l] = sum;
+        }
+    }
+    for (int l = lane; l < r; l += kWave) tp[wid][l] = cmk(0.0, 0.0);
+    __syncthreads();
+    // B once: its output rows and the per-wave partials of tB
+    for (int i0 = wid * kWave * RB; i0 < lenB; i0 += NW * kWave * RB) {
+        cd xi[RB], o[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const int i = i0 + k * kWave + lane;
+            xi[k] = i < lenB ? xB[i] : cmk(0.0, 0.0);
+            o[k] = cmk(0.0, 0.0);
+        }
+        for (int l0 = 0; l0 < r; l0 += LB) {
+            cd bv[LB][RB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u)
+#pragma unroll
+                for (int k = 0; k < RB; ++k) {
+                    const int i = i0 + k * kWave + lane;
+                    bv[u][k] = (l0 + u < r && i < lenB) ? to_cd(Bb[i + (int64_t)(l0 + u) * lenB]) : cmk(0.0, 0.0);
+                }
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                if (l0 + u < r) {
+                    const cd ta = tA[l0 + u];
+                    cd p = cmul(bv[u][0], xi[0]);
+#pragma unroll
+                    for (int k = 1; k < RB; ++k) p = cfma(bv[u][k], xi[k], p);
+#pragma unroll
+                    for (int k = 0; k < RB; ++k) o[k] = cfma(bv[u][k], ta, o[k]);
+                    p = wave_sum(p);
+                    if (lane == 0) tp[wid][l0 + u] = cadd(tp[wid][l0 + u], p);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const int i = i0 + k * kWave + lane;
+            if (i < lenB) outB[i] = o[k];
+        }
+    }
+    __syncthreads();
+    for (int l = tid; l < r + LG; l += NT) {
+        cd sum = cmk(0.0, 0.0);
+        if (l < r) {
+            sum = tp[0][l];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) sum = cadd(sum, tp[w][l]);
+        }
+        tB[l] = sum;   // zero padding past r for the grouped loads below
+    }
+    __syncthreads();
+    // A's output rows, LG rank terms' loads issued together
+    for (int j = tid; j < lenA; j += NT) {
+        cd acc = cmk(0.0, 0.0);
+        for (int l0 = 0; l0 < r; l0 += LG) {
+            cd av[LG];
+#pragma unroll
+            for (int u = 0; u < LG; ++u) av[u] = (l0 + u < r) ? to_cd(Ab[j + (int64_t)(l0 + u) * lenA]) : cmk(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < LG; ++u) acc = cfma(av[u], tB[l0 + u], acc);
+        }
+        outA[j] = acc;
+    }
+}
+
 // The other blocks take one workgroup each: t1 and t2 (the 2r rows of V and
 // of U^T, one wave per row, RU rows' loads issued together), then slot_t and
 // slot_s (one thread per output row, LG rank terms' loads issued together).
+// Single-column passes use far_wg_once instead.
 // Workgroups [0, nwg) take tasks [0, nwg) (largest first); the rest take
 // NW wave tasks each from nwg on. One launch covers every far block, so the
 // small blocks fill the machine while the largest ones run.
@@ -183,6 +302,7 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
     // path already sets); more columns keep the shallower groups
     constexpr int RU = S == 1 ? 6 : 4, JU = S == 1 ? 2 : 1, LG = S == 1 ? 16 : 8;
     __shared__ cd t12[2 * (kMaxRankCap + LG) * S];
+    __shared__ cd tpart[S == 1 ? NW : 1][kMaxRankCap];
     if ((int64_t)blockIdx.x >= nwg) {
         const int64_t task = nwg + ((int64_t)blockIdx.x - nwg) * NW + threadIdx.x / kWave;
         if (task >= ntasks) return;
@@ -200,6 +320,10 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
     const T* V = U + (int64_t)m * r;
     cd* st = slots + slot_base[blockIdx.x] * nrhs;
     cd* ss = st + (int64_t)m * nrhs;
+    if constexpr (S == 1) {   // nrhs is 1 here
+        if (cols_live(mk, 0, 1)) far_wg_once<T, RU, JU, LG>(g, r, U, x, st, t12, t12 + kMaxRankCap + LG, tpart);
+        return;
+    }
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int rp = r + LG;   // t1 rows [0, r), padding, t2 rows from rp
     const int len_max = max(m, nn);
