@@ -168,6 +168,17 @@ __device__ __forceinline__ void far_wave(const ColMask& mk, const AcaTask& g, in
     }
 }
 
+// Wave tasks [0, ntasks) of the arrays passed, NW per workgroup.
+template <int S, class T>
+__global__ void __launch_bounds__(NT)
+k_far_wave(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ rank, T* const* __restrict__ uv,
+           const int64_t* __restrict__ slot_base, int64_t ntasks, const cd* __restrict__ x, int64_t n, int nrhs,
+           cd* __restrict__ slots) {
+    const int64_t task = (int64_t)blockIdx.x * NW + threadIdx.x / kWave;
+    if (task >= ntasks) return;
+    far_wave<S, T>(mk, geom[task], rank[task], uv[task], slots + slot_base[task] * nrhs, x, n, nrhs);
+}
+
 // One column, one workgroup: the larger factor is read once. With A the
 // smaller side and B the larger (element (i, l) of U at U[i + l m], of V^T at
 // V[i + l n]; xA, xB and outA, outB the matching segments of x and slots):
@@ -296,19 +307,13 @@ __device__ __forceinline__ void far_wg_once(const AcaTask& g, int r, const T* U,
 template <int S, class T>
 __global__ void __launch_bounds__(NT)
 k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ rank, T* const* __restrict__ uv,
-         const int64_t* __restrict__ slot_base, int64_t nwg, int64_t ntasks, const cd* __restrict__ x, int64_t n,
-         int nrhs, cd* __restrict__ slots) {
+         const int64_t* __restrict__ slot_base, const cd* __restrict__ x, int64_t n, int nrhs,
+         cd* __restrict__ slots) {
     // one column: more loads in flight (within the register count the wave
     // path already sets); more columns keep the shallower groups
     constexpr int RU = S == 1 ? 6 : 4, JU = S == 1 ? 2 : 1, LG = S == 1 ? 16 : 8;
     __shared__ cd t12[2 * (kMaxRankCap + LG) * S];
     __shared__ cd tpart[S == 1 ? NW : 1][kMaxRankCap];
-    if ((int64_t)blockIdx.x >= nwg) {
-        const int64_t task = nwg + ((int64_t)blockIdx.x - nwg) * NW + threadIdx.x / kWave;
-        if (task >= ntasks) return;
-        far_wave<S, T>(mk, geom[task], rank[task], uv[task], slots + slot_base[task] * nrhs, x, n, nrhs);
-        return;
-    }
     const AcaTask g = geom[blockIdx.x];
     const int m = g.m, nn = g.n, r = rank[blockIdx.x];
     if (r == 0) {
@@ -810,14 +815,25 @@ void near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base,
 template <class T>
 void far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, T* const* uv, const int64_t* slot_base,
             int64_t nwg, int64_t ntasks, const cd* x, int64_t n, int nrhs, cd* slots, hipStream_t s) {
-    if (ntasks == 0) return;
-    const int64_t grid = nwg + (ntasks - nwg + NW - 1) / NW;
-    if (nrhs == 1)
-        hipLaunchKernelGGL((k_far_mv<1, T>), dim3((unsigned)grid), dim3(NT), 0, s, mk, geom, rank, uv, slot_base, nwg,
-                           ntasks, x, n, nrhs, slots);
-    else
-        hipLaunchKernelGGL((k_far_mv<SCH, T>), dim3((unsigned)grid), dim3(NT), 0, s, mk, geom, rank, uv, slot_base,
-                           nwg, ntasks, x, n, nrhs, slots);
+    // the workgroup blocks, then the wave blocks: two kernels on one stream,
+    // so each keeps its own register count (and occupancy)
+    const int64_t nwv = ntasks - nwg;
+    const unsigned gw = (unsigned)((nwv + NW - 1) / NW);
+    if (nrhs == 1) {
+        if (nwg > 0)
+            hipLaunchKernelGGL((k_far_mv<1, T>), dim3((unsigned)nwg), dim3(NT), 0, s, mk, geom, rank, uv, slot_base, x,
+                               n, nrhs, slots);
+        if (nwv > 0)
+            hipLaunchKernelGGL((k_far_wave<1, T>), dim3(gw), dim3(NT), 0, s, mk, geom + nwg, rank + nwg, uv + nwg,
+                               slot_base + nwg, nwv, x, n, nrhs, slots);
+    } else {
+        if (nwg > 0)
+            hipLaunchKernelGGL((k_far_mv<SCH, T>), dim3((unsigned)nwg), dim3(NT), 0, s, mk, geom, rank, uv, slot_base,
+                               x, n, nrhs, slots);
+        if (nwv > 0)
+            hipLaunchKernelGGL((k_far_wave<SCH, T>), dim3(gw), dim3(NT), 0, s, mk, geom + nwg, rank + nwg, uv + nwg,
+                               slot_base + nwg, nwv, x, n, nrhs, slots);
+    }
 }
 }  // namespace
 
