@@ -191,7 +191,7 @@ k_far_wave(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__
 template <class T, int RU, int JU, int LG>
 __device__ __forceinline__ void far_wg_once(const AcaTask& g, int r, const T* U, const cd* x, cd* st, cd* tA, cd* tB,
                                             cd (*tp)[kMaxRankCap]) {
-    constexpr int RB = 4, LB = 4;
+    constexpr int RB = 4, LB = 2;
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int m = g.m, nn = g.n;
     const T* V = U + (int64_t)m * r;
@@ -309,9 +309,8 @@ __global__ void __launch_bounds__(NT)
 k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ rank, T* const* __restrict__ uv,
          const int64_t* __restrict__ slot_base, const cd* __restrict__ x, int64_t n, int nrhs,
          cd* __restrict__ slots) {
-    // one column: more loads in flight (within the register count the wave
-    // path already sets); more columns keep the shallower groups
-    constexpr int RU = S == 1 ? 6 : 4, JU = S == 1 ? 2 : 1, LG = S == 1 ? 16 : 8;
+    // one column: two column groups per step; sized for 5 waves per SIMD
+    constexpr int RU = 4, JU = S == 1 ? 2 : 1, LG = 8;
     __shared__ cd t12[2 * (kMaxRankCap + LG) * S];
     __shared__ cd tpart[S == 1 ? NW : 1][kMaxRankCap];
     const AcaTask g = geom[blockIdx.x];
