@@ -234,6 +234,12 @@ typedef struct hs_kernel_times {
     double  total_ms[HS_KT_COUNT];
 } hs_kernel_times;
 int32_t hs_timing_begin(hs_context* ctx);
+/* As hs_timing_begin, but only every `every`-th launch of each kernel
+ * (counted from this call, the first one included) is bracketed; every = 1
+ * is hs_timing_begin. A sample keeps the events' ordering points out of most
+ * of the timed work while the averages stay per launch.
+ * Errors: HS_EINVAL (NULL ctx, every < 1). */
+int32_t hs_timing_begin_every(hs_context* ctx, int32_t every);
 int32_t hs_timing_end(hs_context* ctx, hs_kernel_times* out);
 
 /* ---- test exports (device handles -> host memory) ---------------------------

@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH):
         "hs_server_request": (i32, [vp, i64, ctypes.POINTER(RequestStats)]),
         "hs_server_destroy": (None, [vp]),
         "hs_timing_begin": (i32, [vp]),
+        "hs_timing_begin_every": (i32, [vp, i32]),
         "hs_timing_end": (i32, [vp, ctypes.POINTER(KernelTimes)]),
         "hs_status_string": (ctypes.c_char_p, [i32]),
         "hs_last_error": (ctypes.c_char_p, []),
@@ -139,7 +140,8 @@ EXPORTED = (
     "hs_context_create", "hs_context_set_stream", "hs_context_destroy", "hs_plan_create", "hs_plan_query",
     "hs_plan_destroy", "hs_plan_export", "hs_h_build", "hs_query_hmatrix", "hs_hmatrix_destroy", "hs_precond_setup",
     "hs_precond_setup_many", "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_precond_apply", "hs_hmatrix_export",
-    "hs_precond_export", "hs_timing_begin", "hs_timing_end", "hs_server_clock", "hs_server_create",
+    "hs_precond_export", "hs_timing_begin", "hs_timing_begin_every", "hs_timing_end", "hs_server_clock",
+    "hs_server_create",
     "hs_server_admit", "hs_server_submit", "hs_server_step", "hs_server_pending", "hs_server_request",
     "hs_server_destroy", "hs_status_string", "hs_last_error",
 )
@@ -228,9 +230,10 @@ class Context:
         _check(L.hs_context_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream), a, f, None))
         self._h = h
 
-    def timing_begin(self):
-        """Start bracketing the sweep and matvec launches with HIP events."""
-        _check(_lib.hs_timing_begin(self._h))
+    def timing_begin(self, every: int = 1):
+        """Start bracketing the sweep and matvec launches with HIP events
+        (every `every`-th launch of each kernel)."""
+        _check(_lib.hs_timing_begin_every(self._h, int(every)))
 
     def timing_end(self) -> dict:
         """Stop timing; {kernel: (launches, total ms)}."""

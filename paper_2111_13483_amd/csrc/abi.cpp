@@ -134,6 +134,8 @@ hs::cf* c64_copy(Owned& own, Owned& tmp, const cd* src, int64_t count, hipStream
 // bracketed by a pair of events on the context's stream.
 struct KernelTimer {
     bool on = false;
+    int every = 1;                       // bracket every `every`-th launch of each kind
+    int64_t seen[HS_KT_COUNT] = {};      // launches of each kind since timing began
     struct Rec {
         int kind;
         hipEvent_t a, b;
@@ -195,6 +197,10 @@ namespace {
 template <class F>
 void timed(hs_context* ctx, int kind, hipStream_t s, F&& f) {
     if (!ctx || !ctx->timer.on) {
+        f();
+        return;
+    }
+    if (ctx->timer.seen[kind]++ % ctx->timer.every != 0) {
         f();
         return;
     }
@@ -614,17 +620,22 @@ int32_t hs_context_set_stream(hs_context* ctx, void* hip_stream) {
 
 void hs_context_destroy(hs_context* ctx) { delete ctx; }
 
-int32_t hs_timing_begin(hs_context* ctx) {
+int32_t hs_timing_begin_every(hs_context* ctx, int32_t every) {
     try {
         if (!ctx) fail(HS_EINVAL, "ctx is NULL");
+        if (every < 1) fail(HS_EINVAL, "every must be >= 1");
         set_device(ctx);
         ctx->timer.release();
+        ctx->timer.every = every;
+        for (int64_t& c : ctx->timer.seen) c = 0;
         ctx->timer.on = true;
         return HS_OK;
     } catch (const Error& e) {
         return set_error(e);
     }
 }
+
+int32_t hs_timing_begin(hs_context* ctx) { return hs_timing_begin_every(ctx, 1); }
 
 int32_t hs_timing_end(hs_context* ctx, hs_kernel_times* out) {
     try {
