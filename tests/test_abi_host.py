@@ -137,3 +137,10 @@ def test_plan_flop_count_matches_pattern():
         fl += sum(8 * b[k] ** 2 * b[j] for j in S)
         fl += sum(8 * b[i] * b[k] * b[j] for a, i in enumerate(S) for j in S[a:])
     assert abs(plan.info()["flops_setup"] - fl) <= 1e-9 * fl
+
+
+def test_timing_argument_validation():
+    L = hsl.load()
+    assert L.hs_timing_begin(None) == hsl.HS_EINVAL
+    assert L.hs_timing_begin_every(None, 4) == hsl.HS_EINVAL
+    assert L.hs_timing_end(None, None) == hsl.HS_EINVAL

@@ -366,3 +366,20 @@ def test_precond_layout_arguments(env, c1_oracle):
         with pytest.raises(hsl.HschurError) as ei:
             hsl.Precond(ctx, H, "rcm", 1e-2, sweep_chunk=bad[0], sweep_fold_cols=bad[1])
         assert ei.value.status == hsl.HS_EINVAL
+
+
+def test_timing_sample_counts(env, c1_oracle):
+    # hs_timing_begin_every brackets launches 0, k, 2k, ... of each kernel
+    hsl, torch, ctx = env
+    wl, hm = c1_oracle
+    H = _gpu_h(env, wl)
+    x = torch.ones(wl.n, dtype=torch.complex128, device="cuda")
+    for every, want in ((1, 7), (3, 3)):
+        ctx.timing_begin(every=every)
+        for _ in range(7):
+            H.matvec(x)
+        kt = ctx.timing_end()
+        assert kt["far_mv"][0] == want and kt["near_mv"][0] == want, (every, kt)
+        assert kt["far_mv"][1] > 0.0
+    with pytest.raises(hsl.HschurError):
+        ctx.timing_begin(every=0)
