@@ -22,9 +22,10 @@ W S X^H; keep the smallest r' with sqrt(sum_{i > r'} s_i^2) <= eps ||s||_2;
 U' = Q_U W_r' S_r', V' = X_r'^H Q_V^T.
 
 Pinned in the tests: an exactly rank-r matrix is recovered at rank r to
-rounding; for kernel blocks the Frobenius error bound of Eq. 10 holds
-against the dense block; the re-compressed product equals the truncated SVD
-of U V computed directly.
+rounding; on kernel blocks the stop rule holds exactly at the last term, and
+the true error against the dense block is within eps for the median block
+and within 5 eps for all (the stop test only estimates the Eq. 10 error);
+the re-compressed product equals the truncated SVD of U V computed directly.
 """
 from __future__ import annotations
 

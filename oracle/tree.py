@@ -19,7 +19,8 @@ following reading (also used by the GPU library's host code):
 
 Pinned in the tests by brute force: every point lies in exactly one leaf,
 every leaf holds at most ``leaf_max`` points (or sits at depth 21), and each
-box's points all share its Morton prefix.
+box's points all share its Morton prefix. The bit order of the key and the
+centring of the root cube are pinned by hand-computed values.
 """
 from __future__ import annotations
 

@@ -63,19 +63,44 @@ def test_recompress_is_truncated_svd_of_product():
 
 
 def test_aca_kernel_blocks_meet_frobenius_bound():
-    # Eq. 10: || Z_sub - U V ||_F <= eps || Z_sub ||_F on real far blocks
+    # Eq. 10 asks for || Z_sub - U V ||_F <= eps || Z_sub ||_F. Partial-pivot ACA
+    # only estimates that error (its stop test looks at the newest rank-one term),
+    # so the pin has three parts:
+    #  * exact: the stop rule itself holds at the last term and fails before it;
+    #  * exact: re-compression drops at most eps of the ACA product's norm;
+    #  * measured: against the dense block the error is within eps for the
+    #    median block and within 5 eps for every block (on this sphere the worst
+    #    is 4.7 eps and 12% of blocks exceed eps). A dropped or mis-signed
+    #    residual term gives errors of order one, far outside both bounds.
+    eps = 1e-4
     wl = W.make_config("c1")
-    hm = hmatrix.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, 1e-4)
-    worst = 0.0
+    hm = hmatrix.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, eps)
+    errs = []
     for (t, s), U, V in zip(hm.part.far, hm.far_u, hm.far_v):
         a0, a1 = hm.box_range(int(t))
         b0, b1 = hm.box_range(int(s))
-        Z = kernel.kernel_block(hm.pts[a0:a1], hm.pts[b0:b1], wl.k, wl.self_h)
-        err = np.linalg.norm(Z - U @ V) / np.linalg.norm(Z)
-        worst = max(worst, err)
+        pt, ps = hm.pts[a0:a1], hm.pts[b0:b1]
+        Z = kernel.kernel_block(pt, ps, wl.k, wl.self_h)
+        errs.append(np.linalg.norm(Z - U @ V) / np.linalg.norm(Z))
         assert U.shape[1] <= min(a1 - a0, b1 - b0)
-    # ACA's stopping test is a heuristic estimate of the error: allow a small factor
-    assert worst <= 5e-4
+        if len(errs) % 7:
+            continue
+        # every 7th block: replay the ACA and check the stop rule term by term
+        Ua, Va, piv, _ = aca.aca(lambda i: Z[i], lambda j: Z[:, j], a1 - a0, b1 - b0, eps)
+        r = Ua.shape[1]
+        for q in range(1, r + 1):
+            term = np.linalg.norm(Ua[:, q - 1]) * np.linalg.norm(Va[q - 1])
+            est = np.linalg.norm(Ua[:, :q] @ Va[:q])
+            if q < r:
+                assert term > eps * est * (1 - 1e-12)
+            elif r < min(a1 - a0, b1 - b0):
+                assert term <= eps * est * (1 + 1e-12)
+        Ur, Vr = aca.recompress(Ua, Va, eps)
+        P = Ua @ Va
+        assert np.linalg.norm(P - Ur @ Vr) <= eps * np.linalg.norm(P) * (1 + 1e-10)
+    errs = np.array(errs)
+    assert np.median(errs) <= eps
+    assert errs.max() <= 5 * eps
 
 
 # ---- ordering: hand-worked cases from the stated rules -------------------------------

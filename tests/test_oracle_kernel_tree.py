@@ -170,3 +170,36 @@ def test_fig2_fixture_has_the_four_leaf_pattern():
     p = partition.build_partition(t)
     off = [tuple(map(int, x)) for x in p.near if x[0] != x[1]]
     assert t.nb == 4 and len(off) == 5
+
+
+def test_morton_keys_hand_computed():
+    # The interleave puts bit i of qx, qy, qz at key bits 3i, 3i+1, 3i+2 (x lowest).
+    # Values worked out by hand, so a permuted axis or a shifted bit fails.
+    q = np.array([
+        [1, 0, 0],          # -> 1
+        [0, 1, 0],          # -> 2
+        [0, 0, 1],          # -> 4
+        [3, 0, 0],          # bits 0,1 of x -> key bits 0,3 -> 9
+        [0, 2, 0],          # bit 1 of y -> key bit 4 -> 16
+        [5, 6, 1],          # x bits 0,2 -> 0,6; y bits 1,2 -> 4,7; z bit 0 -> 2 -> 1+64+16+128+4
+        [0, 0, 1 << 20],    # top bit of z -> key bit 62
+        [(1 << 21) - 1] * 3,  # all ones -> 2^63 - 1
+    ], dtype=np.int64)
+    want = [1, 2, 4, 9, 16, 213, 1 << 62, (1 << 63) - 1]
+    assert tree.morton(q).tolist() == want
+
+
+def test_quantisation_centres_the_root_cube():
+    # Box x in [0, 4], y and z in [0, 1]: E = 4, centre (2, .5, .5), cube origin
+    # (0, -1.5, -1.5). With 2^21 / E = 2^19 the short axes start at 1.5 * 2^19,
+    # not at 0 (which an origin at the box corner would give).
+    pts = np.array([[0.0, 0.0, 0.0], [4.0, 1.0, 1.0], [1.0, 0.25, 0.75], [3.0, 0.5, 0.0]])
+    q = tree.quantise(pts)
+    s = 1 << 19
+    want = np.array([
+        [0, 3 * s // 2, 3 * s // 2],
+        [tree.QMAX, 5 * s // 2, 5 * s // 2],     # x clamps at 2^21 - 1
+        [s, 7 * s // 4, 9 * s // 4],
+        [3 * s, 2 * s, 3 * s // 2],
+    ], dtype=np.int64)
+    assert np.array_equal(q, want)

@@ -130,11 +130,17 @@ def test_fill_compression_bound_and_rule():
     hm = hmatrix.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, 1e-4)
     pc = pipeline.precond_setup(hm, "rcm", 1e-2)
     assert len(pc.lowrank) > 0
+    errs = []
     for (k, j), (U, V) in pc.lowrank.items():
         A = pc.alpha[(k, j)]
         assert not pc.sym.orig[k][pc.sym.rows[k].index(j)]
         assert U.shape[1] * sum(A.shape) < A.size
-        assert np.linalg.norm(A - U @ V) <= 5 * 1e-2 * np.linalg.norm(A)
+        errs.append(np.linalg.norm(A - U @ V) / np.linalg.norm(A))
+    # Same reading as the far-field pin (Eq. 10): ACA's stop test estimates the
+    # error, so the median block is within fill_tol and every block within
+    # 5 fill_tol (measured here: worst 2.0 fill_tol, 8% of blocks above it).
+    assert np.median(errs) <= 1e-2
+    assert max(errs) <= 5 * 1e-2
 
 
 def test_gmres_single_leaf_converges_in_one_step():
