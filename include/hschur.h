@@ -50,6 +50,9 @@ extern "C" {
 #define HS_EHIP           (-4)  /* a HIP runtime call failed */
 #define HS_ESINGULAR      (-5)  /* exactly zero pivot in a leaf-block LU */
 #define HS_ENUMERIC       (-6)  /* NaN or Inf met, or an ACA rank exceeded its cap */
+#define HS_ETIMEOUT       (-7)  /* a device-side wait of the preconditioner apply exceeded the
+                                   context's wait limit (hs_context_set_wait_limit); every kernel
+                                   still ran to its end, the outputs are unspecified */
 
 /* ---- option enums ------------------------------------------------------ */
 #define HS_ORDER_NATURAL    0   /* leaf (octree depth-first) order */
@@ -130,8 +133,19 @@ typedef struct {
  * Errors: HS_ENODEVICE if the device is absent or not gfx950, HS_EINVAL. */
 int32_t hs_context_create(hs_context** out, int32_t device, void* hip_stream,
                           hs_alloc_fn alloc, hs_free_fn free_fn, void* user);
-/* Change the stream later calls enqueue on. */
+/* Change the stream later calls enqueue on. Preconditioner applies (the
+ * sweeps of Eq. 23-24 keep workgroups resident and waiting on each other)
+ * are ordered library-wide per device: an apply issued on one stream waits
+ * for those issued earlier on any other stream, so two never run at once.
+ * A stream that has carried applies must stay valid until the context has
+ * moved off it (this call or hs_context_destroy). */
 int32_t hs_context_set_stream(hs_context* ctx, void* hip_stream);
+/* Bound, in seconds, on every device-side wait inside a preconditioner apply
+ * (default 5). A wait that polls longer gives up: every kernel of the apply
+ * still ends normally, and the call that issued it returns HS_ETIMEOUT.
+ * 0 makes a wait give up at its first check unless already satisfied (used
+ * by the tests to exercise that path). Errors: HS_EINVAL (NULL, negative). */
+int32_t hs_context_set_wait_limit(hs_context* ctx, double seconds);
 void    hs_context_destroy(hs_context* ctx);
 
 /* ---- host-only planning: the integer phases ------------------------------
@@ -230,8 +244,9 @@ int32_t hs_precond_apply(hs_context* ctx, const hs_precond* P, const void* v, vo
 #define HS_KT_FAR_MV    3
 #define HS_KT_COUNT     4
 typedef struct hs_kernel_times {
-    int64_t launches[HS_KT_COUNT];
-    double  total_ms[HS_KT_COUNT];
+    int64_t launches[HS_KT_COUNT];      /* bracketed (timed) launches */
+    double  total_ms[HS_KT_COUNT];      /* summed event time of the bracketed launches */
+    int64_t all_launches[HS_KT_COUNT];  /* every launch made while timing was on, bracketed or not */
 } hs_kernel_times;
 int32_t hs_timing_begin(hs_context* ctx);
 /* As hs_timing_begin, but only every `every`-th launch of each kernel

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhschur.so")
 
 HS_OK, HS_NOT_CONVERGED = 0, 1
-HS_EINVAL, HS_ENOMEM, HS_ENODEVICE, HS_EHIP, HS_ESINGULAR, HS_ENUMERIC = -1, -2, -3, -4, -5, -6
+HS_EINVAL, HS_ENOMEM, HS_ENODEVICE, HS_EHIP, HS_ESINGULAR, HS_ENUMERIC, HS_ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
 ORDER = {"natural": 0, "rcm": 1, "cm": 2}
 X_CODES = {"perm": 1, "leaf_off": 2, "boxes": 3, "near": 4, "far": 5, "order": 6, "rowptr": 7, "cols": 8, "orig": 9}
 H_CODES = {"near_off": 101, "near_data": 102, "far_rank": 103, "far_off": 104, "far_uv": 105, "far_piv": 106}
@@ -75,7 +75,8 @@ class RequestStats(ctypes.Structure):
 
 
 class KernelTimes(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4),
+                ("all_launches", ctypes.c_int64 * 4)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -97,6 +98,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "hs_context_create": (i32, [pvp, i32, vp, ALLOC_FN, FREE_FN, vp]),
         "hs_context_set_stream": (i32, [vp, vp]),
+        "hs_context_set_wait_limit": (i32, [vp, dbl]),
         "hs_context_destroy": (None, [vp]),
         "hs_plan_create": (i32, [vp, i64, i32, i32, pvp]),
         "hs_plan_query": (i32, [vp, ctypes.POINTER(Info)]),
@@ -137,7 +139,7 @@ def load(path: str = LIB_PATH):
 
 
 EXPORTED = (
-    "hs_context_create", "hs_context_set_stream", "hs_context_destroy", "hs_plan_create", "hs_plan_query",
+    "hs_context_create", "hs_context_set_stream", "hs_context_set_wait_limit", "hs_context_destroy", "hs_plan_create", "hs_plan_query",
     "hs_plan_destroy", "hs_plan_export", "hs_h_build", "hs_query_hmatrix", "hs_hmatrix_destroy", "hs_precond_setup",
     "hs_precond_setup_many", "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_precond_apply", "hs_hmatrix_export",
     "hs_precond_export", "hs_timing_begin", "hs_timing_begin_every", "hs_timing_end", "hs_server_clock",
@@ -236,10 +238,19 @@ class Context:
         _check(_lib.hs_timing_begin_every(self._h, int(every)))
 
     def timing_end(self) -> dict:
-        """Stop timing; {kernel: (launches, total ms)}."""
+        """Stop timing; {kernel: (timed launches, their total ms, all launches)}."""
         kt = KernelTimes()
         _check(_lib.hs_timing_end(self._h, ctypes.byref(kt)))
-        return {name: (int(kt.launches[i]), float(kt.total_ms[i])) for i, name in enumerate(KT_NAMES)}
+        return {name: (int(kt.launches[i]), float(kt.total_ms[i]), int(kt.all_launches[i]))
+                for i, name in enumerate(KT_NAMES)}
+
+    def set_wait_limit(self, seconds: float):
+        """Bound on each device-side wait of the preconditioner sweeps."""
+        _check(_lib.hs_context_set_wait_limit(self._h, float(seconds)))
+
+    def set_stream(self, stream):
+        _check(_lib.hs_context_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

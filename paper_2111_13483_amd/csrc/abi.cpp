@@ -11,6 +11,7 @@
 #include <limits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
@@ -183,12 +184,30 @@ struct AuxStream {
     }
 };
 
+// Sweeps of the preconditioner apply keep workgroups resident that wait on
+// each other, so two must never run at once on a device. Applies on one
+// stream are ordered by the stream; across streams (contexts, or a context
+// whose stream changed) each device keeps the stream of its latest apply and
+// an event: an apply on another stream waits for that event, recorded on the
+// previous stream when the stream changes (or when a context moves off it),
+// and after every apply once more than one stream has been seen.
+struct SweepOrder {
+    std::mutex mu;
+    hipStream_t last = nullptr;   // stream of the latest apply not yet captured in `done`
+    bool have_done = false;       // `done` holds a recorded apply that other streams must wait for
+    bool multi = false;           // applies have come from more than one stream
+    hipEvent_t done = nullptr;
+};
+SweepOrder g_sweep_order[64];
+
 struct hs_context {
     int device = 0;
     hipStream_t stream = nullptr;
     Mem mem;
     KernelTimer timer;
     AuxStream aux;
+    double wait_seconds = 5.0;    // bound on a sweep's device-side waits
+    double clock_khz = 0.0;       // constant-rate device clock (wall_clock64)
 };
 
 namespace {
@@ -526,19 +545,74 @@ struct SweepWs {
     int epoch = 0;
 };
 
+SweepOrder& sweep_order(int device) {
+    if (device < 0 || device >= 64) fail(HS_EINVAL, "device index beyond the library's table");
+    return g_sweep_order[device];
+}
+
+// Called before the sweeps of an apply on stream s (see SweepOrder).
+void sweeps_begin(int device, hipStream_t s) {
+    SweepOrder& o = sweep_order(device);
+    std::lock_guard<std::mutex> lk(o.mu);
+    if (o.last != nullptr && o.last != s) {
+        if (!o.done) hip_check(hipEventCreateWithFlags(&o.done, hipEventDisableTiming), "hipEventCreateWithFlags");
+        hip_check(hipEventRecord(o.done, o.last), "hipEventRecord");
+        o.have_done = true;
+        o.multi = true;
+        o.last = nullptr;
+    }
+    if (o.last == nullptr && o.have_done) hip_check(hipStreamWaitEvent(s, o.done, 0), "hipStreamWaitEvent");
+    o.last = s;
+}
+
+// Called after the sweeps of an apply on stream s.
+void sweeps_end(int device, hipStream_t s) {
+    SweepOrder& o = sweep_order(device);
+    std::lock_guard<std::mutex> lk(o.mu);
+    if (!o.multi) return;
+    hip_check(hipEventRecord(o.done, s), "hipEventRecord");
+    o.have_done = true;
+}
+
+// A context moves off stream s (new stream or destruction): capture its
+// latest apply while s is still valid.
+void sweeps_release(int device, hipStream_t s) {
+    SweepOrder& o = sweep_order(device);
+    std::lock_guard<std::mutex> lk(o.mu);
+    if (o.last != s || s == nullptr) return;
+    if (!o.done && hipEventCreateWithFlags(&o.done, hipEventDisableTiming) != hipSuccess) return;
+    if (hipEventRecord(o.done, s) == hipSuccess) o.have_done = true;
+    o.multi = true;
+    o.last = nullptr;
+}
+
 void apply_tree(hs_context* ctx, const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, hipStream_t s,
                 const hs::ColMask& mk) {
     ws.epoch += 1;
+    sweeps_begin(ctx->device, s);
     timed(ctx, HS_KT_SWEEP_FWD, s,
           [&] { hs::launch_sweep(true, mk, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s); });
     timed(ctx, HS_KT_SWEEP_BWD, s,
           [&] { hs::launch_sweep(false, mk, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s); });
+    sweeps_end(ctx->device, s);
+}
+
+// The sweeps' error flag (bounded waits) of a workspace, read after a
+// synchronisation point the caller already pays for.
+void check_sweep_flag(const SweepWs& ws, hipStream_t s) {
+    if (!ws.w.err) return;
+    if (download(ws.w.err, 1, s)[0] != 0)
+        fail(HS_ETIMEOUT, "a device-side wait of the preconditioner sweeps exceeded the context's wait limit");
 }
 
 const hs::ColMask kAllCols{nullptr, 0, 0};
 
-SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s) {
+SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s, const hs_context* ctx) {
     SweepWs sw;
+    sw.w.err = o.get<int>(1);
+    hip_check(hipMemsetAsync(sw.w.err, 0, sizeof(int), s), "memset err");
+    const double ticks = ctx->wait_seconds * ctx->clock_khz * 1e3;
+    sw.w.wait_ticks = ticks < 9e18 ? (long long)ticks : (long long)9e18;
     const size_t nn = (size_t)P->H->n * nrhs;
     sw.w.ybuf = o.get<cd>(nn);
     sw.w.zbuf = o.get<cd>(nn);
@@ -576,6 +650,7 @@ const char* hs_status_string(int32_t st) {
         case HS_EHIP: return "HIP runtime error";
         case HS_ESINGULAR: return "singular leaf block";
         case HS_ENUMERIC: return "numerical failure";
+        case HS_ETIMEOUT: return "device wait timed out";
         default: return "unknown status";
     }
 }
@@ -598,7 +673,12 @@ int32_t hs_context_create(hs_context** out, int32_t device, void* hip_stream, hs
         hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
         if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
             fail(HS_ENODEVICE, std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950");
+        int khz = 0;
+        hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device), "hipDeviceGetAttribute");
+        if (khz <= 0) fail(HS_ENODEVICE, "the device reports no constant-rate clock");
+        if (device >= 64) fail(HS_ENODEVICE, "device index beyond the library's table (64)");
         auto* c = new hs_context;
+        c->clock_khz = khz;
         c->device = device;
         c->stream = static_cast<hipStream_t>(hip_stream);
         c->mem.alloc = alloc;
@@ -614,11 +694,27 @@ int32_t hs_context_create(hs_context** out, int32_t device, void* hip_stream, hs
 
 int32_t hs_context_set_stream(hs_context* ctx, void* hip_stream) {
     if (!ctx) { g_last_error = "ctx is NULL"; return HS_EINVAL; }
+    if (static_cast<hipStream_t>(hip_stream) != ctx->stream) {
+        (void)hipSetDevice(ctx->device);
+        sweeps_release(ctx->device, ctx->stream);
+    }
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     return HS_OK;
 }
 
-void hs_context_destroy(hs_context* ctx) { delete ctx; }
+int32_t hs_context_set_wait_limit(hs_context* ctx, double seconds) {
+    if (!ctx) { g_last_error = "ctx is NULL"; return HS_EINVAL; }
+    if (!(seconds >= 0.0)) { g_last_error = "the wait limit must be >= 0"; return HS_EINVAL; }
+    ctx->wait_seconds = seconds;
+    return HS_OK;
+}
+
+void hs_context_destroy(hs_context* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    sweeps_release(ctx->device, ctx->stream);
+    delete ctx;
+}
 
 int32_t hs_timing_begin_every(hs_context* ctx, int32_t every) {
     try {
@@ -643,6 +739,7 @@ int32_t hs_timing_end(hs_context* ctx, hs_kernel_times* out) {
         set_device(ctx);
         std::memset(out, 0, sizeof(*out));
         ctx->timer.on = false;
+        for (int k = 0; k < HS_KT_COUNT; ++k) out->all_launches[k] = ctx->timer.seen[k];
         hip_check(hipStreamSynchronize(ctx->stream), "stream sync");
         for (const auto& r : ctx->timer.recs) {
             float ms = 0.0f;
@@ -1859,12 +1956,12 @@ int32_t hs_precond_apply(hs_context* ctx, const hs_precond* P, const void* v, vo
         const int64_t n = P->H->n;
         cd* vt = w.get<cd>(n * nrhs);
         cd* zt = w.get<cd>(n * nrhs);
-        SweepWs sw = make_sweep_ws(w, P, (int)nrhs, s);
+        SweepWs sw = make_sweep_ws(w, P, (int)nrhs, s, ctx);
         hs::launch_permute(static_cast<const cd*>(v), vt, P->H->d_perm, n, nrhs, true, s);
         apply_tree(ctx, P, vt, zt, (int)nrhs, sw, s, kAllCols);
         hs::launch_permute(zt, static_cast<cd*>(z), P->H->d_perm, n, nrhs, false, s);
         hip_check(hipGetLastError(), "apply launches");
-        hip_check(hipStreamSynchronize(s), "stream sync");
+        check_sweep_flag(sw, s);
         return HS_OK;
     } catch (const Error& e) {
         return set_error(e);
@@ -1918,8 +2015,21 @@ struct GmresWs {
 // no true-residual pass (inner solves). Otherwise cycles run until every
 // column is done; inside a cycle only the columns still stepping are
 // computed, at its end those that stepped.
+// Column states to the host at a poll, with the sweeps' error flag (bounded
+// waits) read in the same synchronisation.
+std::vector<hs::ColState> poll_states(const GmresWs& G, const int* sweep_err, hipStream_t s) {
+    std::vector<hs::ColState> h(G.ns);
+    int err = 0;
+    hip_check(hipMemcpyAsync(h.data(), G.st, sizeof(hs::ColState) * G.ns, hipMemcpyDeviceToHost, s), "D2H");
+    if (sweep_err) hip_check(hipMemcpyAsync(&err, sweep_err, sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
+    hip_check(hipStreamSynchronize(s), "stream sync");
+    if (err != 0)
+        fail(HS_ETIMEOUT, "a device-side wait of the preconditioner sweeps exceeded the context's wait limit");
+    return h;
+}
+
 void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& matvec, const ApplyFn& precond,
-               bool flexible, bool single, int poll) {
+               bool flexible, bool single, int poll, const int* sweep_err) {
     const int64_t n = G.n, vs = G.vstride;
     const int ns = G.ns, m = G.m;
     const hs::ColMask active{G.st, 1, 0}, stepped{G.st, 2, 0};
@@ -1941,7 +2051,7 @@ void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& mat
             hs::launch_scale_next(G.wv, G.V + (j + 1) * vs, n, n, ns, G.st, G.inv_hn, s);
             if ((j + 1) % poll == 0 && j + 1 < m) {
                 hip_check(hipGetLastError(), "inner launches");
-                std::vector<hs::ColState> cur = download(G.st, ns, s);
+                std::vector<hs::ColState> cur = poll_states(G, sweep_err, s);
                 bool any = false;
                 for (auto& c : cur) any |= c.active != 0;
                 if (!any) break;
@@ -1961,7 +2071,7 @@ void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& mat
         hs::launch_residual(b, G.tmp, G.r, n, ns, G.npart, G.nchunk, s);
         hs::launch_cycle_end(G.npart, G.nchunk, G.st, ns, s);
         hip_check(hipGetLastError(), "cycle launches");
-        std::vector<hs::ColState> cur = download(G.st, ns, s);
+        std::vector<hs::ColState> cur = poll_states(G, sweep_err, s);
         bool all_done = true;
         for (auto& c : cur) all_done &= c.done != 0;
         if (all_done) break;
@@ -2003,7 +2113,7 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         GmresWs G;
         G.alloc(w, n, ns, m, mixed);
         SweepWs sw;
-        if (P) sw = make_sweep_ws(w, P, ns, s);
+        if (P) sw = make_sweep_ws(w, P, ns, s, ctx);
         std::vector<hs::ColState> hst(ns);
         for (auto& c : hst) {
             std::memset(&c, 0, sizeof(c));
@@ -2022,7 +2132,7 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
             else hip_check(hipMemcpyAsync(out, in, sizeof(cd) * n * ns, hipMemcpyDeviceToDevice, s), "D2D");
         };
         if (!mixed) {
-            gmres_run(G, s, bt, xt, matvec, precond, false, false, 4);
+            gmres_run(G, s, bt, xt, matvec, precond, false, false, 4, P ? sw.w.err : nullptr);
         } else {
             // inner solves: complex64 operator and preconditioner copies, FP64 vectors
             GmresWs Gi;
@@ -2046,19 +2156,21 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
                     return;
                 }
                 sw.epoch += 1;
+                sweeps_begin(ctx->device, s);
                 hs::launch_sweep(true, mk, P->sp32, P->items, in, out, ns, sw.w, sw.epoch, s);
                 hs::launch_sweep(false, mk, P->sp32, P->items, in, out, ns, sw.w, sw.epoch, s);
+                sweeps_end(ctx->device, s);
             };
             // one flexible preconditioning step: z = approximate Z^-1 v for the
             // columns still stepping in the outer cycle
             ApplyFn inner = [&](const cd* in, cd* out, const hs::ColMask& mk) {
                 hip_check(hipMemsetAsync(out, 0, sizeof(cd) * n * ns, s), "memset");
                 hs::launch_col_init(Gi.st, mk.st, ns, tol_in, m_in, s);
-                gmres_run(Gi, s, in, out, matvec32, precond32, false, true, 4);
+                gmres_run(Gi, s, in, out, matvec32, precond32, false, true, 4, P ? sw.w.err : nullptr);
             };
-            gmres_run(G, s, bt, xt, matvec, inner, true, false, 4);
+            gmres_run(G, s, bt, xt, matvec, inner, true, false, 4, P ? sw.w.err : nullptr);
         }
-        hst = download(G.st, ns, s);
+        hst = poll_states(G, P ? sw.w.err : nullptr, s);
         hs::launch_permute(xt, static_cast<cd*>(x), H->d_perm, n, ns, false, s);
         hip_check(hipGetLastError(), "permute launch");
         hip_check(hipStreamSynchronize(s), "stream sync");

@@ -324,6 +324,12 @@ struct SweepWork {
     // epoch in all four words has the value without a separate ready count
     unsigned long long* llf;
     unsigned long long* llb;
+    // Bounded waits: a wait that has polled for wait_ticks of the constant-rate
+    // device clock gives up and sets *err; every later wait of the workspace
+    // sees *err and gives up at its next check, so each workgroup runs to the
+    // end of the launch (on scratch data) and the host reports the timeout.
+    int* err;
+    long long wait_ticks;
 };
 constexpr int kMaxChunk = 384;   // points per chunk (bounds the row widths)
 constexpr int kFoldCols = 3072;   // columns of the folded neighbour range per chunk

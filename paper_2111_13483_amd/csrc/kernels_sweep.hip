@@ -37,7 +37,9 @@
 // by the row workers of chunk c, skips the counters: each row result is also
 // written as epoch-tagged words that the readers poll directly. The row workers stay resident for the whole launch, so the
 // device must hold more workgroups than that at once (checked at setup), and
-// sweeps of different streams must not run at the same time.
+// sweeps of different streams must not run at the same time (the host orders
+// them library-wide). Every wait is bounded: past the context's wait limit it
+// gives up, the launch runs to its end and the host reports the timeout.
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -73,6 +75,22 @@ __device__ __forceinline__ void st_sc(cd* p, cd v) {
 }
 __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Every wait is bounded. Once per kBailPolls polls (every poll when the limit
+// is 0) it checks the workspace's error flag and how long it has polled
+// (constant-rate device clock); past wk.wait_ticks, or once another wait has
+// given up, it sets the flag and returns as if satisfied. The launch then runs to its end on scratch data,
+// every later wait of the workspace giving up at its first check, and the
+// host turns the flag into an error. The check sits off the poll's fast path,
+// so a wait that ends normally costs no extra round trip.
+constexpr int kBailPolls = 64;
+
+__device__ __forceinline__ bool must_give_up(const SweepWork& wk, long long t0) {
+    return relaxed_load(wk.err) != 0 || wall_clock64() - t0 > wk.wait_ticks;
+}
+__device__ __forceinline__ void give_up(const SweepWork& wk) {
+    __hip_atomic_store(wk.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The chain's critical exchange (chunk c-1's results read by the row workers
 // of chunk c) goes through flagged copies: 4 words per complex128 value,
 // word w = (epoch << 32) | 32-bit part w of the value. A 64-bit word is
@@ -105,10 +123,11 @@ __device__ __forceinline__ void publish_ll(unsigned long long* ll, int64_t i, in
 // range (a wave's loads cover 512 consecutive bytes) and reloads only the
 // words still missing, until no thread of the workgroup misses one. Every
 // word is written once per launch by the row worker that owns the position,
-// for the same live columns, so the loop ends.
+// for the same live columns, so the loop ends (or gives up, as the counter
+// waits below do).
 template <int S>
 __device__ __forceinline__ void stage_ll(cd* x, int ld, const unsigned long long* ll, int64_t g0, int len, int64_t n,
-                                         int c0, int cs, unsigned tag) {
+                                         int c0, int cs, unsigned tag, const SweepWork& wk) {
     constexpr int PER = (4 * kMaxChunk * S + NT - 1) / NT;
     const int wl = 4 * len, tot = wl * cs;
     unsigned* xw = reinterpret_cast<unsigned*>(x);
@@ -119,7 +138,8 @@ __device__ __forceinline__ void stage_ll(cd* x, int ld, const unsigned long long
 #pragma unroll
     for (int u = 0; u < PER; ++u)
         if ((int)threadIdx.x + u * NT < tot) pend |= 1u << u;
-    for (;;) {
+    const long long t0 = wall_clock64();
+    for (int round = 1;; ++round) {
         // groups of G words in flight (registers: the row workers hold their
         // matrix rows beside this)
         constexpr int G = 6;
@@ -146,6 +166,14 @@ __device__ __forceinline__ void stage_ll(cd* x, int ld, const unsigned long long
                 }
         }
         if (!__syncthreads_or(pend != 0)) break;
+        // bounded like the counter waits (one barrier more every kBailPolls rounds)
+        if (round % kBailPolls == 0 || wk.wait_ticks == 0) {
+            const int bail = threadIdx.x == 0 && must_give_up(wk, t0);
+            if (__syncthreads_or(bail)) {
+                if (threadIdx.x == 0) give_up(wk);
+                break;
+            }
+        }
         __builtin_amdgcn_s_sleep(1);
     }
     __syncthreads();
@@ -215,16 +243,28 @@ __device__ __forceinline__ int take_ticket(unsigned long long* ctr, unsigned lon
 }
 
 // Wave-level wait (no fence): counter *cnt == need.
-__device__ __forceinline__ void wait_count(const int* cnt, int need) {
-    while (relaxed_load(cnt) != need) __builtin_amdgcn_s_sleep(1);
+__device__ __forceinline__ void wait_count(const int* cnt, int need, const SweepWork& wk) {
+    const long long t0 = wall_clock64();
+    for (int it = 1; relaxed_load(cnt) != need; ++it) {
+        if ((it % kBailPolls == 0 || wk.wait_ticks == 0) && must_give_up(wk, t0)) {
+            give_up(wk);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
 }
 
 // Two counters polled together (b may be null): *a == na and *b == nb.
-__device__ __forceinline__ void wait_pair(const int* a, int na, const int* b, int nb) {
-    for (;;) {
+__device__ __forceinline__ void wait_pair(const int* a, int na, const int* b, int nb, const SweepWork& wk) {
+    const long long t0 = wall_clock64();
+    for (int it = 1;; ++it) {
         const int va = relaxed_load(a);
         const int vb = b ? relaxed_load(b) : nb;
         if (va == na && vb == nb) return;
+        if ((it % kBailPolls == 0 || wk.wait_ticks == 0) && must_give_up(wk, t0)) {
+            give_up(wk);
+            return;
+        }
         __builtin_amdgcn_s_sleep(1);
     }
 }
@@ -500,7 +540,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             const int cn = c + kRowSets;
             const SweepChunk dn = it.fchunk[cn < p.nch ? cn : c];
             if (wid == 0)
-                wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c >= 2 ? cntB + kCntPad * (c - 2) : nullptr, epoch * d.need2);
+                wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c >= 2 ? cntB + kCntPad * (c - 2) : nullptr, epoch * d.need2, wk);
             __syncthreads();
             compiler_fence();
             bool first = true;   // the first computed pass waits for the newest chunk
@@ -518,12 +558,12 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
                                     wk.ybuf + (int64_t)c0 * n, mp, d.e_n, n, cs);
                     if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
                     // chunk c-1 (range columns [0, l_n), not read above) as it lands
-                    stage_ll<S>(xs2, d.w2, wk.llf, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch);
+                    stage_ll<S>(xs2, d.w2, wk.llf, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch, wk);
                     if (live) row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
                 } else {
                     stage_direct<S>(xs1, d.nc, wk.rbuf + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n, d.w2,
                                     wk.ybuf + (int64_t)c0 * n, mp, d.e_n, n, cs);
-                    stage_ll<S>(xs2, d.w2, wk.llf, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch);
+                    stage_ll<S>(xs2, d.w2, wk.llf, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch, wk);
                     if (live) {
                         row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
                         row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
@@ -567,7 +607,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             const int bj = p.bsize[j];
             const int64_t sj = p.bstart[j], pj = p.pos[j];
             const int nin = (int)(p.fgptr[j + 1] - p.fgptr[j]);
-            if (wid == 0 && nin > 0) wait_count(cntT + j, epoch * nin);
+            if (wid == 0 && nin > 0) wait_count(cntT + j, epoch * nin, wk);
             __syncthreads();
             compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
@@ -588,7 +628,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             const int e0 = p.fgrp[g];
             const PushEnt& f0 = p.fpush[e0];
             const int csrc = p.chunk_of[f0.src];
-            if (wid == 0) wait_count(cntB + kCntPad * csrc, epoch * p.csize[csrc]);
+            if (wid == 0) wait_count(cntB + kCntPad * csrc, epoch * p.csize[csrc], wk);
             __syncthreads();
             compiler_fence();
             const int ng = p.fgrp_n[g];
@@ -654,7 +694,7 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             const int cn = c - kRowSets;
             const SweepChunk dn = it.bchunk[cn >= 0 ? cn : c];
             if (wid == 0)
-                wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c + 2 < p.nch ? cntB + kCntPad * (c + 2) : nullptr, epoch * d.need2);
+                wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c + 2 < p.nch ? cntB + kCntPad * (c + 2) : nullptr, epoch * d.need2, wk);
             __syncthreads();
             compiler_fence();
             bool first = true;   // the first computed pass waits for the newest chunk
@@ -672,12 +712,12 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
                                     wk.zbuf + (int64_t)c0 * n, mp, d.e_n, n, cs);
                     if (live) row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
                     // chunk c+1 (range columns [0, l_n), not read above) as it lands
-                    stage_ll<S>(xs2, d.w2, wk.llb, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch);
+                    stage_ll<S>(xs2, d.w2, wk.llb, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch, wk);
                     if (live) row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
                 } else {
                     stage_direct<S>(xs1, d.nc, wk.rbuf2 + d.pc + (int64_t)c0 * n, d.nc, xs2 + d.l_n, d.w2,
                                     wk.zbuf + (int64_t)c0 * n, mp, d.e_n, n, cs);
-                    stage_ll<S>(xs2, d.w2, wk.llb, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch);
+                    stage_ll<S>(xs2, d.w2, wk.llb, d.l_g, d.l_n, n, c0, cs, (unsigned)epoch, wk);
                     if (live) {
                         row_partial<S>(R1, w1, xs1, rt.o1, d.nc, R2, d.l_n, d.w2, xs2, d.w2, cs, acc);
                         row_head<S>(R2, d.l_n, xs2, d.w2, cs, acc);
@@ -725,7 +765,7 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             const int64_t pk = p.pos[k];
             const T* Di = p.dinv + p.dinv_off[k];
             const int nin = (int)(p.bgptr[k + 1] - p.bgptr[k]);
-            if (wid == 0 && nin > 0) wait_count(cntT + k, epoch * nin);
+            if (wid == 0 && nin > 0) wait_count(cntT + k, epoch * nin, wk);
             __syncthreads();
             compiler_fence();
             for (int c0 = 0; c0 < nrhs; c0 += S) {
@@ -774,7 +814,7 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             const int e0 = p.bgrp[g];
             const PushEnt& b0 = p.bpush[e0];
             const int csrc = p.chunk_of[b0.src];
-            if (wid == 0) wait_count(cntB + kCntPad * csrc, epoch * p.csize[csrc]);
+            if (wid == 0) wait_count(cntB + kCntPad * csrc, epoch * p.csize[csrc], wk);
             __syncthreads();
             compiler_fence();
             const int ng = p.bgrp_n[g];
