@@ -227,6 +227,22 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P,
 int32_t hs_matvec(hs_context* ctx, const hs_hmatrix* H, const void* x, void* y, int64_t nrhs);
 int32_t hs_precond_apply(hs_context* ctx, const hs_precond* P, const void* v, void* z, int64_t nrhs);
 
+/* y = Z_H x like hs_matvec, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). The tree-order copies of x and y and the per-block partial
+ * results live in a fixed 64 MiB device array of the library (one per
+ * device, held until the process ends) instead of memory from the context's
+ * allocator: the call allocates nothing and does not synchronise (the result
+ * is ready when the context's stream reaches it). The array needs
+ * 2 N nrhs + (partial-result slots) nrhs complex128 values, each part rounded
+ * up to 256 bytes; *scratch_needed (may be NULL) receives that byte count.
+ * Calls that overlap on one device (other streams or threads) share the
+ * array and race; issue them in order. Every scratch word read is written
+ * in the same call, so nothing needs clearing between calls.
+ * Errors: HS_EINVAL (NULL argument, nrhs < 1, more scratch than 64 MiB). */
+int32_t hs_matvec_noalloc(hs_context* ctx, const hs_hmatrix* H, const void* x, void* y, int64_t nrhs,
+                          int64_t* scratch_needed);
+
 /* ---- kernel timing (measurement) -------------------------------------------
  * Between hs_timing_begin and hs_timing_end every launch of the forward and
  * backward preconditioner sweeps (Eq. 23-24) and of the near and far matvec

@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
         "hs_precond_destroy": (None, [vp]),
         "hs_solve": (i32, [vp, vp, vp, vp, vp, i64, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)]),
         "hs_matvec": (i32, [vp, vp, vp, vp, i64]),
+        "hs_matvec_noalloc": (i32, [vp, vp, vp, vp, i64, ctypes.POINTER(i64)]),
         "hs_precond_apply": (i32, [vp, vp, vp, vp, i64]),
         "hs_hmatrix_export": (i32, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
         "hs_precond_export": (i32, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
@@ -141,7 +142,7 @@ def load(path: str = LIB_PATH):
 EXPORTED = (
     "hs_context_create", "hs_context_set_stream", "hs_context_set_wait_limit", "hs_context_destroy", "hs_plan_create", "hs_plan_query",
     "hs_plan_destroy", "hs_plan_export", "hs_h_build", "hs_query_hmatrix", "hs_hmatrix_destroy", "hs_precond_setup",
-    "hs_precond_setup_many", "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_precond_apply", "hs_hmatrix_export",
+    "hs_precond_setup_many", "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_matvec_noalloc", "hs_precond_apply", "hs_hmatrix_export",
     "hs_precond_export", "hs_timing_begin", "hs_timing_begin_every", "hs_timing_end", "hs_server_clock",
     "hs_server_create",
     "hs_server_admit", "hs_server_submit", "hs_server_step", "hs_server_pending", "hs_server_request",

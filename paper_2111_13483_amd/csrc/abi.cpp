@@ -200,6 +200,19 @@ struct SweepOrder {
 };
 SweepOrder g_sweep_order[64];
 
+// Device scratch of the allocation-free matvec (hs_matvec_noalloc): one copy
+// per device, held until the process ends. In host code `scratch` only names
+// the symbol; its device address on each device comes from
+// hipGetSymbolAddress (taken once per device when the first context on that
+// device is created) and only that address is passed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+struct ScratchAddr {
+    std::mutex mu;
+    void* ptr[64] = {};
+};
+ScratchAddr g_scratch;
+
 struct hs_context {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -677,6 +690,15 @@ int32_t hs_context_create(hs_context** out, int32_t device, void* hip_stream, hs
         hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device), "hipDeviceGetAttribute");
         if (khz <= 0) fail(HS_ENODEVICE, "the device reports no constant-rate clock");
         if (device >= 64) fail(HS_ENODEVICE, "device index beyond the library's table (64)");
+        {
+            std::lock_guard<std::mutex> lk(g_scratch.mu);
+            if (!g_scratch.ptr[device]) {
+                hip_check(hipSetDevice(device), "hipSetDevice");
+                void* p = nullptr;
+                hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+                g_scratch.ptr[device] = p;
+            }
+        }
         auto* c = new hs_context;
         c->clock_khz = khz;
         c->device = device;
@@ -1939,6 +1961,48 @@ int32_t hs_matvec(hs_context* ctx, const hs_hmatrix* H, const void* x, void* y, 
         hs::launch_permute(yt, static_cast<cd*>(y), H->d_perm, n, nrhs, false, s);
         hip_check(hipGetLastError(), "matvec launches");
         hip_check(hipStreamSynchronize(s), "stream sync");
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+int32_t hs_matvec_noalloc(hs_context* ctx, const hs_hmatrix* H, const void* x, void* y, int64_t nrhs,
+                          int64_t* scratch_needed) {
+    try {
+        if (!ctx || !H || !x || !y) fail(HS_EINVAL, "NULL argument");
+        if (nrhs < 1) fail(HS_EINVAL, "nrhs must be >= 1");
+        auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+        const int64_t n = H->n;
+        const size_t vbytes = up(sizeof(cd) * (size_t)n * (size_t)nrhs);
+        const size_t sbytes = up(sizeof(cd) * (size_t)H->slot_total * (size_t)nrhs);
+        const size_t need = 2 * vbytes + sbytes;
+        if (scratch_needed) *scratch_needed = (int64_t)need;
+        if (need > kNoAllocScratchBytes)
+            fail(HS_EINVAL, "hs_matvec_noalloc needs " + std::to_string(need) + " bytes of scratch, more than its " +
+                                std::to_string(kNoAllocScratchBytes) + "-byte device array");
+        unsigned char* base = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_scratch.mu);
+            base = static_cast<unsigned char*>(g_scratch.ptr[ctx->device]);
+        }
+        if (!base) fail(HS_EHIP, "the scratch address of this device is unknown");
+        set_device(ctx);
+        hipStream_t s = ctx->stream;
+        cd* xt = reinterpret_cast<cd*>(base);
+        cd* yt = reinterpret_cast<cd*>(base + vbytes);
+        cd* slots = reinterpret_cast<cd*>(base + 2 * vbytes);
+        // near and far kernels one after the other on the context's stream
+        // (no auxiliary stream or events), each writing its own slots; the
+        // gather adds them; every scratch word read was written in this call
+        hs::launch_permute(static_cast<const cd*>(x), xt, H->d_perm, n, nrhs, true, s);
+        hs::launch_near_mv(kAllCols, H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near, xt, n,
+                           (int)nrhs, slots, s);
+        hs::launch_far_mv(kAllCols, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr, H->d_mv_slot, H->n_far_wg,
+                          (int64_t)H->far_geom.size(), xt, n, (int)nrhs, slots, s);
+        hs::launch_gather(kAllCols, H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, n, (int)nrhs, yt, s);
+        hs::launch_permute(yt, static_cast<cd*>(y), H->d_perm, n, nrhs, false, s);
+        hip_check(hipGetLastError(), "matvec launches");
         return HS_OK;
     } catch (const Error& e) {
         return set_error(e);
