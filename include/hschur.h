@@ -104,6 +104,7 @@ typedef struct {
     int32_t fixed_iters;  /* > 0: run exactly this many inner steps, ignoring tol (parity runs) */
     int32_t inner_steps;  /* HS_SOLVE_FGMRES_MIXED: steps of each inner solve; 0 = 20 */
     double  inner_tol;    /* HS_SOLVE_FGMRES_MIXED: relative tolerance ending an inner solve early; 0 = 1e-2 */
+    int32_t use_x0;       /* 1: x holds the initial guess on entry (HS_SOLVE_GMRES only); 0: start from x = 0 */
 } hs_solve_opts;
 
 typedef struct {
@@ -123,6 +124,11 @@ typedef struct {
     int64_t bytes_device;   /* all device memory the handle holds */
     double  flops_setup;    /* algorithmic flops of the Schur elimination (LU + alpha + updates) */
     double  flops_fill;     /* ACA/re-compression flops on fill-in blocks, r^2 (m + n) model */
+    int64_t bytes_estimate; /* plans only: device bytes an H-matrix plus preconditioner of this plan is
+                               expected to hold, computed before any allocation (exact near-field and
+                               block-diagonal sizes; far factors at rank min(m, n, 32); three times the
+                               dense scaling-coefficient bound for the elimination's working blocks,
+                               the stored coefficients and the apply's plan) */
 } hs_info;
 
 /* ---- context ------------------------------------------------------------ */
@@ -221,6 +227,31 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P,
                  const void* b, void* x, int64_t nrhs, const hs_solve_opts* opts,
                  hs_solve_stats* stats);
 
+/* ---- solves of several geometries at once --------------------------------------
+ * Each item is one geometry's system with its own right-hand sides: H, P
+ * (NULL = unpreconditioned), b and x device N x nrhs complex128 in the
+ * caller's order (x is the initial guess on entry when opts->use_x0). The
+ * items' GMRES(m) solves run together: their restart cycles proceed in
+ * lockstep, item i's launches on one of up to four streams (item 0 on the
+ * context's stream, the others on library streams that first wait for the
+ * context's stream), so the work of different geometries overlaps on the
+ * device, and one host poll serves all items. Every column is its own Krylov
+ * space, so its iterates do not depend on the other columns or items (the
+ * same arithmetic as hs_solve up to the rounding order of multi-column
+ * kernels). stats: host array of sum(nrhs) entries, item by item. Returns
+ * HS_NOT_CONVERGED if some column missed tol. Errors: HS_EINVAL (NULL, bad
+ * sizes, a P of another H, a method other than HS_SOLVE_GMRES), HS_ENOMEM,
+ * HS_ETIMEOUT, HS_ENUMERIC. */
+typedef struct {
+    const hs_hmatrix* H;
+    const hs_precond* P;
+    const void* b;
+    void* x;
+    int64_t nrhs;
+} hs_solve_item;
+int32_t hs_solve_many(hs_context* ctx, int64_t nitems, const hs_solve_item* items, const hs_solve_opts* opts,
+                      hs_solve_stats* stats);
+
 /* ---- operator applications -------------------------------------------------
  * y = Z_H x (Eq. 11) and z = P^-1 v = alpha D^-1 alpha^T v (Eq. 23-24);
  * device, N x nrhs complex128, caller order. */
@@ -301,27 +332,39 @@ int32_t hs_timing_end(hs_context* ctx, hs_kernel_times* out);
 int32_t hs_hmatrix_export(const hs_hmatrix* H, int32_t what, void* dst, int64_t cap, int64_t* needed);
 int32_t hs_precond_export(const hs_precond* P, int32_t what, void* dst, int64_t cap, int64_t* needed);
 
-/* ---- serving -----------------------------------------------------------------
- * Resident H-matrices and preconditioners on one context, admitted by their
- * device footprint (hs_query_*.bytes_device; an H-matrix shared by several
- * preconditioners counts once); requests of right-hand-side columns are
- * batched per geometry into one multi-column hs_solve (Sec. 5 solves each
- * right-hand side on its own; batching shares every matrix read, the columns
- * stay independent Krylov spaces).
- *  hs_server_create: budget in bytes, max_batch_cols >= 1, solve options used
- *    for every batch. The context must outlive the server.
- *  hs_server_admit: H (and P, or NULL for unpreconditioned) become geometry
- *    number *geometry; HS_ENOMEM when the footprint exceeds what is left of
- *    the budget. The handles must outlive the server.
+/* ---- serving ------------------------------------------------------------------
+ * Resident geometries on one context (each H-matrix and preconditioner kept in
+ * device memory), admitted by device footprint, and continuous batching of
+ * right-hand-side columns (Sec. 5 solves each right-hand side on its own; the
+ * server shares every matrix read between the columns it runs together).
+ * Every geometry has slots_per_geometry column slots of a GMRES(restart)
+ * solve. hs_server_step runs one restart cycle of every geometry with live
+ * columns, all geometries together (as hs_solve_many). At the cycle boundary
+ * finished columns leave their slots (x copied to the request's buffer) and
+ * pending requests take free slots, oldest first per geometry, so requests
+ * that arrive while others are on the GPU join the running solves without
+ * waiting for them to end. A column's iterates do not depend on the others.
+ *  hs_server_create: budget in bytes (handles plus the solve workspaces of
+ *    their slots), slots_per_geometry in [1, 1024], solve options for every
+ *    column (HS_SOLVE_GMRES, use_x0 = 0). The context must outlive the server.
+ *  hs_server_add_geometry: host points, build and setup options (popts NULL
+ *    = unpreconditioned). The server plans on the host first and refuses with
+ *    HS_ENOMEM, before any device allocation, when the plan's footprint
+ *    estimate (*estimate, may be NULL) exceeds what is left of the budget;
+ *    otherwise it builds the H-matrix and preconditioner (owned by the
+ *    server) and charges their actual bytes plus the slots' workspace,
+ *    freeing them and refusing with HS_ENOMEM if those exceed the budget.
+ *  hs_server_admit: the same for handles the caller built (and keeps alive
+ *    until the server is destroyed); an H-matrix shared by several
+ *    preconditioners counts once.
+ *  hs_server_geometry: the handles of a geometry and the bytes it was charged.
  *  hs_server_submit: b and x device, N x ncols complex128 in the caller's
- *    order, owned by the caller until the request is served; t_arrival on
- *    the hs_server_clock() time base (seconds). Returns a request number.
- *  hs_server_step: serves one batch: the geometry of the oldest pending
- *    request (earliest arrival, then submission), and its pending requests
- *    in arrival order while the batch holds at most max_batch_cols columns
- *    (a larger first request runs alone). Synchronous; *columns_served = 0
- *    when nothing is pending. A column that misses tol is not an error: its
- *    request's stats say so.
+ *    order (ncols <= slots_per_geometry), owned by the caller until the
+ *    request is done; t_arrival on the hs_server_clock() time base (seconds).
+ *  hs_server_step: one cycle as above; synchronous; *columns_served = columns
+ *    finished in this step (0 when nothing runs). A column that misses tol
+ *    within max_iters is not an error: its request's stats say so.
+ *  hs_server_pending: requests not yet done and their unfinished columns.
  *  hs_server_request: state of a request (done, iterations, residual,
  *    arrival and completion times). */
 typedef struct hs_server hs_server;
@@ -332,14 +375,20 @@ typedef struct {
     int32_t converged;    /* 1 if every column met tol */
     double  relres;       /* largest true relative residual over the columns */
     double  t_arrival;    /* as submitted */
-    double  t_done;       /* completion of the batch that served it */
+    double  t_done;       /* host clock when its last column had finished */
     int32_t done;
     int32_t pad;
+    double  t_start;      /* host clock when its columns took their slots (0 while queued) */
 } hs_request_stats;
 double  hs_server_clock(void);
-int32_t hs_server_create(hs_context* ctx, int64_t device_budget_bytes, int32_t max_batch_cols,
+int32_t hs_server_create(hs_context* ctx, int64_t device_budget_bytes, int32_t slots_per_geometry,
                          const hs_solve_opts* opts, hs_server** out);
+int32_t hs_server_add_geometry(hs_server* s, const double* points_host, int64_t n, double k, double self_h,
+                               const hs_build_opts* bopts, const hs_precond_opts* popts, int64_t* estimate,
+                               int32_t* geometry);
 int32_t hs_server_admit(hs_server* s, const hs_hmatrix* H, const hs_precond* P, int32_t* geometry);
+int32_t hs_server_geometry(const hs_server* s, int32_t geometry, const hs_hmatrix** H, const hs_precond** P,
+                           int64_t* bytes);
 int32_t hs_server_submit(hs_server* s, int32_t geometry, const void* b, void* x, int32_t ncols, double t_arrival,
                          int64_t* request);
 int32_t hs_server_step(hs_server* s, int32_t* columns_served);

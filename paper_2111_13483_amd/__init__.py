@@ -48,7 +48,7 @@ class PrecondOpts(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("restart", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iters", ctypes.c_int32), ("fixed_iters", ctypes.c_int32), ("inner_steps", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double)]
+                ("inner_tol", ctypes.c_double), ("use_x0", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -59,7 +59,7 @@ class Info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("n", "nb", "nbox", "n_near", "n_far", "n_pattern", "n_fill", "n_lowrank", "max_dk", "max_rank",
                  "bytes_near", "bytes_far", "bytes_alpha", "bytes_d", "bytes_device")] + \
-               [("flops_setup", ctypes.c_double), ("flops_fill", ctypes.c_double)]
+               [("flops_setup", ctypes.c_double), ("flops_fill", ctypes.c_double), ("bytes_estimate", ctypes.c_int64)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -68,10 +68,16 @@ class Info(ctypes.Structure):
 class RequestStats(ctypes.Structure):
     _fields_ = [("geometry", ctypes.c_int32), ("ncols", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("relres", ctypes.c_double), ("t_arrival", ctypes.c_double),
-                ("t_done", ctypes.c_double), ("done", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("t_done", ctypes.c_double), ("done", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("t_start", ctypes.c_double)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "pad"}
+
+
+class SolveItem(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_void_p), ("P", ctypes.c_void_p), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("nrhs", ctypes.c_int64)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -120,6 +126,11 @@ def load(path: str = LIB_PATH):
         "hs_server_clock": (dbl, []),
         "hs_server_create": (i32, [vp, i64, i32, ctypes.POINTER(SolveOpts), pvp]),
         "hs_server_admit": (i32, [vp, vp, vp, ctypes.POINTER(i32)]),
+        "hs_server_add_geometry": (i32, [vp, vp, i64, dbl, dbl, ctypes.POINTER(BuildOpts),
+                                         ctypes.POINTER(PrecondOpts), ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+        "hs_server_geometry": (i32, [vp, i32, pvp, pvp, ctypes.POINTER(i64)]),
+        "hs_solve_many": (i32, [vp, i64, ctypes.POINTER(SolveItem), ctypes.POINTER(SolveOpts),
+                                ctypes.POINTER(SolveStats)]),
         "hs_server_submit": (i32, [vp, i32, vp, vp, i32, dbl, ctypes.POINTER(i64)]),
         "hs_server_step": (i32, [vp, ctypes.POINTER(i32)]),
         "hs_server_pending": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
@@ -145,7 +156,7 @@ EXPORTED = (
     "hs_precond_setup_many", "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_matvec_noalloc", "hs_precond_apply", "hs_hmatrix_export",
     "hs_precond_export", "hs_timing_begin", "hs_timing_begin_every", "hs_timing_end", "hs_server_clock",
     "hs_server_create",
-    "hs_server_admit", "hs_server_submit", "hs_server_step", "hs_server_pending", "hs_server_request",
+    "hs_server_admit", "hs_server_add_geometry", "hs_server_geometry", "hs_solve_many", "hs_server_submit", "hs_server_step", "hs_server_pending", "hs_server_request",
     "hs_server_destroy", "hs_status_string", "hs_last_error",
 )
 
@@ -370,14 +381,22 @@ class Stats:
 
 
 def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol: float = 1e-6,
-          max_iters: int = 0, fixed_iters: int = 0, mixed: bool = False, inner_steps: int = 0, inner_tol: float = 0.0):
+          max_iters: int = 0, fixed_iters: int = 0, mixed: bool = False, inner_steps: int = 0, inner_tol: float = 0.0,
+          x0=None):
     """Solve Z x = b: right-preconditioned GMRES, or with mixed=True FP64
     flexible GMRES whose preconditioning steps are inner GMRES solves on the
-    complex64 copies; returns (x, [Stats per column])."""
+    complex64 copies; x0 (GMRES only) is the initial guess. Returns
+    (x, [Stats per column])."""
     torch = _torch()
     bc, s = _dev_c128(b, H.n)
-    x = torch.empty_like(bc)
-    opts = SolveOpts(1 if mixed else 0, restart, tol, max_iters, fixed_iters, inner_steps, inner_tol)
+    if x0 is None:
+        x = torch.empty_like(bc)
+    else:
+        x, s0 = _dev_c128(x0, H.n)
+        if s0 != s:
+            raise HschurError(HS_EINVAL, "x0 and b differ in columns")
+    opts = SolveOpts(1 if mixed else 0, restart, tol, max_iters, fixed_iters, inner_steps, inner_tol,
+                     0 if x0 is None else 1)
     st = (SolveStats * s)()
     _check(_lib.hs_solve(ctx._h, H._h, P._h if P is not None else None, ctypes.c_void_p(bc.data_ptr()),
                          ctypes.c_void_p(x.data_ptr()), s, ctypes.byref(opts), st), allow_not_converged=True)
@@ -386,16 +405,47 @@ def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol
     return (x.reshape(-1) if b.dim() == 1 else x), stats
 
 
-class Server:
-    """Resident geometries admitted by device footprint; request columns are
-    batched per geometry into multi-column solves (hs_server_*)."""
+def solve_many(ctx: Context, items, restart: int = 30, tol: float = 1e-6, max_iters: int = 0, fixed_iters: int = 0,
+               use_x0: bool = False):
+    """hs_solve_many: items of (H, P or None, b[, x0]) solved together;
+    returns [(x, [Stats per column]) per item]."""
+    torch = _torch()
+    arr = (SolveItem * len(items))()
+    keep, ncols = [], []
+    for i, it in enumerate(items):
+        H, P, b = it[0], it[1], it[2]
+        bc, s = _dev_c128(b, H.n)
+        if use_x0:
+            x, _ = _dev_c128(it[3], H.n)
+        else:
+            x = torch.empty_like(bc)
+        keep.append((bc, x, b.dim() == 1))
+        ncols.append(s)
+        arr[i] = SolveItem(H._h.value, P._h.value if P is not None else None, bc.data_ptr(), x.data_ptr(), s)
+    opts = SolveOpts(0, restart, tol, max_iters, fixed_iters, 0, 0.0, 1 if use_x0 else 0)
+    st = (SolveStats * sum(ncols))()
+    _check(_lib.hs_solve_many(ctx._h, len(items), arr, ctypes.byref(opts), st), allow_not_converged=True)
+    out, k = [], 0
+    for (bc, x, vec), s in zip(keep, ncols):
+        xx = x.t()
+        out.append(((xx.reshape(-1) if vec else xx), [Stats(st[k + c].iters, bool(st[k + c].converged),
+                                                             st[k + c].relres) for c in range(s)]))
+        k += s
+    return out
 
-    def __init__(self, ctx: Context, budget_bytes: int, max_batch_cols: int = 32, restart: int = 30,
+
+class Server:
+    """Resident geometries admitted by device footprint and continuous
+    batching of right-hand-side columns (hs_server_*): each step runs one
+    restart cycle of every geometry with live columns; finished columns leave
+    their slots and pending requests join at the cycle boundary."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, slots: int = 32, restart: int = 30,
                  tol: float = 1e-6, max_iters: int = 0):
         self.ctx = ctx
-        self._opts = SolveOpts(0, restart, tol, max_iters, 0, 0, 0.0)
+        self._opts = SolveOpts(0, restart, tol, max_iters, 0, 0, 0.0, 0)
         h = ctypes.c_void_p()
-        _check(_lib.hs_server_create(ctx._h, int(budget_bytes), int(max_batch_cols), ctypes.byref(self._opts),
+        _check(_lib.hs_server_create(ctx._h, int(budget_bytes), int(slots), ctypes.byref(self._opts),
                                      ctypes.byref(h)))
         self._h = h
         self._keep = {}     # request -> (b, x) device buffers, alive until served
@@ -408,13 +458,35 @@ class Server:
     def admit(self, H: HMatrix, P: Precond | None) -> int:
         g = ctypes.c_int32()
         _check(_lib.hs_server_admit(self._h, H._h, P._h if P is not None else None, ctypes.byref(g)))
-        self._geo.append((H, P))
+        self._geo.append(H.n)
         return g.value
+
+    def add_geometry(self, points, k: float, self_h: float, leaf_max: int, aca_tol: float = 1e-4,
+                     ordering: str | None = "rcm", fill_tol: float = 1e-2):
+        """Plan on the host, refuse before allocating if the estimate does not
+        fit, else build and set up on the device. Returns (geometry, estimate)."""
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        bo = BuildOpts(leaf_max, aca_tol, 0, 0)
+        po = PrecondOpts(ORDER[ordering], float(fill_tol), 0, 0, 0) if ordering is not None else None
+        est, g = ctypes.c_int64(0), ctypes.c_int32()
+        st = _lib.hs_server_add_geometry(self._h, pts.ctypes.data_as(ctypes.c_void_p), pts.shape[0], float(k),
+                                         float(self_h), ctypes.byref(bo), ctypes.byref(po) if po is not None else None,
+                                         ctypes.byref(est), ctypes.byref(g))
+        self.last_estimate = est.value
+        _check(st)
+        self._geo.append(pts.shape[0])
+        return g.value, est.value
+
+    def geometry(self, g: int):
+        """(H handle, P handle, bytes charged) of a geometry; the handles are
+        borrowed (owned by the server or the caller)."""
+        H, P, nb = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+        _check(_lib.hs_server_geometry(self._h, int(g), ctypes.byref(H), ctypes.byref(P), ctypes.byref(nb)))
+        return H.value, P.value, nb.value
 
     def submit(self, geometry: int, b, t_arrival: float) -> int:
         torch = _torch()
-        H = self._geo[geometry][0]
-        bc, s = _dev_c128(b, H.n)
+        bc, s = _dev_c128(b, self._geo[geometry])
         x = torch.empty_like(bc)
         r = ctypes.c_int64()
         _check(_lib.hs_server_submit(self._h, geometry, ctypes.c_void_p(bc.data_ptr()), ctypes.c_void_p(x.data_ptr()),

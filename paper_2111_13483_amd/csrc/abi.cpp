@@ -460,6 +460,22 @@ void fill_info_plan(const hs_plan& p, hs_info* info) {
         info->bytes_alpha = (int64_t)ab;
         info->bytes_d = (int64_t)db;
     }
+    // footprint estimate (admission before allocation): near blocks exact,
+    // far factors at rank min(m, n, 32), and with a pattern three times the
+    // dense scaling-coefficient bound plus the block diagonal
+    const hs::Tree& t = p.tree;
+    double nearb = 0, farb = 0;
+    for (int64_t e = 0; e < p.part.n_near(); ++e) {
+        const double bi = (double)t.count[t.leaf_box[p.part.near[2 * e]]];
+        const double bj = (double)t.count[t.leaf_box[p.part.near[2 * e + 1]]];
+        nearb += bi * bj * 16.0;
+    }
+    for (int64_t e = 0; e < p.part.n_far(); ++e) {
+        const double m = (double)t.count[p.part.far[2 * e]], nn = (double)t.count[p.part.far[2 * e + 1]];
+        farb += std::min(std::min(m, nn), 32.0) * (m + nn) * 16.0;
+    }
+    info->bytes_near = (int64_t)nearb;
+    info->bytes_estimate = (int64_t)(nearb + farb + 3.0 * (double)info->bytes_alpha + (double)info->bytes_d);
 }
 
 hs::Symbolic make_symbolic(const hs_plan& p, int ordering) {
@@ -2156,6 +2172,11 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         if (P && P->H != H) fail(HS_EINVAL, "the preconditioner belongs to another H-matrix");
         const bool mixed = opts->method == HS_SOLVE_FGMRES_MIXED;
         if (opts->method != HS_SOLVE_GMRES && !mixed) fail(HS_EINVAL, "unsupported method");
+        if (opts->use_x0) {
+            if (mixed) fail(HS_EINVAL, "use_x0 is supported by HS_SOLVE_GMRES only");
+            hs_solve_item it{H, P, b, x, nrhs};
+            return hs_solve_many(ctx, 1, &it, opts, stats);
+        }
         if (mixed && !H->c64) fail(HS_EINVAL, "the mixed solve needs an H-matrix built with store_c64");
         if (mixed && P && !P->c64) fail(HS_EINVAL, "the mixed solve needs a preconditioner set up with HS_PREC_MIXED");
         const int m = opts->restart;
@@ -2252,34 +2273,406 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
     }
 }
 
-// ---- serving ------------------------------------------------------------------------
+// ---- multi-geometry solves: lanes in lockstep -------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+// The solve state of one geometry inside a multi-geometry solve: ns column
+// slots of a right-preconditioned GMRES(m) on tree-order vectors, on one
+// stream. A slot holds one right-hand side from its start (x = 0, or the
+// caller's x0) until its column is done; in serving, a freed slot takes the
+// next pending column at a cycle boundary. Columns are independent Krylov
+// spaces: a column's arithmetic does not depend on the other slots.
+struct Lane {
+    const hs_hmatrix* H = nullptr;
+    const hs_precond* P = nullptr;
+    hipStream_t s = nullptr;
+    bool aux = false;          // near matvec on the context's auxiliary stream
+    int ns = 0, m = 0;
+    Owned w;
+    cd *bt = nullptr, *xt = nullptr, *slots = nullptr;
+    int* d_cols = nullptr;     // slot list for the column starts
+    GmresWs G;
+    SweepWs sw;
+    std::vector<hs::ColState> st;   // host copy at the last poll
+    bool ran = false;          // took part in the current cycle
+    bool stepping = false;     // some column still stepping in the current cycle
+    int err = 0;
+};
+
+// Device bytes a lane allocates (the same sizes as lane_alloc, each rounded
+// up to the allocator's 256-byte granule).
+int64_t lane_bytes(const hs_hmatrix* H, const hs_precond* P, int ns, int m) {
+    auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    const int64_t n = H->n, nn = n * ns, c = 16;
+    const int64_t nch = hs::gmres_nchunk(n);
+    int64_t b = up(nn * c) * 2 + up(H->slot_total * ns * c) + up(ns * 4);
+    b += up(nn * c) * 3 + up((m + 1) * nn * c) + up((int64_t)(m + 1) * m * ns * c) + up(m * ns * 8) + up(m * ns * c) +
+         up((m + 1) * ns * c) + up(m * ns * c) + up(nch * (m + 1) * ns * c) + up(nch * ns * 8) + up(ns * 8) +
+         up(ns * (int64_t)sizeof(hs::ColState));
+    if (P) {
+        b += up(4) + up(nn * c) * 4 + up(std::max<int64_t>(P->fslot_total, 1) * ns * c) +
+             up(std::max<int64_t>(P->bslot_total, 1) * ns * c) +
+             up(((int64_t)4 * hs::kCntPad * P->nchunk + 2 * P->nb) * 4) + up(16) + up(4 * nn * 8) * 2;
+    }
+    return b;
+}
+
+void lane_alloc(hs_context* ctx, Lane& L, const hs_hmatrix* H, const hs_precond* P, int ns, int m, hipStream_t s,
+                bool aux) {
+    L.H = H;
+    L.P = P;
+    L.s = s;
+    L.aux = aux;
+    L.ns = ns;
+    L.m = m;
+    L.w.mem = ctx->mem;
+    const int64_t n = H->n;
+    L.bt = L.w.get<cd>(n * ns);
+    L.xt = L.w.get<cd>(n * ns);
+    L.slots = L.w.get<cd>((size_t)H->slot_total * ns);
+    L.d_cols = L.w.get<int>(ns);
+    L.G.alloc(L.w, n, ns, m, false);
+    if (P) L.sw = make_sweep_ws(L.w, P, ns, s, ctx);
+    // every slot starts free (done)
+    L.st.assign(ns, hs::ColState{});
+    for (auto& c : L.st) c.done = 1;
+    hip_check(hipMemcpyAsync(L.G.st, L.st.data(), sizeof(hs::ColState) * ns, hipMemcpyHostToDevice, s), "H2D");
+}
+
+void lane_matvec(hs_context* ctx, Lane& L, const cd* in, cd* out, const hs::ColMask& mk) {
+    if (L.aux) {
+        matvec_tree(ctx, L.H, in, out, L.ns, L.slots, L.s, mk);
+        return;
+    }
+    // near and far one after the other on the lane's stream (disjoint slots)
+    const hs_hmatrix* H = L.H;
+    timed(ctx, HS_KT_NEAR_MV, L.s, [&] {
+        hs::launch_near_mv(mk, H->d_near_tasks, H->d_near_slot, (int64_t)H->near_tasks.size(), H->d_near, in, H->n,
+                           L.ns, L.slots, L.s);
+    });
+    timed(ctx, HS_KT_FAR_MV, L.s, [&] {
+        hs::launch_far_mv(mk, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr, H->d_mv_slot, H->n_far_wg,
+                          (int64_t)H->far_geom.size(), in, H->n, L.ns, L.slots, L.s);
+    });
+    hs::launch_gather(mk, H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, L.slots, H->n, L.ns, out, L.s);
+}
+
+void lane_precond(hs_context* ctx, Lane& L, const cd* in, cd* out, const hs::ColMask& mk) {
+    if (L.P) apply_tree(ctx, L.P, in, out, L.ns, L.sw, L.s, mk);
+    else hip_check(hipMemcpyAsync(out, in, sizeof(cd) * L.H->n * L.ns, hipMemcpyDeviceToDevice, L.s), "D2D");
+}
+
+// Start the listed slots (their b already in bt, tree order) from x = 0:
+// r = b - Z 0 = b for them (every other column's r is recomputed from the
+// Z x of the last cycle end, unchanged), then their fresh states. The
+// partials are those of ||b||^2, as a solve's first cycle start uses.
+void lane_start_cols(Lane& L, const std::vector<int>& cols, const hs_solve_opts& o, int budget) {
+    if (cols.empty()) return;
+    const int64_t n = L.H->n;
+    for (int c : cols) {
+        hip_check(hipMemsetAsync(L.xt + (int64_t)c * n, 0, sizeof(cd) * n, L.s), "memset");
+        hip_check(hipMemsetAsync(L.G.tmp + (int64_t)c * n, 0, sizeof(cd) * n, L.s), "memset");
+    }
+    hip_check(hipMemcpyAsync(L.d_cols, cols.data(), sizeof(int) * cols.size(), hipMemcpyHostToDevice, L.s), "H2D");
+    hs::launch_residual(L.bt, L.G.tmp, L.G.r, n, L.ns, L.G.npart, L.G.nchunk, L.s);
+    hs::launch_col_start(L.G.npart, L.G.nchunk, L.G.st, L.ns, L.d_cols, (int)cols.size(), o.tol, budget,
+                         o.fixed_iters > 0 ? 1 : 0, L.s);
+    // the slots are live from now on (the host copy catches up at the next poll)
+    for (int c : cols) L.st[c].done = 0;
+}
+
+// Start every slot from the caller's x0 (already in xt): ||b|| from b, then
+// r = b - Z x0.
+void lane_start_x0(hs_context* ctx, Lane& L, const hs_solve_opts& o, int budget) {
+    const int64_t n = L.H->n;
+    std::vector<int> cols(L.ns);
+    for (int c = 0; c < L.ns; ++c) cols[c] = c;
+    hip_check(hipMemcpyAsync(L.d_cols, cols.data(), sizeof(int) * cols.size(), hipMemcpyHostToDevice, L.s), "H2D");
+    hs::launch_col_norms(L.bt, n, L.ns, L.G.npart, L.G.nchunk, L.s);
+    hs::launch_col_start(L.G.npart, L.G.nchunk, L.G.st, L.ns, L.d_cols, L.ns, o.tol, budget, o.fixed_iters > 0 ? 1 : 0,
+                         L.s);
+    lane_matvec(ctx, L, L.xt, L.G.tmp, kAllCols);
+    hs::launch_residual(L.bt, L.G.tmp, L.G.r, n, L.ns, L.G.npart, L.G.nchunk, L.s);
+    for (auto& c : L.st) c.done = 0;
+}
+
+bool lane_live(const Lane& L) {
+    for (const auto& c : L.st)
+        if (!c.done) return true;
+    return false;
+}
+
+// Column states of the given lanes to the host (one synchronisation per
+// stream), with the sweeps' error flags.
+void lanes_poll(std::vector<Lane*>& ls) {
+    for (Lane* L : ls) {
+        hip_check(hipMemcpyAsync(L->st.data(), L->G.st, sizeof(hs::ColState) * L->ns, hipMemcpyDeviceToHost, L->s),
+                  "D2H");
+        L->err = 0;
+        if (L->P) hip_check(hipMemcpyAsync(&L->err, L->sw.w.err, sizeof(int), hipMemcpyDeviceToHost, L->s), "D2H");
+    }
+    for (Lane* L : ls) hip_check(hipStreamSynchronize(L->s), "stream sync");
+    for (Lane* L : ls)
+        if (L->err)
+            fail(HS_ETIMEOUT, "a device-side wait of the preconditioner sweeps exceeded the context's wait limit");
+}
+
+// One restart cycle of every lane with a live column, in lockstep: the
+// lanes' launches alternate step by step, each lane on its own stream, and a
+// poll reads all of them at once. Same arithmetic per lane as gmres_run.
+void lanes_cycle(hs_context* ctx, std::vector<Lane*>& lanes, int poll) {
+    std::vector<Lane*> run;
+    for (Lane* L : lanes) {
+        L->ran = lane_live(*L);
+        L->stepping = L->ran;
+        if (!L->ran) continue;
+        run.push_back(L);
+        hip_check(hipMemsetAsync(L->G.Hh, 0, sizeof(cd) * L->G.ldh * L->ns, L->s), "memset");
+        hs::launch_cycle_start(L->G.r, L->G.V, L->H->n, L->G.g, L->m, L->G.npart, L->G.nchunk, L->G.st, L->H->n, L->ns,
+                               false, L->s);
+    }
+    if (run.empty()) return;
+    int m = 0;
+    for (Lane* L : run) m = std::max(m, L->m);
+    for (int j = 0; j < m; ++j) {
+        for (Lane* L : run) {
+            if (!L->stepping || j >= L->m) continue;
+            GmresWs& G = L->G;
+            const int64_t n = G.n, vs = G.vstride;
+            const hs::ColMask active{G.st, 1, 0};
+            lane_precond(ctx, *L, G.V + j * vs, G.tmp, active);
+            lane_matvec(ctx, *L, G.tmp, G.wv, active);
+            hs::launch_dots(G.V, n, vs, j + 1, G.wv, n, G.ns, G.st, G.partial, G.nchunk, L->s);
+            hs::launch_basis_update(G.V, n, vs, j + 1, G.partial, G.nchunk, G.wv, n, G.ns, G.st, G.Hh, G.ldh, G.m + 1,
+                                    j, false, nullptr, L->s);
+            hs::launch_dots(G.V, n, vs, j + 1, G.wv, n, G.ns, G.st, G.partial, G.nchunk, L->s);
+            hs::launch_basis_update(G.V, n, vs, j + 1, G.partial, G.nchunk, G.wv, n, G.ns, G.st, G.Hh, G.ldh, G.m + 1,
+                                    j, true, G.npart, L->s);
+            hs::launch_givens(G.Hh, G.ldh, G.m, j, G.csv, G.snv, G.g, G.npart, G.nchunk, G.st, G.ns, G.inv_hn, L->s);
+            hs::launch_scale_next(G.wv, G.V + (j + 1) * vs, n, n, G.ns, G.st, G.inv_hn, L->s);
+        }
+        if ((j + 1) % poll == 0 && j + 1 < m) {
+            std::vector<Lane*> live;
+            for (Lane* L : run)
+                if (L->stepping && j + 1 < L->m) live.push_back(L);
+            if (live.empty()) break;
+            for (Lane* L : live) hip_check(hipGetLastError(), "inner launches");
+            lanes_poll(live);
+            bool any = false;
+            for (Lane* L : live) {
+                bool a = false;
+                for (auto& c : L->st) a |= c.active != 0;
+                L->stepping = a;
+                any |= a;
+            }
+            if (!any) break;
+        }
+    }
+    for (Lane* L : run) {
+        GmresWs& G = L->G;
+        const int64_t n = G.n, vs = G.vstride;
+        const hs::ColMask stepped{G.st, 2, 0};
+        hs::launch_lsq(G.Hh, G.ldh, G.m, G.g, G.y, G.st, G.ns, L->s);
+        hs::launch_combine(G.V, n, vs, G.y, G.m, G.tmp, n, G.ns, G.st, L->s);
+        lane_precond(ctx, *L, G.tmp, G.wv, stepped);
+        hs::launch_axpy_x(L->xt, G.wv, n, G.ns, G.st, L->s);
+        lane_matvec(ctx, *L, L->xt, G.tmp, stepped);
+        hs::launch_residual(L->bt, G.tmp, G.r, n, G.ns, G.npart, G.nchunk, L->s);
+        hs::launch_cycle_end(G.npart, G.nchunk, G.st, G.ns, L->s);
+        hip_check(hipGetLastError(), "cycle launches");
+    }
+    lanes_poll(run);
+}
+
+// Streams for lanes: lane 0 on the context's stream, the others spread over
+// up to three library-owned streams (default priority) that first wait for
+// everything already queued on the context's stream.
+struct LaneStreams {
+    hipStream_t s[3] = {};
+    hipEvent_t ev[4] = {};
+    int used = 0;
+    int device = -1;
+    void ensure(int k) {
+        if (device < 0) hip_check(hipGetDevice(&device), "hipGetDevice");
+        for (int i = used; i < k; ++i) {
+            hip_check(hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking), "hipStreamCreateWithFlags");
+            hip_check(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming), "hipEventCreateWithFlags");
+        }
+        if (!ev[3]) hip_check(hipEventCreateWithFlags(&ev[3], hipEventDisableTiming), "hipEventCreateWithFlags");
+        used = std::max(used, k);
+    }
+    ~LaneStreams() {
+        // the sweeps' cross-stream order must not keep a stream about to go
+        if (device >= 0)
+            for (auto x : s)
+                if (x) sweeps_release(device, x);
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto x : s)
+            if (x) (void)hipStreamDestroy(x);
+    }
+};
+
+hipStream_t lane_stream(hs_context* ctx, LaneStreams& ls, size_t i) {
+    if (i == 0) return ctx->stream;
+    return ls.s[(i - 1) % 3];
+}
+
+// Extra streams wait for the context's stream (inputs ready).
+void lanes_fork(hs_context* ctx, LaneStreams& ls, size_t nlanes) {
+    const int k = (int)std::min<size_t>(nlanes > 0 ? nlanes - 1 : 0, 3);
+    if (k == 0) return;
+    ls.ensure(k);
+    hip_check(hipEventRecord(ls.ev[3], ctx->stream), "hipEventRecord");
+    for (int i = 0; i < k; ++i) hip_check(hipStreamWaitEvent(ls.s[i], ls.ev[3], 0), "hipStreamWaitEvent");
+}
+
+// The context's stream waits for the extra streams (outputs ready).
+void lanes_join(hs_context* ctx, LaneStreams& ls) {
+    for (int i = 0; i < ls.used; ++i) {
+        hip_check(hipEventRecord(ls.ev[i], ls.s[i]), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(ctx->stream, ls.ev[i], 0), "hipStreamWaitEvent");
+    }
+}
+
+void check_solve_opts(const hs_solve_opts* o) {
+    if (o->method != HS_SOLVE_GMRES) fail(HS_EINVAL, "only HS_SOLVE_GMRES runs on the multi-geometry engine");
+    if (o->restart < 1 || o->restart > hs::kMaxRankCap) fail(HS_EINVAL, "restart must be in [1, 256]");
+    if (!(o->tol >= 0.0)) fail(HS_EINVAL, "tol must be >= 0");
+}
+
+int solve_budget(const hs_solve_opts* o) {
+    return o->fixed_iters > 0 ? o->fixed_iters : (o->max_iters > 0 ? o->max_iters : 5000);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hs_solve_many(hs_context* ctx, int64_t nitems, const hs_solve_item* items, const hs_solve_opts* opts,
+                      hs_solve_stats* stats) {
+    try {
+        if (!ctx || !items || !opts || !stats) fail(HS_EINVAL, "NULL argument");
+        if (nitems < 1) fail(HS_EINVAL, "nitems must be >= 1");
+        check_solve_opts(opts);
+        for (int64_t i = 0; i < nitems; ++i) {
+            const hs_solve_item& it = items[i];
+            if (!it.H || !it.b || !it.x) fail(HS_EINVAL, "item " + std::to_string(i) + ": NULL H, b or x");
+            if (it.nrhs < 1 || it.nrhs > (1 << 20)) fail(HS_EINVAL, "item " + std::to_string(i) + ": bad nrhs");
+            if (it.P && it.P->H != it.H) fail(HS_EINVAL, "item " + std::to_string(i) + ": P belongs to another H");
+        }
+        set_device(ctx);
+        const int budget = solve_budget(opts);
+        LaneStreams ls;
+        std::vector<std::unique_ptr<Lane>> lanes;
+        lanes_fork(ctx, ls, (size_t)nitems);
+        for (int64_t i = 0; i < nitems; ++i) {
+            const hs_solve_item& it = items[i];
+            auto L = std::make_unique<Lane>();
+            lane_alloc(ctx, *L, it.H, it.P, (int)it.nrhs, opts->restart, lane_stream(ctx, ls, (size_t)i), i == 0);
+            hs::launch_permute(static_cast<const cd*>(it.b), L->bt, it.H->d_perm, it.H->n, it.nrhs, true, L->s);
+            if (opts->use_x0) {
+                hs::launch_permute(static_cast<const cd*>(it.x), L->xt, it.H->d_perm, it.H->n, it.nrhs, true, L->s);
+                lane_start_x0(ctx, *L, *opts, budget);
+            } else {
+                std::vector<int> cols((size_t)it.nrhs);
+                for (int c = 0; c < (int)it.nrhs; ++c) cols[c] = c;
+                lane_start_cols(*L, cols, *opts, budget);
+            }
+            lanes.push_back(std::move(L));
+        }
+        std::vector<Lane*> lp;
+        for (auto& L : lanes) lp.push_back(L.get());
+        for (;;) {
+            bool any = false;
+            for (Lane* L : lp) any |= lane_live(*L);
+            if (!any) break;
+            lanes_cycle(ctx, lp, 4);
+        }
+        int64_t k = 0;
+        bool all_conv = true;
+        for (int64_t i = 0; i < nitems; ++i) {
+            Lane& L = *lanes[i];
+            hs::launch_permute(L.xt, static_cast<cd*>(items[i].x), L.H->d_perm, L.H->n, L.ns, false, L.s);
+            for (int c = 0; c < L.ns; ++c, ++k) {
+                stats[k].iters = L.st[c].total;
+                stats[k].relres = L.st[c].relres;
+                stats[k].converged = L.st[c].relres <= opts->tol ? 1 : 0;
+                if (!std::isfinite(L.st[c].relres)) fail(HS_ENUMERIC, "NaN or Inf in the residual");
+                all_conv &= stats[k].converged != 0;
+            }
+        }
+        for (auto& L : lanes) hip_check(hipGetLastError(), "permute launch");
+        lanes_join(ctx, ls);
+        for (auto& L : lanes) hip_check(hipStreamSynchronize(L->s), "stream sync");
+        return all_conv ? HS_OK : HS_NOT_CONVERGED;
+    } catch (const Error& e) {
+        (void)hipDeviceSynchronize();
+        return set_error(e);
+    }
+}
+
+// ---- serving: continuous batching ----------------------------------------------------------
 
 }  // extern "C"
 
 struct hs_server {
     hs_context* ctx = nullptr;
     int64_t budget = 0, used = 0;
-    int32_t max_cols = 32;
+    int32_t slots = 32;           // column slots per geometry
     hs_solve_opts opts{};
+    LaneStreams ls;
     struct Geometry {
-        const hs_hmatrix* H;
-        const hs_precond* P;
+        const hs_hmatrix* H = nullptr;
+        const hs_precond* P = nullptr;
+        hs_hmatrix* Hown = nullptr;   // built by the server (hs_server_add_geometry)
+        hs_precond* Pown = nullptr;
+        std::unique_ptr<Lane> lane;   // allocated at the geometry's first request
+        std::vector<std::pair<int64_t, int32_t>> slot_req;   // (request, column) per slot, request -1 = free
+        int64_t bytes = 0;
     };
     std::vector<Geometry> geos;
     std::vector<const hs_hmatrix*> counted_h;
     struct Request {
-        int32_t geometry, ncols;
-        const cd* b;
-        cd* x;
-        hs_request_stats st;
+        int32_t geometry = 0, ncols = 0, admitted = 0, retired = 0;
+        const cd* b = nullptr;
+        cd* x = nullptr;
+        hs_request_stats st{};
     };
     std::vector<Request> reqs;
-    std::vector<int64_t> pending;   // request ids in submission order
+    std::vector<int64_t> pending;   // not yet (fully) admitted, submission order
+    ~hs_server() {
+        if (ctx) (void)hipSetDevice(ctx->device);
+        for (auto& g : geos) {
+            g.lane.reset();
+            if (g.Pown) hs_precond_destroy(g.Pown);
+            if (g.Hown) hs_hmatrix_destroy(g.Hown);
+        }
+    }
 };
 
 namespace {
 double server_clock() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int32_t server_take(hs_server* s, const hs_hmatrix* H, const hs_precond* P, hs_hmatrix* Hown, hs_precond* Pown,
+                    int64_t add, int32_t* geometry) {
+    s->used += add;
+    if (std::find(s->counted_h.begin(), s->counted_h.end(), H) == s->counted_h.end()) s->counted_h.push_back(H);
+    hs_server::Geometry g;
+    g.H = H;
+    g.P = P;
+    g.Hown = Hown;
+    g.Pown = Pown;
+    g.bytes = add;
+    g.slot_req.assign(s->slots, {-1, 0});
+    s->geos.push_back(std::move(g));
+    *geometry = (int32_t)s->geos.size() - 1;
+    return HS_OK;
 }
 }  // namespace
 
@@ -2287,17 +2680,19 @@ extern "C" {
 
 double hs_server_clock(void) { return server_clock(); }
 
-int32_t hs_server_create(hs_context* ctx, int64_t device_budget_bytes, int32_t max_batch_cols,
+int32_t hs_server_create(hs_context* ctx, int64_t device_budget_bytes, int32_t slots_per_geometry,
                          const hs_solve_opts* opts, hs_server** out) {
     try {
         if (!ctx || !opts || !out) fail(HS_EINVAL, "NULL argument");
         *out = nullptr;
         if (device_budget_bytes <= 0) fail(HS_EINVAL, "device budget must be positive");
-        if (max_batch_cols < 1) fail(HS_EINVAL, "max_batch_cols must be >= 1");
+        if (slots_per_geometry < 1 || slots_per_geometry > 1024) fail(HS_EINVAL, "slots_per_geometry must be in [1, 1024]");
+        check_solve_opts(opts);
+        if (opts->use_x0) fail(HS_EINVAL, "served columns start from x = 0");
         auto* s = new hs_server;
         s->ctx = ctx;
         s->budget = device_budget_bytes;
-        s->max_cols = max_batch_cols;
+        s->slots = slots_per_geometry;
         s->opts = *opts;
         *out = s;
         return HS_OK;
@@ -2310,17 +2705,67 @@ int32_t hs_server_admit(hs_server* s, const hs_hmatrix* H, const hs_precond* P, 
     try {
         if (!s || !H || !geometry) fail(HS_EINVAL, "NULL argument");
         if (P && P->H != H) fail(HS_EINVAL, "the preconditioner belongs to another H-matrix");
-        int64_t add = P ? P->own.bytes : 0;
+        int64_t add = (P ? P->own.bytes : 0) + lane_bytes(H, P, s->slots, s->opts.restart);
         const bool h_new = std::find(s->counted_h.begin(), s->counted_h.end(), H) == s->counted_h.end();
         if (h_new) add += H->own.bytes;
         if (s->used + add > s->budget)
-            fail(HS_ENOMEM, "admission refused: the geometry's device footprint exceeds the remaining budget");
-        s->used += add;
-        if (h_new) s->counted_h.push_back(H);
-        s->geos.push_back({H, P});
-        *geometry = (int32_t)s->geos.size() - 1;
-        return HS_OK;
+            fail(HS_ENOMEM, "admission refused: the geometry's device footprint (" + std::to_string(add) +
+                                " bytes with its solve workspace) exceeds the remaining budget");
+        return server_take(s, H, P, nullptr, nullptr, add, geometry);
     } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
+int32_t hs_server_add_geometry(hs_server* s, const double* points_host, int64_t n, double k, double self_h,
+                               const hs_build_opts* bopts, const hs_precond_opts* popts, int64_t* estimate,
+                               int32_t* geometry) {
+    hs_hmatrix* H = nullptr;
+    hs_precond* P = nullptr;
+    try {
+        if (!s || !points_host || !bopts || !geometry) fail(HS_EINVAL, "NULL argument");
+        if (n < 1) fail(HS_EINVAL, "n must be >= 1");
+        // 1. footprint from the host plan, before any device allocation
+        hs_plan* plan = nullptr;
+        int32_t rc = hs_plan_create(points_host, n, bopts->leaf_max, popts ? popts->ordering : HS_ORDER_RCM, &plan);
+        if (rc != HS_OK) return rc;
+        std::unique_ptr<hs_plan, void (*)(hs_plan*)> pg(plan, hs_plan_destroy);
+        hs_info inf;
+        hs_plan_query(plan, &inf);
+        const int64_t est = inf.bytes_estimate;
+        if (estimate) *estimate = est;
+        if (s->used + est > s->budget)
+            fail(HS_ENOMEM, "admission refused before allocation: the plan's footprint estimate (" +
+                                std::to_string(est) + " bytes) exceeds the remaining budget");
+        // 2. build on the device, then charge the actual footprint
+        set_device(s->ctx);
+        Owned tmp;
+        tmp.mem = s->ctx->mem;
+        double* d_pts = tmp.get<double>((size_t)n * 3);
+        hip_check(hipMemcpyAsync(d_pts, points_host, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s->ctx->stream),
+                  "H2D");
+        rc = hs_h_build(s->ctx, d_pts, n, k, self_h, bopts, &H);
+        if (rc != HS_OK) return rc;
+        if (popts) {
+            rc = hs_precond_setup(s->ctx, H, popts, &P);
+            if (rc != HS_OK) {
+                hs_hmatrix_destroy(H);
+                return rc;
+            }
+        }
+        tmp.release();
+        const int64_t add = H->own.bytes + (P ? P->own.bytes : 0) + lane_bytes(H, P, s->slots, s->opts.restart);
+        if (s->used + add > s->budget)
+            fail(HS_ENOMEM, "admission refused: the built geometry needs " + std::to_string(add) +
+                                " bytes, more than the remaining budget (the plan estimated " + std::to_string(est) +
+                                ")");
+        rc = server_take(s, H, P, H, P, add, geometry);
+        H = nullptr;
+        P = nullptr;
+        return rc;
+    } catch (const Error& e) {
+        if (P) hs_precond_destroy(P);
+        if (H) hs_hmatrix_destroy(H);
         return set_error(e);
     }
 }
@@ -2330,8 +2775,8 @@ int32_t hs_server_submit(hs_server* s, int32_t geometry, const void* b, void* x,
     try {
         if (!s || !b || !x || !request) fail(HS_EINVAL, "NULL argument");
         if (geometry < 0 || geometry >= (int32_t)s->geos.size()) fail(HS_EINVAL, "unknown geometry");
-        if (ncols < 1) fail(HS_EINVAL, "ncols must be >= 1");
-        hs_server::Request r{};
+        if (ncols < 1 || ncols > s->slots) fail(HS_EINVAL, "ncols must be in [1, slots_per_geometry]");
+        hs_server::Request r;
         r.geometry = geometry;
         r.ncols = ncols;
         r.b = static_cast<const cd*>(b);
@@ -2339,6 +2784,7 @@ int32_t hs_server_submit(hs_server* s, int32_t geometry, const void* b, void* x,
         r.st.geometry = geometry;
         r.st.ncols = ncols;
         r.st.t_arrival = t_arrival;
+        r.st.converged = 1;
         s->reqs.push_back(r);
         *request = (int64_t)s->reqs.size() - 1;
         s->pending.push_back(*request);
@@ -2352,83 +2798,123 @@ int32_t hs_server_step(hs_server* s, int32_t* columns_served) {
     try {
         if (!s || !columns_served) fail(HS_EINVAL, "NULL argument");
         *columns_served = 0;
-        if (s->pending.empty()) return HS_OK;
-        // the oldest pending request decides the geometry; its pending
-        // requests join in arrival order while the batch has room
+        hs_context* ctx = s->ctx;
+        set_device(ctx);
+        const int budget = solve_budget(&s->opts);
+        // 1. admission at the cycle boundary: per geometry, pending requests in
+        //    arrival order take free slots while the oldest one fits (no later
+        //    request of that geometry jumps ahead of it)
         auto older = [&](int64_t p, int64_t q) {
             const auto &a = s->reqs[p].st, &b = s->reqs[q].st;
             return a.t_arrival != b.t_arrival ? a.t_arrival < b.t_arrival : p < q;
         };
         std::vector<int64_t> order(s->pending);
         std::stable_sort(order.begin(), order.end(), older);
-        const int32_t g = s->reqs[order[0]].geometry;
-        std::vector<int64_t> batch;
-        int32_t cols = 0;
+        std::vector<char> blocked(s->geos.size(), 0);
+        std::vector<std::vector<int>> fresh(s->geos.size());
+        std::vector<std::pair<int64_t, int>> admit;   // (request, geometry) admitted now
+        std::vector<int> nfree(s->geos.size(), 0);
+        for (size_t gi = 0; gi < s->geos.size(); ++gi)
+            for (auto& sr : s->geos[gi].slot_req) nfree[gi] += sr.first < 0 ? 1 : 0;
         for (int64_t q : order) {
-            const auto& r = s->reqs[q];
-            if (r.geometry != g) continue;
-            if (!batch.empty() && cols + r.ncols > s->max_cols) break;
-            batch.push_back(q);
-            cols += r.ncols;
-        }
-        const hs_hmatrix* H = s->geos[g].H;
-        const hs_precond* P = s->geos[g].P;
-        hs_context* ctx = s->ctx;
-        set_device(ctx);
-        hipStream_t st = ctx->stream;
-        const int64_t n = H->n;
-        Owned w;
-        w.mem = ctx->mem;
-        cd* B = w.get<cd>((size_t)n * cols);
-        cd* X = w.get<cd>((size_t)n * cols);
-        int64_t off = 0;
-        for (int64_t q : batch) {
-            const auto& r = s->reqs[q];
-            hip_check(hipMemcpyAsync(B + off, r.b, sizeof(cd) * n * r.ncols, hipMemcpyDeviceToDevice, st), "D2D");
-            off += n * r.ncols;
-        }
-        std::vector<hs_solve_stats> stats(cols);
-        const int32_t rc = hs_solve(ctx, H, P, B, X, cols, &s->opts, stats.data());
-        if (rc != HS_OK && rc != HS_NOT_CONVERGED) return rc;
-        off = 0;
-        int32_t c0 = 0;
-        for (int64_t q : batch) {
             auto& r = s->reqs[q];
-            hip_check(hipMemcpyAsync(r.x, X + off, sizeof(cd) * n * r.ncols, hipMemcpyDeviceToDevice, st), "D2D");
-            off += n * r.ncols;
-            r.st.iters = 0;
-            r.st.relres = 0.0;
-            r.st.converged = 1;
-            for (int32_t c = 0; c < r.ncols; ++c) {
-                const auto& cs = stats[c0 + c];
-                r.st.iters = std::max(r.st.iters, cs.iters);
-                r.st.relres = std::max(r.st.relres, cs.relres);
-                r.st.converged &= cs.converged;
+            if (blocked[r.geometry]) continue;
+            if (nfree[r.geometry] < r.ncols) {
+                blocked[r.geometry] = 1;
+                continue;
             }
-            c0 += r.ncols;
+            nfree[r.geometry] -= r.ncols;
+            admit.push_back({q, r.geometry});
+            r.st.t_start = server_clock();
+            auto& g = s->geos[r.geometry];
+            if (!g.lane) {
+                size_t idx = 0;
+                for (auto& gg : s->geos) idx += gg.lane ? 1 : 0;
+                if (idx > 0) s->ls.ensure(std::min<int>((int)idx, 3));
+                g.lane = std::make_unique<Lane>();
+                lane_alloc(ctx, *g.lane, g.H, g.P, s->slots, s->opts.restart, lane_stream(ctx, s->ls, idx), idx == 0);
+            }
         }
-        hip_check(hipStreamSynchronize(st), "stream sync");
-        const double t = server_clock();
-        for (int64_t q : batch) {
-            s->reqs[q].st.t_done = t;
-            s->reqs[q].st.done = 1;
+        // lanes on the library's streams follow the caller's work (the submitted b)
+        if (!admit.empty() && s->ls.used > 0) {
+            hip_check(hipEventRecord(s->ls.ev[3], ctx->stream), "hipEventRecord");
+            for (int i = 0; i < s->ls.used; ++i)
+                hip_check(hipStreamWaitEvent(s->ls.s[i], s->ls.ev[3], 0), "hipStreamWaitEvent");
+        }
+        for (auto& a : admit) {
+            auto& r = s->reqs[a.first];
+            auto& g = s->geos[a.second];
+            Lane& L = *g.lane;
+            int c = 0;
+            for (int sl = 0; sl < s->slots && c < r.ncols; ++sl) {
+                if (g.slot_req[sl].first >= 0) continue;
+                g.slot_req[sl] = {a.first, c};
+                hs::launch_permute(r.b + (int64_t)c * g.H->n, L.bt + (int64_t)sl * g.H->n, g.H->d_perm, g.H->n, 1, true,
+                                   L.s);
+                fresh[a.second].push_back(sl);
+                ++c;
+            }
+            r.admitted = r.ncols;
         }
         std::vector<int64_t> rest;
         for (int64_t q : s->pending)
-            if (!s->reqs[q].st.done) rest.push_back(q);
+            if (s->reqs[q].admitted < s->reqs[q].ncols) rest.push_back(q);
         s->pending.swap(rest);
-        *columns_served = cols;
+        std::vector<Lane*> lanes;
+        for (size_t gi = 0; gi < s->geos.size(); ++gi) {
+            auto& g = s->geos[gi];
+            if (!g.lane) continue;
+            lane_start_cols(*g.lane, fresh[gi], s->opts, budget);
+            lanes.push_back(g.lane.get());
+        }
+        // 2. one restart cycle of every geometry with live columns
+        lanes_cycle(ctx, lanes, 4);
+        // 3. retire finished columns into their requests' x
+        std::vector<int64_t> finished;
+        int32_t served = 0;
+        for (auto& g : s->geos) {
+            if (!g.lane) continue;
+            Lane& L = *g.lane;
+            for (int sl = 0; sl < s->slots; ++sl) {
+                auto& sr = g.slot_req[sl];
+                if (sr.first < 0 || !L.st[sl].done) continue;
+                auto& r = s->reqs[sr.first];
+                hs::launch_permute(L.xt + (int64_t)sl * g.H->n, r.x + (int64_t)sr.second * g.H->n, g.H->d_perm, g.H->n,
+                                   1, false, L.s);
+                const auto& cs = L.st[sl];
+                r.st.iters = std::max(r.st.iters, cs.total);
+                r.st.relres = std::max(r.st.relres, cs.relres);
+                if (!(cs.relres <= s->opts.tol)) r.st.converged = 0;
+                if (++r.retired == r.ncols) finished.push_back(sr.first);
+                sr = {-1, 0};
+                ++served;
+            }
+        }
+        for (auto& g : s->geos)
+            if (g.lane) hip_check(hipStreamSynchronize(g.lane->s), "stream sync");
+        const double t = server_clock();
+        for (int64_t q : finished) {
+            s->reqs[q].st.t_done = t;
+            s->reqs[q].st.done = 1;
+        }
+        *columns_served = served;
         return HS_OK;
     } catch (const Error& e) {
+        (void)hipDeviceSynchronize();
         return set_error(e);
     }
 }
 
 int32_t hs_server_pending(const hs_server* s, int64_t* requests, int64_t* columns) {
     if (!s || !requests || !columns) { g_last_error = "NULL argument"; return HS_EINVAL; }
-    *requests = (int64_t)s->pending.size();
-    int64_t c = 0;
-    for (int64_t q : s->pending) c += s->reqs[q].ncols;
+    // requests not done: queued, or admitted with columns still running
+    int64_t r = 0, c = 0;
+    for (const auto& q : s->reqs)
+        if (!q.st.done) {
+            ++r;
+            c += q.ncols - q.retired;
+        }
+    *requests = r;
     *columns = c;
     return HS_OK;
 }
@@ -2437,6 +2923,15 @@ int32_t hs_server_request(const hs_server* s, int64_t request, hs_request_stats*
     if (!s || !out) { g_last_error = "NULL argument"; return HS_EINVAL; }
     if (request < 0 || request >= (int64_t)s->reqs.size()) { g_last_error = "unknown request"; return HS_EINVAL; }
     *out = s->reqs[request].st;
+    return HS_OK;
+}
+
+int32_t hs_server_geometry(const hs_server* s, int32_t geometry, hs_hmatrix const** H, hs_precond const** P,
+                           int64_t* bytes) {
+    if (!s || geometry < 0 || geometry >= (int32_t)s->geos.size()) { g_last_error = "unknown geometry"; return HS_EINVAL; }
+    if (H) *H = s->geos[geometry].H;
+    if (P) *P = s->geos[geometry].P;
+    if (bytes) *bytes = s->geos[geometry].bytes;
     return HS_OK;
 }
 

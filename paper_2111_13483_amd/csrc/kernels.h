@@ -371,6 +371,10 @@ void launch_scale_next(const cd* w, cd* vnext, int64_t ldv, int64_t n, int nrhs,
 void launch_cycle_start(const cd* r, cd* V, int64_t ldv, cd* g, int m, const double* norm_partial, int nchunk,
                         ColState* st, int64_t n, int nrhs, bool first, hipStream_t s);
 void launch_col_init(ColState* st, const ColState* outer, int nrhs, double tol, int budget, hipStream_t s);
+// Fresh states for the listed columns (cols, ncols entries, device) of a
+// running solve whose residual partials hold ||b||^2 for them.
+void launch_col_start(const double* norm_partial, int nchunk, ColState* st, int nrhs, const int* cols, int ncols,
+                      double tol, int budget, int fixed, hipStream_t s);
 void launch_lsq(const cd* H, int64_t ldh, int m, const cd* g, cd* y, const ColState* st, int nrhs, hipStream_t s);
 void launch_combine(const cd* V, int64_t ldv, int64_t vstride, const cd* y, int m, cd* u, int64_t n, int nrhs,
                     const ColState* st, hipStream_t s);

@@ -699,6 +699,29 @@ __global__ void k_col_init(ColState* __restrict__ st, const ColState* __restrict
     st[c] = s;
 }
 
+// Columns starting a solve inside a running multi-column solve (the listed
+// slots): ||b|| from the chunk partials of b, and a fresh state, as the first
+// cycle start of a solve sets it (relres 1, no steps; a zero b is done).
+__global__ void __launch_bounds__(NT)
+k_col_start(const double* __restrict__ norm_partial, int nchunk, ColState* __restrict__ st, int nrhs,
+            const int* __restrict__ cols, double tol, int budget, int fixed) {
+    __shared__ double red[NW];
+    const int c = cols[blockIdx.x];
+    const double bn = sqrt(sum_chunks(norm_partial, nchunk, nrhs, c, red));
+    if (threadIdx.x != 0) return;
+    ColState s;
+    s.bnorm = bn;
+    s.beta = 0.0;
+    s.relres = bn > 0.0 ? 1.0 : 0.0;
+    s.tol = tol;
+    s.active = s.steps = s.total = 0;
+    s.done = bn > 0.0 ? 0 : 1;
+    s.budget = budget;
+    s.fixed = fixed;
+    s.pad0 = s.pad1 = 0;
+    st[c] = s;
+}
+
 // y = H^-1 g on the leading steps x steps triangle (back substitution).
 __global__ void k_lsq(const cd* __restrict__ H, int64_t ldh, int m, const cd* __restrict__ g, cd* __restrict__ y,
                       const ColState* __restrict__ st, int nrhs) {
@@ -911,6 +934,13 @@ void launch_residual(const cd* b, const cd* zx, cd* r, int64_t n, int nrhs, doub
 
 void launch_col_norms(const cd* v, int64_t n, int nrhs, double* norm_partial, int nchunk, hipStream_t s) {
     hipLaunchKernelGGL(k_col_norms, dim3(nchunk, nrhs), dim3(NT), 0, s, v, n, nrhs, norm_partial, nchunk);
+}
+
+void launch_col_start(const double* norm_partial, int nchunk, ColState* st, int nrhs, const int* cols, int ncols,
+                      double tol, int budget, int fixed, hipStream_t s) {
+    if (ncols > 0)
+        hipLaunchKernelGGL(k_col_start, dim3(ncols), dim3(NT), 0, s, norm_partial, nchunk, st, nrhs, cols, tol, budget,
+                           fixed);
 }
 
 void launch_cycle_end(const double* norm_partial, int nchunk, ColState* st, int nrhs, hipStream_t s) {
