@@ -28,7 +28,9 @@ KERNEL_SOURCES = ("paper_2111_13483_amd/csrc/kernels_sweep.hip", "paper_2111_134
                   "paper_2111_13483_amd/csrc/kernels.h", "paper_2111_13483_amd/csrc/devcommon.h")
 # the instrumented launches and their kernels' names
 TIMING_EVERY = 4
-KERNEL_NAME = {"sweep_fwd": "k_sweep_fwd", "sweep_bwd": "k_sweep_bwd", "near_mv": "k_near_mv", "far_mv": "k_far_mv"}
+KERNEL_NAME = {"sweep_fwd": "k_sweep_fwd", "sweep_bwd": "k_sweep_bwd", "near_mv": "k_near_mv", "far_mv": "k_far_mv",
+               "factor": "k_factor_alpha", "schur": "k_schur_tiles"}
+SOLVE_KERNELS = ("sweep_fwd", "sweep_bwd", "near_mv", "far_mv")
 # the kernels behind each instrumented launch (the far matvec is two kernels,
 # each dispatched once per matvec, on one stream inside one timed region)
 PMC_KERNELS = {"sweep_fwd": ("k_sweep_fwd",), "sweep_bwd": ("k_sweep_bwd",), "near_mv": ("k_near_mv",),
@@ -44,7 +46,10 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the point count (same structure)")
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work to sample")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle GMRES steps timed for the CPU baseline")
+    ap.add_argument("--no-legs", action="store_true", help="skip the multi-RHS, served and mixed legs")
+    ap.add_argument("--serve-rate", type=float, default=10.0, help="arrival rate of the served leg (requests/s)")
+    ap.add_argument("--serve-window", type=float, default=3.0, help="arrival window of the served leg (s)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -53,14 +58,24 @@ def parse():
     ap.add_argument("--out", help="summary file written by --summarize-*")
     ap.add_argument("--command", default="", help="command line recorded in the summary")
     ap.add_argument("--mixed", action="store_true",
-                    help="mixed path: FP64 flexible GMRES(20) with inner GMRES(20) on complex64 copies")
+                    help="mixed path: FP64 flexible GMRES with inner GMRES on complex64 copies")
+    ap.add_argument("--mixed-restart", type=int, default=20, help="outer FGMRES restart of the mixed path")
+    ap.add_argument("--mixed-inner", type=int, default=20, help="inner GMRES steps of the mixed path")
     ap.add_argument("--batch", type=int, default=0, metavar="G",
                     help="batching run: G geometries of the many-geometry recipe, batched vs one-by-one setup")
-    ap.add_argument("--batch-nmax", type=int, default=12000, help="largest N of the batching run")
+    ap.add_argument("--batch-nmax", type=int, default=40000, help="largest N of the batching run")
+    ap.add_argument("--batch-ppl", type=float, default=3.2, help="points per wavelength of the batching run")
+    ap.add_argument("--batch-restart", type=int, default=50, help="GMRES restart of the batching run")
     ap.add_argument("--serve", action="store_true",
                     help="serving run instead of the step benchmark: resident geometries, Poisson request arrivals")
-    ap.add_argument("--serve-rates", default="5,20,80", help="request arrival rates per second")
+    ap.add_argument("--serve-rates", default="10,30,100", help="request arrival rates per second")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="span of arrivals per rate")
+    ap.add_argument("--serve-geos", type=int, default=8)
+    ap.add_argument("--serve-nmin", type=int, default=50000)
+    ap.add_argument("--serve-nmax", type=int, default=200000)
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-restart", type=int, default=50)
+    ap.add_argument("--serve-budget-gib", type=float, default=200.0)
     ap.add_argument("--write-workload", metavar="PATH",
                     help="write the workload (points, first right-hand side) for the hs_bench driver and exit")
     return ap.parse_args()
@@ -178,17 +193,18 @@ def write_workload(args):
 
 
 def batch(args):
-    """Batching: G geometries (sphere, ellipsoid, cube or plate; N uniform in
-    [2000, nmax]; leaves 24-96; about ten points per wavelength), 4 plane-wave
-    right-hand sides each. Times the H-matrix builds, the preconditioner
-    setups once one by one and once batched (shared elimination launches),
-    and the 4-column solves; progress goes to stderr."""
+    """Batching (many geometries): G geometries of the many-geometry recipe
+    (sphere, ellipsoid, cube or plate; N uniform in [2000, nmax]; leaves
+    24-96), 4 plane-wave right-hand sides each. Times the H-matrix builds,
+    the setups one by one and batched (shared elimination launches), and
+    the solves one geometry at a time (plain per-geometry launches) and all
+    together (hs_solve_many). Progress goes to stderr."""
     import torch
     import paper_2111_13483_amd as hsl
     import workloads as W
 
     ctx = hsl.Context(0)
-    geos = W.batch_geometries(args.batch, args.batch_nmax)
+    geos = W.batch_geometries(args.batch, args.batch_nmax, ppl=args.batch_ppl)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Hs = [hsl.HMatrix(ctx, wl.points, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol) for wl in geos]
@@ -206,94 +222,123 @@ def batch(args):
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     print(f"batch: batched setup {t_batched:.2f} s", file=sys.stderr, flush=True)
+    bs = [torch.as_tensor(np.ascontiguousarray(wl.rhs), device="cuda") for wl in geos]
+    restart = args.batch_restart
     t0 = time.perf_counter()
-    iters, conv, cols = [], True, 0
-    for wl, H, P in zip(geos, Hs, Ps):
-        b = torch.as_tensor(np.ascontiguousarray(wl.rhs), device="cuda")
-        x, st = hsl.solve(ctx, H, P, b, restart=wl.restart, tol=wl.tol)
-        iters.append(max(s.iters for s in st))
-        conv &= all(s.converged for s in st)
-        cols += len(st)
+    iters1 = []
+    for wl, H, P, b in zip(geos, Hs, Ps, bs):
+        x, st = hsl.solve(ctx, H, P, b, restart=restart, tol=wl.tol)
+        iters1.append(max(q.iters for q in st))
     torch.cuda.synchronize()
-    t_solve = time.perf_counter() - t0
-    out = {"metric": "batched setup s and RHS solves/s over many geometries", "unit": "s, RHS/s",
-           "data": "synthetic", "n_gpus": 1, "dtype": "c128",
+    t_solve1 = time.perf_counter() - t0
+    print(f"batch: solves one geometry at a time {t_solve1:.2f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    res = hsl.solve_many(ctx, [(H, P, b) for H, P, b in zip(Hs, Ps, bs)], restart=restart, tol=geos[0].tol)
+    torch.cuda.synchronize()
+    t_many = time.perf_counter() - t0
+    print(f"batch: all geometries together {t_many:.2f} s", file=sys.stderr, flush=True)
+    iters = [max(q.iters for q in st) for _, st in res]
+    conv = all(q.converged for _, st in res for q in st)
+    cols = sum(len(st) for _, st in res)
+    out = {"metric": "batched setup s and RHS solves/s over many geometries vs plain per-geometry FP64",
+           "unit": "s, RHS/s", "data": "synthetic", "n_gpus": 1, "dtype": "c128",
            "config": {"workload": f"{len(geos)} geometries, N in [2000, {args.batch_nmax}], leaves 24-96, "
-                                  "lambda = 10 h, 4 plane waves each, GMRES(30) to 1e-6",
+                                  f"lambda = {args.batch_ppl} h, 4 plane waves each, GMRES({restart}) to 1e-6",
                       "sum_n": int(sum(wl.n for wl in geos)),
                       "kinds": {k: sum(1 for wl in geos if wl.name == k) for k in ("sphere", "ellipsoid", "cube",
                                                                                    "plate")}},
            "h_build_s": t_build, "setup_one_by_one_s": t_single, "setup_batched_s": t_batched,
-           "setup_speedup": t_single / t_batched, "solve_s": t_solve, "rhs_per_s": cols / t_solve,
+           "setup_speedup": t_single / t_batched, "solve_one_by_one_s": t_solve1, "solve_together_s": t_many,
+           "solve_speedup": t_solve1 / t_many, "rhs_per_s": cols / t_many, "rhs_per_s_one_by_one": cols / t_solve1,
            "iters_max": max(iters), "iters_median": float(np.median(iters)), "all_converged": conv}
     print(json.dumps(out), flush=True)
 
 
 def serve(args):
-    """Serving: four geometries resident on the GPU (admitted by device
-    footprint); requests of 1-8 right-hand-side columns (half plane waves,
-    half port vectors) arrive as a Poisson process and are batched per
-    geometry, oldest request first, up to 16 columns per solve. Reports
-    arrival-to-completion latency percentiles and RHS solves/s per rate;
-    progress goes to stderr, one line per batch."""
+    """Serving (resident geometries, continuous batching): geometries
+    cycling cube / sphere / plate with N uniform in [nmin, nmax] at
+    lambda = 0.05, admitted by the host plan's footprint estimate and then
+    built and set up on the GPU; requests of 1-32 columns (half plane waves,
+    half port vectors) arrive as a Poisson process and join the running
+    solves at restart-cycle boundaries. Reports arrival-to-completion
+    latency percentiles and RHS solves/s per rate; progress to stderr."""
+    import math as _m
     import torch
     import paper_2111_13483_amd as hsl
     import workloads as W
 
     ctx = hsl.Context(0)
-    specs = [("c2", 8000), ("c2", 5000), ("c1", 4000), ("plate", 3000)]
-    geos, t_setup = [], []
-    srv = hsl.Server(ctx, 64 << 30, max_batch_cols=16, restart=50, tol=1e-6, max_iters=5000)
-    for name, n in specs:
-        wl = W.make_config(name, n=n)
+    top = np.random.default_rng(5)
+    ns = top.integers(args.serve_nmin, args.serve_nmax + 1, size=args.serve_geos)
+    srv = hsl.Server(ctx, int(args.serve_budget_gib * (1 << 30)), slots=args.serve_slots,
+                     restart=args.serve_restart, tol=1e-6, max_iters=5000)
+    geos, info = [], []
+    for i, n in enumerate(ns):
+        rng = np.random.default_rng(5000 + i)
+        kind = ("cube", "sphere", "plate")[i % 3]
+        if kind == "cube":
+            pts, area = W.cube_surface(int(n), rng)
+        elif kind == "sphere":
+            pts, area = W.fibonacci_sphere(int(n), rng), 4.0 * _m.pi
+        else:
+            pts, area = W.plate_box(int(n), rng)
+        h = _m.sqrt(area / n)
+        k = 2.0 * _m.pi / 0.05
         t0 = time.perf_counter()
-        H = hsl.HMatrix(ctx, wl.points, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol)
-        P = hsl.Precond(ctx, H, "rcm", wl.fill_tol)
+        try:
+            g, est = srv.add_geometry(pts, k, h, 64, 1e-4, "rcm", 1e-2)
+        except hsl.HschurError as e:
+            print(f"serve: geometry {i} ({kind}, N={n}) refused: {e}", file=sys.stderr, flush=True)
+            info.append({"kind": kind, "n": int(n), "admitted": False, "estimate": srv.last_estimate})
+            continue
         torch.cuda.synchronize()
-        t_setup.append(time.perf_counter() - t0)
-        geos.append((wl, srv.admit(H, P), H, P))
-        print(f"serve: geometry {name} N={wl.n} ready in {t_setup[-1]:.2f} s", file=sys.stderr, flush=True)
-    rng = np.random.default_rng(5)
+        dt = time.perf_counter() - t0
+        charged = srv.geometry(g)[2]
+        geos.append((g, pts, k, int(n), kind))
+        info.append({"kind": kind, "n": int(n), "admitted": True, "estimate": est, "charged": charged,
+                     "build_and_setup_s": dt})
+        print(f"serve: geometry {i} {kind} N={n} admitted, ready in {dt:.2f} s", file=sys.stderr, flush=True)
     out = {"metric": "serving latency p50/p99 (arrival to completion) and RHS solves/s", "unit": "s, RHS/s",
            "data": "synthetic", "n_gpus": 1, "dtype": "c128",
-           "config": {"workload": "resident " + ", ".join(f"{a} N={b}" for a, b in specs),
-                      "columns_per_request": "uniform 1-8", "max_batch_cols": 16, "solver": "GMRES(50) to 1e-6"},
-           "build_and_setup_s": t_setup, "rates": []}
-    for rate in [float(r) for r in args.serve_rates.split(",")]:
+           "config": {"workload": f"{args.serve_geos} geometries cube/sphere/plate N in [{args.serve_nmin}, "
+                                  f"{args.serve_nmax}], lambda 0.05, leaf 64", "columns_per_request": "uniform 1-32",
+                      "slots_per_geometry": args.serve_slots, "solver": f"GMRES({args.serve_restart}) to 1e-6"},
+           "geometries": info, "rates": []}
+    rng = np.random.default_rng(5)
+    for ri, rate in enumerate(float(r) for r in args.serve_rates.split(",")):
+        rng = np.random.default_rng(50 + ri)
         arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.serve_seconds * 3) + 8))
         arr = arr[arr <= args.serve_seconds]
         reqs = []
         for a in arr:
-            gi = int(rng.integers(0, len(geos)))
-            wl = geos[gi][0]
-            nc = int(rng.integers(1, 9))
-            cols = [W.plane_wave(wl.points, wl.k, rng) if rng.random() < 0.5 else W.port_vector(wl.n, rng)
-                    for _ in range(nc)]
-            reqs.append((a, gi, torch.as_tensor(np.stack(cols, axis=1), device="cuda")))
+            g, pts, k, n, _ = geos[int(rng.integers(0, len(geos)))]
+            nc = int(rng.integers(1, min(32, args.serve_slots) + 1))
+            cols = [W.plane_wave(pts, k, rng) if rng.random() < 0.5 else W.port_vector(n, rng) for _ in range(nc)]
+            reqs.append((a, g, torch.as_tensor(np.stack(cols, axis=1), device="cuda")))
         torch.cuda.synchronize()
         t0 = hsl.Server.clock()
-        ids, i, batches = [], 0, 0
+        ids, i, cycles = [], 0, 0
         while i < len(reqs) or srv.pending()[0]:
             now = hsl.Server.clock() - t0
             while i < len(reqs) and reqs[i][0] <= now:
-                ids.append(srv.submit(geos[reqs[i][1]][1], reqs[i][2], t0 + reqs[i][0]))
+                ids.append(srv.submit(reqs[i][1], reqs[i][2], t0 + reqs[i][0]))
                 i += 1
             if srv.pending()[0]:
-                cols = srv.step()
-                batches += 1
-                print(f"serve: rate {rate:g} batch {batches} columns {cols} at {hsl.Server.clock() - t0:.2f} s",
-                      file=sys.stderr, flush=True)
+                done = srv.step()
+                cycles += 1
+                print(f"serve: rate {rate:g} cycle {cycles} finished {done} columns at "
+                      f"{hsl.Server.clock() - t0:.2f} s", file=sys.stderr, flush=True)
             elif i < len(reqs):
                 time.sleep(max(0.0, reqs[i][0] - (hsl.Server.clock() - t0)))
         st = [srv.request(r) for r in ids]
-        lat = np.array([s["t_done"] - s["t_arrival"] for s in st])
-        ncol = sum(s["ncols"] for s in st)
-        span = max(s["t_done"] for s in st) - t0
-        out["rates"].append({"rate_per_s": rate, "requests": len(st), "columns": ncol, "batches": batches,
+        lat = np.array([q["t_done"] - q["t_arrival"] for q in st])
+        ncol = sum(q["ncols"] for q in st)
+        span = max(q["t_done"] for q in st) - t0
+        out["rates"].append({"rate_per_s": rate, "requests": len(st), "columns": ncol, "cycles": cycles,
                              "latency_p50_s": float(np.percentile(lat, 50)),
                              "latency_p99_s": float(np.percentile(lat, 99)),
-                             "rhs_per_s": ncol / span, "all_converged": all(s["converged"] for s in st),
-                             "max_relres": max(s["relres"] for s in st)})
+                             "rhs_per_s": ncol / span, "all_converged": all(q["converged"] for q in st),
+                             "max_relres": max(q["relres"] for q in st)})
     print(json.dumps(out), flush=True)
 
 
@@ -314,101 +359,120 @@ def committed_traffic():
     return out
 
 
-def cpu_baseline(wl, gpu_iters, budget_s):
-    """Time the oracle on a bounded sample of the same workload and scale each
-    phase to the full problem (the oracle itself is not tuned for this)."""
-    from oracle import aca as oaca
-    from oracle import gmres as ogm  # noqa: F401
-    from oracle import hmatrix as ohm
-    from oracle import kernel as okern
-    from oracle import ordering as oord
-    from oracle import schur as osch
-    from oracle import symbolic as osym
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    rng = np.random.default_rng(0)
+
+def cpu_baseline(wl, gpu_iters, solve_steps):
+    """The oracle as it stands on the host cores: its complete H-matrix build
+    and complete preconditioner setup on the same workload, then its GMRES
+    for a fixed number of steps (the complete per-step path: matvec,
+    P^-1 with D^-1, CGS2 Arnoldi, Givens), scaled per step to the GPU's
+    iteration count. Returns the RHS/s of build + setup + solve."""
+    from oracle import pipeline as opl
+
     t0 = time.perf_counter()
-    hm = ohm.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol, with_far=False)
-    t_near = time.perf_counter() - t0
-    far = hm.part.far
-    nfar = len(far)
-    # far ACA on a uniform random sample of blocks, scaled by the count
+    hm = opl.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol)
+    t_build = time.perf_counter() - t0
+    print(f"bench: oracle h_build {t_build:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    idx = rng.permutation(nfar)
-    done = 0
-    far_s = []
-    for b in idx:
-        t, s = far[b]
-        a0, a1 = hm.box_range(int(t))
-        b0, b1 = hm.box_range(int(s))
-        pt, ps = hm.pts[a0:a1], hm.pts[b0:b1]
-        U, V, _, _ = oaca.aca(lambda i: okern.kernel_row(pt[i], ps, wl.k),
-                              lambda j: okern.kernel_row(ps[j], pt, wl.k), a1 - a0, b1 - b0, wl.aca_tol)
-        U, V = oaca.recompress(U, V, wl.aca_tol)
-        far_s.append((b, U, V))
-        done += 1
-        if time.perf_counter() - t0 > 0.3 * budget_s:
-            break
-    t_far = (time.perf_counter() - t0) * nfar / done
-    # setup: ordering + symbolic in full, elimination over the leading steps (flop-weighted)
+    pc = opl.precond_setup(hm, "rcm", wl.fill_tol)
+    t_setup = time.perf_counter() - t0
+    print(f"bench: oracle precond_setup {t_setup:.1f} s", file=sys.stderr, flush=True)
+    k = max(1, min(solve_steps, gpu_iters))
     t0 = time.perf_counter()
-    order = oord.make_order("rcm", hm.tree.nb, hm.part.near)
-    sym = osym.symbolic(hm.tree.nb, hm.part.near, order)
-    t_sym = time.perf_counter() - t0
-    W, size = osch.initial_blocks(hm, sym)
-    b = size.astype(float)
-    flk = np.array([8 / 3 * b[k] ** 3 + sum(8 * b[k] ** 2 * b[j] for j in sym.rows[k])
-                    + 8 * b[k] * 0.5 * (sum(b[j] for j in sym.rows[k]) ** 2 + sum(b[j] ** 2 for j in sym.rows[k]))
-                    for k in range(sym.nb)])
-    import scipy.linalg as sla
-    t0 = time.perf_counter()
-    kdone = 0
-    for k in range(sym.nb):
-        lu = sla.lu_factor(W[(k, k)])
-        S = sym.rows[k]
-        al = {j: -sla.lu_solve(lu, W[(k, j)]) for j in S}
-        for a, i in enumerate(S):
-            WT = W[(k, i)].T
-            for j in S[a:]:
-                key = (i, j)
-                W[key] = W[key] + WT @ al[j]
-        kdone = k + 1
-        if time.perf_counter() - t0 > 0.3 * budget_s:
-            break
-    t_elim = (time.perf_counter() - t0) * flk.sum() / flk[:kdone].sum()
-    # solve: one near+far matvec (far part scaled from the sample) and a
-    # forward/backward sweep over the leading rows, per GMRES step
-    v = rng.normal(size=hm.n) + 1j * rng.normal(size=hm.n)
-    t0 = time.perf_counter()
-    ohm.near_matvec(hm, v)
-    t_nmv = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for bidx, U, V in far_s:
-        t, s = far[bidx]
-        a0, a1 = hm.box_range(int(t))
-        b0, b1 = hm.box_range(int(s))
-        _ = U @ (V @ v[b0:b1])
-        _ = V.T @ (U.T @ v[a0:a1])
-    t_fmv = (time.perf_counter() - t0) * nfar / max(len(far_s), 1)
-    # the sweeps read each alpha block twice; time the dense products of the rows done above
-    t0 = time.perf_counter()
-    nrows = max(1, kdone)
-    for k in range(nrows):
-        for j in sym.rows[k]:
-            A = W.get((k, j))
-            if A is not None:
-                _ = A.T @ v[:A.shape[0]]
-                _ = A @ v[:A.shape[1]]
-    t_sw = (time.perf_counter() - t0) * sym.nb / nrows
-    t_iter = t_nmv + t_fmv + t_sw
-    total = t_near + t_far + t_sym + t_elim + gpu_iters * t_iter
+    opl.solve(hm, pc, wl.rhs[:, 0], restart=wl.restart, fixed_iters=k)
+    t_steps = time.perf_counter() - t0
+    t_solve = t_steps * gpu_iters / k
+    print(f"bench: oracle {k} GMRES steps {t_steps:.1f} s", file=sys.stderr, flush=True)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    total = t_build + t_setup + t_solve
     return {
         "value": 1.0 / total, "unit": "RHS/s", "cores": threads, "kind": "oracle",
-        "sample": (f"oracle on the same workload: near field in full, ACA on {done}/{nfar} far blocks, "
-                   f"elimination over {kdone}/{sym.nb} steps (flop-weighted), one matvec + sweeps "
-                   f"per GMRES step x {gpu_iters} steps; each phase scaled to the full problem"),
-        "phase_s": {"h_build": t_near + t_far, "setup": t_sym + t_elim, "solve": gpu_iters * t_iter},
+        "sample": (f"oracle on the same workload: complete h_build and precond_setup; GMRES({wl.restart}) for {k} "
+                   f"complete steps, scaled to the GPU's {gpu_iters}; BLAS threads {threads} of "
+                   f"{os.cpu_count()} logical CPUs ({_cpu_model()})"),
+        "phase_s": {"h_build": t_build, "setup": t_setup, "solve": t_solve, "solve_steps_timed": k},
     }
+
+
+def leg_multi_rhs(hsl, torch, ctx, H, P, wl, ncols, plain_solve_s):
+    """ncols plane-wave columns of the same geometry in one multi-column
+    solve (every matrix read shared), against single-RHS plain solves."""
+    import workloads as W
+    rng = np.random.default_rng(77)
+    B = np.stack([W.plane_wave(wl.points, wl.k, rng) for _ in range(ncols)], axis=1)
+    b = torch.as_tensor(B, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = hsl.solve(ctx, H, P, b, restart=wl.restart, tol=wl.tol)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    rate = ncols / t
+    return {"columns": ncols, "solve_s": t, "rhs_per_s": rate, "vs_plain_fp64": rate * plain_solve_s,
+            "iters_max": max(q.iters for q in st), "all_converged": all(q.converged for q in st),
+            "dtype": "c128"}
+
+
+def leg_served(hsl, torch, ctx, H, P, wl, rate, seconds, slots, seed=50):
+    """Continuous batching on the resident geometry: Poisson arrivals of
+    requests with 1-4 columns (half plane waves, half port vectors), served
+    by one restart cycle per step with refills at cycle boundaries."""
+    import workloads as W
+    rng = np.random.default_rng(seed)
+    arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 3) + 8))
+    arr = arr[arr <= seconds]
+    reqs = []
+    for a in arr:
+        nc = int(rng.integers(1, 5))
+        cols = [W.plane_wave(wl.points, wl.k, rng) if rng.random() < 0.5 else W.port_vector(wl.n, rng)
+                for _ in range(nc)]
+        reqs.append((a, torch.as_tensor(np.stack(cols, axis=1), device="cuda")))
+    srv = hsl.Server(ctx, 1 << 40, slots=slots, restart=wl.restart, tol=wl.tol, max_iters=5000)
+    g = srv.admit(H, P)
+    torch.cuda.synchronize()
+    t0 = hsl.Server.clock()
+    ids, i, steps = [], 0, 0
+    while i < len(reqs) or srv.pending()[0]:
+        now = hsl.Server.clock() - t0
+        while i < len(reqs) and reqs[i][0] <= now:
+            ids.append(srv.submit(g, reqs[i][1], t0 + reqs[i][0]))
+            i += 1
+        if srv.pending()[0]:
+            srv.step()
+            steps += 1
+        elif i < len(reqs):
+            time.sleep(max(0.0, reqs[i][0] - (hsl.Server.clock() - t0)))
+    st = [srv.request(r) for r in ids]
+    lat = np.array([q["t_done"] - q["t_arrival"] for q in st])
+    ncol = sum(q["ncols"] for q in st)
+    span = max(q["t_done"] for q in st) - t0
+    return {"rate_per_s": rate, "arrival_window_s": seconds, "requests": len(st), "columns": ncol,
+            "slots": slots, "cycles": steps, "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)), "rhs_per_s": ncol / span,
+            "all_converged": all(q["converged"] for q in st), "max_relres": max(q["relres"] for q in st),
+            "dtype": "c128"}
+
+
+def leg_mixed(hsl, torch, ctx, pts, wl, b, plain_solve_s):
+    """The mixed path on the same workload: FP64 flexible GMRES whose
+    preconditioning steps are inner GMRES solves on complex64 copies."""
+    H = hsl.HMatrix(ctx, pts, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol, store_c64=True)
+    P = hsl.Precond(ctx, H, "rcm", wl.fill_tol, mixed=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = hsl.solve(ctx, H, P, b, restart=20, tol=wl.tol, mixed=True, inner_steps=20, inner_tol=1e-2)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return {"solve_s": t, "vs_plain_fp64": plain_solve_s / t, "outer_iters": st[0].iters,
+            "relres": st[0].relres, "converged": st[0].converged, "dtype": "c64 operator and preconditioner, FP64 outer"}
 
 
 def main():
@@ -459,8 +523,8 @@ def main():
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         if args.mixed:
-            x, st = hsl.solve(ctx, H, P, rhs if args.nrhs > 1 else rhs[:, 0], restart=20, tol=wl.tol, mixed=True,
-                              inner_steps=20, inner_tol=1e-2)
+            x, st = hsl.solve(ctx, H, P, rhs if args.nrhs > 1 else rhs[:, 0], restart=args.mixed_restart, tol=wl.tol,
+                              mixed=True, inner_steps=args.mixed_inner, inner_tol=1e-2)
         else:
             x, st = hsl.solve(ctx, H, P, rhs if args.nrhs > 1 else rhs[:, 0], restart=wl.restart, tol=wl.tol)
         torch.cuda.synchronize()
@@ -489,6 +553,7 @@ def main():
     nrhs = args.nrhs
     steps = args.steps
     lat = np.array([r["step"] for r in rec])
+    solve_s = float(np.median([r["solve"] for r in rec]))
     out = {
         "metric": "precond setup s + RHS solves/s at 1e-6 residual vs plain FP64; p50/p99 latency",
         "value": steps * nrhs / T,
@@ -496,50 +561,84 @@ def main():
         "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * T / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c128", "data": "synthetic",
-        "config": {"workload": f"{wl.name}: sphere+ellipsoid N={wl.n}, lambda=0.1, leaf<=64, ACA 1e-4, RCM, "
-                               f"fill 1e-2, {nrhs} plane-wave RHS, GMRES({wl.restart}) to 1e-6",
+        "dtype": "c64/f64" if args.mixed else "c128", "data": "synthetic",
+        "config": {"workload": (f"{wl.name}: sphere+ellipsoid N={wl.n}, lambda=0.1" if wl.name == "c2" else
+                                f"{wl.name}: N={wl.n}, lambda={2 * math.pi / wl.k:.3g}") +
+                               f", leaf<=64, ACA 1e-4, RCM, fill 1e-2, {nrhs} plane-wave RHS, "
+                               + (f"FGMRES({args.mixed_restart}) with inner GMRES({args.mixed_inner}) to 1e-6"
+                                  if args.mixed else f"GMRES({wl.restart}) to 1e-6"),
                    "n": wl.n, "nrhs": nrhs,
-                   "path": "mixed: FP64 FGMRES(20), inner GMRES(20) to 1e-2 on complex64 copies" if args.mixed
+                   "path": "mixed: FP64 FGMRES, inner GMRES to 1e-2 on complex64 copies" if args.mixed
                    else "plain FP64"},
         "precond_setup_s": float(np.median([r["setup"] for r in rec])),
         "h_build_s": float(np.median([r["h_build"] for r in rec])),
-        "solve_s": float(np.median([r["solve"] for r in rec])),
-        "solve_rhs_per_s": nrhs / float(np.median([r["solve"] for r in rec])),
+        "solve_s": solve_s,
+        "solve_rhs_per_s": nrhs / solve_s,
         "iters": rec[-1]["iters"], "relres": rec[-1]["relres"], "converged": rec[-1]["converged"],
-        "vs_plain_fp64": 1.0,
-        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
-        "hmatrix": {k: hinfo[k] for k in ("nb", "n_near", "n_far", "max_rank", "bytes_near", "bytes_far")},
+        "step_latency_p50_s": float(np.percentile(lat, 50)), "step_latency_p99_s": float(np.percentile(lat, 99)),
+        "hmatrix": {k: hinfo[k] for k in ("nb", "n_near", "n_far", "max_rank", "bytes_near", "bytes_far",
+                                          "bytes_device")},
         "precond": {k: pinfo[k] for k in ("n_pattern", "n_fill", "n_lowrank", "max_dk", "bytes_alpha", "bytes_d",
-                                          "flops_setup")},
+                                          "flops_setup", "bytes_device")},
     }
     # algorithmic HBM bytes per launch: each stored matrix byte the kernel
-    # needs is read once, plus one read and one write of its N x nrhs vectors
+    # needs is read once, plus one read and one write of its N x nrhs vectors;
+    # the mixed path reads the complex64 copies (half the matrix bytes)
+    mat = 0.5 if args.mixed else 1.0
     vec = 32 * wl.n * nrhs
-    alg = {"sweep_fwd": pinfo["bytes_alpha"] + vec,
-           "sweep_bwd": pinfo["bytes_alpha"] + pinfo["bytes_d"] + vec,
-           "near_mv": hinfo["bytes_near"] + vec,
-           "far_mv": hinfo["bytes_far"] + vec}
+    alg = {"sweep_fwd": mat * pinfo["bytes_alpha"] + vec,
+           "sweep_bwd": mat * (pinfo["bytes_alpha"] + pinfo["bytes_d"]) + vec,
+           "near_mv": mat * hinfo["bytes_near"] + vec,
+           "far_mv": mat * hinfo["bytes_far"] + vec}
     kern = {}
-    for name, (cnt, ms) in ktimes.items():
+    for name, (cnt, ms, allc) in ktimes.items():
         if cnt:
             avg = ms / cnt
-            kern[name] = {"launches": cnt, "avg_ms": avg, "alg_bytes": alg[name],
-                          "GB_per_s": alg[name] / (avg * 1e-3) / 1e9}
+            kern[name] = {"timed_launches": cnt, "all_launches": allc, "avg_ms": avg,
+                          "ms_per_step": avg * allc / steps}
+            if name in alg:
+                kern[name]["alg_bytes"] = alg[name]
+                kern[name]["GB_per_s"] = alg[name] / (avg * 1e-3) / 1e9
     # the near-field matvec runs on a second stream beside the far-field one:
     # its event time spans the concurrent far kernel, so it is reported but
     # not a candidate for the dominant kernel
     if "near_mv" in kern:
         kern["near_mv"]["overlaps"] = "far_mv"
-    dom = max((k for k in kern if "overlaps" not in kern[k]), key=lambda k: kern[k]["launches"] * kern[k]["avg_ms"])
+    dom = max((k for k in SOLVE_KERNELS if k in kern and "overlaps" not in kern[k]),
+              key=lambda k: kern[k]["ms_per_step"])
     traffic = committed_traffic()
     achieved = kern[dom]["GB_per_s"]
     out["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAME[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic.get(dom),
                        "alg_bytes_per_launch": alg[dom], "avg_launch_ms": kern[dom]["avg_ms"]}
+    # the setup's elimination against the FP64 peak: exact algorithmic flops
+    # of the filled pattern over the two elimination kernels' time per setup
+    if "factor" in kern and "schur" in kern:
+        t_elim = (kern["factor"]["ms_per_step"] + kern["schur"]["ms_per_step"]) * 1e-3
+        tf = pinfo["flops_setup"] / t_elim / 1e12
+        out["setup_roofline"] = {"bound": "fp64", "kernels": ["k_factor_alpha", "k_schur_tiles"],
+                                 "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": tf / FP64_PEAK_TFLOPS, "elimination_ms": t_elim * 1e3,
+                                 "flops": pinfo["flops_setup"],
+                                 "launches_per_setup": kern["factor"]["all_launches"] // steps}
     out["kernels"] = kern
+    # comparison legs on the same geometry (untimed by the step loop)
+    legs = {}
+    if not args.no_legs and not args.mixed and nrhs == 1:
+        print("bench: multi-RHS leg", file=sys.stderr, flush=True)
+        legs["multi_rhs_16"] = leg_multi_rhs(hsl, torch, ctx, H, P, wl, 16, solve_s)
+        print("bench: served leg", file=sys.stderr, flush=True)
+        legs["served"] = leg_served(hsl, torch, ctx, H, P, wl, args.serve_rate, args.serve_window, 16)
+        print("bench: mixed leg", file=sys.stderr, flush=True)
+        legs["mixed"] = leg_mixed(hsl, torch, ctx, pts, wl, rhs[:, 0], solve_s)
+        out["legs"] = legs
+        out["vs_plain_fp64"] = legs["served"]["rhs_per_s"] * solve_s
+        out["vs_plain_fp64_defn"] = ("served RHS solves/s (continuous batching, Poisson arrivals) over the plain FP64 "
+                                     "single-RHS solve rate on the same geometry")
+        out["latency_p50_s"] = legs["served"]["latency_p50_s"]
+        out["latency_p99_s"] = legs["served"]["latency_p99_s"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, rec[-1]["iters"], args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(wl, rec[-1]["iters"], args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -276,8 +276,9 @@ int32_t hs_matvec_noalloc(hs_context* ctx, const hs_hmatrix* H, const void* x, v
 
 /* ---- kernel timing (measurement) -------------------------------------------
  * Between hs_timing_begin and hs_timing_end every launch of the forward and
- * backward preconditioner sweeps (Eq. 23-24) and of the near and far matvec
- * kernels (Eq. 11) made through ctx is bracketed by a pair of HIP events on
+ * backward preconditioner sweeps (Eq. 23-24), of the near and far matvec
+ * kernels (Eq. 11) and of the two elimination kernels of the setup made
+ * through ctx is bracketed by a pair of HIP events on
  * the stream it runs on: ctx's stream, except the near matvec, which runs on
  * the library's second stream beside the far matvec (its time therefore
  * spans the concurrent far kernel). hs_timing_end synchronises ctx's stream
@@ -289,7 +290,9 @@ int32_t hs_matvec_noalloc(hs_context* ctx, const hs_hmatrix* H, const void* x, v
 #define HS_KT_SWEEP_BWD 1
 #define HS_KT_NEAR_MV   2
 #define HS_KT_FAR_MV    3
-#define HS_KT_COUNT     4
+#define HS_KT_FACTOR    4   /* elimination: leaf-block inversion and alpha panel tiles (Eq. 14, 19) */
+#define HS_KT_SCHUR     5   /* elimination: Schur-complement update tiles (Eq. 38-42) */
+#define HS_KT_COUNT     6
 typedef struct hs_kernel_times {
     int64_t launches[HS_KT_COUNT];      /* bracketed (timed) launches */
     double  total_ms[HS_KT_COUNT];      /* summed event time of the bracketed launches */

@@ -81,8 +81,8 @@ class SolveItem(ctypes.Structure):
 
 
 class KernelTimes(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4),
-                ("all_launches", ctypes.c_int64 * 4)]
+    _fields_ = [("launches", ctypes.c_int64 * 6), ("total_ms", ctypes.c_double * 6),
+                ("all_launches", ctypes.c_int64 * 6)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -160,7 +160,7 @@ EXPORTED = (
     "hs_server_destroy", "hs_status_string", "hs_last_error",
 )
 
-KT_NAMES = ("sweep_fwd", "sweep_bwd", "near_mv", "far_mv")
+KT_NAMES = ("sweep_fwd", "sweep_bwd", "near_mv", "far_mv", "factor", "schur")
 
 
 def _check(status: int, allow_not_converged: bool = False) -> int:

@@ -1831,29 +1831,50 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
         hs::PairStep* d_ps = tmp.upload(ps, s);
         hs::launch_pair_table(d_ps, (int64_t)ps.size(), j->d_err, s);
     }
-    // per step: factor/alpha tiles (one per 64 panel columns, at least one)
-    // and Schur tiles of every job
+    // Launch L takes, from every job, the steps that are the L-th of their
+    // connected component of the leaf graph. Components have separate
+    // elimination trees (every block of S_k is an ancestor of k), so their
+    // steps read and write disjoint blocks, while the steps of one component
+    // keep their order. Per launch: factor/alpha tiles (one per 64 panel
+    // columns, at least one) and Schur tiles.
+    std::vector<std::vector<std::pair<size_t, int64_t>>> launch;   // (job, step) per launch
+    for (size_t q = 0; q < jobs.size(); ++q) {
+        SetupJob* j = jobs[q];
+        const hs::Symbolic& sy = j->P->plan.sym;
+        // component of each step: that of its elimination-tree root
+        std::vector<int64_t> root(j->nb);
+        for (int64_t k = j->nb - 1; k >= 0; --k) root[k] = sy.parent[k] < 0 ? k : root[sy.parent[k]];
+        std::unordered_map<int64_t, int64_t> seen;
+        for (int64_t k = 0; k < j->nb; ++k) {
+            const int64_t L = seen[root[k]]++;
+            if ((int64_t)launch.size() <= L) launch.resize(L + 1);
+            launch[L].push_back({q, k});
+        }
+    }
+    const int64_t nl = (int64_t)launch.size();
     std::vector<hs::ElimTile> ft, st;
-    std::vector<int64_t> fp(steps + 1, 0), sp(steps + 1, 0);
-    for (int64_t k = 0; k < steps; ++k) {
-        for (size_t q = 0; q < jobs.size(); ++q) {
-            SetupJob* j = jobs[q];
-            if (k >= j->nb) continue;
-            const int32_t step = (int32_t)(base[q] + k);
+    std::vector<int64_t> fp(nl + 1, 0), sp(nl + 1, 0);
+    for (int64_t L = 0; L < nl; ++L) {
+        for (const auto& qk : launch[L]) {
+            SetupJob* j = jobs[qk.first];
+            const int64_t k = qk.second;
+            const int32_t step = (int32_t)(base[qk.first] + k);
             const int32_t nt = std::max<int32_t>(1, (j->panel_m[k] + 63) / 64);
             for (int32_t t = 0; t < nt; ++t) ft.push_back(hs::ElimTile{step, (int16_t)t, 0});
             for (int64_t t = j->tile_ptr[k]; t < j->tile_ptr[k + 1]; ++t)
                 st.push_back(hs::ElimTile{step, j->tiles[t].first, j->tiles[t].second});
         }
-        fp[k + 1] = (int64_t)ft.size();
-        sp[k + 1] = (int64_t)st.size();
+        fp[L + 1] = (int64_t)ft.size();
+        sp[L + 1] = (int64_t)st.size();
     }
+    (void)steps;
     hs::ElimStep* d_es = tmp.upload(es, s);
     hs::ElimTile* d_ft = tmp.upload(ft, s);
     hs::ElimTile* d_st = tmp.upload(st, s);
-    for (int64_t k = 0; k < steps; ++k) {
-        hs::launch_factor_alpha(d_es, d_ft + fp[k], fp[k + 1] - fp[k], s);
-        hs::launch_schur_tiles(d_es, d_st + sp[k], sp[k + 1] - sp[k], s);
+    hs_context* ctx = jobs.front()->ctx;
+    for (int64_t L = 0; L < nl; ++L) {
+        timed(ctx, HS_KT_FACTOR, s, [&] { hs::launch_factor_alpha(d_es, d_ft + fp[L], fp[L + 1] - fp[L], s); });
+        timed(ctx, HS_KT_SCHUR, s, [&] { hs::launch_schur_tiles(d_es, d_st + sp[L], sp[L + 1] - sp[L], s); });
     }
     hip_check(hipGetLastError(), "elimination launches");
     hip_check(hipStreamSynchronize(s), "stream sync");

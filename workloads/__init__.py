@@ -146,7 +146,8 @@ def make_config(name: str, n: int | None = None, nrhs: int = 1, seed: int | None
 
     * ``c1``: Fibonacci unit sphere, N=1200, lambda=0.5, leaf<=32, GMRES(30).
     * ``c2``: sphere + ellipsoid, N=20000, lambda=0.1, leaf<=64, GMRES(50).
-    * ``c3``: cube surface (edge 2), N=100000, lambda=0.05, leaf<=64.
+    * ``c3``: cube surface (edge 2), N=100000, lambda=0.05, leaf<=64, GMRES(100)
+      (GMRES(20) stagnates there; 50 takes 797 steps, 100 takes 341).
     * ``plate``: thin plate 2 x 2 x 0.05 with lambda = 10 h.
     ``n`` overrides the point count (the wavelength is kept) for scaled-down
     cases with the same structure.
@@ -167,7 +168,7 @@ def make_config(name: str, n: int | None = None, nrhs: int = 1, seed: int | None
         n = n or 100000
         rng = np.random.default_rng(3 if seed is None else seed)
         pts, area = cube_surface(n, rng)
-        lam, leaf, restart = 0.05, 64, 20
+        lam, leaf, restart = 0.05, 64, 100
     elif name == "plate":
         n = n or 5985
         rng = np.random.default_rng(6 if seed is None else seed)
@@ -187,12 +188,13 @@ def make_config(name: str, n: int | None = None, nrhs: int = 1, seed: int | None
 CONFIGS = ("c1", "c2", "c3", "plate")
 
 
-def batch_geometries(count: int = 64, n_max: int = 40000, seed: int = 4, nrhs: int = 4) -> list:
+def batch_geometries(count: int = 64, n_max: int = 40000, seed: int = 4, nrhs: int = 4, ppl: float = 3.2) -> list:
     """Many geometries for batched runs: the body is uniform over sphere,
     ellipsoid (axes 1, 0.6, 0.3), cube (edge 2) and plate box (2 x 2 x 0.05);
-    N uniform in [2000, n_max]; leaf_max uniform in [24, 96]; lambda = 10 h
-    (about ten points per wavelength); nrhs plane waves. Geometry i uses the
-    child seed 1000 * seed + i."""
+    N uniform in [2000, n_max]; leaf_max uniform in [24, 96]; lambda = ppl h
+    (ppl points per wavelength: 3.2 is the density of the 100,000-point cube
+    at lambda = 0.05); nrhs plane waves. Geometry i uses the child seed
+    1000 * seed + i."""
     out = []
     top = np.random.default_rng(seed)
     kinds = top.integers(0, 4, size=count)
@@ -211,7 +213,7 @@ def batch_geometries(count: int = 64, n_max: int = 40000, seed: int = 4, nrhs: i
         else:
             (pts, area), name = plate_box(n, rng), "plate"
         h = math.sqrt(area / n)
-        k = 2.0 * math.pi / (10.0 * h)
+        k = 2.0 * math.pi / (ppl * h)
         rhs = np.stack([plane_wave(pts, k, rng) for _ in range(nrhs)], axis=1)
         out.append(Workload(name=name, points=pts, k=k, self_h=h, leaf_max=int(leaves[i]), restart=30,
                             rhs=np.asfortranarray(rhs)))
