@@ -1872,9 +1872,10 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
     hs::ElimTile* d_ft = tmp.upload(ft, s);
     hs::ElimTile* d_st = tmp.upload(st, s);
     hs_context* ctx = jobs.front()->ctx;
+    const bool fp32 = jobs.front()->opts->precision == HS_PREC_MIXED;
     for (int64_t L = 0; L < nl; ++L) {
         timed(ctx, HS_KT_FACTOR, s, [&] { hs::launch_factor_alpha(d_es, d_ft + fp[L], fp[L + 1] - fp[L], s); });
-        timed(ctx, HS_KT_SCHUR, s, [&] { hs::launch_schur_tiles(d_es, d_st + sp[L], sp[L + 1] - sp[L], s); });
+        timed(ctx, HS_KT_SCHUR, s, [&] { hs::launch_schur_tiles(d_es, d_st + sp[L], sp[L + 1] - sp[L], fp32, s); });
     }
     hip_check(hipGetLastError(), "elimination launches");
     hip_check(hipStreamSynchronize(s), "stream sync");

@@ -82,6 +82,48 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 __device__ __forceinline__ cd wave_sum(cd v) { return cmk(wave_sum(v.x), wave_sum(v.y)); }
 
+// ---- complex64 arithmetic (the mixed path's copies compute in FP32) ----
+// Arith<T>: the type a kernel computes in for matrix storage T. complex128
+// storage computes in FP64; complex64 copies compute in FP32 with FP32
+// accumulation, their FP64 input vectors narrowed on load and the results
+// widened on store.
+template <class T> struct Arith;
+template <> struct Arith<cd> { typedef cd type; };
+template <> struct Arith<cf> { typedef cf type; };
+template <class T> using arith_t = typename Arith<T>::type;
+
+__device__ __forceinline__ cf cmkf(float r, float i) { cf z; z.x = r; z.y = i; return z; }
+template <class A> __device__ __forceinline__ A czero();
+template <> __device__ __forceinline__ cd czero<cd>() { return cmk(0.0, 0.0); }
+template <> __device__ __forceinline__ cf czero<cf>() { return cmkf(0.0f, 0.0f); }
+template <class A> __device__ __forceinline__ A to_arith(cd v);
+template <> __device__ __forceinline__ cd to_arith<cd>(cd v) { return v; }
+template <> __device__ __forceinline__ cf to_arith<cf>(cd v) { return cmkf((float)v.x, (float)v.y); }
+template <class A> __device__ __forceinline__ A to_arith(cf v);
+template <> __device__ __forceinline__ cf to_arith<cf>(cf v) { return v; }
+template <> __device__ __forceinline__ cd to_arith<cd>(cf v) { return to_cd(v); }
+__device__ __forceinline__ cf cadd(cf a, cf b) { return cmkf(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cf cmul(cf a, cf b) { return cmkf(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ cf cfma(cf b, cf c, cf a) {
+    return cmkf(fmaf(b.x, c.x, fmaf(-b.y, c.y, a.x)), fmaf(b.x, c.y, fmaf(b.y, c.x, a.y)));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float readlane_f32(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+// the same reduction order as the FP64 wave_sum
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_f32<0xB1>(v);
+    v += dpp_f32<0x4E>(v);
+    v += dpp_f32<0x124>(v);
+    v += dpp_f32<0x128>(v);
+    return (readlane_f32(v, 0) + readlane_f32(v, 16)) + (readlane_f32(v, 32) + readlane_f32(v, 48));
+}
+__device__ __forceinline__ cf wave_sum(cf v) { return cmkf(wave_sum(v.x), wave_sum(v.y)); }
+
 // Argmax with ties to the lowest index; key < 0 marks "no candidate".
 struct ArgMax { double v; int i; };
 __device__ __forceinline__ ArgMax amax_pick(ArgMax a, ArgMax b) {

@@ -159,7 +159,8 @@ struct PairStep {
 };
 void launch_pair_table(const PairStep* steps, int64_t nsteps, int* err, hipStream_t s);
 void launch_factor_alpha(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, hipStream_t s);
-void launch_schur_tiles(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, hipStream_t s);
+// fp32: the products in complex64 with FP32 accumulation (mixed-precision setups)
+void launch_schur_tiles(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, bool fp32, hipStream_t s);
 // Chunk products M = L C of the sweep plan, by 64 x 64 output tiles: one
 // entry per row of a chunk (A row at a_off, nonzero over chunk columns
 // [k0, k0 + kw), output row at c_off) and one per tile (chunk, first row,

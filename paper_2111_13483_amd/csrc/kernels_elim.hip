@@ -410,13 +410,17 @@ __global__ void __launch_bounds__(NTF) k_factor_alpha(const ElimStep* __restrict
 
 // One 64 x 64 tile (ti, tj) of C = W_kS^T alpha_kS (K = b_k), each element
 // (p, q) with block(p) <= block(q) added to its target block.
+// A = cd: FP64 products; A = cf (mixed-precision setups): the panel tiles
+// are rounded to complex64 and the product is formed and accumulated in
+// FP32, then added to the FP64 target once.
+template <class A>
 __global__ void __launch_bounds__(NT) k_schur_tiles(const ElimStep* __restrict__ steps,
                                                     const ElimTile* __restrict__ tiles) {
     const ElimTile tl = tiles[blockIdx.x];
     const ElimStep st = steps[tl.step];
     const int kk = st.bk, m = st.m, ne = st.ne;
-    __shared__ cd Xs[kKc][kTile];
-    __shared__ cd Ys[kKc][kTile];
+    __shared__ A Xs[kKc][kTile];
+    __shared__ A Ys[kKc][kTile];
     __shared__ int rblk[kTile], cblk[kTile];   // panel block of each tile row / column (-1 past the panel)
     __shared__ int rst[kTile], cst[kTile];     // its first panel column
     __shared__ int rbj[kTile], cbj[kTile];     // its width
@@ -479,11 +483,11 @@ __global__ void __launch_bounds__(NT) k_schur_tiles(const ElimStep* __restrict__
     const int64_t co = ca >= 0 ? (int64_t)kk * cst[c] + (gc + c - cst[c]) : 0;
     const int rb = rbj[c], cbw = cbj[c];
     // the product is accumulated from zero in ascending l and added once
-    cd prod[4][4];
+    A prod[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) prod[i][j] = cmk(0.0, 0.0);
+        for (int j = 0; j < 4; ++j) prod[i][j] = czero<A>();
     for (int k0 = 0; k0 < kk; k0 += kKc) {
         cd xv[SU], yv[SU];
 #pragma unroll
@@ -498,13 +502,13 @@ __global__ void __launch_bounds__(NT) k_schur_tiles(const ElimStep* __restrict__
         for (int u = 0; u < SU; ++u) {
             const int gl = k0 + l0 + 4 * u;
             const bool ok = gl < kk;
-            Xs[l0 + 4 * u][c] = (ok && ra >= 0) ? xv[u] : cmk(0.0, 0.0);
-            Ys[l0 + 4 * u][c] = (ok && ca >= 0) ? yv[u] : cmk(0.0, 0.0);
+            Xs[l0 + 4 * u][c] = (ok && ra >= 0) ? to_arith<A>(xv[u]) : czero<A>();
+            Ys[l0 + 4 * u][c] = (ok && ca >= 0) ? to_arith<A>(yv[u]) : czero<A>();
         }
         __syncthreads();
         const int lend = kk - k0 < kKc ? kk - k0 : kKc;
         for (int l = 0; l < lend; ++l) {
-            cd av[4], bv[4];
+            A av[4], bv[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) av[i] = Xs[l][ty * 4 + i];
 #pragma unroll
@@ -519,7 +523,7 @@ __global__ void __launch_bounds__(NT) k_schur_tiles(const ElimStep* __restrict__
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (live[i][j]) gst(st.w + dst[i][j], cadd(acc[i][j], prod[i][j]));
+            if (live[i][j]) gst(st.w + dst[i][j], cadd(acc[i][j], to_cd(prod[i][j])));
 }
 
 void launch_pair_table(const PairStep* steps, int64_t nsteps, int* err, hipStream_t s) {
@@ -530,8 +534,10 @@ void launch_factor_alpha(const ElimStep* steps, const ElimTile* tiles, int64_t n
     if (ntiles > 0) hipLaunchKernelGGL(k_factor_alpha, dim3((unsigned)ntiles), dim3(NTF), 0, s, steps, tiles);
 }
 
-void launch_schur_tiles(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, hipStream_t s) {
-    if (ntiles > 0) hipLaunchKernelGGL(k_schur_tiles, dim3((unsigned)ntiles), dim3(NT), 0, s, steps, tiles);
+void launch_schur_tiles(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, bool fp32, hipStream_t s) {
+    if (ntiles <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_schur_tiles<cf>, dim3((unsigned)ntiles), dim3(NT), 0, s, steps, tiles);
+    else hipLaunchKernelGGL(k_schur_tiles<cd>, dim3((unsigned)ntiles), dim3(NT), 0, s, steps, tiles);
 }
 
 }  // namespace hs

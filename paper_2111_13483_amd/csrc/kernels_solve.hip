@@ -36,9 +36,10 @@ template <int S, class T>
 __global__ void __launch_bounds__(NT)
 k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restrict__ slot_base, const T* __restrict__ Z,
           const cd* __restrict__ x, int64_t n, int nrhs, cd* __restrict__ slots) {
+    using A = arith_t<T>;
     constexpr int RU = 4;
-    __shared__ cd xi[kMaxLeaf * S], xj[kMaxLeaf * S];
-    __shared__ cd colp[NW][kMaxLeaf * S];
+    __shared__ A xi[kMaxLeaf * S], xj[kMaxLeaf * S];
+    __shared__ A colp[NW][kMaxLeaf * S];
     const NearTask t = tasks[blockIdx.x];
     const int m = t.m, nn = t.n;
     const bool diag = t.i0 == t.j0;
@@ -50,29 +51,29 @@ k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restr
         const int cs = min(S, nrhs - c0);
         if (!cols_live(mk, c0, cs)) continue;
         __syncthreads();
-        for (int e = tid; e < m * cs; e += NT) xi[e] = x[t.i0 + e % m + (int64_t)(c0 + e / m) * n];
-        for (int e = tid; e < nn * cs; e += NT) xj[e] = x[t.j0 + e % nn + (int64_t)(c0 + e / nn) * n];
+        for (int e = tid; e < m * cs; e += NT) xi[e] = to_arith<A>(x[t.i0 + e % m + (int64_t)(c0 + e / m) * n]);
+        for (int e = tid; e < nn * cs; e += NT) xj[e] = to_arith<A>(x[t.j0 + e % nn + (int64_t)(c0 + e / nn) * n]);
         __syncthreads();
-        cd cacc[2][S];
+        A cacc[2][S];
 #pragma unroll
         for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int c = 0; c < S; ++c) cacc[q][c] = cmk(0.0, 0.0);
+            for (int c = 0; c < S; ++c) cacc[q][c] = czero<A>();
         for (int a0 = wid; a0 < m; a0 += NW * RU) {
-            cd z[RU][2];
+            A z[RU][2];
 #pragma unroll
             for (int u = 0; u < RU; ++u)
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     const int a = a0 + u * NW, b = lane + q * kWave;
-                    z[u][q] = (a < m && b < nn) ? to_cd(blk[(int64_t)a * nn + b]) : cmk(0.0, 0.0);
+                    z[u][q] = (a < m && b < nn) ? to_arith<A>(blk[(int64_t)a * nn + b]) : czero<A>();
                 }
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
                 const int a = a0 + u * NW;
-                cd racc[S];
+                A racc[S];
 #pragma unroll
-                for (int c = 0; c < S; ++c) racc[c] = cmk(0.0, 0.0);
+                for (int c = 0; c < S; ++c) racc[c] = czero<A>();
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     const int b = lane + q * kWave;
@@ -87,8 +88,8 @@ k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restr
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
                     if (c < cs) {
-                        const cd r = wave_sum(racc[c]);
-                        if (lane == 0 && a < m) s1[a + (int64_t)(c0 + c) * m] = r;
+                        const A r = wave_sum(racc[c]);
+                        if (lane == 0 && a < m) s1[a + (int64_t)(c0 + c) * m] = to_cd(r);
                     }
                 }
             }
@@ -104,10 +105,10 @@ k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restr
             }
             __syncthreads();
             for (int e = tid; e < nn * cs; e += NT) {
-                cd sum = colp[0][e];
+                A sum = colp[0][e];
 #pragma unroll
                 for (int w = 1; w < NW; ++w) sum = cadd(sum, colp[w][e]);
-                s2[e % nn + (int64_t)(c0 + e / nn) * nn] = sum;
+                s2[e % nn + (int64_t)(c0 + e / nn) * nn] = to_cd(sum);
             }
         }
     }
@@ -124,35 +125,36 @@ k_near_mv(ColMask mk, const NearTask* __restrict__ tasks, const int64_t* __restr
 template <int S, class T>
 __device__ __forceinline__ void far_wave(const ColMask& mk, const AcaTask& g, int r, const T* U, cd* st, const cd* x,
                                          int64_t n, int nrhs) {
+    using A = arith_t<T>;
     constexpr int RS = kFarWaveRank;
     const int lane = threadIdx.x % kWave;
     const int m = g.m, nn = g.n;
     cd* ss = st + (int64_t)m * nrhs;
     const T* V = U + (int64_t)m * r;
-    cd u[RS], v[RS];
+    A u[RS], v[RS];
 #pragma unroll
     for (int l = 0; l < RS; ++l) {
-        u[l] = (l < r && lane < m) ? to_cd(U[lane + (int64_t)l * m]) : cmk(0.0, 0.0);
-        v[l] = (l < r && lane < nn) ? to_cd(V[(int64_t)l * nn + lane]) : cmk(0.0, 0.0);
+        u[l] = (l < r && lane < m) ? to_arith<A>(U[lane + (int64_t)l * m]) : czero<A>();
+        v[l] = (l < r && lane < nn) ? to_arith<A>(V[(int64_t)l * nn + lane]) : czero<A>();
     }
     for (int c0 = 0; c0 < nrhs; c0 += S) {
         const int cs = min(S, nrhs - c0);
         if (!cols_live(mk, c0, cs)) continue;
-        cd xs[S], xt[S], ot[S], os[S];
+        A xs[S], xt[S], ot[S], os[S];
 #pragma unroll
         for (int c = 0; c < S; ++c) {
-            xs[c] = (c < cs && lane < nn) ? x[g.s0 + lane + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
-            xt[c] = (c < cs && lane < m) ? x[g.t0 + lane + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
-            ot[c] = cmk(0.0, 0.0);
-            os[c] = cmk(0.0, 0.0);
+            xs[c] = (c < cs && lane < nn) ? to_arith<A>(x[g.s0 + lane + (int64_t)(c0 + c) * n]) : czero<A>();
+            xt[c] = (c < cs && lane < m) ? to_arith<A>(x[g.t0 + lane + (int64_t)(c0 + c) * n]) : czero<A>();
+            ot[c] = czero<A>();
+            os[c] = czero<A>();
         }
 #pragma unroll
         for (int l = 0; l < RS; ++l) {
             if (l < r) {
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
-                    const cd t1 = wave_sum(cmul(v[l], xs[c]));
-                    const cd t2 = wave_sum(cmul(u[l], xt[c]));
+                    const A t1 = wave_sum(cmul(v[l], xs[c]));
+                    const A t2 = wave_sum(cmul(u[l], xt[c]));
                     ot[c] = cfma(u[l], t1, ot[c]);
                     os[c] = cfma(v[l], t2, os[c]);
                 }
@@ -161,8 +163,8 @@ __device__ __forceinline__ void far_wave(const ColMask& mk, const AcaTask& g, in
 #pragma unroll
         for (int c = 0; c < S; ++c) {
             if (c < cs) {
-                if (lane < m) st[lane + (int64_t)(c0 + c) * m] = ot[c];
-                if (lane < nn) ss[lane + (int64_t)(c0 + c) * nn] = os[c];
+                if (lane < m) st[lane + (int64_t)(c0 + c) * m] = to_cd(ot[c]);
+                if (lane < nn) ss[lane + (int64_t)(c0 + c) * nn] = to_cd(os[c]);
             }
         }
     }
@@ -188,9 +190,9 @@ k_far_wave(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__
 //                                                RB x 64 rows; per-wave partial
 //                                                tB summed in wave order)
 //   outA[j] = sum_l A(j, l) tB[l]               (one thread per row)
-template <class T, int RU, int JU, int LG>
-__device__ __forceinline__ void far_wg_once(const AcaTask& g, int r, const T* U, const cd* x, cd* st, cd* tA, cd* tB,
-                                            cd (*tp)[kMaxRankCap]) {
+template <class T, int RU, int JU, int LG, class A = arith_t<T>>
+__device__ __forceinline__ void far_wg_once(const AcaTask& g, int r, const T* U, const cd* x, cd* st, A* tA, A* tB,
+                                            A (*tp)[kMaxRankCap]) {
     constexpr int RB = 4, LB = 2;
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int m = g.m, nn = g.n;
@@ -205,19 +207,19 @@ __device__ __forceinline__ void far_wg_once(const AcaTask& g, int r, const T* U,
     cd* outB = ubig ? st : st + m;
     // tA: rows of A^T, JU column groups per step
     for (int l0 = wid; l0 < r; l0 += NW * RU) {
-        cd acc[RU];
+        A acc[RU];
 #pragma unroll
-        for (int u = 0; u < RU; ++u) acc[u] = cmk(0.0, 0.0);
+        for (int u = 0; u < RU; ++u) acc[u] = czero<A>();
         for (int j0 = 0; j0 < lenA; j0 += JU * kWave) {
-            cd val[JU][RU], xv[JU];
+            A val[JU][RU], xv[JU];
 #pragma unroll
             for (int jj = 0; jj < JU; ++jj) {
                 const int j = j0 + jj * kWave + lane;
-                xv[jj] = j < lenA ? xA[j] : cmk(0.0, 0.0);
+                xv[jj] = j < lenA ? to_arith<A>(xA[j]) : czero<A>();
 #pragma unroll
                 for (int u = 0; u < RU; ++u) {
                     const int l = l0 + u * NW;
-                    val[jj][u] = (l < r && j < lenA) ? to_cd(Ab[(int64_t)l * lenA + j]) : cmk(0.0, 0.0);
+                    val[jj][u] = (l < r && j < lenA) ? to_arith<A>(Ab[(int64_t)l * lenA + j]) : czero<A>();
                 }
             }
 #pragma unroll
@@ -228,35 +230,35 @@ __device__ __forceinline__ void far_wg_once(const AcaTask& g, int r, const T* U,
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int l = l0 + u * NW;
-            const cd sum = wave_sum(acc[u]);
+            const A sum = wave_sum(acc[u]);
             if (lane == 0 && l < r) tA[l] = sum;
         }
     }
-    for (int l = lane; l < r; l += kWave) tp[wid][l] = cmk(0.0, 0.0);
+    for (int l = lane; l < r; l += kWave) tp[wid][l] = czero<A>();
     __syncthreads();
     // B once: its output rows and the per-wave partials of tB
     for (int i0 = wid * kWave * RB; i0 < lenB; i0 += NW * kWave * RB) {
-        cd xi[RB], o[RB];
+        A xi[RB], o[RB];
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
             const int i = i0 + k * kWave + lane;
-            xi[k] = i < lenB ? xB[i] : cmk(0.0, 0.0);
-            o[k] = cmk(0.0, 0.0);
+            xi[k] = i < lenB ? to_arith<A>(xB[i]) : czero<A>();
+            o[k] = czero<A>();
         }
         for (int l0 = 0; l0 < r; l0 += LB) {
-            cd bv[LB][RB];
+            A bv[LB][RB];
 #pragma unroll
             for (int u = 0; u < LB; ++u)
 #pragma unroll
                 for (int k = 0; k < RB; ++k) {
                     const int i = i0 + k * kWave + lane;
-                    bv[u][k] = (l0 + u < r && i < lenB) ? to_cd(Bb[i + (int64_t)(l0 + u) * lenB]) : cmk(0.0, 0.0);
+                    bv[u][k] = (l0 + u < r && i < lenB) ? to_arith<A>(Bb[i + (int64_t)(l0 + u) * lenB]) : czero<A>();
                 }
 #pragma unroll
             for (int u = 0; u < LB; ++u) {
                 if (l0 + u < r) {
-                    const cd ta = tA[l0 + u];
-                    cd p = cmul(bv[u][0], xi[0]);
+                    const A ta = tA[l0 + u];
+                    A p = cmul(bv[u][0], xi[0]);
 #pragma unroll
                     for (int k = 1; k < RB; ++k) p = cfma(bv[u][k], xi[k], p);
 #pragma unroll
@@ -269,12 +271,12 @@ __device__ __forceinline__ void far_wg_once(const AcaTask& g, int r, const T* U,
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
             const int i = i0 + k * kWave + lane;
-            if (i < lenB) outB[i] = o[k];
+            if (i < lenB) outB[i] = to_cd(o[k]);
         }
     }
     __syncthreads();
     for (int l = tid; l < r + LG; l += NT) {
-        cd sum = cmk(0.0, 0.0);
+        A sum = czero<A>();
         if (l < r) {
             sum = tp[0][l];
 #pragma unroll
@@ -285,15 +287,15 @@ __device__ __forceinline__ void far_wg_once(const AcaTask& g, int r, const T* U,
     __syncthreads();
     // A's output rows, LG rank terms' loads issued together
     for (int j = tid; j < lenA; j += NT) {
-        cd acc = cmk(0.0, 0.0);
+        A acc = czero<A>();
         for (int l0 = 0; l0 < r; l0 += LG) {
-            cd av[LG];
+            A av[LG];
 #pragma unroll
-            for (int u = 0; u < LG; ++u) av[u] = (l0 + u < r) ? to_cd(Ab[j + (int64_t)(l0 + u) * lenA]) : cmk(0.0, 0.0);
+            for (int u = 0; u < LG; ++u) av[u] = (l0 + u < r) ? to_arith<A>(Ab[j + (int64_t)(l0 + u) * lenA]) : czero<A>();
 #pragma unroll
             for (int u = 0; u < LG; ++u) acc = cfma(av[u], tB[l0 + u], acc);
         }
-        outA[j] = acc;
+        outA[j] = to_cd(acc);
     }
 }
 
@@ -309,10 +311,11 @@ __global__ void __launch_bounds__(NT)
 k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ rank, T* const* __restrict__ uv,
          const int64_t* __restrict__ slot_base, const cd* __restrict__ x, int64_t n, int nrhs,
          cd* __restrict__ slots) {
+    using A = arith_t<T>;
     // one column: two column groups per step; sized for 5 waves per SIMD
     constexpr int RU = 4, JU = S == 1 ? 2 : 1, LG = 8;
-    __shared__ cd t12[2 * (kMaxRankCap + LG) * S];
-    __shared__ cd tpart[S == 1 ? NW : 1][kMaxRankCap];
+    __shared__ A t12[2 * (kMaxRankCap + LG) * S];
+    __shared__ A tpart[S == 1 ? NW : 1][kMaxRankCap];
     const AcaTask g = geom[blockIdx.x];
     const int m = g.m, nn = g.n, r = rank[blockIdx.x];
     if (r == 0) {
@@ -336,22 +339,22 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
         if (!cols_live(mk, c0, cs)) continue;
         __syncthreads();
         for (int l0 = wid; l0 < 2 * r; l0 += NW * RU) {
-            cd acc[RU][S];
+            A acc[RU][S];
 #pragma unroll
             for (int u = 0; u < RU; ++u)
 #pragma unroll
-                for (int c = 0; c < S; ++c) acc[u][c] = cmk(0.0, 0.0);
+                for (int c = 0; c < S; ++c) acc[u][c] = czero<A>();
             // JU column groups per step; x_s and x_t are read once per group
             // and shared by the rows (entries past a row's end are zero)
             for (int j0 = 0; j0 < len_max; j0 += JU * kWave) {
-                cd val[JU][RU], xsv[JU][S], xtv[JU][S];
+                A val[JU][RU], xsv[JU][S], xtv[JU][S];
 #pragma unroll
                 for (int jj = 0; jj < JU; ++jj) {
                     const int j = j0 + jj * kWave + lane;
 #pragma unroll
                     for (int c = 0; c < S; ++c) {
-                        xsv[jj][c] = (c < cs && j < nn) ? x[g.s0 + j + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
-                        xtv[jj][c] = (c < cs && j < m) ? x[g.t0 + j + (int64_t)(c0 + c) * n] : cmk(0.0, 0.0);
+                        xsv[jj][c] = (c < cs && j < nn) ? to_arith<A>(x[g.s0 + j + (int64_t)(c0 + c) * n]) : czero<A>();
+                        xtv[jj][c] = (c < cs && j < m) ? to_arith<A>(x[g.t0 + j + (int64_t)(c0 + c) * n]) : czero<A>();
                     }
 #pragma unroll
                     for (int u = 0; u < RU; ++u) {
@@ -359,7 +362,7 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
                         const bool isv = l < r;
                         const int len = isv ? nn : m;
                         const T* row = isv ? V + (int64_t)l * nn : U + (int64_t)(l - r) * m;
-                        val[jj][u] = (l < 2 * r && j < len) ? to_cd(row[j]) : cmk(0.0, 0.0);
+                        val[jj][u] = (l < 2 * r && j < len) ? to_arith<A>(row[j]) : czero<A>();
                     }
                 }
 #pragma unroll
@@ -377,15 +380,15 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
                 const int l = l0 + u * NW;
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
-                    const cd sum = wave_sum(acc[u][c]);
+                    const A sum = wave_sum(acc[u][c]);
                     if (lane == 0 && l < 2 * r) t12[((l < r) ? l : rp + (l - r)) * S + c] = sum;
                 }
             }
         }
         // zero padding so the grouped loads below read finite values
         if (tid < LG * S) {
-            t12[r * S + tid] = cmk(0.0, 0.0);
-            t12[(rp + r) * S + tid] = cmk(0.0, 0.0);
+            t12[r * S + tid] = czero<A>();
+            t12[(rp + r) * S + tid] = czero<A>();
         }
         __syncthreads();
         for (int e = tid; e < m + nn; e += NT) {
@@ -393,14 +396,14 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
             const int idx = top ? e : e - m;
             const int ld = top ? m : nn;
             const T* base = (top ? U : V) + idx;
-            const cd* tv = t12 + (top ? 0 : rp) * S;
-            cd acc[S];
+            const A* tv = t12 + (top ? 0 : rp) * S;
+            A acc[S];
 #pragma unroll
-            for (int c = 0; c < S; ++c) acc[c] = cmk(0.0, 0.0);
+            for (int c = 0; c < S; ++c) acc[c] = czero<A>();
             for (int l0 = 0; l0 < r; l0 += LG) {
-                cd bv[LG];
+                A bv[LG];
 #pragma unroll
-                for (int u = 0; u < LG; ++u) bv[u] = (l0 + u < r) ? to_cd(base[(int64_t)(l0 + u) * ld]) : cmk(0.0, 0.0);
+                for (int u = 0; u < LG; ++u) bv[u] = (l0 + u < r) ? to_arith<A>(base[(int64_t)(l0 + u) * ld]) : czero<A>();
 #pragma unroll
                 for (int u = 0; u < LG; ++u)
 #pragma unroll
@@ -409,7 +412,7 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
             cd* out = top ? st : ss;
 #pragma unroll
             for (int c = 0; c < S; ++c)
-                if (c < cs) out[idx + (int64_t)(c0 + c) * ld] = acc[c];
+                if (c < cs) out[idx + (int64_t)(c0 + c) * ld] = to_cd(acc[c]);
         }
     }
 }

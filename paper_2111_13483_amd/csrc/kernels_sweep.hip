@@ -234,6 +234,10 @@ __device__ __forceinline__ void stage_direct(cd* x1, int ld1, const cd* g1, int 
 __device__ __forceinline__ cd bcast_cd(cd v, int src) {
     return cmk(readlane_f64(v.x, src), readlane_f64(v.y, src));
 }
+__device__ __forceinline__ cd bcast_a(cd v, int src) { return bcast_cd(v, src); }
+__device__ __forceinline__ cf bcast_a(cf v, int src) {
+    return cmkf(readlane_f32(v.x, src), readlane_f32(v.y, src));
+}
 
 __device__ __forceinline__ int take_ticket(unsigned long long* ctr, unsigned long long base, int* s_t) {
     __syncthreads();
@@ -277,18 +281,18 @@ constexpr int QF = kFoldCols / kWave;   // column groups of the folded neighbour
 // inputs: load_row reads A1 (width w1 <= kMaxChunk) and A2 (width w2 <=
 // kFoldCols) into registers; row_partial multiplies them with the LDS
 // copies of x1 and x2, a column range at a time.
-template <class T>
-__device__ __forceinline__ void load_row(const T* A1, int w1, const T* A2, int w2, cd (&R1)[QC], cd (&R2)[QF]) {
+template <class T, class A>
+__device__ __forceinline__ void load_row(const T* A1, int w1, const T* A2, int w2, A (&R1)[QC], A (&R2)[QF]) {
     const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int q = 0; q < QC; ++q) {
         const int col = lane + q * kWave;
-        R1[q] = col < w1 ? to_cd(A1[col]) : cmk(0.0, 0.0);
+        R1[q] = col < w1 ? to_arith<A>(A1[col]) : czero<A>();
     }
 #pragma unroll
     for (int q = 0; q < QF; ++q) {
         const int col = lane + q * kWave;
-        R2[q] = col < w2 ? to_cd(A2[col]) : cmk(0.0, 0.0);
+        R2[q] = col < w2 ? to_arith<A>(A2[col]) : czero<A>();
     }
 }
 
@@ -302,32 +306,32 @@ __device__ __forceinline__ void load_row(const T* A1, int w1, const T* A2, int w
 // use one base address with immediate offsets and go out XG at a time; the
 // exact zeros added leave the sums unchanged. With more columns the
 // registers are not there for that, and each group is a guarded read.
-template <int S>
-__device__ __forceinline__ void row_partial(const cd (&R1)[QC], int w1, const cd* xs1, int o1, int ld1,
-                                            const cd (&R2)[QF], int lo, int hi, const cd* xs2, int ld2, int cs,
-                                            cd (&acc)[S]) {
+template <int S, class A>
+__device__ __forceinline__ void row_partial(const A (&R1)[QC], int w1, const cd* xs1, int o1, int ld1,
+                                            const A (&R2)[QF], int lo, int hi, const cd* xs2, int ld2, int cs,
+                                            A (&acc)[S]) {
     const int lane = threadIdx.x % kWave;
-    const cd zero = cmk(0.0, 0.0);
+    const A zero = czero<A>();
 #pragma unroll
     for (int c = 0; c < S; ++c) {
         if (c < cs) {
             // two interleaved partial sums (even and odd column groups) halve
             // the dependent FMA chain; they are added in a fixed order
-            cd a[2] = {zero, zero};
+            A a[2] = {zero, zero};
             if constexpr (S == 1) {
 #pragma unroll
                 for (int q = 0; q < QC; ++q) {
                     const int col = lane + q * kWave;
-                    const cd xv = xs1[o1 + col];
+                    const A xv = to_arith<A>(xs1[o1 + col]);
                     a[q & 1] = cfma(R1[q], col < w1 ? xv : zero, a[q & 1]);
                 }
                 constexpr int XG = 8;
                 static_assert(QF % XG == 0, "whole read groups");
 #pragma unroll
                 for (int q0 = 0; q0 < QF; q0 += XG) {
-                    cd xv[XG];
+                    A xv[XG];
 #pragma unroll
-                    for (int g = 0; g < XG; ++g) xv[g] = xs2[lane + (q0 + g) * kWave];
+                    for (int g = 0; g < XG; ++g) xv[g] = to_arith<A>(xs2[lane + (q0 + g) * kWave]);
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int g = 0; g < XG; ++g) {
@@ -339,12 +343,12 @@ __device__ __forceinline__ void row_partial(const cd (&R1)[QC], int w1, const cd
 #pragma unroll
                 for (int q = 0; q < QC; ++q) {
                     const int col = lane + q * kWave;
-                    if (col < w1) a[q & 1] = cfma(R1[q], xs1[o1 + col + c * ld1], a[q & 1]);
+                    if (col < w1) a[q & 1] = cfma(R1[q], to_arith<A>(xs1[o1 + col + c * ld1]), a[q & 1]);
                 }
 #pragma unroll
                 for (int q = 0; q < QF; ++q) {
                     const int col = lane + q * kWave;
-                    if (col >= lo && col < hi) a[q & 1] = cfma(R2[q], xs2[col + c * ld2], a[q & 1]);
+                    if (col >= lo && col < hi) a[q & 1] = cfma(R2[q], to_arith<A>(xs2[col + c * ld2]), a[q & 1]);
                 }
             }
             acc[c] = cadd(acc[c], cadd(a[0], a[1]));
@@ -352,10 +356,10 @@ __device__ __forceinline__ void row_partial(const cd (&R1)[QC], int w1, const cd
     }
 }
 
-template <int S>
-__device__ __forceinline__ void row_head(const cd (&R2)[QF], int hi, const cd* xs2, int ld2, int cs, cd (&acc)[S]) {
+template <int S, class A>
+__device__ __forceinline__ void row_head(const A (&R2)[QF], int hi, const cd* xs2, int ld2, int cs, A (&acc)[S]) {
     const int lane = threadIdx.x % kWave;
-    const cd zero = cmk(0.0, 0.0);
+    const A zero = czero<A>();
 #pragma unroll
     for (int c = 0; c < S; ++c) {
         if (c < cs) {
@@ -363,10 +367,10 @@ __device__ __forceinline__ void row_head(const cd (&R2)[QF], int hi, const cd* x
             for (int q = 0; q < QC; ++q) {
                 const int col = lane + q * kWave;
                 if constexpr (S == 1) {
-                    const cd xv = xs2[col];
+                    const A xv = to_arith<A>(xs2[col]);
                     acc[c] = cfma(R2[q], col < hi ? xv : zero, acc[c]);
                 } else {
-                    if (col < hi) acc[c] = cfma(R2[q], xs2[col + c * ld2], acc[c]);
+                    if (col < hi) acc[c] = cfma(R2[q], to_arith<A>(xs2[col + c * ld2]), acc[c]);
                 }
             }
         }
@@ -382,28 +386,29 @@ __device__ __forceinline__ void row_head(const cd (&R2)[QF], int hi, const cd* x
 template <int S, bool FWD, int Q, class T>
 __device__ __forceinline__ void push_one(const PushEnt& e, const T* alpha, const cd* src, int64_t so, int bo, int bt,
                                          int64_t n, int c0, int cs, cd* slot) {
+    using A = arith_t<T>;
     const int lane = threadIdx.x % kWave;
-    cd x[Q][S], acc[Q][S];
+    A x[Q][S], acc[Q][S];
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int c = 0; c < S; ++c) {
             const int a = lane + q * kWave;
-            x[q][c] = (a < bo && c < cs) ? ld_sc(src + so + a + (int64_t)(c0 + c) * n) : cmk(0.0, 0.0);
-            acc[q][c] = cmk(0.0, 0.0);
+            x[q][c] = (a < bo && c < cs) ? to_arith<A>(ld_sc(src + so + a + (int64_t)(c0 + c) * n)) : czero<A>();
+            acc[q][c] = czero<A>();
         }
     const int rows = FWD ? bo : bt, cols = FWD ? bt : bo;
-    const T* A = alpha + e.aoff;
+    const T* A_ = alpha + e.aoff;
     if (e.rank < 0) {
         constexpr int RQ = rb_of<Q>();
         for (int a0 = 0; a0 < rows; a0 += RQ) {
-            cd Ar[RQ][Q];
+            A Ar[RQ][Q];
 #pragma unroll
             for (int r = 0; r < RQ; ++r)
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     const int b = lane + q * kWave;
-                    Ar[r][q] = (a0 + r < rows && b < cols) ? to_cd(A[(int64_t)(a0 + r) * cols + b]) : cmk(0.0, 0.0);
+                    Ar[r][q] = (a0 + r < rows && b < cols) ? to_arith<A>(A_[(int64_t)(a0 + r) * cols + b]) : czero<A>();
                 }
 #pragma unroll
             for (int r = 0; r < RQ; ++r) {
@@ -412,11 +417,11 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const T* alpha, const
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
                     if (FWD) {
-                        const cd xa = bcast_cd(a < kWave ? x[0][c] : x[Q - 1][c], a % kWave);
+                        const A xa = bcast_a(a < kWave ? x[0][c] : x[Q - 1][c], a % kWave);
 #pragma unroll
                         for (int q = 0; q < Q; ++q) acc[q][c] = cfma(Ar[r][q], xa, acc[q][c]);
                     } else {
-                        cd sr = cmul(Ar[r][0], x[0][c]);
+                        A sr = cmul(Ar[r][0], x[0][c]);
                         if (Q > 1) sr = cfma(Ar[r][Q - 1], x[Q - 1][c], sr);
                         sr = wave_sum(sr);
                         if (lane == a % kWave) {
@@ -429,19 +434,19 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const T* alpha, const
         }
     } else {
         const int rk = e.rank;
-        const T* Uf = A;
-        const T* Vf = A + (int64_t)rows * rk;
+        const T* Uf = A_;
+        const T* Vf = A_ + (int64_t)rows * rk;
         constexpr int RQ = rb_of<Q>();
         for (int l0 = 0; l0 < rk; l0 += RQ) {
-            cd Ur[RQ][Q], Vr[RQ][Q];
+            A Ur[RQ][Q], Vr[RQ][Q];
 #pragma unroll
             for (int r = 0; r < RQ; ++r)
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     const int xx = lane + q * kWave;
                     const bool on = l0 + r < rk;
-                    Ur[r][q] = (on && xx < rows) ? to_cd(Uf[(int64_t)(l0 + r) * rows + xx]) : cmk(0.0, 0.0);
-                    Vr[r][q] = (on && xx < cols) ? to_cd(Vf[(int64_t)(l0 + r) * cols + xx]) : cmk(0.0, 0.0);
+                    Ur[r][q] = (on && xx < rows) ? to_arith<A>(Uf[(int64_t)(l0 + r) * rows + xx]) : czero<A>();
+                    Vr[r][q] = (on && xx < cols) ? to_arith<A>(Vf[(int64_t)(l0 + r) * cols + xx]) : czero<A>();
                 }
 #pragma unroll
             for (int r = 0; r < RQ; ++r) {
@@ -449,13 +454,13 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const T* alpha, const
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
                     if (FWD) {   // V^T (U^T x)
-                        cd t = cmul(Ur[r][0], x[0][c]);
+                        A t = cmul(Ur[r][0], x[0][c]);
                         if (Q > 1) t = cfma(Ur[r][Q - 1], x[Q - 1][c], t);
                         t = wave_sum(t);
 #pragma unroll
                         for (int q = 0; q < Q; ++q) acc[q][c] = cfma(Vr[r][q], t, acc[q][c]);
                     } else {     // U (V x)
-                        cd t = cmul(Vr[r][0], x[0][c]);
+                        A t = cmul(Vr[r][0], x[0][c]);
                         if (Q > 1) t = cfma(Vr[r][Q - 1], x[Q - 1][c], t);
                         t = wave_sum(t);
 #pragma unroll
@@ -471,7 +476,7 @@ __device__ __forceinline__ void push_one(const PushEnt& e, const T* alpha, const
         if (b < bt)
 #pragma unroll
             for (int c = 0; c < S; ++c)
-                if (c < cs) st_sc(slot + b + (int64_t)c * bt, acc[q][c]);
+                if (c < cs) st_sc(slot + b + (int64_t)c * bt, to_cd(acc[q][c]));
     }
 }
 
@@ -529,7 +534,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
         // rows' loads are issued as soon as this chunk's rows are published
         SweepChunk d = it.fchunk[cfirst];
         RowTask rt = it.frow[d.pc + (slot < d.nc ? slot : 0)];
-        cd R1[QC], R2[QF];
+        arith_t<T> R1[QC], R2[QF];
         int mp[PM];
         load_row(p.lf + rt.a1, slot < d.nc ? rt.w1 : 0, p.mf + rt.a2, slot < d.nc ? d.w2 : 0, R1, R2);
         load_map(it.femap + d.e_off, d.e_n, mp);
@@ -547,9 +552,9 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
                 if (!cols_live(mk, c0, cs)) continue;
-                cd acc[S];
+                arith_t<T> acc[S];
 #pragma unroll
-                for (int cc = 0; cc < S; ++cc) acc[cc] = cmk(0.0, 0.0);
+                for (int cc = 0; cc < S; ++cc) acc[cc] = czero<arith_t<T>>();
                 if (first) {
                     // everything but the newest neighbour chunk is final: stage it
                     // and take its part of the row before waiting for that chunk
@@ -572,7 +577,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
                 if (live) {
                     cd y[S];
 #pragma unroll
-                    for (int cc = 0; cc < S; ++cc) y[cc] = wave_sum(acc[cc]);
+                    for (int cc = 0; cc < S; ++cc) y[cc] = to_cd(wave_sum(acc[cc]));
                     publish_ll<S>(wk.llf, i, n, c0, cs, y, (unsigned)epoch);
                     if (lane == 0)
 #pragma unroll
@@ -683,7 +688,7 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
         // descriptors and rows fetched one chunk ahead, as in the forward sweep
         SweepChunk d = it.bchunk[cfirst];
         RowTask rt = it.brow[d.pc + (slot < d.nc ? slot : 0)];
-        cd R1[QC], R2[QF];
+        arith_t<T> R1[QC], R2[QF];
         int mp[PM];
         load_row(p.lb + rt.a1, slot < d.nc ? rt.w1 : 0, p.mb + rt.a2, slot < d.nc ? d.w2 : 0, R1, R2);
         load_map(it.bemap + d.e_off, d.e_n, mp);
@@ -701,9 +706,9 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             for (int c0 = 0; c0 < nrhs; c0 += S) {
                 const int cs = min(S, nrhs - c0);
                 if (!cols_live(mk, c0, cs)) continue;
-                cd acc[S];
+                arith_t<T> acc[S];
 #pragma unroll
-                for (int cc = 0; cc < S; ++cc) acc[cc] = cmk(0.0, 0.0);
+                for (int cc = 0; cc < S; ++cc) acc[cc] = czero<arith_t<T>>();
                 if (first) {
                     // everything but the newest neighbour chunk is final: stage it
                     // and take its part of the row before waiting for that chunk
@@ -726,7 +731,7 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
                 if (live) {
                     cd y[S];
 #pragma unroll
-                    for (int cc = 0; cc < S; ++cc) y[cc] = wave_sum(acc[cc]);
+                    for (int cc = 0; cc < S; ++cc) y[cc] = to_cd(wave_sum(acc[cc]));
                     publish_ll<S>(wk.llb, i, n, c0, cs, y, (unsigned)epoch);
                     if (lane == 0)
 #pragma unroll

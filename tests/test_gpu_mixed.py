@@ -1,13 +1,15 @@
 """Mixed-precision solve: FP64 flexible GMRES on the FP64 operator whose
-preconditioning steps are inner GMRES solves on complex64 copies of the
-operator and of the preconditioner. Pinned by the oracle operator: the true
-residual of the mixed solution, measured with the FP64 oracle H-matrix,
-meets the tolerance."""
+preconditioning steps are inner GMRES solves computed in FP32 on complex64
+copies of the operator and of the preconditioner (built with FP32 Schur
+updates). Pinned by the oracle operator: the true residual of the mixed
+solution, measured with the FP64 oracle H-matrix, meets the tolerance, and
+the error against the FP64 oracle's solution is stated and bounded."""
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import hmatrix as ohm
+from oracle import pipeline as opl
 
 pytestmark = pytest.mark.gpu
 
@@ -37,10 +39,27 @@ def test_mixed_solve_true_residual(env, case):
         xt = x[perm, c]
         r = wl.rhs[perm, c] - ohm.matvec(hm, xt)
         assert np.linalg.norm(r) <= 1.01e-6 * np.linalg.norm(wl.rhs[:, c])
-    # the same system in plain FP64: the solutions agree to the residual level
-    x64, st64 = hsl.solve(ctx, H, P, b, restart=30, tol=1e-6)
-    x64 = x64.cpu().numpy()
-    assert np.linalg.norm(x - x64) <= 1e-3 * np.linalg.norm(x64)
+    # against the FP64 oracle's own solution (GMRES to 1e-10 on the oracle
+    # operator and preconditioner): the error the 1e-6 residual allows
+    if case == "c1":
+        pc = opl.precond_setup(hm, "rcm", wl.fill_tol)
+        ref = opl.solve(hm, pc, wl.rhs[:, 0], restart=30, tol=1e-10)
+        err = np.linalg.norm(x[:, 0] - ref.x) / np.linalg.norm(ref.x)
+        print(f"mixed vs FP64 oracle solution: relative error {err:.2e}")
+        assert err <= 1e-4
+
+
+def test_mixed_setup_uses_fp32_schur_updates(env):
+    # The mixed setup forms the Schur-update products in complex64 with FP32
+    # accumulation: its block pivots D_k differ from the FP64 setup's at the
+    # FP32 rounding level, neither bit-equal nor far off.
+    hsl, torch, ctx = env
+    wl = W.make_config("c1")
+    H = hsl.HMatrix(ctx, wl.points, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol, store_c64=True)
+    d64 = hsl.Precond(ctx, H, "rcm", 0.0).export("d")
+    d32 = hsl.Precond(ctx, H, "rcm", 0.0, mixed=True).export("d")
+    rel = np.linalg.norm(d32 - d64) / np.linalg.norm(d64)
+    assert 1e-10 < rel < 1e-5, rel
 
 
 def test_mixed_solve_needs_copies(env):
