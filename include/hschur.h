@@ -58,6 +58,8 @@ extern "C" {
 #define HS_ORDER_NATURAL    0   /* leaf (octree depth-first) order */
 #define HS_ORDER_RCM        1   /* reverse Cuthill-McKee (Algorithm 1, Table 3) */
 #define HS_ORDER_CM         2   /* Cuthill-McKee */
+#define HS_ORDER_SLOAN      3   /* Sloan's profile and wavefront reduction (Table 3, Fig. 7; used for Sec. 5) */
+#define HS_ORDER_KING       4   /* King's front-minimising ordering (Table 3, Fig. 6) */
 
 #define HS_PREC_FP64        0   /* complex128 throughout */
 #define HS_PREC_MIXED       1   /* also keep complex64 copies of the apply's matrices (for HS_SOLVE_FGMRES_MIXED) */

@@ -18,6 +18,10 @@ paper names no start node or tie rule, so this reading is used:
   ascending (degree, id);
 * RCM is the reverse of the whole Cuthill-McKee list.
 
+Sloan's and King's orderings (Table 3, Figs. 6-7; the paper ran Sloan's
+for every result of Sec. 5) follow their published algorithms with the same
+start-node and tie readings; see ``sloan`` and ``king``.
+
 Output: ``order[new] = old``. Pinned in the tests on hand-worked graphs
 (path, star, ring, grid, two components), by the permutation property, and
 by the Liu-Sherman result that the reversed ordering's profile is never
@@ -100,6 +104,108 @@ def reverse_cuthill_mckee(nb: int, near: np.ndarray) -> np.ndarray:
     return cuthill_mckee(nb, near)[::-1].copy()
 
 
+def _components_starts(adj, deg, nb):
+    """Seeds of the components in the order they are taken (the unvisited
+    node of smallest (degree, id) each time) with each component's nodes."""
+    seen = np.zeros(nb, dtype=bool)
+    out = []
+    for _ in range(nb):
+        cand = [v for v in range(nb) if not seen[v]]
+        if not cand:
+            break
+        s0 = min(cand, key=lambda v: (deg[v], v))
+        comp = [w for level in _levels(adj, s0, deg) for w in level]
+        for w in comp:
+            seen[w] = True
+        out.append((s0, comp))
+    return out
+
+
+SLOAN_W1, SLOAN_W2 = 1, 2
+
+
+def sloan(nb: int, near: np.ndarray, w1: int = SLOAN_W1, w2: int = SLOAN_W2) -> np.ndarray:
+    """Sloan's profile and wavefront reduction (Sloan's 1986 algorithm as
+    restated by Kumfert and Pothen), per component:
+
+    * start s: the pseudo-peripheral node found from the component's seed
+      (as for Cuthill-McKee); end e: the node of smallest (degree, id) in
+      the last level of the level structure rooted at s;
+    * priority P(i) = w1 dist(i, e) - w2 (deg(i) + 1);
+    * states inactive / preactive / active / postactive, s preactive first;
+      repeatedly take the queued (preactive or active) node of largest
+      priority, ties to the lowest id. If it was preactive, each neighbour
+      gains w2 and an inactive neighbour becomes preactive. It is numbered
+      (postactive). Each of its preactive neighbours becomes active and gains
+      w2, and each non-postactive neighbour of such a node gains w2, an
+      inactive one becoming preactive.
+    """
+    adj = leaf_graph(nb, near)
+    deg = [len(a) for a in adj]
+    order = []
+    INACT, PRE, ACT, POST = 0, 1, 2, 3
+    status = [INACT] * nb
+    prio = [0] * nb
+    for s0, comp in _components_starts(adj, deg, nb):
+        s = pseudo_peripheral(adj, s0, deg)
+        last = _levels(adj, s, deg)[-1]
+        e = min(last, key=lambda v: (deg[v], v))
+        for d, level in enumerate(_levels(adj, e, deg)):
+            for v in level:
+                prio[v] = w1 * d - w2 * (deg[v] + 1)
+        status[s] = PRE
+        queue = {s}
+        while queue:
+            i = max(queue, key=lambda v: (prio[v], -v))
+            queue.remove(i)
+            if status[i] == PRE:
+                for j in adj[i]:
+                    prio[j] += w2
+                    if status[j] == INACT:
+                        status[j] = PRE
+                        queue.add(j)
+            order.append(i)
+            status[i] = POST
+            for j in adj[i]:
+                if status[j] == PRE:
+                    status[j] = ACT
+                    prio[j] += w2
+                    for k in adj[j]:
+                        if status[k] != POST:
+                            prio[k] += w2
+                            if status[k] == INACT:
+                                status[k] = PRE
+                                queue.add(k)
+    return np.array(order, dtype=np.int64)
+
+
+def king(nb: int, near: np.ndarray) -> np.ndarray:
+    """King's front-minimising ordering, per component: number the
+    pseudo-peripheral start first (as for Cuthill-McKee); then, of the front
+    (unnumbered nodes adjacent to numbered ones), number the node that adds
+    the fewest new nodes to the front, ties to the lowest id."""
+    adj = leaf_graph(nb, near)
+    deg = [len(a) for a in adj]
+    order = []
+    numbered = np.zeros(nb, dtype=bool)
+    for s0, comp in _components_starts(adj, deg, nb):
+        s = pseudo_peripheral(adj, s0, deg)
+        front = set()
+        nxt = s
+        while nxt is not None:
+            numbered[nxt] = True
+            front.discard(nxt)
+            order.append(nxt)
+            for w in adj[nxt]:
+                if not numbered[w]:
+                    front.add(w)
+            if not front:
+                nxt = None
+                break
+            nxt = min(front, key=lambda v: (sum(1 for w in adj[v] if not numbered[w] and w not in front), v))
+    return np.array(order, dtype=np.int64)
+
+
 def make_order(kind: str, nb: int, near: np.ndarray) -> np.ndarray:
     kind = kind.lower()
     if kind == "natural":
@@ -108,6 +214,10 @@ def make_order(kind: str, nb: int, near: np.ndarray) -> np.ndarray:
         return cuthill_mckee(nb, near)
     if kind == "rcm":
         return reverse_cuthill_mckee(nb, near)
+    if kind == "sloan":
+        return sloan(nb, near)
+    if kind == "king":
+        return king(nb, near)
     raise ValueError(f"unknown ordering {kind}")
 
 

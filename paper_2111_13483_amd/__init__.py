@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libhschur.so")
 
 HS_OK, HS_NOT_CONVERGED = 0, 1
 HS_EINVAL, HS_ENOMEM, HS_ENODEVICE, HS_EHIP, HS_ESINGULAR, HS_ENUMERIC, HS_ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
-ORDER = {"natural": 0, "rcm": 1, "cm": 2}
+ORDER = {"natural": 0, "rcm": 1, "cm": 2, "sloan": 3, "king": 4}
 X_CODES = {"perm": 1, "leaf_off": 2, "boxes": 3, "near": 4, "far": 5, "order": 6, "rowptr": 7, "cols": 8, "orig": 9}
 H_CODES = {"near_off": 101, "near_data": 102, "far_rank": 103, "far_off": 104, "far_uv": 105, "far_piv": 106}
 P_CODES = {"d": 201, "alpha_kind": 202, "alpha_off": 203, "alpha": 204}

@@ -801,7 +801,7 @@ int32_t hs_plan_create(const double* pts, int64_t n, int32_t leaf_max, int32_t o
         if (!pts) fail(HS_EINVAL, "points is NULL");
         if (n < 1) fail(HS_EINVAL, "n must be >= 1");
         if (leaf_max < 1) fail(HS_EINVAL, "leaf_max must be >= 1");
-        if (ordering < 0 || ordering > 2) fail(HS_EINVAL, "unknown ordering");
+        if (ordering < 0 || ordering > 4) fail(HS_EINVAL, "unknown ordering");
         auto p = std::make_unique<hs_plan>();
         try {
             p->tree = hs::build_tree(pts, n, leaf_max);
@@ -1902,7 +1902,7 @@ int32_t hs_precond_setup_many(hs_context* ctx, int64_t count, const hs_hmatrix* 
         for (int64_t g = 0; g < count; ++g) {
             const hs_hmatrix* H = Hs[g];
         if (!ctx || !H || !opts) fail(HS_EINVAL, "NULL argument");
-            if (opts->ordering < 0 || opts->ordering > 2) fail(HS_EINVAL, "unknown ordering");
+            if (opts->ordering < 0 || opts->ordering > 4) fail(HS_EINVAL, "unknown ordering");
             if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
             if (opts->precision != HS_PREC_FP64 && opts->precision != HS_PREC_MIXED) fail(HS_EINVAL, "unsupported precision");
             if (opts->sweep_chunk < 0 || opts->sweep_chunk > hs::kMaxChunk) fail(HS_EINVAL, "sweep_chunk must be in [0, 384]");

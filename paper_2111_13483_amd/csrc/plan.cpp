@@ -6,7 +6,8 @@
 // than leaf_max points. Partition (Eq. 8, Fig. 1) with adjacency
 // admissibility by symmetric dual traversal. Ordering (Algorithm 1):
 // Cuthill-McKee from a George-Liu pseudo-peripheral node, reversed for
-// RCM. Symbolic fill (Sec. 3.3): row patterns of the eliminated leaf graph
+// RCM; Sloan's and King's profile-reducing orderings from the same start.
+// Symbolic fill (Sec. 3.3): row patterns of the eliminated leaf graph
 // via the elimination tree.
 #include "plan.h"
 
@@ -224,6 +225,121 @@ bool deg_less(const Graph& g, int64_t a, int64_t b) {
 
 }  // namespace
 
+namespace {
+
+// George-Liu pseudo-peripheral node of r's component (size: its node count)
+int64_t pseudo_peripheral(const Graph& g, int64_t r, std::vector<int64_t>& mark, int64_t& stamp, int64_t& size) {
+    std::vector<int64_t> last;
+    size = 0;
+    int64_t nlev = levels(g, r, mark, stamp++, last, size);
+    int64_t start = r;
+    if (!(nlev == 1 || nlev == size)) {
+        for (;;) {
+            int64_t x = last[0];
+            for (int64_t v : last) if (deg_less(g, v, x)) x = v;
+            int64_t sz2 = 0;
+            std::vector<int64_t> last2;
+            int64_t nlev2 = levels(g, x, mark, stamp++, last2, sz2);
+            if (nlev2 <= nlev) { start = x; break; }
+            r = x; nlev = nlev2; last.swap(last2);
+            start = r;
+            if (nlev >= size) break;
+        }
+    }
+    return start;
+}
+
+// Sloan's ordering of one component from start s (statuses, priorities
+// P = w1 dist(e) - w2 (deg + 1), largest priority first, ties to the lowest id)
+void sloan_component(const Graph& g, int64_t s, std::vector<int64_t>& mark, int64_t& stamp,
+                     std::vector<int>& status, std::vector<int64_t>& prio, std::vector<int64_t>& order) {
+    constexpr int64_t W1 = 1, W2 = 2;
+    enum { INACT = 0, PRE = 1, ACT = 2, POST = 3 };
+    std::vector<int64_t> last;
+    int64_t size = 0;
+    levels(g, s, mark, stamp++, last, size);
+    int64_t e = last[0];
+    for (int64_t v : last) if (deg_less(g, v, e)) e = v;
+    // distances from e (breadth-first levels of e's component)
+    std::vector<int64_t> cur{e}, nxt;
+    const int64_t st = stamp++;
+    mark[e] = st;
+    for (int64_t d = 0; !cur.empty(); ++d) {
+        nxt.clear();
+        for (int64_t v : cur) {
+            prio[v] = W1 * d - W2 * (g.deg[v] + 1);
+            for (int64_t w : g.adj[v])
+                if (mark[w] != st) { mark[w] = st; nxt.push_back(w); }
+        }
+        cur.swap(nxt);
+    }
+    // queue of preactive and active nodes: a max-heap on (priority, -id)
+    // with one entry per priority change; stale entries are skipped
+    typedef std::pair<int64_t, int64_t> Ent;   // (priority, -id)
+    std::vector<Ent> heap;
+    auto push = [&](int64_t v) {
+        heap.push_back({prio[v], -v});
+        std::push_heap(heap.begin(), heap.end());
+    };
+    status[s] = PRE;
+    push(s);
+    while (!heap.empty()) {
+        std::pop_heap(heap.begin(), heap.end());
+        const Ent top = heap.back();
+        heap.pop_back();
+        const int64_t i = -top.second;
+        if (status[i] == POST || status[i] == INACT || prio[i] != top.first) continue;
+        if (status[i] == PRE) {
+            for (int64_t j : g.adj[i]) {
+                prio[j] += W2;
+                if (status[j] == INACT) status[j] = PRE;
+                if (status[j] == PRE || status[j] == ACT) push(j);
+            }
+        }
+        order.push_back(i);
+        status[i] = POST;
+        for (int64_t j : g.adj[i]) {
+            if (status[j] != PRE) continue;
+            status[j] = ACT;
+            prio[j] += W2;
+            push(j);
+            for (int64_t k : g.adj[j]) {
+                if (status[k] == POST) continue;
+                prio[k] += W2;
+                if (status[k] == INACT) status[k] = PRE;
+                push(k);
+            }
+        }
+    }
+}
+
+// King's ordering of one component from start s: number, from the front,
+// the node adding the fewest new front nodes, ties to the lowest id
+void king_component(const Graph& g, int64_t s, std::vector<char>& numbered, std::vector<char>& infront,
+                    std::vector<int64_t>& order) {
+    std::vector<int64_t> front;
+    int64_t nxt = s;
+    while (nxt >= 0) {
+        numbered[nxt] = 1;
+        if (infront[nxt]) {
+            infront[nxt] = 0;
+            front.erase(std::find(front.begin(), front.end(), nxt));
+        }
+        order.push_back(nxt);
+        for (int64_t w : g.adj[nxt])
+            if (!numbered[w] && !infront[w]) { infront[w] = 1; front.push_back(w); }
+        nxt = -1;
+        int64_t best = 0;
+        for (int64_t v : front) {
+            int64_t add = 0;
+            for (int64_t w : g.adj[v]) add += (!numbered[w] && !infront[w]) ? 1 : 0;
+            if (nxt < 0 || add < best || (add == best && v < nxt)) { nxt = v; best = add; }
+        }
+    }
+}
+
+}  // namespace
+
 std::vector<int64_t> make_order(int kind, int64_t nb, const Partition& p) {
     std::vector<int64_t> order;
     order.reserve(nb);
@@ -231,10 +347,11 @@ std::vector<int64_t> make_order(int kind, int64_t nb, const Partition& p) {
         for (int64_t i = 0; i < nb; ++i) order.push_back(i);
         return order;
     }
-    if (kind != 1 && kind != 2) throw std::invalid_argument("unknown ordering");
+    if (kind < 1 || kind > 4) throw std::invalid_argument("unknown ordering");
     Graph g = leaf_graph(nb, p);
-    std::vector<char> visited(nb, 0);
-    std::vector<int64_t> mark(nb, -1), last;
+    std::vector<char> visited(nb, 0), infront(nb, 0);
+    std::vector<int64_t> mark(nb, -1), prio(nb, 0);
+    std::vector<int> status(nb, 0);
     int64_t stamp = 0;
     // candidates in (degree, id) order for picking each component's first node
     std::vector<int64_t> cand(nb);
@@ -243,36 +360,28 @@ std::vector<int64_t> make_order(int kind, int64_t nb, const Partition& p) {
     size_t cpos = 0;
     while ((int64_t)order.size() < nb) {
         while (visited[cand[cpos]]) ++cpos;
-        int64_t r = cand[cpos];
-        // George-Liu pseudo-peripheral node
         int64_t size = 0;
-        int64_t nlev = levels(g, r, mark, stamp++, last, size);
-        int64_t start = r;
-        if (!(nlev == 1 || nlev == size)) {
-            for (;;) {
-                int64_t x = last[0];
-                for (int64_t v : last) if (deg_less(g, v, x)) x = v;
-                int64_t sz2 = 0;
-                std::vector<int64_t> last2;
-                int64_t nlev2 = levels(g, x, mark, stamp++, last2, sz2);
-                if (nlev2 <= nlev) { start = x; break; }
-                r = x; nlev = nlev2; last.swap(last2);
-                start = r;
-                if (nlev >= size) break;
+        const int64_t start = pseudo_peripheral(g, cand[cpos], mark, stamp, size);
+        const size_t head0 = order.size();
+        if (kind == 3) {
+            sloan_component(g, start, mark, stamp, status, prio, order);
+        } else if (kind == 4) {
+            king_component(g, start, visited, infront, order);
+        } else {
+            // breadth-first search, neighbours in (degree, id) order
+            size_t head = order.size();
+            visited[start] = 1;
+            order.push_back(start);
+            std::vector<int64_t> nbrs;
+            while (head < order.size()) {
+                int64_t v = order[head++];
+                nbrs.clear();
+                for (int64_t w : g.adj[v]) if (!visited[w]) nbrs.push_back(w);
+                std::sort(nbrs.begin(), nbrs.end(), [&](int64_t a, int64_t b) { return deg_less(g, a, b); });
+                for (int64_t w : nbrs) { visited[w] = 1; order.push_back(w); }
             }
         }
-        // breadth-first search, neighbours in (degree, id) order
-        size_t head = order.size();
-        visited[start] = 1;
-        order.push_back(start);
-        std::vector<int64_t> nbrs;
-        while (head < order.size()) {
-            int64_t v = order[head++];
-            nbrs.clear();
-            for (int64_t w : g.adj[v]) if (!visited[w]) nbrs.push_back(w);
-            std::sort(nbrs.begin(), nbrs.end(), [&](int64_t a, int64_t b) { return deg_less(g, a, b); });
-            for (int64_t w : nbrs) { visited[w] = 1; order.push_back(w); }
-        }
+        for (size_t q = head0; q < order.size(); ++q) visited[order[q]] = 1;
     }
     if (kind == 1) std::reverse(order.begin(), order.end());
     return order;

@@ -86,7 +86,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,gen,leaf", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("kind", ["natural", "rcm", "cm"])
+@pytest.mark.parametrize("kind", ["natural", "rcm", "cm", "sloan", "king"])
 def test_plan_bit_exact_with_oracle(name, gen, leaf, kind):
     pts = gen()
     t, p, s = _oracle_plan(pts, leaf, kind)

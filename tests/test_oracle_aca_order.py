@@ -140,6 +140,48 @@ def test_cm_grid3x3():
     assert ordering.reverse_cuthill_mckee(9, near).tolist() == [0, 3, 1, 6, 4, 2, 7, 5, 8]
 
 
+# Sloan and King: results worked out by hand from the stated rules (start s
+# from the pseudo-peripheral finder, end e the (degree, id)-smallest node of
+# s's last level, P = dist(e) - 2 (deg + 1), ties to the lowest id).
+
+def test_sloan_king_path():
+    near = _edges([(0, 1), (1, 2), (2, 3), (3, 4)])
+    assert ordering.sloan(5, near).tolist() == [0, 1, 2, 3, 4]
+    assert ordering.king(5, near).tolist() == [0, 1, 2, 3, 4]
+
+
+def test_sloan_king_star():
+    # s = 2 (the finder moves from seed 1 to 2), e = 1, P = (-9, -4, -2, -2, -2)
+    near = _edges([(0, 1), (0, 2), (0, 3), (0, 4)])
+    assert ordering.sloan(5, near).tolist() == [2, 3, 4, 0, 1]
+    assert ordering.king(5, near).tolist() == [2, 0, 1, 3, 4]
+
+
+def test_sloan_king_ladder():
+    # 0-1-2 over 3-4-5 with rungs: s = 5, e = 0, P = (-6, -7, -4, -5, -6, -3)
+    near = _edges([(0, 1), (1, 2), (3, 4), (4, 5), (0, 3), (1, 4), (2, 5)])
+    assert ordering.sloan(6, near).tolist() == [5, 2, 4, 1, 3, 0]
+    assert ordering.king(6, near).tolist() == [5, 2, 1, 0, 3, 4]
+
+
+def test_sloan_king_components_and_plate_profile():
+    # two components and an isolated node: a permutation, components in seed order
+    near = _edges([(0, 1), (1, 2), (4, 5), (5, 6), (6, 7)])
+    for fn in (ordering.sloan, ordering.king):
+        o = fn(8, near).tolist()
+        assert sorted(o) == list(range(8))
+        assert o[0] == 3 and set(o[1:4]) == {0, 1, 2} and set(o[4:]) == {4, 5, 6, 7}
+    # on the plate's leaf graph both reduce the profile of the natural order,
+    # Sloan at least as much as King (the trend of Table 4)
+    wl = W.make_config("plate")
+    t = tree.build_tree(wl.points, wl.leaf_max)
+    p = partition.build_partition(t)
+    nat = ordering.profile(t.nb, p.near, np.arange(t.nb))
+    ps = ordering.profile(t.nb, p.near, ordering.sloan(t.nb, p.near))
+    pk = ordering.profile(t.nb, p.near, ordering.king(t.nb, p.near))
+    assert ps < nat and pk < nat and ps <= pk
+
+
 def test_cm_two_components_and_isolated_node():
     near = _edges([(0, 1), (2, 3), (3, 4), (2, 4), (5, 5)])
     assert ordering.cuthill_mckee(6, near).tolist() == [5, 0, 1, 3, 2, 4]
@@ -188,7 +230,7 @@ def _dense_fill(nb, near, order):
     return F
 
 
-@pytest.mark.parametrize("kind", ["natural", "cm", "rcm"])
+@pytest.mark.parametrize("kind", ["natural", "cm", "rcm", "sloan", "king"])
 def test_symbolic_matches_dense_boolean_elimination(kind):
     rng = np.random.default_rng(11)
     pts = W.fibonacci_sphere(900, rng)

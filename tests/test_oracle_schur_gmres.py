@@ -89,7 +89,7 @@ def test_fig2_first_step_structure():
     assert np.linalg.norm(pc.alpha[(1, 3)] - a13) <= 1e-11 * np.linalg.norm(a13)
 
 
-@pytest.mark.parametrize("kind", ["natural", "cm", "rcm"])
+@pytest.mark.parametrize("kind", ["natural", "cm", "rcm", "sloan", "king"])
 def test_exact_preconditioner_is_near_field_inverse(kind):
     # with no fill-in dropped, alpha D^-1 alpha^T = Z_N^-1 for every ordering
     hm, rng = _small_hm(n=400, leaf=16, seed=5)
