@@ -61,6 +61,8 @@ def parse():
                     help="mixed path: FP64 flexible GMRES with inner GMRES on complex64 copies")
     ap.add_argument("--mixed-restart", type=int, default=20, help="outer FGMRES restart of the mixed path")
     ap.add_argument("--mixed-inner", type=int, default=20, help="inner GMRES steps of the mixed path")
+    ap.add_argument("--orderings", action="store_true",
+                    help="ordering trend study (natural, CM, RCM, King, Sloan) on the 5,985-point plate")
     ap.add_argument("--batch", type=int, default=0, metavar="G",
                     help="batching run: G geometries of the many-geometry recipe, batched vs one-by-one setup")
     ap.add_argument("--batch-nmax", type=int, default=40000, help="largest N of the batching run")
@@ -342,6 +344,57 @@ def serve(args):
     print(json.dumps(out), flush=True)
 
 
+def orderings(args):
+    """Near-field orderings on the synthetic 5,985-point plate (the paper's
+    5 lambda plate, Table 3 and 4): per ordering and leaf size, the exact
+    counts of the host plan (pattern blocks, dense scaling-coefficient
+    elements, setup flops), the preconditioner setup time on the GPU, the
+    stored coefficient bytes after fill-in compression, the apply time and
+    the GMRES iterations for one plane wave. Trends only: the paper's RWG
+    matrices are not these."""
+    import torch
+    import paper_2111_13483_amd as hsl
+    import workloads as W
+
+    ctx = hsl.Context(0)
+    wl = W.make_config("plate", n=5985)
+    b = torch.as_tensor(wl.rhs[:, 0], device="cuda")
+    rows = []
+    for leaf in (32, 96):
+        H = hsl.HMatrix(ctx, wl.points, wl.k, wl.self_h, leaf, wl.aca_tol)
+        v = torch.as_tensor(np.random.default_rng(1).normal(size=wl.n) + 0j, device="cuda")
+        for kind in ("natural", "cm", "rcm", "king", "sloan"):
+            plan = hsl.Plan(wl.points, leaf, kind).info()
+            ts = []
+            for _ in range(4):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                P = hsl.Precond(ctx, H, kind, wl.fill_tol)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            P.apply(v)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(20):
+                P.apply(v)
+            torch.cuda.synchronize()
+            t_apply = (time.perf_counter() - t0) / 20
+            x, st = hsl.solve(ctx, H, P, b, restart=wl.restart, tol=wl.tol)
+            pi = P.info()
+            rows.append({"leaf_max": leaf, "ordering": kind, "nb": plan["nb"], "pattern_blocks": plan["n_pattern"],
+                         "fill_blocks": plan["n_fill"], "alpha_dense_elems": plan["bytes_alpha"] // 16,
+                         "setup_flops": plan["flops_setup"], "setup_s": float(np.median(ts[1:])),
+                         "alpha_stored_bytes": pi["bytes_alpha"], "lowrank_blocks": pi["n_lowrank"],
+                         "apply_ms": 1e3 * t_apply, "gmres_iters": st[0].iters, "converged": st[0].converged})
+            print(f"orderings: leaf {leaf} {kind}: setup {rows[-1]['setup_s']:.4f} s, apply "
+                  f"{rows[-1]['apply_ms']:.3f} ms, {st[0].iters} iterations", file=sys.stderr, flush=True)
+            del P
+        del H
+    print(json.dumps({"metric": "near-field ordering trends on the 5,985-point plate", "data": "synthetic",
+                      "config": {"workload": "plate 2 x 2 x 0.05, N = 5985, lambda = 10 h, ACA 1e-4, fill 1e-2, "
+                                             "GMRES(30) to 1e-6"}, "rows": rows}), flush=True)
+
+
 def committed_traffic():
     """Scaled HBM bytes per launch from the committed counter summary; a
     kernel is absent when its sources changed since the counters were taken."""
@@ -495,6 +548,9 @@ def main():
         return
     if args.batch:
         batch(args)
+        return
+    if args.orderings:
+        orderings(args)
         return
     import torch
     import paper_2111_13483_amd as hsl

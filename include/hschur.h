@@ -69,6 +69,12 @@ extern "C" {
                                    inner right-preconditioned GMRES on the complex64 operator copies with the
                                    complex64 preconditioner copies (vectors and Arnoldi in FP64); needs
                                    store_c64 at build and HS_PREC_MIXED at setup */
+#define HS_SOLVE_TRANSFORMED 2  /* the paper's transformed system (Eq. 25-28): GMRES on
+                                   x~ + D^-1 alpha^T Z_F alpha x~ = D^-1 alpha^T b, x = alpha x~ (no near-field
+                                   matvec in the iteration); its iteration monitors the transformed residual,
+                                   stats report the true ||b - Z x|| / ||b||, which meets tol only up to the
+                                   fill-in compression error (alpha^T Z_N alpha = D exactly at fill_tol = 0);
+                                   needs P */
 
 typedef struct hs_context hs_context;
 typedef struct hs_plan    hs_plan;

@@ -382,11 +382,12 @@ class Stats:
 
 def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol: float = 1e-6,
           max_iters: int = 0, fixed_iters: int = 0, mixed: bool = False, inner_steps: int = 0, inner_tol: float = 0.0,
-          x0=None):
+          x0=None, transformed: bool = False):
     """Solve Z x = b: right-preconditioned GMRES, or with mixed=True FP64
     flexible GMRES whose preconditioning steps are inner GMRES solves on the
-    complex64 copies; x0 (GMRES only) is the initial guess. Returns
-    (x, [Stats per column])."""
+    complex64 copies; x0 (GMRES only) is the initial guess; transformed=True
+    solves the paper's transformed system (Eq. 25-28) instead, its stats
+    holding the true residual. Returns (x, [Stats per column])."""
     torch = _torch()
     bc, s = _dev_c128(b, H.n)
     if x0 is None:
@@ -395,7 +396,8 @@ def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol
         x, s0 = _dev_c128(x0, H.n)
         if s0 != s:
             raise HschurError(HS_EINVAL, "x0 and b differ in columns")
-    opts = SolveOpts(1 if mixed else 0, restart, tol, max_iters, fixed_iters, inner_steps, inner_tol,
+    method = 2 if transformed else (1 if mixed else 0)
+    opts = SolveOpts(method, restart, tol, max_iters, fixed_iters, inner_steps, inner_tol,
                      0 if x0 is None else 1)
     st = (SolveStats * s)()
     _check(_lib.hs_solve(ctx._h, H._h, P._h if P is not None else None, ctypes.c_void_p(bc.data_ptr()),

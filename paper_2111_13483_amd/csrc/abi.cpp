@@ -273,6 +273,7 @@ struct hs_hmatrix {
     LowRankSet far;
     int64_t bytes_near = 0, bytes_far = 0;
     int64_t slot_total = 0;
+    int64_t near_slot_end = 0;   // slots [0, near_slot_end) belong to the near blocks
     // device
     double* d_pts = nullptr;
     int64_t* d_perm = nullptr;
@@ -569,9 +570,12 @@ void matvec_tree(hs_context* ctx, const hs_hmatrix* H, const cd* x, cd* y, int n
     hs::launch_gather(mk, H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, H->n, nrhs, y, s);
 }
 
+// A sweep direction's counters advance with its own epoch, so forward and
+// backward sweeps may also run alone (the transformed system applies
+// alpha^T and alpha separately).
 struct SweepWs {
     hs::SweepWork w{};
-    int epoch = 0;
+    int epoch_f = 0, epoch_b = 0;
 };
 
 SweepOrder& sweep_order(int device) {
@@ -617,12 +621,35 @@ void sweeps_release(int device, hipStream_t s) {
 
 void apply_tree(hs_context* ctx, const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, hipStream_t s,
                 const hs::ColMask& mk) {
-    ws.epoch += 1;
+    ws.epoch_f += 1;
+    ws.epoch_b += 1;
     sweeps_begin(ctx->device, s);
     timed(ctx, HS_KT_SWEEP_FWD, s,
-          [&] { hs::launch_sweep(true, mk, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s); });
+          [&] { hs::launch_sweep(true, mk, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch_f, s); });
     timed(ctx, HS_KT_SWEEP_BWD, s,
-          [&] { hs::launch_sweep(false, mk, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch, s); });
+          [&] { hs::launch_sweep(false, mk, P->sp, P->items, v, z, nrhs, ws.w, ws.epoch_b, s); });
+    sweeps_end(ctx->device, s);
+}
+
+// alpha^T v (forward sweep alone; tree order in and out; tmp: elimination-order scratch unused)
+void alpha_t_tree(hs_context* ctx, const hs_precond* P, const cd* v, cd* out, int nrhs, SweepWs& ws, hipStream_t s,
+                  const hs::ColMask& mk) {
+    ws.epoch_f += 1;
+    sweeps_begin(ctx->device, s);
+    timed(ctx, HS_KT_SWEEP_FWD, s,
+          [&] { hs::launch_sweep(true, mk, P->sp, P->items, v, out, nrhs, ws.w, ws.epoch_f, s); });
+    sweeps_end(ctx->device, s);
+    hs::launch_elim_move(P->sp, ws.w.ybuf, out, nrhs, false, s);
+}
+
+// alpha u (backward sweep without D^-1; tree order in and out)
+void alpha_tree(hs_context* ctx, const hs_precond* P, const cd* u, cd* out, int nrhs, SweepWs& ws, hipStream_t s,
+                const hs::ColMask& mk) {
+    hs::launch_elim_move(P->sp, u, ws.w.ybuf, nrhs, true, s);
+    ws.epoch_b += 1;
+    sweeps_begin(ctx->device, s);
+    timed(ctx, HS_KT_SWEEP_BWD, s,
+          [&] { hs::launch_sweep(false, mk, P->sp, P->items, u, out, nrhs, ws.w, ws.epoch_b, s, false); });
     sweeps_end(ctx->device, s);
 }
 
@@ -949,6 +976,7 @@ int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double 
             if (i != j) lists[j].push_back(hs::GatherEnt{slot + nt.m, nt.n, 0});
             slot += nt.m + (i != j ? nt.n : 0);
         }
+        H->near_slot_end = slot;
         // leaves of a box: leaf starts are sorted, boxes are contiguous point ranges
         auto leaves_of = [&](int64_t b, int64_t& l0, int64_t& l1) {
             const int64_t s0 = t.start[b], s1 = t.start[b] + t.count[b];
@@ -2182,6 +2210,97 @@ void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& mat
     }
 }
 
+// The paper's transformed system (Eq. 25-28): GMRES on
+//   x~ + D^-1 alpha^T Z_F alpha x~ = D^-1 alpha^T b,  x = alpha x~,
+// with the identity as right preconditioner, so the iteration monitors the
+// transformed left-preconditioned residual; the near-field matvec drops out
+// (alpha^T Z_N alpha = D). The true residual of x is computed at the end
+// with the full operator and reported in stats.
+int32_t solve_transformed(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, const void* b, void* x,
+                          int64_t nrhs, const hs_solve_opts* opts, hs_solve_stats* stats) {
+    if (!P) fail(HS_EINVAL, "the transformed system needs a preconditioner (its alpha and D)");
+    if (opts->use_x0) fail(HS_EINVAL, "use_x0 is supported by HS_SOLVE_GMRES only");
+    const int m = opts->restart;
+    if (m < 1 || m > hs::kMaxRankCap) fail(HS_EINVAL, "restart must be in [1, 256]");
+    if (!(opts->tol >= 0.0)) fail(HS_EINVAL, "tol must be >= 0");
+    const int budget = opts->fixed_iters > 0 ? opts->fixed_iters : (opts->max_iters > 0 ? opts->max_iters : 5000);
+    set_device(ctx);
+    hipStream_t s = ctx->stream;
+    const int64_t n = H->n;
+    const int ns = (int)nrhs;
+    Owned w;
+    w.mem = ctx->mem;
+    cd* bt = w.get<cd>(n * ns);
+    cd* rhs = w.get<cd>(n * ns);
+    cd* xt = w.get<cd>(n * ns);
+    cd* u = w.get<cd>(n * ns);
+    cd* t2 = w.get<cd>(n * ns);
+    cd* slots = w.get<cd>((size_t)H->slot_total * ns);
+    // the near slots stay zero: only the far kernels write, so the gather sums Z_F alone
+    hip_check(hipMemsetAsync(slots, 0, sizeof(cd) * (size_t)H->near_slot_end * ns, s), "memset");
+    GmresWs G;
+    G.alloc(w, n, ns, m, false);
+    SweepWs sw = make_sweep_ws(w, P, ns, s, ctx);
+    std::vector<hs::ColState> hst(ns);
+    for (auto& c : hst) {
+        std::memset(&c, 0, sizeof(c));
+        c.tol = opts->tol;
+        c.budget = budget;
+        c.fixed = opts->fixed_iters > 0 ? 1 : 0;
+    }
+    hip_check(hipMemcpyAsync(G.st, hst.data(), sizeof(hs::ColState) * ns, hipMemcpyHostToDevice, s), "H2D");
+    hip_check(hipMemsetAsync(xt, 0, sizeof(cd) * n * ns, s), "memset");
+    hs::launch_permute(static_cast<const cd*>(b), bt, H->d_perm, n, ns, true, s);
+    auto far_only = [&](const cd* in, cd* out, const hs::ColMask& mk) {
+        timed(ctx, HS_KT_FAR_MV, s, [&] {
+            hs::launch_far_mv(mk, H->d_mv_geom, H->d_mv_rank, H->d_mv_ptr, H->d_mv_slot, H->n_far_wg,
+                              (int64_t)H->far_geom.size(), in, n, ns, slots, s);
+        });
+        hs::launch_gather(mk, H->d_leaf_off, H->d_gptr, H->d_gent, H->nb, slots, n, ns, out, s);
+    };
+    // right-hand side D^-1 alpha^T b
+    alpha_t_tree(ctx, P, bt, t2, ns, sw, s, kAllCols);
+    hs::launch_block_dinv(P->sp, t2, nullptr, rhs, ns, s);
+    cd* zf = w.get<cd>(n * ns);
+    // in -> out = in + D^-1 alpha^T Z_F alpha in (out may not alias in)
+    ApplyFn op = [&](const cd* in, cd* out, const hs::ColMask& mk) {
+        alpha_tree(ctx, P, in, u, ns, sw, s, mk);
+        far_only(u, zf, mk);
+        alpha_t_tree(ctx, P, zf, t2, ns, sw, s, mk);
+        hs::launch_block_dinv(P->sp, t2, in, out, ns, s);
+    };
+    ApplyFn ident = [&](const cd* in, cd* out, const hs::ColMask& mk) {
+        (void)mk;
+        if (in != out) hip_check(hipMemcpyAsync(out, in, sizeof(cd) * n * ns, hipMemcpyDeviceToDevice, s), "D2D");
+    };
+    gmres_run(G, s, rhs, xt, op, ident, false, false, 4, sw.w.err);
+    hst = poll_states(G, sw.w.err, s);
+    // x = alpha x~, its true residual with the full operator
+    alpha_tree(ctx, P, xt, u, ns, sw, s, kAllCols);
+    matvec_tree(ctx, H, u, t2, ns, slots, s, kAllCols);
+    hs::launch_residual(bt, t2, G.r, n, ns, G.npart, G.nchunk, s);
+    std::vector<double> rp = download(G.npart, (size_t)G.nchunk * ns, s);
+    hs::launch_col_norms(bt, n, ns, G.npart, G.nchunk, s);
+    std::vector<double> bp = download(G.npart, (size_t)G.nchunk * ns, s);
+    hs::launch_permute(u, static_cast<cd*>(x), H->d_perm, n, ns, false, s);
+    hip_check(hipGetLastError(), "transformed solve launches");
+    check_sweep_flag(sw, s);
+    bool all_conv = true;
+    for (int c = 0; c < ns; ++c) {
+        double rr = 0, bb = 0;
+        for (int ch = 0; ch < G.nchunk; ++ch) {
+            rr += rp[(size_t)ch * ns + c];
+            bb += bp[(size_t)ch * ns + c];
+        }
+        stats[c].iters = hst[c].total;
+        stats[c].relres = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        stats[c].converged = stats[c].relres <= opts->tol ? 1 : 0;
+        if (!std::isfinite(stats[c].relres)) fail(HS_ENUMERIC, "NaN or Inf in the residual");
+        all_conv &= stats[c].converged != 0;
+    }
+    return all_conv ? HS_OK : HS_NOT_CONVERGED;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2193,6 +2312,7 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         if (nrhs < 1) fail(HS_EINVAL, "nrhs must be >= 1");
         if (P && P->H != H) fail(HS_EINVAL, "the preconditioner belongs to another H-matrix");
         const bool mixed = opts->method == HS_SOLVE_FGMRES_MIXED;
+        if (opts->method == HS_SOLVE_TRANSFORMED) return solve_transformed(ctx, H, P, b, x, nrhs, opts, stats);
         if (opts->method != HS_SOLVE_GMRES && !mixed) fail(HS_EINVAL, "unsupported method");
         if (opts->use_x0) {
             if (mixed) fail(HS_EINVAL, "use_x0 is supported by HS_SOLVE_GMRES only");
@@ -2262,10 +2382,11 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
                     hip_check(hipMemcpyAsync(out, in, sizeof(cd) * n * ns, hipMemcpyDeviceToDevice, s), "D2D");
                     return;
                 }
-                sw.epoch += 1;
+                sw.epoch_f += 1;
+                sw.epoch_b += 1;
                 sweeps_begin(ctx->device, s);
-                hs::launch_sweep(true, mk, P->sp32, P->items, in, out, ns, sw.w, sw.epoch, s);
-                hs::launch_sweep(false, mk, P->sp32, P->items, in, out, ns, sw.w, sw.epoch, s);
+                hs::launch_sweep(true, mk, P->sp32, P->items, in, out, ns, sw.w, sw.epoch_f, s);
+                hs::launch_sweep(false, mk, P->sp32, P->items, in, out, ns, sw.w, sw.epoch_b, s);
                 sweeps_end(ctx->device, s);
             };
             // one flexible preconditioning step: z = approximate Z^-1 v for the

@@ -338,10 +338,15 @@ static_assert(kRowWorkers * 4 == kMaxChunk, "one point row per wave of the row w
 static_assert(kFoldCols % 64 == 0 && kFoldCols >= kMaxChunk, "fold range in whole wavefront groups");
 // One sweep (forward: v -> y in the work buffers; backward: D^-1 y -> z);
 // the backward launch must follow the forward one of the same epoch.
+// (dinv false: the backward sweep applies alpha alone, without D^-1)
 void launch_sweep(bool forward, const ColMask& mk, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z,
-                  int nrhs, const SweepWork& w, int epoch, hipStream_t s);
+                  int nrhs, const SweepWork& w, int epoch, hipStream_t s, bool dinv = true);
 void launch_sweep(bool forward, const ColMask& mk, const SweepPlanT<cf>& p, const SweepItems& it, const cd* v, cd* z,
-                  int nrhs, const SweepWork& w, int epoch, hipStream_t s);
+                  int nrhs, const SweepWork& w, int epoch, hipStream_t s, bool dinv = true);
+// tree order <-> the sweeps' elimination-order buffer (to_elim: tree -> elimination)
+void launch_elim_move(const SweepPlan& p, const cd* src, cd* dst, int nrhs, bool to_elim, hipStream_t s);
+// out = add + D^-1 in, block by block in tree order (add may be null)
+void launch_block_dinv(const SweepPlan& p, const cd* in, const cd* add, cd* out, int nrhs, hipStream_t s);
 int sweep_grid(int64_t nitems);
 // Workgroups of the sweep kernels that can be resident at once on a device;
 // the row workers spin for the whole launch, so this must exceed

@@ -664,7 +664,7 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
 template <int S, int Q, class T>
 __global__ void __launch_bounds__(NT)
 k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, SweepWork wk, int nrhs,
-            unsigned long long base, int epoch) {
+            unsigned long long base, int epoch, int dmode) {
     __shared__ int s_t;
     __shared__ cd ysh[kMaxLeaf * S];
     __shared__ cd ztsh[kMaxLeaf * S];
@@ -779,7 +779,9 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
                 for (int q = tid; q < bk * cs; q += NT) ysh[q] = wk.ybuf[pk + q % bk + (int64_t)(c0 + q / bk) * n];
                 __syncthreads();
                 constexpr int RQ = rb_of<Q>();
-                for (int a0 = wid; a0 < bk; a0 += NW * RQ) {
+                if (!dmode)   // alpha alone (no block-diagonal solve): r'_k = y_k + slots
+                    for (int q = tid; q < bk * cs; q += NT) ztsh[q] = ysh[q];
+                for (int a0 = dmode ? wid : bk; a0 < bk; a0 += NW * RQ) {
                     cd Dr[RQ][Q];
 #pragma unroll
                     for (int r = 0; r < RQ; ++r)
@@ -954,7 +956,7 @@ int sweep_capacity(int device) {
 namespace {
 template <class T>
 void sweep(bool forward, const ColMask& mk, const SweepPlanT<T>& p, const SweepItems& it, const cd* v, cd* z, int nrhs,
-           const SweepWork& w, int epoch, hipStream_t s) {
+           const SweepWork& w, int epoch, bool dinv, hipStream_t s) {
     const int64_t nit = forward ? it.nfwd : it.nbwd;
     const int G = sweep_grid(nit);
     const unsigned long long base = (unsigned long long)(epoch - 1) * (unsigned long long)(nit + G);
@@ -964,7 +966,8 @@ void sweep(bool forward, const ColMask& mk, const SweepPlanT<T>& p, const SweepI
         if (forward)                                                                                               \
             hipLaunchKernelGGL((k_sweep_fwd<SS, QQ, T>), dim3(G), dim3(NT), 0, s, mk, p, it, v, w, nrhs, base, epoch); \
         else                                                                                                       \
-            hipLaunchKernelGGL((k_sweep_bwd<SS, QQ, T>), dim3(G), dim3(NT), 0, s, mk, p, it, z, w, nrhs, base, epoch); \
+            hipLaunchKernelGGL((k_sweep_bwd<SS, QQ, T>), dim3(G), dim3(NT), 0, s, mk, p, it, z, w, nrhs, base, epoch, \
+                               (int)dinv);                                                                     \
     } while (0)
     if (nrhs == 1) {
         if (wide) HS_SWEEP(1, 2); else HS_SWEEP(1, 1);
@@ -976,12 +979,50 @@ void sweep(bool forward, const ColMask& mk, const SweepPlanT<T>& p, const SweepI
 }  // namespace
 
 void launch_sweep(bool forward, const ColMask& mk, const SweepPlan& p, const SweepItems& it, const cd* v, cd* z,
-                  int nrhs, const SweepWork& w, int epoch, hipStream_t s) {
-    sweep(forward, mk, p, it, v, z, nrhs, w, epoch, s);
+                  int nrhs, const SweepWork& w, int epoch, hipStream_t s, bool dinv) {
+    sweep(forward, mk, p, it, v, z, nrhs, w, epoch, dinv, s);
 }
 void launch_sweep(bool forward, const ColMask& mk, const SweepPlanT<cf>& p, const SweepItems& it, const cd* v, cd* z,
-                  int nrhs, const SweepWork& w, int epoch, hipStream_t s) {
-    sweep(forward, mk, p, it, v, z, nrhs, w, epoch, s);
+                  int nrhs, const SweepWork& w, int epoch, hipStream_t s, bool dinv) {
+    sweep(forward, mk, p, it, v, z, nrhs, w, epoch, dinv, s);
+}
+
+// Vectors between tree order and the sweeps' elimination-order work buffer
+// (block k at pos[k]); N x nrhs, column stride n in both.
+__global__ void k_elim_move(SweepPlan p, const cd* __restrict__ src, cd* __restrict__ dst, int nrhs, int to_elim) {
+    const int k = blockIdx.x, c = blockIdx.y;
+    const int bk = p.bsize[k];
+    const int64_t t0 = p.bstart[k] + (int64_t)c * p.n, e0 = p.pos[k] + (int64_t)c * p.n;
+    for (int a = threadIdx.x; a < bk; a += blockDim.x) {
+        if (to_elim) dst[e0 + a] = src[t0 + a];
+        else dst[t0 + a] = src[e0 + a];
+    }
+}
+
+// out = add + D^-1 in block by block (add may be null), tree order; one
+// workgroup per block and column, one wave per row of D_k^-1.
+__global__ void __launch_bounds__(NT) k_block_dinv(SweepPlan p, const cd* __restrict__ in, const cd* __restrict__ add,
+                                                   cd* __restrict__ out, int nrhs) {
+    const int k = blockIdx.x, c = blockIdx.y;
+    const int bk = p.bsize[k];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    const int64_t t0 = p.bstart[k] + (int64_t)c * p.n;
+    const cd* Di = p.dinv + p.dinv_off[k];
+    for (int a = wid; a < bk; a += NW) {
+        cd s = cmk(0.0, 0.0);
+        for (int b = lane; b < bk; b += kWave) s = cfma(Di[(int64_t)a * bk + b], in[t0 + b], s);
+        s = wave_sum(s);
+        if (lane == 0) out[t0 + a] = add ? cadd(add[t0 + a], s) : s;
+    }
+}
+
+void launch_elim_move(const SweepPlan& p, const cd* src, cd* dst, int nrhs, bool to_elim, hipStream_t s) {
+    if (p.nb > 0)
+        hipLaunchKernelGGL(k_elim_move, dim3(p.nb, nrhs), dim3(64), 0, s, p, src, dst, nrhs, (int)to_elim);
+}
+
+void launch_block_dinv(const SweepPlan& p, const cd* in, const cd* add, cd* out, int nrhs, hipStream_t s) {
+    if (p.nb > 0) hipLaunchKernelGGL(k_block_dinv, dim3(p.nb, nrhs), dim3(NT), 0, s, p, in, add, out, nrhs);
 }
 
 void launch_linv(const SweepPlan& p, int nchunk, const int32_t* chunk_first, const int64_t* intptr,

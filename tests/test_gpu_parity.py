@@ -128,7 +128,7 @@ def test_matvec_and_symmetry(env, c1_oracle, nrhs):
 
 
 @pytest.mark.parametrize("case", ["c1", "pair", "plate"])
-@pytest.mark.parametrize("kind", ["natural", "rcm", "cm"])
+@pytest.mark.parametrize("kind", ["natural", "rcm", "cm", "sloan", "king"])
 def test_precond_exact_parity(env, case, kind):
     # fill_tol = 0: every alpha block dense; D_k, alpha and P^-1 v against the oracle
     hsl, torch, ctx = env

@@ -193,3 +193,52 @@ def test_preconditioned_and_plain_solutions_agree():
     Zh = hmatrix.dense_h(hm)
     cond = np.linalg.cond(Zh)
     assert np.linalg.norm(a.x - p.x) <= 2 * cond * 1e-10 * np.linalg.norm(p.x)
+
+
+# ---- the transformed system of Eq. 25-28 ---------------------------------------
+
+def test_transformed_near_field_is_block_diagonal():
+    # alpha^T Z_N alpha = D (Eq. 20-21, 26-27) by brute force: apply the
+    # operators to every unit vector of a small case, fill_tol = 0
+    from oracle import transformed as otr
+    hm, _ = _small_hm(n=180, leaf=10, seed=12)
+    for kind in ("natural", "rcm"):
+        order = ordering.make_order(kind, hm.tree.nb, hm.part.near)
+        sym = symbolic.symbolic(hm.tree.nb, hm.part.near, order)
+        pc = schur.precond_setup(hm, sym, 0.0)
+        n = hm.n
+        A = np.zeros((n, n), dtype=complex)
+        AT = np.zeros((n, n), dtype=complex)
+        for i in range(n):
+            e = np.zeros(n, dtype=complex)
+            e[i] = 1.0
+            A[:, i] = otr.alpha(pc, e)
+            AT[:, i] = otr.alpha_T(pc, e)
+        assert np.allclose(AT, A.T, rtol=0, atol=1e-12 * np.abs(A).max())
+        ZN = hmatrix.dense_near(hm)
+        T = A.T @ ZN @ A
+        Dd = np.zeros((n, n), dtype=complex)
+        for k in range(pc.nb):
+            s = slice(int(pc.start[k]), int(pc.start[k] + pc.size[k]))
+            Dd[s, s] = pc.D[k]
+        assert np.linalg.norm(T - Dd) <= 1e-10 * np.linalg.norm(Dd)
+
+
+def test_transformed_solve_matches_right_preconditioned_solve():
+    from oracle import transformed as otr
+    wl = W.make_config("c1", n=700)
+    hm = hmatrix.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, 1e-4)
+    b = wl.rhs[:, 0]
+    pc0 = pipeline.precond_setup(hm, "rcm", 0.0)
+    x, st, res = otr.solve(hm, pc0, b, restart=30, tol=1e-10)
+    ref = pipeline.solve(hm, pc0, b, restart=30, tol=1e-10)
+    assert st.converged and res <= 1e-8
+    assert np.linalg.norm(x - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+    # with compressed fill-ins the transformed system is perturbed
+    # (alpha^T Z_N alpha != D): its solution's true residual sits near
+    # fill_tol / 10 (measured 6.7e-4 at 1e-2, 4.9e-5 at 1e-3), which is
+    # what is reported
+    for ft in (1e-2, 1e-3):
+        pc = pipeline.precond_setup(hm, "rcm", ft)
+        x2, st2, res2 = otr.solve(hm, pc, b, restart=30, tol=1e-6)
+        assert st2.converged and 1e-6 < res2 < ft
