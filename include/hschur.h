@@ -61,6 +61,10 @@ extern "C" {
 #define HS_ORDER_SLOAN      3   /* Sloan's profile and wavefront reduction (Table 3, Fig. 7; used for Sec. 5) */
 #define HS_ORDER_KING       4   /* King's front-minimising ordering (Table 3, Fig. 6) */
 
+#define HS_PC_SCHUR         0   /* the symmetric near-field Schur-complement preconditioner */
+#define HS_PC_BLOCK_JACOBI  1   /* comparator: P^-1 = blockdiag(Z_kk)^-1, the leaves' own near blocks inverted,
+                                   no coupling (ordering and fill_tol ignored; FP64 only) */
+
 #define HS_PREC_FP64        0   /* complex128 throughout */
 #define HS_PREC_MIXED       1   /* also keep complex64 copies of the apply's matrices (for HS_SOLVE_FGMRES_MIXED) */
 
@@ -75,6 +79,10 @@ extern "C" {
                                    stats report the true ||b - Z x|| / ||b||, which meets tol only up to the
                                    fill-in compression error (alpha^T Z_N alpha = D exactly at fill_tol = 0);
                                    needs P */
+#define HS_SOLVE_BLOCK_GMRES 3  /* comparator: coupled block GMRES(restart), one Krylov space shared by the
+                                   nrhs columns (block Arnoldi with block CGS2 and Cholesky QR, block
+                                   Hessenberg least squares), right-preconditioned by P (NULL = none); iters
+                                   counts block steps, max_iters bounds them; at most 256 columns */
 
 typedef struct hs_context hs_context;
 typedef struct hs_plan    hs_plan;
@@ -102,6 +110,7 @@ typedef struct {
      * send more entries through the pushed far-entry path. */
     int32_t sweep_chunk;
     int32_t sweep_fold_cols;
+    int32_t kind;         /* HS_PC_SCHUR (the method) or HS_PC_BLOCK_JACOBI (comparator) */
 } hs_precond_opts;
 
 typedef struct {

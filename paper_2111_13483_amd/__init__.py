@@ -42,7 +42,10 @@ class BuildOpts(ctypes.Structure):
 
 class PrecondOpts(ctypes.Structure):
     _fields_ = [("ordering", ctypes.c_int32), ("fill_tol", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("sweep_chunk", ctypes.c_int32), ("sweep_fold_cols", ctypes.c_int32)]
+                ("sweep_chunk", ctypes.c_int32), ("sweep_fold_cols", ctypes.c_int32), ("kind", ctypes.c_int32)]
+
+
+PC_KIND = {"schur": 0, "block_jacobi": 1}
 
 
 class SolveOpts(ctypes.Structure):
@@ -322,9 +325,11 @@ class HMatrix:
 
 class Precond:
     def __init__(self, ctx: Context, H: HMatrix, ordering: str = "rcm", fill_tol: float = 1e-2, sweep_chunk: int = 0,
-                 sweep_fold_cols: int = 0, mixed: bool = False):
+                 sweep_fold_cols: int = 0, mixed: bool = False, kind: str = "schur"):
+        """kind="block_jacobi" sets up the comparator blockdiag(Z_kk)^-1 instead."""
         self.ctx, self.H = ctx, H
-        opts = PrecondOpts(ORDER[ordering], float(fill_tol), 1 if mixed else 0, int(sweep_chunk), int(sweep_fold_cols))
+        opts = PrecondOpts(ORDER[ordering], float(fill_tol), 1 if mixed else 0, int(sweep_chunk), int(sweep_fold_cols),
+                           PC_KIND[kind])
         h = ctypes.c_void_p()
         _check(_lib.hs_precond_setup(ctx._h, H._h, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
@@ -382,12 +387,13 @@ class Stats:
 
 def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol: float = 1e-6,
           max_iters: int = 0, fixed_iters: int = 0, mixed: bool = False, inner_steps: int = 0, inner_tol: float = 0.0,
-          x0=None, transformed: bool = False):
+          x0=None, transformed: bool = False, block: bool = False):
     """Solve Z x = b: right-preconditioned GMRES, or with mixed=True FP64
     flexible GMRES whose preconditioning steps are inner GMRES solves on the
     complex64 copies; x0 (GMRES only) is the initial guess; transformed=True
     solves the paper's transformed system (Eq. 25-28) instead, its stats
-    holding the true residual. Returns (x, [Stats per column])."""
+    holding the true residual; block=True runs the coupled block-GMRES
+    comparator (iters = block steps). Returns (x, [Stats per column])."""
     torch = _torch()
     bc, s = _dev_c128(b, H.n)
     if x0 is None:
@@ -396,7 +402,7 @@ def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol
         x, s0 = _dev_c128(x0, H.n)
         if s0 != s:
             raise HschurError(HS_EINVAL, "x0 and b differ in columns")
-    method = 2 if transformed else (1 if mixed else 0)
+    method = 3 if block else (2 if transformed else (1 if mixed else 0))
     opts = SolveOpts(method, restart, tol, max_iters, fixed_iters, inner_steps, inner_tol,
                      0 if x0 is None else 1)
     st = (SolveStats * s)()

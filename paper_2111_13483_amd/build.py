@@ -60,7 +60,8 @@ def build(verbose: bool = False) -> str:
             if o.strip():
                 print(o)
     tmp = OUT + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs +
+         ["-L" + os.path.join(ROCM, "lib"), "-lrocblas", "-Wl,-rpath," + os.path.join(ROCM, "lib")])
     os.replace(tmp, OUT)
     # C-ABI-only driver for hardware-counter runs (links the library by rpath)
     tmp = BENCH_EXE + ".tmp"

@@ -2,10 +2,12 @@
 // handles, device memory, orchestration of the host integer phases and the
 // gfx950 kernels of the build, setup and solve phases.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <functional>
 #include <limits>
@@ -221,6 +223,10 @@ struct hs_context {
     AuxStream aux;
     double wait_seconds = 5.0;    // bound on a sweep's device-side waits
     double clock_khz = 0.0;       // constant-rate device clock (wall_clock64)
+    rocblas_handle blas = nullptr;   // plain GEMMs of the block-GMRES comparator (created on first use)
+    ~hs_context() {
+        if (blas) (void)rocblas_destroy_handle(blas);
+    }
 };
 
 namespace {
@@ -324,6 +330,7 @@ struct hs_precond {
     int64_t alpha_t_elems = 0;
     // complex64 copies of the apply's matrices (HS_PREC_MIXED)
     bool c64 = false;
+    bool block_jacobi = false;   // HS_PC_BLOCK_JACOBI: P^-1 = blockdiag(Z_kk)^-1
     hs::SweepPlanT<hs::cf> sp32{};
 };
 
@@ -621,6 +628,10 @@ void sweeps_release(int device, hipStream_t s) {
 
 void apply_tree(hs_context* ctx, const hs_precond* P, const cd* v, cd* z, int nrhs, SweepWs& ws, hipStream_t s,
                 const hs::ColMask& mk) {
+    if (P->block_jacobi) {
+        hs::launch_block_dinv(P->sp, v, nullptr, z, nrhs, s);
+        return;
+    }
     ws.epoch_f += 1;
     ws.epoch_b += 1;
     sweeps_begin(ctx->device, s);
@@ -1174,7 +1185,21 @@ struct SetupJob {
         P->H = H;
         P->plan.tree = H->plan.tree;
         P->plan.part = H->plan.part;
-        P->plan.sym = make_symbolic(H->plan, opts->ordering);
+        if (opts->kind == HS_PC_BLOCK_JACOBI) {
+            // the comparator: no coupling between leaves, natural order, so
+            // the setup inverts the diagonal near blocks Z_kk and nothing else
+            hs::Partition self;
+            for (int64_t l = 0; l < H->nb; ++l) {
+                self.near.push_back(l);
+                self.near.push_back(l);
+            }
+            std::vector<int64_t> id(H->nb);
+            for (int64_t l = 0; l < H->nb; ++l) id[l] = l;
+            P->plan.sym = hs::symbolic(H->nb, self, id);
+            P->block_jacobi = true;
+        } else {
+            P->plan.sym = make_symbolic(H->plan, opts->ordering);
+        }
         P->plan.has_sym = true;
         const hs::Symbolic& sy = P->plan.sym;
         const hs::Partition& p = H->plan.part;
@@ -1933,6 +1958,9 @@ int32_t hs_precond_setup_many(hs_context* ctx, int64_t count, const hs_hmatrix* 
             if (opts->ordering < 0 || opts->ordering > 4) fail(HS_EINVAL, "unknown ordering");
             if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
             if (opts->precision != HS_PREC_FP64 && opts->precision != HS_PREC_MIXED) fail(HS_EINVAL, "unsupported precision");
+            if (opts->kind != HS_PC_SCHUR && opts->kind != HS_PC_BLOCK_JACOBI) fail(HS_EINVAL, "unknown preconditioner kind");
+            if (opts->kind == HS_PC_BLOCK_JACOBI && opts->precision != HS_PREC_FP64)
+                fail(HS_EINVAL, "the block-Jacobi comparator is FP64 only");
             if (opts->sweep_chunk < 0 || opts->sweep_chunk > hs::kMaxChunk) fail(HS_EINVAL, "sweep_chunk must be in [0, 384]");
             const int32_t chunk_lim = opts->sweep_chunk > 0 ? opts->sweep_chunk : hs::kMaxChunk;
             if (opts->sweep_fold_cols != 0 && (opts->sweep_fold_cols < chunk_lim || opts->sweep_fold_cols > hs::kFoldCols))
@@ -2210,6 +2238,262 @@ void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& mat
     }
 }
 
+
+// ---- coupled block GMRES (comparator) -----------------------------------------------
+
+typedef std::complex<double> zc;
+
+void blas_check(rocblas_status st, const char* what) {
+    if (st != rocblas_status_success) fail(HS_EHIP, std::string(what) + ": rocBLAS status " + std::to_string((int)st));
+}
+
+rocblas_handle ctx_blas(hs_context* ctx) {
+    if (!ctx->blas) blas_check(rocblas_create_handle(&ctx->blas), "rocblas_create_handle");
+    blas_check(rocblas_set_stream(ctx->blas, ctx->stream), "rocblas_set_stream");
+    blas_check(rocblas_set_pointer_mode(ctx->blas, rocblas_pointer_mode_host), "rocblas_set_pointer_mode");
+    return ctx->blas;
+}
+
+const rocblas_double_complex* rz(const zc* p) { return reinterpret_cast<const rocblas_double_complex*>(p); }
+const rocblas_double_complex* rz(const cd* p) { return reinterpret_cast<const rocblas_double_complex*>(p); }
+rocblas_double_complex* rz(cd* p) { return reinterpret_cast<rocblas_double_complex*>(p); }
+
+// Cholesky G = C^H C of an s x s Hermitian matrix (column-major); false if a
+// pivot is not positive (the columns are dependent).
+bool chol_upper(const std::vector<zc>& G, int s, std::vector<zc>& C) {
+    C.assign((size_t)s * s, zc(0.0, 0.0));
+    for (int j = 0; j < s; ++j) {
+        for (int i = 0; i <= j; ++i) {
+            zc sum = G[(size_t)i + (size_t)j * s];
+            for (int l = 0; l < i; ++l) sum -= std::conj(C[(size_t)l + (size_t)i * s]) * C[(size_t)l + (size_t)j * s];
+            if (i == j) {
+                const double d = sum.real();
+                if (!(d > 0.0)) return false;
+                C[(size_t)j + (size_t)j * s] = zc(std::sqrt(d), 0.0);
+            } else {
+                C[(size_t)i + (size_t)j * s] = sum / C[(size_t)i + (size_t)i * s];
+            }
+        }
+    }
+    return true;
+}
+
+// In place W (n x s, device) = Q R by Cholesky QR applied twice; R (host,
+// s x s upper, column-major) = C2 C1. False on dependent columns.
+bool cholqr2(rocblas_handle hb, cd* W, int64_t n, int s, cd* d_g, std::vector<zc>& R, hipStream_t st) {
+    const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
+    std::vector<zc> G((size_t)s * s), C, Rt((size_t)s * s, zc(0.0, 0.0));
+    for (int i = 0; i < s; ++i) Rt[(size_t)i + (size_t)i * s] = zc(1.0, 0.0);
+    for (int pass = 0; pass < 2; ++pass) {
+        blas_check(rocblas_zgemm(hb, rocblas_operation_conjugate_transpose, rocblas_operation_none, s, s, (int)n, &one,
+                                 rz(W), (int)n, rz(W), (int)n, &zero, rz(d_g), s), "zgemm (W^H W)");
+        hip_check(hipMemcpyAsync(G.data(), d_g, sizeof(zc) * s * s, hipMemcpyDeviceToHost, st), "D2H");
+        hip_check(hipStreamSynchronize(st), "stream sync");
+        if (!chol_upper(G, s, C)) return false;
+        hip_check(hipMemcpyAsync(d_g, C.data(), sizeof(zc) * s * s, hipMemcpyHostToDevice, st), "H2D");
+        blas_check(rocblas_ztrsm(hb, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                                 rocblas_diagonal_non_unit, (int)n, s, &one, rz(d_g), s, rz(W), (int)n),
+                   "ztrsm (W C^-1)");
+        std::vector<zc> nr((size_t)s * s, zc(0.0, 0.0));   // C Rt
+        for (int j = 0; j < s; ++j)
+            for (int i = 0; i <= j; ++i) {
+                zc acc(0.0, 0.0);
+                for (int l = i; l <= j; ++l) acc += C[(size_t)i + (size_t)l * s] * Rt[(size_t)l + (size_t)j * s];
+                nr[(size_t)i + (size_t)j * s] = acc;
+            }
+        Rt.swap(nr);
+    }
+    R.swap(Rt);
+    return true;
+}
+
+// min || rhs - H Y ||_F column by column for H (M x K, column-major, M > K)
+// by complex Householder QR; returns Y (K x ns) and each column's residual norm.
+void block_ls(std::vector<zc> H, int M, int K, std::vector<zc> rhs, int ns, std::vector<zc>& Y,
+              std::vector<double>& res) {
+    for (int c = 0; c < K; ++c) {
+        double nrm = 0.0;
+        for (int i = c; i < M; ++i) nrm += std::norm(H[(size_t)i + (size_t)c * M]);
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) continue;
+        const zc a = H[(size_t)c + (size_t)c * M];
+        const zc ph = std::abs(a) > 0.0 ? a / std::abs(a) : zc(1.0, 0.0);
+        const zc alpha = -ph * nrm;
+        std::vector<zc> v((size_t)(M - c));
+        for (int i = c; i < M; ++i) v[(size_t)(i - c)] = H[(size_t)i + (size_t)c * M];
+        v[0] -= alpha;
+        double vn = 0.0;
+        for (auto& e : v) vn += std::norm(e);
+        if (vn == 0.0) continue;
+        auto reflect = [&](zc* col) {
+            zc d(0.0, 0.0);
+            for (int i = c; i < M; ++i) d += std::conj(v[(size_t)(i - c)]) * col[i];
+            d *= 2.0 / vn;
+            for (int i = c; i < M; ++i) col[i] -= d * v[(size_t)(i - c)];
+        };
+        for (int j = c; j < K; ++j) reflect(&H[(size_t)j * M]);
+        for (int j = 0; j < ns; ++j) reflect(&rhs[(size_t)j * M]);
+    }
+    Y.assign((size_t)K * ns, zc(0.0, 0.0));
+    res.assign(ns, 0.0);
+    for (int j = 0; j < ns; ++j) {
+        for (int i = K - 1; i >= 0; --i) {
+            zc sum = rhs[(size_t)i + (size_t)j * M];
+            for (int l = i + 1; l < K; ++l) sum -= H[(size_t)i + (size_t)l * M] * Y[(size_t)l + (size_t)j * K];
+            const zc d = H[(size_t)i + (size_t)i * M];
+            Y[(size_t)i + (size_t)j * K] = std::abs(d) > 0.0 ? sum / d : zc(0.0, 0.0);
+        }
+        double r = 0.0;
+        for (int i = K; i < M; ++i) r += std::norm(rhs[(size_t)i + (size_t)j * M]);
+        res[j] = std::sqrt(r);
+    }
+}
+
+// Coupled block GMRES(m), right-preconditioned: one Krylov space for the
+// nrhs columns (see hschur.h). Steps are block steps.
+int32_t solve_block(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, const void* b, void* x, int64_t nrhs,
+                    const hs_solve_opts* opts, hs_solve_stats* stats) {
+    if (opts->use_x0) fail(HS_EINVAL, "use_x0 is supported by HS_SOLVE_GMRES only");
+    const int m = opts->restart;
+    if (m < 1 || m > hs::kMaxRankCap) fail(HS_EINVAL, "restart must be in [1, 256]");
+    if (!(opts->tol >= 0.0)) fail(HS_EINVAL, "tol must be >= 0");
+    if (nrhs > 256) fail(HS_EINVAL, "block GMRES takes at most 256 columns");
+    const int budget = opts->fixed_iters > 0 ? opts->fixed_iters : (opts->max_iters > 0 ? opts->max_iters : 5000);
+    const bool fixed = opts->fixed_iters > 0;
+    set_device(ctx);
+    hipStream_t st = ctx->stream;
+    rocblas_handle hb = ctx_blas(ctx);
+    const int64_t n = H->n;
+    const int ns = (int)nrhs;
+    const int64_t blk = n * ns;
+    Owned w;
+    w.mem = ctx->mem;
+    cd* bt = w.get<cd>(blk);
+    cd* xt = w.get<cd>(blk);
+    cd* V = w.get<cd>((size_t)(m + 1) * blk);
+    cd* Wt = w.get<cd>(blk);
+    cd* tmp = w.get<cd>(blk);
+    cd* d_h = w.get<cd>((size_t)(m + 1) * ns * ns);
+    cd* d_g = w.get<cd>((size_t)ns * ns);
+    cd* d_y = w.get<cd>((size_t)m * ns * ns);
+    cd* slots = w.get<cd>((size_t)H->slot_total * ns);
+    const int nchunk = hs::gmres_nchunk(n);
+    double* npart = w.get<double>((size_t)nchunk * ns);
+    SweepWs sw;
+    if (P) sw = make_sweep_ws(w, P, ns, st, ctx);
+    hs::launch_permute(static_cast<const cd*>(b), bt, H->d_perm, n, ns, true, st);
+    hip_check(hipMemsetAsync(xt, 0, sizeof(cd) * blk, st), "memset");
+    auto col_norms = [&](const cd* v) {
+        hs::launch_col_norms(v, n, ns, npart, nchunk, st);
+        std::vector<double> pp = download(npart, (size_t)nchunk * ns, st);
+        std::vector<double> out(ns, 0.0);
+        for (int c = 0; c < ns; ++c) {
+            for (int ch = 0; ch < nchunk; ++ch) out[c] += pp[(size_t)ch * ns + c];
+            out[c] = std::sqrt(out[c]);
+        }
+        return out;
+    };
+    auto precond = [&](const cd* in, cd* out) {
+        if (P) apply_tree(ctx, P, in, out, ns, sw, st, kAllCols);
+        else hip_check(hipMemcpyAsync(out, in, sizeof(cd) * blk, hipMemcpyDeviceToDevice, st), "D2D");
+    };
+    const std::vector<double> bn = col_norms(bt);
+    const rocblas_double_complex one{1.0, 0.0}, mone{-1.0, 0.0}, zero{0.0, 0.0};
+    int steps = 0;
+    std::vector<double> rel(ns, 1.0);
+    bool first = true;
+    for (;;) {
+        // R = B - Z X into V_0, then V_0 S = R
+        if (first) {
+            hip_check(hipMemcpyAsync(V, bt, sizeof(cd) * blk, hipMemcpyDeviceToDevice, st), "D2D");
+        } else {
+            matvec_tree(ctx, H, xt, tmp, ns, slots, st, kAllCols);
+            hs::launch_residual(bt, tmp, V, n, ns, npart, nchunk, st);
+        }
+        first = false;
+        std::vector<zc> S;
+        if (!cholqr2(hb, V, n, ns, d_g, S, st)) break;   // dependent residual columns
+        std::vector<zc> Hb((size_t)(m + 1) * ns * m * ns, zc(0.0, 0.0));
+        const int M0 = (m + 1) * ns;
+        std::vector<zc> Y;
+        int k = 0;
+        while (k < m && steps < budget) {
+            cd* Vk = V + (size_t)k * blk;
+            cd* Vn = V + (size_t)(k + 1) * blk;
+            precond(Vk, Wt);
+            matvec_tree(ctx, H, Wt, Vn, ns, slots, st, kAllCols);
+            const int kc = (k + 1) * ns;
+            std::vector<zc> h((size_t)kc * ns, zc(0.0, 0.0)), h2((size_t)kc * ns);
+            for (int pass = 0; pass < 2; ++pass) {
+                blas_check(rocblas_zgemm(hb, rocblas_operation_conjugate_transpose, rocblas_operation_none, kc, ns,
+                                         (int)n, &one, rz(V), (int)n, rz(Vn), (int)n, &zero, rz(d_h), kc),
+                           "zgemm (V^H W)");
+                blas_check(rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)n, ns, kc, &mone,
+                                         rz(V), (int)n, rz(d_h), kc, &one, rz(Vn), (int)n),
+                           "zgemm (W - V H)");
+                hip_check(hipMemcpyAsync(h2.data(), d_h, sizeof(zc) * kc * ns, hipMemcpyDeviceToHost, st), "D2H");
+                hip_check(hipStreamSynchronize(st), "stream sync");
+                for (size_t e = 0; e < h.size(); ++e) h[e] += h2[e];
+            }
+            std::vector<zc> Hn;
+            const bool ok = cholqr2(hb, Vn, n, ns, d_g, Hn, st);
+            for (int j = 0; j < ns; ++j) {
+                for (int i = 0; i < kc; ++i) Hb[(size_t)i + (size_t)(k * ns + j) * M0] = h[(size_t)i + (size_t)j * kc];
+                for (int i = 0; i < ns; ++i)
+                    Hb[(size_t)(kc + i) + (size_t)(k * ns + j) * M0] = ok ? Hn[(size_t)i + (size_t)j * ns] : zc(0.0, 0.0);
+            }
+            ++k;
+            ++steps;
+            // least squares on the leading (k + 1) s x k s block
+            const int M = (k + 1) * ns, K = k * ns;
+            std::vector<zc> Hk((size_t)M * K), rhs((size_t)M * ns, zc(0.0, 0.0));
+            for (int j = 0; j < K; ++j)
+                for (int i = 0; i < M; ++i) Hk[(size_t)i + (size_t)j * M] = Hb[(size_t)i + (size_t)j * M0];
+            for (int j = 0; j < ns; ++j)
+                for (int i = 0; i < ns; ++i) rhs[(size_t)i + (size_t)j * M] = S[(size_t)i + (size_t)j * ns];
+            std::vector<double> lsr;
+            block_ls(Hk, M, K, rhs, ns, Y, lsr);
+            bool done = !fixed;
+            for (int c = 0; c < ns; ++c) done &= lsr[c] <= opts->tol * bn[c];
+            if (done || !ok) break;
+        }
+        if (k == 0) break;
+        // X += P^-1 (V Y)
+        const int K = k * ns;
+        hip_check(hipMemcpyAsync(d_y, Y.data(), sizeof(zc) * K * ns, hipMemcpyHostToDevice, st), "H2D");
+        blas_check(rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)n, ns, K, &one, rz(V),
+                                 (int)n, rz(d_y), K, &zero, rz(tmp), (int)n),
+                   "zgemm (V Y)");
+        precond(tmp, Wt);
+        blas_check(rocblas_zaxpy(hb, (int)blk, &one, rz(Wt), 1, rz(xt), 1), "zaxpy");
+        // true residual
+        matvec_tree(ctx, H, xt, tmp, ns, slots, st, kAllCols);
+        hs::launch_residual(bt, tmp, Wt, n, ns, npart, nchunk, st);
+        std::vector<double> pp = download(npart, (size_t)nchunk * ns, st);
+        bool all = true;
+        for (int c = 0; c < ns; ++c) {
+            double r = 0.0;
+            for (int ch = 0; ch < nchunk; ++ch) r += pp[(size_t)ch * ns + c];
+            rel[c] = bn[c] > 0.0 ? std::sqrt(r) / bn[c] : 0.0;
+            all &= rel[c] <= opts->tol;
+        }
+        if (steps >= budget || (!fixed && all)) break;
+    }
+    hs::launch_permute(xt, static_cast<cd*>(x), H->d_perm, n, ns, false, st);
+    hip_check(hipGetLastError(), "block GMRES launches");
+    hip_check(hipStreamSynchronize(st), "stream sync");
+    if (P) check_sweep_flag(sw, st);
+    bool all_conv = true;
+    for (int c = 0; c < ns; ++c) {
+        stats[c].iters = steps;
+        stats[c].relres = rel[c];
+        stats[c].converged = rel[c] <= opts->tol ? 1 : 0;
+        if (!std::isfinite(rel[c])) fail(HS_ENUMERIC, "NaN or Inf in the residual");
+        all_conv &= stats[c].converged != 0;
+    }
+    return all_conv ? HS_OK : HS_NOT_CONVERGED;
+}
+
 // The paper's transformed system (Eq. 25-28): GMRES on
 //   x~ + D^-1 alpha^T Z_F alpha x~ = D^-1 alpha^T b,  x = alpha x~,
 // with the identity as right preconditioner, so the iteration monitors the
@@ -2218,7 +2502,7 @@ void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& mat
 // with the full operator and reported in stats.
 int32_t solve_transformed(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, const void* b, void* x,
                           int64_t nrhs, const hs_solve_opts* opts, hs_solve_stats* stats) {
-    if (!P) fail(HS_EINVAL, "the transformed system needs a preconditioner (its alpha and D)");
+    if (!P || P->block_jacobi) fail(HS_EINVAL, "the transformed system needs a Schur preconditioner (its alpha and D)");
     if (opts->use_x0) fail(HS_EINVAL, "use_x0 is supported by HS_SOLVE_GMRES only");
     const int m = opts->restart;
     if (m < 1 || m > hs::kMaxRankCap) fail(HS_EINVAL, "restart must be in [1, 256]");
@@ -2313,6 +2597,7 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         if (P && P->H != H) fail(HS_EINVAL, "the preconditioner belongs to another H-matrix");
         const bool mixed = opts->method == HS_SOLVE_FGMRES_MIXED;
         if (opts->method == HS_SOLVE_TRANSFORMED) return solve_transformed(ctx, H, P, b, x, nrhs, opts, stats);
+        if (opts->method == HS_SOLVE_BLOCK_GMRES) return solve_block(ctx, H, P, b, x, nrhs, opts, stats);
         if (opts->method != HS_SOLVE_GMRES && !mixed) fail(HS_EINVAL, "unsupported method");
         if (opts->use_x0) {
             if (mixed) fail(HS_EINVAL, "use_x0 is supported by HS_SOLVE_GMRES only");

@@ -242,3 +242,49 @@ def test_transformed_solve_matches_right_preconditioned_solve():
         pc = pipeline.precond_setup(hm, "rcm", ft)
         x2, st2, res2 = otr.solve(hm, pc, b, restart=30, tol=1e-6)
         assert st2.converged and 1e-6 < res2 < ft
+
+
+# ---- comparators: block Jacobi and coupled block GMRES --------------------------
+
+def test_block_jacobi_is_block_diagonal_solve():
+    from oracle import comparators as ocmp
+    hm, rng = _small_hm(n=200, leaf=12, seed=31)
+    bj = ocmp.block_jacobi_setup(hm)
+    v = rng.normal(size=hm.n) + 1j * rng.normal(size=hm.n)
+    ZN = hmatrix.dense_near(hm)
+    Bd = np.zeros_like(ZN)
+    for leaf in range(hm.tree.nb):
+        a, b = hm.leaf_range(leaf)
+        Bd[a:b, a:b] = ZN[a:b, a:b]
+    assert np.allclose(ocmp.block_jacobi_apply(bj, v), np.linalg.solve(Bd, v), rtol=0,
+                       atol=1e-11 * np.linalg.norm(v))
+
+
+def test_block_gmres_one_column_is_gmres():
+    from oracle import comparators as ocmp
+    from oracle import gmres as ogm
+    wl = W.make_config("c1", n=500)
+    hm = hmatrix.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, 1e-4)
+    pc = pipeline.precond_setup(hm, "rcm", 1e-2)
+    mv = lambda v: hmatrix.matvec(hm, v)          # noqa: E731
+    pre = lambda v: schur.apply(pc, v)            # noqa: E731
+    b = wl.rhs[hm.tree.perm, 0]
+    x1, st1 = ogm.gmres(mv, pre, b, 20, 1e-6, fixed_iters=27)
+    X, st = ocmp.block_gmres(mv, pre, b[:, None], 20, 1e-6, fixed_steps=27)
+    assert np.linalg.norm(X[:, 0] - x1) <= 1e-10 * np.linalg.norm(x1)
+
+
+def test_block_gmres_exact_in_n_over_s_steps():
+    # a 48-point system with 4 right-hand sides: the block Krylov space fills
+    # the whole space after 12 block steps, so X is the dense solution
+    from oracle import comparators as ocmp
+    rng = np.random.default_rng(4)
+    pts = W.fibonacci_sphere(48, rng)
+    hm = hmatrix.h_build(pts, 3.0, np.sqrt(4 * np.pi / 48), 8, 1e-13)
+    Z = hmatrix.dense_h(hm)
+    Bm = rng.normal(size=(48, 4)) + 1j * rng.normal(size=(48, 4))
+    X, st = ocmp.block_gmres(lambda v: Z @ v, lambda v: v, Bm, 12, 0.0, fixed_steps=12)
+    ref = np.linalg.solve(Z, Bm)
+    assert np.linalg.norm(X - ref) <= 1e-9 * np.linalg.norm(ref)
+    X2, st2 = ocmp.block_gmres(lambda v: Z @ v, lambda v: v, Bm, 12, 1e-10)
+    assert st2.converged and st2.steps <= 12
