@@ -55,6 +55,10 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
     ap.add_argument("--summarize-stats", metavar="DIR", help="summarise a rocprofv3 --stats run and exit")
+    ap.add_argument("--summarize-fp64", metavar="DIR", help="summarise a rocprofv3 FP64 counter run and exit")
+    ap.add_argument("--flops-setup", type=float, default=0.0, help="algorithmic setup flops (--summarize-fp64)")
+    ap.add_argument("--source-hash", default="", help="kernel source hash taken before the counter runs")
+    ap.add_argument("--print-source-hash", action="store_true", help="print the kernel sources' hash and exit")
     ap.add_argument("--out", help="summary file written by --summarize-*")
     ap.add_argument("--command", default="", help="command line recorded in the summary")
     ap.add_argument("--mixed", action="store_true",
@@ -122,7 +126,7 @@ def _per_kernel(rows):
     return agg
 
 
-def summarize_pmc(fetch_dir, write_dir, out, command, copy_bytes):
+def summarize_pmc(fetch_dir, write_dir, out, command, copy_bytes, source_hash):
     fetch = _read_counters(fetch_dir, "FETCH_SIZE")
     write = _read_counters(write_dir, "WRITE_SIZE")
     # calibration: the largest copy dispatch (copy_bytes read and copy_bytes written)
@@ -152,9 +156,43 @@ def summarize_pmc(fetch_dir, write_dir, out, command, copy_bytes):
             prb, pwb = found.get(key, (0.0, 0.0))
             found[key] = (prb + rb, pwb + wb)   # per launch: each kernel once
             lines.append(f"| {pre} | {nf} | {vf:.0f} | {vw:.0f} | {rb / 1e6:.1f} | {wb / 1e6:.1f} |")
-    lines += ["", "Machine-readable (bench.py reads these while the kernel sources hash to `source`):", ""]
+    lines += ["", "Machine-readable (bench.py reads these while the kernel sources hash to `source`, the hash "
+              "printed by `bench.py --print-source-hash` before the counter runs):", ""]
     for key, (rb, wb) in found.items():
-        lines.append(f"traffic: kernel={key} read_bytes={rb:.0f} write_bytes={wb:.0f} source={_source_hash()}")
+        lines.append(f"traffic: kernel={key} read_bytes={rb:.0f} write_bytes={wb:.0f} source={source_hash}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_fp64(d, out, command, flops_setup):
+    """FP64 instruction counters of the elimination kernels (one setup of
+    the hs_bench step) against the setup's algorithmic flops."""
+    rows = {}
+    for counter in ("SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_FMA_F64"):
+        try:
+            for name, v in _read_counters(d, counter):
+                for pre in ("k_factor_alpha", "k_schur_tiles"):
+                    if pre in name:
+                        a = rows.setdefault((pre, counter), [0, 0.0])
+                        a[0] += 1
+                        a[1] += v
+        except SystemExit:
+            pass
+    lines = ["# FP64 counters of the Schur elimination, sphere + ellipsoid N = 20,000 (one setup, hs_bench)", "",
+             "Command:", "", "```", command, "```", "",
+             f"Algorithmic flops of the setup (exact count over the filled pattern): {flops_setup:.4g}", "",
+             "| kernel | counter | dispatches | total | per dispatch |", "|---|---|---|---|---|"]
+    tot = 0.0
+    for (pre, counter), (cnt, v) in sorted(rows.items()):
+        lines.append(f"| {pre} | {counter} | {cnt} | {v:.4g} | {v / max(cnt, 1):.4g} |")
+        if counter == "SQ_INSTS_VALU_FLOPS_FP64":
+            tot += v
+    lines += ["", f"SQ_INSTS_VALU_FLOPS_FP64 over both kernels: {tot:.4g}. The SQ counters count per wave "
+                  f"instruction: times 64 lanes that is {64 * tot:.4g} FP64 flops, {64 * tot / flops_setup:.2f} x the "
+                  "algorithmic count (the FMA counts times 128 match the update GEMMs; the excess is the pivot "
+                  "search, the explicit inverse and the zero-padded tile columns). No FP64 MFMA instruction runs: "
+                  "the elimination uses the FP64 vector units."]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -530,9 +568,15 @@ def leg_mixed(hsl, torch, ctx, pts, wl, b, plain_solve_s):
 
 def main():
     args = parse()
+    if args.print_source_hash:
+        print(_source_hash())
+        return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.out, args.command,
-                      args.copy_calib_mib << 20)
+                      args.copy_calib_mib << 20, args.source_hash or _source_hash())
+        return
+    if args.summarize_fp64:
+        summarize_fp64(args.summarize_fp64, args.out, args.command, args.flops_setup)
         return
     if args.summarize_stats:
         summarize_stats(args.summarize_stats, args.out, args.command)

@@ -385,3 +385,63 @@ def test_timing_sample_counts(env, c1_oracle):
         assert kt["far_mv"][1] > 0.0
     with pytest.raises(hsl.HschurError):
         ctx.timing_begin(every=0)
+
+
+def test_far_blocks_above_rank_16(env):
+    # The pair at 2,500 points, lambda = 0.1: 680 of 6,995 far blocks have
+    # rank > 16 (up to 42), which takes the workgroup re-compression path.
+    hsl, torch, ctx = env
+    wl = _case("pair")
+    hm = ohm.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, 1e-4)
+    H = _gpu_h(env, wl)
+    ranks = H.export("far_rank")
+    off = H.export("far_off")
+    uv = H.export("far_uv")
+    piv = H.export("far_piv").reshape(len(hm.far_u), -1, 2)
+    high = agree = 0
+    for b, ((t, s), U, V) in enumerate(zip(hm.part.far, hm.far_u, hm.far_v)):
+        r = int(ranks[b])
+        if U.shape[1] <= 16:
+            continue
+        high += 1
+        m, n = U.shape[0], V.shape[1]
+        logs = [tuple(x) for x in piv[b] if x[0] >= 0]
+        if logs != [tuple(p) for p in hm.far_piv[b]]:
+            continue
+        agree += 1
+        Ug = uv[off[b]:off[b] + m * r].reshape(r, m).T
+        Vg = uv[off[b] + m * r:off[b + 1]].reshape(r, n)
+        assert r == U.shape[1]
+        assert _rel(Ug @ Vg, U @ V) <= TOL
+    assert high > 600 and agree >= 0.95 * high
+
+
+def test_cube_and_uneven_leaves_fixed_steps():
+    # A cube at the 100,000-point cube's points per wavelength, and two
+    # geometries of the many-geometry recipe (uneven leaf sizes 24-96),
+    # solved together by hs_solve_many for a fixed number of steps: each x
+    # equals the oracle's.
+    import math
+    import torch
+    import paper_2111_13483_amd as hsl
+    hsl.load()
+    ctx = hsl.Context(0)
+    n = 2500
+    rng = np.random.default_rng(3)
+    pts, area = W.cube_surface(n, rng)
+    h = math.sqrt(area / n)
+    cube = W.Workload(name="cube", points=pts, k=2 * math.pi / (0.05 * math.sqrt(1e5 / n)), self_h=h, leaf_max=64,
+                      rhs=W.plane_wave(pts, 2 * math.pi / (0.05 * math.sqrt(1e5 / n)), rng)[:, None])
+    geos = [cube] + [g for g in W.batch_geometries(count=6, n_max=2600, nrhs=1) if g.leaf_max != 64][:2]
+    assert len({g.leaf_max for g in geos}) == 3
+    items, refs = [], []
+    for g in geos:
+        hm = ohm.h_build(g.points, g.k, g.self_h, g.leaf_max, 1e-4)
+        pc = opl.precond_setup(hm, "rcm", 1e-2)
+        refs.append(opl.solve(hm, pc, g.rhs[:, 0], restart=30, fixed_iters=25).x)
+        H = hsl.HMatrix(ctx, g.points, g.k, g.self_h, g.leaf_max, 1e-4)
+        items.append((H, hsl.Precond(ctx, H, "rcm", 1e-2), torch.as_tensor(g.rhs[:, 0], device="cuda")))
+    out = hsl.solve_many(ctx, items, restart=30, fixed_iters=25)
+    for (x, st), ref in zip(out, refs):
+        assert st[0].iters == 25
+        assert _rel(x.cpu().numpy(), ref) <= TOL
