@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--batch-nmax", type=int, default=40000, help="largest N of the batching run")
     ap.add_argument("--batch-ppl", type=float, default=3.2, help="points per wavelength of the batching run")
     ap.add_argument("--batch-restart", type=int, default=50, help="GMRES restart of the batching run")
+    ap.add_argument("--batch-tune", action="store_true", help="autotune the apply layout for the batch")
     ap.add_argument("--serve", action="store_true",
                     help="serving run instead of the step benchmark: resident geometries, Poisson request arrivals")
     ap.add_argument("--serve-rates", default="10,30,100", help="request arrival rates per second")
@@ -257,8 +258,16 @@ def batch(args):
     t_single = time.perf_counter() - t0
     del Ps1
     print(f"batch: setups one by one {t_single:.2f} s", file=sys.stderr, flush=True)
+    layout, tune_s, tune_ms = (0, 0), 0.0, None
+    if args.batch_tune:
+        # the autotuner on the largest geometry; its layout serves the batch
+        big = int(np.argmax([wl.n for wl in geos]))
+        t0 = time.perf_counter()
+        layout, tune_ms = hsl.Precond.tune(ctx, Hs[big], "rcm", geos[big].fill_tol, nrhs=4, reps=5)
+        tune_s = time.perf_counter() - t0
+        print(f"batch: tuned apply layout {layout} in {tune_s:.2f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    Ps = hsl.Precond.many(ctx, Hs, "rcm", geos[0].fill_tol)
+    Ps = hsl.Precond.many(ctx, Hs, "rcm", geos[0].fill_tol, sweep_chunk=layout[0], sweep_fold_cols=layout[1])
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     print(f"batch: batched setup {t_batched:.2f} s", file=sys.stderr, flush=True)
@@ -290,6 +299,7 @@ def batch(args):
            "h_build_s": t_build, "setup_one_by_one_s": t_single, "setup_batched_s": t_batched,
            "setup_speedup": t_single / t_batched, "solve_one_by_one_s": t_solve1, "solve_together_s": t_many,
            "solve_speedup": t_solve1 / t_many, "rhs_per_s": cols / t_many, "rhs_per_s_one_by_one": cols / t_solve1,
+           "tuned_layout": list(layout), "tune_s": tune_s, "tune_apply_ms": tune_ms,
            "iters_max": max(iters), "iters_median": float(np.median(iters)), "all_converged": conv}
     print(json.dumps(out), flush=True)
 

@@ -232,6 +232,18 @@ int32_t hs_precond_setup(hs_context* ctx, const hs_hmatrix* H, const hs_precond_
  * those of separate hs_precond_setup calls. */
 int32_t hs_precond_setup_many(hs_context* ctx, int64_t count, const hs_hmatrix* const* Hs,
                               const hs_precond_opts* opts, hs_precond** out);
+/* Apply-layout autotuner (the evaluation layout of the sweeps, hs_precond_opts
+ * sweep_chunk x sweep_fold_cols): sets up H's preconditioner with each layout
+ * of a fixed grid (chunks 384, 256, 192 points x folded ranges 3072, 2048,
+ * 1536 columns, range >= chunk: 9 layouts), times `reps` applies of nrhs
+ * columns of each with HIP events on the context's stream after one warm-up
+ * apply, and writes the fastest layout to *best (the other fields as in
+ * opts). times_ms (NULL or 9 entries) receives each layout's average apply
+ * time in grid order; *ncand (may be NULL) the number of layouts. Every
+ * layout gives the same operator (the triangular solves in another order).
+ * Errors: HS_EINVAL (NULL, nrhs or reps < 1, a block-Jacobi kind), setup errors. */
+int32_t hs_precond_tune(hs_context* ctx, const hs_hmatrix* H, const hs_precond_opts* opts, int32_t nrhs, int32_t reps,
+                        hs_precond_opts* best, double* times_ms, int32_t* ncand);
 int32_t hs_query_precond(const hs_precond* P, hs_info* info);
 void    hs_precond_destroy(hs_precond* P);
 

@@ -119,6 +119,8 @@ def load(path: str = LIB_PATH):
         "hs_precond_setup": (i32, [vp, vp, ctypes.POINTER(PrecondOpts), pvp]),
         "hs_precond_setup_many": (i32, [vp, i64, pvp, ctypes.POINTER(PrecondOpts), pvp]),
         "hs_query_precond": (i32, [vp, ctypes.POINTER(Info)]),
+        "hs_precond_tune": (i32, [vp, vp, ctypes.POINTER(PrecondOpts), i32, i32, ctypes.POINTER(PrecondOpts),
+                                  ctypes.POINTER(dbl), ctypes.POINTER(i32)]),
         "hs_precond_destroy": (None, [vp]),
         "hs_solve": (i32, [vp, vp, vp, vp, vp, i64, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)]),
         "hs_matvec": (i32, [vp, vp, vp, vp, i64]),
@@ -156,7 +158,7 @@ def load(path: str = LIB_PATH):
 EXPORTED = (
     "hs_context_create", "hs_context_set_stream", "hs_context_set_wait_limit", "hs_context_destroy", "hs_plan_create", "hs_plan_query",
     "hs_plan_destroy", "hs_plan_export", "hs_h_build", "hs_query_hmatrix", "hs_hmatrix_destroy", "hs_precond_setup",
-    "hs_precond_setup_many", "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_matvec_noalloc", "hs_precond_apply", "hs_hmatrix_export",
+    "hs_precond_setup_many", "hs_precond_tune", "hs_query_precond", "hs_precond_destroy", "hs_solve", "hs_matvec", "hs_matvec_noalloc", "hs_precond_apply", "hs_hmatrix_export",
     "hs_precond_export", "hs_timing_begin", "hs_timing_begin_every", "hs_timing_end", "hs_server_clock",
     "hs_server_create",
     "hs_server_admit", "hs_server_add_geometry", "hs_server_geometry", "hs_solve_many", "hs_server_submit", "hs_server_step", "hs_server_pending", "hs_server_request",
@@ -350,6 +352,18 @@ class Precond:
             P._h = ctypes.c_void_p(h)
             res.append(P)
         return res
+
+    @staticmethod
+    def tune(ctx: Context, H: HMatrix, ordering: str = "rcm", fill_tol: float = 1e-2, nrhs: int = 1, reps: int = 10):
+        """hs_precond_tune: the fastest apply layout; returns
+        ((sweep_chunk, sweep_fold_cols), [average apply ms per layout])."""
+        opts = PrecondOpts(ORDER[ordering], float(fill_tol), 0, 0, 0, 0)
+        best = PrecondOpts()
+        times = (ctypes.c_double * 9)()
+        k = ctypes.c_int32()
+        _check(_lib.hs_precond_tune(ctx._h, H._h, ctypes.byref(opts), int(nrhs), int(reps), ctypes.byref(best), times,
+                                    ctypes.byref(k)))
+        return (best.sweep_chunk, best.sweep_fold_cols), [times[i] for i in range(k.value)]
 
     def info(self) -> dict:
         inf = Info()

@@ -1998,6 +1998,71 @@ int32_t hs_precond_setup_many(hs_context* ctx, int64_t count, const hs_hmatrix* 
     }
 }
 
+int32_t hs_precond_tune(hs_context* ctx, const hs_hmatrix* H, const hs_precond_opts* opts, int32_t nrhs, int32_t reps,
+                        hs_precond_opts* best, double* times_ms, int32_t* ncand) {
+    try {
+        if (!ctx || !H || !opts || !best) fail(HS_EINVAL, "NULL argument");
+        if (nrhs < 1 || reps < 1) fail(HS_EINVAL, "nrhs and reps must be >= 1");
+        if (opts->kind != HS_PC_SCHUR) fail(HS_EINVAL, "the layouts belong to the Schur preconditioner");
+        // the candidate grid: chunk sizes x folded-range widths (width >= chunk)
+        static const int32_t chunks[] = {384, 256, 192};
+        static const int32_t folds[] = {3072, 2048, 1536};
+        set_device(ctx);
+        hipStream_t s = ctx->stream;
+        const int64_t n = H->n;
+        Owned w;
+        w.mem = ctx->mem;
+        cd* v = w.get<cd>((size_t)n * nrhs);
+        cd* z = w.get<cd>((size_t)n * nrhs);
+        std::vector<cd> ones((size_t)n * nrhs);
+        for (auto& e : ones) { e.x = 1.0; e.y = 0.0; }
+        hip_check(hipMemcpyAsync(v, ones.data(), sizeof(cd) * ones.size(), hipMemcpyHostToDevice, s), "H2D");
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "hipEventCreate");
+        hip_check(hipEventCreate(&e1), "hipEventCreate");
+        double best_ms = 0.0;
+        int32_t k = 0;
+        for (int32_t c : chunks) {
+            for (int32_t f : folds) {
+                if (f < c) continue;
+                hs_precond_opts o = *opts;
+                o.sweep_chunk = c;
+                o.sweep_fold_cols = f;
+                hs_precond* P = nullptr;
+                const int32_t rc = hs_precond_setup(ctx, H, &o, &P);
+                if (rc != HS_OK) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return rc;
+                }
+                std::unique_ptr<hs_precond, void (*)(hs_precond*)> pg(P, hs_precond_destroy);
+                SweepWs sw = make_sweep_ws(w, P, nrhs, s, ctx);
+                apply_tree(ctx, P, v, z, nrhs, sw, s, kAllCols);   // warm-up
+                hip_check(hipEventRecord(e0, s), "hipEventRecord");
+                for (int32_t r = 0; r < reps; ++r) apply_tree(ctx, P, v, z, nrhs, sw, s, kAllCols);
+                hip_check(hipEventRecord(e1, s), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                check_sweep_flag(sw, s);
+                float ms = 0.0f;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                const double avg = (double)ms / reps;
+                if (times_ms) times_ms[k] = avg;
+                if (k == 0 || avg < best_ms) {
+                    best_ms = avg;
+                    *best = o;
+                }
+                ++k;
+            }
+        }
+        if (ncand) *ncand = k;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return HS_OK;
+    } catch (const Error& e) {
+        return set_error(e);
+    }
+}
+
 int32_t hs_query_precond(const hs_precond* P, hs_info* info) {
     if (!P || !info) { g_last_error = "NULL argument"; return HS_EINVAL; }
     fill_info_plan(P->plan, info);
