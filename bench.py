@@ -65,6 +65,10 @@ def parse():
                     help="mixed path: FP64 flexible GMRES with inner GMRES on complex64 copies")
     ap.add_argument("--mixed-restart", type=int, default=20, help="outer FGMRES restart of the mixed path")
     ap.add_argument("--mixed-inner", type=int, default=20, help="inner GMRES steps of the mixed path")
+    ap.add_argument("--fill-study", action="store_true", help="fill-in compression study on the plate")
+    ap.add_argument("--table2", action="store_true",
+                    help="symmetric against non-symmetric elimination on the 5,985-point plate")
+    ap.add_argument("--setup-scaling", action="store_true", help="setup cost against N on the plate")
     ap.add_argument("--orderings", action="store_true",
                     help="ordering trend study (natural, CM, RCM, King, Sloan) on the 5,985-point plate")
     ap.add_argument("--batch", type=int, default=0, metavar="G",
@@ -73,6 +77,8 @@ def parse():
     ap.add_argument("--batch-ppl", type=float, default=3.2, help="points per wavelength of the batching run")
     ap.add_argument("--batch-restart", type=int, default=50, help="GMRES restart of the batching run")
     ap.add_argument("--batch-tune", action="store_true", help="autotune the apply layout for the batch")
+    ap.add_argument("--batch-max-iters", type=int, default=2000, help="GMRES step cap per column in the batch run")
+    ap.add_argument("--batch-group", type=int, default=16, help="geometries per hs_solve_many call")
     ap.add_argument("--serve", action="store_true",
                     help="serving run instead of the step benchmark: resident geometries, Poisson request arrivals")
     ap.add_argument("--serve-rates", default="10,30,100", help="request arrival rates per second")
@@ -273,16 +279,26 @@ def batch(args):
     print(f"batch: batched setup {t_batched:.2f} s", file=sys.stderr, flush=True)
     bs = [torch.as_tensor(np.ascontiguousarray(wl.rhs), device="cuda") for wl in geos]
     restart = args.batch_restart
+    mi = args.batch_max_iters
     t0 = time.perf_counter()
     iters1 = []
-    for wl, H, P, b in zip(geos, Hs, Ps, bs):
-        x, st = hsl.solve(ctx, H, P, b, restart=restart, tol=wl.tol)
+    for i, (wl, H, P, b) in enumerate(zip(geos, Hs, Ps, bs)):
+        x, st = hsl.solve(ctx, H, P, b, restart=restart, tol=wl.tol, max_iters=mi)
         iters1.append(max(q.iters for q in st))
+        print(f"batch: geometry {i} ({wl.name}, N={wl.n}, leaf {wl.leaf_max}) alone: {iters1[-1]} steps",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_solve1 = time.perf_counter() - t0
     print(f"batch: solves one geometry at a time {t_solve1:.2f} s", file=sys.stderr, flush=True)
+    # together, in groups of batch_group geometries per hs_solve_many call
     t0 = time.perf_counter()
-    res = hsl.solve_many(ctx, [(H, P, b) for H, P, b in zip(Hs, Ps, bs)], restart=restart, tol=geos[0].tol)
+    res = []
+    g = args.batch_group
+    for q in range(0, len(geos), g):
+        res += hsl.solve_many(ctx, [(H, P, b) for H, P, b in zip(Hs[q:q + g], Ps[q:q + g], bs[q:q + g])],
+                              restart=restart, tol=geos[0].tol, max_iters=mi)
+        print(f"batch: geometries {q}-{min(q + g, len(geos)) - 1} together done at "
+              f"{time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_many = time.perf_counter() - t0
     print(f"batch: all geometries together {t_many:.2f} s", file=sys.stderr, flush=True)
@@ -292,7 +308,8 @@ def batch(args):
     out = {"metric": "batched setup s and RHS solves/s over many geometries vs plain per-geometry FP64",
            "unit": "s, RHS/s", "data": "synthetic", "n_gpus": 1, "dtype": "c128",
            "config": {"workload": f"{len(geos)} geometries, N in [2000, {args.batch_nmax}], leaves 24-96, "
-                                  f"lambda = {args.batch_ppl} h, 4 plane waves each, GMRES({restart}) to 1e-6",
+                                  f"lambda = {args.batch_ppl} h, 4 plane waves each, GMRES({restart}) to 1e-6 "
+                                  f"(at most {mi} steps), {g} geometries per hs_solve_many call",
                       "sum_n": int(sum(wl.n for wl in geos)),
                       "kinds": {k: sum(1 for wl in geos if wl.name == k) for k in ("sphere", "ellipsoid", "cube",
                                                                                    "plate")}},
@@ -300,7 +317,8 @@ def batch(args):
            "setup_speedup": t_single / t_batched, "solve_one_by_one_s": t_solve1, "solve_together_s": t_many,
            "solve_speedup": t_solve1 / t_many, "rhs_per_s": cols / t_many, "rhs_per_s_one_by_one": cols / t_solve1,
            "tuned_layout": list(layout), "tune_s": tune_s, "tune_apply_ms": tune_ms,
-           "iters_max": max(iters), "iters_median": float(np.median(iters)), "all_converged": conv}
+           "iters_max": max(iters), "iters_median": float(np.median(iters)), "all_converged": conv,
+           "unconverged_columns": sum(1 for _, st in res for q in st if not q.converged)}
     print(json.dumps(out), flush=True)
 
 
@@ -441,6 +459,128 @@ def orderings(args):
     print(json.dumps({"metric": "near-field ordering trends on the 5,985-point plate", "data": "synthetic",
                       "config": {"workload": "plate 2 x 2 x 0.05, N = 5985, lambda = 10 h, ACA 1e-4, fill 1e-2, "
                                              "GMRES(30) to 1e-6"}, "rows": rows}), flush=True)
+
+
+def table2(args):
+    """Symmetric against non-symmetric elimination (Sec. 3.2, Table 2) on the
+    synthetic 5,985-point plate: setup time (median of three after one warm
+    setup) and the elimination kernels' own time, per leaf size and ordering
+    (Table 2's symmetric time equals Table 3's unordered one, so the paper
+    ran it in natural order)."""
+    import torch
+    import paper_2111_13483_amd as hsl
+    import workloads as W
+
+    ctx = hsl.Context(0)
+    wl = W.make_config("plate", n=5985)
+    rows = []
+    for leaf in (32, 96):
+        H = hsl.HMatrix(ctx, wl.points, wl.k, wl.self_h, leaf, wl.aca_tol)
+        for order in ("natural", "sloan"):
+            row = {"leaf_max": leaf, "ordering": order}
+            for kind in ("schur", "schur_nonsym"):
+                ts = []
+                for rep in range(5):
+                    if rep == 4:
+                        ctx.timing_begin(every=1)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    P = hsl.Precond(ctx, H, order, wl.fill_tol, kind=kind)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                    del P
+                kt = ctx.timing_end()
+                tag = "sym" if kind == "schur" else "nonsym"
+                row[f"setup_s_{tag}"] = float(np.median(ts[1:4]))
+                row[f"elimination_ms_{tag}"] = kt["factor"][1] + kt["schur"][1]
+                row[f"elimination_launches_{tag}"] = kt["factor"][2] + kt["schur"][2]
+            row["setup_ratio"] = row["setup_s_nonsym"] / row["setup_s_sym"]
+            row["elimination_ratio"] = row["elimination_ms_nonsym"] / row["elimination_ms_sym"]
+            rows.append(row)
+            print(f"table2: leaf {leaf} {order}: setup {row['setup_s_sym']:.4f} s symmetric, "
+                  f"{row['setup_s_nonsym']:.4f} s non-symmetric; elimination {row['elimination_ms_sym']:.2f} / "
+                  f"{row['elimination_ms_nonsym']:.2f} ms", file=sys.stderr, flush=True)
+        del H
+    print(json.dumps({"metric": "symmetric vs non-symmetric preconditioner setup (Sec. 3.2, Table 2 trend)",
+                      "data": "synthetic", "paper_ratio": 140.02 / 90.59,
+                      "config": {"workload": "plate 2 x 2 x 0.05, N = 5985, lambda = 10 h, ACA 1e-4, fill 1e-2"},
+                      "rows": rows}), flush=True)
+
+
+def fill_study(args):
+    """Fill-in compression tolerance (Table 6 analogue) on the 5,985-point
+    plate at leaf 96: stored scaling-coefficient bytes and low-rank blocks,
+    apply time and GMRES steps for fill_tol 0 (dense), 1e-3 and 1e-2."""
+    import torch
+    import paper_2111_13483_amd as hsl
+    import workloads as W
+
+    ctx = hsl.Context(0)
+    wl = W.make_config("plate", n=5985)
+    H = hsl.HMatrix(ctx, wl.points, wl.k, wl.self_h, 96, wl.aca_tol)
+    b = torch.as_tensor(wl.rhs[:, 0], device="cuda")
+    v = torch.as_tensor(np.random.default_rng(1).normal(size=wl.n) + 0j, device="cuda")
+    rows = []
+    for ft in (0.0, 1e-3, 1e-2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = hsl.Precond(ctx, H, "sloan", ft)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        P.apply(v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            P.apply(v)
+        torch.cuda.synchronize()
+        t_apply = (time.perf_counter() - t0) / 20
+        x, st = hsl.solve(ctx, H, P, b, restart=wl.restart, tol=wl.tol)
+        pi = P.info()
+        rows.append({"fill_tol": ft, "alpha_bytes": pi["bytes_alpha"], "lowrank_blocks": pi["n_lowrank"],
+                     "fill_blocks": pi["n_fill"], "setup_s": t_setup, "apply_ms": 1e3 * t_apply,
+                     "gmres_iters": st[0].iters, "relres": st[0].relres})
+        print(f"fill: {ft:g}: alpha {pi['bytes_alpha'] / 1e6:.1f} MB, apply {1e3 * t_apply:.3f} ms, "
+              f"{st[0].iters} steps", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "fill-in compression (Sec. 3.4, Table 6 trend)", "data": "synthetic",
+                      "config": {"workload": "plate 2 x 2 x 0.05, N = 5985, lambda = 10 h, leaf 96, Sloan, "
+                                             "GMRES(30) to 1e-6"}, "rows": rows}), flush=True)
+
+
+def setup_scaling(args):
+    """Setup cost against N (Sec. 4, Fig. 8 trend): the plate at a fixed 3.2
+    points per wavelength and leaf 64, N doubling; setup time, its
+    elimination time, exact setup flops and stored coefficient bytes."""
+    import math as _m
+    import torch
+    import paper_2111_13483_amd as hsl
+    import workloads as W
+
+    ctx = hsl.Context(0)
+    rows = []
+    for n in (4000, 8000, 16000, 32000, 64000, 128000):
+        rng = np.random.default_rng(n)
+        pts, area = W.plate_box(n, rng)
+        h = _m.sqrt(area / n)
+        H = hsl.HMatrix(ctx, pts, 2.0 * _m.pi / (3.2 * h), h, 64, 1e-4)
+        ts = []
+        for rep in range(2):
+            if rep == 1:
+                ctx.timing_begin(every=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P = hsl.Precond(ctx, H, "sloan", 1e-2)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        kt = ctx.timing_end()
+        pi = P.info()
+        rows.append({"n": n, "nb": pi["nb"], "setup_s": ts[1], "elimination_ms": kt["factor"][1] + kt["schur"][1],
+                     "setup_flops": pi["flops_setup"], "alpha_bytes": pi["bytes_alpha"],
+                     "flops_per_point": pi["flops_setup"] / n})
+        print(f"scaling: N={n}: setup {ts[1]:.3f} s, flops {pi['flops_setup']:.3e}", file=sys.stderr, flush=True)
+        del P, H
+    print(json.dumps({"metric": "setup cost against N (Sec. 4 trend)", "data": "synthetic",
+                      "config": {"workload": "plate 2 x 2 x 0.05, lambda = 3.2 h, leaf 64, Sloan, fill 1e-2"},
+                      "rows": rows}), flush=True)
 
 
 def committed_traffic():
@@ -605,6 +745,15 @@ def main():
         return
     if args.orderings:
         orderings(args)
+        return
+    if args.fill_study:
+        fill_study(args)
+        return
+    if args.table2:
+        table2(args)
+        return
+    if args.setup_scaling:
+        setup_scaling(args)
         return
     import torch
     import paper_2111_13483_amd as hsl

@@ -64,6 +64,12 @@ extern "C" {
 #define HS_PC_SCHUR         0   /* the symmetric near-field Schur-complement preconditioner */
 #define HS_PC_BLOCK_JACOBI  1   /* comparator: P^-1 = blockdiag(Z_kk)^-1, the leaves' own near blocks inverted,
                                    no coupling (ordering and fill_tol ignored; FP64 only) */
+#define HS_PC_SCHUR_NONSYM  2   /* comparator (Sec. 3.2, Table 2): the same preconditioner from the non-symmetric
+                                   elimination, which keeps both triangles of the working matrix, forms the left
+                                   coefficients alpha'_ik = -W_ik W_kk^-1 (Eq. 14) beside the right ones
+                                   (Eq. 16) and updates every pair of S_k instead of i <= j; the apply uses
+                                   alpha as HS_PC_SCHUR does (alpha' = alpha^T for the symmetric Z here), and
+                                   HS_P_ALPHA_LEFT exports alpha' */
 
 #define HS_PREC_FP64        0   /* complex128 throughout */
 #define HS_PREC_MIXED       1   /* also keep complex64 copies of the apply's matrices (for HS_SOLVE_FGMRES_MIXED) */
@@ -110,7 +116,7 @@ typedef struct {
      * send more entries through the pushed far-entry path. */
     int32_t sweep_chunk;
     int32_t sweep_fold_cols;
-    int32_t kind;         /* HS_PC_SCHUR (the method) or HS_PC_BLOCK_JACOBI (comparator) */
+    int32_t kind;         /* HS_PC_SCHUR (the method), HS_PC_BLOCK_JACOBI or HS_PC_SCHUR_NONSYM (comparators) */
 } hs_precond_opts;
 
 typedef struct {
@@ -350,6 +356,9 @@ int32_t hs_timing_end(hs_context* ctx, hs_kernel_times* out);
  *  HS_P_ALPHA_KIND int64 n_pattern rank of the stored block, -1 = dense
  *  HS_P_ALPHA_OFF  int64 n_pattern+1 element offsets into HS_P_ALPHA
  *  HS_P_ALPHA      complex128      dense blocks b_k x b_j row-major, or U (b_k x r col-major) then V (r x b_j row-major)
+ *  HS_P_ALPHA_LEFT complex128      HS_PC_SCHUR_NONSYM only (else HS_EINVAL): per pattern entry (k, j), in
+ *                                  pattern order and back to back, alpha'_jk^T as a dense b_k x b_j row-major
+ *                                  block, before fill-in compression
  */
 #define HS_H_NEAR_OFF   101
 #define HS_H_NEAR_DATA  102
@@ -361,6 +370,7 @@ int32_t hs_timing_end(hs_context* ctx, hs_kernel_times* out);
 #define HS_P_ALPHA_KIND 202
 #define HS_P_ALPHA_OFF  203
 #define HS_P_ALPHA      204
+#define HS_P_ALPHA_LEFT 205
 int32_t hs_hmatrix_export(const hs_hmatrix* H, int32_t what, void* dst, int64_t cap, int64_t* needed);
 int32_t hs_precond_export(const hs_precond* P, int32_t what, void* dst, int64_t cap, int64_t* needed);
 

@@ -26,7 +26,7 @@ HS_EINVAL, HS_ENOMEM, HS_ENODEVICE, HS_EHIP, HS_ESINGULAR, HS_ENUMERIC, HS_ETIME
 ORDER = {"natural": 0, "rcm": 1, "cm": 2, "sloan": 3, "king": 4}
 X_CODES = {"perm": 1, "leaf_off": 2, "boxes": 3, "near": 4, "far": 5, "order": 6, "rowptr": 7, "cols": 8, "orig": 9}
 H_CODES = {"near_off": 101, "near_data": 102, "far_rank": 103, "far_off": 104, "far_uv": 105, "far_piv": 106}
-P_CODES = {"d": 201, "alpha_kind": 202, "alpha_off": 203, "alpha": 204}
+P_CODES = {"d": 201, "alpha_kind": 202, "alpha_off": 203, "alpha": 204, "alpha_left": 205}
 
 
 class HschurError(RuntimeError):
@@ -45,7 +45,7 @@ class PrecondOpts(ctypes.Structure):
                 ("sweep_chunk", ctypes.c_int32), ("sweep_fold_cols", ctypes.c_int32), ("kind", ctypes.c_int32)]
 
 
-PC_KIND = {"schur": 0, "block_jacobi": 1}
+PC_KIND = {"schur": 0, "block_jacobi": 1, "schur_nonsym": 2}
 
 
 class SolveOpts(ctypes.Structure):
@@ -328,7 +328,9 @@ class HMatrix:
 class Precond:
     def __init__(self, ctx: Context, H: HMatrix, ordering: str = "rcm", fill_tol: float = 1e-2, sweep_chunk: int = 0,
                  sweep_fold_cols: int = 0, mixed: bool = False, kind: str = "schur"):
-        """kind="block_jacobi" sets up the comparator blockdiag(Z_kk)^-1 instead."""
+        """kind="block_jacobi" sets up the comparator blockdiag(Z_kk)^-1 instead;
+        kind="schur_nonsym" runs the non-symmetric elimination (left
+        coefficients formed separately, export("alpha_left"))."""
         self.ctx, self.H = ctx, H
         opts = PrecondOpts(ORDER[ordering], float(fill_tol), 1 if mixed else 0, int(sweep_chunk), int(sweep_fold_cols),
                            PC_KIND[kind])
@@ -373,7 +375,7 @@ class Precond:
     def export(self, what: str) -> np.ndarray:
         if what in X_CODES:
             return _export(_lib.hs_precond_export, self._h, X_CODES[what], np.int64)
-        dt = np.complex128 if what in ("d", "alpha") else np.int64
+        dt = np.complex128 if what in ("d", "alpha", "alpha_left") else np.int64
         return _export(_lib.hs_precond_export, self._h, P_CODES[what], dt)
 
     def apply(self, v):

@@ -331,6 +331,10 @@ struct hs_precond {
     // complex64 copies of the apply's matrices (HS_PREC_MIXED)
     bool c64 = false;
     bool block_jacobi = false;   // HS_PC_BLOCK_JACOBI: P^-1 = blockdiag(Z_kk)^-1
+    // HS_PC_SCHUR_NONSYM: the left coefficients alpha'_jk, stored transposed
+    // (b_k x b_j row-major, dense, pattern entries back to back)
+    cd* d_alpha_left = nullptr;
+    int64_t alpha_left_elems = 0;
     hs::SweepPlanT<hs::cf> sp32{};
 };
 
@@ -1169,6 +1173,11 @@ struct SetupJob {
     Owned tmp;
     cd* W = nullptr;
     cd* Ad = nullptr;
+    // non-symmetric elimination: the lower blocks W_jk held as Wt_kj = W_jk^T
+    // at the W offsets, and the left coefficients alpha'_jk^T at the alpha offsets
+    bool nonsym = false;
+    cd* WL = nullptr;
+    cd* Bd = nullptr;
     int* d_err = nullptr;
     // elimination panels: the pattern in CSR (int32), per row the panel column
     // starts (ne + 1 values at rowptr[k] + k), the pair-table offsets, and the
@@ -1245,12 +1254,20 @@ struct SetupJob {
         Owned& o = P->own;
         P->d_dinv = o.get<cd>(dtot);
         P->d_D = o.get<cd>(dtot);
+        nonsym = opts->kind == HS_PC_SCHUR_NONSYM;
+        if (nonsym) {
+            WL = tmp.get<cd>(wtot);
+            Bd = o.get<cd>(atot);
+            P->d_alpha_left = Bd;
+            P->alpha_left_elems = atot;
+        }
         d_err = tmp.get<int>(1);
         hip_check(hipMemsetAsync(d_err, 0, sizeof(int), s), "memset");
         // scatter Z_N into W (row k of the working matrix = leaf order[k])
         std::map<std::pair<int64_t, int64_t>, int64_t> near_idx;
         for (int64_t e = 0; e < p.n_near(); ++e) near_idx[{p.near[2 * e], p.near[2 * e + 1]}] = e;
         std::vector<hs::CopyTask> init;
+        std::vector<hs::CopyTask> init_low;   // Wt_kj = W_jk^T = Z_kj (Z_N is symmetric)
         for (int64_t kk = 0; kk < nb; ++kk) {
             const int64_t ok = sy.order[kk];
             const int32_t bk = P->bsize[kk];
@@ -1265,11 +1282,17 @@ struct SetupJob {
                 } else {
                     init.push_back(hs::CopyTask{w_off[e], H->near_tasks[near_idx.at({oj, ok})].off, bk, bj, 1, 0});
                 }
+                if (nonsym) init_low.push_back(init.back());
             }
         }
         hs::CopyTask* d_init = tmp.upload(init, s);
         hs::launch_copy_blocks(d_init, (int64_t)init.size(), H->d_near, W, s);
         hip_check(hipGetLastError(), "k_copy_blocks launch");
+        if (nonsym) {
+            hs::CopyTask* d_low = tmp.upload(init_low, s);
+            hs::launch_copy_blocks(d_low, (int64_t)init_low.size(), H->d_near, WL, s);
+            hip_check(hipGetLastError(), "k_copy_blocks launch");
+        }
         // elimination panels of every step
         rp32.assign(nb + 1, 0);
         cols32.assign(nnz, 0);
@@ -1850,7 +1873,7 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
     tmp.mem = jobs.front()->ctx->mem;
     int64_t steps = 0;
     std::vector<hs::ElimStep> es;
-    std::vector<int64_t> base;
+    std::vector<std::vector<int32_t>> sidx;   // per job and step: its (upper) entry in es
     for (auto* j : jobs) {
         hs_precond* P = j->P.get();
         const hs::Symbolic& sy = P->plan.sym;
@@ -1862,7 +1885,7 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
         const int32_t* d_pcol = tmp.upload(j->pcol, s);
         int64_t* d_pair = tmp.get<int64_t>(std::max<int64_t>(j->pair_ptr[j->nb], 1));
         std::vector<hs::PairStep> ps;
-        base.push_back((int64_t)es.size());
+        sidx.emplace_back(j->nb);
         for (int64_t k = 0; k < j->nb; ++k) {
             const int64_t r0 = sy.rowptr[k];
             const int32_t ne = (int32_t)(sy.rowptr[k + 1] - r0);
@@ -1871,6 +1894,7 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
             e.wkk = j->W + j->wd_off[k];
             e.dinv = P->d_dinv + P->d_off[k];
             e.x = ne > 0 ? j->W + j->w_off[r0] : j->W;
+            e.xs = j->nonsym && ne > 0 ? j->WL + j->w_off[r0] : e.x;
             e.y = ne > 0 ? j->Ad + j->ad_off[r0] : j->Ad;
             e.w = j->W;
             e.pair = d_pair + j->pair_ptr[k];
@@ -1879,7 +1903,19 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
             e.bk = P->bsize[k];
             e.ne = ne;
             e.m = j->panel_m[k];
+            e.flags = 0;
+            sidx.back()[k] = (int32_t)es.size();
             es.push_back(e);
+            if (j->nonsym && ne > 0) {
+                // the left coefficients and the lower triangle's updates
+                hs::ElimStep l = e;
+                l.x = e.xs;
+                l.xs = e.x;
+                l.y = j->Bd + j->ad_off[r0];
+                l.w = j->WL;
+                l.flags = hs::kElimTrans | hs::kElimStrict;
+                es.push_back(l);
+            }
         }
         hs::PairStep* d_ps = tmp.upload(ps, s);
         hs::launch_pair_table(d_ps, (int64_t)ps.size(), j->d_err, s);
@@ -1911,11 +1947,15 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
         for (const auto& qk : launch[L]) {
             SetupJob* j = jobs[qk.first];
             const int64_t k = qk.second;
-            const int32_t step = (int32_t)(base[qk.first] + k);
+            const int32_t step = sidx[qk.first][k];
             const int32_t nt = std::max<int32_t>(1, (j->panel_m[k] + 63) / 64);
-            for (int32_t t = 0; t < nt; ++t) ft.push_back(hs::ElimTile{step, (int16_t)t, 0});
-            for (int64_t t = j->tile_ptr[k]; t < j->tile_ptr[k + 1]; ++t)
-                st.push_back(hs::ElimTile{step, j->tiles[t].first, j->tiles[t].second});
+            // the non-symmetric elimination's second entry (step + 1) exists iff row k is not empty
+            const int32_t nent = j->nonsym && j->panel_m[k] > 0 ? 2 : 1;
+            for (int32_t q = 0; q < nent; ++q) {
+                for (int32_t t = 0; t < nt; ++t) ft.push_back(hs::ElimTile{step + q, (int16_t)t, 0});
+                for (int64_t t = j->tile_ptr[k]; t < j->tile_ptr[k + 1]; ++t)
+                    st.push_back(hs::ElimTile{step + q, j->tiles[t].first, j->tiles[t].second});
+            }
         }
         fp[L + 1] = (int64_t)ft.size();
         sp[L + 1] = (int64_t)st.size();
@@ -1958,7 +1998,8 @@ int32_t hs_precond_setup_many(hs_context* ctx, int64_t count, const hs_hmatrix* 
             if (opts->ordering < 0 || opts->ordering > 4) fail(HS_EINVAL, "unknown ordering");
             if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
             if (opts->precision != HS_PREC_FP64 && opts->precision != HS_PREC_MIXED) fail(HS_EINVAL, "unsupported precision");
-            if (opts->kind != HS_PC_SCHUR && opts->kind != HS_PC_BLOCK_JACOBI) fail(HS_EINVAL, "unknown preconditioner kind");
+            if (opts->kind != HS_PC_SCHUR && opts->kind != HS_PC_BLOCK_JACOBI && opts->kind != HS_PC_SCHUR_NONSYM)
+                fail(HS_EINVAL, "unknown preconditioner kind");
             if (opts->kind == HS_PC_BLOCK_JACOBI && opts->precision != HS_PREC_FP64)
                 fail(HS_EINVAL, "the block-Jacobi comparator is FP64 only");
             if (opts->sweep_chunk < 0 || opts->sweep_chunk > hs::kMaxChunk) fail(HS_EINVAL, "sweep_chunk must be in [0, 384]");
@@ -2094,6 +2135,9 @@ int32_t hs_precond_export(const hs_precond* P, int32_t what, void* dst, int64_t 
                 return copy_host(v, dst, cap, needed);
             }
             case HS_P_ALPHA: return copy_out(P->d_alpha, P->alpha_elems * 16, dst, cap, needed, nullptr);
+            case HS_P_ALPHA_LEFT:
+                if (!P->d_alpha_left) fail(HS_EINVAL, "only a non-symmetric setup keeps the left coefficients");
+                return copy_out(P->d_alpha_left, P->alpha_left_elems * 16, dst, cap, needed, nullptr);
             default: fail(HS_EINVAL, "unknown export code");
         }
     } catch (const Error& e) {

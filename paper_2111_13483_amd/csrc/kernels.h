@@ -132,14 +132,23 @@ void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd
 struct ElimStep {
     const cd* wkk;         // W_kk, b_k x b_k row-major
     cd* dinv;              // W_kk^-1 (out)
-    const cd* x;           // W_kS panel
+    const cd* x;           // W_kS panel: the factor kernel's right-hand side
+    const cd* xs;          // the panel whose transpose is the Schur product's left operand
     cd* y;                 // alpha_kS panel (out)
     cd* w;                 // base of the Schur targets
     const int64_t* pair;   // ne (ne + 1) / 2 target offsets
     const int32_t* pcol;   // ne + 1 panel column starts
     int* err;              // device error flag of the geometry
-    int32_t bk, ne, m, pad;
+    int32_t bk, ne, m, flags;
 };
+// ElimStep flags. Symmetric elimination: none (xs = x). The non-symmetric
+// elimination (Sec. 3.2's comparator) runs two entries per step:
+//   upper: x = W_kS, xs = Wt_kS (the lower blocks W_ik stored transposed in
+//          the upper layout), y = alpha_kS; targets W_ab += W_ak alpha_kb, a <= b;
+//   lower: x = Wt_kS with kElimTrans (y = -W_kk^-T Wt_kS = alpha'_Sk^T), xs =
+//          W_kS; targets Wt_ab += W_ka^T y_kb (kElimStrict: a < b only).
+constexpr int32_t kElimTrans = 1;    // factor: y = -W_kk^-T x, and D^-1 is not written
+constexpr int32_t kElimStrict = 2;   // Schur: only targets with block(row) < block(column)
 // One workgroup's share of a step: panel column tile ti (factor/alpha) or
 // output tile (ti, tj) (Schur update).
 struct ElimTile {

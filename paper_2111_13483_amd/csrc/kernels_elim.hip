@@ -14,6 +14,12 @@
 // column g is local column g - pcol[a] of the a-th block. alpha_kS has the
 // same packing. The per-step pair table gives the offset of every target
 // block; k_pair_table fills it from the filled pattern.
+//
+// The non-symmetric elimination that Sec. 3.2 compares against (Table 2)
+// uses the same two kernels on two entries per step (ElimStep flags): the
+// left coefficients alpha'_ik = -W_ik W_kk^-1 are formed from the lower
+// blocks, held transposed in a second copy of the upper layout, and both
+// triangles receive their own Schur updates.
 #include "devcommon.h"
 
 namespace hs {
@@ -358,8 +364,9 @@ __global__ void __launch_bounds__(NTF) k_factor_alpha(const ElimStep* __restrict
     else if (b <= kWave) ok = gj_invert<8, false>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
     else ok = gj_invert<(kMaxLeaf + NWF - 1) / NWF, true>(st.wkk, b, st.err, A, colbuf, pinv, prow, srcmap);
     if (!ok) return;
+    const bool tr = (st.flags & kElimTrans) != 0;
     // W_kk^-1[i][j] = A[i][srcmap[j]]
-    if (tl.ti == 0)
+    if (tl.ti == 0 && !tr)
         for (int e = tid; e < b * b; e += NTF) {
             const int i = e / b, j = e - (e / b) * b;
             gst(st.dinv + e, A[srcmap[j] * kLdc + i]);
@@ -372,7 +379,8 @@ __global__ void __launch_bounds__(NTF) k_factor_alpha(const ElimStep* __restrict
         for (int g = lo; g < hi; ++g) cblk[g - g0] = a;
     }
     __syncthreads();
-    // alpha tile: Y[r][g] = -sum_l W_kk^-1[r][l] X[l][g], lane = column, wave = rows wv, wv + 8, ...
+    // alpha tile: Y[r][g] = -sum_l W_kk^-1[r][l] X[l][g] (kElimTrans: W_kk^-1[l][r]),
+    // lane = column, wave = rows wv, wv + 8, ...
     const int g = g0 + lane;
     if (g >= st.m) return;
     const int a = cblk[lane];
@@ -385,19 +393,44 @@ __global__ void __launch_bounds__(NTF) k_factor_alpha(const ElimStep* __restrict
 #pragma unroll
     for (int q = 0; q < RW; ++q) acc[q] = cmk(0.0, 0.0);
     constexpr int LB = 16;
-    for (int l0 = 0; l0 < b; l0 += LB) {
-        cd xv[LB];
+    if (!tr) {
+        for (int l0 = 0; l0 < b; l0 += LB) {
+            cd xv[LB];
 #pragma unroll
-        for (int u = 0; u < LB; ++u) xv[u] = gld(xg + (int64_t)(l0 + u < b ? l0 + u : b - 1) * bj);
+            for (int u = 0; u < LB; ++u) xv[u] = gld(xg + (int64_t)(l0 + u < b ? l0 + u : b - 1) * bj);
 #pragma unroll
-        for (int u = 0; u < LB; ++u) {
-            const int l = l0 + u;
-            if (l >= b) break;
-            const cd* dcol = A + srcmap[l] * kLdc;
+            for (int u = 0; u < LB; ++u) {
+                const int l = l0 + u;
+                if (l >= b) break;
+                const cd* dcol = A + srcmap[l] * kLdc;
 #pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                const int r = wv + NWF * q;
-                if (r < b) acc[q] = cfma(dcol[r], xv[u], acc[q]);
+                for (int q = 0; q < RW; ++q) {
+                    const int r = wv + NWF * q;
+                    if (r < b) acc[q] = cfma(dcol[r], xv[u], acc[q]);
+                }
+            }
+        }
+    } else {
+        // W_kk^-1[l][r] = A[srcmap[r] * kLdc + l]: this wave's rows r fix the columns of A it reads
+        int srow[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const int r = wv + NWF * q;
+            srow[q] = r < b ? srcmap[r] * kLdc : 0;
+        }
+        for (int l0 = 0; l0 < b; l0 += LB) {
+            cd xv[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) xv[u] = gld(xg + (int64_t)(l0 + u < b ? l0 + u : b - 1) * bj);
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int l = l0 + u;
+                if (l >= b) break;
+#pragma unroll
+                for (int q = 0; q < RW; ++q) {
+                    const int r = wv + NWF * q;
+                    if (r < b) acc[q] = cfma(A[srow[q] + l], xv[u], acc[q]);
+                }
             }
         }
     }
@@ -408,8 +441,9 @@ __global__ void __launch_bounds__(NTF) k_factor_alpha(const ElimStep* __restrict
     }
 }
 
-// One 64 x 64 tile (ti, tj) of C = W_kS^T alpha_kS (K = b_k), each element
-// (p, q) with block(p) <= block(q) added to its target block.
+// One 64 x 64 tile (ti, tj) of C = Xs_kS^T alpha_kS (K = b_k; Xs = W for the
+// symmetric elimination), each element (p, q) with block(p) <= block(q)
+// (kElimStrict: <) added to its target block.
 // A = cd: FP64 products; A = cf (mixed-precision setups): the panel tiles
 // are rounded to complex64 and the product is formed and accumulated in
 // FP32, then added to the FP64 target once.
@@ -426,6 +460,7 @@ __global__ void __launch_bounds__(NT) k_schur_tiles(const ElimStep* __restrict__
     __shared__ int rbj[kTile], cbj[kTile];     // its width
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
     const int gr = tl.ti * kTile, gc = tl.tj * kTile;
+    const bool strict = (st.flags & kElimStrict) != 0;
     if (tid < kTile) { rblk[tid] = -1; cblk[tid] = -1; }
     __syncthreads();
     // every block marks its span in the row tile and in the column tile
@@ -460,7 +495,7 @@ __global__ void __launch_bounds__(NT) k_schur_tiles(const ElimStep* __restrict__
             const int64_t tbase = (int64_t)ap[i] * ne - (int64_t)ap[i] * (ap[i] - 1) / 2 - ap[i];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                live[i][j] = ap[i] >= 0 && aq[j] >= ap[i];   // aq = -1 past the panel
+                live[i][j] = ap[i] >= 0 && (strict ? aq[j] > ap[i] : aq[j] >= ap[i]);   // aq = -1 past the panel
                 dst[i][j] = gld(st.pair + (live[i][j] ? tbase + aq[j] : 0));
             }
         }
@@ -494,7 +529,7 @@ __global__ void __launch_bounds__(NT) k_schur_tiles(const ElimStep* __restrict__
         for (int u = 0; u < SU; ++u) {
             const int gl = k0 + l0 + 4 * u;
             const bool ok = gl < kk;
-            xv[u] = gld(st.x + ((ok && ra >= 0) ? ro + (int64_t)gl * rb : 0));
+            xv[u] = gld(st.xs + ((ok && ra >= 0) ? ro + (int64_t)gl * rb : 0));
             yv[u] = gld(st.y + ((ok && ca >= 0) ? co + (int64_t)gl * cbw : 0));
         }
         if (k0 > 0) __syncthreads();

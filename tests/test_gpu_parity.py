@@ -107,7 +107,7 @@ def test_far_blocks_and_pivots(env, c1_oracle):
     assert agree >= 0.99 * len(hm.far_u)
 
 
-@pytest.mark.parametrize("nrhs", [1, 3, 6])
+@pytest.mark.parametrize("nrhs", [1, 3, 6, 9, 16])
 def test_matvec_and_symmetry(env, c1_oracle, nrhs):
     hsl, torch, ctx = env
     wl, hm = c1_oracle
