@@ -89,6 +89,12 @@ extern "C" {
                                    nrhs columns (block Arnoldi with block CGS2 and Cholesky QR, block
                                    Hessenberg least squares), right-preconditioned by P (NULL = none); iters
                                    counts block steps, max_iters bounds them; at most 256 columns */
+#define HS_SOLVE_GMRES_MIXED_IR 4 /* restarted right-preconditioned GMRES whose Arnoldi steps apply the complex64
+                                   operator and preconditioner copies (FP32 arithmetic; vectors, Arnoldi and
+                                   Givens in FP64), with the true residual recomputed on the FP64 operator at
+                                   every restart, so each cycle is one step of iterative refinement; stats and
+                                   convergence use that FP64 residual; needs store_c64 and HS_PREC_MIXED like
+                                   HS_SOLVE_FGMRES_MIXED */
 
 typedef struct hs_context hs_context;
 typedef struct hs_plan    hs_plan;

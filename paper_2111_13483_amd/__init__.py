@@ -406,7 +406,8 @@ def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol
           x0=None, transformed: bool = False, block: bool = False):
     """Solve Z x = b: right-preconditioned GMRES, or with mixed=True FP64
     flexible GMRES whose preconditioning steps are inner GMRES solves on the
-    complex64 copies; x0 (GMRES only) is the initial guess; transformed=True
+    complex64 copies, or with mixed="refined" GMRES whose Arnoldi steps use
+    the complex64 copies and whose restarts recompute the FP64 residual; x0 (GMRES only) is the initial guess; transformed=True
     solves the paper's transformed system (Eq. 25-28) instead, its stats
     holding the true residual; block=True runs the coupled block-GMRES
     comparator (iters = block steps). Returns (x, [Stats per column])."""
@@ -418,7 +419,7 @@ def solve(ctx: Context, H: HMatrix, P: Precond | None, b, restart: int = 30, tol
         x, s0 = _dev_c128(x0, H.n)
         if s0 != s:
             raise HschurError(HS_EINVAL, "x0 and b differ in columns")
-    method = 3 if block else (2 if transformed else (1 if mixed else 0))
+    method = 3 if block else (2 if transformed else (4 if mixed == "refined" else (1 if mixed else 0)))
     opts = SolveOpts(method, restart, tol, max_iters, fixed_iters, inner_steps, inner_tol,
                      0 if x0 is None else 1)
     st = (SolveStats * s)()

@@ -561,7 +561,9 @@ struct MatvecWs {
 // mk selects the columns computed (all for the public entry points)
 // Near and far matvec write disjoint slot ranges and only read x, so the near
 // part runs on the auxiliary stream beside the far part; the gather waits for
-// both. The fork follows all earlier work on s.
+// both. The fork follows all earlier work on s. (The wave-sized far blocks on
+// a third stream made the c2 solve 2% slower: the three kernels then compete
+// for the same CUs.)
 void matvec_tree(hs_context* ctx, const hs_hmatrix* H, const cd* x, cd* y, int nrhs, cd* slots, hipStream_t s,
                  const hs::ColMask& mk) {
     AuxStream& ax = ctx->aux;
@@ -2295,8 +2297,11 @@ std::vector<hs::ColState> poll_states(const GmresWs& G, const int* sweep_err, hi
     return h;
 }
 
+// resid (optional) replaces matvec for the true residual at each cycle end:
+// with the FP64 operator there, a cycle built on complex64 copies becomes one
+// step of iterative refinement.
 void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& matvec, const ApplyFn& precond,
-               bool flexible, bool single, int poll, const int* sweep_err) {
+               bool flexible, bool single, int poll, const int* sweep_err, const ApplyFn* resid = nullptr) {
     const int64_t n = G.n, vs = G.vstride;
     const int ns = G.ns, m = G.m;
     const hs::ColMask active{G.st, 1, 0}, stepped{G.st, 2, 0};
@@ -2334,7 +2339,7 @@ void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& mat
             hs::launch_axpy_x(x, G.wv, n, ns, G.st, s);
         }
         if (single) break;
-        matvec(x, G.tmp, stepped);
+        (resid ? *resid : matvec)(x, G.tmp, stepped);
         hs::launch_residual(b, G.tmp, G.r, n, ns, G.npart, G.nchunk, s);
         hs::launch_cycle_end(G.npart, G.nchunk, G.st, ns, s);
         hip_check(hipGetLastError(), "cycle launches");
@@ -2704,7 +2709,8 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         if (!ctx || !H || !b || !x || !opts || !stats) fail(HS_EINVAL, "NULL argument");
         if (nrhs < 1) fail(HS_EINVAL, "nrhs must be >= 1");
         if (P && P->H != H) fail(HS_EINVAL, "the preconditioner belongs to another H-matrix");
-        const bool mixed = opts->method == HS_SOLVE_FGMRES_MIXED;
+        const bool refined = opts->method == HS_SOLVE_GMRES_MIXED_IR;
+        const bool mixed = opts->method == HS_SOLVE_FGMRES_MIXED || refined;
         if (opts->method == HS_SOLVE_TRANSFORMED) return solve_transformed(ctx, H, P, b, x, nrhs, opts, stats);
         if (opts->method == HS_SOLVE_BLOCK_GMRES) return solve_block(ctx, H, P, b, x, nrhs, opts, stats);
         if (opts->method != HS_SOLVE_GMRES && !mixed) fail(HS_EINVAL, "unsupported method");
@@ -2732,7 +2738,7 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         cd* xt = w.get<cd>(n * ns);
         cd* slots = w.get<cd>((size_t)H->slot_total * ns);
         GmresWs G;
-        G.alloc(w, n, ns, m, mixed);
+        G.alloc(w, n, ns, m, mixed && !refined);
         SweepWs sw;
         if (P) sw = make_sweep_ws(w, P, ns, s, ctx);
         std::vector<hs::ColState> hst(ns);
@@ -2755,9 +2761,6 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         if (!mixed) {
             gmres_run(G, s, bt, xt, matvec, precond, false, false, 4, P ? sw.w.err : nullptr);
         } else {
-            // inner solves: complex64 operator and preconditioner copies, FP64 vectors
-            GmresWs Gi;
-            Gi.alloc(w, n, ns, m_in, false);
             ApplyFn matvec32 = [&](const cd* in, cd* out, const hs::ColMask& mk) {
                 AuxStream& ax = ctx->aux;
                 ax.ensure();
@@ -2783,14 +2786,23 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
                 hs::launch_sweep(false, mk, P->sp32, P->items, in, out, ns, sw.w, sw.epoch_b, s);
                 sweeps_end(ctx->device, s);
             };
-            // one flexible preconditioning step: z = approximate Z^-1 v for the
-            // columns still stepping in the outer cycle
-            ApplyFn inner = [&](const cd* in, cd* out, const hs::ColMask& mk) {
-                hip_check(hipMemsetAsync(out, 0, sizeof(cd) * n * ns, s), "memset");
-                hs::launch_col_init(Gi.st, mk.st, ns, tol_in, m_in, s);
-                gmres_run(Gi, s, in, out, matvec32, precond32, false, true, 4, P ? sw.w.err : nullptr);
-            };
-            gmres_run(G, s, bt, xt, matvec, inner, true, false, 4, P ? sw.w.err : nullptr);
+            if (refined) {
+                // Arnoldi on the complex64 copies (FP32 arithmetic, FP64
+                // vectors and Givens), the true residual on the FP64 operator
+                gmres_run(G, s, bt, xt, matvec32, precond32, false, false, 4, P ? sw.w.err : nullptr, &matvec);
+            } else {
+                // inner solves: complex64 operator and preconditioner copies, FP64 vectors
+                GmresWs Gi;
+                Gi.alloc(w, n, ns, m_in, false);
+                // one flexible preconditioning step: z = approximate Z^-1 v for the
+                // columns still stepping in the outer cycle
+                ApplyFn inner = [&](const cd* in, cd* out, const hs::ColMask& mk) {
+                    hip_check(hipMemsetAsync(out, 0, sizeof(cd) * n * ns, s), "memset");
+                    hs::launch_col_init(Gi.st, mk.st, ns, tol_in, m_in, s);
+                    gmres_run(Gi, s, in, out, matvec32, precond32, false, true, 4, P ? sw.w.err : nullptr);
+                };
+                gmres_run(G, s, bt, xt, matvec, inner, true, false, 4, P ? sw.w.err : nullptr);
+            }
         }
         hst = poll_states(G, P ? sw.w.err : nullptr, s);
         hs::launch_permute(xt, static_cast<cd*>(x), H->d_perm, n, ns, false, s);

@@ -1,9 +1,14 @@
-"""Mixed-precision solve: FP64 flexible GMRES on the FP64 operator whose
-preconditioning steps are inner GMRES solves computed in FP32 on complex64
-copies of the operator and of the preconditioner (built with FP32 Schur
-updates). Pinned by the oracle operator: the true residual of the mixed
-solution, measured with the FP64 oracle H-matrix, meets the tolerance, and
-the error against the FP64 oracle's solution is stated and bounded."""
+"""Mixed-precision solves on complex64 copies of the operator and of the
+preconditioner (built with FP32 Schur updates), computed in FP32:
+
+* mixed=True: FP64 flexible GMRES on the FP64 operator whose preconditioning
+  steps are inner GMRES solves on the copies;
+* mixed="refined": GMRES whose Arnoldi steps use the copies, with the true
+  residual recomputed on the FP64 operator at every restart.
+
+Pinned by the oracle operator: the true residual of the mixed solution,
+measured with the FP64 oracle H-matrix, meets the tolerance, and the error
+against the FP64 oracle's solution is stated and bounded."""
 import numpy as np
 import pytest
 
@@ -23,15 +28,16 @@ def env():
     return hsl, torch, hsl.Context(0)
 
 
+@pytest.mark.parametrize("mode", [True, "refined"])
 @pytest.mark.parametrize("case", ["c1", "plate"])
-def test_mixed_solve_true_residual(env, case):
+def test_mixed_solve_true_residual(env, case, mode):
     hsl, torch, ctx = env
     wl = W.make_config(case, n=1500 if case == "plate" else None, nrhs=3)
     hm = ohm.h_build(wl.points, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol)
     H = hsl.HMatrix(ctx, wl.points, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol, store_c64=True)
     P = hsl.Precond(ctx, H, "rcm", wl.fill_tol, mixed=True)
     b = torch.as_tensor(np.ascontiguousarray(wl.rhs), device="cuda")
-    x, st = hsl.solve(ctx, H, P, b, restart=20, tol=1e-6, mixed=True)
+    x, st = hsl.solve(ctx, H, P, b, restart=20, tol=1e-6, mixed=mode)
     x = x.cpu().numpy()
     perm = hm.tree.perm
     for c in range(wl.rhs.shape[1]):
@@ -45,8 +51,23 @@ def test_mixed_solve_true_residual(env, case):
         pc = opl.precond_setup(hm, "rcm", wl.fill_tol)
         ref = opl.solve(hm, pc, wl.rhs[:, 0], restart=30, tol=1e-10)
         err = np.linalg.norm(x[:, 0] - ref.x) / np.linalg.norm(ref.x)
-        print(f"mixed vs FP64 oracle solution: relative error {err:.2e}")
+        print(f"mixed ({mode}) vs FP64 oracle solution: relative error {err:.2e}")
         assert err <= 1e-4
+
+
+def test_refined_takes_about_the_fp64_step_count(env):
+    # the complex64 copies change the Krylov space only at the FP32 rounding
+    # level, so the refined solve needs about the steps of the FP64 GMRES
+    hsl, torch, ctx = env
+    wl = W.make_config("c1", nrhs=2)
+    H = hsl.HMatrix(ctx, wl.points, wl.k, wl.self_h, wl.leaf_max, wl.aca_tol, store_c64=True)
+    P = hsl.Precond(ctx, H, "rcm", wl.fill_tol, mixed=True)
+    b = torch.as_tensor(np.ascontiguousarray(wl.rhs), device="cuda")
+    _, s64 = hsl.solve(ctx, H, P, b, restart=wl.restart, tol=1e-6)
+    _, s32 = hsl.solve(ctx, H, P, b, restart=wl.restart, tol=1e-6, mixed="refined")
+    for a, c in zip(s64, s32):
+        assert c.converged and c.relres <= 1e-6
+        assert c.iters <= a.iters + wl.restart, (a.iters, c.iters)
 
 
 def test_mixed_setup_uses_fp32_schur_updates(env):
@@ -75,6 +96,9 @@ def test_mixed_solve_needs_copies(env):
     P2 = hsl.Precond(ctx, H2, "rcm", wl.fill_tol)
     with pytest.raises(hsl.HschurError) as ei:
         hsl.solve(ctx, H2, P2, b, mixed=True)
+    assert ei.value.status == hsl.HS_EINVAL
+    with pytest.raises(hsl.HschurError) as ei:
+        hsl.solve(ctx, H2, P2, b, mixed="refined")
     assert ei.value.status == hsl.HS_EINVAL
     # unpreconditioned mixed solve: the inner solves run on the complex64 operator alone
     x, st = hsl.solve(ctx, H2, None, b, restart=20, tol=1e-6, mixed=True, inner_steps=10)
