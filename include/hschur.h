@@ -333,7 +333,9 @@ int32_t hs_matvec_noalloc(hs_context* ctx, const hs_hmatrix* H, const void* x, v
 #define HS_KT_FAR_MV    3
 #define HS_KT_FACTOR    4   /* elimination: leaf-block inversion and alpha panel tiles (Eq. 14, 19) */
 #define HS_KT_SCHUR     5   /* elimination: Schur-complement update tiles (Eq. 38-42) */
-#define HS_KT_COUNT     6
+#define HS_KT_ELIM      6   /* a whole elimination (all steps of one setup call) on ctx's stream: its wall
+                               time, the launch gaps between its kernels included */
+#define HS_KT_COUNT     7
 typedef struct hs_kernel_times {
     int64_t launches[HS_KT_COUNT];      /* bracketed (timed) launches */
     double  total_ms[HS_KT_COUNT];      /* summed event time of the bracketed launches */

@@ -84,8 +84,8 @@ class SolveItem(ctypes.Structure):
 
 
 class KernelTimes(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 6), ("total_ms", ctypes.c_double * 6),
-                ("all_launches", ctypes.c_int64 * 6)]
+    _fields_ = [("launches", ctypes.c_int64 * 7), ("total_ms", ctypes.c_double * 7),
+                ("all_launches", ctypes.c_int64 * 7)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -165,7 +165,7 @@ EXPORTED = (
     "hs_server_destroy", "hs_status_string", "hs_last_error",
 )
 
-KT_NAMES = ("sweep_fwd", "sweep_bwd", "near_mv", "far_mv", "factor", "schur")
+KT_NAMES = ("sweep_fwd", "sweep_bwd", "near_mv", "far_mv", "factor", "schur", "elimination")
 
 
 def _check(status: int, allow_not_converged: bool = False) -> int:

@@ -1927,7 +1927,11 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
     // elimination trees (every block of S_k is an ancestor of k), so their
     // steps read and write disjoint blocks, while the steps of one component
     // keep their order. Per launch: factor/alpha tiles (one per 64 panel
-    // columns, at least one) and Schur tiles.
+    // columns, at least one) and Schur tiles. (Running the Schur tiles that
+    // the next step's row does not need on a second stream, beside the next
+    // factor launch, made the c2 elimination slower, 70.6 ms against 61: the
+    // factor workgroups need a whole CU's LDS, and the split launch and the
+    // cross-stream waits cost more than the overlap gained.)
     std::vector<std::vector<std::pair<size_t, int64_t>>> launch;   // (job, step) per launch
     for (size_t q = 0; q < jobs.size(); ++q) {
         SetupJob* j = jobs[q];
@@ -1968,10 +1972,12 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
     hs::ElimTile* d_st = tmp.upload(st, s);
     hs_context* ctx = jobs.front()->ctx;
     const bool fp32 = jobs.front()->opts->precision == HS_PREC_MIXED;
-    for (int64_t L = 0; L < nl; ++L) {
-        timed(ctx, HS_KT_FACTOR, s, [&] { hs::launch_factor_alpha(d_es, d_ft + fp[L], fp[L + 1] - fp[L], s); });
-        timed(ctx, HS_KT_SCHUR, s, [&] { hs::launch_schur_tiles(d_es, d_st + sp[L], sp[L + 1] - sp[L], fp32, s); });
-    }
+    timed(ctx, HS_KT_ELIM, s, [&] {
+        for (int64_t L = 0; L < nl; ++L) {
+            timed(ctx, HS_KT_FACTOR, s, [&] { hs::launch_factor_alpha(d_es, d_ft + fp[L], fp[L + 1] - fp[L], s); });
+            timed(ctx, HS_KT_SCHUR, s, [&] { hs::launch_schur_tiles(d_es, d_st + sp[L], sp[L + 1] - sp[L], fp32, s); });
+        }
+    });
     hip_check(hipGetLastError(), "elimination launches");
     hip_check(hipStreamSynchronize(s), "stream sync");
 }
