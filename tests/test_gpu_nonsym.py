@@ -87,6 +87,10 @@ def test_nonsymmetric_setup_matches_oracle(env, case, kind):
     ref = np.empty_like(v)
     ref[perm] = osch.apply(pc, v[perm])
     assert _rel(z, ref) <= TOL
+    # leaf by leaf as well: one wrong block is not diluted by the others
+    off = hm.tree.leaf_offsets()
+    zt, rt = z[perm], ref[perm]
+    assert max(_rel(zt[a:b], rt[a:b]) for a, b in zip(off[:-1], off[1:])) <= 1e-9
     assert _rel(z, Ps.apply(vt).cpu().numpy()) <= TOL
 
 

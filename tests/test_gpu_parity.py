@@ -1,8 +1,10 @@
 """GPU parity: the HIP path through the C-ABI against the CPU FP64 oracle.
 
 Integer structures bit-exact; near blocks, far products, D_k, alpha, P^-1 v,
-Z v and fixed-iteration GMRES iterates within 1e-10 relative (FP64 path);
-converged solves at the 1e-6 true residual of the paper's GMRES setting.
+Z v and fixed-iteration GMRES iterates within 1e-10 relative (FP64 path),
+the vectors also leaf by leaf (every leaf segment within 1e-9 of its own
+norm, so one wrong block is not diluted by the rest); converged solves at
+the 1e-6 true residual of the paper's GMRES setting.
 """
 import numpy as np
 import pytest
@@ -20,6 +22,28 @@ TOL = 1e-10
 
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+SEG_TOL = 1e-9
+
+
+def _seg_rel(a, b, hm):
+    """Largest relative error over the leaf segments (one leaf's rows, all
+    columns), so that one wrong leaf block is not diluted by the rest of the
+    vector; a and b in the caller's point order."""
+    perm = hm.tree.perm
+    off = hm.tree.leaf_offsets()
+    a2 = np.asarray(a).reshape(len(perm), -1)[perm]
+    b2 = np.asarray(b).reshape(len(perm), -1)[perm]
+    worst = 0.0
+    for s0, s1 in zip(off[:-1], off[1:]):
+        worst = max(worst, _rel(a2[s0:s1], b2[s0:s1]))
+    return worst
+
+
+def _check_vec(a, b, hm, tol=TOL):
+    assert _rel(a, b) <= tol
+    assert _seg_rel(a, b, hm) <= SEG_TOL
 
 
 @pytest.fixture(scope="module")
@@ -118,7 +142,7 @@ def test_matvec_and_symmetry(env, c1_oracle, nrhs):
     perm = hm.tree.perm
     ref = np.empty_like(x)
     ref[perm] = ohm.matvec(hm, x[perm])
-    assert _rel(y, ref) <= TOL
+    _check_vec(y, ref, hm)
     # complex symmetry u^T Z v = v^T Z u of the GPU operator
     u = x[:, 0]
     v = x[:, -1] if nrhs > 1 else rng.normal(size=wl.n) + 0j
@@ -161,7 +185,7 @@ def test_precond_exact_parity(env, case, kind):
     perm = hm.tree.perm
     ref = np.empty_like(v)
     ref[perm] = osch.apply(pc, v[perm])
-    assert _rel(z, ref) <= TOL
+    _check_vec(z, ref, hm)
     # and it is the near-field inverse: Z_N z = v
     back = np.empty_like(v)
     back[perm] = ohm.near_matvec(hm, z[perm])
@@ -192,7 +216,7 @@ def test_precond_compressed_parity(env, c1_oracle):
     perm = hm.tree.perm
     ref = np.empty_like(v)
     ref[perm] = osch.apply(pc, v[perm])
-    assert _rel(z, ref) <= TOL
+    _check_vec(z, ref, hm)
     # symmetry of the compressed preconditioner
     zu = P.apply(torch.as_tensor(v[:, 1].copy(), device="cuda")).cpu().numpy()
     assert abs(v[:, 0] @ zu - v[:, 1] @ z[:, 0]) <= 1e-12 * abs(v[:, 0] @ zu)
@@ -211,7 +235,7 @@ def test_solve_fixed_iterations_parity(env, c1_oracle):
     x, st = hsl.solve(ctx, H, P, torch.as_tensor(b, device="cuda"), restart=30, fixed_iters=it)
     x = x.cpu().numpy()
     assert st[0].iters == it
-    assert _rel(x, ref_fixed.x) <= TOL
+    _check_vec(x, ref_fixed.x, hm)
     # converged solve: same iteration count and a true residual <= 1e-6 on the oracle operator
     x2, st2 = hsl.solve(ctx, H, P, torch.as_tensor(b, device="cuda"), restart=30, tol=1e-6)
     x2 = x2.cpu().numpy()
@@ -286,11 +310,11 @@ def test_ragged_leaves_tiny_and_leaf1(env):
         ref = np.empty_like(v)
         ref[perm] = osch.apply(pc, v[perm])
         z = P.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
-        assert _rel(z, ref) <= TOL
+        _check_vec(z, ref, hm)
         y = H.matvec(torch.as_tensor(v, device="cuda")).cpu().numpy()
         ry = np.empty_like(v)
         ry[perm] = ohm.matvec(hm, v[perm])
-        assert _rel(y, ry) <= TOL
+        _check_vec(y, ry, hm)
 
 
 @pytest.mark.parametrize("fill_tol", [0.0, 1e-2])
@@ -311,7 +335,7 @@ def test_precond_wide_leaves(env, fill_tol):
         z = P.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
         ref = np.empty_like(v)
         ref[perm] = osch.apply(pc, v[perm])
-        assert _rel(z, ref) <= TOL
+        _check_vec(z, ref, hm)
 
 
 @pytest.fixture(scope="module")
@@ -336,7 +360,7 @@ def test_precond_sweep_layouts(env, pair_oracle, layout):
         z = P.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
         ref = np.empty_like(v)
         ref[perm] = osch.apply(pc, v[perm])
-        assert _rel(z, ref) <= TOL, (layout, cols)
+        _check_vec(z, ref, hm)
 
 
 @pytest.mark.parametrize("fill_tol", [0.0, 1e-2])
@@ -357,7 +381,7 @@ def test_precond_wide_leaves_small_chunks(env, fill_tol):
         z = P.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
         ref = np.empty_like(v)
         ref[perm] = osch.apply(pc, v[perm])
-        assert _rel(z, ref) <= TOL
+        _check_vec(z, ref, hm)
 
 
 def test_precond_layout_arguments(env, c1_oracle):
@@ -434,14 +458,15 @@ def test_cube_and_uneven_leaves_fixed_steps():
                       rhs=W.plane_wave(pts, 2 * math.pi / (0.05 * math.sqrt(1e5 / n)), rng)[:, None])
     geos = [cube] + [g for g in W.batch_geometries(count=6, n_max=2600, nrhs=1) if g.leaf_max != 64][:2]
     assert len({g.leaf_max for g in geos}) == 3
-    items, refs = [], []
+    items, refs, hms = [], [], []
     for g in geos:
         hm = ohm.h_build(g.points, g.k, g.self_h, g.leaf_max, 1e-4)
+        hms.append(hm)
         pc = opl.precond_setup(hm, "rcm", 1e-2)
         refs.append(opl.solve(hm, pc, g.rhs[:, 0], restart=30, fixed_iters=25).x)
         H = hsl.HMatrix(ctx, g.points, g.k, g.self_h, g.leaf_max, 1e-4)
         items.append((H, hsl.Precond(ctx, H, "rcm", 1e-2), torch.as_tensor(g.rhs[:, 0], device="cuda")))
     out = hsl.solve_many(ctx, items, restart=30, fixed_iters=25)
-    for (x, st), ref in zip(out, refs):
+    for (x, st), ref, hm in zip(out, refs, hms):
         assert st[0].iters == 25
-        assert _rel(x.cpu().numpy(), ref) <= TOL
+        _check_vec(x.cpu().numpy(), ref, hm)
