@@ -1795,6 +1795,7 @@ struct SetupJob {
                     f.e_off = fe_off[c];
                     f.need1 = csize[c - 1];
                     f.need2 = c >= 2 ? csize[c - 2] : 0;
+                    f.need3 = c >= 3 ? csize[c - 3] : 0;
                 }
                 fch[c] = f;
                 hs::SweepChunk b{};
@@ -1809,6 +1810,7 @@ struct SetupJob {
                     b.e_off = be_off[c];
                     b.need1 = csize[c + 1];
                     b.need2 = c + 2 < nch ? csize[c + 2] : 0;
+                    b.need3 = c + 3 < nch ? csize[c + 3] : 0;
                 }
                 bch[c] = b;
                 for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk)

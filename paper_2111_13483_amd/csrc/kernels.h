@@ -284,7 +284,8 @@ struct SweepChunk {
     int32_t e_n, e_off;      // the rest (columns [l_n, w2)): points and their offset into the position map
     int32_t nblocks;         // blocks of the chunk (phase A count)
     int32_t need1, need2;    // points of chunks c -/+ 1 and c -/+ 2 (0 if absent)
-    int32_t pad[2];
+    int32_t need3;           // points of chunk c -/+ 3 (0 if absent)
+    int32_t pad;
 };
 // Per point row (indexed by elimination-order position): its slices of the
 // chunk inverse (a1, width w1, first column o1 in the chunk) and of the

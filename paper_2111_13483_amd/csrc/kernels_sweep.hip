@@ -258,13 +258,16 @@ __device__ __forceinline__ void wait_count(const int* cnt, int need, const Sweep
     }
 }
 
-// Two counters polled together (b may be null): *a == na and *b == nb.
-__device__ __forceinline__ void wait_pair(const int* a, int na, const int* b, int nb, const SweepWork& wk) {
+// Three counters polled together (b and c may be null): *a == na, *b == nb
+// and *c == nc.
+__device__ __forceinline__ void wait_three(const int* a, int na, const int* b, int nb, const int* c, int nc,
+                                           const SweepWork& wk) {
     const long long t0 = wall_clock64();
     for (int it = 1;; ++it) {
         const int va = relaxed_load(a);
         const int vb = b ? relaxed_load(b) : nb;
-        if (va == na && vb == nb) return;
+        const int vc = c ? relaxed_load(c) : nc;
+        if (va == na && vb == nb && vc == nc) return;
         if ((it % kBailPolls == 0 || wk.wait_ticks == 0) && must_give_up(wk, t0)) {
             give_up(wk);
             return;
@@ -544,8 +547,14 @@ k_sweep_fwd(ColMask mk, SweepPlanT<T> p, SweepItems it, const cd* __restrict__ v
             const int w1 = live ? rt.w1 : 0;
             const int cn = c + kRowSets;
             const SweepChunk dn = it.fchunk[cn < p.nch ? cn : c];
+            // phase A of chunk c, and chunks c-2 and c-3 stored and counted: the
+            // early range (chunks <= c-2) is then final, since every older
+            // chunk's count was awaited by chunk c-2 or c-3 before they ran
+            // (chunk c-2 read chunk c-3 from its flagged words, not from its
+            // count)
             if (wid == 0)
-                wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c >= 2 ? cntB + kCntPad * (c - 2) : nullptr, epoch * d.need2, wk);
+                wait_three(cntA + kCntPad * c, epoch * d.nblocks, c >= 2 ? cntB + kCntPad * (c - 2) : nullptr,
+                           epoch * d.need2, c >= 3 ? cntB + kCntPad * (c - 3) : nullptr, epoch * d.need3, wk);
             __syncthreads();
             compiler_fence();
             bool first = true;   // the first computed pass waits for the newest chunk
@@ -698,8 +707,9 @@ k_sweep_bwd(ColMask mk, SweepPlanT<T> p, SweepItems it, cd* __restrict__ z, Swee
             const int w1 = live ? rt.w1 : 0;
             const int cn = c - kRowSets;
             const SweepChunk dn = it.bchunk[cn >= 0 ? cn : c];
-            if (wid == 0)
-                wait_pair(cntA + kCntPad * c, epoch * d.nblocks, c + 2 < p.nch ? cntB + kCntPad * (c + 2) : nullptr, epoch * d.need2, wk);
+            if (wid == 0)   // as in the forward sweep, with chunks c+2 and c+3
+                wait_three(cntA + kCntPad * c, epoch * d.nblocks, c + 2 < p.nch ? cntB + kCntPad * (c + 2) : nullptr,
+                           epoch * d.need2, c + 3 < p.nch ? cntB + kCntPad * (c + 3) : nullptr, epoch * d.need3, wk);
             __syncthreads();
             compiler_fence();
             bool first = true;   // the first computed pass waits for the newest chunk
