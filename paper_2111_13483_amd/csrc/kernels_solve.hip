@@ -14,7 +14,6 @@ namespace {
 constexpr int NT = 256;
 constexpr int NW = NT / kWave;
 constexpr int SCH = 4;   // right-hand sides per pass over a block
-constexpr int SCW = 8;   // the same from eight columns on, for the workgroup far blocks
 }
 
 // ---------------------------------------------------------------- permute
@@ -313,9 +312,8 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
          const int64_t* __restrict__ slot_base, const cd* __restrict__ x, int64_t n, int nrhs,
          cd* __restrict__ slots) {
     using A = arith_t<T>;
-    // one column: two column groups per step; sized for 5 waves per SIMD;
-    // eight columns per pass take two rows per wave (the accumulators grow)
-    constexpr int RU = S >= 8 ? 2 : 4, JU = S == 1 ? 2 : 1, LG = 8;
+    // one column: two column groups per step; sized for 5 waves per SIMD
+    constexpr int RU = 4, JU = S == 1 ? 2 : 1, LG = 8;
     __shared__ A t12[2 * (kMaxRankCap + LG) * S];
     __shared__ A tpart[S == 1 ? NW : 1][kMaxRankCap];
     const AcaTask g = geom[blockIdx.x];
@@ -835,7 +833,7 @@ void near_mv(const ColMask& mk, const NearTask* tasks, const int64_t* slot_base,
     if (nrhs == 1)
         hipLaunchKernelGGL((k_near_mv<1, T>), dim3((unsigned)ntasks), dim3(NT), 0, s, mk, tasks, slot_base, Z, x, n,
                            nrhs, slots);
-    else   // (eight-column passes measured slower here: 2.4 ms against 1.6 ms at 16 columns on 20,000 points)
+    else
         hipLaunchKernelGGL((k_near_mv<SCH, T>), dim3((unsigned)ntasks), dim3(NT), 0, s, mk, tasks, slot_base, Z, x, n,
                            nrhs, slots);
 }
@@ -854,11 +852,8 @@ void far_mv(const ColMask& mk, const AcaTask* geom, const int* rank, T* const* u
             hipLaunchKernelGGL((k_far_wave<1, T>), dim3(gw), dim3(NT), 0, s, mk, geom + nwg, rank + nwg, uv + nwg,
                                slot_base + nwg, nwv, x, n, nrhs, slots);
     } else {
-        if (nwg > 0 && nrhs < SCW)
+        if (nwg > 0)
             hipLaunchKernelGGL((k_far_mv<SCH, T>), dim3((unsigned)nwg), dim3(NT), 0, s, mk, geom, rank, uv, slot_base,
-                               x, n, nrhs, slots);
-        else if (nwg > 0)
-            hipLaunchKernelGGL((k_far_mv<SCW, T>), dim3((unsigned)nwg), dim3(NT), 0, s, mk, geom, rank, uv, slot_base,
                                x, n, nrhs, slots);
         if (nwv > 0)
             hipLaunchKernelGGL((k_far_wave<SCH, T>), dim3(gw), dim3(NT), 0, s, mk, geom + nwg, rank + nwg, uv + nwg,
