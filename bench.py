@@ -552,7 +552,9 @@ def fill_study(args):
 def setup_scaling(args):
     """Setup cost against N (Sec. 4, Fig. 8 trend): the plate at a fixed 3.2
     points per wavelength and leaf 64, N doubling; setup time, its
-    elimination time, exact setup flops and stored coefficient bytes."""
+    elimination time, exact setup flops and stored coefficient bytes, for the
+    dense-W elimination and for the setup-side low-rank arithmetic (its
+    factored flop count)."""
     import math as _m
     import torch
     import paper_2111_13483_amd as hsl
@@ -576,11 +578,21 @@ def setup_scaling(args):
             ts.append(time.perf_counter() - t0)
         kt = ctx.timing_end()
         pi = P.info()
+        # the same setup with the setup-side low-rank arithmetic
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        PL = hsl.Precond(ctx, H, "sloan", 1e-2, kind="schur_lowrank")
+        torch.cuda.synchronize()
+        t_lr = time.perf_counter() - t0
+        pl = PL.info()
         rows.append({"n": n, "nb": pi["nb"], "setup_s": ts[1], "elimination_ms": kt["elimination"][1],
                      "setup_flops": pi["flops_setup"], "alpha_bytes": pi["bytes_alpha"],
-                     "flops_per_point": pi["flops_setup"] / n})
-        print(f"scaling: N={n}: setup {ts[1]:.3f} s, flops {pi['flops_setup']:.3e}", file=sys.stderr, flush=True)
-        del P, H
+                     "flops_per_point": pi["flops_setup"] / n,
+                     "lowrank_setup_s": t_lr, "lowrank_setup_flops": pl["flops_setup"],
+                     "lowrank_alpha_bytes": pl["bytes_alpha"], "lowrank_blocks": pl["n_lowrank"]})
+        print(f"scaling: N={n}: setup {ts[1]:.3f} s, flops {pi['flops_setup']:.3e}; low-rank arithmetic "
+              f"{t_lr:.3f} s, flops {pl['flops_setup']:.3e}", file=sys.stderr, flush=True)
+        del P, PL, H
     print(json.dumps({"metric": "setup cost against N (Sec. 4 trend)", "data": "synthetic",
                       "config": {"workload": "plate 2 x 2 x 0.05, lambda = 3.2 h, leaf 64, Sloan, fill 1e-2"},
                       "rows": rows}), flush=True)

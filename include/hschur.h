@@ -70,6 +70,13 @@ extern "C" {
                                    (Eq. 16) and updates every pair of S_k instead of i <= j; the apply uses
                                    alpha as HS_PC_SCHUR does (alpha' = alpha^T for the symmetric Z here), and
                                    HS_P_ALPHA_LEFT exports alpha' */
+#define HS_PC_SCHUR_LOWRANK 3   /* the setup-side low-rank arithmetic (Sec. 3.4 with the cost argument of Sec. 4):
+                                   each fill-in block W_kj is compressed (ACA + re-compression at fill_tol) when
+                                   step k reaches it, replaced by U V where r (b_k + b_j) < b_k b_j, and carried
+                                   in factored form through the coefficient and Schur products; P^-1 is then
+                                   exactly (Z_N + Delta)^-1 with Delta_kj = U V - W_kj. One host round trip per
+                                   step (the ranks), so it is slower than HS_PC_SCHUR at these leaf sizes;
+                                   FP64 only */
 
 #define HS_PREC_FP64        0   /* complex128 throughout */
 #define HS_PREC_MIXED       1   /* also keep complex64 copies of the apply's matrices (for HS_SOLVE_FGMRES_MIXED) */
@@ -122,7 +129,8 @@ typedef struct {
      * send more entries through the pushed far-entry path. */
     int32_t sweep_chunk;
     int32_t sweep_fold_cols;
-    int32_t kind;         /* HS_PC_SCHUR (the method), HS_PC_BLOCK_JACOBI or HS_PC_SCHUR_NONSYM (comparators) */
+    int32_t kind;         /* HS_PC_SCHUR (the method), HS_PC_SCHUR_LOWRANK (its setup-side low-rank
+                             variant), HS_PC_BLOCK_JACOBI or HS_PC_SCHUR_NONSYM (comparators) */
 } hs_precond_opts;
 
 typedef struct {
@@ -151,7 +159,10 @@ typedef struct {
     int64_t max_rank;       /* largest far-field rank after re-compression */
     int64_t bytes_near, bytes_far, bytes_alpha, bytes_d;   /* stored matrix bytes */
     int64_t bytes_device;   /* all device memory the handle holds */
-    double  flops_setup;    /* algorithmic flops of the Schur elimination (LU + alpha + updates) */
+    double  flops_setup;    /* algorithmic flops of the Schur elimination (LU + alpha + updates); for an
+                               HS_PC_SCHUR_LOWRANK preconditioner, those of its factored arithmetic
+                               (compression, coefficients and core products over the compressed panels,
+                               expansions) */
     double  flops_fill;     /* ACA/re-compression flops on fill-in blocks, r^2 (m + n) model */
     int64_t bytes_estimate; /* plans only: device bytes an H-matrix plus preconditioner of this plan is
                                expected to hold, computed before any allocation (exact near-field and

@@ -45,7 +45,7 @@ class PrecondOpts(ctypes.Structure):
                 ("sweep_chunk", ctypes.c_int32), ("sweep_fold_cols", ctypes.c_int32), ("kind", ctypes.c_int32)]
 
 
-PC_KIND = {"schur": 0, "block_jacobi": 1, "schur_nonsym": 2}
+PC_KIND = {"schur": 0, "block_jacobi": 1, "schur_nonsym": 2, "schur_lowrank": 3}
 
 
 class SolveOpts(ctypes.Structure):
@@ -330,7 +330,9 @@ class Precond:
                  sweep_fold_cols: int = 0, mixed: bool = False, kind: str = "schur"):
         """kind="block_jacobi" sets up the comparator blockdiag(Z_kk)^-1 instead;
         kind="schur_nonsym" runs the non-symmetric elimination (left
-        coefficients formed separately, export("alpha_left"))."""
+        coefficients formed separately, export("alpha_left")); kind=
+        "schur_lowrank" carries the fill-in blocks compressed through the
+        elimination."""
         self.ctx, self.H = ctx, H
         opts = PrecondOpts(ORDER[ordering], float(fill_tol), 1 if mixed else 0, int(sweep_chunk), int(sweep_fold_cols),
                            PC_KIND[kind])

@@ -315,6 +315,7 @@ struct hs_precond {
     int64_t alpha_elems = 0, d_elems = 0;
     int64_t n_lowrank = 0, n_fill = 0, max_dk = 0;
     double flops_setup = 0, flops_fill = 0;
+    double flops_factored = 0;   // HS_PC_SCHUR_LOWRANK: the elimination's flops with the replaced blocks factored
     // device
     cd* d_D = nullptr;       // final W_kk
     cd* d_dinv = nullptr;    // D_k^-1
@@ -1180,6 +1181,17 @@ struct SetupJob {
     bool nonsym = false;
     cd* WL = nullptr;
     cd* Bd = nullptr;
+    // setup-side low-rank arithmetic (HS_PC_SCHUR_LOWRANK): per pattern entry,
+    // the rank of a replaced fill-in block (-1: dense), its V factor, its
+    // coefficient block's position in Ad and its ACA rank; the factors live
+    // in lrown until the alpha store is built; W holds tcap more elements for
+    // the steps' product cores
+    bool lowrank = false;
+    std::vector<int32_t> lr_rank, lr_rank_aca;
+    std::vector<const cd*> lr_v;
+    std::vector<int64_t> lr_apos;
+    Owned lrown;
+    int64_t tcap = 0, xcap = 0;
     int* d_err = nullptr;
     // elimination panels: the pattern in CSR (int32), per row the panel column
     // starts (ne + 1 values at rowptr[k] + k), the pair-table offsets, and the
@@ -1251,7 +1263,23 @@ struct SetupJob {
         }
         P->d_elems = dtot;
         tmp.mem = ctx->mem;
-        W = tmp.get<cd>(wtot);
+        lowrank = opts->kind == HS_PC_SCHUR_LOWRANK;
+        if (lowrank) {
+            // bounds over the steps of the product cores (pairs a <= b of
+            // S_k at the dense widths) and of the panel (b_k x m_k)
+            for (int64_t kk = 0; kk < nb; ++kk) {
+                double sj = 0, sj2 = 0;
+                for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
+                    const double bj = P->bsize[sy.cols[e]];
+                    sj += bj;
+                    sj2 += bj * bj;
+                }
+                tcap = std::max<int64_t>(tcap, (int64_t)(0.5 * (sj * sj + sj2)));
+                xcap = std::max<int64_t>(xcap, (int64_t)(P->bsize[kk] * sj));
+            }
+            lrown.mem = ctx->mem;
+        }
+        W = tmp.get<cd>(wtot + tcap);
         Ad = tmp.get<cd>(atot);
         Owned& o = P->own;
         P->d_dinv = o.get<cd>(dtot);
@@ -1340,6 +1368,194 @@ struct SetupJob {
         }
     }
 
+    // The elimination with the setup-side low-rank arithmetic (Sec. 3.4 and
+    // the cost argument of Sec. 4), one step at a time. At step k the fill-in
+    // blocks W_kj of row k are final; each is compressed by ACA +
+    // re-compression at fill_tol (the ranks come back to the host) and, where
+    // r (b_k + b_j) < b_k b_j, replaced by U V for everything that follows.
+    // The step then works on the compressed panel, [W_kj | U_kj] block by
+    // block (width b_j or r):
+    //   alpha' = -W_kk^-1 panel (the factor kernel): alpha_kj, or U'_kj with
+    //     alpha_kj = U'_kj V_kj;
+    //   C' = panel^T alpha' over the pairs a <= b (the Schur tile kernel): a
+    //     pair of two dense blocks goes straight into W_ij; any other into a
+    //     core T_ab of the compressed shape, which k_core_expand adds to W_ij as
+    //     L^T T R (L = V_a or the identity, R = V_b or the identity).
+    // A replaced block enters only through these products, so the result is
+    // the exact elimination of Z_N + Delta (Delta_kj = U V - W_kj), as in the
+    // oracle's definition; FP64 only.
+    void eliminate_lowrank() {
+        const hs::Symbolic& sy = P->plan.sym;
+        lr_rank.assign(nnz, -1);
+        lr_rank_aca.assign(nnz, 0);
+        lr_v.assign(nnz, nullptr);
+        lr_apos.assign(nnz, 0);
+        cd* Xp = tmp.get<cd>(std::max<int64_t>(xcap, 1));
+        // W offset of pattern entry (i, j), j in S_i (the rows' columns are sorted)
+        auto entry = [&](int64_t i, int64_t j) -> int64_t {
+            const auto b0 = sy.cols.begin() + sy.rowptr[i], b1 = sy.cols.begin() + sy.rowptr[i + 1];
+            const auto it = std::lower_bound(b0, b1, j);
+            if (it == b1 || *it != j) fail(HS_EINVAL, "filled pattern is not closed under elimination");
+            return (int64_t)(it - sy.cols.begin());
+        };
+        timed(ctx, HS_KT_ELIM, s, [&] {
+            for (int64_t k = 0; k < nb; ++k) {
+                Owned st;
+                st.mem = ctx->mem;
+                const int64_t r0 = sy.rowptr[k];
+                const int32_t ne = (int32_t)(sy.rowptr[k + 1] - r0);
+                const int32_t bk = P->bsize[k];
+                // 1. the final fill-in blocks of row k, compressed
+                std::vector<hs::AcaTask> at;
+                std::vector<int64_t> fe;
+                if (opts->fill_tol > 0.0)
+                    for (int32_t a = 0; a < ne; ++a) {
+                        const int64_t e = r0 + a;
+                        if (sy.orig[e]) continue;
+                        hs::AcaTask t{};
+                        t.src_off = w_off[e];
+                        t.m = bk;
+                        t.n = P->bsize[sy.cols[e]];
+                        at.push_back(t);
+                        fe.push_back(e);
+                    }
+                LowRankSet set;
+                if (!at.empty()) {
+                    compress_blocks(lrown, s, at, true, nullptr, 0.0, W, opts->fill_tol, hs::kMaxLeaf, d_err, nullptr,
+                                    set, nullptr);
+                    check_device_flag(d_err, s);
+                }
+                std::vector<int32_t> w(ne), rk(ne, -1), bw(ne);
+                std::vector<const cd*> up(ne, nullptr), vp(ne, nullptr);
+                for (int32_t a = 0; a < ne; ++a) w[a] = bw[a] = P->bsize[sy.cols[r0 + a]];
+                for (size_t q = 0; q < fe.size(); ++q) {
+                    const int64_t e = fe[q];
+                    const int32_t a = (int32_t)(e - r0), r = set.rank[q];
+                    lr_rank_aca[e] = set.rank_aca[q];
+                    if ((int64_t)r * (bk + bw[a]) < (int64_t)bk * bw[a]) {
+                        rk[a] = r;
+                        w[a] = r;
+                        up[a] = set.ptr[q];
+                        vp[a] = set.ptr[q] ? set.ptr[q] + (int64_t)bk * r : nullptr;
+                        lr_rank[e] = r;
+                        lr_v[e] = vp[a];
+                    }
+                }
+                // 2. the compressed panel: block a at columns [pc[a], pc[a + 1])
+                std::vector<int32_t> pc(ne + 1, 0);
+                for (int32_t a = 0; a < ne; ++a) pc[a + 1] = pc[a] + w[a];
+                const int32_t m = pc[ne];
+                if ((int64_t)bk * m > xcap) fail(HS_EINVAL, "compressed panel larger than its bound");
+                for (int32_t a = 0; a < ne; ++a) lr_apos[r0 + a] = ad_off[r0] + (int64_t)bk * pc[a];
+                std::vector<hs::CopyTask> xc;
+                std::vector<hs::ColMajorCopy> uc;
+                for (int32_t a = 0; a < ne; ++a) {
+                    if (rk[a] < 0) xc.push_back(hs::CopyTask{(int64_t)bk * pc[a], w_off[r0 + a], bk, w[a], 0, 0});
+                    else if (rk[a] > 0) uc.push_back(hs::ColMajorCopy{up[a], (int64_t)bk * pc[a], bk, rk[a]});
+                }
+                // 3. pair table: W targets for dense pairs, cores at wtot + toff for the others
+                std::vector<int64_t> pair((size_t)ne * (ne + 1) / 2 + 1, 0);
+                std::vector<hs::CopyTask> zc;
+                std::vector<hs::CoreExpandTask> ex;
+                int64_t toff = 0;
+                for (int32_t a = 0; a < ne; ++a) {
+                    const int64_t i = sy.cols[r0 + a];
+                    for (int32_t b = a; b < ne; ++b) {
+                        const int64_t j = sy.cols[r0 + b];
+                        const int64_t target = a == b ? wd_off[i] : w_off[entry(i, j)];
+                        const int64_t idx = (int64_t)a * ne - (int64_t)a * (a - 1) / 2 - a + b;
+                        if (rk[a] < 0 && rk[b] < 0) {
+                            pair[idx] = target;
+                            continue;
+                        }
+                        pair[idx] = wtot + toff;
+                        const int64_t len = (int64_t)w[a] * w[b];
+                        if (len > 0) {
+                            zc.push_back(hs::CopyTask{wtot + toff, -1, w[a], w[b], 0, 0});
+                            ex.push_back(hs::CoreExpandTask{rk[a] > 0 ? vp[a] : nullptr, rk[b] > 0 ? vp[b] : nullptr, target,
+                                                        wtot + toff, bw[a], bw[b], rk[a] > 0 ? rk[a] : 0,
+                                                        rk[b] > 0 ? rk[b] : 0});
+                        }
+                        toff += len;
+                    }
+                }
+                if (toff > tcap) fail(HS_EINVAL, "product cores larger than their bound");
+                // the step's flops in factored form (complex multiply-add = 8):
+                // inversion, coefficients over the compressed panel, fill-in
+                // compression 8 (2 r^2 (b_k + b_j) + r^3) at the ACA rank, core
+                // products over pairs a <= b and their expansions
+                {
+                    double fl = 8.0 / 3.0 * bk * (double)bk * bk + 8.0 * bk * (double)bk * m;
+                    for (size_t q = 0; q < fe.size(); ++q) {
+                        const double rc = set.rank_aca[q];
+                        fl += 8.0 * (2.0 * rc * rc * (bk + at[q].n) + rc * rc * rc);
+                    }
+                    for (int32_t a = 0; a < ne; ++a)
+                        for (int32_t b = a; b < ne; ++b) {
+                            fl += 8.0 * w[a] * (double)bk * w[b];
+                            const bool la = rk[a] >= 0, lb = rk[b] >= 0;
+                            if (la && lb)
+                                fl += 8.0 * std::min((double)bw[a] * rk[a] * rk[b] + (double)bw[a] * rk[b] * bw[b],
+                                                     (double)rk[a] * rk[b] * bw[b] + (double)bw[a] * rk[a] * bw[b]);
+                            else if (la)
+                                fl += 8.0 * bw[a] * (double)rk[a] * bw[b];
+                            else if (lb)
+                                fl += 8.0 * bw[a] * (double)rk[b] * bw[b];
+                        }
+                    P->flops_factored += fl;
+                }
+                // 4. tiles: factor tiles over the compressed panel, Schur tiles
+                // (ti, tj) holding an element with block(row) <= block(column)
+                const int32_t nt = (m + 63) / 64;
+                std::vector<hs::ElimTile> ft, stl;
+                for (int32_t t = 0; t < std::max<int32_t>(1, nt); ++t) ft.push_back(hs::ElimTile{0, (int16_t)t, 0});
+                {
+                    std::vector<int32_t> afirst(nt), alast(nt);
+                    int32_t a = 0;
+                    for (int32_t t = 0; t < nt; ++t) {
+                        while (pc[a + 1] <= 64 * t) ++a;
+                        afirst[t] = a;
+                    }
+                    a = 0;
+                    for (int32_t t = 0; t < nt; ++t) {
+                        const int32_t g = std::min(64 * t + 63, m - 1);
+                        while (pc[a + 1] <= g) ++a;
+                        alast[t] = a;
+                    }
+                    for (int32_t ti = 0; ti < nt; ++ti)
+                        for (int32_t tj = 0; tj < nt; ++tj)
+                            if (afirst[ti] <= alast[tj]) stl.push_back(hs::ElimTile{0, (int16_t)ti, (int16_t)tj});
+                }
+                hs::ElimStep es{};
+                es.wkk = W + wd_off[k];
+                es.dinv = P->d_dinv + P->d_off[k];
+                es.x = ne > 0 ? Xp : W;
+                es.xs = es.x;
+                es.y = ne > 0 ? Ad + ad_off[r0] : Ad;
+                es.w = W;
+                es.pair = st.upload(pair, s);
+                es.pcol = st.upload(pc, s);
+                es.err = d_err;
+                es.bk = bk;
+                es.ne = ne;
+                es.m = m;
+                es.flags = 0;
+                std::vector<hs::ElimStep> esv{es};
+                const hs::ElimStep* d_es = st.upload(esv, s);
+                hs::launch_copy_blocks(st.upload(xc, s), (int64_t)xc.size(), W, Xp, s);
+                hs::launch_copy_colmajor(st.upload(uc, s), (int64_t)uc.size(), Xp, s);
+                hs::launch_copy_blocks(st.upload(zc, s), (int64_t)zc.size(), W, W, s);
+                timed(ctx, HS_KT_FACTOR, s, [&] { hs::launch_factor_alpha(d_es, st.upload(ft, s), (int64_t)ft.size(), s); });
+                timed(ctx, HS_KT_SCHUR, s, [&] {
+                    hs::launch_schur_tiles(d_es, st.upload(stl, s), (int64_t)stl.size(), false, s);
+                });
+                hs::launch_core_expand(st.upload(ex, s), (int64_t)ex.size(), W, s);
+                hip_check(hipGetLastError(), "low-rank elimination launches");
+                hip_check(hipStreamSynchronize(s), "stream sync");   // the step's tables are freed next
+            }
+        });
+    }
+
     // after the elimination: D, fill-in compression, the alpha store and the sweep plan
     void finish() {
         const hs::Symbolic& sy = P->plan.sym;
@@ -1363,7 +1579,51 @@ struct SetupJob {
         P->a_rank.assign(nnz, -1);
         LowRankSet fills;
         std::vector<char> keep(fill_e.size(), 0);
-        if (opts->fill_tol > 0.0 && !fill_e.empty()) {
+        if (lowrank) {
+            // the coefficient blocks as the low-rank elimination left them: a
+            // dense block in its row's compressed panel, or U' there (b_k x r,
+            // row-major) with V from the fill-in compression
+            P->a_off.resize(nnz);
+            int64_t ftot = 0;
+            for (int64_t e = 0; e < nnz; ++e) {
+                P->a_rank[e] = lr_rank[e];
+                P->a_off[e] = ftot;
+                const int64_t bk = P->bsize[row_of[e]], bj = P->bsize[sy.cols[e]];
+                ftot += lr_rank[e] >= 0 ? (int64_t)lr_rank[e] * (bk + bj) : bk * bj;
+                if (lr_rank[e] >= 0) ++P->n_lowrank;
+                const double rr = lr_rank_aca[e];
+                P->flops_fill += rr * rr * (double)(bk + bj);
+            }
+            P->alpha_elems = ftot;
+            P->d_alpha = o.get<cd>(std::max<int64_t>(ftot, 1));
+            std::vector<hs::CopyTask> cp;
+            std::vector<hs::PtrCopy> vc;
+            for (int64_t e = 0; e < nnz; ++e) {
+                const int32_t bk = P->bsize[row_of[e]], bj = P->bsize[sy.cols[e]], r = lr_rank[e];
+                if (r < 0) {
+                    cp.push_back(hs::CopyTask{P->a_off[e], lr_apos[e], bk, bj, 0, 0});
+                } else if (r > 0) {
+                    // column-major b_k x r = row-major r x b_k, from the row-major b_k x r panel block
+                    cp.push_back(hs::CopyTask{P->a_off[e], lr_apos[e], r, bk, 1, 0});
+                    vc.push_back(hs::PtrCopy{lr_v[e], P->a_off[e] + (int64_t)bk * r, (int64_t)r * bj});
+                }
+            }
+            hs::CopyTask* d_cp = tmp.upload(cp, s);
+            hs::launch_copy_blocks(d_cp, (int64_t)cp.size(), Ad, P->d_alpha, s);
+            hs::PtrCopy* d_vc = tmp.upload(vc, s);
+            hs::launch_copy_ptrs(d_vc, (int64_t)vc.size(), P->d_alpha, s);
+            // the sweep plan below reads the dense coefficient blocks at their
+            // dense positions in Ad (the low-rank ones it expands from the
+            // store): put them back there from the store
+            std::vector<hs::CopyTask> back;
+            for (int64_t e = 0; e < nnz; ++e)
+                if (lr_rank[e] < 0)
+                    back.push_back(hs::CopyTask{ad_off[e], P->a_off[e], P->bsize[row_of[e]], P->bsize[sy.cols[e]], 0, 0});
+            hs::CopyTask* d_back = tmp.upload(back, s);
+            hs::launch_copy_blocks(d_back, (int64_t)back.size(), P->d_alpha, Ad, s);
+            hip_check(hipStreamSynchronize(s), "stream sync");
+            lrown.release();
+        } else if (opts->fill_tol > 0.0 && !fill_e.empty()) {
             std::vector<hs::AcaTask> ft;
             for (int64_t e : fill_e) {
                 hs::AcaTask a{};
@@ -2008,8 +2268,11 @@ int32_t hs_precond_setup_many(hs_context* ctx, int64_t count, const hs_hmatrix* 
             if (opts->ordering < 0 || opts->ordering > 4) fail(HS_EINVAL, "unknown ordering");
             if (!(opts->fill_tol >= 0.0)) fail(HS_EINVAL, "fill_tol must be >= 0");
             if (opts->precision != HS_PREC_FP64 && opts->precision != HS_PREC_MIXED) fail(HS_EINVAL, "unsupported precision");
-            if (opts->kind != HS_PC_SCHUR && opts->kind != HS_PC_BLOCK_JACOBI && opts->kind != HS_PC_SCHUR_NONSYM)
+            if (opts->kind != HS_PC_SCHUR && opts->kind != HS_PC_BLOCK_JACOBI && opts->kind != HS_PC_SCHUR_NONSYM &&
+                opts->kind != HS_PC_SCHUR_LOWRANK)
                 fail(HS_EINVAL, "unknown preconditioner kind");
+            if (opts->kind == HS_PC_SCHUR_LOWRANK && opts->precision != HS_PREC_FP64)
+                fail(HS_EINVAL, "the low-rank setup arithmetic is FP64 only");
             if (opts->kind == HS_PC_BLOCK_JACOBI && opts->precision != HS_PREC_FP64)
                 fail(HS_EINVAL, "the block-Jacobi comparator is FP64 only");
             if (opts->sweep_chunk < 0 || opts->sweep_chunk > hs::kMaxChunk) fail(HS_EINVAL, "sweep_chunk must be in [0, 384]");
@@ -2037,7 +2300,12 @@ int32_t hs_precond_setup_many(hs_context* ctx, int64_t count, const hs_hmatrix* 
             jp.push_back(j.get());
             jobs.push_back(std::move(j));
         }
-        eliminate(jp, ctx->stream);
+        if (opts->kind == HS_PC_SCHUR_LOWRANK) {
+            // one geometry at a time: each step's ranks come back to the host
+            for (auto& j : jobs) j->eliminate_lowrank();
+        } else {
+            eliminate(jp, ctx->stream);
+        }
         for (auto& j : jobs) j->finish();
         for (int64_t g = 0; g < count; ++g) out[g] = jobs[g]->P.release();
         return HS_OK;
@@ -2121,6 +2389,7 @@ int32_t hs_query_precond(const hs_precond* P, hs_info* info) {
     info->bytes_alpha = P->alpha_elems * 16;
     info->bytes_d = P->d_elems * 16;
     info->flops_fill = P->flops_fill;
+    if (P->flops_factored > 0) info->flops_setup = P->flops_factored;
     info->bytes_device = P->own.bytes;
     return HS_OK;
 }

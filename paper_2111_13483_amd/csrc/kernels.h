@@ -122,6 +122,25 @@ struct PtrCopy {
     int64_t count;
 };
 void launch_copy_ptrs(const PtrCopy* tasks, int64_t ntasks, cd* dst, hipStream_t s);
+// dst (rows x cols row-major, at dst_off) = the rows x cols column-major
+// matrix at src (a low-rank factor U laid into a row-major panel)
+struct ColMajorCopy {
+    const cd* src;
+    int64_t dst_off;
+    int32_t rows, cols;
+};
+void launch_copy_colmajor(const ColMajorCopy* tasks, int64_t ntasks, cd* dst, hipStream_t s);
+// Setup-side low-rank arithmetic: base[dst_off] (ba x bb row-major) +=
+// L^T T R with T = base[t_off] (ta x tb row-major), L = va (ra x ba
+// row-major, ta = ra) or the identity (va null, ta = ba), and R = vb (rb x
+// bb row-major, tb = rb) or the identity (vb null, tb = bb).
+struct CoreExpandTask {
+    const cd* va;
+    const cd* vb;
+    int64_t dst_off, t_off;
+    int32_t ba, bb, ra, rb;
+};
+void launch_core_expand(const CoreExpandTask* tasks, int64_t ntasks, cd* base, hipStream_t s);
 void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd* dst, hipStream_t s);
 // One elimination step k of one geometry (Eq. 14, 19). The pattern blocks
 // W_kj of row k (j in S_k ascending) lie back to back at x, b_k x b_j each,

@@ -41,6 +41,39 @@ __global__ void __launch_bounds__(NT) k_copy_ptrs(const PtrCopy* __restrict__ ta
     for (int64_t e = threadIdx.x; e < t.count; e += NT) d[e] = t.src[e];
 }
 
+__global__ void __launch_bounds__(NT) k_copy_colmajor(const ColMajorCopy* __restrict__ tasks, cd* __restrict__ dst) {
+    const ColMajorCopy t = tasks[blockIdx.x];
+    cd* d = dst + t.dst_off;
+    for (int e = threadIdx.x; e < t.rows * t.cols; e += NT) {
+        const int i = e / t.cols, l = e % t.cols;
+        d[e] = t.src[(int64_t)l * t.rows + i];
+    }
+}
+
+// One workgroup per target block; element (i, j) of L^T T R is
+// sum_p L[p][i] sum_q T[p][q] R[q][j], with identity factors skipped.
+__global__ void __launch_bounds__(NT) k_core_expand(const CoreExpandTask* __restrict__ tasks, cd* __restrict__ base) {
+    const CoreExpandTask t = tasks[blockIdx.x];
+    const int ta = t.va ? t.ra : t.ba, tb = t.vb ? t.rb : t.bb;
+    const cd* T = base + t.t_off;
+    cd* D = base + t.dst_off;
+    for (int e = threadIdx.x; e < t.ba * t.bb; e += NT) {
+        const int i = e / t.bb, j = e % t.bb;
+        cd acc = cmk(0.0, 0.0);
+        for (int pp = 0; pp < ta; ++pp) {
+            if (t.va == nullptr && pp != i) continue;
+            cd row = cmk(0.0, 0.0);   // (T R)[pp][j]
+            if (t.vb) {
+                for (int q = 0; q < tb; ++q) row = cfma(T[(int64_t)pp * tb + q], t.vb[(int64_t)q * t.bb + j], row);
+            } else {
+                row = T[(int64_t)pp * tb + j];
+            }
+            acc = t.va ? cfma(t.va[(int64_t)pp * t.ba + i], row, acc) : row;
+        }
+        D[e] = cadd(D[e], acc);
+    }
+}
+
 __global__ void __launch_bounds__(NT) k_to_c64(const PtrCopy* __restrict__ tasks, cf* __restrict__ dst) {
     const PtrCopy t = tasks[blockIdx.x];
     cf* d = dst + t.dst_off;
@@ -214,6 +247,14 @@ void launch_copy_blocks(const CopyTask* tasks, int64_t ntasks, const cd* src, cd
 
 void launch_copy_ptrs(const PtrCopy* tasks, int64_t ntasks, cd* dst, hipStream_t s) {
     if (ntasks > 0) hipLaunchKernelGGL(k_copy_ptrs, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, dst);
+}
+
+void launch_copy_colmajor(const ColMajorCopy* tasks, int64_t ntasks, cd* dst, hipStream_t s) {
+    if (ntasks > 0) hipLaunchKernelGGL(k_copy_colmajor, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, dst);
+}
+
+void launch_core_expand(const CoreExpandTask* tasks, int64_t ntasks, cd* base, hipStream_t s) {
+    if (ntasks > 0) hipLaunchKernelGGL(k_core_expand, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, base);
 }
 
 void launch_to_c64(const PtrCopy* tasks, int64_t ntasks, cf* dst, hipStream_t s) {
