@@ -1163,6 +1163,30 @@ namespace {
 
 // One preconditioner setup, in phases so that the elimination steps of several
 // geometries can share launches (hs_precond_setup_many).
+// The Schur tiles of one step: (ti, tj) covers panel rows kSchurRows ti ..
+// and columns 64 tj .. of the product W_kS^T alpha_kS and is listed when it
+// holds an element with block(row) <= block(column), i.e. when the block of
+// its first row is <= the block of its last column (pc: panel column starts
+// of the step's blocks, m columns).
+void schur_tile_list(const int32_t* pc, int32_t m, std::vector<std::pair<int16_t, int16_t>>& out) {
+    const int32_t nr = (m + hs::kSchurRows - 1) / hs::kSchurRows, nc = (m + 63) / 64;
+    std::vector<int32_t> afirst(nr), alast(nc);
+    int32_t a = 0;
+    for (int32_t t = 0; t < nr; ++t) {
+        while (pc[a + 1] <= hs::kSchurRows * t) ++a;
+        afirst[t] = a;
+    }
+    a = 0;
+    for (int32_t t = 0; t < nc; ++t) {
+        const int32_t g = std::min(64 * t + 63, m - 1);
+        while (pc[a + 1] <= g) ++a;
+        alast[t] = a;
+    }
+    for (int32_t ti = 0; ti < nr; ++ti)
+        for (int32_t tj = 0; tj < nc; ++tj)
+            if (afirst[ti] <= alast[tj]) out.emplace_back((int16_t)ti, (int16_t)tj);
+}
+
 struct SetupJob {
     hs_context* ctx = nullptr;
     const hs_hmatrix* H = nullptr;
@@ -1193,6 +1217,7 @@ struct SetupJob {
     Owned lrown;
     int64_t tcap = 0, xcap = 0;
     int* d_err = nullptr;
+    bool d_kept = false;   // D_k written by the elimination (else copied from W in finish)
     // elimination panels: the pattern in CSR (int32), per row the panel column
     // starts (ne + 1 values at rowptr[k] + k), the pair-table offsets, and the
     // Schur output tiles (ti, tj) of every step at tile_ptr[k] .. tile_ptr[k+1]
@@ -1331,7 +1356,6 @@ struct SetupJob {
         tile_ptr.assign(nb + 1, 0);
         panel_m.assign(nb, 0);
         tiles.clear();
-        std::vector<int32_t> afirst, alast;
         for (int64_t kk = 0; kk < nb; ++kk) {
             const int64_t r0 = sy.rowptr[kk], r1 = sy.rowptr[kk + 1], ne = r1 - r0;
             if (ne > hs::kMaxPattern) fail(HS_EINVAL, "a row of the filled pattern has more than 1024 blocks");
@@ -1345,25 +1369,7 @@ struct SetupJob {
             const int32_t m = pc[ne];
             panel_m[kk] = m;
             pair_ptr[kk + 1] = pair_ptr[kk] + ne * (ne + 1) / 2;
-            // tile (ti, tj) holds an element with block(row) <= block(column)
-            // iff the block of its first row is <= the block of its last column
-            const int32_t nt = (m + 63) / 64;
-            afirst.assign(nt, 0);
-            alast.assign(nt, 0);
-            int32_t a = 0;
-            for (int32_t t = 0; t < nt; ++t) {
-                while (pc[a + 1] <= 64 * t) ++a;
-                afirst[t] = a;
-            }
-            a = 0;
-            for (int32_t t = 0; t < nt; ++t) {
-                const int32_t g = std::min(64 * t + 63, m - 1);
-                while (pc[a + 1] <= g) ++a;
-                alast[t] = a;
-            }
-            for (int32_t ti = 0; ti < nt; ++ti)
-                for (int32_t tj = 0; tj < nt; ++tj)
-                    if (afirst[ti] <= alast[tj]) tiles.emplace_back((int16_t)ti, (int16_t)tj);
+            schur_tile_list(pc, m, tiles);
             tile_ptr[kk + 1] = (int64_t)tiles.size();
         }
     }
@@ -1508,23 +1514,11 @@ struct SetupJob {
                 // (ti, tj) holding an element with block(row) <= block(column)
                 const int32_t nt = (m + 63) / 64;
                 std::vector<hs::ElimTile> ft, stl;
-                for (int32_t t = 0; t < std::max<int32_t>(1, nt); ++t) ft.push_back(hs::ElimTile{0, (int16_t)t, 0});
+                for (int32_t t = 0; t < std::max<int32_t>(1, nt); ++t) ft.push_back(hs::ElimTile{0, (int16_t)t, -1});
                 {
-                    std::vector<int32_t> afirst(nt), alast(nt);
-                    int32_t a = 0;
-                    for (int32_t t = 0; t < nt; ++t) {
-                        while (pc[a + 1] <= 64 * t) ++a;
-                        afirst[t] = a;
-                    }
-                    a = 0;
-                    for (int32_t t = 0; t < nt; ++t) {
-                        const int32_t g = std::min(64 * t + 63, m - 1);
-                        while (pc[a + 1] <= g) ++a;
-                        alast[t] = a;
-                    }
-                    for (int32_t ti = 0; ti < nt; ++ti)
-                        for (int32_t tj = 0; tj < nt; ++tj)
-                            if (afirst[ti] <= alast[tj]) stl.push_back(hs::ElimTile{0, (int16_t)ti, (int16_t)tj});
+                    std::vector<std::pair<int16_t, int16_t>> tl;
+                    schur_tile_list(pc.data(), m, tl);
+                    for (const auto& t : tl) stl.push_back(hs::ElimTile{0, t.first, t.second});
                 }
                 hs::ElimStep es{};
                 es.wkk = W + wd_off[k];
@@ -1545,9 +1539,11 @@ struct SetupJob {
                 hs::launch_copy_blocks(st.upload(xc, s), (int64_t)xc.size(), W, Xp, s);
                 hs::launch_copy_colmajor(st.upload(uc, s), (int64_t)uc.size(), Xp, s);
                 hs::launch_copy_blocks(st.upload(zc, s), (int64_t)zc.size(), W, W, s);
-                timed(ctx, HS_KT_FACTOR, s, [&] { hs::launch_factor_alpha(d_es, st.upload(ft, s), (int64_t)ft.size(), s); });
+                timed(ctx, HS_KT_FACTOR, s, [&] {
+                    hs::launch_elim_items(d_es, st.upload(ft, s), (int64_t)ft.size(), false, s);
+                });
                 timed(ctx, HS_KT_SCHUR, s, [&] {
-                    hs::launch_schur_tiles(d_es, st.upload(stl, s), (int64_t)stl.size(), false, s);
+                    hs::launch_elim_items(d_es, st.upload(stl, s), (int64_t)stl.size(), false, s);
                 });
                 hs::launch_core_expand(st.upload(ex, s), (int64_t)ex.size(), W, s);
                 hip_check(hipGetLastError(), "low-rank elimination launches");
@@ -1565,12 +1561,14 @@ struct SetupJob {
         (void)o;
         hip_check(hipGetLastError(), "elimination launches");
         check_device_flag(d_err, s);
-        // keep D_k = final W_kk
-        std::vector<hs::CopyTask> dcp;
-        for (int64_t kk = 0; kk < nb; ++kk)
-            dcp.push_back(hs::CopyTask{P->d_off[kk], wd_off[kk], P->bsize[kk], P->bsize[kk], 0, 0});
-        hs::CopyTask* d_dcp = tmp.upload(dcp, s);
-        hs::launch_copy_blocks(d_dcp, (int64_t)dcp.size(), W, P->d_D, s);
+        // keep D_k = final W_kk (the persistent elimination has written it)
+        if (!d_kept) {
+            std::vector<hs::CopyTask> dcp;
+            for (int64_t kk = 0; kk < nb; ++kk)
+                dcp.push_back(hs::CopyTask{P->d_off[kk], wd_off[kk], P->bsize[kk], P->bsize[kk], 0, 0});
+            hs::CopyTask* d_dcp = tmp.upload(dcp, s);
+            hs::launch_copy_blocks(d_dcp, (int64_t)dcp.size(), W, P->d_D, s);
+        }
         // fill-in compression (Sec. 3.4)
         std::vector<int64_t> fill_e;
         for (int64_t e = 0; e < nnz; ++e)
@@ -2130,23 +2128,43 @@ struct SetupJob {
 };
 
 // The elimination of every job (Eq. 14, 19: invert W_kk, alpha_kj =
-// -W_kk^-1 W_kj, W_ij += W_ki^T alpha_kj): step k of all jobs with more than
-// k blocks shares one factor/alpha launch and one Schur launch.
+// -W_kk^-1 W_kj, W_ij += W_ki^T alpha_kj).
+//
+// Components of the leaf graph have separate elimination trees (every block
+// of S_k is an ancestor of k), so their steps read and write disjoint blocks,
+// while the steps of one component k_1, k_2, ... keep their order. Each entry
+// (a step; the non-symmetric elimination has two per non-empty row)
+// contributes factor tiles F (one per 64 panel columns, at least one) and
+// Schur tiles S. Per component the launches are
+//   {F(k_1)}, then for each i: {F(k_i+1), S(k_i)} when step k_i+1 takes the
+//   look-ahead (S_{k_i} starts with k_i+1: its factor tiles apply k_i's update
+//   of row k_i+1 themselves and k_i's Schur tiles skip that row), else
+//   {S(k_i)}, {F(k_i+1)};
+// launch g runs the g-th group of every component. Every item's inputs come
+// from earlier launches, so one kernel boundary per group orders the steps,
+// and with the look-ahead the inversion chain waits for no Schur launch.
+// (One persistent launch with device-side readiness counters, tried instead,
+// was slower: its blocks handed between workgroups needed device-scope loads
+// and stores, which made each Schur tile about twice as slow, 71.7 ms against
+// 59.6 ms on c2.)
 void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
     Owned tmp;
     tmp.mem = jobs.front()->ctx->mem;
-    int64_t steps = 0;
     std::vector<hs::ElimStep> es;
     std::vector<std::vector<int32_t>> sidx;   // per job and step: its (upper) entry in es
-    for (auto* j : jobs) {
+    std::vector<std::vector<int32_t>> lamap_h(jobs.size());
+    std::vector<int32_t*> lamap_d(jobs.size());
+    for (size_t q = 0; q < jobs.size(); ++q) {
+        SetupJob* j = jobs[q];
         hs_precond* P = j->P.get();
         const hs::Symbolic& sy = P->plan.sym;
-        steps = std::max(steps, j->nb);
         const int32_t* d_rp = tmp.upload(j->rp32, s);
         const int32_t* d_cols = tmp.upload(j->cols32, s);
         const int64_t* d_woff = tmp.upload(j->w_off, s);
         const int64_t* d_wdoff = tmp.upload(j->wd_off, s);
         const int32_t* d_pcol = tmp.upload(j->pcol, s);
+        lamap_h[q].assign(std::max<size_t>(j->cols32.size(), 1), -1);
+        lamap_d[q] = tmp.get<int32_t>(lamap_h[q].size());
         int64_t* d_pair = tmp.get<int64_t>(std::max<int64_t>(j->pair_ptr[j->nb], 1));
         std::vector<hs::PairStep> ps;
         sidx.emplace_back(j->nb);
@@ -2168,6 +2186,9 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
             e.ne = ne;
             e.m = j->panel_m[k];
             e.flags = 0;
+            e.dfin = P->d_D + P->d_off[k];
+            e.lamap = lamap_d[q] + r0;
+            e.prev = -1;
             sidx.back()[k] = (int32_t)es.size();
             es.push_back(e);
             if (j->nonsym && ne > 0) {
@@ -2178,67 +2199,112 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
                 l.y = j->Bd + j->ad_off[r0];
                 l.w = j->WL;
                 l.flags = hs::kElimTrans | hs::kElimStrict;
+                l.dfin = nullptr;
                 es.push_back(l);
             }
         }
         hs::PairStep* d_ps = tmp.upload(ps, s);
         hs::launch_pair_table(d_ps, (int64_t)ps.size(), j->d_err, s);
+        j->d_kept = true;
     }
-    // Launch L takes, from every job, the steps that are the L-th of their
-    // connected component of the leaf graph. Components have separate
-    // elimination trees (every block of S_k is an ancestor of k), so their
-    // steps read and write disjoint blocks, while the steps of one component
-    // keep their order. Per launch: factor/alpha tiles (one per 64 panel
-    // columns, at least one) and Schur tiles. (Running the Schur tiles that
-    // the next step's row does not need on a second stream, beside the next
-    // factor launch, made the c2 elimination slower, 70.6 ms against 61: the
-    // factor workgroups need a whole CU's LDS, and the split launch and the
-    // cross-stream waits cost more than the overlap gained.)
-    std::vector<std::vector<std::pair<size_t, int64_t>>> launch;   // (job, step) per launch
+    // components: the steps of each, in order (a component's steps are those
+    // with the same elimination-tree root)
+    std::vector<std::vector<std::pair<size_t, int64_t>>> comps;
     for (size_t q = 0; q < jobs.size(); ++q) {
         SetupJob* j = jobs[q];
         const hs::Symbolic& sy = j->P->plan.sym;
-        // component of each step: that of its elimination-tree root
         std::vector<int64_t> root(j->nb);
         for (int64_t k = j->nb - 1; k >= 0; --k) root[k] = sy.parent[k] < 0 ? k : root[sy.parent[k]];
-        std::unordered_map<int64_t, int64_t> seen;
+        std::unordered_map<int64_t, size_t> cid;
         for (int64_t k = 0; k < j->nb; ++k) {
-            const int64_t L = seen[root[k]]++;
-            if ((int64_t)launch.size() <= L) launch.resize(L + 1);
-            launch[L].push_back({q, k});
+            auto it = cid.find(root[k]);
+            if (it == cid.end()) {
+                it = cid.emplace(root[k], comps.size()).first;
+                comps.emplace_back();
+            }
+            comps[it->second].push_back({q, k});
         }
     }
-    const int64_t nl = (int64_t)launch.size();
-    std::vector<hs::ElimTile> ft, st;
-    std::vector<int64_t> fp(nl + 1, 0), sp(nl + 1, 0);
-    for (int64_t L = 0; L < nl; ++L) {
-        for (const auto& qk : launch[L]) {
-            SetupJob* j = jobs[qk.first];
-            const int64_t k = qk.second;
-            const int32_t step = sidx[qk.first][k];
-            const int32_t nt = std::max<int32_t>(1, (j->panel_m[k] + 63) / 64);
-            // the non-symmetric elimination's second entry (step + 1) exists iff row k is not empty
-            const int32_t nent = j->nonsym && j->panel_m[k] > 0 ? 2 : 1;
-            for (int32_t q = 0; q < nent; ++q) {
-                for (int32_t t = 0; t < nt; ++t) ft.push_back(hs::ElimTile{step + q, (int16_t)t, 0});
-                for (int64_t t = j->tile_ptr[k]; t < j->tile_ptr[k + 1]; ++t)
-                    st.push_back(hs::ElimTile{step + q, j->tiles[t].first, j->tiles[t].second});
+    // the look-ahead: flags, previous entries and the maps of S_k into S_p
+    for (const auto& c : comps) {
+        for (size_t i = 1; i < c.size(); ++i) {
+            const size_t q = c[i].first;
+            SetupJob* j = jobs[q];
+            if (j->nonsym) continue;
+            const int64_t kp = c[i - 1].second, k = c[i].second;
+            const hs::Symbolic& sy = j->P->plan.sym;
+            const int64_t p0 = sy.rowptr[kp], p1 = sy.rowptr[kp + 1];
+            if (p1 == p0 || sy.cols[p0] != k) continue;
+            // only where the factor tile stages its look-ahead operands in
+            // LDS (b_k <= 32, b_p <= 64): for larger blocks the update's
+            // global-memory round trips cost more than the Schur launch
+            if (j->P->bsize[k] > 32 || j->P->bsize[kp] > 64) continue;
+            const int32_t ep = sidx[q][kp], ek = sidx[q][k];
+            es[ek].flags |= hs::kElimLook;
+            es[ek].prev = ep;
+            es[ep].flags |= hs::kElimSkip0;
+            // each block of S_k: its first column in kp's panel (S_kp sorted; -1 if absent)
+            const int64_t r0 = sy.rowptr[k], r1 = sy.rowptr[k + 1];
+            int64_t e2 = p0;
+            for (int64_t e = r0; e < r1; ++e) {
+                while (e2 < p1 && sy.cols[e2] < sy.cols[e]) ++e2;
+                lamap_h[q][e] = (e2 < p1 && sy.cols[e2] == sy.cols[e]) ? j->pcol[p0 + kp + (e2 - p0)] : -1;
             }
         }
-        fp[L + 1] = (int64_t)ft.size();
-        sp[L + 1] = (int64_t)st.size();
     }
-    (void)steps;
-    hs::ElimStep* d_es = tmp.upload(es, s);
-    hs::ElimTile* d_ft = tmp.upload(ft, s);
-    hs::ElimTile* d_st = tmp.upload(st, s);
+    for (size_t q = 0; q < jobs.size(); ++q)
+        hip_check(hipMemcpyAsync(lamap_d[q], lamap_h[q].data(), sizeof(int32_t) * lamap_h[q].size(),
+                                 hipMemcpyHostToDevice, s), "upload lamap");
+    // the launch groups of each component, then launch g = every component's g-th group
+    auto add_f = [&](std::vector<hs::ElimTile>& out, size_t q, int64_t k) {
+        const int32_t e0 = sidx[q][k];
+        const int32_t nent = jobs[q]->nonsym && jobs[q]->panel_m[k] > 0 ? 2 : 1;
+        const int32_t nt = std::max<int32_t>(1, (jobs[q]->panel_m[k] + 63) / 64);
+        for (int32_t t = 0; t < nent; ++t)
+            for (int32_t i = 0; i < nt; ++i) out.push_back(hs::ElimTile{e0 + t, (int16_t)i, -1});
+    };
+    auto add_s = [&](std::vector<hs::ElimTile>& out, size_t q, int64_t k) {
+        SetupJob* j = jobs[q];
+        const int32_t e0 = sidx[q][k];
+        const int32_t nent = j->nonsym && j->panel_m[k] > 0 ? 2 : 1;
+        for (int32_t t = 0; t < nent; ++t)
+            for (int64_t i = j->tile_ptr[k]; i < j->tile_ptr[k + 1]; ++i)
+                out.push_back(hs::ElimTile{e0 + t, j->tiles[i].first, j->tiles[i].second});
+    };
+    std::vector<std::vector<hs::ElimTile>> groups;
+    for (const auto& c : comps) {
+        size_t g = 0;
+        auto at = [&](size_t gi) -> std::vector<hs::ElimTile>& {
+            if (groups.size() <= gi) groups.resize(gi + 1);
+            return groups[gi];
+        };
+        add_f(at(g++), c[0].first, c[0].second);
+        for (size_t i = 0; i < c.size(); ++i) {
+            const size_t q = c[i].first;
+            const bool next = i + 1 < c.size();
+            if (next && (es[sidx[q][c[i + 1].second]].flags & hs::kElimLook)) {
+                auto& grp = at(g++);
+                add_f(grp, q, c[i + 1].second);
+                add_s(grp, q, c[i].second);
+            } else {
+                add_s(at(g++), q, c[i].second);
+                if (next) add_f(at(g++), q, c[i + 1].second);
+            }
+        }
+    }
+    std::vector<int64_t> gp(groups.size() + 1, 0);
+    std::vector<hs::ElimTile> items;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        items.insert(items.end(), groups[g].begin(), groups[g].end());
+        gp[g + 1] = (int64_t)items.size();
+    }
+    const hs::ElimStep* d_es = tmp.upload(es, s);
+    const hs::ElimTile* d_items = tmp.upload(items, s);
     hs_context* ctx = jobs.front()->ctx;
     const bool fp32 = jobs.front()->opts->precision == HS_PREC_MIXED;
     timed(ctx, HS_KT_ELIM, s, [&] {
-        for (int64_t L = 0; L < nl; ++L) {
-            timed(ctx, HS_KT_FACTOR, s, [&] { hs::launch_factor_alpha(d_es, d_ft + fp[L], fp[L + 1] - fp[L], s); });
-            timed(ctx, HS_KT_SCHUR, s, [&] { hs::launch_schur_tiles(d_es, d_st + sp[L], sp[L + 1] - sp[L], fp32, s); });
-        }
+        for (size_t g = 0; g < groups.size(); ++g)
+            timed(ctx, HS_KT_FACTOR, s, [&] { hs::launch_elim_items(d_es, d_items + gp[g], gp[g + 1] - gp[g], fp32, s); });
     });
     hip_check(hipGetLastError(), "elimination launches");
     hip_check(hipStreamSynchronize(s), "stream sync");

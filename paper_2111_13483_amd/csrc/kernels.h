@@ -14,6 +14,7 @@ enum : int { kErrSingular = 1, kErrNumeric = 2, kErrRankCap = 4, kErrCoincident 
 
 constexpr int kMaxLeaf = 96;       // largest leaf block the dense kernels take (LDS bound)
 constexpr int kMaxPattern = 1024;  // longest row of the filled pattern the elimination takes
+constexpr int kSchurRows = 128;    // Schur tiles of the elimination: kSchurRows x 64 panel columns
 
 // Per-column GMRES state on the device.
 struct ColState {
@@ -159,6 +160,11 @@ struct ElimStep {
     const int32_t* pcol;   // ne + 1 panel column starts
     int* err;              // device error flag of the geometry
     int32_t bk, ne, m, flags;
+    // look-ahead (kElimLook):
+    cd* dfin;              // the final W_kk, written by factor tile 0 (null: left in W)
+    const int32_t* lamap;  // per block a of S_k, its first column in the previous step's panel (-1: absent)
+    int32_t prev;          // entry of the previous step of the same component (-1: none)
+    int32_t pad;
 };
 // ElimStep flags. Symmetric elimination: none (xs = x). The non-symmetric
 // elimination (Sec. 3.2's comparator) runs two entries per step:
@@ -168,8 +174,16 @@ struct ElimStep {
 //          W_kS; targets Wt_ab += W_ka^T y_kb (kElimStrict: a < b only).
 constexpr int32_t kElimTrans = 1;    // factor: y = -W_kk^-T x, and D^-1 is not written
 constexpr int32_t kElimStrict = 2;   // Schur: only targets with block(row) < block(column)
-// One workgroup's share of a step: panel column tile ti (factor/alpha) or
-// output tile (ti, tj) (Schur update).
+// Look-ahead (symmetric elimination): when S_p of the previous step p of the
+// component starts with k, step k's factor tiles apply p's update of row k
+// themselves (kElimLook on k) and p's Schur tiles skip the rows of their
+// block 0 (kElimSkip0 on p), so step k's factor tiles and p's Schur tiles can
+// share a launch.
+constexpr int32_t kElimLook = 4;
+constexpr int32_t kElimSkip0 = 8;
+// One workgroup's share of a step: panel column tile ti (factor/alpha, 64
+// columns) or output tile (ti, tj) (Schur update: panel rows kSchurRows ti ..,
+// columns 64 tj ..).
 struct ElimTile {
     int32_t step;
     int16_t ti, tj;
@@ -186,9 +200,11 @@ struct PairStep {
     int32_t ne, pad;
 };
 void launch_pair_table(const PairStep* steps, int64_t nsteps, int* err, hipStream_t s);
-void launch_factor_alpha(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, hipStream_t s);
-// fp32: the products in complex64 with FP32 accumulation (mixed-precision setups)
-void launch_schur_tiles(const ElimStep* steps, const ElimTile* tiles, int64_t ntiles, bool fp32, hipStream_t s);
+// One elimination launch over items (tj < 0: a factor tile, ti its panel
+// tile; else Schur tile (ti, tj)) whose inputs earlier launches wrote. fp32:
+// the Schur products in complex64 with FP32 accumulation (mixed-precision
+// setups).
+void launch_elim_items(const ElimStep* steps, const ElimTile* items, int64_t nitems, bool fp32, hipStream_t s);
 // Chunk products M = L C of the sweep plan, by 64 x 64 output tiles: one
 // entry per row of a chunk (A row at a_off, nonzero over chunk columns
 // [k0, k0 + kw), output row at c_off) and one per tile (chunk, first row,
