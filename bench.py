@@ -29,7 +29,7 @@ KERNEL_SOURCES = ("paper_2111_13483_amd/csrc/kernels_sweep.hip", "paper_2111_134
 # the instrumented launches and their kernels' names
 TIMING_EVERY = 4
 KERNEL_NAME = {"sweep_fwd": "k_sweep_fwd", "sweep_bwd": "k_sweep_bwd", "near_mv": "k_near_mv", "far_mv": "k_far_mv",
-               "factor": "k_factor_alpha", "schur": "k_schur_tiles"}
+               "factor": "k_elim_items", "schur": "k_elim_items"}
 SOLVE_KERNELS = ("sweep_fwd", "sweep_bwd", "near_mv", "far_mv")
 # the kernels behind each instrumented launch (the far matvec is two kernels,
 # each dispatched once per matvec, on one stream inside one timed region)
@@ -182,7 +182,7 @@ def summarize_fp64(d, out, command, flops_setup):
     for counter in ("SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_FMA_F64"):
         try:
             for name, v in _read_counters(d, counter):
-                for pre in ("k_factor_alpha", "k_schur_tiles"):
+                for pre in ("k_elim_items",):
                     if pre in name:
                         a = rows.setdefault((pre, counter), [0, 0.0])
                         a[0] += 1
@@ -900,16 +900,17 @@ def main():
                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic.get(dom),
                        "alg_bytes_per_launch": alg[dom], "avg_launch_ms": kern[dom]["avg_ms"]}
     # the setup's elimination against the FP64 peak: exact algorithmic flops
-    # of the filled pattern over the elimination's wall time per setup (its
-    # factor and Schur launches overlap on two streams)
+    # of the filled pattern over the elimination's wall time per setup (from
+    # its first launch to its last, gaps included)
     if "elimination" in kern and "factor" in kern:
         t_elim = kern["elimination"]["ms_per_step"] * 1e-3
         tf = pinfo["flops_setup"] / t_elim / 1e12
-        out["setup_roofline"] = {"bound": "fp64", "kernels": ["k_factor_alpha", "k_schur_tiles"],
+        out["setup_roofline"] = {"bound": "fp64", "kernels": ["k_elim_items"],
                                  "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                                  "frac": tf / FP64_PEAK_TFLOPS, "elimination_ms": t_elim * 1e3,
                                  "flops": pinfo["flops_setup"],
-                                 "launches_per_setup": kern["factor"]["all_launches"] // steps}
+                                 "launches_per_setup": (kern["factor"]["all_launches"] +
+                                                        kern.get("schur", {}).get("all_launches", 0)) // steps}
     out["kernels"] = kern
     # comparison legs on the same geometry (untimed by the step loop)
     legs = {}

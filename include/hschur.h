@@ -342,8 +342,10 @@ int32_t hs_matvec_noalloc(hs_context* ctx, const hs_hmatrix* H, const void* x, v
 #define HS_KT_SWEEP_BWD 1
 #define HS_KT_NEAR_MV   2
 #define HS_KT_FAR_MV    3
-#define HS_KT_FACTOR    4   /* elimination: leaf-block inversion and alpha panel tiles (Eq. 14, 19) */
-#define HS_KT_SCHUR     5   /* elimination: Schur-complement update tiles (Eq. 38-42) */
+#define HS_KT_FACTOR    4   /* elimination launches holding leaf-block inversions and alpha panel tiles
+                               (Eq. 14, 19), with the previous step's Schur tiles beside them when the
+                               step takes the look-ahead */
+#define HS_KT_SCHUR     5   /* elimination launches of Schur-complement update tiles alone (Eq. 38-42) */
 #define HS_KT_ELIM      6   /* a whole elimination (all steps of one setup call) on ctx's stream: its wall
                                time, the launch gaps between its kernels included */
 #define HS_KT_COUNT     7

@@ -2303,8 +2303,12 @@ void eliminate(std::vector<SetupJob*>& jobs, hipStream_t s) {
     hs_context* ctx = jobs.front()->ctx;
     const bool fp32 = jobs.front()->opts->precision == HS_PREC_MIXED;
     timed(ctx, HS_KT_ELIM, s, [&] {
-        for (size_t g = 0; g < groups.size(); ++g)
-            timed(ctx, HS_KT_FACTOR, s, [&] { hs::launch_elim_items(d_es, d_items + gp[g], gp[g + 1] - gp[g], fp32, s); });
+        for (size_t g = 0; g < groups.size(); ++g) {
+            bool has_f = false;
+            for (int64_t i = gp[g]; i < gp[g + 1] && !has_f; ++i) has_f = items[i].tj < 0;
+            timed(ctx, has_f ? HS_KT_FACTOR : HS_KT_SCHUR, s,
+                  [&] { hs::launch_elim_items(d_es, d_items + gp[g], gp[g + 1] - gp[g], fp32, s); });
+        }
     });
     hip_check(hipGetLastError(), "elimination launches");
     hip_check(hipStreamSynchronize(s), "stream sync");
