@@ -316,8 +316,9 @@ struct GjRot {
 
 // Gauss-Jordan inversion of W_kk for b <= 2U <= 32 by wave 0 alone, with no
 // barrier per pivot step: lane = row r (lane & 31) in half h (lane >> 5).
-// W_kk is read from LDS (row-major, stride b, possibly sharing A's storage:
-// wave 0 holds it in registers before it writes A). Pivot rule: the largest
+// W_kk is read from LDS (row-major, row stride ldi, possibly sharing A's
+// storage: wave 0 holds it in registers before it writes A); the result goes
+// to A column-major with column stride ldo. Pivot rule: the largest
 // |a|^2 among the rows not yet eliminated, ties to the lowest position in the
 // interchanged order; rows are not moved (each lane keeps its row's position
 // and a used flag) and each column is stored by final position at the end,
@@ -332,7 +333,7 @@ struct GjRot {
 // *okf carries the outcome to them.
 template <int U>
 __device__ __forceinline__ bool gj_invert_rot(const cd* wkk, int b, int* err, cd* A, cd* rowx, cd* colx,
-                                              int* srcmap, int* okf) {
+                                              int* srcmap, int* okf, int ldi, int ldo) {
     const int tid = threadIdx.x, lane = tid % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
     if (wv == 0) {
@@ -348,7 +349,7 @@ __device__ __forceinline__ bool gj_invert_rot(const cd* wkk, int b, int* err, cd
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = 2 * u + g.h;
-            g.e[u] = wkk[(g.vr ? g.r : 0) * b + (j < b ? j : 0)];
+            g.e[u] = wkk[(g.vr ? g.r : 0) * ldi + (j < b ? j : 0)];
         }
         g.pos = g.r;
         g.x0 = lane;
@@ -371,7 +372,7 @@ __device__ __forceinline__ bool gj_invert_rot(const cd* wkk, int b, int* err, cd
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = 2 * ((u + T) % U) + g.h;
-                if (j < b && g.vr) A[j * kLdc + g.pos] = g.e[u];
+                if (j < b && g.vr) A[j * ldo + g.pos] = g.e[u];
             }
             if (lane < b) srcmap[lane] = g.x0;
         }
@@ -381,6 +382,20 @@ __device__ __forceinline__ bool gj_invert_rot(const cd* wkk, int b, int* err, cd
     return *okf != 0;
 }
 
+
+// gj_invert_rot with U chosen for b <= 32 (U = ceil(b / 2), rounded up to even)
+__device__ __forceinline__ bool invert_small(const cd* src, int b, int* err, cd* out, cd* rowx, cd* colx, int* srcmap,
+                                             int* okf, int ldi, int ldo) {
+    const int need = (b + 1) / 2;
+    if (need <= 2) return gj_invert_rot<2>(src, b, err, out, rowx, colx, srcmap, okf, ldi, ldo);
+    if (need <= 4) return gj_invert_rot<4>(src, b, err, out, rowx, colx, srcmap, okf, ldi, ldo);
+    if (need <= 6) return gj_invert_rot<6>(src, b, err, out, rowx, colx, srcmap, okf, ldi, ldo);
+    if (need <= 8) return gj_invert_rot<8>(src, b, err, out, rowx, colx, srcmap, okf, ldi, ldo);
+    if (need <= 10) return gj_invert_rot<10>(src, b, err, out, rowx, colx, srcmap, okf, ldi, ldo);
+    if (need <= 12) return gj_invert_rot<12>(src, b, err, out, rowx, colx, srcmap, okf, ldi, ldo);
+    if (need <= 14) return gj_invert_rot<14>(src, b, err, out, rowx, colx, srcmap, okf, ldi, ldo);
+    return gj_invert_rot<16>(src, b, err, out, rowx, colx, srcmap, okf, ldi, ldo);
+}
 
 namespace {
 
@@ -442,6 +457,97 @@ struct SchurSmem {
     int rst[kTileR], cst[kTile];     // its first panel column
     int rbj[kTileR], cbj[kTile];     // its width
 };
+
+// W_kk^-1 for 32 < b <= 64 by 2 x 2 blocks: with W_kk = [P Q; R T] (P of
+// b1 = ceil(b / 2) rows), P^-1 and the inverse of the Schur complement
+// T - R P^-1 Q each come from the single-wave Gauss-Jordan (partial pivoting
+// within each half), joined by products in LDS:
+//   E = P^-1 Q, F = R P^-1, H = (T - R E)^-1, G = E H,
+//   W_kk^-1 = [P^-1 + G F, -G; -H F, H].
+// Two inversions of b / 2 pivots cost less than one eight-wave inversion of
+// b pivots (measured: 313k cycles at b = 64 for the latter). W_kk is in A
+// (row-major, stride b); on return A holds W_kk^-1 column-major (stride
+// kLdc) with srcmap the identity, the layout gj_invert leaves.
+__device__ __forceinline__ bool invert_blocked(FactorSmem& sm, int b, int* err) {
+    const int tid = threadIdx.x;
+    const int b1 = (b + 1) / 2, b2 = b - b1;
+    const int l1 = b1 + 1, l2 = b2 + 1;   // column strides of the half inverses
+    cd* const M = sm.A;
+    cd* const Po = sm.A + 4096;            // P^-1 by columns (b1 x l1)
+    cd* const E = Po + 32 * 33;            // b1 x b2
+    cd* const F = E + 32 * 32;             // b2 x b1
+    cd* const Sc = F + 32 * 32;            // b2 x b2, then H by columns
+    cd* const Ho = Sc + 32 * 32;           // b2 x l2
+    int* const sp = sm.srcmap;
+    int* const sh = sm.srcmap + 32;
+    if (!invert_small(M, b1, err, Po, sm.colbuf[0], sm.colbuf[1], sp, &sm.okf, b, l1)) return false;
+    // P^-1[i][j] = Po[sp[j] l1 + i]
+    for (int e = tid; e < 2 * b1 * b2; e += NTF) {
+        cd acc = cmk(0.0, 0.0);
+        if (e < b1 * b2) {
+            const int i = e / b2, j = e - (e / b2) * b2;
+            for (int l = 0; l < b1; ++l) acc = cfma(Po[sp[l] * l1 + i], M[l * b + b1 + j], acc);
+            E[e] = acc;
+        } else {
+            const int f = e - b1 * b2, i = f / b1, j = f - (f / b1) * b1;
+            for (int l = 0; l < b1; ++l) acc = cfma(M[(b1 + i) * b + l], Po[sp[j] * l1 + l], acc);
+            F[f] = acc;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < b2 * b2; e += NTF) {
+        const int i = e / b2, j = e - (e / b2) * b2;
+        cd acc = cmk(0.0, 0.0);
+        for (int l = 0; l < b1; ++l) acc = cfma(M[(b1 + i) * b + l], E[l * b2 + j], acc);
+        Sc[e] = csub(M[(b1 + i) * b + b1 + j], acc);
+    }
+    __syncthreads();
+    if (!invert_small(Sc, b2, err, Ho, sm.colbuf[0], sm.colbuf[1], sh, &sm.okf, b2, l2)) return false;
+    // H[i][j] = Ho[sh[j] l2 + i]; G = E H over M (no longer needed)
+    cd* const G = M;
+    for (int e = tid; e < b1 * b2; e += NTF) {
+        const int i = e / b2, j = e - (e / b2) * b2;
+        cd acc = cmk(0.0, 0.0);
+        for (int k = 0; k < b2; ++k) acc = cfma(E[i * b2 + k], Ho[sh[j] * l2 + k], acc);
+        G[e] = acc;
+    }
+    __syncthreads();
+    constexpr int PT = 64 * 64 / NTF;
+    cd v[PT];
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int e = tid + u * NTF;
+        v[u] = cmk(0.0, 0.0);
+        if (e < b * b) {
+            const int i = e / b, j = e - (e / b) * b;
+            if (i < b1 && j < b1) {
+                cd acc = Po[sp[j] * l1 + i];
+                for (int k = 0; k < b2; ++k) acc = cfma(G[i * b2 + k], F[k * b1 + j], acc);
+                v[u] = acc;
+            } else if (i < b1) {
+                v[u] = cscale(G[i * b2 + (j - b1)], -1.0);
+            } else if (j < b1) {
+                cd acc = cmk(0.0, 0.0);
+                for (int k = 0; k < b2; ++k) acc = cfma(Ho[sh[k] * l2 + (i - b1)], F[k * b1 + j], acc);
+                v[u] = cscale(acc, -1.0);
+            } else {
+                v[u] = Ho[sh[j - b1] * l2 + (i - b1)];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int e = tid + u * NTF;
+        if (e < b * b) {
+            const int i = e / b, j = e - (e / b) * b;
+            sm.A[j * kLdc + i] = v[u];
+        }
+    }
+    if (tid < b) sm.srcmap[tid] = tid;
+    __syncthreads();
+    return true;
+}
 
 // The look-ahead update of one factor tile's columns (kElimLook):
 // step k applies the previous step p's update of its own row, X_kg += W_pk^T
@@ -589,20 +695,7 @@ __device__ __forceinline__ void factor_tile_small(const ElimStep& st, const Elim
             for (int l = wv - 1; l < b; l += NWF - 1) Xs[l * kTile + lane] = X.ld(on ? xg + (int64_t)l * bj : -1);
         }
     }
-    bool ok;
-    {
-        const int need = (b + 1) / 2;
-        cd* rx = sm.colbuf[0];
-        cd* cx = sm.colbuf[1];
-        if (need <= 2) ok = gj_invert_rot<2>(A, b, st.err, A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 4) ok = gj_invert_rot<4>(A, b, st.err, A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 6) ok = gj_invert_rot<6>(A, b, st.err, A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 8) ok = gj_invert_rot<8>(A, b, st.err, A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 10) ok = gj_invert_rot<10>(A, b, st.err, A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 12) ok = gj_invert_rot<12>(A, b, st.err, A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 14) ok = gj_invert_rot<14>(A, b, st.err, A, rx, cx, sm.srcmap, &sm.okf);
-        else ok = gj_invert_rot<16>(A, b, st.err, A, rx, cx, sm.srcmap, &sm.okf);
-    }
+    const bool ok = invert_small(A, b, st.err, A, sm.colbuf[0], sm.colbuf[1], sm.srcmap, &sm.okf, b, kLdc);
     if (!ok) return;
     const bool tr = (st.flags & kElimTrans) != 0;
     if (ti == 0 && !tr)
@@ -687,21 +780,16 @@ __device__ __forceinline__ void factor_tile(const ElimStep& st, const ElimStep* 
     bool ok;
     if (b <= 32) {
         if (ps && wv > 0) lookahead_cols<(32 + NWF - 2) / (NWF - 1)>(st, *ps, sm, g0, wv - 1, NWF - 1);
-        const int need = (b + 1) / 2;
-        cd* rx = sm.colbuf[0];
-        cd* cx = sm.colbuf[1];
-        if (need <= 2) ok = gj_invert_rot<2>(sm.A, b, st.err, sm.A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 4) ok = gj_invert_rot<4>(sm.A, b, st.err, sm.A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 6) ok = gj_invert_rot<6>(sm.A, b, st.err, sm.A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 8) ok = gj_invert_rot<8>(sm.A, b, st.err, sm.A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 10) ok = gj_invert_rot<10>(sm.A, b, st.err, sm.A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 12) ok = gj_invert_rot<12>(sm.A, b, st.err, sm.A, rx, cx, sm.srcmap, &sm.okf);
-        else if (need <= 14) ok = gj_invert_rot<14>(sm.A, b, st.err, sm.A, rx, cx, sm.srcmap, &sm.okf);
-        else ok = gj_invert_rot<16>(sm.A, b, st.err, sm.A, rx, cx, sm.srcmap, &sm.okf);
+        ok = invert_small(sm.A, b, st.err, sm.A, sm.colbuf[0], sm.colbuf[1], sm.srcmap, &sm.okf, b, kLdc);
+    } else if (b <= 64) {
+        ok = invert_blocked(sm, b, st.err);
+        if (ps) {
+            lookahead_cols<4>(st, *ps, sm, g0, wv, NWF);
+            __syncthreads();
+        }
     } else {
-        if (b <= kWave) ok = gj_invert<8, false>(sm.A, b, st.err, sm.A, sm.colbuf, sm.pinv, sm.prow, sm.srcmap);
-        else ok = gj_invert<(kMaxLeaf + NWF - 1) / NWF, true>(sm.A, b, st.err, sm.A, sm.colbuf, sm.pinv, sm.prow,
-                                                             sm.srcmap);
+        ok = gj_invert<(kMaxLeaf + NWF - 1) / NWF, true>(sm.A, b, st.err, sm.A, sm.colbuf, sm.pinv, sm.prow,
+                                                         sm.srcmap);
         if (ps) {
             lookahead_cols<4>(st, *ps, sm, g0, wv, NWF);
             __syncthreads();
