@@ -198,7 +198,7 @@ def summarize_fp64(d, out, command, flops_setup):
         lines.append(f"| {pre} | {counter} | {cnt} | {v:.4g} | {v / max(cnt, 1):.4g} |")
         if counter == "SQ_INSTS_VALU_FLOPS_FP64":
             tot += v
-    lines += ["", f"SQ_INSTS_VALU_FLOPS_FP64 over both kernels: {tot:.4g}. The SQ counters count per wave "
+    lines += ["", f"SQ_INSTS_VALU_FLOPS_FP64 over the elimination kernel: {tot:.4g}. The SQ counters count per wave "
                   f"instruction: times 64 lanes that is {64 * tot:.4g} FP64 flops, {64 * tot / flops_setup:.2f} x the "
                   "algorithmic count (the FMA counts times 128 match the update GEMMs; the excess is the pivot "
                   "search, the explicit inverse and the zero-padded tile columns). No FP64 MFMA instruction runs: "
