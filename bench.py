@@ -894,7 +894,9 @@ def main():
         kern["near_mv"]["overlaps"] = "far_mv"
     dom = max((k for k in SOLVE_KERNELS if k in kern and "overlaps" not in kern[k]),
               key=lambda k: kern[k]["ms_per_step"])
-    traffic = committed_traffic()
+    # the committed counters were taken on the default workload (c2, full size,
+    # one column): other workloads report no traffic
+    traffic = committed_traffic() if (args.workload == "c2" and not args.n and nrhs == 1 and not args.mixed) else {}
     achieved = kern[dom]["GB_per_s"]
     out["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAME[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic.get(dom),
