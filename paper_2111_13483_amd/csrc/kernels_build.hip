@@ -90,13 +90,14 @@ __device__ __forceinline__ cd src_val(const AcaTask& t, const double* pts, doubl
 // m + n "used" bytes.
 template <bool DENSE>
 __global__ void __launch_bounds__(NT)
-k_aca(const AcaTask* __restrict__ tasks, const double* __restrict__ pts, double k, const cd* __restrict__ dense,
-      cd* __restrict__ scratch, uint8_t* __restrict__ flags, double eps, int* __restrict__ rank_out,
-      int* __restrict__ piv_log, int piv_stride, int* err) {
+k_aca(const AcaTask* __restrict__ tasks, const int* __restrict__ order, const double* __restrict__ pts, double k,
+      const cd* __restrict__ dense, cd* __restrict__ scratch, uint8_t* __restrict__ flags, double eps,
+      int* __restrict__ rank_out, int* __restrict__ piv_log, int piv_stride, int* err) {
     __shared__ double redv[NW];
     __shared__ int redi[NW];
     __shared__ double cross_part[NW];
-    const AcaTask t = tasks[blockIdx.x];
+    const int bi = order[blockIdx.x];   // the largest blocks first
+    const AcaTask t = tasks[bi];
     const int m = t.m, n = t.n, cap = t.cap;
     cd* U = scratch + t.u_off;
     cd* V = scratch + t.v_off;
@@ -169,8 +170,8 @@ k_aca(const AcaTask* __restrict__ tasks, const double* __restrict__ pts, double 
         for (int w = 0; w < NW; ++w) cross += cross_part[w];
         norm2 += nu2 * nv2 + 2.0 * cross;
         if (tid == 0 && piv_log) {
-            piv_log[(int64_t)blockIdx.x * piv_stride + 2 * rank] = i;
-            piv_log[(int64_t)blockIdx.x * piv_stride + 2 * rank + 1] = js;
+            piv_log[(int64_t)bi * piv_stride + 2 * rank] = i;
+            piv_log[(int64_t)bi * piv_stride + 2 * rank + 1] = js;
         }
         ++rank;
         if (sqrt(nu2 * nv2) <= eps * sqrt(fmax(norm2, 0.0))) break;
@@ -187,7 +188,7 @@ k_aca(const AcaTask* __restrict__ tasks, const double* __restrict__ pts, double 
         i = nx.i;
     }
     if (tid == 0) {
-        rank_out[blockIdx.x] = rank;
+        rank_out[bi] = rank;
         if (capped) raise_err(err, kErrRankCap);
     }
 }
@@ -292,26 +293,29 @@ __device__ void jacobi_svd(cd* M, cd* X, int r, int* rot_flag) {
 
 // Re-compression, phase A: QR of U and V^T in place, core M = R_U R_V^T,
 // Jacobi SVD, singular values sorted (descending, ties by index) and the
-// truncated rank.
+// truncated rank. Workgroup w takes block order[w] (the host lists the
+// costliest blocks first, so the longest ones do not trail the launch).
 __global__ void __launch_bounds__(NTR)
-k_recompress_a(const AcaTask* __restrict__ tasks, cd* __restrict__ scratch, const int* __restrict__ rank_in,
-               cd* __restrict__ ws, const int64_t* __restrict__ ws_off, double eps, int* __restrict__ rank_out) {
+k_recompress_a(const AcaTask* __restrict__ tasks, const int* __restrict__ order, cd* __restrict__ scratch,
+               const int* __restrict__ rank_in, cd* __restrict__ ws, const int64_t* __restrict__ ws_off, double eps,
+               int* __restrict__ rank_out) {
     __shared__ cd hbuf[kMaxRankCap];
     __shared__ double red[NWR];
     __shared__ int rot_flag;
     __shared__ double sig[kMaxRankCap];
     __shared__ int srt[kMaxRankCap];
     __shared__ cd lbuf[kRcLds];
-    const AcaTask t = tasks[blockIdx.x];
-    const int r = rank_in[blockIdx.x];
+    const int bi = order[blockIdx.x];
+    const AcaTask t = tasks[bi];
+    const int r = rank_in[bi];
     const int tid = threadIdx.x;
     if (r == 0) {
-        if (tid == 0) rank_out[blockIdx.x] = 0;
+        if (tid == 0) rank_out[bi] = 0;
         return;
     }
     cd* U = scratch + t.u_off;
     cd* V = scratch + t.v_off;
-    cd* RU = ws + ws_off[blockIdx.x];
+    cd* RU = ws + ws_off[bi];
     cd* RV = RU + (int64_t)r * r;
     cd* M = RV + (int64_t)r * r;
     cd* X = M + (int64_t)r * r;
@@ -372,7 +376,7 @@ k_recompress_a(const AcaTask* __restrict__ tasks, cd* __restrict__ scratch, cons
             tail2 += sig[srt[i]] * sig[srt[i]];
             if (sqrt(tail2) <= lim) keep = i;
         }
-        rank_out[blockIdx.x] = keep;
+        rank_out[bi] = keep;
     }
     for (int c = tid; c < r; c += NTR) srt_g[c] = srt[c];
 }
@@ -380,19 +384,20 @@ k_recompress_a(const AcaTask* __restrict__ tasks, cd* __restrict__ scratch, cons
 // Re-compression, phase B: write U' = Q_U M[:, srt[:r']] (m x r'
 // column-major) and V' = X[:, srt[:r']]^H Q_V^T (r' x n row-major).
 __global__ void __launch_bounds__(NTR)
-k_recompress_b(const AcaTask* __restrict__ tasks, const cd* __restrict__ scratch, const int* __restrict__ rank_in,
-               const cd* __restrict__ ws, const int64_t* __restrict__ ws_off, const int* __restrict__ rank_new,
-               cd* const* __restrict__ dst) {
-    const AcaTask t = tasks[blockIdx.x];
-    const int r = rank_in[blockIdx.x], rp = rank_new[blockIdx.x];
+k_recompress_b(const AcaTask* __restrict__ tasks, const int* __restrict__ order, const cd* __restrict__ scratch,
+               const int* __restrict__ rank_in, const cd* __restrict__ ws, const int64_t* __restrict__ ws_off,
+               const int* __restrict__ rank_new, cd* const* __restrict__ dst) {
+    const int bi = order[blockIdx.x];
+    const AcaTask t = tasks[bi];
+    const int r = rank_in[bi], rp = rank_new[bi];
     if (rp == 0) return;
     const int m = t.m, n = t.n;
     const cd* Q = scratch + t.u_off;
     const cd* Qv = scratch + t.v_off;
-    const cd* M = ws + ws_off[blockIdx.x] + 2 * (int64_t)r * r;
+    const cd* M = ws + ws_off[bi] + 2 * (int64_t)r * r;
     const cd* X = M + (int64_t)r * r;
     const int* srt = reinterpret_cast<const int*>(X + (int64_t)r * r);
-    cd* Uo = dst[blockIdx.x];
+    cd* Uo = dst[bi];
     if (Uo == nullptr) return;   // block kept dense
     cd* Vo = Uo + (int64_t)m * rp;
     for (int e = threadIdx.x; e < m * rp; e += NTR) {
@@ -418,30 +423,30 @@ void launch_near_assemble(const NearTask* tasks, int64_t ntasks, const double* p
     if (ntasks > 0) hipLaunchKernelGGL(k_near_assemble, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, pts, k, h, out, err);
 }
 
-void launch_aca(bool dense, const AcaTask* tasks, int64_t ntasks, const double* pts, double k, const cd* dense_src,
-                cd* scratch, uint8_t* flags, double eps, int* rank_out, int* piv_log, int piv_stride, int* err,
-                hipStream_t s) {
+void launch_aca(bool dense, const AcaTask* tasks, const int* order, int64_t ntasks, const double* pts, double k,
+                const cd* dense_src, cd* scratch, uint8_t* flags, double eps, int* rank_out, int* piv_log,
+                int piv_stride, int* err, hipStream_t s) {
     if (ntasks == 0) return;
     if (dense)
-        hipLaunchKernelGGL(k_aca<true>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, pts, k, dense_src, scratch, flags,
-                           eps, rank_out, piv_log, piv_stride, err);
+        hipLaunchKernelGGL(k_aca<true>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, order, pts, k, dense_src, scratch,
+                           flags, eps, rank_out, piv_log, piv_stride, err);
     else
-        hipLaunchKernelGGL(k_aca<false>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, pts, k, dense_src, scratch, flags,
-                           eps, rank_out, piv_log, piv_stride, err);
+        hipLaunchKernelGGL(k_aca<false>, dim3((unsigned)ntasks), dim3(NT), 0, s, tasks, order, pts, k, dense_src, scratch,
+                           flags, eps, rank_out, piv_log, piv_stride, err);
 }
 
-void launch_recompress_a(const AcaTask* tasks, int64_t ntasks, cd* scratch, const int* rank_in, cd* ws,
-                         const int64_t* ws_off, double eps, int* rank_out, hipStream_t s) {
+void launch_recompress_a(const AcaTask* tasks, const int* order, int64_t ntasks, cd* scratch, const int* rank_in,
+                         cd* ws, const int64_t* ws_off, double eps, int* rank_out, hipStream_t s) {
     if (ntasks > 0)
-        hipLaunchKernelGGL(k_recompress_a, dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, scratch, rank_in, ws, ws_off, eps,
-                           rank_out);
+        hipLaunchKernelGGL(k_recompress_a, dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, order, scratch, rank_in, ws,
+                           ws_off, eps, rank_out);
 }
 
-void launch_recompress_b(const AcaTask* tasks, int64_t ntasks, const cd* scratch, const int* rank_in, const cd* ws,
-                         const int64_t* ws_off, const int* rank_new, cd* const* dst, hipStream_t s) {
+void launch_recompress_b(const AcaTask* tasks, const int* order, int64_t ntasks, const cd* scratch, const int* rank_in,
+                         const cd* ws, const int64_t* ws_off, const int* rank_new, cd* const* dst, hipStream_t s) {
     if (ntasks > 0)
-        hipLaunchKernelGGL(k_recompress_b, dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, scratch, rank_in, ws, ws_off,
-                           rank_new, dst);
+        hipLaunchKernelGGL(k_recompress_b, dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, order, scratch, rank_in, ws,
+                           ws_off, rank_new, dst);
 }
 
 }  // namespace hs
