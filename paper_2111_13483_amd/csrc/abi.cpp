@@ -390,14 +390,19 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
         uint8_t* flags = tmp.get<uint8_t>(flag_bytes);
         int* d_rank = tmp.get<int>(nb_);
         int* d_rank2 = tmp.get<int>(nb_);
-        // the largest blocks first (their ranks, and so their ACA steps, are the largest)
-        std::vector<int32_t> aorder(nb_);
-        for (int64_t i = 0; i < nb_; ++i) aorder[i] = (int32_t)i;
-        std::stable_sort(aorder.begin(), aorder.end(), [&](int32_t a, int32_t b) {
-            return (double)(bt[a].m + bt[a].n) * std::min(bt[a].m, bt[a].n) >
-                   (double)(bt[b].m + bt[b].n) * std::min(bt[b].m, bt[b].n);
-        });
-        const int32_t* d_aorder = tmp.upload(aorder, s);
+        // far field: the largest blocks first (their ranks, and so their ACA
+        // steps, are the largest); the fill-in blocks (leaf x leaf, similar
+        // sizes) keep their order, which saves the host sort
+        const int32_t* d_aorder = nullptr;
+        if (!dense) {
+            std::vector<int32_t> aorder(nb_);
+            for (int64_t i = 0; i < nb_; ++i) aorder[i] = (int32_t)i;
+            std::stable_sort(aorder.begin(), aorder.end(), [&](int32_t a, int32_t b) {
+                return (double)(bt[a].m + bt[a].n) * std::min(bt[a].m, bt[a].n) >
+                       (double)(bt[b].m + bt[b].n) * std::min(bt[b].m, bt[b].n);
+            });
+            d_aorder = tmp.upload(aorder, s);
+        }
         hs::launch_aca(dense, d_t, d_aorder, nb_, pts, k, src, scratch, flags, eps, d_rank,
                        d_piv_log ? d_piv_log + b0 * 2 * cap_max : nullptr, 2 * cap_max, d_err, s);
         hip_check(hipGetLastError(), "k_aca launch");
@@ -410,17 +415,20 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
         }
         int64_t* d_ws_off = tmp.upload(ws_off, s);
         cd* d_ws = tmp.get<cd>(ws);
-        // costliest blocks first: QR of both factors ((m + n) r^2) and the
-        // core's Jacobi sweeps (~ r^3); ties by block index
-        std::vector<int32_t> order(nb_);
-        for (int64_t i = 0; i < nb_; ++i) order[i] = (int32_t)i;
-        std::vector<double> cost(nb_);
-        for (int64_t i = 0; i < nb_; ++i) {
-            const double rr = r[i];
-            cost[i] = (bt[i].m + bt[i].n) * rr * rr + 10.0 * rr * rr * rr;
+        // far field: the costliest blocks first, QR of both factors
+        // ((m + n) r^2) and the core's Jacobi sweeps (~ r^3), ties by index
+        const int32_t* d_order = nullptr;
+        if (!dense) {
+            std::vector<int32_t> order(nb_);
+            for (int64_t i = 0; i < nb_; ++i) order[i] = (int32_t)i;
+            std::vector<double> cost(nb_);
+            for (int64_t i = 0; i < nb_; ++i) {
+                const double rr = r[i];
+                cost[i] = (bt[i].m + bt[i].n) * rr * rr + 10.0 * rr * rr * rr;
+            }
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+            d_order = tmp.upload(order, s);
         }
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
-        const int32_t* d_order = tmp.upload(order, s);
         hs::launch_recompress_a(d_t, d_order, nb_, scratch, d_rank, d_ws, d_ws_off, eps, d_rank2, s);
         hip_check(hipGetLastError(), "k_recompress_a launch");
         std::vector<int> r2 = download(d_rank2, nb_, s);

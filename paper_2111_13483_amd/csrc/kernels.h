@@ -107,12 +107,13 @@ struct GatherEnt {
 // ---- build ----
 void launch_near_assemble(const NearTask* tasks, int64_t ntasks, const double* pts, double k, double h, cd* out,
                           int* err, hipStream_t s);
-// ACA of every block, one workgroup each; workgroup w takes block order[w].
+// ACA of every block, one workgroup each; workgroup w takes block order[w]
+// (null: w).
 void launch_aca(bool dense, const AcaTask* tasks, const int* order, int64_t ntasks, const double* pts, double k,
                 const cd* dense_src, cd* scratch, uint8_t* flags, double eps, int* rank_out, int* piv_log,
                 int piv_stride, int* err, hipStream_t s);
 // Re-compression of every block, one workgroup each; workgroup w takes
-// block order[w] (a permutation of the blocks, costliest first).
+// block order[w] (a permutation of the blocks, costliest first; null: w).
 void launch_recompress_a(const AcaTask* tasks, const int* order, int64_t ntasks, cd* scratch, const int* rank_in,
                          cd* ws, const int64_t* ws_off, double eps, int* rank_out, hipStream_t s);
 void launch_recompress_b(const AcaTask* tasks, const int* order, int64_t ntasks, const cd* scratch, const int* rank_in,

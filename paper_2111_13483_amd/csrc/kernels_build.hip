@@ -96,7 +96,7 @@ k_aca(const AcaTask* __restrict__ tasks, const int* __restrict__ order, const do
     __shared__ double redv[NW];
     __shared__ int redi[NW];
     __shared__ double cross_part[NW];
-    const int bi = order[blockIdx.x];   // the largest blocks first
+    const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;   // the largest blocks first
     const AcaTask t = tasks[bi];
     const int m = t.m, n = t.n, cap = t.cap;
     cd* U = scratch + t.u_off;
@@ -294,7 +294,8 @@ __device__ void jacobi_svd(cd* M, cd* X, int r, int* rot_flag) {
 // Re-compression, phase A: QR of U and V^T in place, core M = R_U R_V^T,
 // Jacobi SVD, singular values sorted (descending, ties by index) and the
 // truncated rank. Workgroup w takes block order[w] (the host lists the
-// costliest blocks first, so the longest ones do not trail the launch).
+// costliest blocks first, so the longest ones do not trail the launch; null:
+// block w).
 __global__ void __launch_bounds__(NTR)
 k_recompress_a(const AcaTask* __restrict__ tasks, const int* __restrict__ order, cd* __restrict__ scratch,
                const int* __restrict__ rank_in, cd* __restrict__ ws, const int64_t* __restrict__ ws_off, double eps,
@@ -305,7 +306,7 @@ k_recompress_a(const AcaTask* __restrict__ tasks, const int* __restrict__ order,
     __shared__ double sig[kMaxRankCap];
     __shared__ int srt[kMaxRankCap];
     __shared__ cd lbuf[kRcLds];
-    const int bi = order[blockIdx.x];
+    const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
     const AcaTask t = tasks[bi];
     const int r = rank_in[bi];
     const int tid = threadIdx.x;
@@ -387,7 +388,7 @@ __global__ void __launch_bounds__(NTR)
 k_recompress_b(const AcaTask* __restrict__ tasks, const int* __restrict__ order, const cd* __restrict__ scratch,
                const int* __restrict__ rank_in, const cd* __restrict__ ws, const int64_t* __restrict__ ws_off,
                const int* __restrict__ rank_new, cd* const* __restrict__ dst) {
-    const int bi = order[blockIdx.x];
+    const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
     const AcaTask t = tasks[bi];
     const int r = rank_in[bi], rp = rank_new[bi];
     if (rp == 0) return;
