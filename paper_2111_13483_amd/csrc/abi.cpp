@@ -347,10 +347,11 @@ void set_device(const hs_context* ctx) { hip_check(hipSetDevice(ctx->device), "h
 // budget. Dense blocks read src (row-major m x n at src_off); otherwise the
 // kernel is evaluated on the points. The final factors go into chunks owned
 // by `own`; piv_log (optional) receives (i, j) per ACA step, stride 2*cap_max.
+// With ax (far field), the blocks of rank above kRcWideRank are re-compressed
+// by wide workgroups on the auxiliary stream beside the others.
 void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, bool dense, const double* pts,
                      double k, const cd* src, double eps, int cap_max, int* d_err, int* d_piv_log,
-                     LowRankSet& out, const std::vector<char>* keep_rule_dense /* unused */) {
-    (void)keep_rule_dense;
+                     LowRankSet& out, AuxStream* ax) {
     const int64_t nt = (int64_t)tasks.size();
     out.rank.assign(nt, 0);
     out.rank_aca.assign(nt, 0);
@@ -415,22 +416,51 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
         }
         int64_t* d_ws_off = tmp.upload(ws_off, s);
         cd* d_ws = tmp.get<cd>(ws);
-        // far field: the costliest blocks first, QR of both factors
+        // far field: the blocks of rank above kRcWideRank (few, but the
+        // slowest) on wide workgroups on the auxiliary stream, the others
+        // beside them with the costliest first: QR of both factors
         // ((m + n) r^2) and the core's Jacobi sweeps (~ r^3), ties by index
-        const int32_t* d_order = nullptr;
+        std::vector<int32_t> wide, rest;
+        for (int64_t i = 0; i < nb_; ++i) {
+            if (ax && r[i] > hs::kRcWideRank)
+                wide.push_back((int32_t)i);
+            else
+                rest.push_back((int32_t)i);
+        }
+        const int32_t* d_wide = nullptr;
+        const int32_t* d_rest = nullptr;
         if (!dense) {
-            std::vector<int32_t> order(nb_);
-            for (int64_t i = 0; i < nb_; ++i) order[i] = (int32_t)i;
             std::vector<double> cost(nb_);
             for (int64_t i = 0; i < nb_; ++i) {
                 const double rr = r[i];
                 cost[i] = (bt[i].m + bt[i].n) * rr * rr + 10.0 * rr * rr * rr;
             }
-            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
-            d_order = tmp.upload(order, s);
+            auto by_cost = [&](int32_t a, int32_t b) { return cost[a] > cost[b]; };
+            std::stable_sort(wide.begin(), wide.end(), by_cost);
+            std::stable_sort(rest.begin(), rest.end(), by_cost);
         }
-        hs::launch_recompress_a(d_t, d_order, nb_, scratch, d_rank, d_ws, d_ws_off, eps, d_rank2, s);
+        if (!wide.empty()) d_wide = tmp.upload(wide, s);
+        // all blocks in index order need no list (the fill-in batches)
+        if (!dense || !wide.empty()) d_rest = tmp.upload(rest, s);
+        auto fork = [&] {
+            if (wide.empty()) return;
+            ax->ensure();
+            hip_check(hipEventRecord(ax->fork, s), "hipEventRecord");
+            hip_check(hipStreamWaitEvent(ax->s, ax->fork, 0), "hipStreamWaitEvent");
+        };
+        auto join = [&] {
+            if (wide.empty()) return;
+            hip_check(hipEventRecord(ax->join, ax->s), "hipEventRecord");
+            hip_check(hipStreamWaitEvent(s, ax->join, 0), "hipStreamWaitEvent");
+        };
+        fork();
+        if (!wide.empty())
+            hs::launch_recompress_a(true, d_t, d_wide, (int64_t)wide.size(), scratch, d_rank, d_ws, d_ws_off, eps,
+                                    d_rank2, ax->s);
+        hs::launch_recompress_a(false, d_t, d_rest, (int64_t)rest.size(), scratch, d_rank, d_ws, d_ws_off, eps,
+                                d_rank2, s);
         hip_check(hipGetLastError(), "k_recompress_a launch");
+        join();
         std::vector<int> r2 = download(d_rank2, nb_, s);
         int64_t fin = 0;
         for (int64_t i = 0; i < nb_; ++i) fin += (int64_t)r2[i] * (bt[i].m + bt[i].n);
@@ -447,8 +477,14 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
             }
         }
         cd** d_dst = tmp.upload(dst, s);
-        hs::launch_recompress_b(d_t, d_order, nb_, scratch, d_rank, d_ws, d_ws_off, d_rank2, d_dst, s);
+        fork();
+        if (!wide.empty())
+            hs::launch_recompress_b(true, d_t, d_wide, (int64_t)wide.size(), scratch, d_rank, d_ws, d_ws_off, d_rank2,
+                                    d_dst, ax->s);
+        hs::launch_recompress_b(false, d_t, d_rest, (int64_t)rest.size(), scratch, d_rank, d_ws, d_ws_off, d_rank2,
+                                d_dst, s);
         hip_check(hipGetLastError(), "k_recompress_b launch");
+        join();
         hip_check(hipStreamSynchronize(s), "stream sync");
         b0 = b1;
     }
@@ -1001,7 +1037,7 @@ int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double 
         H->d_far_piv = o.get<int>((size_t)std::max<int64_t>(p.n_far(), 1) * 2 * cap);
         hip_check(hipMemsetAsync(H->d_far_piv, 0xff, sizeof(int) * std::max<int64_t>(p.n_far(), 1) * 2 * cap, s), "memset");
         compress_blocks(o, s, H->far_geom, false, H->d_pts, k, nullptr, opts->aca_tol, cap, d_err, H->d_far_piv, H->far,
-                        nullptr);
+                        &ctx->aux);
         check_device_flag(d_err, s);
         int64_t fb = 0;
         for (size_t b = 0; b < H->far_geom.size(); ++b) {

@@ -112,12 +112,16 @@ void launch_near_assemble(const NearTask* tasks, int64_t ntasks, const double* p
 void launch_aca(bool dense, const AcaTask* tasks, const int* order, int64_t ntasks, const double* pts, double k,
                 const cd* dense_src, cd* scratch, uint8_t* flags, double eps, int* rank_out, int* piv_log,
                 int piv_stride, int* err, hipStream_t s);
-// Re-compression of every block, one workgroup each; workgroup w takes
-// block order[w] (a permutation of the blocks, costliest first; null: w).
-void launch_recompress_a(const AcaTask* tasks, const int* order, int64_t ntasks, cd* scratch, const int* rank_in,
-                         cd* ws, const int64_t* ws_off, double eps, int* rank_out, hipStream_t s);
-void launch_recompress_b(const AcaTask* tasks, const int* order, int64_t ntasks, const cd* scratch, const int* rank_in,
-                         const cd* ws, const int64_t* ws_off, const int* rank_new, cd* const* dst, hipStream_t s);
+// Re-compression of the listed blocks, one workgroup each; workgroup w takes
+// block order[w] (null: w). wide: 1024-thread workgroups with a 64 KB LDS
+// buffer, for the blocks of rank above kRcWideRank (their QR dot products and
+// Jacobi pairs spread over 16 waves); else 256 threads and 8 KB.
+constexpr int kRcWideRank = 32;
+void launch_recompress_a(bool wide, const AcaTask* tasks, const int* order, int64_t ntasks, cd* scratch,
+                         const int* rank_in, cd* ws, const int64_t* ws_off, double eps, int* rank_out, hipStream_t s);
+void launch_recompress_b(bool wide, const AcaTask* tasks, const int* order, int64_t ntasks, const cd* scratch,
+                         const int* rank_in, const cd* ws, const int64_t* ws_off, const int* rank_new, cd* const* dst,
+                         hipStream_t s);
 
 // ---- setup ----
 // Contiguous copies from scattered device sources: dst[dst_off + e] = src[e], e < count.

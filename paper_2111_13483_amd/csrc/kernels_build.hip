@@ -24,7 +24,14 @@ constexpr int NTR = 256;
 // with its rotations (2 r^2 <= kRcLds) rotated there; small enough (8 KB)
 // that the kernel's occupancy stays bound by its registers
 constexpr int kRcLds = 512;
-constexpr int NWR = NTR / kWave;
+// Blocks of rank above kRcWideRank: 1024 threads, and cores up to rank 45
+// (2 r^2 <= 4096) rotated in LDS.
+constexpr int NTW = 1024;
+constexpr int kRcLdsWide = 4096;
+// loads in flight per lane in the QR of the factors (registers: 1024-thread
+// workgroups may take 128 VGPRs, the 256-thread ones share CUs with many)
+constexpr int kQbWide = 8;
+constexpr int kQbRest = 4;
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
 // exp(-j k r) / (4 pi r) with the products and sums rounded as written.
@@ -197,53 +204,80 @@ namespace {
 
 // In-place QR of the r columns (each of length len, stride len) of A by
 // classical Gram-Schmidt applied twice; R (r x r, column-major) receives the
-// triangular factor. hbuf: LDS of >= r entries.
+// triangular factor. hbuf: LDS of >= r entries. The factors of the large
+// blocks stay in global memory, so the dot products and the column update
+// are unrolled QB times to keep QB loads per lane in flight (a column of
+// 2,000 points is then 32 / QB rounds of load latency per lane).
+template <int NTQ, int QB>
 __device__ void cgs2_qr(cd* A, int len, int r, cd* R, cd* hbuf, double* red) {
+    constexpr int NWQ = NTQ / kWave;
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     for (int c = 0; c < r; ++c) {
         cd* ac = A + (int64_t)c * len;
         for (int pass = 0; pass < 2; ++pass) {
-            for (int l = wid; l < c; l += NWR) {
+            for (int l = wid; l < c; l += NWQ) {
                 const cd* al = A + (int64_t)l * len;
                 cd d = cmk(0.0, 0.0);
+#pragma unroll QB
                 for (int x = lane; x < len; x += kWave) d = cfmac(al[x], ac[x], d);
                 d = wave_sum(d);
                 if (lane == 0) hbuf[l] = d;
             }
             __syncthreads();
-            for (int x = tid; x < len; x += NTR) {
+            for (int x = tid; x < len; x += NTQ) {
                 cd v = ac[x];
+#pragma unroll QB
                 for (int l = 0; l < c; ++l) v = csub(v, cmul(A[(int64_t)l * len + x], hbuf[l]));
                 ac[x] = v;
             }
-            for (int l = tid; l < c; l += NTR) {
+            for (int l = tid; l < c; l += NTQ) {
                 cd prev = pass == 0 ? cmk(0.0, 0.0) : R[l + (int64_t)c * r];
                 R[l + (int64_t)c * r] = cadd(prev, hbuf[l]);
             }
             __syncthreads();
         }
         double p = 0.0;
-        for (int x = tid; x < len; x += NTR) p += cabs2(ac[x]);
-        const double nrm = sqrt(wg_sum<NTR>(p, red));
+        for (int x = tid; x < len; x += NTQ) p += cabs2(ac[x]);
+        const double nrm = sqrt(wg_sum<NTQ>(p, red));
         const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        for (int x = tid; x < len; x += NTR) ac[x] = cscale(ac[x], inv);
+        for (int x = tid; x < len; x += NTQ) ac[x] = cscale(ac[x], inv);
         if (tid == 0) R[c + (int64_t)c * r] = cmk(nrm, 0.0);
-        for (int l = c + 1 + tid; l < r; l += NTR) R[l + (int64_t)c * r] = cmk(0.0, 0.0);
+        for (int l = c + 1 + tid; l < r; l += NTQ) R[l + (int64_t)c * r] = cmk(0.0, 0.0);
         __syncthreads();
     }
 }
 
+// Sum over a row of 16 lanes, the same bits in every lane of the row: each
+// DPP step adds the value of a partner lane whose group holds the same
+// operands (quad_perm [1,0,3,2] and [2,3,0,1], then row_half_mirror pairing
+// the two quads of each half, then row_mirror pairing the halves), so the
+// lanes' sums differ only in operand order. The moves stay within the row,
+// so only the row has to be active.
+__device__ __forceinline__ double row_sum(double v) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    return v;
+}
+__device__ __forceinline__ cd row_sum(cd v) { return cmk(row_sum(v.x), row_sum(v.y)); }
+
+constexpr int kJr = 16;   // lanes per Jacobi pair: one DPP row
+
 // One-sided Jacobi on the columns of M (r x r, column-major), accumulating
 // the right rotations in X (starts as I). Round-robin pairs, one pair per
-// wave at a time.
+// row of 16 lanes at a time (a round's pairs are disjoint, so up to
+// NTQ / 16 of them run at once; each lane takes every 16th entry).
+template <int NTQ>
 __device__ void jacobi_svd(cd* M, cd* X, int r, int* rot_flag) {
-    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    constexpr int NG = NTQ / kJr;
+    const int tid = threadIdx.x, gl = tid % kJr, grp = tid / kJr;
     const int np = (r + 1) & ~1;
     for (int sweep = 0; sweep < 40; ++sweep) {
         if (tid == 0) *rot_flag = 0;
         __syncthreads();
         for (int round = 0; round < np - 1; ++round) {
-            for (int pk = wid; pk < np / 2; pk += NWR) {
+            for (int pk = grp; pk < np / 2; pk += NG) {
                 int p, q;
                 if (pk == 0) { p = round; q = np - 1; }
                 else { p = (round + pk) % (np - 1); q = (round - pk + np - 1) % (np - 1); }
@@ -253,33 +287,33 @@ __device__ void jacobi_svd(cd* M, cd* X, int r, int* rot_flag) {
                 cd* mq = M + (int64_t)q * r;
                 double a = 0.0, b = 0.0;
                 cd c = cmk(0.0, 0.0);
-                for (int x = lane; x < r; x += kWave) {
+                for (int x = gl; x < r; x += kJr) {
                     a += cabs2(mp[x]);
                     b += cabs2(mq[x]);
                     c = cfmac(mp[x], mq[x], c);
                 }
-                a = wave_sum(a);
-                b = wave_sum(b);
-                c = wave_sum(c);
+                a = row_sum(a);
+                b = row_sum(b);
+                c = row_sum(c);
                 const double ac = sqrt(cabs2(c));
                 if (!(ac > 1e-15 * sqrt(a * b)) || ac == 0.0) continue;
                 const double zeta = (b - a) / (2.0 * ac);
                 const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double cs = 1.0 / sqrt(1.0 + tn * tn), sn = cs * tn;
                 const cd ph = cmk(c.x / ac, -c.y / ac);   // e^{-i phi}
-                for (int x = lane; x < r; x += kWave) {
+                for (int x = gl; x < r; x += kJr) {
                     cd u = mp[x], w = cmul(ph, mq[x]);
                     mp[x] = cmk(cs * u.x - sn * w.x, cs * u.y - sn * w.y);
                     mq[x] = cmk(sn * u.x + cs * w.x, sn * u.y + cs * w.y);
                 }
                 cd* xp = X + (int64_t)p * r;
                 cd* xq = X + (int64_t)q * r;
-                for (int x = lane; x < r; x += kWave) {
+                for (int x = gl; x < r; x += kJr) {
                     cd u = xp[x], w = cmul(ph, xq[x]);
                     xp[x] = cmk(cs * u.x - sn * w.x, cs * u.y - sn * w.y);
                     xq[x] = cmk(sn * u.x + cs * w.x, sn * u.y + cs * w.y);
                 }
-                if (lane == 0) *rot_flag = 1;
+                if (gl == 0) *rot_flag = 1;
             }
             __syncthreads();
         }
@@ -296,16 +330,17 @@ __device__ void jacobi_svd(cd* M, cd* X, int r, int* rot_flag) {
 // truncated rank. Workgroup w takes block order[w] (the host lists the
 // costliest blocks first, so the longest ones do not trail the launch; null:
 // block w).
-__global__ void __launch_bounds__(NTR)
+template <int NTQ, int LDSC, int QB>
+__global__ void __launch_bounds__(NTQ)
 k_recompress_a(const AcaTask* __restrict__ tasks, const int* __restrict__ order, cd* __restrict__ scratch,
                const int* __restrict__ rank_in, cd* __restrict__ ws, const int64_t* __restrict__ ws_off, double eps,
                int* __restrict__ rank_out) {
     __shared__ cd hbuf[kMaxRankCap];
-    __shared__ double red[NWR];
+    __shared__ double red[NTQ / kWave];
     __shared__ int rot_flag;
     __shared__ double sig[kMaxRankCap];
     __shared__ int srt[kMaxRankCap];
-    __shared__ cd lbuf[kRcLds];
+    __shared__ cd lbuf[LDSC];
     const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
     const AcaTask t = tasks[bi];
     const int r = rank_in[bi];
@@ -322,22 +357,22 @@ k_recompress_a(const AcaTask* __restrict__ tasks, const int* __restrict__ order,
     cd* X = M + (int64_t)r * r;
     int* srt_g = reinterpret_cast<int*>(X + (int64_t)r * r);
     auto qr = [&](cd* G, int len, cd* R) {
-        if (len * r <= kRcLds) {
-            for (int e = tid; e < len * r; e += NTR) lbuf[e] = G[e];
+        if (len * r <= LDSC) {
+            for (int e = tid; e < len * r; e += NTQ) lbuf[e] = G[e];
             __syncthreads();
-            cgs2_qr(lbuf, len, r, R, hbuf, red);
-            for (int e = tid; e < len * r; e += NTR) G[e] = lbuf[e];
+            cgs2_qr<NTQ, QB>(lbuf, len, r, R, hbuf, red);
+            for (int e = tid; e < len * r; e += NTQ) G[e] = lbuf[e];
             __syncthreads();
         } else {
-            cgs2_qr(G, len, r, R, hbuf, red);
+            cgs2_qr<NTQ, QB>(G, len, r, R, hbuf, red);
         }
     };
     qr(U, t.m, RU);
     qr(V, t.n, RV);
-    const bool core_lds = 2 * r * r <= kRcLds;
+    const bool core_lds = 2 * r * r <= LDSC;
     cd* Mw = core_lds ? lbuf : M;
     cd* Xw = core_lds ? lbuf + r * r : X;
-    for (int e = tid; e < r * r; e += NTR) {
+    for (int e = tid; e < r * r; e += NTQ) {
         const int a = e % r, b = e / r;
         cd s = cmk(0.0, 0.0);
         // R_U upper triangular: l >= a; R_V: l >= b
@@ -346,21 +381,21 @@ k_recompress_a(const AcaTask* __restrict__ tasks, const int* __restrict__ order,
         Xw[e] = cmk(a == b ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
-    jacobi_svd(Mw, Xw, r, &rot_flag);
+    jacobi_svd<NTQ>(Mw, Xw, r, &rot_flag);
     __syncthreads();
     if (core_lds)
-        for (int e = tid; e < r * r; e += NTR) {
+        for (int e = tid; e < r * r; e += NTQ) {
             M[e] = Mw[e];
             X[e] = Xw[e];
         }
-    for (int c = tid; c < r; c += NTR) {
+    for (int c = tid; c < r; c += NTQ) {
         double s = 0.0;
         for (int x = 0; x < r; ++x) s += cabs2(Mw[x + (int64_t)c * r]);
         sig[c] = sqrt(s);
     }
     __syncthreads();
     // rank sort: position of column c = #{d : sig[d] > sig[c] or (== and d < c)}
-    for (int c = tid; c < r; c += NTR) {
+    for (int c = tid; c < r; c += NTQ) {
         int pos = 0;
         for (int d = 0; d < r; ++d) pos += (sig[d] > sig[c]) || (sig[d] == sig[c] && d < c);
         srt[pos] = c;
@@ -379,12 +414,13 @@ k_recompress_a(const AcaTask* __restrict__ tasks, const int* __restrict__ order,
         }
         rank_out[bi] = keep;
     }
-    for (int c = tid; c < r; c += NTR) srt_g[c] = srt[c];
+    for (int c = tid; c < r; c += NTQ) srt_g[c] = srt[c];
 }
 
 // Re-compression, phase B: write U' = Q_U M[:, srt[:r']] (m x r'
 // column-major) and V' = X[:, srt[:r']]^H Q_V^T (r' x n row-major).
-__global__ void __launch_bounds__(NTR)
+template <int NTQ>
+__global__ void __launch_bounds__(NTQ)
 k_recompress_b(const AcaTask* __restrict__ tasks, const int* __restrict__ order, const cd* __restrict__ scratch,
                const int* __restrict__ rank_in, const cd* __restrict__ ws, const int64_t* __restrict__ ws_off,
                const int* __restrict__ rank_new, cd* const* __restrict__ dst) {
@@ -401,14 +437,14 @@ k_recompress_b(const AcaTask* __restrict__ tasks, const int* __restrict__ order,
     cd* Uo = dst[bi];
     if (Uo == nullptr) return;   // block kept dense
     cd* Vo = Uo + (int64_t)m * rp;
-    for (int e = threadIdx.x; e < m * rp; e += NTR) {
+    for (int e = threadIdx.x; e < m * rp; e += NTQ) {
         const int x = e % m, c = e / m;
         const cd* mc = M + (int64_t)srt[c] * r;
         cd s = cmk(0.0, 0.0);
         for (int l = 0; l < r; ++l) s = cfma(Q[(int64_t)l * m + x], mc[l], s);
         Uo[e] = s;
     }
-    for (int e = threadIdx.x; e < rp * n; e += NTR) {
+    for (int e = threadIdx.x; e < rp * n; e += NTQ) {
         const int c = e / n, y = e % n;
         const cd* xc = X + (int64_t)srt[c] * r;
         cd s = cmk(0.0, 0.0);
@@ -436,18 +472,27 @@ void launch_aca(bool dense, const AcaTask* tasks, const int* order, int64_t ntas
                            flags, eps, rank_out, piv_log, piv_stride, err);
 }
 
-void launch_recompress_a(const AcaTask* tasks, const int* order, int64_t ntasks, cd* scratch, const int* rank_in,
-                         cd* ws, const int64_t* ws_off, double eps, int* rank_out, hipStream_t s) {
-    if (ntasks > 0)
-        hipLaunchKernelGGL(k_recompress_a, dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, order, scratch, rank_in, ws,
-                           ws_off, eps, rank_out);
+void launch_recompress_a(bool wide, const AcaTask* tasks, const int* order, int64_t ntasks, cd* scratch,
+                         const int* rank_in, cd* ws, const int64_t* ws_off, double eps, int* rank_out, hipStream_t s) {
+    if (ntasks <= 0) return;
+    if (wide)
+        hipLaunchKernelGGL((k_recompress_a<NTW, kRcLdsWide, kQbWide>), dim3((unsigned)ntasks), dim3(NTW), 0, s, tasks, order,
+                           scratch, rank_in, ws, ws_off, eps, rank_out);
+    else
+        hipLaunchKernelGGL((k_recompress_a<NTR, kRcLds, kQbRest>), dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, order, scratch,
+                           rank_in, ws, ws_off, eps, rank_out);
 }
 
-void launch_recompress_b(const AcaTask* tasks, const int* order, int64_t ntasks, const cd* scratch, const int* rank_in,
-                         const cd* ws, const int64_t* ws_off, const int* rank_new, cd* const* dst, hipStream_t s) {
-    if (ntasks > 0)
-        hipLaunchKernelGGL(k_recompress_b, dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, order, scratch, rank_in, ws,
-                           ws_off, rank_new, dst);
+void launch_recompress_b(bool wide, const AcaTask* tasks, const int* order, int64_t ntasks, const cd* scratch,
+                         const int* rank_in, const cd* ws, const int64_t* ws_off, const int* rank_new, cd* const* dst,
+                         hipStream_t s) {
+    if (ntasks <= 0) return;
+    if (wide)
+        hipLaunchKernelGGL(k_recompress_b<NTW>, dim3((unsigned)ntasks), dim3(NTW), 0, s, tasks, order, scratch, rank_in,
+                           ws, ws_off, rank_new, dst);
+    else
+        hipLaunchKernelGGL(k_recompress_b<NTR>, dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, order, scratch, rank_in,
+                           ws, ws_off, rank_new, dst);
 }
 
 }  // namespace hs
