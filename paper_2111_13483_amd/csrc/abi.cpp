@@ -2655,6 +2655,60 @@ namespace {
 
 using ApplyFn = std::function<void(const cd* in, cd* out, const hs::ColMask& mk)>;
 
+// Inner polls one poll behind: at each poll point the column states (and the
+// sweeps' error flag) are copied into pinned host memory behind an event,
+// and the host reads the copy of the previous poll point, whose work has
+// long finished, instead of draining the stream. The launches for the next
+// group of steps are therefore queued before the GPU runs out of work.
+// Steps taken after a column stopped skip it (the kernels read its state),
+// so the lag costs at most one group of empty steps when all have stopped.
+struct PollRing {
+    hs::ColState* h = nullptr;   // pinned: 2 slots of ns states
+    int* err = nullptr;          // pinned: 2 flags
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int ns = 0, next = 0, pending = -1;
+    explicit PollRing(int ns_) : ns(ns_) {
+        hip_check(hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(hs::ColState) * 2 * ns, hipHostMallocDefault),
+                  "hipHostMalloc");
+        hip_check(hipHostMalloc(reinterpret_cast<void**>(&err), sizeof(int) * 2, hipHostMallocDefault),
+                  "hipHostMalloc");
+        for (auto& e : ev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
+    }
+    ~PollRing() {
+        if (pending >= 0) (void)hipEventSynchronize(ev[pending]);   // a copy may still land in h / err
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (h) (void)hipHostFree(h);
+        if (err) (void)hipHostFree(err);
+    }
+    PollRing(const PollRing&) = delete;
+    PollRing& operator=(const PollRing&) = delete;
+    // Queue this poll point's copies; true when the previous poll point saw
+    // no column still stepping.
+    bool poll(const hs::ColState* d_st, const int* sweep_err, hipStream_t s) {
+        const int k = next;
+        err[k] = 0;
+        hip_check(hipMemcpyAsync(h + (size_t)k * ns, d_st, sizeof(hs::ColState) * ns, hipMemcpyDeviceToHost, s), "D2H");
+        if (sweep_err) hip_check(hipMemcpyAsync(err + k, sweep_err, sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
+        hip_check(hipEventRecord(ev[k], s), "hipEventRecord");
+        next ^= 1;
+        const int q = pending;
+        pending = k;
+        if (q < 0) return false;
+        hip_check(hipEventSynchronize(ev[q]), "hipEventSynchronize");
+        if (err[q] != 0)
+            fail(HS_ETIMEOUT, "a device-side wait of the preconditioner sweeps exceeded the context's wait limit");
+        bool any = false;
+        for (int c = 0; c < ns; ++c) any |= h[(size_t)q * ns + c].active != 0;
+        return !any;
+    }
+    // Start of a cycle: the copy still pending (if any) lands first.
+    void reset() {
+        if (pending >= 0) hip_check(hipEventSynchronize(ev[pending]), "hipEventSynchronize");
+        pending = -1;
+    }
+};
+
 // Workspace of a multi-column GMRES(m) (or flexible GMRES(m): Z keeps the
 // preconditioned basis) on tree-order vectors.
 struct GmresWs {
@@ -2663,6 +2717,7 @@ struct GmresWs {
     cd *r, *wv, *tmp, *V, *Z, *Hh, *snv, *g, *y, *partial;
     double *csv, *npart, *inv_hn;
     hs::ColState* st;
+    std::shared_ptr<PollRing> ring;   // created at the first solve on this workspace
     void alloc(Owned& w, int64_t n_, int ns_, int m_, bool flexible) {
         n = n_;
         ns = ns_;
@@ -2718,7 +2773,10 @@ void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& mat
     hip_check(hipMemsetAsync(G.Hh, 0, sizeof(cd) * G.ldh * ns, s), "memset");
     hs::launch_col_norms(b, n, ns, G.npart, G.nchunk, s);
     hs::launch_cycle_start(b, G.V, n, G.g, m, G.npart, G.nchunk, G.st, n, ns, true, s);
+    if (!G.ring || G.ring->ns != ns) G.ring = std::make_shared<PollRing>(ns);
+    PollRing& ring = *G.ring;
     for (;;) {
+        ring.reset();
         for (int j = 0; j < m; ++j) {
             cd* zj = flexible ? G.Z + j * vs : G.tmp;
             precond(G.V + j * vs, zj, active);
@@ -2733,10 +2791,7 @@ void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& mat
             hs::launch_scale_next(G.wv, G.V + (j + 1) * vs, n, n, ns, G.st, G.inv_hn, s);
             if ((j + 1) % poll == 0 && j + 1 < m) {
                 hip_check(hipGetLastError(), "inner launches");
-                std::vector<hs::ColState> cur = poll_states(G, sweep_err, s);
-                bool any = false;
-                for (auto& c : cur) any |= c.active != 0;
-                if (!any) break;
+                if (ring.poll(G.st, sweep_err, s)) break;
             }
         }
         hs::launch_lsq(G.Hh, G.ldh, m, G.g, G.y, G.st, ns, s);
