@@ -3444,6 +3444,8 @@ void lanes_cycle(hs_context* ctx, std::vector<Lane*>& lanes, int poll) {
         L->stepping = L->ran;
         if (!L->ran) continue;
         run.push_back(L);
+        if (!L->G.ring || L->G.ring->ns != L->ns) L->G.ring = std::make_shared<PollRing>(L->ns);
+        L->G.ring->reset();
         hip_check(hipMemsetAsync(L->G.Hh, 0, sizeof(cd) * L->G.ldh * L->ns, L->s), "memset");
         hs::launch_cycle_start(L->G.r, L->G.V, L->H->n, L->G.g, L->m, L->G.npart, L->G.nchunk, L->G.st, L->H->n, L->ns,
                                false, L->s);
@@ -3474,13 +3476,12 @@ void lanes_cycle(hs_context* ctx, std::vector<Lane*>& lanes, int poll) {
                 if (L->stepping && j + 1 < L->m) live.push_back(L);
             if (live.empty()) break;
             for (Lane* L : live) hip_check(hipGetLastError(), "inner launches");
-            lanes_poll(live);
+            // one poll behind, as in gmres_run: a lane stops stepping once
+            // its previous poll point saw no column still stepping
             bool any = false;
             for (Lane* L : live) {
-                bool a = false;
-                for (auto& c : L->st) a |= c.active != 0;
-                L->stepping = a;
-                any |= a;
+                L->stepping = !L->G.ring->poll(L->G.st, L->P ? L->sw.w.err : nullptr, L->s);
+                any |= L->stepping;
             }
             if (!any) break;
         }
