@@ -27,7 +27,7 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_c2_sphere_ellipsoid_n2
 KERNEL_SOURCES = ("paper_2111_13483_amd/csrc/kernels_sweep.hip", "paper_2111_13483_amd/csrc/kernels_solve.hip",
                   "paper_2111_13483_amd/csrc/kernels.h", "paper_2111_13483_amd/csrc/devcommon.h")
 # the instrumented launches and their kernels' names
-TIMING_EVERY = 4
+TIMING_EVERY = 8
 KERNEL_NAME = {"sweep_fwd": "k_sweep_fwd", "sweep_bwd": "k_sweep_bwd", "near_mv": "k_near_mv", "far_mv": "k_far_mv",
                "factor": "k_elim_items", "schur": "k_elim_items"}
 SOLVE_KERNELS = ("sweep_fwd", "sweep_bwd", "near_mv", "far_mv")

@@ -538,7 +538,7 @@ __global__ void __launch_bounds__(NT)
 k_basis_update(const cd* __restrict__ V, int64_t ldv, int64_t vstride, int nvec, const cd* __restrict__ partial,
                int nchunk, cd* __restrict__ w, int64_t n, int nrhs, const ColState* __restrict__ st, cd* __restrict__ H,
                int64_t ldh, int mp1, int hcol, int accumulate_h, double* __restrict__ norm_partial) {
-    constexpr int DG = 8;
+    constexpr int DG = 32;
     __shared__ cd h[kMaxRankCap + DG];
     __shared__ cd hp[NW][kWave];
     __shared__ double red[NW];
@@ -548,8 +548,10 @@ k_basis_update(const cd* __restrict__ V, int64_t ldv, int64_t vstride, int nvec,
     for (int l0 = 0; l0 < nvec; l0 += kWave) {
         const int l = l0 + lane;
         cd s = cmk(0.0, 0.0);
-        if (l < nvec)
+        if (l < nvec) {
+#pragma unroll 8
             for (int q = wid; q < nchunk; q += NW) s = cadd(s, partial[((int64_t)q * nrhs + c) * nvec + l]);
+        }
         hp[wid][lane] = s;
         __syncthreads();
         if (threadIdx.x < kWave && l < nvec) {
@@ -589,30 +591,17 @@ k_basis_update(const cd* __restrict__ V, int64_t ldv, int64_t vstride, int nvec,
     }
 }
 
-// One Arnoldi step's Hessenberg column j: h_{j+1,j} = ||w||, previous
-// rotations, a new complex Givens rotation (real cosine), the residual
-// estimate g and the column's stopping test. One workgroup per column.
-__global__ void __launch_bounds__(NT)
-k_givens(cd* __restrict__ H, int64_t ldh, int m, int j, double* __restrict__ csv, cd* __restrict__ snv,
-         cd* __restrict__ g, const double* __restrict__ norm_partial, int nchunk, ColState* __restrict__ st, int nrhs,
-         double* __restrict__ inv_hn) {
-    __shared__ double red[NW];
-    const int c = blockIdx.x;
-    if (!st[c].active) return;
-    const double nn = sum_chunks(norm_partial, nchunk, nrhs, c, red);
-    if (threadIdx.x != 0) return;
-    ColState s = st[c];
-    const int mp1 = m + 1;
-    const double hn = sqrt(nn);
-    cd* Hc = H + c * ldh + (int64_t)j * mp1;
-    double* cs = csv + (int64_t)c * m;
-    cd* sn = snv + (int64_t)c * m;
-    cd* gc = g + (int64_t)c * mp1;
+namespace {
+// Thread 0's part of k_givens on the staged column Hc (j + 2 entries) and
+// rotations cl / sl: earlier rotations, the new one (stored to cs / sn and
+// cl / sl), the residual estimate and the stopping test.
+__device__ void givens_column(cd* Hc, double* cl, cd* sl, int j, double hn, int m, ColState& s, cd* gc, double* cs,
+                              cd* sn, double* inv_hn) {
     Hc[j + 1] = cmk(hn, 0.0);
     for (int i = 0; i < j; ++i) {
         const cd a = Hc[i], b = Hc[i + 1];
-        const cd t = cadd(cscale(a, cs[i]), cmul(sn[i], b));
-        Hc[i + 1] = csub(cscale(b, cs[i]), cmul(cconj(sn[i]), a));
+        const cd t = cadd(cscale(a, cl[i]), cmul(sl[i], b));
+        Hc[i + 1] = csub(cscale(b, cl[i]), cmul(cconj(sl[i]), a));
         Hc[i] = t;
     }
     const cd a = Hc[j];
@@ -636,14 +625,51 @@ k_givens(cd* __restrict__ H, int64_t ldh, int m, int j, double* __restrict__ csv
     gc[j] = cscale(gj, cc);
     s.steps += 1;
     s.total += 1;
-    inv_hn[c] = hn > 0.0 ? 1.0 / hn : 0.0;
+    *inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
     bool stop = false;
     if (!s.fixed && sqrt(cabs2(gc[j + 1])) / s.bnorm <= s.tol) stop = true;
     if (s.total >= s.budget || hn == 0.0) stop = true;
     if (s.steps >= m) stop = true;
     if (stop) s.active = 0;
-    st[c] = s;
 }
+}  // namespace
+
+// One Arnoldi step's Hessenberg column j: h_{j+1,j} = ||w||, previous
+// rotations, a new complex Givens rotation (real cosine), the residual
+// estimate g and the column's stopping test. One workgroup per column.
+__global__ void __launch_bounds__(NT)
+k_givens(cd* __restrict__ H, int64_t ldh, int m, int j, double* __restrict__ csv, cd* __restrict__ snv,
+         cd* __restrict__ g, const double* __restrict__ norm_partial, int nchunk, ColState* __restrict__ st, int nrhs,
+         double* __restrict__ inv_hn) {
+    __shared__ double red[NW];
+    // the column and the earlier rotations, staged by the whole workgroup so
+    // that the sequential rotations read LDS instead of dependent global loads
+    __shared__ cd hcol[kMaxRankCap + 1], snl[kMaxRankCap];
+    __shared__ double csl[kMaxRankCap];
+    const int c = blockIdx.x;
+    if (!st[c].active) return;
+    const int mp1 = m + 1;
+    cd* Hg = H + c * ldh + (int64_t)j * mp1;
+    double* cs = csv + (int64_t)c * m;
+    cd* sn = snv + (int64_t)c * m;
+    for (int i = threadIdx.x; i <= j; i += NT) hcol[i] = Hg[i];
+    for (int i = threadIdx.x; i < j; i += NT) {
+        csl[i] = cs[i];
+        snl[i] = sn[i];
+    }
+    const double nn = sum_chunks(norm_partial, nchunk, nrhs, c, red);   // its barriers order the staging
+    if (threadIdx.x == 0) {
+        ColState s = st[c];
+        const double hn = sqrt(nn);
+        cd* Hc = hcol;
+        cd* gc = g + (int64_t)c * mp1;
+        givens_column(Hc, csl, snl, j, hn, m, s, gc, cs, sn, inv_hn + c);
+        st[c] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j + 1; i += NT) Hg[i] = hcol[i];
+}
+
 
 __global__ void k_scale_next(const cd* __restrict__ w, cd* __restrict__ vnext, int64_t ldv, int64_t n, int nrhs,
                              const ColState* __restrict__ st, const double* __restrict__ inv_hn) {
