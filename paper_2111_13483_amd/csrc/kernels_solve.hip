@@ -419,9 +419,17 @@ k_far_mv(ColMask mk, const AcaTask* __restrict__ geom, const int* __restrict__ r
 
 // ---------------------------------------------------------------- gather
 // y on leaf L = sum of the slots that cover it. The four waves of the
-// workgroup take the leaf's gather entries in turn (GR loads in flight per
-// lane) and their partial sums are added in wave order, so the result does
-// not depend on timing.
+// workgroup take the leaf's gather entries in turn and their partial sums are
+// added in wave order, so the result does not depend on timing. Each wave
+// reads the descriptors of up to 64 of its entries at once (one per lane)
+// and hands them to all lanes by lane reads, so the slot loads (GR in flight
+// per lane) wait for one descriptor round trip per 64 entries, not per GR.
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int lane) {
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __global__ void __launch_bounds__(NT)
 k_gather(ColMask mk, const int64_t* __restrict__ leaf_off, const int64_t* __restrict__ gptr,
          const GatherEnt* __restrict__ gent, const cd* __restrict__ slots, int64_t n, int nrhs, cd* __restrict__ y) {
@@ -438,22 +446,25 @@ k_gather(ColMask mk, const int64_t* __restrict__ leaf_off, const int64_t* __rest
         const int a = ok ? e % b : 0, c = ok ? e / b : 0;
         const bool live = ok && col_live(mk, c);
         cd acc = cmk(0.0, 0.0);
-        if (live) {
-            for (int64_t q = e0 + wid; q < e1; q += NW * GR) {
+        // this wave's entries are e0 + wid + k NW, k = 0, 1, ...; chunks of 64
+        for (int64_t q0 = e0 + wid; q0 < e1; q0 += (int64_t)NW * kWave) {
+            const int64_t ql = q0 + (int64_t)lane * NW;
+            GatherEnt gd{0, 0, 0};
+            if (ql < e1) gd = gent[ql];
+            const int cnt = (int)min<int64_t>(kWave, (e1 - q0 + NW - 1) / NW);
+            for (int u0 = 0; u0 < cnt; u0 += GR) {
                 cd v[GR];
 #pragma unroll
                 for (int u = 0; u < GR; ++u) {
-                    const int64_t qq = q + (int64_t)u * NW;
-                    if (qq < e1) {
-                        const GatherEnt g = gent[qq];
-                        v[u] = slots[g.base * nrhs + g.off + a + (int64_t)c * g.len];
-                    } else {
-                        v[u] = cmk(0.0, 0.0);
-                    }
+                    const int src = min(u0 + u, cnt - 1);
+                    const int64_t gb = readlane_i64(gd.base, src);
+                    const int gl = __builtin_amdgcn_readlane(gd.len, src);
+                    const int go = __builtin_amdgcn_readlane(gd.off, src);
+                    v[u] = (live && u0 + u < cnt) ? slots[gb * nrhs + go + a + (int64_t)c * gl] : cmk(0.0, 0.0);
                 }
 #pragma unroll
                 for (int u = 0; u < GR; ++u)
-                    if (q + (int64_t)u * NW < e1) acc = cadd(acc, v[u]);
+                    if (u0 + u < cnt) acc = cadd(acc, v[u]);
             }
         }
         part[wid][lane] = acc;
@@ -492,22 +503,27 @@ __device__ __forceinline__ double sum_chunks(const double* __restrict__ p, int n
 }  // namespace
 
 // partial[(ch * nrhs + c) * nvec + l] = sum_{i in chunk} conj(V_l[i, c]) w[i, c].
-// Rows over threads; the vectors' loads are issued in groups of DG.
+// The vectors in groups of DG, one group per wave at a time (the waves work
+// on different groups at once); a wave's lanes take the chunk's rows in
+// turn, with a group's loads for two rows in flight together.
 __global__ void __launch_bounds__(NT)
 k_dots(const cd* __restrict__ V, int64_t ldv, int64_t vstride, int nvec, const cd* __restrict__ w, int64_t n,
        int nrhs, const ColState* __restrict__ st, cd* __restrict__ partial, int nchunk) {
     constexpr int DG = 8;
-    __shared__ cd red[NW][kMaxRankCap + 1];
     const int ch = blockIdx.x, c = blockIdx.y;
     if (!st[c].active) return;
     int64_t i0, i1;
     chunk_range(n, nchunk, ch, i0, i1);
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    cd acc[DG];
-    for (int l0 = 0; l0 < nvec; l0 += DG) {
+    const int ngroups = (nvec + DG - 1) / DG;
+    cd* pc = partial + ((int64_t)ch * nrhs + c) * nvec;
+    for (int gi = wid; gi < ngroups; gi += NW) {
+        const int l0 = gi * DG;
+        cd acc[DG];
 #pragma unroll
         for (int u = 0; u < DG; ++u) acc[u] = cmk(0.0, 0.0);
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += NT) {
+#pragma unroll 2
+        for (int64_t i = i0 + lane; i < i1; i += kWave) {
             const cd wi = w[c * n + i];
             const cd* vb = V + c * ldv + i;
             cd vv[DG];
@@ -519,15 +535,8 @@ k_dots(const cd* __restrict__ V, int64_t ldv, int64_t vstride, int nvec, const c
 #pragma unroll
         for (int u = 0; u < DG; ++u) {
             const cd sum = wave_sum(acc[u]);
-            if (lane == 0 && l0 + u < nvec) red[wid][l0 + u] = sum;
+            if (lane == 0 && l0 + u < nvec) pc[l0 + u] = sum;
         }
-    }
-    __syncthreads();
-    for (int l = threadIdx.x; l < nvec; l += NT) {
-        cd sum = red[0][l];
-#pragma unroll
-        for (int q = 1; q < NW; ++q) sum = cadd(sum, red[q][l]);
-        partial[((int64_t)ch * nrhs + c) * nvec + l] = sum;
     }
 }
 
