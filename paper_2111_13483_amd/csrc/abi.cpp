@@ -2715,7 +2715,7 @@ struct GmresWs {
     int64_t n = 0, vstride = 0, ldh = 0;
     int ns = 0, m = 0, nchunk = 0;
     cd *r, *wv, *tmp, *V, *Z, *Hh, *snv, *g, *y, *partial;
-    double *csv, *npart, *inv_hn;
+    double *csv, *npart;
     hs::ColState* st;
     std::shared_ptr<PollRing> ring;   // created at the first solve on this workspace
     void alloc(Owned& w, int64_t n_, int ns_, int m_, bool flexible) {
@@ -2737,7 +2737,6 @@ struct GmresWs {
         y = w.get<cd>((size_t)m * ns);
         partial = w.get<cd>((size_t)nchunk * (m + 1) * ns);
         npart = w.get<double>((size_t)nchunk * ns);
-        inv_hn = w.get<double>(ns);
         st = w.get<hs::ColState>(ns);
     }
 };
@@ -2787,8 +2786,8 @@ void gmres_run(GmresWs& G, hipStream_t s, const cd* b, cd* x, const ApplyFn& mat
             hs::launch_dots(G.V, n, vs, j + 1, G.wv, n, ns, G.st, G.partial, G.nchunk, s);
             hs::launch_basis_update(G.V, n, vs, j + 1, G.partial, G.nchunk, G.wv, n, ns, G.st, G.Hh, G.ldh, m + 1, j,
                                     true, G.npart, s);
-            hs::launch_givens(G.Hh, G.ldh, m, j, G.csv, G.snv, G.g, G.npart, G.nchunk, G.st, ns, G.inv_hn, s);
-            hs::launch_scale_next(G.wv, G.V + (j + 1) * vs, n, n, ns, G.st, G.inv_hn, s);
+            hs::launch_givens_scale(G.Hh, G.ldh, m, j, G.csv, G.snv, G.g, G.npart, G.nchunk, G.st, ns, G.wv,
+                                    G.V + (j + 1) * vs, n, n, s);
             if ((j + 1) % poll == 0 && j + 1 < m) {
                 hip_check(hipGetLastError(), "inner launches");
                 if (ring.poll(G.st, sweep_err, s)) break;
@@ -3467,8 +3466,8 @@ void lanes_cycle(hs_context* ctx, std::vector<Lane*>& lanes, int poll) {
             hs::launch_dots(G.V, n, vs, j + 1, G.wv, n, G.ns, G.st, G.partial, G.nchunk, L->s);
             hs::launch_basis_update(G.V, n, vs, j + 1, G.partial, G.nchunk, G.wv, n, G.ns, G.st, G.Hh, G.ldh, G.m + 1,
                                     j, true, G.npart, L->s);
-            hs::launch_givens(G.Hh, G.ldh, G.m, j, G.csv, G.snv, G.g, G.npart, G.nchunk, G.st, G.ns, G.inv_hn, L->s);
-            hs::launch_scale_next(G.wv, G.V + (j + 1) * vs, n, n, G.ns, G.st, G.inv_hn, L->s);
+            hs::launch_givens_scale(G.Hh, G.ldh, G.m, j, G.csv, G.snv, G.g, G.npart, G.nchunk, G.st, G.ns, G.wv,
+                                    G.V + (j + 1) * vs, n, n, L->s);
         }
         if ((j + 1) % poll == 0 && j + 1 < m) {
             std::vector<Lane*> live;

@@ -423,10 +423,11 @@ void launch_dots(const cd* V, int64_t ldv, int64_t vstride, int nvec, const cd* 
 void launch_basis_update(const cd* V, int64_t ldv, int64_t vstride, int nvec, const cd* partial, int nchunk,
                          cd* w, int64_t n, int nrhs, const ColState* st, cd* H, int64_t ldh, int mp1, int hcol,
                          bool accumulate_h, double* norm_partial, hipStream_t s);
-void launch_givens(cd* H, int64_t ldh, int m, int j, double* cs, cd* sn, cd* g, const double* norm_partial,
-                   int nchunk, ColState* st, int nrhs, double* inv_hn, hipStream_t s);
-void launch_scale_next(const cd* w, cd* vnext, int64_t ldv, int64_t n, int nrhs, const ColState* st,
-                       const double* inv_hn, hipStream_t s);
+// Hessenberg column j with its Givens rotation and stopping test, and
+// v_{j+1} = w / h_{j+1,j} (ldv: column stride of v), in one launch.
+void launch_givens_scale(cd* H, int64_t ldh, int m, int j, double* cs, cd* sn, cd* g, const double* norm_partial,
+                         int nchunk, ColState* st, int nrhs, const cd* w, cd* vnext, int64_t ldv, int64_t n,
+                         hipStream_t s);
 void launch_cycle_start(const cd* r, cd* V, int64_t ldv, cd* g, int m, const double* norm_partial, int nchunk,
                         ColState* st, int64_t n, int nrhs, bool first, hipStream_t s);
 void launch_col_init(ColState* st, const ColState* outer, int nrhs, double tol, int budget, hipStream_t s);

@@ -601,11 +601,11 @@ k_basis_update(const cd* __restrict__ V, int64_t ldv, int64_t vstride, int nvec,
 }
 
 namespace {
-// Thread 0's part of k_givens on the staged column Hc (j + 2 entries) and
+// Thread 0's part of k_givens_scale on the staged column Hc (j + 2 entries) and
 // rotations cl / sl: earlier rotations, the new one (stored to cs / sn and
 // cl / sl), the residual estimate and the stopping test.
 __device__ void givens_column(cd* Hc, double* cl, cd* sl, int j, double hn, int m, ColState& s, cd* gc, double* cs,
-                              cd* sn, double* inv_hn) {
+                              cd* sn) {
     Hc[j + 1] = cmk(hn, 0.0);
     for (int i = 0; i < j; ++i) {
         const cd a = Hc[i], b = Hc[i + 1];
@@ -634,7 +634,6 @@ __device__ void givens_column(cd* Hc, double* cl, cd* sl, int j, double hn, int 
     gc[j] = cscale(gj, cc);
     s.steps += 1;
     s.total += 1;
-    *inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
     bool stop = false;
     if (!s.fixed && sqrt(cabs2(gc[j + 1])) / s.bnorm <= s.tol) stop = true;
     if (s.total >= s.budget || hn == 0.0) stop = true;
@@ -643,20 +642,32 @@ __device__ void givens_column(cd* Hc, double* cl, cd* sl, int j, double hn, int 
 }
 }  // namespace
 
-// One Arnoldi step's Hessenberg column j: h_{j+1,j} = ||w||, previous
+// The end of one Arnoldi step, in one launch. Workgroup x = 0 of column
+// c = y forms the Hessenberg column j: h_{j+1,j} = ||w||, the previous
 // rotations, a new complex Givens rotation (real cosine), the residual
-// estimate g and the column's stopping test. One workgroup per column.
+// estimate g and the column's stopping test. The other workgroups scale w
+// into v_{j+1} by 1 / h_{j+1,j}; every workgroup sums the same norm partials
+// in the same order, so all use the same h_{j+1,j}. A column that stops at
+// this step may be scaled or not (its v_{j+1} is never read).
 __global__ void __launch_bounds__(NT)
-k_givens(cd* __restrict__ H, int64_t ldh, int m, int j, double* __restrict__ csv, cd* __restrict__ snv,
-         cd* __restrict__ g, const double* __restrict__ norm_partial, int nchunk, ColState* __restrict__ st, int nrhs,
-         double* __restrict__ inv_hn) {
+k_givens_scale(cd* __restrict__ H, int64_t ldh, int m, int j, double* __restrict__ csv, cd* __restrict__ snv,
+               cd* __restrict__ g, const double* __restrict__ norm_partial, int nchunk, ColState* __restrict__ st,
+               int nrhs, const cd* __restrict__ w, cd* __restrict__ vnext, int64_t ldv, int64_t n) {
     __shared__ double red[NW];
     // the column and the earlier rotations, staged by the whole workgroup so
     // that the sequential rotations read LDS instead of dependent global loads
     __shared__ cd hcol[kMaxRankCap + 1], snl[kMaxRankCap];
     __shared__ double csl[kMaxRankCap];
-    const int c = blockIdx.x;
+    const int c = blockIdx.y;
     if (!st[c].active) return;
+    if (blockIdx.x > 0) {
+        const double hn = sqrt(sum_chunks(norm_partial, nchunk, nrhs, c, red));
+        const double sc = hn > 0.0 ? 1.0 / hn : 0.0;
+        const int64_t stride = (int64_t)(gridDim.x - 1) * NT;
+        for (int64_t i = (blockIdx.x - 1) * (int64_t)NT + threadIdx.x; i < n; i += stride)
+            vnext[c * ldv + i] = cscale(w[c * n + i], sc);
+        return;
+    }
     const int mp1 = m + 1;
     cd* Hg = H + c * ldh + (int64_t)j * mp1;
     double* cs = csv + (int64_t)c * m;
@@ -670,23 +681,12 @@ k_givens(cd* __restrict__ H, int64_t ldh, int m, int j, double* __restrict__ csv
     if (threadIdx.x == 0) {
         ColState s = st[c];
         const double hn = sqrt(nn);
-        cd* Hc = hcol;
         cd* gc = g + (int64_t)c * mp1;
-        givens_column(Hc, csl, snl, j, hn, m, s, gc, cs, sn, inv_hn + c);
+        givens_column(hcol, csl, snl, j, hn, m, s, gc, cs, sn);
         st[c] = s;
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= j + 1; i += NT) Hg[i] = hcol[i];
-}
-
-
-__global__ void k_scale_next(const cd* __restrict__ w, cd* __restrict__ vnext, int64_t ldv, int64_t n, int nrhs,
-                             const ColState* __restrict__ st, const double* __restrict__ inv_hn) {
-    const int c = blockIdx.y;
-    if (!st[c].active) return;
-    const double s = inv_hn[c];
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        vnext[c * ldv + i] = cscale(w[c * n + i], s);
 }
 
 // Start of a restart cycle: beta = ||r||, V_0 = r / beta, g = (beta, 0, ...).
@@ -931,15 +931,11 @@ void launch_basis_update(const cd* V, int64_t ldv, int64_t vstride, int nvec, co
                        nrhs, st, H, ldh, mp1, hcol, (int)accumulate_h, norm_partial);
 }
 
-void launch_givens(cd* H, int64_t ldh, int m, int j, double* cs, cd* sn, cd* g, const double* norm_partial, int nchunk,
-                   ColState* st, int nrhs, double* inv_hn, hipStream_t s) {
-    hipLaunchKernelGGL(k_givens, dim3(nrhs), dim3(NT), 0, s, H, ldh, m, j, cs, sn, g, norm_partial, nchunk, st, nrhs,
-                       inv_hn);
-}
-
-void launch_scale_next(const cd* w, cd* vnext, int64_t ldv, int64_t n, int nrhs, const ColState* st,
-                       const double* inv_hn, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_next, dim3(grid1(n), nrhs), dim3(NT), 0, s, w, vnext, ldv, n, nrhs, st, inv_hn);
+void launch_givens_scale(cd* H, int64_t ldh, int m, int j, double* cs, cd* sn, cd* g, const double* norm_partial,
+                         int nchunk, ColState* st, int nrhs, const cd* w, cd* vnext, int64_t ldv, int64_t n,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_givens_scale, dim3(1 + grid1(n), nrhs), dim3(NT), 0, s, H, ldh, m, j, cs, sn, g, norm_partial,
+                       nchunk, st, nrhs, w, vnext, ldv, n);
 }
 
 void launch_cycle_start(const cd* r, cd* V, int64_t ldv, cd* g, int m, const double* norm_partial, int nchunk,
