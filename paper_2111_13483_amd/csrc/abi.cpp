@@ -13,6 +13,8 @@
 #include <limits>
 #include <map>
 #include <memory>
+#include <thread>
+#include <exception>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -343,6 +345,35 @@ namespace {
 
 void set_device(const hs_context* ctx) { hip_check(hipSetDevice(ctx->device), "hipSetDevice"); }
 
+// Indices 0..n-1 ordered by key descending, equal keys in index order: an
+// LSD radix sort of the complemented keys, 16 bits a pass, as many passes as
+// the largest key needs (a tenth of a comparison sort's time on the far
+// field's 26,000 blocks, which the host sorts three times per H-matrix).
+std::vector<int32_t> order_by_key_desc(const std::vector<uint64_t>& key) {
+    const size_t n = key.size();
+    std::vector<int32_t> a(n), b(n);
+    for (size_t i = 0; i < n; ++i) a[i] = (int32_t)i;
+    uint64_t mx = 0;
+    for (uint64_t k : key) mx = std::max(mx, k);
+    std::vector<uint32_t> cnt(size_t(1) << 16);
+    for (int shift = 0; shift < 64 && (mx >> shift) != 0; shift += 16) {
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (size_t i = 0; i < n; ++i) ++cnt[((mx - key[i]) >> shift) & 0xffff];
+        uint32_t sum = 0;
+        for (auto& c : cnt) {
+            const uint32_t t = c;
+            c = sum;
+            sum += t;
+        }
+        for (size_t i = 0; i < n; ++i) {
+            const int32_t v = a[i];
+            b[cnt[((mx - key[v]) >> shift) & 0xffff]++] = v;
+        }
+        a.swap(b);
+    }
+    return a;
+}
+
 // ACA + re-compression of a list of blocks in batches bounded by the scratch
 // budget. Dense blocks read src (row-major m x n at src_off); otherwise the
 // kernel is evaluated on the points. The final factors go into chunks owned
@@ -396,13 +427,10 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
         // sizes) keep their order, which saves the host sort
         const int32_t* d_aorder = nullptr;
         if (!dense) {
-            std::vector<int32_t> aorder(nb_);
-            for (int64_t i = 0; i < nb_; ++i) aorder[i] = (int32_t)i;
-            std::stable_sort(aorder.begin(), aorder.end(), [&](int32_t a, int32_t b) {
-                return (double)(bt[a].m + bt[a].n) * std::min(bt[a].m, bt[a].n) >
-                       (double)(bt[b].m + bt[b].n) * std::min(bt[b].m, bt[b].n);
-            });
-            d_aorder = tmp.upload(aorder, s);
+            std::vector<uint64_t> key(nb_);
+            for (int64_t i = 0; i < nb_; ++i)
+                key[i] = (uint64_t)(bt[i].m + bt[i].n) * (uint64_t)std::min(bt[i].m, bt[i].n);
+            d_aorder = tmp.upload(order_by_key_desc(key), s);
         }
         hs::launch_aca(dense, d_t, d_aorder, nb_, pts, k, src, scratch, flags, eps, d_rank,
                        d_piv_log ? d_piv_log + b0 * 2 * cap_max : nullptr, 2 * cap_max, d_err, s);
@@ -430,14 +458,19 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
         const int32_t* d_wide = nullptr;
         const int32_t* d_rest = nullptr;
         if (!dense) {
-            std::vector<double> cost(nb_);
-            for (int64_t i = 0; i < nb_; ++i) {
-                const double rr = r[i];
-                cost[i] = (bt[i].m + bt[i].n) * rr * rr + 10.0 * rr * rr * rr;
-            }
-            auto by_cost = [&](int32_t a, int32_t b) { return cost[a] > cost[b]; };
-            std::stable_sort(wide.begin(), wide.end(), by_cost);
-            std::stable_sort(rest.begin(), rest.end(), by_cost);
+            auto by_cost = [&](std::vector<int32_t>& list) {
+                std::vector<uint64_t> key(list.size());
+                for (size_t q = 0; q < list.size(); ++q) {
+                    const uint64_t i = (uint64_t)list[q], rr = (uint64_t)r[i];
+                    key[q] = (uint64_t)(bt[i].m + bt[i].n) * rr * rr + 10 * rr * rr * rr;
+                }
+                const std::vector<int32_t> o = order_by_key_desc(key);
+                std::vector<int32_t> sorted(list.size());
+                for (size_t q = 0; q < list.size(); ++q) sorted[q] = list[o[q]];
+                list.swap(sorted);
+            };
+            by_cost(wide);
+            by_cost(rest);
         }
         if (!wide.empty()) d_wide = tmp.upload(wide, s);
         // all blocks in index order need no list (the fill-in batches)
@@ -1036,8 +1069,66 @@ int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double 
         }
         H->d_far_piv = o.get<int>((size_t)std::max<int64_t>(p.n_far(), 1) * 2 * cap);
         hip_check(hipMemsetAsync(H->d_far_piv, 0xff, sizeof(int) * std::max<int64_t>(p.n_far(), 1) * 2 * cap, s), "memset");
+        // matvec slots and per-leaf gather lists (fixed summation order): they
+        // depend on the partition only, so a host thread builds them while
+        // the far field is compressed on the GPU
+        std::vector<int64_t> near_slot(H->near_tasks.size()), far_slot(H->far_geom.size());
+        std::vector<int64_t> gptr(t.nb() + 1, 0);
+        std::vector<hs::GatherEnt> gent;
+        int64_t near_slot_end = 0, slot_total = 0;
+        std::exception_ptr gl_err;
+        std::thread gl_thread([&] {
+            try {
+                std::vector<std::vector<hs::GatherEnt>> lists(t.nb());
+                int64_t slot = 0;
+                for (int64_t e = 0; e < p.n_near(); ++e) {
+                    const int64_t i = p.near[2 * e], j = p.near[2 * e + 1];
+                    const hs::NearTask& nt = H->near_tasks[e];
+                    near_slot[e] = slot;
+                    lists[i].push_back(hs::GatherEnt{slot, nt.m, 0});
+                    if (i != j) lists[j].push_back(hs::GatherEnt{slot + nt.m, nt.n, 0});
+                    slot += nt.m + (i != j ? nt.n : 0);
+                }
+                near_slot_end = slot;
+                // leaves of a box: leaf starts are sorted, boxes are contiguous point ranges
+                auto leaves_of = [&](int64_t b, int64_t& l0, int64_t& l1) {
+                    const int64_t s0 = t.start[b], s1 = t.start[b] + t.count[b];
+                    l0 = std::lower_bound(H->leaf_off.begin(), H->leaf_off.end() - 1, s0) - H->leaf_off.begin();
+                    l1 = std::lower_bound(H->leaf_off.begin(), H->leaf_off.end() - 1, s1) - H->leaf_off.begin();
+                };
+                for (int64_t e = 0; e < p.n_far(); ++e) {
+                    const hs::AcaTask& g = H->far_geom[e];
+                    far_slot[e] = slot;
+                    int64_t l0, l1;
+                    leaves_of(p.far[2 * e], l0, l1);
+                    for (int64_t l = l0; l < l1; ++l)
+                        lists[l].push_back(hs::GatherEnt{slot, g.m, (int32_t)(H->leaf_off[l] - g.t0)});
+                    leaves_of(p.far[2 * e + 1], l0, l1);
+                    for (int64_t l = l0; l < l1; ++l)
+                        lists[l].push_back(hs::GatherEnt{slot + g.m, g.n, (int32_t)(H->leaf_off[l] - g.s0)});
+                    slot += g.m + g.n;
+                }
+                slot_total = slot;
+                for (int64_t l = 0; l < t.nb(); ++l) {
+                    gent.insert(gent.end(), lists[l].begin(), lists[l].end());
+                    gptr[l + 1] = (int64_t)gent.size();
+                }
+            } catch (...) {
+                gl_err = std::current_exception();
+            }
+        });
+        struct Joiner {
+            std::thread& th;
+            ~Joiner() {
+                if (th.joinable()) th.join();
+            }
+        } gl_join{gl_thread};
         compress_blocks(o, s, H->far_geom, false, H->d_pts, k, nullptr, opts->aca_tol, cap, d_err, H->d_far_piv, H->far,
                         &ctx->aux);
+        gl_thread.join();
+        if (gl_err) std::rethrow_exception(gl_err);
+        H->near_slot_end = near_slot_end;
+        H->slot_total = slot_total;
         check_device_flag(d_err, s);
         int64_t fb = 0;
         for (size_t b = 0; b < H->far_geom.size(); ++b) {
@@ -1045,62 +1136,22 @@ int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double 
             fb += (int64_t)H->far.rank[b] * (H->far_geom[b].m + H->far_geom[b].n);
         }
         H->bytes_far = fb * 16;
-        // matvec slots and per-leaf gather lists (fixed summation order)
-        std::vector<std::vector<hs::GatherEnt>> lists(t.nb());
-        std::vector<int64_t> near_slot(H->near_tasks.size()), far_slot(H->far_geom.size());
-        int64_t slot = 0;
-        for (int64_t e = 0; e < p.n_near(); ++e) {
-            const int64_t i = p.near[2 * e], j = p.near[2 * e + 1];
-            const hs::NearTask& nt = H->near_tasks[e];
-            near_slot[e] = slot;
-            lists[i].push_back(hs::GatherEnt{slot, nt.m, 0});
-            if (i != j) lists[j].push_back(hs::GatherEnt{slot + nt.m, nt.n, 0});
-            slot += nt.m + (i != j ? nt.n : 0);
-        }
-        H->near_slot_end = slot;
-        // leaves of a box: leaf starts are sorted, boxes are contiguous point ranges
-        auto leaves_of = [&](int64_t b, int64_t& l0, int64_t& l1) {
-            const int64_t s0 = t.start[b], s1 = t.start[b] + t.count[b];
-            l0 = std::lower_bound(H->leaf_off.begin(), H->leaf_off.end() - 1, s0) - H->leaf_off.begin();
-            l1 = std::lower_bound(H->leaf_off.begin(), H->leaf_off.end() - 1, s1) - H->leaf_off.begin();
-        };
-        for (int64_t e = 0; e < p.n_far(); ++e) {
-            const hs::AcaTask& g = H->far_geom[e];
-            far_slot[e] = slot;
-            int64_t l0, l1;
-            leaves_of(p.far[2 * e], l0, l1);
-            for (int64_t l = l0; l < l1; ++l)
-                lists[l].push_back(hs::GatherEnt{slot, g.m, (int32_t)(H->leaf_off[l] - g.t0)});
-            leaves_of(p.far[2 * e + 1], l0, l1);
-            for (int64_t l = l0; l < l1; ++l)
-                lists[l].push_back(hs::GatherEnt{slot + g.m, g.n, (int32_t)(H->leaf_off[l] - g.s0)});
-            slot += g.m + g.n;
-        }
-        H->slot_total = slot;
-        std::vector<int64_t> gptr(t.nb() + 1, 0);
-        std::vector<hs::GatherEnt> gent;
-        for (int64_t l = 0; l < t.nb(); ++l) {
-            gent.insert(gent.end(), lists[l].begin(), lists[l].end());
-            gptr[l + 1] = (int64_t)gent.size();
-        }
         H->d_near_slot = o.upload(near_slot, s);
         {
             // the matvec takes the workgroup blocks largest first so the long
             // ones do not trail the launch, then the blocks small enough for
             // one wave (at most 64 x 64 points, rank <= kFarWaveRank)
             const int64_t nf = p.n_far();
-            std::vector<int64_t> ord(nf);
-            for (int64_t e = 0; e < nf; ++e) ord[e] = e;
             auto cost = [&](int64_t e) {
-                return (int64_t)H->far.rank[e] * (H->far_geom[e].m + H->far_geom[e].n);
+                return (uint64_t)H->far.rank[e] * (uint64_t)(H->far_geom[e].m + H->far_geom[e].n);
             };
             auto wave = [&](int64_t e) {
                 return H->far_geom[e].m <= 64 && H->far_geom[e].n <= 64 && H->far.rank[e] <= hs::kFarWaveRank;
             };
-            std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
-                if (wave(x) != wave(y)) return !wave(x);
-                return cost(x) > cost(y);
-            });
+            // workgroup blocks (bit 62 set) before wave blocks, each by cost
+            std::vector<uint64_t> key(nf);
+            for (int64_t e = 0; e < nf; ++e) key[e] = (wave(e) ? 0 : uint64_t(1) << 62) | cost(e);
+            const std::vector<int32_t> ord = order_by_key_desc(key);
             H->n_far_wg = 0;
             for (int64_t e = 0; e < nf; ++e) H->n_far_wg += wave(e) ? 0 : 1;
             std::vector<hs::AcaTask> mg(nf);
