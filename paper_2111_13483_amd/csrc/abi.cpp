@@ -1829,7 +1829,17 @@ struct SetupJob {
         // first, while they fit in fold_cols columns; the entries of the source
         // blocks left out are pushed. Backward mirrored (chunk c+1, then >= c+2).
         std::vector<int32_t> fwidth(nch, 0), bwidth(nch, 0), fl_n(nch, 0), bl_n(nch, 0);
-        std::vector<std::unordered_map<int32_t, int32_t>> ffold(nch), bfold(nch);   // block -> column
+        // block -> column of a chunk's range: pairs sorted by block once built
+        struct FoldMap {
+            std::vector<std::pair<int32_t, int32_t>> kv;
+            void set(int32_t k, int32_t v) { kv.emplace_back(k, v); }
+            void seal() { std::sort(kv.begin(), kv.end()); }
+            int32_t find(int32_t k) const {
+                const auto it = std::lower_bound(kv.begin(), kv.end(), std::make_pair(k, INT32_MIN));
+                return it != kv.end() && it->first == k ? it->second : -1;
+            }
+        };
+        std::vector<FoldMap> ffold(nch), bfold(nch);
         std::vector<int32_t> femap, bemap, fe_off(nch + 1, 0), be_off(nch + 1, 0);
         {
             std::vector<std::vector<int32_t>> fsrc(nch), bsrc(nch);
@@ -1858,13 +1868,13 @@ struct SetupJob {
                 if (c > 0) {
                     int32_t cols = 0;
                     for (int32_t kk = chunk_first[c - 1]; kk < chunk_first[c]; ++kk) {
-                        ffold[c][kk] = cols;
+                        ffold[c].set(kk, cols);
                         cols += P->bsize[kk];
                     }
                     fl_n[c] = cols;
                     for (int32_t kk : fsrc[c]) {
                         if (cols + P->bsize[kk] > fold_cols) break;
-                        ffold[c][kk] = cols;
+                        ffold[c].set(kk, cols);
                         for (int32_t q = 0; q < P->bsize[kk]; ++q) femap.push_back((int32_t)(pos[kk] + q));
                         cols += P->bsize[kk];
                     }
@@ -1874,13 +1884,13 @@ struct SetupJob {
                 if (c + 1 < nch) {
                     int32_t cols = 0;
                     for (int32_t kk = chunk_first[c + 1]; kk < chunk_first[c + 2]; ++kk) {
-                        bfold[c][kk] = cols;
+                        bfold[c].set(kk, cols);
                         cols += P->bsize[kk];
                     }
                     bl_n[c] = cols;
                     for (int32_t kk : bsrc[c]) {
                         if (cols + P->bsize[kk] > fold_cols) break;
-                        bfold[c][kk] = cols;
+                        bfold[c].set(kk, cols);
                         for (int32_t q = 0; q < P->bsize[kk]; ++q) bemap.push_back((int32_t)(pos[kk] + q));
                         cols += P->bsize[kk];
                     }
@@ -1889,6 +1899,10 @@ struct SetupJob {
             }
             fe_off[nch] = (int32_t)femap.size();
             be_off[nch] = (int32_t)bemap.size();
+            for (int64_t c = 0; c < nch; ++c) {
+                ffold[c].seal();
+                bfold[c].seal();
+            }
         }
         std::vector<int64_t> lf_off(nb), lb_off(nb), mf_off(nb), mb_off(nb), cf_off(nch, -1), cb_off(nch, -1);
         int64_t lft = 0, lbt = 0, mft = 0, mbt = 0, cft = 0, cbt = 0;
@@ -1928,11 +1942,11 @@ struct SetupJob {
                     const int32_t j = (int32_t)sy.cols[e];
                     const int32_t ck = chunk_of[kk], cj = chunk_of[j];
                     const int32_t bk = P->bsize[kk], bj = P->bsize[j];
-                    const auto fit = ffold[cj].find((int32_t)kk);
-                    const auto bit = bfold[ck].find(j);
                     const bool in_chunk = cj == ck;
-                    const bool ffolded = !in_chunk && fit != ffold[cj].end();
-                    const bool bfolded = !in_chunk && bit != bfold[ck].end();
+                    const int32_t fcol = in_chunk ? -1 : ffold[cj].find((int32_t)kk);
+                    const int32_t bcol = in_chunk ? -1 : bfold[ck].find(j);
+                    const bool ffolded = fcol >= 0;
+                    const bool bfolded = bcol >= 0;
                     if ((in_chunk || ffolded || bfolded) && P->a_rank[e] >= 0)
                         expand.push_back(hs::ExpandTask{P->a_off[e], ad_off[e], bk, bj, P->a_rank[e], 0});
                     if (in_chunk) {
@@ -1941,13 +1955,13 @@ struct SetupJob {
                     }
                     // forward coupling of chunk cj: rows of block j, columns of block k (alpha_kj^T)
                     if (ffolded)
-                        cfc.push_back(hs::CopyTask{cf_off[cj] + (int64_t)loc[j] * fwidth[cj] + fit->second, ad_off[e],
+                        cfc.push_back(hs::CopyTask{cf_off[cj] + (int64_t)loc[j] * fwidth[cj] + fcol, ad_off[e],
                                                    bj, bk, 1, fwidth[cj]});
                     else
                         far_f.push_back(e);
                     // backward coupling of chunk ck: rows of block k, columns of block j (alpha_kj)
                     if (bfolded)
-                        cbc.push_back(hs::CopyTask{cb_off[ck] + (int64_t)loc[kk] * bwidth[ck] + bit->second, ad_off[e],
+                        cbc.push_back(hs::CopyTask{cb_off[ck] + (int64_t)loc[kk] * bwidth[ck] + bcol, ad_off[e],
                                                    bk, bj, 0, bwidth[ck]});
                     else
                         far_b.push_back(e);
