@@ -1683,6 +1683,219 @@ struct SetupJob {
             hs::CopyTask* d_dcp = tmp.upload(dcp, s);
             hs::launch_copy_blocks(d_dcp, (int64_t)dcp.size(), W, P->d_D, s);
         }
+        // The sweep plan's layout (chunks, folded ranges, the class of each
+        // pattern entry) depends on the symbolic pattern only: a host thread
+        // builds it while the fill-in blocks are compressed on the GPU.
+        // block -> column of a chunk's range: pairs sorted by block once built
+        struct FoldMap {
+            std::vector<std::pair<int32_t, int32_t>> kv;
+            void set(int32_t k, int32_t v) { kv.emplace_back(k, v); }
+            void seal() { std::sort(kv.begin(), kv.end()); }
+            int32_t find(int32_t k) const {
+                const auto it = std::lower_bound(kv.begin(), kv.end(), std::make_pair(k, INT32_MIN));
+                return it != kv.end() && it->first == k ? it->second : -1;
+            }
+        };
+        std::vector<int32_t> chunk_of, loc, wdt, wtt, clast, chunk_first, csize, fwidth, bwidth, fl_n, bl_n;
+        std::vector<int64_t> pos, lf_off, lb_off, mf_off, mb_off, cf_off, cb_off, intptr;
+        int64_t nch = 0, lft = 0, lbt = 0, mft = 0, mbt = 0, cft = 0, cbt = 0;
+        std::vector<FoldMap> ffold, bfold;
+        std::vector<int32_t> femap, bemap, fe_off, be_off;
+        std::vector<hs::SweepEnt> intent;
+        std::vector<hs::ExpandTask> expand;
+        std::vector<hs::CopyTask> cfc, cbc;
+        std::vector<int64_t> far_f, far_b;   // pushed entries, row-major order
+        std::vector<uint8_t> eclass;         // 1: in-chunk or folded entry (a compressed one is expanded)
+        std::exception_ptr plan_err;
+        std::thread plan_thread([&] {
+            try {
+                // ---- chunked sweep plan: consecutive block rows grouped up to kMaxChunk points
+                chunk_of.assign(nb, 0);
+                loc.assign(nb, 0);
+                wdt.assign(nb, 0);
+                wtt.assign(nb, 0);
+                clast.assign(nb, 0);
+                pos.assign(nb, 0);
+                {
+                    int64_t pp = 0;
+                    int32_t cur = -1, used = chunk_lim;
+                    for (int64_t kk = 0; kk < nb; ++kk) {
+                        const int32_t bk = P->bsize[kk];
+                        if (used + bk > chunk_lim) {
+                            ++cur;
+                            used = 0;
+                            chunk_first.push_back((int32_t)kk);
+                        }
+                        chunk_of[kk] = cur;
+                        loc[kk] = used;
+                        used += bk;
+                        wdt[kk] = used;
+                        pos[kk] = pp;
+                        pp += bk;
+                    }
+                    chunk_first.push_back((int32_t)nb);
+                }
+                nch = (int64_t)chunk_first.size() - 1;
+                P->nchunk = nch;
+                csize.assign(nch, 0);
+                for (int64_t c = 0; c < nch; ++c) {
+                    int32_t sz = 0;
+                    for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) sz += P->bsize[kk];
+                    csize[c] = sz;
+                    for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) {
+                        clast[kk] = chunk_first[c + 1] - 1;
+                        wtt[kk] = sz - loc[kk];
+                    }
+                }
+                // Folded neighbour ranges. Forward, chunk c: all of chunk c-1 (contiguous),
+                // then the source blocks of chunks <= c-2 coupled to chunk c, nearest chunk
+                // first, while they fit in fold_cols columns; the entries of the source
+                // blocks left out are pushed. Backward mirrored (chunk c+1, then >= c+2).
+                fwidth.assign(nch, 0);
+                bwidth.assign(nch, 0);
+                fl_n.assign(nch, 0);
+                bl_n.assign(nch, 0);
+                ffold.assign(nch, FoldMap{});
+                bfold.assign(nch, FoldMap{});
+                fe_off.assign(nch + 1, 0);
+                be_off.assign(nch + 1, 0);
+                {
+                    std::vector<std::vector<int32_t>> fsrc(nch), bsrc(nch);
+                    for (int64_t kk = 0; kk < nb; ++kk)
+                        for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
+                            const int32_t j = (int32_t)sy.cols[e];
+                            const int32_t ck = chunk_of[kk], cj = chunk_of[j];
+                            if (cj >= ck + 2) {
+                                fsrc[cj].push_back((int32_t)kk);
+                                bsrc[ck].push_back(j);
+                            }
+                        }
+                    auto uniq = [](std::vector<int32_t>& v) {
+                        std::sort(v.begin(), v.end());
+                        v.erase(std::unique(v.begin(), v.end()), v.end());
+                    };
+                    for (int64_t c = 0; c < nch; ++c) {
+                        uniq(fsrc[c]);
+                        uniq(bsrc[c]);
+                        // nearest chunk first, blocks ascending within a chunk
+                        std::stable_sort(fsrc[c].begin(), fsrc[c].end(),
+                                         [&](int32_t x, int32_t y) { return chunk_of[x] > chunk_of[y]; });
+                        std::stable_sort(bsrc[c].begin(), bsrc[c].end(),
+                                         [&](int32_t x, int32_t y) { return chunk_of[x] < chunk_of[y]; });
+                        fe_off[c] = (int32_t)femap.size();
+                        if (c > 0) {
+                            int32_t cols = 0;
+                            for (int32_t kk = chunk_first[c - 1]; kk < chunk_first[c]; ++kk) {
+                                ffold[c].set(kk, cols);
+                                cols += P->bsize[kk];
+                            }
+                            fl_n[c] = cols;
+                            for (int32_t kk : fsrc[c]) {
+                                if (cols + P->bsize[kk] > fold_cols) break;
+                                ffold[c].set(kk, cols);
+                                for (int32_t q = 0; q < P->bsize[kk]; ++q) femap.push_back((int32_t)(pos[kk] + q));
+                                cols += P->bsize[kk];
+                            }
+                            fwidth[c] = cols;
+                        }
+                        be_off[c] = (int32_t)bemap.size();
+                        if (c + 1 < nch) {
+                            int32_t cols = 0;
+                            for (int32_t kk = chunk_first[c + 1]; kk < chunk_first[c + 2]; ++kk) {
+                                bfold[c].set(kk, cols);
+                                cols += P->bsize[kk];
+                            }
+                            bl_n[c] = cols;
+                            for (int32_t kk : bsrc[c]) {
+                                if (cols + P->bsize[kk] > fold_cols) break;
+                                bfold[c].set(kk, cols);
+                                for (int32_t q = 0; q < P->bsize[kk]; ++q) bemap.push_back((int32_t)(pos[kk] + q));
+                                cols += P->bsize[kk];
+                            }
+                            bwidth[c] = cols;
+                        }
+                    }
+                    fe_off[nch] = (int32_t)femap.size();
+                    be_off[nch] = (int32_t)bemap.size();
+                    for (int64_t c = 0; c < nch; ++c) {
+                        ffold[c].seal();
+                        bfold[c].seal();
+                    }
+                }
+                lf_off.assign(nb, 0);
+                lb_off.assign(nb, 0);
+                mf_off.assign(nb, 0);
+                mb_off.assign(nb, 0);
+                cf_off.assign(nch, -1);
+                cb_off.assign(nch, -1);
+                for (int64_t kk = 0; kk < nb; ++kk) {
+                    const int64_t bk = P->bsize[kk], c = chunk_of[kk];
+                    lf_off[kk] = lft;
+                    lft += bk * wdt[kk];
+                    lb_off[kk] = lbt;
+                    lbt += bk * wtt[kk];
+                    mf_off[kk] = mft;
+                    mft += bk * fwidth[c];
+                    mb_off[kk] = mbt;
+                    mbt += bk * bwidth[c];
+                }
+                for (int64_t c = 0; c < nch; ++c) {
+                    cf_off[c] = cft;
+                    cft += (int64_t)csize[c] * fwidth[c];
+                    cb_off[c] = cbt;
+                    cbt += (int64_t)csize[c] * bwidth[c];
+                }
+                P->linv_elems = lft + lbt + mft + mbt;
+                // entries: in-chunk ones feed Linv, folded ones the coupling products of
+                // their target chunk, the rest are pushed from their source block into
+                // per-entry slots (separately per direction)
+                intptr.assign(nb + 1, 0);
+                for (int64_t e = 0; e < nnz; ++e)
+                    if (chunk_of[row_of[e]] == chunk_of[sy.cols[e]]) intptr[sy.cols[e] + 1]++;
+                for (int64_t j = 0; j < nb; ++j) intptr[j + 1] += intptr[j];
+                intent.assign(intptr[nb], hs::SweepEnt{});
+                eclass.assign(nnz, 0);
+                {
+                    std::vector<int64_t> fi(intptr.begin(), intptr.end() - 1);
+                    for (int64_t kk = 0; kk < nb; ++kk)
+                        for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
+                            const int32_t j = (int32_t)sy.cols[e];
+                            const int32_t ck = chunk_of[kk], cj = chunk_of[j];
+                            const int32_t bk = P->bsize[kk], bj = P->bsize[j];
+                            const bool in_chunk = cj == ck;
+                            const int32_t fcol = in_chunk ? -1 : ffold[cj].find((int32_t)kk);
+                            const int32_t bcol = in_chunk ? -1 : bfold[ck].find(j);
+                            const bool ffolded = fcol >= 0;
+                            const bool bfolded = bcol >= 0;
+                            if (in_chunk || ffolded || bfolded) eclass[e] = 1;
+                            if (in_chunk) {
+                                intent[fi[j]++] = hs::SweepEnt{ad_off[e], (int32_t)kk, -1};
+                                continue;
+                            }
+                            // forward coupling of chunk cj: rows of block j, columns of block k (alpha_kj^T)
+                            if (ffolded)
+                                cfc.push_back(hs::CopyTask{cf_off[cj] + (int64_t)loc[j] * fwidth[cj] + fcol, ad_off[e],
+                                                           bj, bk, 1, fwidth[cj]});
+                            else
+                                far_f.push_back(e);
+                            // backward coupling of chunk ck: rows of block k, columns of block j (alpha_kj)
+                            if (bfolded)
+                                cbc.push_back(hs::CopyTask{cb_off[ck] + (int64_t)loc[kk] * bwidth[ck] + bcol, ad_off[e],
+                                                           bk, bj, 0, bwidth[ck]});
+                            else
+                                far_b.push_back(e);
+                        }
+                }
+            } catch (...) {
+                plan_err = std::current_exception();
+            }
+        });
+        struct PlanJoiner {
+            std::thread& th;
+            ~PlanJoiner() {
+                if (th.joinable()) th.join();
+            }
+        } plan_join{plan_thread};
         // fill-in compression (Sec. 3.4)
         std::vector<int64_t> fill_e;
         for (int64_t e = 0; e < nnz; ++e)
@@ -1790,183 +2003,12 @@ struct SetupJob {
             P->d_alpha = o.get<cd>(std::max<int64_t>(atot, 1));
             hip_check(hipMemcpyAsync(P->d_alpha, Ad, atot * 16, hipMemcpyDeviceToDevice, s), "D2D");
         }
-        // ---- chunked sweep plan: consecutive block rows grouped up to kMaxChunk points
-        std::vector<int32_t> chunk_of(nb), loc(nb), wdt(nb), wtt(nb), clast(nb), chunk_first;
-        std::vector<int64_t> pos(nb);
-        {
-            int64_t pp = 0;
-            int32_t cur = -1, used = chunk_lim;
-            for (int64_t kk = 0; kk < nb; ++kk) {
-                const int32_t bk = P->bsize[kk];
-                if (used + bk > chunk_lim) {
-                    ++cur;
-                    used = 0;
-                    chunk_first.push_back((int32_t)kk);
-                }
-                chunk_of[kk] = cur;
-                loc[kk] = used;
-                used += bk;
-                wdt[kk] = used;
-                pos[kk] = pp;
-                pp += bk;
-            }
-            chunk_first.push_back((int32_t)nb);
-        }
-        const int64_t nch = (int64_t)chunk_first.size() - 1;
-        P->nchunk = nch;
-        std::vector<int32_t> csize(nch);
-        for (int64_t c = 0; c < nch; ++c) {
-            int32_t sz = 0;
-            for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) sz += P->bsize[kk];
-            csize[c] = sz;
-            for (int32_t kk = chunk_first[c]; kk < chunk_first[c + 1]; ++kk) {
-                clast[kk] = chunk_first[c + 1] - 1;
-                wtt[kk] = sz - loc[kk];
-            }
-        }
-        // Folded neighbour ranges. Forward, chunk c: all of chunk c-1 (contiguous),
-        // then the source blocks of chunks <= c-2 coupled to chunk c, nearest chunk
-        // first, while they fit in fold_cols columns; the entries of the source
-        // blocks left out are pushed. Backward mirrored (chunk c+1, then >= c+2).
-        std::vector<int32_t> fwidth(nch, 0), bwidth(nch, 0), fl_n(nch, 0), bl_n(nch, 0);
-        // block -> column of a chunk's range: pairs sorted by block once built
-        struct FoldMap {
-            std::vector<std::pair<int32_t, int32_t>> kv;
-            void set(int32_t k, int32_t v) { kv.emplace_back(k, v); }
-            void seal() { std::sort(kv.begin(), kv.end()); }
-            int32_t find(int32_t k) const {
-                const auto it = std::lower_bound(kv.begin(), kv.end(), std::make_pair(k, INT32_MIN));
-                return it != kv.end() && it->first == k ? it->second : -1;
-            }
-        };
-        std::vector<FoldMap> ffold(nch), bfold(nch);
-        std::vector<int32_t> femap, bemap, fe_off(nch + 1, 0), be_off(nch + 1, 0);
-        {
-            std::vector<std::vector<int32_t>> fsrc(nch), bsrc(nch);
-            for (int64_t kk = 0; kk < nb; ++kk)
-                for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
-                    const int32_t j = (int32_t)sy.cols[e];
-                    const int32_t ck = chunk_of[kk], cj = chunk_of[j];
-                    if (cj >= ck + 2) {
-                        fsrc[cj].push_back((int32_t)kk);
-                        bsrc[ck].push_back(j);
-                    }
-                }
-            auto uniq = [](std::vector<int32_t>& v) {
-                std::sort(v.begin(), v.end());
-                v.erase(std::unique(v.begin(), v.end()), v.end());
-            };
-            for (int64_t c = 0; c < nch; ++c) {
-                uniq(fsrc[c]);
-                uniq(bsrc[c]);
-                // nearest chunk first, blocks ascending within a chunk
-                std::stable_sort(fsrc[c].begin(), fsrc[c].end(),
-                                 [&](int32_t x, int32_t y) { return chunk_of[x] > chunk_of[y]; });
-                std::stable_sort(bsrc[c].begin(), bsrc[c].end(),
-                                 [&](int32_t x, int32_t y) { return chunk_of[x] < chunk_of[y]; });
-                fe_off[c] = (int32_t)femap.size();
-                if (c > 0) {
-                    int32_t cols = 0;
-                    for (int32_t kk = chunk_first[c - 1]; kk < chunk_first[c]; ++kk) {
-                        ffold[c].set(kk, cols);
-                        cols += P->bsize[kk];
-                    }
-                    fl_n[c] = cols;
-                    for (int32_t kk : fsrc[c]) {
-                        if (cols + P->bsize[kk] > fold_cols) break;
-                        ffold[c].set(kk, cols);
-                        for (int32_t q = 0; q < P->bsize[kk]; ++q) femap.push_back((int32_t)(pos[kk] + q));
-                        cols += P->bsize[kk];
-                    }
-                    fwidth[c] = cols;
-                }
-                be_off[c] = (int32_t)bemap.size();
-                if (c + 1 < nch) {
-                    int32_t cols = 0;
-                    for (int32_t kk = chunk_first[c + 1]; kk < chunk_first[c + 2]; ++kk) {
-                        bfold[c].set(kk, cols);
-                        cols += P->bsize[kk];
-                    }
-                    bl_n[c] = cols;
-                    for (int32_t kk : bsrc[c]) {
-                        if (cols + P->bsize[kk] > fold_cols) break;
-                        bfold[c].set(kk, cols);
-                        for (int32_t q = 0; q < P->bsize[kk]; ++q) bemap.push_back((int32_t)(pos[kk] + q));
-                        cols += P->bsize[kk];
-                    }
-                    bwidth[c] = cols;
-                }
-            }
-            fe_off[nch] = (int32_t)femap.size();
-            be_off[nch] = (int32_t)bemap.size();
-            for (int64_t c = 0; c < nch; ++c) {
-                ffold[c].seal();
-                bfold[c].seal();
-            }
-        }
-        std::vector<int64_t> lf_off(nb), lb_off(nb), mf_off(nb), mb_off(nb), cf_off(nch, -1), cb_off(nch, -1);
-        int64_t lft = 0, lbt = 0, mft = 0, mbt = 0, cft = 0, cbt = 0;
-        for (int64_t kk = 0; kk < nb; ++kk) {
-            const int64_t bk = P->bsize[kk], c = chunk_of[kk];
-            lf_off[kk] = lft;
-            lft += bk * wdt[kk];
-            lb_off[kk] = lbt;
-            lbt += bk * wtt[kk];
-            mf_off[kk] = mft;
-            mft += bk * fwidth[c];
-            mb_off[kk] = mbt;
-            mbt += bk * bwidth[c];
-        }
-        for (int64_t c = 0; c < nch; ++c) {
-            cf_off[c] = cft;
-            cft += (int64_t)csize[c] * fwidth[c];
-            cb_off[c] = cbt;
-            cbt += (int64_t)csize[c] * bwidth[c];
-        }
-        P->linv_elems = lft + lbt + mft + mbt;
-        // entries: in-chunk ones feed Linv, folded ones the coupling products of
-        // their target chunk, the rest are pushed from their source block into
-        // per-entry slots (separately per direction)
-        std::vector<int64_t> intptr(nb + 1, 0);
+        plan_thread.join();
+        if (plan_err) std::rethrow_exception(plan_err);
         for (int64_t e = 0; e < nnz; ++e)
-            if (chunk_of[row_of[e]] == chunk_of[sy.cols[e]]) intptr[sy.cols[e] + 1]++;
-        for (int64_t j = 0; j < nb; ++j) intptr[j + 1] += intptr[j];
-        std::vector<hs::SweepEnt> intent(intptr[nb]);
-        std::vector<hs::ExpandTask> expand;
-        std::vector<hs::CopyTask> cfc, cbc;
-        std::vector<int64_t> far_f, far_b;   // pushed entries, row-major order
-        {
-            std::vector<int64_t> fi(intptr.begin(), intptr.end() - 1);
-            for (int64_t kk = 0; kk < nb; ++kk)
-                for (int64_t e = sy.rowptr[kk]; e < sy.rowptr[kk + 1]; ++e) {
-                    const int32_t j = (int32_t)sy.cols[e];
-                    const int32_t ck = chunk_of[kk], cj = chunk_of[j];
-                    const int32_t bk = P->bsize[kk], bj = P->bsize[j];
-                    const bool in_chunk = cj == ck;
-                    const int32_t fcol = in_chunk ? -1 : ffold[cj].find((int32_t)kk);
-                    const int32_t bcol = in_chunk ? -1 : bfold[ck].find(j);
-                    const bool ffolded = fcol >= 0;
-                    const bool bfolded = bcol >= 0;
-                    if ((in_chunk || ffolded || bfolded) && P->a_rank[e] >= 0)
-                        expand.push_back(hs::ExpandTask{P->a_off[e], ad_off[e], bk, bj, P->a_rank[e], 0});
-                    if (in_chunk) {
-                        intent[fi[j]++] = hs::SweepEnt{ad_off[e], (int32_t)kk, -1};
-                        continue;
-                    }
-                    // forward coupling of chunk cj: rows of block j, columns of block k (alpha_kj^T)
-                    if (ffolded)
-                        cfc.push_back(hs::CopyTask{cf_off[cj] + (int64_t)loc[j] * fwidth[cj] + fcol, ad_off[e],
-                                                   bj, bk, 1, fwidth[cj]});
-                    else
-                        far_f.push_back(e);
-                    // backward coupling of chunk ck: rows of block k, columns of block j (alpha_kj)
-                    if (bfolded)
-                        cbc.push_back(hs::CopyTask{cb_off[ck] + (int64_t)loc[kk] * bwidth[ck] + bcol, ad_off[e],
-                                                   bk, bj, 0, bwidth[ck]});
-                    else
-                        far_b.push_back(e);
-                }
-        }
+            if (eclass[e] && P->a_rank[e] >= 0)
+                expand.push_back(hs::ExpandTask{P->a_off[e], ad_off[e], P->bsize[row_of[e]], P->bsize[sy.cols[e]],
+                                                P->a_rank[e], 0});
         // push lists (grouped by source chunk) and per-target gather lists
         std::vector<hs::PushEnt> fpush, bpush;
         std::vector<int32_t> fgrp, fgrp_n, bgrp, bgrp_n;
