@@ -457,6 +457,12 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
         }
         const int32_t* d_wide = nullptr;
         const int32_t* d_rest = nullptr;
+        // lists of small blocks only (the fill-in of leaves up to 64 points):
+        // one wave per block, many resident per CU
+        bool all_small = dense;
+        for (int64_t i = 0; i < nb_ && all_small; ++i)
+            all_small = bt[i].m <= hs::kRcSmallLen && bt[i].n <= hs::kRcSmallLen;
+        const int rest_kind = all_small ? hs::kRcSmall : hs::kRcRest;
         if (!dense) {
             auto by_cost = [&](std::vector<int32_t>& list) {
                 std::vector<uint64_t> key(list.size());
@@ -488,9 +494,9 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
         };
         fork();
         if (!wide.empty())
-            hs::launch_recompress_a(true, d_t, d_wide, (int64_t)wide.size(), scratch, d_rank, d_ws, d_ws_off, eps,
+            hs::launch_recompress_a(hs::kRcWide, d_t, d_wide, (int64_t)wide.size(), scratch, d_rank, d_ws, d_ws_off, eps,
                                     d_rank2, ax->s);
-        hs::launch_recompress_a(false, d_t, d_rest, (int64_t)rest.size(), scratch, d_rank, d_ws, d_ws_off, eps,
+        hs::launch_recompress_a(rest_kind, d_t, d_rest, (int64_t)rest.size(), scratch, d_rank, d_ws, d_ws_off, eps,
                                 d_rank2, s);
         hip_check(hipGetLastError(), "k_recompress_a launch");
         join();
@@ -512,9 +518,9 @@ void compress_blocks(Owned& own, hipStream_t s, std::vector<hs::AcaTask> tasks, 
         cd** d_dst = tmp.upload(dst, s);
         fork();
         if (!wide.empty())
-            hs::launch_recompress_b(true, d_t, d_wide, (int64_t)wide.size(), scratch, d_rank, d_ws, d_ws_off, d_rank2,
+            hs::launch_recompress_b(hs::kRcWide, d_t, d_wide, (int64_t)wide.size(), scratch, d_rank, d_ws, d_ws_off, d_rank2,
                                     d_dst, ax->s);
-        hs::launch_recompress_b(false, d_t, d_rest, (int64_t)rest.size(), scratch, d_rank, d_ws, d_ws_off, d_rank2,
+        hs::launch_recompress_b(rest_kind, d_t, d_rest, (int64_t)rest.size(), scratch, d_rank, d_ws, d_ws_off, d_rank2,
                                 d_dst, s);
         hip_check(hipGetLastError(), "k_recompress_b launch");
         join();

@@ -113,13 +113,17 @@ void launch_aca(bool dense, const AcaTask* tasks, const int* order, int64_t ntas
                 const cd* dense_src, cd* scratch, uint8_t* flags, double eps, int* rank_out, int* piv_log,
                 int piv_stride, int* err, hipStream_t s);
 // Re-compression of the listed blocks, one workgroup each; workgroup w takes
-// block order[w] (null: w). wide: 1024-thread workgroups with a 64 KB LDS
-// buffer, for the blocks of rank above kRcWideRank (their QR dot products and
-// Jacobi pairs spread over 16 waves); else 256 threads and 8 KB.
+// block order[w] (null: w). kind kRcWide: 1024-thread workgroups with a
+// 64 KB LDS buffer, for the blocks of rank above kRcWideRank (their QR dot
+// products and Jacobi pairs spread over 16 waves); kRcRest: 256 threads and
+// 8 KB; kRcSmall: one wave and 16 KB, for lists of blocks of at most
+// kRcSmallLen points a side (the fill-in blocks of leaves up to 64 points).
 constexpr int kRcWideRank = 32;
-void launch_recompress_a(bool wide, const AcaTask* tasks, const int* order, int64_t ntasks, cd* scratch,
+constexpr int kRcSmallLen = 64;
+enum { kRcRest = 0, kRcWide = 1, kRcSmall = 2 };
+void launch_recompress_a(int kind, const AcaTask* tasks, const int* order, int64_t ntasks, cd* scratch,
                          const int* rank_in, cd* ws, const int64_t* ws_off, double eps, int* rank_out, hipStream_t s);
-void launch_recompress_b(bool wide, const AcaTask* tasks, const int* order, int64_t ntasks, const cd* scratch,
+void launch_recompress_b(int kind, const AcaTask* tasks, const int* order, int64_t ntasks, const cd* scratch,
                          const int* rank_in, const cd* ws, const int64_t* ws_off, const int* rank_new, cd* const* dst,
                          hipStream_t s);
 

@@ -32,6 +32,11 @@ constexpr int kRcLdsWide = 4096;
 // workgroups may take 128 VGPRs, the 256-thread ones share CUs with many)
 constexpr int kQbWide = 8;
 constexpr int kQbRest = 4;
+// Lists of small blocks (kRcSmall): one wave each, factors of up to 64 x 8
+// and cores up to rank 16 worked on in its 8 KB of LDS; ranks of at most
+// kRcSmallLen (about 10 KB of LDS in all, 16 workgroups per CU).
+constexpr int kRcLdsSmall = 512;
+constexpr int kQbSmall = 2;
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
 // exp(-j k r) / (4 pi r) with the products and sums rounded as written.
@@ -330,16 +335,16 @@ __device__ void jacobi_svd(cd* M, cd* X, int r, int* rot_flag) {
 // truncated rank. Workgroup w takes block order[w] (the host lists the
 // costliest blocks first, so the longest ones do not trail the launch; null:
 // block w).
-template <int NTQ, int LDSC, int QB>
+template <int NTQ, int LDSC, int QB, int RMX = kMaxRankCap>
 __global__ void __launch_bounds__(NTQ)
 k_recompress_a(const AcaTask* __restrict__ tasks, const int* __restrict__ order, cd* __restrict__ scratch,
                const int* __restrict__ rank_in, cd* __restrict__ ws, const int64_t* __restrict__ ws_off, double eps,
                int* __restrict__ rank_out) {
-    __shared__ cd hbuf[kMaxRankCap];
+    __shared__ cd hbuf[RMX];
     __shared__ double red[NTQ / kWave];
     __shared__ int rot_flag;
-    __shared__ double sig[kMaxRankCap];
-    __shared__ int srt[kMaxRankCap];
+    __shared__ double sig[RMX];
+    __shared__ int srt[RMX];
     __shared__ cd lbuf[LDSC];
     const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
     const AcaTask t = tasks[bi];
@@ -472,24 +477,30 @@ void launch_aca(bool dense, const AcaTask* tasks, const int* order, int64_t ntas
                            flags, eps, rank_out, piv_log, piv_stride, err);
 }
 
-void launch_recompress_a(bool wide, const AcaTask* tasks, const int* order, int64_t ntasks, cd* scratch,
+void launch_recompress_a(int kind, const AcaTask* tasks, const int* order, int64_t ntasks, cd* scratch,
                          const int* rank_in, cd* ws, const int64_t* ws_off, double eps, int* rank_out, hipStream_t s) {
     if (ntasks <= 0) return;
-    if (wide)
+    if (kind == kRcWide)
         hipLaunchKernelGGL((k_recompress_a<NTW, kRcLdsWide, kQbWide>), dim3((unsigned)ntasks), dim3(NTW), 0, s, tasks, order,
                            scratch, rank_in, ws, ws_off, eps, rank_out);
+    else if (kind == kRcSmall)
+        hipLaunchKernelGGL((k_recompress_a<kWave, kRcLdsSmall, kQbSmall, kRcSmallLen>), dim3((unsigned)ntasks), dim3(kWave), 0, s, tasks,
+                           order, scratch, rank_in, ws, ws_off, eps, rank_out);
     else
         hipLaunchKernelGGL((k_recompress_a<NTR, kRcLds, kQbRest>), dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, order, scratch,
                            rank_in, ws, ws_off, eps, rank_out);
 }
 
-void launch_recompress_b(bool wide, const AcaTask* tasks, const int* order, int64_t ntasks, const cd* scratch,
+void launch_recompress_b(int kind, const AcaTask* tasks, const int* order, int64_t ntasks, const cd* scratch,
                          const int* rank_in, const cd* ws, const int64_t* ws_off, const int* rank_new, cd* const* dst,
                          hipStream_t s) {
     if (ntasks <= 0) return;
-    if (wide)
+    if (kind == kRcWide)
         hipLaunchKernelGGL(k_recompress_b<NTW>, dim3((unsigned)ntasks), dim3(NTW), 0, s, tasks, order, scratch, rank_in,
                            ws, ws_off, rank_new, dst);
+    else if (kind == kRcSmall)
+        hipLaunchKernelGGL(k_recompress_b<kWave>, dim3((unsigned)ntasks), dim3(kWave), 0, s, tasks, order, scratch,
+                           rank_in, ws, ws_off, rank_new, dst);
     else
         hipLaunchKernelGGL(k_recompress_b<NTR>, dim3((unsigned)ntasks), dim3(NTR), 0, s, tasks, order, scratch, rank_in,
                            ws, ws_off, rank_new, dst);
