@@ -302,6 +302,23 @@ struct hs_hmatrix {
     bool c64 = false;
     hs::cf* d_near32 = nullptr;
     hs::cf** d_mv_ptr32 = nullptr;
+    // The far field is compressed by a host thread on the H-matrix's own
+    // streams while the caller goes on (a preconditioner setup reads only the
+    // near field); every entry point that reads the far field joins it first.
+    mutable std::thread far_thread;
+    mutable std::exception_ptr far_err;
+    hipStream_t far_s = nullptr;
+    hipEvent_t far_start = nullptr;   // the build's uploads on the caller's stream
+    AuxStream far_aux;
+    void join_far() const {
+        if (far_thread.joinable()) far_thread.join();
+        if (far_err) std::rethrow_exception(far_err);
+    }
+    ~hs_hmatrix() {
+        if (far_thread.joinable()) far_thread.join();
+        if (far_s) (void)hipStreamDestroy(far_s);
+        if (far_start) (void)hipEventDestroy(far_start);
+    }
 };
 
 struct hs_precond {
@@ -814,6 +831,146 @@ SweepWs make_sweep_ws(Owned& o, const hs_precond* P, int nrhs, hipStream_t s, co
 
 // =============================================================================== C-ABI
 
+namespace {
+
+// The far field of an H-matrix: ACA + re-compression of every far block,
+// the matvec's slot layout, gather lists and launch order, and the complex64
+// copies when asked for; on the H-matrix's own stream H->far_s (run by the
+// build's far-field host thread).
+void build_far(hs_hmatrix* H, double k, double aca_tol, int cap, bool store_c64, int* d_err) {
+    hipStream_t s = H->far_s;
+    Owned& o = H->own;
+    const hs::Tree& t = H->plan.tree;
+    const hs::Partition& p = H->plan.part;
+    // matvec slots and per-leaf gather lists (fixed summation order): they
+    // depend on the partition only, so a host thread builds them while
+    // the far field is compressed on the GPU
+    std::vector<int64_t> near_slot(H->near_tasks.size()), far_slot(H->far_geom.size());
+    std::vector<int64_t> gptr(t.nb() + 1, 0);
+    std::vector<hs::GatherEnt> gent;
+    int64_t near_slot_end = 0, slot_total = 0;
+    std::exception_ptr gl_err;
+    std::thread gl_thread([&] {
+        try {
+            std::vector<std::vector<hs::GatherEnt>> lists(t.nb());
+            int64_t slot = 0;
+            for (int64_t e = 0; e < p.n_near(); ++e) {
+                const int64_t i = p.near[2 * e], j = p.near[2 * e + 1];
+                const hs::NearTask& nt = H->near_tasks[e];
+                near_slot[e] = slot;
+                lists[i].push_back(hs::GatherEnt{slot, nt.m, 0});
+                if (i != j) lists[j].push_back(hs::GatherEnt{slot + nt.m, nt.n, 0});
+                slot += nt.m + (i != j ? nt.n : 0);
+            }
+            near_slot_end = slot;
+            // leaves of a box: leaf starts are sorted, boxes are contiguous point ranges
+            auto leaves_of = [&](int64_t b, int64_t& l0, int64_t& l1) {
+                const int64_t s0 = t.start[b], s1 = t.start[b] + t.count[b];
+                l0 = std::lower_bound(H->leaf_off.begin(), H->leaf_off.end() - 1, s0) - H->leaf_off.begin();
+                l1 = std::lower_bound(H->leaf_off.begin(), H->leaf_off.end() - 1, s1) - H->leaf_off.begin();
+            };
+            for (int64_t e = 0; e < p.n_far(); ++e) {
+                const hs::AcaTask& g = H->far_geom[e];
+                far_slot[e] = slot;
+                int64_t l0, l1;
+                leaves_of(p.far[2 * e], l0, l1);
+                for (int64_t l = l0; l < l1; ++l)
+                    lists[l].push_back(hs::GatherEnt{slot, g.m, (int32_t)(H->leaf_off[l] - g.t0)});
+                leaves_of(p.far[2 * e + 1], l0, l1);
+                for (int64_t l = l0; l < l1; ++l)
+                    lists[l].push_back(hs::GatherEnt{slot + g.m, g.n, (int32_t)(H->leaf_off[l] - g.s0)});
+                slot += g.m + g.n;
+            }
+            slot_total = slot;
+            for (int64_t l = 0; l < t.nb(); ++l) {
+                gent.insert(gent.end(), lists[l].begin(), lists[l].end());
+                gptr[l + 1] = (int64_t)gent.size();
+            }
+        } catch (...) {
+            gl_err = std::current_exception();
+        }
+    });
+    struct Joiner {
+        std::thread& th;
+        ~Joiner() {
+            if (th.joinable()) th.join();
+        }
+    } gl_join{gl_thread};
+    compress_blocks(o, s, H->far_geom, false, H->d_pts, k, nullptr, aca_tol, cap, d_err, H->d_far_piv, H->far,
+                    &H->far_aux);
+    gl_thread.join();
+    if (gl_err) std::rethrow_exception(gl_err);
+    H->near_slot_end = near_slot_end;
+    H->slot_total = slot_total;
+    check_device_flag(d_err, s);
+    int64_t fb = 0;
+    for (size_t b = 0; b < H->far_geom.size(); ++b) {
+        H->far_geom[b].cap = cap;
+        fb += (int64_t)H->far.rank[b] * (H->far_geom[b].m + H->far_geom[b].n);
+    }
+    H->bytes_far = fb * 16;
+    H->d_near_slot = o.upload(near_slot, s);
+    {
+        // the matvec takes the workgroup blocks largest first so the long
+        // ones do not trail the launch, then the blocks small enough for
+        // one wave (at most 64 x 64 points, rank <= kFarWaveRank)
+        const int64_t nf = p.n_far();
+        auto cost = [&](int64_t e) {
+            return (uint64_t)H->far.rank[e] * (uint64_t)(H->far_geom[e].m + H->far_geom[e].n);
+        };
+        auto wave = [&](int64_t e) {
+            return H->far_geom[e].m <= 64 && H->far_geom[e].n <= 64 && H->far.rank[e] <= hs::kFarWaveRank;
+        };
+        // workgroup blocks (bit 62 set) before wave blocks, each by cost
+        std::vector<uint64_t> key(nf);
+        for (int64_t e = 0; e < nf; ++e) key[e] = (wave(e) ? 0 : uint64_t(1) << 62) | cost(e);
+        const std::vector<int32_t> ord = order_by_key_desc(key);
+        H->n_far_wg = 0;
+        for (int64_t e = 0; e < nf; ++e) H->n_far_wg += wave(e) ? 0 : 1;
+        std::vector<hs::AcaTask> mg(nf);
+        std::vector<int> mr(nf);
+        std::vector<cd*> mp(nf);
+        std::vector<int64_t> ms(nf);
+        for (int64_t q = 0; q < nf; ++q) {
+            mg[q] = H->far_geom[ord[q]];
+            mr[q] = H->far.rank[ord[q]];
+            mp[q] = H->far.ptr[ord[q]];
+            ms[q] = far_slot[ord[q]];
+        }
+        H->d_mv_geom = o.upload(mg, s);
+        H->d_mv_rank = o.upload(mr, s);
+        H->d_mv_ptr = o.upload(mp, s);
+        H->d_mv_slot = o.upload(ms, s);
+        if (store_c64) {
+            Owned tmp;
+            tmp.mem = o.mem;
+            H->d_near32 = c64_copy(o, tmp, H->d_near, H->bytes_near / 16, s);
+            int64_t tot = 0;
+            for (int64_t q = 0; q < nf; ++q) tot += (int64_t)mr[q] * (mg[q].m + mg[q].n);
+            hs::cf* base = o.get<hs::cf>((size_t)std::max<int64_t>(tot, 1));
+            std::vector<hs::PtrCopy> t;
+            std::vector<hs::cf*> mp32(nf, nullptr);
+            int64_t off = 0;
+            for (int64_t q = 0; q < nf; ++q) {
+                const int64_t cnt = (int64_t)mr[q] * (mg[q].m + mg[q].n);
+                mp32[q] = base + off;
+                if (cnt) t.push_back(hs::PtrCopy{mp[q], off, cnt});
+                off += cnt;
+            }
+            hs::PtrCopy* d_t = tmp.upload(t, s);
+            hs::launch_to_c64(d_t, (int64_t)t.size(), base, s);
+            H->d_mv_ptr32 = o.upload(mp32, s);
+            hip_check(hipStreamSynchronize(s), "stream sync");
+            H->c64 = true;
+        }
+    }
+    H->d_gptr = o.upload(gptr, s);
+    H->d_gent = o.upload(gent, s);
+    hip_check(hipStreamSynchronize(s), "stream sync");
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* hs_status_string(int32_t st) {
@@ -1075,131 +1232,29 @@ int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double 
         }
         H->d_far_piv = o.get<int>((size_t)std::max<int64_t>(p.n_far(), 1) * 2 * cap);
         hip_check(hipMemsetAsync(H->d_far_piv, 0xff, sizeof(int) * std::max<int64_t>(p.n_far(), 1) * 2 * cap, s), "memset");
-        // matvec slots and per-leaf gather lists (fixed summation order): they
-        // depend on the partition only, so a host thread builds them while
-        // the far field is compressed on the GPU
-        std::vector<int64_t> near_slot(H->near_tasks.size()), far_slot(H->far_geom.size());
-        std::vector<int64_t> gptr(t.nb() + 1, 0);
-        std::vector<hs::GatherEnt> gent;
-        int64_t near_slot_end = 0, slot_total = 0;
-        std::exception_ptr gl_err;
-        std::thread gl_thread([&] {
-            try {
-                std::vector<std::vector<hs::GatherEnt>> lists(t.nb());
-                int64_t slot = 0;
-                for (int64_t e = 0; e < p.n_near(); ++e) {
-                    const int64_t i = p.near[2 * e], j = p.near[2 * e + 1];
-                    const hs::NearTask& nt = H->near_tasks[e];
-                    near_slot[e] = slot;
-                    lists[i].push_back(hs::GatherEnt{slot, nt.m, 0});
-                    if (i != j) lists[j].push_back(hs::GatherEnt{slot + nt.m, nt.n, 0});
-                    slot += nt.m + (i != j ? nt.n : 0);
-                }
-                near_slot_end = slot;
-                // leaves of a box: leaf starts are sorted, boxes are contiguous point ranges
-                auto leaves_of = [&](int64_t b, int64_t& l0, int64_t& l1) {
-                    const int64_t s0 = t.start[b], s1 = t.start[b] + t.count[b];
-                    l0 = std::lower_bound(H->leaf_off.begin(), H->leaf_off.end() - 1, s0) - H->leaf_off.begin();
-                    l1 = std::lower_bound(H->leaf_off.begin(), H->leaf_off.end() - 1, s1) - H->leaf_off.begin();
-                };
-                for (int64_t e = 0; e < p.n_far(); ++e) {
-                    const hs::AcaTask& g = H->far_geom[e];
-                    far_slot[e] = slot;
-                    int64_t l0, l1;
-                    leaves_of(p.far[2 * e], l0, l1);
-                    for (int64_t l = l0; l < l1; ++l)
-                        lists[l].push_back(hs::GatherEnt{slot, g.m, (int32_t)(H->leaf_off[l] - g.t0)});
-                    leaves_of(p.far[2 * e + 1], l0, l1);
-                    for (int64_t l = l0; l < l1; ++l)
-                        lists[l].push_back(hs::GatherEnt{slot + g.m, g.n, (int32_t)(H->leaf_off[l] - g.s0)});
-                    slot += g.m + g.n;
-                }
-                slot_total = slot;
-                for (int64_t l = 0; l < t.nb(); ++l) {
-                    gent.insert(gent.end(), lists[l].begin(), lists[l].end());
-                    gptr[l + 1] = (int64_t)gent.size();
-                }
-            } catch (...) {
-                gl_err = std::current_exception();
-            }
-        });
-        struct Joiner {
-            std::thread& th;
-            ~Joiner() {
-                if (th.joinable()) th.join();
-            }
-        } gl_join{gl_thread};
-        compress_blocks(o, s, H->far_geom, false, H->d_pts, k, nullptr, opts->aca_tol, cap, d_err, H->d_far_piv, H->far,
-                        &ctx->aux);
-        gl_thread.join();
-        if (gl_err) std::rethrow_exception(gl_err);
-        H->near_slot_end = near_slot_end;
-        H->slot_total = slot_total;
-        check_device_flag(d_err, s);
-        int64_t fb = 0;
-        for (size_t b = 0; b < H->far_geom.size(); ++b) {
-            H->far_geom[b].cap = cap;
-            fb += (int64_t)H->far.rank[b] * (H->far_geom[b].m + H->far_geom[b].n);
-        }
-        H->bytes_far = fb * 16;
-        H->d_near_slot = o.upload(near_slot, s);
+        // the far field on the H-matrix's own streams, after this stream's
+        // uploads; a host thread runs it while the caller goes on
+        int* d_err_far = o.get<int>(1);
+        hip_check(hipMemsetAsync(d_err_far, 0, sizeof(int), s), "memset");
+        hip_check(hipStreamCreateWithFlags(&H->far_s, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+        hip_check(hipEventCreateWithFlags(&H->far_start, hipEventDisableTiming), "hipEventCreateWithFlags");
+        hip_check(hipEventRecord(H->far_start, s), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(H->far_s, H->far_start, 0), "hipStreamWaitEvent");
         {
-            // the matvec takes the workgroup blocks largest first so the long
-            // ones do not trail the launch, then the blocks small enough for
-            // one wave (at most 64 x 64 points, rank <= kFarWaveRank)
-            const int64_t nf = p.n_far();
-            auto cost = [&](int64_t e) {
-                return (uint64_t)H->far.rank[e] * (uint64_t)(H->far_geom[e].m + H->far_geom[e].n);
-            };
-            auto wave = [&](int64_t e) {
-                return H->far_geom[e].m <= 64 && H->far_geom[e].n <= 64 && H->far.rank[e] <= hs::kFarWaveRank;
-            };
-            // workgroup blocks (bit 62 set) before wave blocks, each by cost
-            std::vector<uint64_t> key(nf);
-            for (int64_t e = 0; e < nf; ++e) key[e] = (wave(e) ? 0 : uint64_t(1) << 62) | cost(e);
-            const std::vector<int32_t> ord = order_by_key_desc(key);
-            H->n_far_wg = 0;
-            for (int64_t e = 0; e < nf; ++e) H->n_far_wg += wave(e) ? 0 : 1;
-            std::vector<hs::AcaTask> mg(nf);
-            std::vector<int> mr(nf);
-            std::vector<cd*> mp(nf);
-            std::vector<int64_t> ms(nf);
-            for (int64_t q = 0; q < nf; ++q) {
-                mg[q] = H->far_geom[ord[q]];
-                mr[q] = H->far.rank[ord[q]];
-                mp[q] = H->far.ptr[ord[q]];
-                ms[q] = far_slot[ord[q]];
-            }
-            H->d_mv_geom = o.upload(mg, s);
-            H->d_mv_rank = o.upload(mr, s);
-            H->d_mv_ptr = o.upload(mp, s);
-            H->d_mv_slot = o.upload(ms, s);
-            if (opts->store_c64) {
-                Owned tmp;
-                tmp.mem = o.mem;
-                H->d_near32 = c64_copy(o, tmp, H->d_near, H->bytes_near / 16, s);
-                int64_t tot = 0;
-                for (int64_t q = 0; q < nf; ++q) tot += (int64_t)mr[q] * (mg[q].m + mg[q].n);
-                hs::cf* base = o.get<hs::cf>((size_t)std::max<int64_t>(tot, 1));
-                std::vector<hs::PtrCopy> t;
-                std::vector<hs::cf*> mp32(nf, nullptr);
-                int64_t off = 0;
-                for (int64_t q = 0; q < nf; ++q) {
-                    const int64_t cnt = (int64_t)mr[q] * (mg[q].m + mg[q].n);
-                    mp32[q] = base + off;
-                    if (cnt) t.push_back(hs::PtrCopy{mp[q], off, cnt});
-                    off += cnt;
+            hs_hmatrix* Hp = H.get();
+            const int dev = ctx->device;
+            const double aca_tol = opts->aca_tol;
+            const bool store_c64 = opts->store_c64 != 0;
+            Hp->far_thread = std::thread([Hp, dev, k, aca_tol, cap, store_c64, d_err_far] {
+                try {
+                    hip_check(hipSetDevice(dev), "hipSetDevice");
+                    build_far(Hp, k, aca_tol, cap, store_c64, d_err_far);
+                } catch (...) {
+                    Hp->far_err = std::current_exception();
                 }
-                hs::PtrCopy* d_t = tmp.upload(t, s);
-                hs::launch_to_c64(d_t, (int64_t)t.size(), base, s);
-                H->d_mv_ptr32 = o.upload(mp32, s);
-                hip_check(hipStreamSynchronize(s), "stream sync");
-                H->c64 = true;
-            }
+            });
         }
-        H->d_gptr = o.upload(gptr, s);
-        H->d_gent = o.upload(gent, s);
-        hip_check(hipStreamSynchronize(s), "stream sync");
+        check_device_flag(d_err, s);   // the near field's (synchronises this stream)
         *out = H.release();
         return HS_OK;
     } catch (const Error& e) {
@@ -1212,6 +1267,14 @@ int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double 
 
 int32_t hs_query_hmatrix(const hs_hmatrix* H, hs_info* info) {
     if (!H || !info) { g_last_error = "NULL argument"; return HS_EINVAL; }
+    try {
+        H->join_far();
+    } catch (const Error& e) {
+        return set_error(e);
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return HS_ENOMEM;
+    }
     fill_info_plan(H->plan, info);
     info->bytes_near = H->bytes_near;
     info->bytes_far = H->bytes_far;
@@ -1228,6 +1291,7 @@ int32_t hs_hmatrix_export(const hs_hmatrix* H, int32_t what, void* dst, int64_t 
     try {
         if (!H) fail(HS_EINVAL, "H is NULL");
         if (what >= HS_X_PERM && what <= HS_X_FAR) return export_plan(H->plan, what, dst, cap, needed);
+        H->join_far();
         hip_check(hipSetDevice(H->own.mem.device), "hipSetDevice");
         hipStream_t s = nullptr;
         hip_check(hipDeviceSynchronize(), "device sync");
@@ -2676,6 +2740,7 @@ int32_t hs_matvec(hs_context* ctx, const hs_hmatrix* H, const void* x, void* y, 
     try {
         if (!ctx || !H || !x || !y) fail(HS_EINVAL, "NULL argument");
         if (nrhs < 1) fail(HS_EINVAL, "nrhs must be >= 1");
+        H->join_far();
         set_device(ctx);
         hipStream_t s = ctx->stream;
         Owned w;
@@ -2700,6 +2765,7 @@ int32_t hs_matvec_noalloc(hs_context* ctx, const hs_hmatrix* H, const void* x, v
     try {
         if (!ctx || !H || !x || !y) fail(HS_EINVAL, "NULL argument");
         if (nrhs < 1) fail(HS_EINVAL, "nrhs must be >= 1");
+        H->join_far();   // a no-op once the far field is in (no allocation)
         auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
         const int64_t n = H->n;
         const size_t vbytes = up(sizeof(cd) * (size_t)n * (size_t)nrhs);
@@ -3286,6 +3352,7 @@ int32_t hs_solve(hs_context* ctx, const hs_hmatrix* H, const hs_precond* P, cons
         if (!ctx || !H || !b || !x || !opts || !stats) fail(HS_EINVAL, "NULL argument");
         if (nrhs < 1) fail(HS_EINVAL, "nrhs must be >= 1");
         if (P && P->H != H) fail(HS_EINVAL, "the preconditioner belongs to another H-matrix");
+        H->join_far();
         const bool refined = opts->method == HS_SOLVE_GMRES_MIXED_IR;
         const bool mixed = opts->method == HS_SOLVE_FGMRES_MIXED || refined;
         if (opts->method == HS_SOLVE_TRANSFORMED) return solve_transformed(ctx, H, P, b, x, nrhs, opts, stats);
@@ -3448,6 +3515,7 @@ int64_t lane_bytes(const hs_hmatrix* H, const hs_precond* P, int ns, int m) {
 
 void lane_alloc(hs_context* ctx, Lane& L, const hs_hmatrix* H, const hs_precond* P, int ns, int m, hipStream_t s,
                 bool aux) {
+    H->join_far();
     L.H = H;
     L.P = P;
     L.s = s;
@@ -3688,6 +3756,7 @@ int32_t hs_solve_many(hs_context* ctx, int64_t nitems, const hs_solve_item* item
         for (int64_t i = 0; i < nitems; ++i) {
             const hs_solve_item& it = items[i];
             if (!it.H || !it.b || !it.x) fail(HS_EINVAL, "item " + std::to_string(i) + ": NULL H, b or x");
+            it.H->join_far();
             if (it.nrhs < 1 || it.nrhs > (1 << 20)) fail(HS_EINVAL, "item " + std::to_string(i) + ": bad nrhs");
             if (it.P && it.P->H != it.H) fail(HS_EINVAL, "item " + std::to_string(i) + ": P belongs to another H");
         }
@@ -3832,6 +3901,7 @@ int32_t hs_server_admit(hs_server* s, const hs_hmatrix* H, const hs_precond* P, 
     try {
         if (!s || !H || !geometry) fail(HS_EINVAL, "NULL argument");
         if (P && P->H != H) fail(HS_EINVAL, "the preconditioner belongs to another H-matrix");
+        H->join_far();
         int64_t add = (P ? P->own.bytes : 0) + lane_bytes(H, P, s->slots, s->opts.restart);
         const bool h_new = std::find(s->counted_h.begin(), s->counted_h.end(), H) == s->counted_h.end();
         if (h_new) add += H->own.bytes;
@@ -3881,6 +3951,7 @@ int32_t hs_server_add_geometry(hs_server* s, const double* points_host, int64_t 
             }
         }
         tmp.release();
+        H->join_far();
         const int64_t add = H->own.bytes + (P ? P->own.bytes : 0) + lane_bytes(H, P, s->slots, s->opts.restart);
         if (s->used + add > s->budget)
             fail(HS_ENOMEM, "admission refused: the built geometry needs " + std::to_string(add) +
