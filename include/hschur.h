@@ -234,8 +234,17 @@ int32_t hs_plan_export(const hs_plan* plan, int32_t what, void* dst, int64_t cap
  * h of the self term. Near blocks are assembled on the GPU, far blocks are
  * compressed on the GPU by partial-pivoting ACA then QR + SVD
  * re-compression at opts->aca_tol.
+ * The call returns once the near field is assembled (its errors checked);
+ * the far field is compressed meanwhile by a library host thread on streams
+ * of the H-matrix's own, so the caller's next work (a preconditioner setup,
+ * which reads only the near field) runs beside it. Every call that reads
+ * the far field (hs_matvec, hs_matvec_noalloc, hs_solve, hs_solve_many, the
+ * server, hs_query_hmatrix, hs_hmatrix_export) waits for it first and
+ * reports its errors; hs_hmatrix_destroy waits for it too. The context must
+ * outlive the H-matrix, as for every object made with it.
  * Errors: HS_EINVAL (n < 1, k < 0, self_h <= 0, leaf_max < 1, coincident
- * points), HS_ENOMEM, HS_ENUMERIC (rank above rank_cap). */
+ * points), HS_ENOMEM; from the far field, at the first call that reads it
+ * (and every later one): HS_ENOMEM, HS_ENUMERIC (rank above rank_cap). */
 int32_t hs_h_build(hs_context* ctx, const double* points_xyz, int64_t n, double k, double self_h,
                    const hs_build_opts* opts, hs_hmatrix** out);
 int32_t hs_query_hmatrix(const hs_hmatrix* H, hs_info* info);
